@@ -1,0 +1,110 @@
+"""Slow, non-FFT references for the collision operator (oracle pins only).
+
+* `mode_sum_lplus`: the FSM of `collision` written as the explicit spectral
+  convolution  (Q+)^_k = N_p^-3 sum_{l + m = k (mod N_p)} beta(l, m) g^_l h^_m,
+  beta(l, m) = 4 b0 sum_p W_p phi_p(l) psi_p(m), evaluated in O(N_p^6).  The FFT
+  form must equal it to rounding: this pins the pointwise-product /
+  convolution bookkeeping, the zero extension, the Nyquist handling and the
+  normalisation of the FFT implementation.
+* `sigma_quadrature_L`: L(h)(v) from the plain definition eq. LBE_collision
+  (sigma representation, hard spheres B = b0 |u|) for h = f_eq p(v) with p a
+  polynomial: with f(v') f(v*') = f(v) f(v*),
+  L(h)(v) = b0 f(v) int dv* f(v*) |u| int dsigma [p(v') + p(v*') - p(v) - p(v*)],
+  v', v*' = (v + v*)/2 +- |u| sigma / 2.  Computed by product Gauss quadrature
+  in u = v - v* (spherical coordinates) and sigma.  Independent of every FSM
+  choice (truncation, directions, padding), so it checks the whole reading.
+"""
+import math
+
+import numpy as np
+
+from .collision import phi_factor, psi_factor
+
+
+def full_tables(fsm):
+    """phi_p, psi_p on the full N_p^3 spectrum (FFT index order)."""
+    Np = fsm.n_pad
+    lf = np.fft.fftfreq(Np, 1.0 / Np)
+    l0, l1, l2 = np.meshgrid(lf, lf, lf, indexing="ij")
+    nyq = (l0 == -Np // 2) | (l1 == -Np // 2) | (l2 == -Np // 2)
+    ph = np.empty((fsm.D,) + l0.shape)
+    ps = np.empty_like(ph)
+    for p, e in enumerate(fsm.dirs):
+        s = l0 * e[0] + l1 * e[1] + l2 * e[2]
+        perp = np.sqrt(np.maximum((l0 - s * e[0]) ** 2 + (l1 - s * e[1]) ** 2
+                                  + (l2 - s * e[2]) ** 2, 0.0))
+        a = phi_factor(s, fsm.R, fsm.L_p, fsm.alpha, fsm.gamma)
+        b = psi_factor(perp, fsm.R, fsm.L_p, fsm.gamma)
+        a[nyq] = 0.0
+        b[nyq] = 0.0
+        ph[p], ps[p] = a, b
+    return ph, ps
+
+
+def _gain_mode_sum(fsm, ph, ps, g, h):
+    Np = fsm.n_pad
+    n = Np ** 3
+    G = np.fft.fftn(fsm.pad(g)).ravel()
+    H = np.fft.fftn(fsm.pad(h)).ravel()
+    phf = ph.reshape(fsm.D, n)
+    psf = ps.reshape(fsm.D, n)
+    beta = 4.0 * fsm.b0 * np.einsum("p,pl,pm->lm", fsm.W, phf, psf)
+    k = np.stack(np.unravel_index(np.arange(n), (Np,) * 3), axis=-1)
+    out = np.zeros(n, dtype=complex)
+    for kk in range(n):
+        m = np.ravel_multi_index(((k[kk][:, None] - k.T) % Np), (Np,) * 3)
+        out[kk] = np.sum(beta[np.arange(n), m] * G * H[m])
+    q = np.fft.ifftn(out.reshape((Np,) * 3) / n)
+    return fsm.crop(q), beta
+
+
+def mode_sum_lplus(fsm, h):
+    """L+(h) by explicit spectral convolutions (tiny grids only)."""
+    ph, ps = full_tables(fsm)
+    feq = fsm.grid.feq
+    q1, beta = _gain_mode_sum(fsm, ph, ps, feq, h)
+    q2, _ = _gain_mode_sum(fsm, ph, ps, h, feq)
+    Np = fsm.n_pad
+    H = np.fft.fftn(fsm.pad(h))
+    bd = np.diag(beta).reshape((Np,) * 3)
+    loss = feq * fsm.crop(np.fft.ifftn(bd * H))
+    return (q1 + q2 - loss).real, np.abs(q1.imag).max() + np.abs(q2.imag).max()
+
+
+def _gauss(a, b, n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (b - a) * x + 0.5 * (b + a), 0.5 * (b - a) * w
+
+
+def sphere_rule(nt, nph):
+    """Product Gauss rule on the unit sphere: points (n, 3), weights (n,)."""
+    ct, wt = _gauss(-1.0, 1.0, nt)
+    ph, wp = _gauss(0.0, 2.0 * math.pi, nph)
+    st = np.sqrt(1.0 - ct ** 2)
+    pts = np.stack([np.outer(st, np.cos(ph)), np.outer(st, np.sin(ph)),
+                    np.outer(ct, np.ones_like(ph))], axis=-1).reshape(-1, 3)
+    return pts, np.outer(wt, wp).ravel()
+
+
+def sigma_quadrature_L(v, poly, b0, nr=96, nu_ang=(24, 48), ns=(8, 16), rmax=None):
+    """Hard-sphere L(f_eq p)(v) at one point v from eq. LBE_collision.
+
+    poly: callable mapping an (..., 3) array of velocities to p(v).
+    """
+    v = np.asarray(v, dtype=np.float64)
+    rmax = rmax or (np.linalg.norm(v) + 8.0)
+    r, wr = _gauss(0.0, rmax, nr)
+    om, wom = sphere_rule(*nu_ang)
+    sg, wsg = sphere_rule(*ns)
+    f = lambda x: np.exp(-np.sum(x * x, axis=-1)) / math.pi ** 1.5
+    pv = poly(v)
+    total = 0.0
+    for ri, wri in zip(r, wr):
+        u = ri * om                           # (nu, 3), u = v - v*
+        vs = v - u
+        G = 0.5 * (v + vs)                    # (nu, 3)
+        vp = G[:, None, :] + 0.5 * ri * sg[None, :, :]
+        vsp = G[:, None, :] - 0.5 * ri * sg[None, :, :]
+        br = (poly(vp) + poly(vsp)) @ wsg - 4.0 * math.pi * (pv + poly(vs))
+        total += wri * ri ** 2 * ri * np.sum(wom * f(vs) * br)
+    return b0 * f(v) * total

@@ -1,0 +1,289 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the pin it implements; none of them re-derives the oracle's
+own formula.  All run on the CPU (no GPU marker).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import collision, direct, modes, solver
+from oracle import transport as tr
+from oracle.velocity import POISEUILLE, TRANSPIRATION, VelocityGrid
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+_cache = {}
+
+
+def fsm(n, m, lv=6.0, **kw):
+    key = (n, m, lv, tuple(sorted(kw.items())))
+    if key not in _cache:
+        _cache[key] = collision.FSM(VelocityGrid(n, lv), m_angle=m, **kw)
+    return _cache[key]
+
+
+def smooth_poly(V):
+    """A smooth non-invariant test polynomial (shear, heat-flux and v1^2 parts)."""
+    v1, v2, v3 = V[..., 0], V[..., 1], V[..., 2]
+    return v1 * v2 + 0.3 * v3 * (np.sum(V * V, axis=-1) - 2.5) + 0.2 * v1 ** 2
+
+
+def grid_vec(g):
+    return np.stack([g.V1, g.V2, g.V3], axis=-1)
+
+
+# ------------------------------------------------------------------ P1
+def test_P1_nubar_hard_sphere():
+    """Average collision frequency = 1.25 delta for hard spheres (Sec. 2.5)."""
+    ref = GOLDEN["nubar_over_delta_hs"]["value"]
+    assert abs(fsm(24, 8).nubar() - ref) < 1e-6
+    assert abs(fsm(16, 6).nubar() - ref) < 2e-5
+
+
+# ------------------------------------------------------------------ P2
+@pytest.mark.parametrize("alpha", [1.0, collision.ipl_alpha(0.81)])
+def test_P2_shear_rayleigh_quotient_equals_delta(alpha):
+    """First Chapman-Enskog viscosity: -<phi, L phi>/<phi, phi> = delta (delta = 1).
+
+    The amplitude b0 comes from a closed-form bracket; the FSM evaluates the
+    quotient by a completely different route (spectral convolutions).
+    """
+    f = fsm(24, 8, alpha=alpha)
+    g = f.grid
+    phi = g.V1 * g.V2 * g.feq
+    rq = -np.sum(phi * f.apply(phi) / g.feq) / np.sum(phi * phi / g.feq)
+    assert abs(rq - 1.0) < 5e-4
+
+
+# ------------------------------------------------------------------ P3
+def test_P3_nu_eq_hard_sphere_closed_form():
+    """nu_eq(v) = 4 pi b0 [e^-v^2/sqrt(pi) + (|v| + 1/(2|v|)) erf |v|] (textbook)."""
+    errs = []
+    for n, m in [(16, 6), (24, 8)]:
+        f = fsm(n, m)
+        g = f.grid
+        r = np.sqrt(g.vsq)
+        exact = 4 * math.pi * f.b0 * (np.exp(-g.vsq) / math.sqrt(math.pi)
+                                      + (r + 0.5 / r) * special.erf(r))
+        sel = r < 4.0
+        errs.append(np.max(np.abs(f.nu[sel] - exact[sel]) / exact[sel]))
+    assert errs[1] < 6e-3
+    assert errs[1] < 0.5 * errs[0]
+
+
+# ------------------------------------------------------------------ P4
+def test_P4_fft_form_equals_mode_sum():
+    """FFT evaluation == explicit O(N_p^6) spectral convolution, to rounding."""
+    g = VelocityGrid(6, 4.0)
+    f = collision.FSM(g, n_pad=12, m_angle=3)
+    rng = np.random.default_rng(7)
+    h = rng.standard_normal(g.feq.shape) * g.feq
+    ref, imag = direct.mode_sum_lplus(f, h)
+    assert imag < 1e-15
+    assert np.max(np.abs(ref - f.lplus(h))) < 1e-13 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------------ P5
+def test_P5_conservation():
+    """L(psi f_eq) ~ 0 and sum w psi L(h) ~ 0 for psi in {1, v, |v|^2}."""
+    f = fsm(24, 8)
+    g = f.grid
+    sc = np.max(np.abs(f.nu * g.feq))
+    for psi in collision.invariants(g):
+        assert np.max(np.abs(f.apply(psi * g.feq))) < 2e-5 * sc
+    h = g.feq * smooth_poly(grid_vec(g))
+    L = f.apply(h)
+    scl = np.max(np.abs(L))
+    for psi in collision.invariants(g):
+        assert abs(g.integrate(psi * L)) < 3e-5 * g.integrate(np.abs(psi * L))
+    # after the projection the moments vanish to rounding
+    Lp = collision.ProjectedFSM(f).apply(h)
+    for psi in collision.invariants(g):
+        assert abs(g.integrate(psi * Lp)) < 1e-14 * scl
+
+
+# ------------------------------------------------------------------ P6
+def test_P6_self_adjoint_and_dissipative():
+    """<g, L h> = <h, L g> in L2(1/f_eq) and <h, L h> <= 0 on smooth functions."""
+    f = fsm(24, 8)
+    g = f.grid
+    V = grid_vec(g)
+    inner = np.sqrt(g.vsq) <= 4.0
+    basis = [V[..., 0] * V[..., 2], V[..., 2] * (g.vsq - 2.5), V[..., 0] * V[..., 1],
+             V[..., 0] ** 2 - V[..., 1] ** 2, smooth_poly(V)]
+    hs = [b * g.feq for b in basis]
+    Ls = [f.apply(h) for h in hs]
+
+    def ip(a, b):
+        return np.sum((a * b / g.feq)[inner])
+
+    for i in range(len(hs)):
+        assert ip(hs[i], Ls[i]) < 0.0
+        for j in range(i + 1, len(hs)):
+            a, b = ip(hs[i], Ls[j]), ip(hs[j], Ls[i])
+            scale = math.sqrt(abs(ip(hs[i], Ls[i]) * ip(hs[j], Ls[j])))
+            assert abs(a - b) < 3e-3 * scale
+
+
+# ------------------------------------------------------------------ P7
+def test_P7_fsm_matches_direct_collision_integral():
+    """FSM L(f_eq p) vs sigma-representation quadrature of eq. LBE_collision."""
+    errs = []
+    for n, m, lv in [(16, 6, 4.0), (24, 8, 5.0)]:
+        f = fsm(n, m, lv)
+        g = f.grid
+        L = f.apply(g.feq * smooth_poly(grid_vec(g)))
+        sc = np.max(np.abs(f.nu * g.feq * smooth_poly(grid_vec(g))))
+        e = 0.0
+        for idx in [(n // 2, n // 2, n // 2), (n // 2 - 2, n // 2 + 1, n // 2 + 3),
+                    (n // 4, n // 2, 3 * n // 4)]:
+            v = np.array([g.v1d[i] for i in idx])
+            e = max(e, abs(direct.sigma_quadrature_L(v, smooth_poly, f.b0) - L[idx]) / sc)
+        errs.append(e)
+    assert errs[1] < 5e-4
+    assert errs[1] < 0.2 * errs[0]
+
+
+# ------------------------------------------------------------------ P8
+@pytest.mark.parametrize("n_s,kind", [(16, "uniform"), (12, "tanh")])
+def test_P8_free_molecular_planar_exact(n_s, kind):
+    """delta = 0: second-order upwind is exact for the linear-in-x solution.
+
+    M = 1/2 sum w v3 S/|v1|, Q likewise, and M_T = Q_P (Onsager) exactly.
+    """
+    f = fsm(16, 6)
+    x = tr.nodes_uniform(n_s) if kind == "uniform" else tr.nodes_tanh(n_s)
+    rP = solver.solve_1d(f, x, 0.0, POISEUILLE, "CIS")
+    rT = solver.solve_1d(f, x, 0.0, TRANSPIRATION, "SIS")
+    MP, QP = tr.free_molecular_1d(f.grid, POISEUILLE)
+    MT, QT = tr.free_molecular_1d(f.grid, TRANSPIRATION)
+    assert abs(rP.M - MP) < 1e-13 * abs(MP) and abs(rP.Q - QP) < 1e-13 * abs(QP)
+    assert abs(rT.M - MT) < 1e-13 * abs(MT) and abs(rT.Q - QT) < 1e-13 * abs(QT)
+    assert abs(MT - QP) < 1e-14
+    # U3 is uniform across the channel (h linear in x for every velocity)
+    assert np.ptp(rP.U) < 1e-13 * abs(MP)
+
+
+# ------------------------------------------------------------------ P10
+@pytest.mark.parametrize("delta", [0.1, 1.0, 10.0, 100.0])
+def test_P10_bgk_mode_eigenvalues(delta):
+    """Mode machinery with the BGK operator == its exact grid form; continuum
+    closed forms sqrt(pi) z e^{z^2} erfc z and the SIS integral at large delta."""
+    g = VelocityGrid(12, 5.0)
+    b = modes.BGKOperator(g)
+    K = modes.lplus_matrix(b)
+    P = modes.symmetry_projector(g)
+    Fc, Fs, c = modes.bgk_factors_discrete(g, delta)
+    w_cis = modes.spectral_radius(modes.cis_map(K, b.nu, g, delta), P)
+    w_sis = modes.spectral_radius(modes.sis_map(K, b.nu, g, delta, 1.0), P)
+    assert abs(w_cis - abs(Fc)) < 1e-12
+    assert abs(w_sis - abs((1 - c) * Fc + c * Fs)) < 1e-12
+    # continuum values: need a fine v1 grid when delta/(2 pi) is small
+    dv = 12.0 / 4000
+    v = -6.0 + (np.arange(4000) + 0.5) * dv
+    den = delta + 2j * math.pi * v
+    wts = dv * np.exp(-v * v) / math.sqrt(math.pi)
+    cis_1d = abs(np.sum(wts * delta / den))
+    sis_1d = abs(np.sum(wts * delta * (2 * v * v - 1) / den))
+    tol = 1e-6 if delta >= 1.0 else 2e-3
+    assert abs(cis_1d - modes.bgk_cis_omega(delta)) < tol
+    assert abs(sis_1d - modes.bgk_sis_omega(delta)) < tol
+
+
+# ------------------------------------------------------------------ P11 / E1
+def test_P11_fitted_omega_equals_spectral_radius_and_sis_beats_cis():
+    """The paper's fitted omega equals the iteration's spectral radius; SIS
+    omega stays well below CIS omega at large delta (Fig. 1 trend)."""
+    g = VelocityGrid(10, 4.0)
+    f = collision.FSM(g, m_angle=6)
+    K = modes.lplus_matrix(f)
+    P = modes.symmetry_projector(g)
+    S = g.source(POISEUILLE).ravel()
+    delta = 10.0
+    den = delta * f.nu.ravel() + 2j * math.pi * g.V1.ravel()
+    Tc = modes.cis_map(K, f.nu, g, delta)
+    rho_c = modes.spectral_radius(Tc, P)
+    U = modes.iterate(Tc, S / den, 200, g)
+    assert abs(modes.fitted_omega(U, tail=60) - rho_c) < 2e-3
+    Ts = modes.sis_map(K, f.nu, g, delta, f.nubar())
+    rho_s = modes.spectral_radius(Ts, P)
+    assert rho_c > 0.8
+    # the paper reports a maximum SIS eigenvalue of about 0.6
+    assert rho_s < GOLDEN["sis_max_eigenvalue"]["value"] < 0.7 * rho_c
+
+
+# ------------------------------------------------------------------ P13, SIS speed-up
+def test_P13_sis_cis_gap_shrinks_on_refinement():
+    """SIS and CIS reach the same flow rate up to spatial discretisation error;
+    the gap shrinks as the grid is refined (Sec. 2.4 reports < 0.5% at 100
+    sections)."""
+    f = collision.ProjectedFSM(fsm(12, 6, 4.0))
+    gaps = []
+    for n_s in (6, 18):
+        x = tr.nodes_uniform(n_s)
+        rs = solver.solve_1d(f, x, 2.0, POISEUILLE, "SIS", eps=1e-9)
+        rc = solver.solve_1d(f, x, 2.0, POISEUILLE, "CIS", eps=1e-9, max_it=2000)
+        assert rs.converged and rc.converged
+        gaps.append(abs(rs.M - rc.M) / abs(rc.M))
+    assert gaps[1] < 0.5 * gaps[0]
+    assert gaps[1] < 0.01
+
+
+def test_sis_needs_far_fewer_iterations_than_cis():
+    """Table 1 trend: at delta = 10 CIS needs an order of magnitude more
+    iterations than SIS (777 vs 54 in the paper)."""
+    f = collision.ProjectedFSM(fsm(12, 6, 4.0))
+    x = tr.nodes_uniform(5)
+    rs = solver.solve_1d(f, x, 10.0, POISEUILLE, "SIS", eps=1e-8)
+    rc = solver.solve_1d(f, x, 10.0, POISEUILLE, "CIS", eps=1e-8, max_it=3000)
+    assert rs.converged and rc.converged
+    assert rc.iters > 5 * rs.iters
+
+
+# ------------------------------------------------------------------ P15
+def test_P15_navier_stokes_limit_permeability():
+    """kappa = M/delta approaches 1/12 from above at large delta (Sec. 2.6)."""
+    f = collision.ProjectedFSM(fsm(12, 6, 4.0))
+    x = tr.nodes_uniform(10)
+    kap = [solver.solve_1d(f, x, d, POISEUILLE, "SIS", eps=1e-9).M / d for d in (20.0, 200.0)]
+    ref = GOLDEN["intrinsic_permeability"]["value"]
+    assert kap[0] > kap[1] > ref * 0.97
+    assert abs(kap[1] - ref) < 0.05 * ref
+
+
+# ------------------------------------------------------------------ grids
+def test_smoothstep_smallest_section():
+    """Sec. 2.4: 100 smoothstep sections, smallest 1.24e-6."""
+    x = tr.nodes_smoothstep(100)
+    assert x[0] == -0.5 and abs(x[-1]) < 1e-15
+    assert abs(np.min(np.diff(x)) - GOLDEN["smallest_section_smoothstep_100"]["value"]) < 5e-9
+
+
+def test_tanh_nodes_endpoints_and_clustering():
+    x = tr.nodes_tanh(100, 3.0)
+    d = np.diff(x)
+    assert x[0] == -0.5 and abs(x[-1]) < 1e-15
+    assert np.all(d > 0) and d[0] < d[-1] / 50
+
+
+# ------------------------------------------------------------------ a planted mistake is caught
+def test_planted_sign_error_in_gain_breaks_conservation():
+    """A dropped/negated gain term (a plausible oracle mistake) fails P5."""
+    f = fsm(16, 6, 4.0)
+    g = f.grid
+    h = g.V3 * g.feq
+    good = f.apply(h)
+    H = np.fft.rfftn(f.pad(h))
+    shp = (f.n_pad,) * 3
+    acc = np.zeros_like(h)
+    for p in range(f.D):   # only Q+(f_eq, h): the Q+(h, f_eq) term dropped
+        acc += f.W[p] * f.B[p] * f.crop(np.fft.irfftn(f.psi[p] * H, s=shp, axes=(-3, -2, -1)))
+    bad = 4 * f.b0 * acc - g.feq * f.crop(np.fft.irfftn(f.beta * H, s=shp, axes=(-3, -2, -1))) - f.nu * h
+    sc = np.max(np.abs(f.nu * h))
+    assert np.max(np.abs(good)) < 1e-3 * sc
+    assert np.max(np.abs(bad)) > 1e-1 * sc
