@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the SIS hot path on one MI355X.
+
+Workload (default): planar Poiseuille + thermal transpiration of a
+hard-sphere gas, 100 wall-clustered (tanh, factor 3) sections per half
+channel, 32^3 velocities on [-6, 6]^3 padded to 64^3, M = 12 (144 solid-angle
+directions), delta in {0.1, 1, 10, 100} x {Poiseuille, transpiration}:
+8 cases x 101 nodes = 808 spatial cells in one batch.
+
+A step is one SIS outer iteration over the whole batch: collision (dense
+fast-spectral operator contraction + epilogue), transport sweep with fused
+moments, diffusion correction, flow rates and convergence test, launched as
+one captured HIP graph.  value = cells x steps / wall time (cell-updates of
+L(h) per second, inputs resident in HBM).
+
+Also reported: the collision contraction's roofline (HIP events around each
+eager launch), the time-to-residual 1e-8 of FP64 vs mixed-precision
+collision, and the CPU oracle's cell-update rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s of L(h) + time-to-residual 1e-8, mixed SIS vs FP64 plain"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, n_cells):
+    """The oracle (NumPy FFT form of L) timed on a bounded sample of cells."""
+    import numpy as np
+    from oracle import collision
+    from oracle.velocity import VelocityGrid
+    from paper_1612_04488_amd import inputs
+    t0 = time.perf_counter()
+    f = collision.FSM(VelocityGrid(w["n_v"], w["l_v"]), n_pad=w["n_pad"], m_angle=w["m_angle"])
+    t_build = time.perf_counter() - t0
+    h = inputs.smooth_h(w["n_v"], w["l_v"], n_cells)
+    t0 = time.perf_counter()
+    for c in range(n_cells):
+        f.apply(h[c])
+    dt = time.perf_counter() - t0
+    return {"value": n_cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"L(h) of {n_cells} smooth cells of the benchmark batch, one process "
+                      f"(NumPy FFT, single thread); table build {t_build:.1f} s excluded",
+            "cpu": _cpu_model(), "host_cpu_count": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttr", action="store_true", help="skip time-to-residual runs")
+    ap.add_argument("--cpu-cells", type=int, default=12)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
+                                   "described in DESIGN.md but not implemented",
+                          "n_gpus": args.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1612_04488_amd import inputs, sis
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = inputs.PLANAR_BATCH if args.workload == "batch" else inputs.PLANAR_SMALL
+    t0 = time.perf_counter()
+    plan = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"])
+    t_plan = time.perf_counter() - t0
+    info = plan.info
+    log(f"plan {w['name']}: {t_plan:.2f} s (host {info['plan_seconds_host']:.2f} s), "
+        f"operator {info['operator_bytes'] / 2**30:.2f} GiB")
+    xs = inputs.workload_nodes(w)
+    geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
+    nc, n3 = geom.n_cells, plan.n3
+    plan.set_precision(args.precision)
+
+    # ---------------------------------------------------------- whole-step throughput
+    state = sis.State(plan, geom, scheme="SIS", eps=0.0, max_it=1 << 30, project=args.precision != "fp64")
+    state.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    state.step(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    log(f"{args.steps} steps: wall {wall * 1e3:.2f} ms, events {ev_ms:.2f} ms")
+    ms_per_step = wall * 1e3 / args.steps
+    value = nc * args.steps / wall
+    state.close()
+
+    # ---------------------------------------------------------- dominant kernel: contraction
+    h = torch.tensor(inputs.smooth_h(w["n_v"], w["l_v"], nc).reshape(nc, n3), device="cuda")
+    delta = torch.tensor(np.repeat(w["deltas"], [len(x) for x in xs]), dtype=torch.float64, device="cuda")
+    rhs = torch.empty_like(h)
+    plan.collide(h, delta, rhs)   # warm
+    torch.cuda.synchronize()
+    plan.timing(True)
+    for _ in range(max(args.steps, 5)):
+        plan.collide(h, delta, rhs)
+    gemm_ms, launches = plan.timing_read()
+    plan.timing(False)
+    avg_ms = gemm_ms / launches
+    flops = 2.0 * n3 * n3 * nc
+    executed = flops * (3 if args.precision == "bf16x3" else 1)
+    achieved = executed / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    log(f"contraction: {avg_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s of {peak} peak")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": f"gemm_{args.precision}", "avg_launch_ms": round(avg_ms, 4),
+                "flops_per_launch": executed,
+                "flops_per_cell_update": 2.0 * n3 * n3,
+                "fsm_fft_flops_per_cell_update": None}
+    D = info["n_dir"]
+    Np3 = w["n_pad"] ** 3
+    roofline["fsm_fft_flops_per_cell_update"] = (2 * D + 2) * 2.5 * Np3 * np.log2(Np3) + 6 * D * Np3
+
+    # ---------------------------------------------------------- time to residual 1e-8
+    ttr = {}
+    if not args.no_ttr:
+        ref = None
+        for prec in ["fp64", "fp32", "bf16x3"]:
+            plan.set_precision(prec)
+            r = sis.solve(plan, geom, scheme="SIS", eps=1e-8, max_it=400, project=prec != "fp64",
+                          raise_not_converged=False)
+            e = {"seconds": round(r["seconds"], 4), "iters": r["iters"].tolist(),
+                 "converged": bool(r["status"] == 0), "M": r["M"].tolist(), "Q": r["Q"].tolist()}
+            if ref is None:
+                ref = r
+            else:
+                e["max_rel_dev_M_vs_fp64"] = float(np.max(np.abs(r["M"] - ref["M"]) / np.abs(ref["M"])))
+                e["max_rel_dev_Q_vs_fp64"] = float(np.max(np.abs(r["Q"] - ref["Q"]) / np.abs(ref["Q"])))
+            ttr[prec] = e
+            log(f"time-to-residual {prec}: {r['seconds']:.3f} s, iters {r['iters'].tolist()}")
+        plan.set_precision(args.precision)
+
+    out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.precision],
+           "data": "synthetic",
+           "config": {"workload": w["name"], "n_v": w["n_v"], "l_v": w["l_v"], "n_pad": w["n_pad"],
+                      "directions": D, "cells": nc, "cases": geom.n_cases, "deltas": w["deltas"],
+                      "flows": w["flows"], "scheme": "SIS", "collision_precision": args.precision},
+           "roofline": roofline,
+           "plan_seconds": round(t_plan, 3),
+           "time_to_residual_1e-8": ttr}
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        cb = cpu_baseline(w, args.cpu_cells)
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu"] = value / cb["value"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

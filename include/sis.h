@@ -1,0 +1,254 @@
+/*
+ * sis.h -- C ABI of libsis.so: the per-iteration hot path of the synthetic
+ * iterative scheme (SIS) for the steady linearized Boltzmann equation
+ * (Wu, Zhang, Liu, Zhang & Reese, arXiv:1612.04488) on one AMD MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Velocity space: a uniform cell-centred grid of n_v points per axis on
+ *   [-l_v, l_v]^3 (Sec. 2; grid deferred by the paper to its FSM reference).
+ *   A velocity distribution of one spatial cell is n3 = n_v^3 doubles in
+ *   C order [v1][v2][v3] (v3 fastest).  Arrays over many cells are
+ *   [cell][v1][v2][v3], cells contiguous; the cells of several cases are
+ *   concatenated in case order.
+ * - All array arguments of the compute calls are caller-owned DEVICE
+ *   pointers (FP64 unless stated), borrowed for the duration of the call in
+ *   stream order; the library never frees or retains them.  Descriptor
+ *   structs are HOST memory and are copied during the call.
+ * - Every call validates its arguments on the host before anything is
+ *   enqueued and returns a negative sis_status on failure; the message is
+ *   available from sis_last_error() on the calling thread.  Asynchronous
+ *   device faults surface as SIS_E_DEVICE at the next synchronising call.
+ *   No C++ exception crosses this interface.
+ * - A plan is used by one stream at a time.  Compute calls are asynchronous
+ *   with respect to the host unless stated.
+ * - The collision operator is linear in the rarefaction parameter delta
+ *   (eq. delta, Sec. 2.1): tables are built once for delta = 1 and every call
+ *   takes delta per cell or per case.
+ */
+#ifndef SIS_H
+#define SIS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sis_status;
+enum {
+  SIS_OK = 0,
+  SIS_E_INVALID = -1,       /* bad argument value or null pointer             */
+  SIS_E_SHAPE = -2,         /* inconsistent sizes                             */
+  SIS_E_DEVICE = -3,        /* a HIP runtime call failed                      */
+  SIS_E_OOM = -4,           /* device or host allocation failed               */
+  SIS_E_NOT_CONVERGED = -5, /* sis_solve hit max_it; results are still filled */
+  SIS_E_NUMERIC = -6,       /* NaN/Inf detected in a flow rate                */
+  SIS_E_UNSUPPORTED = -7    /* valid request this build does not implement    */
+};
+
+/* Collision kernels: B = b0 |u|^alpha sin^(alpha+gamma-1)(theta/2) cos^-gamma(theta/2)
+ * (sigma representation, deflection angle theta), b0 set by the first
+ * Chapman-Enskog viscosity so that delta = p0 l / (mu v_m).                */
+enum { SIS_KERNEL_HARD_SPHERE = 0, SIS_KERNEL_IPL = 1 };
+/* Arithmetic of the collision contraction (everything else is FP64).       */
+enum { SIS_PREC_FP64 = 0, SIS_PREC_FP32 = 1, SIS_PREC_BF16X3 = 2 };
+/* Source terms S of Sec. 2 with X_P = X_T = -1.                             */
+enum { SIS_FLOW_NONE = 0, SIS_FLOW_POISEUILLE = 1, SIS_FLOW_TRANSPIRATION = 2 };
+enum { SIS_SCHEME_CIS = 0, SIS_SCHEME_SIS = 1 };
+enum { SIS_GEOM_PLANAR_HALF = 0 };
+
+const char* sis_last_error(void);   /* thread-local; valid until the next call on this thread */
+int32_t sis_version(void);          /* 100 * major + minor                                    */
+
+/* ------------------------------------------------------------------ plans
+ * A plan holds the velocity grid and the fast-spectral collision operator
+ * of one gas, assembled on the device at creation.
+ *
+ * Operator (eq. LBE_collision, evaluated by the fast spectral method that
+ * Sec. 2.4 cites; Carleman form): h is zero-extended to an n_pad^3 periodic
+ * box, |x|,|y| truncated at r_trunc (0 -> 4 L_p/(3 + sqrt 2)), directions
+ * e = (sin t cos p, sin t sin p, cos t) with (t, p) the m_angle-point
+ * Gauss-Legendre nodes on [0, pi]^2, weight w_t w_p sin t.  With
+ * phi_p(l) = phi(l.e_p), psi_p(l) = psi(|l - (l.e_p) e_p|) (Nyquist modes 0),
+ *   L+(h) = Q+(f_eq,h) + Q+(h,f_eq) - f_eq F^-1[beta F h],
+ *   Q+(g,h) = 4 b0 sum_p W_p F^-1[phi_p F g] F^-1[psi_p F h],
+ *   nu_eq = F^-1[beta F f_eq],  beta = 4 b0 sum_p W_p phi_p psi_p,
+ *   L(h) = L+(h) - nu_eq h.
+ * The plan stores the n3 x n3 matrix of h -> L+(h) (delta = 1), assembled
+ * from these spectral factors, and applies it as a dense contraction.       */
+typedef struct sis_plan* sis_plan_t;
+
+typedef struct {
+  int32_t n_v;        /* velocity points per axis (even, 4..40)                        */
+  double  l_v;        /* velocity half-width (> 0)                                     */
+  int32_t n_pad;      /* padded DFT size per axis (even, >= n_v; 0 -> 2 n_v)           */
+  int32_t m_angle;    /* Gauss points per angle; directions D = m_angle^2 (1..32)     */
+  double  r_trunc;    /* truncation radius (0 -> 4 L_p / (3 + sqrt 2))                 */
+  int32_t kernel;     /* SIS_KERNEL_*                                                  */
+  double  visc_index; /* IPL viscosity index w: alpha = 2 (1 - w), gamma = 0           */
+  int32_t n_threads;  /* host threads for table construction (0 -> hardware count)    */
+} sis_velocity_desc;
+
+typedef struct {
+  int32_t n_v, n3, n_pad, m_angle, n_dir;
+  double  l_v, dv, b0, r_trunc, nubar;   /* nubar = int nu_eq f_eq at delta = 1 (Sec. 2.5) */
+  double  alpha, gamma;
+  int64_t operator_bytes;                /* device bytes of the FP64 operator                */
+  double  plan_seconds_host, plan_seconds_device;
+} sis_plan_info;
+
+/* Build the tables on the host (threads) and assemble the operator on the
+ * current device with `stream`.  Synchronous.  Owns ~8 n3^2 bytes of device
+ * memory plus tables.                                                        */
+sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, sis_plan_t* out);
+sis_status sis_plan_destroy(sis_plan_t plan);
+sis_status sis_plan_query(sis_plan_t plan, sis_plan_info* out);
+
+/* Copy plan tables to HOST arrays (any may be NULL):
+ * v1d[n_v], feq[n3], nu[n3] (delta = 1), op[n3*n3] (row-major, row = output
+ * velocity; the L+ matrix at delta = 1).  Synchronous.                     */
+sis_status sis_plan_tables(sis_plan_t plan, double* v1d, double* feq, double* nu, double* op);
+
+/* Host-only table construction (no device needed): the delta = 1 collision
+ * frequency nu_eq[n3], the equilibrium feq[n3], and optionally the
+ * f_eq-fields A_p = F^-1[psi_p F f_eq], B_p = F^-1[phi_p F f_eq] on the n3
+ * grid for every direction p ([n_dir][n3] each), as used by the assembly.
+ * Arrays are HOST memory, any may be NULL.  Reports b0 and nubar.           */
+sis_status sis_host_tables(const sis_velocity_desc* desc, double* feq, double* nu,
+                           double* A, double* B, double* b0, double* nubar);
+
+/* Select the arithmetic of the collision contraction for later sis_collide
+ * / sis_solve calls on this plan (builds the low-precision operator copy on
+ * first use; synchronous).                                                   */
+sis_status sis_plan_set_precision(sis_plan_t plan, int32_t precision, hipStream_t stream);
+
+/* ------------------------------------------------------------------ geometry
+ * Device-resident spatial geometry for a batch of independent cases.
+ * SIS_GEOM_PLANAR_HALF: case c is the half channel -1/2 <= x1 <= 0 with
+ * nodes x1[node_offset[c] .. node_offset[c+1]) (strictly increasing,
+ * first -1/2 = diffuse wall, last 0 = specular symmetry plane, >= 2 nodes).
+ * One spatial cell per node; cells of all cases concatenated in case order.
+ * delta[c], flow[c] (SIS_FLOW_*) are per case.  Host arrays; copied.        */
+typedef struct {
+  int32_t kind;                 /* SIS_GEOM_*                    */
+  int32_t n_cases;
+  const int64_t* node_offset;   /* [n_cases + 1], node_offset[0] = 0 */
+  const double*  x1;            /* [node_offset[n_cases]]        */
+  const double*  delta;         /* [n_cases], >= 0               */
+  const int32_t* flow;          /* [n_cases]                     */
+} sis_geometry_desc;
+typedef struct sis_geom* sis_geom_t;
+
+sis_status sis_geometry_create(sis_plan_t plan, const sis_geometry_desc* desc,
+                               hipStream_t stream, sis_geom_t* out);
+sis_status sis_geometry_destroy(sis_geom_t geom);
+int64_t    sis_geometry_cells(sis_geom_t geom);
+
+/* ------------------------------------------------------------------ compute
+ * sis_collide -- collision step of one outer iteration for n_cells cells
+ * (eq. LBE_collision applied pointwise in space, eq. syn_LBE right side,
+ * correction of eq. guided applied on load):
+ *   h^k      = h + dU[c] * 2 v3 f_eq                (dU may be NULL: no correction)
+ *   L+       = delta[c] * L+_1(h^k),   L = L+ - delta[c] nu_1 h^k
+ *   rhs_out  = L+ + S(flow[c])                       [n_cells][n3]
+ *   lh_out   = L                                     [n_cells][n3]  (nullable)
+ *   amom_out = { 2 sum w v1 v3 L, 2 sum w v1 v3 h^k,
+ *                2 sum w v2 v3 L, 2 sum w v2 v3 h^k }  [n_cells][4] (nullable)
+ *   (so A1 = 2 int v1 v3 (L + N delta h) = amom[0] + N delta[c] amom[1]).
+ * If project != 0 the minimum-norm invariant projection is applied to L
+ * (and L+): L -= f_eq sum_i c_i psi_i, c = Gram^-1 m, m_i = sum w psi_i L,
+ * psi in {1, v1, v2, v3, |v|^2}.
+ * delta[n_cells] and flow[n_cells] (int32) are DEVICE arrays; flow may be NULL.
+ * Arithmetic of the contraction per sis_plan_set_precision; rest FP64.      */
+sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const double* dU,
+                       const double* delta, const int32_t* flow, int32_t project,
+                       double* rhs_out, double* lh_out, double* amom_out, hipStream_t stream);
+
+/* sis_transport_sweep -- solve delta nu h + v1 dh/dx1 = rhs per velocity
+ * (eq. syn_LBE / eq. LBE_iteration) by second-order upwind differences, first
+ * order at the first step from each boundary; v1 > 0: h = 0 at the wall,
+ * march to x1 = 0; v1 < 0: specular h(0, v1) = h(0, -v1), march to the wall.
+ * rhs, h_half_out: [cells][n3].  mom_out (nullable): [cells][4] =
+ * { U3, q3, G1 = F_201/4, P13 } of h_half (midpoint sums, weight dv^3).     */
+sis_status sis_transport_sweep(sis_plan_t plan, sis_geom_t geom, const double* rhs,
+                               double* h_half_out, double* mom_out, hipStream_t stream);
+
+/* sis_moments -- { U3, q3, G1, P13 } of h[n_cells][n3] -> mom_out[n_cells][4]. */
+sis_status sis_moments(sis_plan_t plan, int64_t n_cells, const double* h, double* mom_out,
+                       hipStream_t stream);
+
+/* sis_diffusion_correct -- planar form of the SIS velocity equation
+ * (eq. first_order with the tuning parameter N, Sec. 2.5):
+ *   d(U + G1)/dx1 = -N delta x1 [Poiseuille] + A1,   A1 = amom[0] + N delta amom[1],
+ * marched from the wall with the upwind stencil (first order at the first
+ * step), U at the wall = U3 of h_half.  mom_half: [cells][4] from the sweep;
+ * amom: [cells][4] from sis_collide (NULL -> A1 = 0).  N <= 0 -> nubar.
+ * Outputs U_out[cells] and dU_out[cells] = U - U3(h_half) (the correction
+ * amplitude of eq. guided), both nullable.                                   */
+sis_status sis_diffusion_correct(sis_plan_t plan, sis_geom_t geom, const double* mom_half,
+                                 const double* amom, double N, double* U_out, double* dU_out,
+                                 hipStream_t stream);
+
+/* ------------------------------------------------------------------ solver
+ * sis_solve -- CIS or SIS outer iterations from h = 0 for every case of a
+ * geometry until the relative change of both flow rates M = 2 int U3 dx1 and
+ * Q = 2 int q3 dx1 between consecutive iterations is below eps (per case),
+ * or max_it.  One iteration = sis_collide + sis_transport_sweep (+
+ * sis_diffusion_correct for SIS) + flow rates, launched as a captured HIP
+ * graph.  Converged cases are frozen while the others continue.  Results are
+ * copied to HOST arrays (each nullable).  Synchronous.                      */
+typedef struct {
+  int32_t scheme;        /* SIS_SCHEME_*                                   */
+  double  N;             /* penalty parameter; <= 0 -> nubar (Sec. 2.5)    */
+  double  eps;           /* convergence criterion (>= 0; 0 runs exactly max_it iterations) */
+  int32_t max_it;        /* >= 1                                           */
+  int32_t project;       /* invariant projection of L in sis_collide       */
+  int32_t check_every;   /* host convergence poll period (0 -> 4)          */
+  int32_t use_graph;     /* capture one iteration in a HIP graph (0/1)     */
+} sis_solve_opts;
+
+typedef struct {
+  double*  M;            /* [n_cases] mass flow rate                                   */
+  double*  Q;            /* [n_cases] heat flow rate                                   */
+  int32_t* iters;        /* [n_cases] iterations until the criterion held (or max_it) */
+  double*  residual;     /* [n_cases] last relative change                            */
+  double*  U;            /* [cells] U3 of the final iterate                           */
+  double*  q;            /* [cells] q3 of the final iterate                           */
+  double   seconds;      /* wall time of the iteration loop (excl. setup)             */
+  int32_t  total_iters;  /* outer iterations launched                                 */
+} sis_solve_result;
+
+sis_status sis_solve(sis_plan_t plan, sis_geom_t geom, const sis_solve_opts* opts,
+                     sis_solve_result* result, hipStream_t stream);
+
+/* Persistent iteration state (what sis_solve runs on): device buffers for
+ * h^{k+1/2}, the right side, moments, the pending correction dU and the
+ * per-case flow rates / convergence flags, plus the captured graph of one
+ * iteration.  Created with h = 0.  Owns ~2 cells*n3*8 bytes.
+ * sis_state_step enqueues n_iters iterations on `stream` (asynchronous);
+ * converged cases are frozen by the kernels themselves.
+ * sis_state_poll synchronises `stream` and returns the number of cases still
+ * iterating.  sis_state_results synchronises and fills `result` (seconds =
+ * 0, total_iters = iterations enqueued since create/reset).                 */
+typedef struct sis_state* sis_state_t;
+sis_status sis_state_create(sis_plan_t plan, sis_geom_t geom, const sis_solve_opts* opts,
+                            hipStream_t stream, sis_state_t* out);
+sis_status sis_state_reset(sis_state_t state, hipStream_t stream);
+sis_status sis_state_step(sis_state_t state, int32_t n_iters, hipStream_t stream);
+sis_status sis_state_poll(sis_state_t state, int32_t* n_active, hipStream_t stream);
+sis_status sis_state_results(sis_state_t state, sis_solve_result* result, hipStream_t stream);
+sis_status sis_state_destroy(sis_state_t state);
+
+/* Kernel timing of the collision contraction: while enabled, every eager
+ * (non-graph) contraction launch on a plan is bracketed by HIP events on its
+ * stream; sis_plan_timing_read synchronises and returns the summed
+ * milliseconds and the number of launches since enabling.                   */
+sis_status sis_plan_timing(sis_plan_t plan, int32_t enable);
+sis_status sis_plan_timing_read(sis_plan_t plan, double* gemm_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIS_H */

@@ -1,0 +1,901 @@
+// C ABI of libsis.so (declarations and contracts in include/sis.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "planner.h"
+#include "sis.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+sis_status fail(sis_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+template <class T>
+hipError_t dmalloc(T** p, size_t count) {
+  return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Grow-only device scratch buffer.
+struct Scratch {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need) {
+    if (need <= bytes) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, need);
+    if (e == hipSuccess) bytes = need;
+    return e;
+  }
+  ~Scratch() { dfree(p); }
+};
+
+}  // namespace
+
+struct sis_plan {
+  int device = 0;
+  int n = 0, n3 = 0, np = 0, D = 0, m_angle = 0;
+  double lv = 0, dv = 0, w = 0, b0 = 0, R = 0, nubar = 0, alpha = 1, gamma = 0;
+  double host_s = 0, dev_s = 0;
+  int precision = SIS_PREC_FP64;
+  double* op = nullptr;         // [n3][n3] L+ at delta = 1
+  float* op32 = nullptr;
+  uint16_t* ophi = nullptr;
+  uint16_t* oplo = nullptr;
+  double* v1d = nullptr;        // [n]
+  double* feq = nullptr;        // [n3]
+  double* nu = nullptr;         // [n3]
+  double* Kc = nullptr;         // [n3] L+(2 v3 feq)
+  double* gram_inv = nullptr;   // [25]
+  double cU = 0, cq = 0;        // U3, q3 of 2 v3 feq
+  std::vector<double> h_v1d, h_feq, h_nu;
+  Scratch ws_acc, ws_part;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  ~sis_plan() {
+    for (auto& e : events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    dfree(op); dfree(op32); dfree(ophi); dfree(oplo);
+    dfree(v1d); dfree(feq); dfree(nu); dfree(Kc); dfree(gram_inv);
+  }
+};
+
+struct sis_geom {
+  sis_plan* plan = nullptr;
+  int kind = 0, n_cases = 0, max_nodes = 0;
+  int64_t n_cells = 0;
+  std::vector<int64_t> h_off;
+  std::vector<double> h_x, h_delta;
+  std::vector<int32_t> h_flow;
+  int64_t* off = nullptr;
+  double* x = nullptr;
+  double* coef = nullptr;        // [cells][6]
+  double* delta_case = nullptr;
+  int32_t* flow_case = nullptr;
+  double* delta_cell = nullptr;
+  int32_t* flow_cell = nullptr;
+  int32_t* case_of_cell = nullptr;
+  ~sis_geom() {
+    dfree(off); dfree(x); dfree(coef); dfree(delta_case); dfree(flow_case);
+    dfree(delta_cell); dfree(flow_cell); dfree(case_of_cell);
+  }
+};
+
+namespace {
+
+bool invert5(const double* a, double* inv) {
+  double m[5][10];
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 10; ++j) m[i][j] = j < 5 ? a[i * 5 + j] : (j - 5 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 5; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 5; ++r)
+      if (std::fabs(m[r][c]) > std::fabs(m[piv][c])) piv = r;
+    if (m[piv][c] == 0.0) return false;
+    if (piv != c)
+      for (int j = 0; j < 10; ++j) std::swap(m[c][j], m[piv][j]);
+    const double d = m[c][c];
+    for (int j = 0; j < 10; ++j) m[c][j] /= d;
+    for (int r = 0; r < 5; ++r)
+      if (r != c) {
+        const double f = m[r][c];
+        for (int j = 0; j < 10; ++j) m[r][j] -= f * m[c][j];
+      }
+  }
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) inv[i * 5 + j] = m[i][j + 5];
+  return true;
+}
+
+sis_status validate_desc(const sis_velocity_desc* d) {
+  if (!d) return fail(SIS_E_INVALID, "null velocity descriptor");
+  if (d->n_v < 4 || d->n_v > 40 || d->n_v % 2) return fail(SIS_E_INVALID, "n_v must be even in [4, 40] (got %d)", d->n_v);
+  if (!(d->l_v > 0.0) || !std::isfinite(d->l_v)) return fail(SIS_E_INVALID, "l_v must be positive");
+  const int np = d->n_pad > 0 ? d->n_pad : 2 * d->n_v;
+  if (np < d->n_v || np % 2 || np > 128) return fail(SIS_E_INVALID, "n_pad must be even, >= n_v and <= 128 (got %d)", np);
+  if (d->m_angle < 1 || d->m_angle > 32) return fail(SIS_E_INVALID, "m_angle must be in [1, 32]");
+  if (d->r_trunc < 0.0) return fail(SIS_E_INVALID, "r_trunc must be >= 0");
+  if (d->kernel != SIS_KERNEL_HARD_SPHERE && d->kernel != SIS_KERNEL_IPL)
+    return fail(SIS_E_UNSUPPORTED, "unknown collision kernel %d", d->kernel);
+  if (d->kernel == SIS_KERNEL_IPL && !(d->visc_index >= 0.5 && d->visc_index <= 1.0))
+    return fail(SIS_E_INVALID, "IPL viscosity index must be in [0.5, 1]");
+  return SIS_OK;
+}
+
+sis::TableDesc table_desc(const sis_velocity_desc* d) {
+  sis::TableDesc t;
+  t.n_v = d->n_v;
+  t.l_v = d->l_v;
+  t.n_pad = d->n_pad;
+  t.m_angle = d->m_angle;
+  t.r_trunc = d->r_trunc;
+  t.alpha = d->kernel == SIS_KERNEL_IPL ? 2.0 * (1.0 - d->visc_index) : 1.0;
+  t.gamma = 0.0;
+  t.n_threads = d->n_threads;
+  return t;
+}
+
+// Choose tile and split-K for a contraction of M cells against the n3 x n3 operator.
+void choose_gemm(int64_t M, int n3, int* tile, int* splits) {
+  *tile = M >= 256 ? 0 : 1;
+  const int64_t bm = *tile == 0 ? 128 : 32;
+  const int64_t blocks = ((n3 + 127) / 128) * ((M + bm - 1) / bm);
+  int s = 1;
+  while (blocks * s < 1024 && s < 16 && n3 / (s * 2) >= 256) s *= 2;
+  *splits = s;
+}
+
+sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const double* dU,
+                       const double* delta, const int32_t* flow, int project, double* rhs,
+                       double* lh, double* amom, const int32_t* cell_active, hipStream_t s) {
+  int tile, splits;
+  choose_gemm(n_cells, p->n3, &tile, &splits);
+  double* acc = rhs;
+  if (splits > 1) {
+    HIP_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * n_cells * p->n3 * sizeof(double)));
+    acc = static_cast<double*>(p->ws_acc.p);
+  }
+  sis::GemmArgs g{};
+  g.precision = p->precision;
+  g.X = h;
+  g.op64 = p->op;
+  g.op32 = p->op32;
+  g.ophi = p->ophi;
+  g.oplo = p->oplo;
+  g.acc = acc;
+  g.M = n_cells;
+  g.N = p->n3;
+  g.K = p->n3;
+  g.splits = splits;
+  g.tile = tile;
+  if (p->timing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+      hipEvent_t a, b;
+      HIP_TRY(hipEventCreate(&a));
+      HIP_TRY(hipEventCreate(&b));
+      p->events.emplace_back(a, b);
+      HIP_TRY(hipEventRecord(a, s));
+      HIP_TRY(sis::launch_gemm(g, s));
+      HIP_TRY(hipEventRecord(b, s));
+    } else {
+      HIP_TRY(sis::launch_gemm(g, s));
+    }
+  } else {
+    HIP_TRY(sis::launch_gemm(g, s));
+  }
+  sis::FinishArgs f{};
+  f.n = p->n;
+  f.n3 = p->n3;
+  f.n_cells = n_cells;
+  f.splits = splits;
+  f.acc = acc;
+  f.h = h;
+  f.dU = dU;
+  f.delta = delta;
+  f.flow = flow;
+  f.project = project;
+  f.v1d = p->v1d;
+  f.feq = p->feq;
+  f.nu = p->nu;
+  f.Kc = p->Kc;
+  f.gram_inv = p->gram_inv;
+  f.w = p->w;
+  f.active = cell_active;
+  f.rhs = rhs;
+  f.lh = lh;
+  f.amom = amom;
+  HIP_TRY(sis::launch_finish(f, s));
+  return SIS_OK;
+}
+
+sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, double* mom,
+                     const int32_t* case_active, hipStream_t s) {
+  const int W = (p->n3 / 2 + 63) / 64;
+  HIP_TRY(p->ws_part.ensure(static_cast<size_t>(g->n_cells) * 8 * W * sizeof(double)));
+  sis::SweepArgs a{};
+  a.n = p->n;
+  a.n3 = p->n3;
+  a.n_cases = g->n_cases;
+  a.node_off = g->off;
+  a.coef = g->coef;
+  a.delta_case = g->delta_case;
+  a.v1d = p->v1d;
+  a.nu = p->nu;
+  a.rhs = rhs;
+  a.h = h;
+  a.part = static_cast<double*>(p->ws_part.p);
+  a.W = W;
+  a.case_active = case_active;
+  a.w = p->w;
+  a.max_nodes = g->max_nodes;
+  HIP_TRY(sis::launch_sweep1d(a, s));
+  if (mom) HIP_TRY(sis::launch_reduce_partials(a.part, W, g->n_cells, mom, s));
+  return SIS_OK;
+}
+
+sis_status check_plan(sis_plan_t p) {
+  if (!p) return fail(SIS_E_INVALID, "null plan");
+  return SIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sis_last_error(void) { return g_err.c_str(); }
+int32_t sis_version(void) { return 100; }
+
+sis_status sis_host_tables(const sis_velocity_desc* desc, double* feq, double* nu, double* A,
+                           double* B, double* b0, double* nubar) {
+  sis_status st = validate_desc(desc);
+  if (st) return st;
+  sis::HostTables t;
+  std::string err;
+  if (!sis::build_host_tables(table_desc(desc), false, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
+  if (feq) std::memcpy(feq, t.feq.data(), t.n3 * sizeof(double));
+  if (nu) std::memcpy(nu, t.nu.data(), t.n3 * sizeof(double));
+  if (A) std::memcpy(A, t.A.data(), t.A.size() * sizeof(double));
+  if (B) std::memcpy(B, t.B.data(), t.B.size() * sizeof(double));
+  if (b0) *b0 = t.b0;
+  if (nubar) *nubar = t.nubar;
+  g_err.clear();
+  return SIS_OK;
+}
+
+sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, sis_plan_t* out) {
+  if (!out) return fail(SIS_E_INVALID, "null output handle");
+  *out = nullptr;
+  sis_status st = validate_desc(desc);
+  if (st) return st;
+  auto t0 = std::chrono::steady_clock::now();
+  sis::HostTables t;
+  std::string err;
+  if (!sis::build_host_tables(table_desc(desc), true, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
+  auto t1 = std::chrono::steady_clock::now();
+
+  sis_plan* p = new sis_plan();
+  HIP_TRY(hipGetDevice(&p->device));
+  p->n = t.n;
+  p->n3 = t.n3;
+  p->np = t.np;
+  p->D = t.D;
+  p->m_angle = desc->m_angle;
+  p->lv = t.lv;
+  p->dv = t.dv;
+  p->w = t.dv * t.dv * t.dv;
+  p->b0 = t.b0;
+  p->R = t.R;
+  p->nubar = t.nubar;
+  p->alpha = t.alpha;
+  p->gamma = t.gamma;
+  p->h_v1d = t.v1d;
+  p->h_feq = t.feq;
+  p->h_nu = t.nu;
+  const int n = t.n, n3 = t.n3, D = t.D;
+
+  // pre-scale the f_eq fields by 4 b0 W_p
+  for (int d = 0; d < D; ++d) {
+    const double sc = 4.0 * t.b0 * t.W[d];
+    for (int i = 0; i < n3; ++i) {
+      t.A[static_cast<size_t>(d) * n3 + i] *= sc;
+      t.B[static_cast<size_t>(d) * n3 + i] *= sc;
+    }
+  }
+  double *dPsi = nullptr, *dPhi = nullptr, *dA = nullptr, *dB = nullptr, *dbr = nullptr;
+  auto cleanup = [&]() { dfree(dPsi); dfree(dPhi); dfree(dA); dfree(dB); dfree(dbr); };
+#define PLAN_TRY(expr)                                                                       \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      cleanup();                                                                             \
+      delete p;                                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s", #expr,      \
+                  hipGetErrorString(e_));                                                    \
+    }                                                                                        \
+  } while (0)
+  PLAN_TRY(dmalloc(&dPsi, t.Psi.size()));
+  PLAN_TRY(dmalloc(&dPhi, t.Phi.size()));
+  PLAN_TRY(dmalloc(&dA, t.A.size()));
+  PLAN_TRY(dmalloc(&dB, t.B.size()));
+  PLAN_TRY(dmalloc(&dbr, t.beta_r.size()));
+  PLAN_TRY(dmalloc(&p->op, static_cast<size_t>(n3) * n3));
+  PLAN_TRY(dmalloc(&p->v1d, n));
+  PLAN_TRY(dmalloc(&p->feq, n3));
+  PLAN_TRY(dmalloc(&p->nu, n3));
+  PLAN_TRY(dmalloc(&p->Kc, n3));
+  PLAN_TRY(dmalloc(&p->gram_inv, 25));
+  PLAN_TRY(hipMemcpyAsync(dPsi, t.Psi.data(), t.Psi.size() * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dPhi, t.Phi.data(), t.Phi.size() * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dA, t.A.data(), t.A.size() * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dB, t.B.data(), t.B.size() * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dbr, t.beta_r.data(), t.beta_r.size() * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(p->v1d, t.v1d.data(), n * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(p->feq, t.feq.data(), n3 * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(p->nu, t.nu.data(), n3 * 8, hipMemcpyHostToDevice, stream));
+
+  // Gram matrix of the invariants {1, v1, v2, v3, |v|^2} with weight w f_eq
+  double G[25] = {0}, Gi[25];
+  std::vector<double> corr(n3);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      for (int c = 0; c < n; ++c) {
+        const int i = (a * n + b) * n + c;
+        const double v1 = t.v1d[a], v2 = t.v1d[b], v3 = t.v1d[c];
+        const double psi[5] = {1.0, v1, v2, v3, v1 * v1 + v2 * v2 + v3 * v3};
+        for (int r = 0; r < 5; ++r)
+          for (int q = 0; q < 5; ++q) G[r * 5 + q] += p->w * psi[r] * psi[q] * t.feq[i];
+        corr[i] = 2.0 * v3 * t.feq[i];
+        p->cU += p->w * v3 * corr[i];
+        p->cq += p->w * (psi[4] - 2.5) * v3 * corr[i];
+      }
+  if (!invert5(G, Gi)) {
+    cleanup();
+    delete p;
+    return fail(SIS_E_NUMERIC, "singular invariant Gram matrix");
+  }
+  PLAN_TRY(hipMemcpyAsync(p->gram_inv, Gi, 25 * 8, hipMemcpyHostToDevice, stream));
+
+  PLAN_TRY(sis::launch_assemble(n, D, dPsi, dPhi, dA, dB, p->feq, dbr, p->op, stream));
+  // Kc = L+(2 v3 feq): one-row contraction against the operator
+  double* dcorr = dA;  // reuse (large enough)
+  PLAN_TRY(hipMemcpyAsync(dcorr, corr.data(), n3 * 8, hipMemcpyHostToDevice, stream));
+  {
+    sis::GemmArgs g{};
+    g.precision = 0;
+    g.X = dcorr;
+    g.op64 = p->op;
+    g.acc = p->Kc;
+    g.M = 1;
+    g.N = n3;
+    g.K = n3;
+    g.splits = 1;
+    g.tile = 1;
+    PLAN_TRY(sis::launch_gemm(g, stream));
+  }
+  PLAN_TRY(hipStreamSynchronize(stream));
+  cleanup();
+#undef PLAN_TRY
+  auto t2 = std::chrono::steady_clock::now();
+  p->host_s = std::chrono::duration<double>(t1 - t0).count();
+  p->dev_s = std::chrono::duration<double>(t2 - t1).count();
+  *out = p;
+  g_err.clear();
+  return SIS_OK;
+}
+
+sis_status sis_plan_destroy(sis_plan_t plan) {
+  if (!plan) return fail(SIS_E_INVALID, "null plan");
+  delete plan;
+  return SIS_OK;
+}
+
+sis_status sis_plan_query(sis_plan_t p, sis_plan_info* out) {
+  if (sis_status st = check_plan(p)) return st;
+  if (!out) return fail(SIS_E_INVALID, "null output");
+  out->n_v = p->n;
+  out->n3 = p->n3;
+  out->n_pad = p->np;
+  out->m_angle = p->m_angle;
+  out->n_dir = p->D;
+  out->l_v = p->lv;
+  out->dv = p->dv;
+  out->b0 = p->b0;
+  out->r_trunc = p->R;
+  out->nubar = p->nubar;
+  out->alpha = p->alpha;
+  out->gamma = p->gamma;
+  out->operator_bytes = static_cast<int64_t>(p->n3) * p->n3 * 8;
+  out->plan_seconds_host = p->host_s;
+  out->plan_seconds_device = p->dev_s;
+  return SIS_OK;
+}
+
+sis_status sis_plan_tables(sis_plan_t p, double* v1d, double* feq, double* nu, double* op) {
+  if (sis_status st = check_plan(p)) return st;
+  if (v1d) std::memcpy(v1d, p->h_v1d.data(), p->n * 8);
+  if (feq) std::memcpy(feq, p->h_feq.data(), p->n3 * 8);
+  if (nu) std::memcpy(nu, p->h_nu.data(), p->n3 * 8);
+  if (op) HIP_TRY(hipMemcpy(op, p->op, static_cast<size_t>(p->n3) * p->n3 * 8, hipMemcpyDeviceToHost));
+  return SIS_OK;
+}
+
+sis_status sis_plan_set_precision(sis_plan_t p, int32_t precision, hipStream_t stream) {
+  if (sis_status st = check_plan(p)) return st;
+  const int64_t cnt = static_cast<int64_t>(p->n3) * p->n3;
+  if (precision == SIS_PREC_FP64) {
+  } else if (precision == SIS_PREC_FP32) {
+    if (!p->op32) {
+      HIP_TRY(dmalloc(&p->op32, cnt));
+      HIP_TRY(sis::launch_convert_f32(p->op, p->op32, cnt, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+    }
+  } else if (precision == SIS_PREC_BF16X3) {
+    if (p->n3 % 8) return fail(SIS_E_UNSUPPORTED, "BF16X3 needs n_v^3 divisible by 8");
+    if (!p->ophi) {
+      HIP_TRY(dmalloc(&p->ophi, cnt));
+      HIP_TRY(dmalloc(&p->oplo, cnt));
+      HIP_TRY(sis::launch_split_bf16(p->op, p->ophi, p->oplo, cnt, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+    }
+  } else {
+    return fail(SIS_E_UNSUPPORTED, "unknown precision %d", precision);
+  }
+  p->precision = precision;
+  return SIS_OK;
+}
+
+sis_status sis_geometry_create(sis_plan_t p, const sis_geometry_desc* d, hipStream_t stream,
+                               sis_geom_t* out) {
+  if (sis_status st = check_plan(p)) return st;
+  if (!d || !out) return fail(SIS_E_INVALID, "null argument");
+  *out = nullptr;
+  if (d->kind != SIS_GEOM_PLANAR_HALF) return fail(SIS_E_UNSUPPORTED, "geometry kind %d not supported", d->kind);
+  if (d->n_cases < 1) return fail(SIS_E_INVALID, "n_cases must be >= 1");
+  if (!d->node_offset || !d->x1 || !d->delta || !d->flow) return fail(SIS_E_INVALID, "null geometry array");
+  if (d->node_offset[0] != 0) return fail(SIS_E_INVALID, "node_offset[0] must be 0");
+  auto* g = new sis_geom();
+  g->plan = p;
+  g->kind = d->kind;
+  g->n_cases = d->n_cases;
+  g->h_off.assign(d->node_offset, d->node_offset + d->n_cases + 1);
+  g->n_cells = g->h_off.back();
+  for (int c = 0; c < d->n_cases; ++c) {
+    const int64_t a = g->h_off[c], b = g->h_off[c + 1];
+    if (b - a < 2) { delete g; return fail(SIS_E_SHAPE, "case %d has fewer than 2 nodes", c); }
+    g->max_nodes = std::max<int>(g->max_nodes, static_cast<int>(b - a));
+    if (d->x1[a] != -0.5 || d->x1[b - 1] != 0.0) { delete g; return fail(SIS_E_INVALID, "case %d nodes must run from -0.5 to 0", c); }
+    for (int64_t i = a + 1; i < b; ++i)
+      if (!(d->x1[i] > d->x1[i - 1])) { delete g; return fail(SIS_E_INVALID, "case %d nodes not increasing", c); }
+    if (!(d->delta[c] >= 0.0) || !std::isfinite(d->delta[c])) { delete g; return fail(SIS_E_INVALID, "case %d delta must be >= 0", c); }
+    if (d->flow[c] < 0 || d->flow[c] > 2) { delete g; return fail(SIS_E_INVALID, "case %d flow code %d", c, d->flow[c]); }
+  }
+  g->h_x.assign(d->x1, d->x1 + g->n_cells);
+  g->h_delta.assign(d->delta, d->delta + d->n_cases);
+  g->h_flow.assign(d->flow, d->flow + d->n_cases);
+  // upwind stencil coefficients per node (first order at the first step from a boundary)
+  std::vector<double> coef(static_cast<size_t>(g->n_cells) * 6, 0.0);
+  std::vector<double> dcell(g->n_cells);
+  std::vector<int32_t> fcell(g->n_cells), ccell(g->n_cells);
+  for (int c = 0; c < d->n_cases; ++c) {
+    const int64_t a = g->h_off[c], b = g->h_off[c + 1];
+    const int nn = static_cast<int>(b - a);
+    const double* x = d->x1 + a;
+    for (int i = 0; i < nn; ++i) {
+      double* q = &coef[(a + i) * 6];
+      if (i >= 1) {
+        const double d1 = x[i] - x[i - 1];
+        if (i == 1) { q[0] = 1.0 / d1; q[1] = -1.0 / d1; q[2] = 0.0; }
+        else {
+          const double d2 = x[i - 1] - x[i - 2];
+          q[0] = (2.0 * d1 + d2) / (d1 * (d1 + d2));
+          q[1] = -(d1 + d2) / (d1 * d2);
+          q[2] = d1 / (d2 * (d1 + d2));
+        }
+      }
+      if (i <= nn - 2) {
+        const double d1 = x[i + 1] - x[i];
+        if (i == nn - 2) { q[3] = 1.0 / d1; q[4] = -1.0 / d1; q[5] = 0.0; }
+        else {
+          const double d2 = x[i + 2] - x[i + 1];
+          q[3] = (2.0 * d1 + d2) / (d1 * (d1 + d2));
+          q[4] = -(d1 + d2) / (d1 * d2);
+          q[5] = d1 / (d2 * (d1 + d2));
+        }
+      }
+      dcell[a + i] = d->delta[c];
+      fcell[a + i] = d->flow[c];
+      ccell[a + i] = c;
+    }
+  }
+#define GEOM_TRY(expr)                                                                         \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      delete g;                                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s", #expr,        \
+                  hipGetErrorString(e_));                                                      \
+    }                                                                                          \
+  } while (0)
+  const int64_t nc = g->n_cells;
+  GEOM_TRY(dmalloc(&g->off, d->n_cases + 1));
+  GEOM_TRY(dmalloc(&g->x, nc));
+  GEOM_TRY(dmalloc(&g->coef, nc * 6));
+  GEOM_TRY(dmalloc(&g->delta_case, d->n_cases));
+  GEOM_TRY(dmalloc(&g->flow_case, d->n_cases));
+  GEOM_TRY(dmalloc(&g->delta_cell, nc));
+  GEOM_TRY(dmalloc(&g->flow_cell, nc));
+  GEOM_TRY(dmalloc(&g->case_of_cell, nc));
+  GEOM_TRY(hipMemcpyAsync(g->off, g->h_off.data(), (d->n_cases + 1) * 8, hipMemcpyHostToDevice, stream));
+  GEOM_TRY(hipMemcpyAsync(g->x, d->x1, nc * 8, hipMemcpyHostToDevice, stream));
+  GEOM_TRY(hipMemcpyAsync(g->coef, coef.data(), nc * 6 * 8, hipMemcpyHostToDevice, stream));
+  GEOM_TRY(hipMemcpyAsync(g->delta_case, d->delta, d->n_cases * 8, hipMemcpyHostToDevice, stream));
+  GEOM_TRY(hipMemcpyAsync(g->flow_case, d->flow, d->n_cases * 4, hipMemcpyHostToDevice, stream));
+  GEOM_TRY(hipMemcpyAsync(g->delta_cell, dcell.data(), nc * 8, hipMemcpyHostToDevice, stream));
+  GEOM_TRY(hipMemcpyAsync(g->flow_cell, fcell.data(), nc * 4, hipMemcpyHostToDevice, stream));
+  GEOM_TRY(hipMemcpyAsync(g->case_of_cell, ccell.data(), nc * 4, hipMemcpyHostToDevice, stream));
+  GEOM_TRY(hipStreamSynchronize(stream));
+#undef GEOM_TRY
+  *out = g;
+  g_err.clear();
+  return SIS_OK;
+}
+
+sis_status sis_geometry_destroy(sis_geom_t g) {
+  if (!g) return fail(SIS_E_INVALID, "null geometry");
+  delete g;
+  return SIS_OK;
+}
+
+int64_t sis_geometry_cells(sis_geom_t g) { return g ? g->n_cells : -1; }
+
+sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,
+                       const double* delta, const int32_t* flow, int32_t project, double* rhs_out,
+                       double* lh_out, double* amom_out, hipStream_t stream) {
+  if (sis_status st = check_plan(p)) return st;
+  if (n_cells < 0) return fail(SIS_E_SHAPE, "n_cells must be >= 0");
+  if (n_cells == 0) return SIS_OK;
+  if (n_cells > (int64_t(1) << 31) / 1) return fail(SIS_E_SHAPE, "n_cells too large");
+  if (!h || !delta || !rhs_out) return fail(SIS_E_INVALID, "h, delta and rhs_out must be non-null");
+  if (!aligned16(h) || !aligned16(rhs_out)) return fail(SIS_E_INVALID, "h and rhs_out must be 16-byte aligned");
+  if (h == rhs_out) return fail(SIS_E_INVALID, "rhs_out must not alias h");
+  return run_collide(p, n_cells, h, dU, delta, flow, project, rhs_out, lh_out, amom_out, nullptr, stream);
+}
+
+sis_status sis_transport_sweep(sis_plan_t p, sis_geom_t g, const double* rhs, double* h_half_out,
+                               double* mom_out, hipStream_t stream) {
+  if (sis_status st = check_plan(p)) return st;
+  if (!g || g->plan != p) return fail(SIS_E_INVALID, "geometry does not belong to this plan");
+  if (!rhs || !h_half_out) return fail(SIS_E_INVALID, "rhs and h_half_out must be non-null");
+  if (rhs == h_half_out) return fail(SIS_E_INVALID, "h_half_out must not alias rhs");
+  return run_sweep(p, g, rhs, h_half_out, mom_out, nullptr, stream);
+}
+
+sis_status sis_moments(sis_plan_t p, int64_t n_cells, const double* h, double* mom_out, hipStream_t stream) {
+  if (sis_status st = check_plan(p)) return st;
+  if (n_cells < 0) return fail(SIS_E_SHAPE, "n_cells must be >= 0");
+  if (n_cells == 0) return SIS_OK;
+  if (!h || !mom_out) return fail(SIS_E_INVALID, "null array");
+  HIP_TRY(sis::launch_moments(p->n, p->n3, n_cells, p->v1d, h, p->w, mom_out, stream));
+  return SIS_OK;
+}
+
+sis_status sis_diffusion_correct(sis_plan_t p, sis_geom_t g, const double* mom_half,
+                                 const double* amom, double N, double* U_out, double* dU_out,
+                                 hipStream_t stream) {
+  if (sis_status st = check_plan(p)) return st;
+  if (!g || g->plan != p) return fail(SIS_E_INVALID, "geometry does not belong to this plan");
+  if (!mom_half) return fail(SIS_E_INVALID, "mom_half must be non-null");
+  if (!std::isfinite(N)) return fail(SIS_E_INVALID, "N must be finite");
+  sis::DiffusionArgs a{};
+  a.n_cases = g->n_cases;
+  a.node_off = g->off;
+  a.x = g->x;
+  a.coef = g->coef;
+  a.delta_case = g->delta_case;
+  a.flow_case = g->flow_case;
+  a.mom = mom_half;
+  a.amom = amom;
+  a.N = N > 0.0 ? N : p->nubar;
+  a.sis = 1;
+  a.cU = p->cU;
+  a.cq = p->cq;
+  a.U = U_out;
+  a.dU = dU_out;
+  HIP_TRY(sis::launch_diffusion1d(a, stream));
+  return SIS_OK;
+}
+
+}  // extern "C"
+
+struct sis_state {
+  sis_plan* p = nullptr;
+  sis_geom* g = nullptr;
+  sis_solve_opts o{};
+  double Npen = 0.0;
+  double *h = nullptr, *rhs = nullptr, *amom = nullptr, *mom = nullptr, *dU = nullptr, *U = nullptr,
+         *q = nullptr, *state = nullptr;
+  int32_t *iters = nullptr, *cact = nullptr, *lact = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int total = 0;
+  ~sis_state() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    dfree(h); dfree(rhs); dfree(amom); dfree(mom); dfree(dU); dfree(U); dfree(q); dfree(state);
+    dfree(iters); dfree(cact); dfree(lact);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+namespace {
+
+sis_status state_iteration(sis_state* b, hipStream_t s) {
+  sis_plan* p = b->p;
+  sis_geom* g = b->g;
+  const bool sis = b->o.scheme == SIS_SCHEME_SIS;
+  if (sis_status st = run_collide(p, g->n_cells, b->h, sis ? b->dU : nullptr, g->delta_cell,
+                                  g->flow_cell, b->o.project, b->rhs, nullptr, b->amom, b->lact, s))
+    return st;
+  if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s)) return st;
+  sis::DiffusionArgs a{};
+  a.n_cases = g->n_cases;
+  a.node_off = g->off;
+  a.x = g->x;
+  a.coef = g->coef;
+  a.delta_case = g->delta_case;
+  a.flow_case = g->flow_case;
+  a.mom = b->mom;
+  a.amom = b->amom;
+  a.N = b->Npen;
+  a.sis = sis ? 1 : 0;
+  a.cU = p->cU;
+  a.cq = p->cq;
+  a.U = nullptr;
+  a.ufield = b->U;
+  a.dU = b->dU;
+  a.state = b->state;
+  a.iters = b->iters;
+  a.case_active = b->cact;
+  a.qfield = b->q;
+  a.eps = b->o.eps;
+  HIP_TRY(sis::launch_diffusion1d(a, s));
+  HIP_TRY(sis::launch_expand_active(b->cact, g->case_of_cell, g->n_cells, b->lact, s));
+  return SIS_OK;
+}
+
+sis_status state_init(sis_state* b, hipStream_t s) {
+  const int64_t nc = b->g->n_cells;
+  const int ncase = b->g->n_cases;
+  HIP_TRY(hipMemsetAsync(b->h, 0, static_cast<size_t>(nc) * b->p->n3 * 8, s));
+  HIP_TRY(hipMemsetAsync(b->dU, 0, nc * 8, s));
+  HIP_TRY(hipMemsetAsync(b->U, 0, nc * 8, s));
+  HIP_TRY(hipMemsetAsync(b->q, 0, nc * 8, s));
+  HIP_TRY(hipMemsetAsync(b->state, 0, ncase * 4 * 8, s));
+  HIP_TRY(hipMemsetAsync(b->iters, 0, ncase * 4, s));
+  std::vector<int32_t> ones(std::max<int64_t>(nc, ncase), 1);
+  HIP_TRY(hipMemcpyAsync(b->cact, ones.data(), ncase * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->lact, ones.data(), nc * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  b->total = 0;
+  return SIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o, hipStream_t stream,
+                            sis_state_t* out) {
+  if (sis_status st = check_plan(p)) return st;
+  if (!out) return fail(SIS_E_INVALID, "null output handle");
+  *out = nullptr;
+  if (!g || g->plan != p) return fail(SIS_E_INVALID, "geometry does not belong to this plan");
+  if (!o) return fail(SIS_E_INVALID, "null options");
+  if (o->scheme != SIS_SCHEME_CIS && o->scheme != SIS_SCHEME_SIS) return fail(SIS_E_INVALID, "unknown scheme");
+  if (!(o->eps >= 0.0)) return fail(SIS_E_INVALID, "eps must be >= 0");
+  if (o->max_it < 1) return fail(SIS_E_INVALID, "max_it must be >= 1");
+  auto* b = new sis_state();
+  b->p = p;
+  b->g = g;
+  b->o = *o;
+  b->Npen = o->N > 0.0 ? o->N : p->nubar;
+  const int64_t nc = g->n_cells;
+  const int ncase = g->n_cases;
+  const int n3 = p->n3;
+#define ST_TRY(expr)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      delete b;                                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s", #expr,         \
+                  hipGetErrorString(e_));                                                       \
+    }                                                                                           \
+  } while (0)
+  ST_TRY(dmalloc(&b->h, static_cast<size_t>(nc) * n3));
+  ST_TRY(dmalloc(&b->rhs, static_cast<size_t>(nc) * n3));
+  ST_TRY(dmalloc(&b->amom, nc * 4));
+  ST_TRY(dmalloc(&b->mom, nc * 4));
+  ST_TRY(dmalloc(&b->dU, nc));
+  ST_TRY(dmalloc(&b->U, nc));
+  ST_TRY(dmalloc(&b->q, nc));
+  ST_TRY(dmalloc(&b->state, ncase * 4));
+  ST_TRY(dmalloc(&b->iters, ncase));
+  ST_TRY(dmalloc(&b->cact, ncase));
+  ST_TRY(dmalloc(&b->lact, nc));
+  {
+    int tile, splits;
+    choose_gemm(nc, n3, &tile, &splits);
+    if (splits > 1) ST_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
+    const int W = (n3 / 2 + 63) / 64;
+    ST_TRY(p->ws_part.ensure(static_cast<size_t>(nc) * 8 * W * 8));
+  }
+  hipStream_t s = stream;
+  if (o->use_graph) {
+    ST_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    s = b->cap;
+  }
+  if (sis_status st = state_init(b, s)) { delete b; return st; }
+  if (o->use_graph) {
+    ST_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    sis_status st = state_iteration(b, b->cap);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &gr);
+    if (st) { if (gr) (void)hipGraphDestroy(gr); delete b; return st; }
+    ST_TRY(e);
+    b->graph = gr;
+    ST_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+#undef ST_TRY
+  *out = b;
+  g_err.clear();
+  return SIS_OK;
+}
+
+sis_status sis_state_reset(sis_state_t b, hipStream_t stream) {
+  if (!b) return fail(SIS_E_INVALID, "null state");
+  return state_init(b, stream);
+}
+
+sis_status sis_state_step(sis_state_t b, int32_t n_iters, hipStream_t stream) {
+  if (!b) return fail(SIS_E_INVALID, "null state");
+  if (n_iters < 0) return fail(SIS_E_INVALID, "n_iters must be >= 0");
+  for (int i = 0; i < n_iters; ++i) {
+    if (b->exec) {
+      HIP_TRY(hipGraphLaunch(b->exec, stream));
+    } else if (sis_status st = state_iteration(b, stream)) {
+      return st;
+    }
+  }
+  b->total += n_iters;
+  return SIS_OK;
+}
+
+sis_status sis_state_poll(sis_state_t b, int32_t* n_active, hipStream_t stream) {
+  if (!b || !n_active) return fail(SIS_E_INVALID, "null argument");
+  std::vector<int32_t> act(b->g->n_cases);
+  HIP_TRY(hipMemcpyAsync(act.data(), b->cact, act.size() * 4, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  int n = 0;
+  for (int32_t a : act) n += a != 0;
+  *n_active = n;
+  return SIS_OK;
+}
+
+sis_status sis_state_results(sis_state_t b, sis_solve_result* r, hipStream_t stream) {
+  if (!b || !r) return fail(SIS_E_INVALID, "null argument");
+  const int ncase = b->g->n_cases;
+  const int64_t nc = b->g->n_cells;
+  HIP_TRY(hipStreamSynchronize(stream));
+  std::vector<double> st(static_cast<size_t>(ncase) * 4);
+  std::vector<int32_t> hit(ncase);
+  HIP_TRY(hipMemcpy(st.data(), b->state, ncase * 4 * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hit.data(), b->iters, ncase * 4, hipMemcpyDeviceToHost));
+  if (r->U) HIP_TRY(hipMemcpy(r->U, b->U, nc * 8, hipMemcpyDeviceToHost));
+  if (r->q) HIP_TRY(hipMemcpy(r->q, b->q, nc * 8, hipMemcpyDeviceToHost));
+  bool nan = false, notconv = false;
+  for (int c = 0; c < ncase; ++c) {
+    if (r->M) r->M[c] = st[c * 4 + 0];
+    if (r->Q) r->Q[c] = st[c * 4 + 1];
+    if (r->residual) r->residual[c] = st[c * 4 + 2];
+    if (r->iters) r->iters[c] = hit[c];
+    if (!std::isfinite(st[c * 4 + 0]) || !std::isfinite(st[c * 4 + 1])) nan = true;
+    if (!(st[c * 4 + 2] < b->o.eps)) notconv = true;
+  }
+  r->seconds = 0.0;
+  r->total_iters = b->total;
+  if (nan) return fail(SIS_E_NUMERIC, "NaN/Inf in a flow rate");
+  if (notconv) return fail(SIS_E_NOT_CONVERGED, "not every case has converged");
+  g_err.clear();
+  return SIS_OK;
+}
+
+sis_status sis_state_destroy(sis_state_t b) {
+  if (!b) return fail(SIS_E_INVALID, "null state");
+  delete b;
+  return SIS_OK;
+}
+
+sis_status sis_solve(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o, sis_solve_result* r,
+                     hipStream_t user_stream) {
+  if (!r) return fail(SIS_E_INVALID, "null result");
+  hipStream_t s = user_stream;
+  sis_state_t b = nullptr;
+  if (sis_status st = sis_state_create(p, g, o, s, &b)) return st;
+  const int every = o->check_every > 0 ? o->check_every : 4;
+  auto t0 = std::chrono::steady_clock::now();
+  int total = 0;
+  for (;;) {
+    const int k = std::min(every, o->max_it - total);
+    if (sis_status st = sis_state_step(b, k, s)) { sis_state_destroy(b); return st; }
+    total += k;
+    int32_t active = 0;
+    if (sis_status st = sis_state_poll(b, &active, s)) { sis_state_destroy(b); return st; }
+    if (active == 0 || total >= o->max_it) break;
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  sis_status st = sis_state_results(b, r, s);
+  r->seconds = std::chrono::duration<double>(t1 - t0).count();
+  std::string keep = g_err;
+  sis_state_destroy(b);
+  g_err = keep;
+  return st;
+}
+
+sis_status sis_plan_timing(sis_plan_t p, int32_t enable) {
+  if (sis_status st = check_plan(p)) return st;
+  for (auto& e : p->events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  p->events.clear();
+  p->timing = enable != 0;
+  return SIS_OK;
+}
+
+sis_status sis_plan_timing_read(sis_plan_t p, double* ms, int64_t* launches) {
+  if (sis_status st = check_plan(p)) return st;
+  double tot = 0.0;
+  for (auto& e : p->events) {
+    HIP_TRY(hipEventSynchronize(e.second));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, e.first, e.second));
+    tot += t;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = static_cast<int64_t>(p->events.size());
+  return SIS_OK;
+}
+
+}  // extern "C"

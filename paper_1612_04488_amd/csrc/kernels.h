@@ -1,0 +1,113 @@
+// Launch wrappers of the device kernels (kernels.hip).  All pointers are
+// device pointers; every wrapper enqueues on `s` and returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sis {
+
+// Operator assembly: op[i][j] = sum_p [Bs_p(i) Psi_p(i-j) + As_p(i) Phi_p(i-j)] - feq(i) beta_r(i-j)
+// (As, Bs pre-scaled by 4 b0 W_p).  n3 x n3 row-major output.
+hipError_t launch_assemble(int n, int D, const double* Psi, const double* Phi, const double* As,
+                           const double* Bs, const double* feq, const double* beta_r, double* op,
+                           hipStream_t s);
+
+// op2 = op (double) rounded to float / split into bf16 hi + lo.
+hipError_t launch_convert_f32(const double* op, float* out, int64_t count, hipStream_t s);
+hipError_t launch_split_bf16(const double* op, uint16_t* hi, uint16_t* lo, int64_t count, hipStream_t s);
+
+// Contraction acc[z][m][n] = sum_{k in split z} X[m][k] * op[n][k]  (op stored n x k).
+// precision: 0 fp64 (op64), 1 fp32 (op32), 2 bf16x3 (ophi/oplo).  Accumulators
+// are written as double for every precision.
+struct GemmArgs {
+  int precision;
+  const double* X;
+  const double* op64;
+  const float* op32;
+  const uint16_t* ophi;
+  const uint16_t* oplo;
+  double* acc;
+  int64_t M;
+  int N, K;
+  int splits;        // split-K factor (grid.z)
+  int tile;          // tile configuration id (0 large, 1 small-M)
+};
+hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
+int gemm_k_per_split(int K, int splits);
+
+struct FinishArgs {
+  int n, n3;
+  int64_t n_cells;
+  int splits;
+  const double* acc;       // [splits][n_cells][n3]
+  const double* h;         // [n_cells][n3]
+  const double* dU;        // [n_cells] or null
+  const double* delta;     // [n_cells]
+  const int32_t* flow;     // [n_cells] or null
+  int project;
+  const double* v1d;       // [n]
+  const double* feq;       // [n3]
+  const double* nu;        // [n3]
+  const double* Kc;        // [n3]  L+_1(2 v3 feq)
+  const double* gram_inv;  // [25]
+  double w;
+  const int32_t* active;   // [n_cells] or null: skip cells with active == 0
+  double* rhs;             // [n_cells][n3]  (may alias acc when splits == 1)
+  double* lh;              // [n_cells][n3] or null
+  double* amom;            // [n_cells][4] or null
+};
+hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
+
+struct SweepArgs {
+  int n, n3;
+  int n_cases;
+  const int64_t* node_off;   // [n_cases+1]
+  const double* coef;        // [cells][6]: backward a,b,c ; forward a,b,c
+  const double* delta_case;  // [n_cases]
+  const double* v1d;         // [n]
+  const double* nu;          // [n3]
+  const double* rhs;         // [cells][n3]
+  double* h;                 // [cells][n3]
+  double* part;              // [cells][2][4][W] wave partials of {U3, q3, G1, P13}
+  int W;                     // waves per case = n3 / 128
+  const int32_t* case_active;// [n_cases] or null
+  double w;
+  int max_nodes;
+};
+hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s);
+// mom[cell][4] = sum over the wave partials (fixed order)
+hipError_t launch_reduce_partials(const double* part, int W, int64_t n_cells, double* mom,
+                                  hipStream_t s);
+// mom[cell][4] = {U3, q3, G1, P13} of h directly
+hipError_t launch_moments(int n, int n3, int64_t n_cells, const double* v1d, const double* h,
+                          double w, double* mom, hipStream_t s);
+
+struct DiffusionArgs {
+  int n_cases;
+  const int64_t* node_off;
+  const double* x;           // [cells]
+  const double* coef;        // [cells][6]
+  const double* delta_case;  // [n_cases]
+  const int32_t* flow_case;  // [n_cases]
+  const double* mom;         // [cells][4]
+  const double* amom;        // [cells][4] or null
+  double N;
+  int sis;                   // 1: solve the velocity equation; 0: dU = 0 (CIS)
+  double cU, cq;             // moments U3, q3 of the correction shape 2 v3 f_eq
+  double* U;                 // [cells] or null
+  double* dU;                // [cells] or null
+  // solver state (all null outside sis_solve)
+  double* state;             // [n_cases][4]: M_prev, Q_prev, residual, M  (+ Q in [n_cases][4]+..)
+  int32_t* iters;            // [n_cases]
+  int32_t* case_active;      // [n_cases]
+  double* qfield;            // [cells] q3 of the new iterate or null
+  double* ufield;            // [cells] U3 of the new iterate or null
+  double eps;
+};
+hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s);
+
+// cell_active[c] = case_active[case_of_cell[c]]
+hipError_t launch_expand_active(const int32_t* case_active, const int32_t* case_of_cell,
+                                int64_t n_cells, int32_t* cell_active, hipStream_t s);
+
+}  // namespace sis

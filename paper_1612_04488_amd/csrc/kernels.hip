@@ -1,0 +1,837 @@
+// Device kernels of the SIS hot path for gfx950 (CDNA4, 64-wide wavefronts).
+//
+//  assemble      plan-time: dense matrix of h -> L+(h) from the fast-spectral
+//                real-space kernels (one 32x32 output tile per workgroup,
+//                direction tables staged through LDS)
+//  gemm          collision contraction acc = X * op^T on MFMA
+//                (FP64 v_mfma_f64_16x16x4; FP32 / 3xBF16 variants)
+//  finish        per-cell epilogue: correction of eq. guided, delta scaling,
+//                source, L, moments A1/A2, invariant projection
+//  sweep1d       upwind transport sweep per velocity pair (+v1, -v1),
+//                moments of h^{k+1/2} as per-wave partial sums
+//  diffusion1d   per-case march of the SIS velocity equation, flow rates,
+//                convergence test
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace sis {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of K values per thread, fixed order.  Result in out[] for all threads.
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double* sh /* >= 4*K */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) sh[wave * K + k] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w * K + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ assemble
+constexpr int kAsmPB = 8;      // directions staged per LDS round
+constexpr int kAsmOuts = 7;    // outputs per thread (n^2 <= 256 * 7)
+
+__global__ __launch_bounds__(256) void assemble_kernel(int n, int D, const double* __restrict__ Psi,
+                                                       const double* __restrict__ Phi,
+                                                       const double* __restrict__ As,
+                                                       const double* __restrict__ Bs,
+                                                       const double* __restrict__ feq,
+                                                       const double* __restrict__ beta_r,
+                                                       double* __restrict__ op) {
+  const int nd = 2 * n - 1;
+  const int n3 = n * n * n;
+  const int bi = blockIdx.x, bj = blockIdx.y;
+  const int i0 = bi / n, i1 = bi % n, j0 = bj / n, j1 = bj % n;
+  const int d0 = i0 - j0 + n - 1, d1 = i1 - j1 + n - 1;
+  extern __shared__ double sm[];
+  double* sPsi = sm;
+  double* sPhi = sm + kAsmPB * nd;
+  double* sA = sm + 2 * kAsmPB * nd;
+  double* sB = sA + kAsmPB * n;
+  const int nout = n * n;
+  double acc[kAsmOuts];
+#pragma unroll
+  for (int k = 0; k < kAsmOuts; ++k) acc[k] = 0.0;
+  const size_t row = (static_cast<size_t>(d0) * nd + d1) * nd;
+  for (int p0 = 0; p0 < D; p0 += kAsmPB) {
+    const int pb = min(kAsmPB, D - p0);
+    for (int q = threadIdx.x; q < pb * nd; q += blockDim.x) {
+      const int pp = q / nd, r = q % nd;
+      const size_t src = static_cast<size_t>(p0 + pp) * nd * nd * nd + row + r;
+      sPsi[pp * nd + r] = Psi[src];
+      sPhi[pp * nd + r] = Phi[src];
+    }
+    for (int q = threadIdx.x; q < pb * n; q += blockDim.x) {
+      const int pp = q / n, r = q % n;
+      const size_t src = static_cast<size_t>(p0 + pp) * n3 + static_cast<size_t>(bi) * n + r;
+      sA[pp * n + r] = As[src];
+      sB[pp * n + r] = Bs[src];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kAsmOuts; ++k) {
+      const int o = threadIdx.x + k * blockDim.x;
+      if (o < nout) {
+        const int i2 = o / n, j2 = o % n, dd = i2 - j2 + n - 1;
+        double a = acc[k];
+        for (int pp = 0; pp < pb; ++pp)
+          a += sB[pp * n + i2] * sPsi[pp * nd + dd] + sA[pp * n + i2] * sPhi[pp * nd + dd];
+        acc[k] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kAsmOuts; ++k) {
+    const int o = threadIdx.x + k * blockDim.x;
+    if (o < nout) {
+      const int i2 = o / n, j2 = o % n, dd = i2 - j2 + n - 1;
+      const int ii = bi * n + i2, jj = bj * n + j2;
+      op[static_cast<size_t>(ii) * n3 + jj] = acc[k] - feq[ii] * beta_r[row + dd];
+    }
+  }
+}
+
+__global__ void convert_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = static_cast<float>(in[i]);
+}
+
+__device__ inline uint16_t bf16_rne(float f) {
+  const uint32_t b = __float_as_uint(f);
+  const uint32_t r = b + 0x7FFFu + ((b >> 16) & 1u);
+  return static_cast<uint16_t>(r >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+__global__ void split_bf16_kernel(const double* __restrict__ in, uint16_t* __restrict__ hi,
+                                  uint16_t* __restrict__ lo, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) {
+    const double x = in[i];
+    const uint16_t h = bf16_rne(static_cast<float>(x));
+    hi[i] = h;
+    lo[i] = bf16_rne(static_cast<float>(x - static_cast<double>(bf16_to_f32(h))));
+  }
+}
+
+// ------------------------------------------------------------------ FP64 MFMA GEMM
+// acc[z][m][n] = sum_{k in [z*kps, min(K,(z+1)*kps))} X[m][k] * Op[n][k]
+// Both operands are k-contiguous.  LDS tiles are stored k-major so that the
+// 16 lanes of an MFMA operand column read 16 consecutive doubles.
+constexpr int kBK = 16;
+constexpr int kPad = 4;
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict__ X,
+                                                       const double* __restrict__ Op,
+                                                       double* __restrict__ C, int64_t M, int N,
+                                                       int K, int kps) {
+  constexpr int WAVES_N = BN / WN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int A_LD = BM * kBK / 2 / 256;
+  constexpr int B_LD = BN * kBK / 2 / 256;
+  static_assert((BM / WM) * (BN / WN) == 4, "4 waves per workgroup");
+  static_assert(A_LD >= 1 && B_LD >= 1, "tile too small");
+  __shared__ double As[2][kBK][BM + kPad];
+  __shared__ double Bs[2][kBK][BN + kPad];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM;
+  const int n0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * kps;
+  const int kend = min(K, kbeg + kps);
+  double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
+
+  double2 ra[A_LD], rb[B_LD];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (kBK / 2), kc = (q % (kBK / 2)) * 2;
+      const int64_t gm = m0 + r;
+      const int gk = k0 + kc;
+      ra[i] = (gm < M && gk < kend) ? *reinterpret_cast<const double2*>(X + gm * K + gk)
+                                    : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (kBK / 2), kc = (q % (kBK / 2)) * 2;
+      const int gn = n0 + r;
+      const int gk = k0 + kc;
+      rb[i] = (gn < N && gk < kend)
+                  ? *reinterpret_cast<const double2*>(Op + static_cast<int64_t>(gn) * K + gk)
+                  : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (kBK / 2), kc = (q % (kBK / 2)) * 2;
+      As[buf][kc][r] = ra[i].x;
+      As[buf][kc + 1][r] = ra[i].y;
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (kBK / 2), kc = (q % (kBK / 2)) * 2;
+      Bs[buf][kc][r] = rb[i].x;
+      Bs[buf][kc + 1][r] = rb[i].y;
+    }
+  };
+
+  v4d acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = kend > kbeg ? (kend - kbeg + kBK - 1) / kBK : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  const int kr = lane >> 4, cc = lane & 15;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kbeg + (kt + 1) * kBK);
+#pragma unroll
+    for (int kk = 0; kk < kBK / 4; ++kk) {
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[cur][kk * 4 + kr][wm + i * 16 + cc];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[cur][kk * 4 + kr][wn + j * 16 + cc];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+  // D layout of the 16x16x4 FP64 MFMA: lane l, element r -> row (l/16) + 4 r,
+  // column l%16 (rows interleaved, unlike the FP32 forms)
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm + i * 16 + kr + 4 * r;
+        const int gn = n0 + wn + j * 16 + cc;
+        if (gm < M && gn < N) Cz[gm * N + gn] = acc[i][j][r];
+      }
+}
+
+// ------------------------------------------------------------------ FP32 MFMA GEMM
+// X is converted from double to float when staged; op is stored as float.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const double* __restrict__ X,
+                                                       const float* __restrict__ Op,
+                                                       double* __restrict__ C, int64_t M, int N,
+                                                       int K, int kps) {
+  constexpr int BK = 32;
+  constexpr int WAVES_N = BN / WN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int A_LD = BM * BK / 2 / 256;   // double2 loads of X
+  constexpr int B_LD = BN * BK / 4 / 256;   // float4 loads of Op
+  static_assert((BM / WM) * (BN / WN) == 4, "4 waves per workgroup");
+  static_assert(A_LD >= 1 && B_LD >= 1, "tile too small");
+  __shared__ float As[2][BK][BM + 4];
+  __shared__ float Bs[2][BK][BN + 4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM;
+  const int n0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * kps;
+  const int kend = min(K, kbeg + kps);
+  double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
+
+  double2 ra[A_LD];
+  float4 rb[B_LD];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
+      const int64_t gm = m0 + r;
+      const int gk = k0 + kc;
+      ra[i] = (gm < M && gk < kend) ? *reinterpret_cast<const double2*>(X + gm * K + gk)
+                                    : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (BK / 4), kc = (q % (BK / 4)) * 4;
+      const int gn = n0 + r;
+      const int gk = k0 + kc;
+      if (gn < N && gk + 3 < kend) {
+        rb[i] = *reinterpret_cast<const float4*>(Op + static_cast<int64_t>(gn) * K + gk);
+      } else {
+        float t[4];
+        for (int e = 0; e < 4; ++e)
+          t[e] = (gn < N && gk + e < kend) ? Op[static_cast<int64_t>(gn) * K + gk + e] : 0.0f;
+        rb[i] = make_float4(t[0], t[1], t[2], t[3]);
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
+      As[buf][kc][r] = static_cast<float>(ra[i].x);
+      As[buf][kc + 1][r] = static_cast<float>(ra[i].y);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (BK / 4), kc = (q % (BK / 4)) * 4;
+      Bs[buf][kc][r] = rb[i].x;
+      Bs[buf][kc + 1][r] = rb[i].y;
+      Bs[buf][kc + 2][r] = rb[i].z;
+      Bs[buf][kc + 3][r] = rb[i].w;
+    }
+  };
+
+  v4f acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  const int kr = lane >> 4, cc = lane & 15;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      float a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[cur][kk * 4 + kr][wm + i * 16 + cc];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[cur][kk * 4 + kr][wn + j * 16 + cc];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm + i * 16 + kr * 4 + r;
+        const int gn = n0 + wn + j * 16 + cc;
+        if (gm < M && gn < N) Cz[gm * N + gn] = static_cast<double>(acc[i][j][r]);
+      }
+}
+
+// ------------------------------------------------------------------ 3xBF16 MFMA GEMM
+// x ~ xh + xl, op ~ oh + ol (bf16 pairs); acc += xh*oh + xh*ol + xl*oh on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const double* __restrict__ X,
+                                                          const uint16_t* __restrict__ Oh,
+                                                          const uint16_t* __restrict__ Ol,
+                                                          double* __restrict__ C, int64_t M,
+                                                          int N, int K, int kps) {
+  constexpr int BK = 32;                      // one MFMA k-step
+  constexpr int WAVES_N = BN / WN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int A_LD = BM * BK / 2 / 256;     // double2 loads of X
+  constexpr int B_LD = BN * BK / 8 / 256;     // 8 x bf16 (16 B) loads of each op half
+  static_assert((BM / WM) * (BN / WN) == 4, "4 waves per workgroup");
+  static_assert(A_LD >= 1 && B_LD >= 1, "tile too small");
+  // LDS rows hold the 32 k-values of one m (or n) contiguously (+pad) so a lane
+  // reads its 8 consecutive k values as one 16-byte vector.
+  constexpr int RS = BK + 8;
+  __shared__ uint16_t Ah[2][BM][RS], Al[2][BM][RS];
+  __shared__ uint16_t Bh[2][BN][RS], Bl[2][BN][RS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM;
+  const int n0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * kps;
+  const int kend = min(K, kbeg + kps);
+  double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
+
+  double2 ra[A_LD];
+  uint4 rbh[B_LD], rbl[B_LD];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
+      const int64_t gm = m0 + r;
+      const int gk = k0 + kc;
+      ra[i] = (gm < M && gk < kend) ? *reinterpret_cast<const double2*>(X + gm * K + gk)
+                                    : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (BK / 8), kc = (q % (BK / 8)) * 8;
+      const int gn = n0 + r;
+      const int gk = k0 + kc;
+      if (gn < N && gk + 7 < kend) {
+        rbh[i] = *reinterpret_cast<const uint4*>(Oh + static_cast<int64_t>(gn) * K + gk);
+        rbl[i] = *reinterpret_cast<const uint4*>(Ol + static_cast<int64_t>(gn) * K + gk);
+      } else {
+        uint16_t th[8], tl[8];
+        for (int e = 0; e < 8; ++e) {
+          const bool ok = gn < N && gk + e < kend;
+          th[e] = ok ? Oh[static_cast<int64_t>(gn) * K + gk + e] : 0;
+          tl[e] = ok ? Ol[static_cast<int64_t>(gn) * K + gk + e] : 0;
+        }
+        rbh[i] = make_uint4(th[0] | (uint32_t(th[1]) << 16), th[2] | (uint32_t(th[3]) << 16),
+                            th[4] | (uint32_t(th[5]) << 16), th[6] | (uint32_t(th[7]) << 16));
+        rbl[i] = make_uint4(tl[0] | (uint32_t(tl[1]) << 16), tl[2] | (uint32_t(tl[3]) << 16),
+                            tl[4] | (uint32_t(tl[5]) << 16), tl[6] | (uint32_t(tl[7]) << 16));
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
+      const double x0 = ra[i].x, x1 = ra[i].y;
+      const uint16_t h0 = bf16_rne(static_cast<float>(x0)), h1 = bf16_rne(static_cast<float>(x1));
+      const uint16_t l0 = bf16_rne(static_cast<float>(x0 - static_cast<double>(bf16_to_f32(h0))));
+      const uint16_t l1 = bf16_rne(static_cast<float>(x1 - static_cast<double>(bf16_to_f32(h1))));
+      *reinterpret_cast<uint32_t*>(&Ah[buf][r][kc]) = h0 | (uint32_t(h1) << 16);
+      *reinterpret_cast<uint32_t*>(&Al[buf][r][kc]) = l0 | (uint32_t(l1) << 16);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q / (BK / 8), kc = (q % (BK / 8)) * 8;
+      *reinterpret_cast<uint4*>(&Bh[buf][r][kc]) = rbh[i];
+      *reinterpret_cast<uint4*>(&Bl[buf][r][kc]) = rbl[i];
+    }
+  };
+
+  v4f acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  // operand layout of the 16x16x32 bf16 MFMA: lane l holds row (l % 16),
+  // k = 8 * (l / 16) .. + 7
+  const int rr = lane & 15, kq = (lane >> 4) * 8;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+    v8bf ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      ah[i] = *reinterpret_cast<const v8bf*>(&Ah[cur][wm + i * 16 + rr][kq]);
+      al[i] = *reinterpret_cast<const v8bf*>(&Al[cur][wm + i * 16 + rr][kq]);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      bh[j] = *reinterpret_cast<const v8bf*>(&Bh[cur][wn + j * 16 + rr][kq]);
+      bl[j] = *reinterpret_cast<const v8bf*>(&Bl[cur][wn + j * 16 + rr][kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const int gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N) Cz[gm * N + gn] = static_cast<double>(acc[i][j][r]);
+      }
+}
+
+// ------------------------------------------------------------------ finish
+__global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
+  __shared__ double sh[4 * 9];
+  __shared__ double coef[5];
+  const int64_t c = blockIdx.x;
+  if (a.active && !a.active[c]) return;
+  const int n = a.n, n3 = a.n3, nn = n * n;
+  const double del = a.delta[c];
+  const int fl = a.flow ? a.flow[c] : 0;
+  const double dUc = a.dU ? a.dU[c] : 0.0;
+  const int64_t base = c * n3;
+  const int64_t sstride = a.n_cells * static_cast<int64_t>(n3);
+  double m[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m[k] = 0.0;
+  for (int v = threadIdx.x; v < n3; v += blockDim.x) {
+    const int j1 = v / nn, j2 = (v / n) % n, j3 = v % n;
+    const double v1 = a.v1d[j1], v2 = a.v1d[j2], v3 = a.v1d[j3];
+    const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+    const double f = a.feq[v];
+    double s = 0.0;
+    for (int z = 0; z < a.splits; ++z) s += a.acc[z * sstride + base + v];
+    const double lp = s + dUc * a.Kc[v];
+    const double hk = a.h[base + v] + dUc * 2.0 * v3 * f;
+    const double L = del * (lp - a.nu[v] * hk);
+    double S = 0.0;
+    if (fl == 1) S = v3 * f;
+    else if (fl == 2) S = v3 * (vsq - 2.5) * f;
+    a.rhs[base + v] = del * lp + S;
+    if (a.lh) a.lh[base + v] = L;
+    const double wL = a.w * L;
+    m[0] += wL;
+    m[1] += wL * v1;
+    m[2] += wL * v2;
+    m[3] += wL * v3;
+    m[4] += wL * vsq;
+    m[5] += 2.0 * a.w * v1 * v3 * L;
+    m[6] += 2.0 * a.w * v1 * v3 * hk;
+    m[7] += 2.0 * a.w * v2 * v3 * L;
+    m[8] += 2.0 * a.w * v2 * v3 * hk;
+  }
+  block_sum<9>(m, sh);
+  if (a.project) {
+    if (threadIdx.x < 5) {
+      double s = 0.0;
+      for (int k = 0; k < 5; ++k) s += a.gram_inv[threadIdx.x * 5 + k] * m[k];
+      coef[threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v < n3; v += blockDim.x) {
+      const int j1 = v / nn, j2 = (v / n) % n, j3 = v % n;
+      const double v1 = a.v1d[j1], v2 = a.v1d[j2], v3 = a.v1d[j3];
+      const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+      const double corr = a.feq[v] * (coef[0] + coef[1] * v1 + coef[2] * v2 + coef[3] * v3 + coef[4] * vsq);
+      a.rhs[base + v] -= corr;
+      if (a.lh) a.lh[base + v] -= corr;
+    }
+  }
+  if (a.amom && threadIdx.x == 0) {
+    a.amom[c * 4 + 0] = m[5];
+    a.amom[c * 4 + 1] = m[6];
+    a.amom[c * 4 + 2] = m[7];
+    a.amom[c * 4 + 3] = m[8];
+  }
+}
+
+// ------------------------------------------------------------------ sweep
+// One thread per velocity pair (v1 > 0 index jp, mirror jm) of one case.
+__global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
+  const int cs = blockIdx.y;
+  if (a.case_active && !a.case_active[cs]) return;
+  const int n = a.n, nn = n * n, half = a.n3 / 2, n3 = a.n3;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = t < half;
+  const int tt = valid ? t : 0;
+  const int wave = t >> 6;
+  const bool writer = (threadIdx.x & 63) == 0;
+  const int64_t c0 = a.node_off[cs];
+  const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
+  const int j1h = tt / nn, r = tt % nn;
+  const int jp = n / 2 + j1h, jm = n / 2 - 1 - j1h;
+  const int vp = jp * nn + r, vm = jm * nn + r;
+  const double v1 = a.v1d[jp];
+  const double v2 = a.v1d[r / n], v3 = a.v1d[r % n];
+  const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+  const double del = a.delta_case[cs];
+  const double dnp = del * a.nu[vp], dnm = del * a.nu[vm];
+  const double z = valid ? 1.0 : 0.0;
+  const double wU = z * a.w * v3, wq = z * a.w * (vsq - 2.5) * v3;
+  const double wG = z * a.w * v3 * (2.0 * v1 * v1 - 1.0), wP = z * 2.0 * a.w * v1 * v3;
+  const int W = a.W;
+  auto put = [&](int64_t cell, int pass, double h) {
+    const double s0 = wave_sum(wU * h), s1 = wave_sum(wq * h), s2 = wave_sum(wG * h);
+    const double s3 = wave_sum((pass == 0 ? wP : -wP) * h);
+    if (writer) {
+      double* p = a.part + ((cell * 2 + pass) * 4) * W + wave;
+      p[0] = s0;
+      p[W] = s1;
+      p[2 * W] = s2;
+      p[3 * W] = s3;
+    }
+  };
+  // v1 > 0: wall value 0, march towards the symmetry plane
+  double h1 = 0.0, h2 = 0.0;
+  if (valid) a.h[c0 * n3 + vp] = 0.0;
+  put(c0, 0, 0.0);
+  for (int i = 1; i < nodes; ++i) {
+    const int64_t cell = c0 + i;
+    const double ca = a.coef[cell * 6 + 0], cb = a.coef[cell * 6 + 1], cc = a.coef[cell * 6 + 2];
+    const double rhs = valid ? a.rhs[cell * n3 + vp] : 0.0;
+    const double val = (rhs - v1 * (cb * h1 + cc * h2)) / (dnp + v1 * ca);
+    if (valid) a.h[cell * n3 + vp] = val;
+    h2 = h1;
+    h1 = val;
+    put(cell, 0, val);
+  }
+  // v1 < 0: specular reflection at the last node, march to the wall
+  const int64_t last = c0 + nodes - 1;
+  double g1 = h1, g2 = 0.0;
+  if (valid) a.h[last * n3 + vm] = g1;
+  put(last, 1, g1);
+  for (int i = nodes - 2; i >= 0; --i) {
+    const int64_t cell = c0 + i;
+    const double ca = a.coef[cell * 6 + 3], cb = a.coef[cell * 6 + 4], cc = a.coef[cell * 6 + 5];
+    const double rhs = valid ? a.rhs[cell * n3 + vm] : 0.0;
+    const double val = (rhs - v1 * (cb * g1 + cc * g2)) / (dnm + v1 * ca);
+    if (valid) a.h[cell * n3 + vm] = val;
+    g2 = g1;
+    g1 = val;
+    put(cell, 1, val);
+  }
+}
+
+__global__ __launch_bounds__(64) void reduce_partials_kernel(const double* __restrict__ part, int W,
+                                                             double* __restrict__ mom) {
+  // one wave per cell: lanes stride over the 2 * W partials of each moment
+  const int64_t c = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int q = 0; q < 4; ++q) {
+    double s = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const double* p = part + ((c * 2 + pass) * 4 + q) * W;
+      for (int w = lane; w < W; w += 64) s += p[w];
+    }
+    s = wave_sum(s);
+    if (lane == 0) mom[c * 4 + q] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void moments_kernel(int n, int n3, const double* __restrict__ v1d,
+                                                      const double* __restrict__ h, double w,
+                                                      double* __restrict__ mom) {
+  __shared__ double sh[4 * 4];
+  const int64_t c = blockIdx.x;
+  const int nn = n * n;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int v = threadIdx.x; v < n3; v += blockDim.x) {
+    const double v1 = v1d[v / nn], v2 = v1d[(v / n) % n], v3 = v1d[v % n];
+    const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+    const double x = w * h[c * n3 + v];
+    m[0] += v3 * x;
+    m[1] += (vsq - 2.5) * v3 * x;
+    m[2] += v3 * (2.0 * v1 * v1 - 1.0) * x;
+    m[3] += 2.0 * v1 * v3 * x;
+  }
+  block_sum<4>(m, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) mom[c * 4 + k] = m[k];
+}
+
+// ------------------------------------------------------------------ diffusion (1-D)
+__global__ __launch_bounds__(64) void diffusion1d_kernel(DiffusionArgs a) {
+  const int cs = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  if (a.case_active && !a.case_active[cs]) return;
+  const int64_t c0 = a.node_off[cs];
+  const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
+  const double del = a.delta_case[cs];
+  const bool pois = a.flow_case[cs] == 1;
+  double y1 = 0.0, y2 = 0.0;
+  double Mr = 0.0, Qr = 0.0, Up = 0.0, qp = 0.0, xp = 0.0;
+  for (int i = 0; i < nodes; ++i) {
+    const int64_t cell = c0 + i;
+    const double Uh = a.mom[cell * 4 + 0], qh = a.mom[cell * 4 + 1], G1 = a.mom[cell * 4 + 2];
+    double dU = 0.0, Usol = Uh;
+    if (a.sis) {
+      double y;
+      if (i == 0) {
+        y = Uh + G1;
+      } else {
+        double A1 = 0.0;
+        if (a.amom) A1 = a.amom[cell * 4 + 0] + a.N * del * a.amom[cell * 4 + 1];
+        const double src = A1 - (pois ? a.N * del * a.x[cell] : 0.0);
+        const double ca = a.coef[cell * 6 + 0], cb = a.coef[cell * 6 + 1], cc = a.coef[cell * 6 + 2];
+        y = (src - cb * y1 - cc * y2) / ca;
+      }
+      y2 = y1;
+      y1 = y;
+      Usol = y - G1;
+      dU = Usol - Uh;
+    }
+    // moments of h^{k+1} = h^{k+1/2} + dU 2 v3 f_eq (eq. guided)
+    const double Un = Uh + dU * a.cU, qn = qh + dU * a.cq;
+    if (a.U) a.U[cell] = Usol;
+    if (a.dU) a.dU[cell] = dU;
+    if (a.qfield) a.qfield[cell] = qn;
+    if (a.ufield) a.ufield[cell] = Un;
+    const double x = a.x[cell];
+    if (i > 0) {
+      Mr += 0.5 * (Un + Up) * (x - xp);
+      Qr += 0.5 * (qn + qp) * (x - xp);
+    }
+    Up = Un;
+    qp = qn;
+    xp = x;
+  }
+  if (a.state) {
+    const double M = 2.0 * Mr, Q = 2.0 * Qr;
+    double* st = a.state + cs * 4;
+    const double dM = fabs(M - st[0]) / fmax(fabs(M), 1e-300);
+    const double dQ = fabs(Q - st[1]) / fmax(fabs(Q), 1e-300);
+    const double res = fmax(dM, dQ);
+    st[0] = M;
+    st[1] = Q;
+    st[2] = (M != M || Q != Q) ? __builtin_nan("") : res;
+    const int it = a.iters[cs] + 1;
+    a.iters[cs] = it;
+    if (!(res >= a.eps) || M != M || Q != Q) a.case_active[cs] = 0;
+    st[3] = static_cast<double>(it);
+  }
+}
+
+__global__ void expand_active_kernel(const int32_t* __restrict__ case_active,
+                                     const int32_t* __restrict__ case_of_cell, int64_t n_cells,
+                                     int32_t* __restrict__ cell_active) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n_cells) cell_active[i] = case_active[case_of_cell[i]];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_assemble(int n, int D, const double* Psi, const double* Phi, const double* As,
+                           const double* Bs, const double* feq, const double* beta_r, double* op,
+                           hipStream_t s) {
+  const int nd = 2 * n - 1;
+  const size_t shm = static_cast<size_t>(kAsmPB) * (2 * nd + 2 * n) * sizeof(double);
+  dim3 grid(n * n, n * n);
+  hipLaunchKernelGGL(assemble_kernel, grid, dim3(256), shm, s, n, D, Psi, Phi, As, Bs, feq, beta_r, op);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_f32(const double* op, float* out, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(convert_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, op, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_bf16(const double* op, uint16_t* hi, uint16_t* lo, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(split_bf16_kernel, dim3((count + 255) / 256), dim3(256), 0, s, op, hi, lo, count);
+  return hipGetLastError();
+}
+
+int gemm_k_per_split(int K, int splits) {
+  const int unit = 32;  // multiple of every BK
+  int kps = (K + splits - 1) / splits;
+  kps = (kps + unit - 1) / unit * unit;
+  return kps;
+}
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
+  const int kps = gemm_k_per_split(g.K, g.splits);
+  const int BN = 128;
+  const int BM = g.tile == 0 ? 128 : 32;
+  dim3 grid((g.N + BN - 1) / BN, static_cast<unsigned>((g.M + BM - 1) / BM), g.splits);
+  if (g.precision == 0) {
+    if (g.tile == 0)
+      hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
+    else
+      hipLaunchKernelGGL((gemm_f64_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
+  } else if (g.precision == 1) {
+    if (g.tile == 0)
+      hipLaunchKernelGGL((gemm_f32_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.op32, g.acc, g.M, g.N, g.K, kps);
+    else
+      hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.op32, g.acc, g.M, g.N, g.K, kps);
+  } else {
+    if (g.tile == 0)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
+    else
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(finish_kernel, dim3(static_cast<unsigned>(a.n_cells)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s) {
+  const int half = a.n3 / 2;
+  dim3 grid((half + 255) / 256, a.n_cases);
+  hipLaunchKernelGGL(sweep1d_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* part, int W, int64_t n_cells, double* mom, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(static_cast<unsigned>(n_cells)), dim3(64), 0, s, part, W, mom);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int n, int n3, int64_t n_cells, const double* v1d, const double* h,
+                          double w, double* mom, hipStream_t s) {
+  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>(n_cells)), dim3(256), 0, s, n, n3, v1d, h, w, mom);
+  return hipGetLastError();
+}
+
+hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(diffusion1d_kernel, dim3(a.n_cases), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_active(const int32_t* case_active, const int32_t* case_of_cell,
+                                int64_t n_cells, int32_t* cell_active, hipStream_t s) {
+  hipLaunchKernelGGL(expand_active_kernel, dim3(static_cast<unsigned>((n_cells + 255) / 256)), dim3(256), 0, s,
+                     case_active, case_of_cell, n_cells, cell_active);
+  return hipGetLastError();
+}
+
+}  // namespace sis

@@ -1,0 +1,43 @@
+// Host-side construction of the velocity grid and of the fast-spectral
+// collision tables (no device code).  See planner.cpp for the definitions.
+#pragma once
+#include <string>
+#include <vector>
+
+namespace sis {
+
+struct Quadrature {
+  std::vector<double> x, w;
+};
+
+// Gauss quadrature for the weight (1-x)^a (1+x)^b on [-1, 1] (Golub-Welsch).
+bool gauss_jacobi(int n, double a, double b, Quadrature& q);
+
+// Kernel amplitude b0 for delta = 1 (first Chapman-Enskog viscosity).
+double b0_unit(double alpha, double gamma);
+
+struct TableDesc {
+  int n_v = 16;
+  double l_v = 6.0;
+  int n_pad = 0;
+  int m_angle = 6;
+  double r_trunc = 0.0;
+  double alpha = 1.0, gamma = 0.0;
+  int n_threads = 0;
+};
+
+struct HostTables {
+  int n = 0, n3 = 0, np = 0, nd = 0, nd3 = 0, D = 0;
+  double lv = 0, dv = 0, Lp = 0, R = 0, b0 = 0, nubar = 0, alpha = 1, gamma = 0;
+  std::vector<double> v1d;          // [n]
+  std::vector<double> feq, nu;      // [n3], nu at delta = 1
+  std::vector<double> W;            // [D] direction weights
+  std::vector<double> A, B;         // [D][n3]  F^-1[psi_p F f_eq], F^-1[phi_p F f_eq]
+  std::vector<double> Psi, Phi;     // [D][nd3] real-space kernels on d in [-(n-1), n-1]^3
+  std::vector<double> beta_r;       // [nd3]    real-space loss kernel F^-1[beta]
+};
+
+// Build all tables.  want_kernels = false skips Psi/Phi/beta_r (cheaper).
+bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std::string& err);
+
+}  // namespace sis

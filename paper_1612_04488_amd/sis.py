@@ -1,0 +1,343 @@
+"""Thin ctypes binding of libsis.so (include/sis.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch provides device memory and the current stream.  If the
+library has not been built this module raises on import of the library
+(no fallback of any kind).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsis.so")
+
+SIS_OK = 0
+SIS_E_INVALID = -1
+SIS_E_SHAPE = -2
+SIS_E_DEVICE = -3
+SIS_E_OOM = -4
+SIS_E_NOT_CONVERGED = -5
+SIS_E_NUMERIC = -6
+SIS_E_UNSUPPORTED = -7
+
+KERNEL_HARD_SPHERE = 0
+KERNEL_IPL = 1
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
+FLOW_NONE, FLOW_POISEUILLE, FLOW_TRANSPIRATION = 0, 1, 2
+SCHEME_CIS, SCHEME_SIS = 0, 1
+GEOM_PLANAR_HALF = 0
+
+
+class SisError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sis error {code}: {msg}")
+        self.code = code
+
+
+class VelocityDesc(ctypes.Structure):
+    _fields_ = [("n_v", ctypes.c_int32), ("l_v", ctypes.c_double), ("n_pad", ctypes.c_int32),
+                ("m_angle", ctypes.c_int32), ("r_trunc", ctypes.c_double),
+                ("kernel", ctypes.c_int32), ("visc_index", ctypes.c_double),
+                ("n_threads", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_v", ctypes.c_int32), ("n3", ctypes.c_int32), ("n_pad", ctypes.c_int32),
+                ("m_angle", ctypes.c_int32), ("n_dir", ctypes.c_int32),
+                ("l_v", ctypes.c_double), ("dv", ctypes.c_double), ("b0", ctypes.c_double),
+                ("r_trunc", ctypes.c_double), ("nubar", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("operator_bytes", ctypes.c_int64), ("plan_seconds_host", ctypes.c_double),
+                ("plan_seconds_device", ctypes.c_double)]
+
+
+class GeometryDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_cases", ctypes.c_int32),
+                ("node_offset", ctypes.POINTER(ctypes.c_int64)),
+                ("x1", ctypes.POINTER(ctypes.c_double)),
+                ("delta", ctypes.POINTER(ctypes.c_double)),
+                ("flow", ctypes.POINTER(ctypes.c_int32))]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("N", ctypes.c_double), ("eps", ctypes.c_double),
+                ("max_it", ctypes.c_int32), ("project", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("M", ctypes.POINTER(ctypes.c_double)), ("Q", ctypes.POINTER(ctypes.c_double)),
+                ("iters", ctypes.POINTER(ctypes.c_int32)),
+                ("residual", ctypes.POINTER(ctypes.c_double)),
+                ("U", ctypes.POINTER(ctypes.c_double)), ("q", ctypes.POINTER(ctypes.c_double)),
+                ("seconds", ctypes.c_double), ("total_iters", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "sis_last_error": (ctypes.c_char_p, []),
+    "sis_version": (ctypes.c_int32, []),
+    "sis_plan_create": (ctypes.c_int32, [ctypes.POINTER(VelocityDesc), _P, ctypes.POINTER(_P)]),
+    "sis_plan_destroy": (ctypes.c_int32, [_P]),
+    "sis_plan_query": (ctypes.c_int32, [_P, ctypes.POINTER(PlanInfo)]),
+    "sis_plan_tables": (ctypes.c_int32, [_P, _P, _P, _P, _P]),
+    "sis_host_tables": (ctypes.c_int32, [ctypes.POINTER(VelocityDesc), _P, _P, _P, _P, _D, _D]),
+    "sis_plan_set_precision": (ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    "sis_geometry_create": (ctypes.c_int32, [_P, ctypes.POINTER(GeometryDesc), _P, ctypes.POINTER(_P)]),
+    "sis_geometry_destroy": (ctypes.c_int32, [_P]),
+    "sis_geometry_cells": (ctypes.c_int64, [_P]),
+    "sis_collide": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
+    "sis_transport_sweep": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
+    "sis_moments": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P]),
+    "sis_diffusion_correct": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P]),
+    "sis_solve": (ctypes.c_int32, [_P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveResult), _P]),
+    "sis_state_create": (ctypes.c_int32, [_P, _P, ctypes.POINTER(SolveOpts), _P, ctypes.POINTER(_P)]),
+    "sis_state_reset": (ctypes.c_int32, [_P, _P]),
+    "sis_state_step": (ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    "sis_state_poll": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
+    "sis_state_results": (ctypes.c_int32, [_P, ctypes.POINTER(SolveResult), _P]),
+    "sis_state_destroy": (ctypes.c_int32, [_P]),
+    "sis_plan_timing": (ctypes.c_int32, [_P, ctypes.c_int32]),
+    "sis_plan_timing_read": (ctypes.c_int32, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsis.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1612_04488_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != SIS_OK:
+        raise SisError(code, lib().sis_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    """Device pointer of a tensor (or None)."""
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def velocity_desc(n_v, l_v=6.0, n_pad=0, m_angle=6, kernel="hs", visc_index=0.81,
+                  r_trunc=0.0, n_threads=0):
+    k = KERNEL_HARD_SPHERE if kernel == "hs" else KERNEL_IPL
+    return VelocityDesc(n_v, l_v, n_pad, m_angle, r_trunc, k, visc_index, n_threads)
+
+
+def host_tables(desc):
+    """Host-only tables (no GPU): dict with feq, nu, A, B (numpy), b0, nubar."""
+    import numpy as np
+    n3 = desc.n_v ** 3
+    D = desc.m_angle ** 2
+    feq, nu = np.zeros(n3), np.zeros(n3)
+    A, B = np.zeros((D, n3)), np.zeros((D, n3))
+    b0, nubar = ctypes.c_double(), ctypes.c_double()
+    check(lib().sis_host_tables(ctypes.byref(desc), feq.ctypes.data_as(_P), nu.ctypes.data_as(_P),
+                                A.ctypes.data_as(_P), B.ctypes.data_as(_P),
+                                ctypes.byref(b0), ctypes.byref(nubar)))
+    return dict(feq=feq, nu=nu, A=A, B=B, b0=b0.value, nubar=nubar.value)
+
+
+class Plan:
+    """Velocity grid + assembled fast-spectral operator on the current device."""
+
+    def __init__(self, n_v, l_v=6.0, n_pad=0, m_angle=6, kernel="hs", visc_index=0.81,
+                 r_trunc=0.0, n_threads=0, stream=None):
+        self.desc = velocity_desc(n_v, l_v, n_pad, m_angle, kernel, visc_index, r_trunc, n_threads)
+        h = ctypes.c_void_p()
+        check(lib().sis_plan_create(ctypes.byref(self.desc), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.n_v = n_v
+        self.n3 = n_v ** 3
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sis_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self):
+        i = PlanInfo()
+        check(lib().sis_plan_query(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+
+    def tables(self, operator=False):
+        import numpy as np
+        v1d, feq, nu = np.zeros(self.n_v), np.zeros(self.n3), np.zeros(self.n3)
+        op = np.zeros((self.n3, self.n3)) if operator else None
+        check(lib().sis_plan_tables(self.handle, v1d.ctypes.data_as(_P), feq.ctypes.data_as(_P),
+                                    nu.ctypes.data_as(_P),
+                                    op.ctypes.data_as(_P) if operator else None))
+        return dict(v1d=v1d, feq=feq, nu=nu, op=op)
+
+    def set_precision(self, precision, stream=None):
+        p = PRECISIONS.get(precision, precision)
+        check(lib().sis_plan_set_precision(self.handle, p, _stream(stream)))
+
+    def collide(self, h, delta, rhs_out, dU=None, flow=None, project=False, lh_out=None,
+                amom_out=None, stream=None):
+        n_cells = h.shape[0]
+        check(lib().sis_collide(self.handle, n_cells, _ptr(h), _ptr(dU), _ptr(delta), _ptr(flow),
+                                1 if project else 0, _ptr(rhs_out), _ptr(lh_out), _ptr(amom_out),
+                                _stream(stream)))
+
+    def timing(self, enable):
+        check(lib().sis_plan_timing(self.handle, 1 if enable else 0))
+
+    def timing_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(lib().sis_plan_timing_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def moments(self, h, mom_out, stream=None):
+        check(lib().sis_moments(self.handle, h.shape[0], _ptr(h), _ptr(mom_out), _stream(stream)))
+
+
+class Geometry:
+    """Planar half-channel geometry for a batch of cases (host arrays copied)."""
+
+    def __init__(self, plan, xs, deltas, flows, stream=None):
+        import numpy as np
+        self.plan = plan
+        off = np.zeros(len(xs) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([len(x) for x in xs])
+        self.offsets = off
+        self._x = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64) for x in xs]))
+        self._d = np.ascontiguousarray(np.asarray(deltas, np.float64))
+        self._f = np.ascontiguousarray(np.asarray(flows, np.int32))
+        d = GeometryDesc(GEOM_PLANAR_HALF, len(xs),
+                         self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                         self._x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         self._d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         self._f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        h = ctypes.c_void_p()
+        check(lib().sis_geometry_create(plan.handle, ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.n_cells = int(off[-1])
+        self.n_cases = len(xs)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sis_geometry_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def transport_sweep(plan, geom, rhs, h_half_out, mom_out=None, stream=None):
+    check(lib().sis_transport_sweep(plan.handle, geom.handle, _ptr(rhs), _ptr(h_half_out),
+                                    _ptr(mom_out), _stream(stream)))
+
+
+def diffusion_correct(plan, geom, mom_half, amom, N, U_out=None, dU_out=None, stream=None):
+    check(lib().sis_diffusion_correct(plan.handle, geom.handle, _ptr(mom_half), _ptr(amom),
+                                      float(N), _ptr(U_out), _ptr(dU_out), _stream(stream)))
+
+
+def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False,
+          check_every=4, use_graph=True, stream=None, raise_not_converged=True):
+    """Run sis_solve; returns a dict of numpy arrays (M, Q, iters, residual, U, q)."""
+    import numpy as np
+    nc, ns = geom.n_cells, geom.n_cases
+    M, Q, res = np.zeros(ns), np.zeros(ns), np.zeros(ns)
+    it = np.zeros(ns, dtype=np.int32)
+    U, q = np.zeros(nc), np.zeros(nc)
+    r = SolveResult(M.ctypes.data_as(_D), Q.ctypes.data_as(_D),
+                    it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), res.ctypes.data_as(_D),
+                    U.ctypes.data_as(_D), q.ctypes.data_as(_D), 0.0, 0)
+    o = SolveOpts(SCHEME_SIS if scheme == "SIS" else SCHEME_CIS, float(N), float(eps), int(max_it),
+                  1 if project else 0, int(check_every), 1 if use_graph else 0)
+    code = lib().sis_solve(plan.handle, geom.handle, ctypes.byref(o), ctypes.byref(r), _stream(stream))
+    if code != SIS_OK and not (code == SIS_E_NOT_CONVERGED and not raise_not_converged):
+        check(code)
+    return dict(M=M, Q=Q, iters=it, residual=res, U=U, q=q, seconds=r.seconds,
+                total_iters=r.total_iters, status=code)
+
+
+def _opts(scheme, N, eps, max_it, project, check_every, use_graph):
+    return SolveOpts(SCHEME_SIS if scheme == "SIS" else SCHEME_CIS, float(N), float(eps),
+                     int(max_it), 1 if project else 0, int(check_every), 1 if use_graph else 0)
+
+
+class State:
+    """Persistent iteration state of sis_solve (sis_state_* entry points)."""
+
+    def __init__(self, plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False,
+                 use_graph=True, stream=None):
+        self.plan, self.geom = plan, geom
+        o = _opts(scheme, N, eps, max_it, project, 4, use_graph)
+        h = ctypes.c_void_p()
+        check(lib().sis_state_create(plan.handle, geom.handle, ctypes.byref(o), _stream(stream),
+                                     ctypes.byref(h)))
+        self.handle = h
+
+    def reset(self, stream=None):
+        check(lib().sis_state_reset(self.handle, _stream(stream)))
+
+    def step(self, n_iters=1, stream=None):
+        check(lib().sis_state_step(self.handle, int(n_iters), _stream(stream)))
+
+    def poll(self, stream=None):
+        n = ctypes.c_int32()
+        check(lib().sis_state_poll(self.handle, ctypes.byref(n), _stream(stream)))
+        return n.value
+
+    def results(self, stream=None, raise_not_converged=False):
+        import numpy as np
+        nc, ns = self.geom.n_cells, self.geom.n_cases
+        M, Q, res = np.zeros(ns), np.zeros(ns), np.zeros(ns)
+        it = np.zeros(ns, dtype=np.int32)
+        U, q = np.zeros(nc), np.zeros(nc)
+        r = SolveResult(M.ctypes.data_as(_D), Q.ctypes.data_as(_D),
+                        it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), res.ctypes.data_as(_D),
+                        U.ctypes.data_as(_D), q.ctypes.data_as(_D), 0.0, 0)
+        code = lib().sis_state_results(self.handle, ctypes.byref(r), _stream(stream))
+        if code not in (SIS_OK, SIS_E_NOT_CONVERGED) or (code != SIS_OK and raise_not_converged):
+            check(code)
+        return dict(M=M, Q=Q, iters=it, residual=res, U=U, q=q, total_iters=r.total_iters,
+                    status=code)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sis_state_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
