@@ -179,7 +179,10 @@ void choose_gemm(int64_t M, int n3, int* tile, int* splits) {
 
 sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const double* dU,
                        const double* delta, const int32_t* flow, int project, double* rhs,
-                       double* lh, double* amom, const int32_t* cell_active, hipStream_t s) {
+                       double* lh, double* amom, const int32_t* cell_active, hipStream_t s,
+                       int precision = -1, int anchor_mode = 0, double* xref = nullptr,
+                       double* accref = nullptr) {
+  if (precision < 0) precision = p->precision;
   int tile, splits;
   choose_gemm(n_cells, p->n3, &tile, &splits);
   double* acc = rhs;
@@ -188,8 +191,9 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
     acc = static_cast<double*>(p->ws_acc.p);
   }
   sis::GemmArgs g{};
-  g.precision = p->precision;
+  g.precision = precision;
   g.X = h;
+  g.Xref = anchor_mode == 2 ? xref : nullptr;
   g.op64 = p->op;
   g.op32 = p->op32;
   g.ophi = p->ophi;
@@ -235,6 +239,9 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   f.gram_inv = p->gram_inv;
   f.w = p->w;
   f.active = cell_active;
+  f.anchor_mode = anchor_mode;
+  f.accref = accref;
+  f.xref = xref;
   f.rhs = rhs;
   f.lh = lh;
   f.amom = amom;
@@ -649,13 +656,18 @@ struct sis_state {
   double *h = nullptr, *rhs = nullptr, *amom = nullptr, *mom = nullptr, *dU = nullptr, *U = nullptr,
          *q = nullptr, *state = nullptr;
   int32_t *iters = nullptr, *cact = nullptr, *lact = nullptr;
+  double *xref = nullptr, *accref = nullptr;   // FP64 anchor of the defect correction
+  int precision = 0, refresh = 1;
   hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};    // [0] refresh / plain, [1] incremental
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   int total = 0;
   ~sis_state() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int i = 0; i < 2; ++i) {
+      if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+    }
+    dfree(xref); dfree(accref);
     dfree(h); dfree(rhs); dfree(amom); dfree(mom); dfree(dU); dfree(U); dfree(q); dfree(state);
     dfree(iters); dfree(cact); dfree(lact);
     if (cap) (void)hipStreamDestroy(cap);
@@ -664,12 +676,22 @@ struct sis_state {
 
 namespace {
 
-sis_status state_iteration(sis_state* b, hipStream_t s) {
+// kind 0: plain (FP64) or refresh iteration; kind 1: incremental low-precision iteration
+sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
   sis_plan* p = b->p;
   sis_geom* g = b->g;
   const bool sis = b->o.scheme == SIS_SCHEME_SIS;
+  const bool mixed = b->precision != SIS_PREC_FP64;
+  int prec = b->precision, mode = 0;
+  if (mixed && b->refresh == 1) {
+    prec = SIS_PREC_FP64;
+  } else if (mixed && b->refresh > 1) {
+    prec = kind == 0 ? SIS_PREC_FP64 : b->precision;
+    mode = kind == 0 ? 1 : 2;
+  }
   if (sis_status st = run_collide(p, g->n_cells, b->h, sis ? b->dU : nullptr, g->delta_cell,
-                                  g->flow_cell, b->o.project, b->rhs, nullptr, b->amom, b->lact, s))
+                                  g->flow_cell, b->o.project, b->rhs, nullptr, b->amom, b->lact, s,
+                                  prec, mode, b->xref, b->accref))
     return st;
   if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s)) return st;
   sis::DiffusionArgs a{};
@@ -733,6 +755,11 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   b->p = p;
   b->g = g;
   b->o = *o;
+  b->precision = p->precision;
+  // refresh: 0 = plain contraction in the plan precision every iteration,
+  //          1 = FP64 every iteration, R > 1 = FP64 anchor every R-th iteration
+  b->refresh = p->precision == SIS_PREC_FP64 ? 0
+               : (o->refresh_every < 0 ? 0 : (o->refresh_every == 0 ? 8 : o->refresh_every));
   b->Npen = o->N > 0.0 ? o->N : p->nubar;
   const int64_t nc = g->n_cells;
   const int ncase = g->n_cases;
@@ -757,6 +784,10 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   ST_TRY(dmalloc(&b->iters, ncase));
   ST_TRY(dmalloc(&b->cact, ncase));
   ST_TRY(dmalloc(&b->lact, nc));
+  if (b->refresh > 1) {
+    ST_TRY(dmalloc(&b->xref, static_cast<size_t>(nc) * n3));
+    ST_TRY(dmalloc(&b->accref, static_cast<size_t>(nc) * n3));
+  }
   {
     int tile, splits;
     choose_gemm(nc, n3, &tile, &splits);
@@ -771,14 +802,17 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   }
   if (sis_status st = state_init(b, s)) { delete b; return st; }
   if (o->use_graph) {
-    ST_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    sis_status st = state_iteration(b, b->cap);
-    hipGraph_t gr = nullptr;
-    hipError_t e = hipStreamEndCapture(b->cap, &gr);
-    if (st) { if (gr) (void)hipGraphDestroy(gr); delete b; return st; }
-    ST_TRY(e);
-    b->graph = gr;
-    ST_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    const int kinds = b->refresh > 1 ? 2 : 1;
+    for (int k = 0; k < kinds; ++k) {
+      ST_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      sis_status st = state_iteration(b, b->cap, k);
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(b->cap, &gr);
+      if (st) { if (gr) (void)hipGraphDestroy(gr); delete b; return st; }
+      ST_TRY(e);
+      b->graph[k] = gr;
+      ST_TRY(hipGraphInstantiate(&b->exec[k], b->graph[k], nullptr, nullptr, 0));
+    }
   }
 #undef ST_TRY
   *out = b;
@@ -795,13 +829,14 @@ sis_status sis_state_step(sis_state_t b, int32_t n_iters, hipStream_t stream) {
   if (!b) return fail(SIS_E_INVALID, "null state");
   if (n_iters < 0) return fail(SIS_E_INVALID, "n_iters must be >= 0");
   for (int i = 0; i < n_iters; ++i) {
-    if (b->exec) {
-      HIP_TRY(hipGraphLaunch(b->exec, stream));
-    } else if (sis_status st = state_iteration(b, stream)) {
+    const int kind = (b->refresh > 1 && (b->total % b->refresh) != 0) ? 1 : 0;
+    if (b->exec[kind]) {
+      HIP_TRY(hipGraphLaunch(b->exec[kind], stream));
+    } else if (sis_status st = state_iteration(b, stream, kind)) {
       return st;
     }
+    ++b->total;
   }
-  b->total += n_iters;
   return SIS_OK;
 }
 

@@ -22,6 +22,7 @@ hipError_t launch_split_bf16(const double* op, uint16_t* hi, uint16_t* lo, int64
 struct GemmArgs {
   int precision;
   const double* X;
+  const double* Xref;      // null, or anchor: the contraction is applied to X - Xref
   const double* op64;
   const float* op32;
   const uint16_t* ophi;
@@ -52,6 +53,12 @@ struct FinishArgs {
   const double* gram_inv;  // [25]
   double w;
   const int32_t* active;   // [n_cells] or null: skip cells with active == 0
+  // FP64-anchored defect correction (solver only; mode 0 = off):
+  //  mode 1 (refresh):     acc is op*h in FP64; store accref = acc, xref = h
+  //  mode 2 (incremental): acc is op~*(h - xref); use accref + acc
+  int anchor_mode;
+  double* accref;          // [n_cells][n3]
+  double* xref;            // [n_cells][n3]
   double* rhs;             // [n_cells][n3]  (may alias acc when splits == 1)
   double* lh;              // [n_cells][n3] or null
   double* amom;            // [n_cells][4] or null

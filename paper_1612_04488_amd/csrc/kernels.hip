@@ -254,6 +254,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 // X is converted from double to float when staged; op is stored as float.
 template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const double* __restrict__ X,
+                                                       const double* __restrict__ Xref,
                                                        const float* __restrict__ Op,
                                                        double* __restrict__ C, int64_t M, int N,
                                                        int K, int kps) {
@@ -284,8 +285,16 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const double* __restrict_
       const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
       const int64_t gm = m0 + r;
       const int gk = k0 + kc;
-      ra[i] = (gm < M && gk < kend) ? *reinterpret_cast<const double2*>(X + gm * K + gk)
-                                    : make_double2(0.0, 0.0);
+      if (gm < M && gk < kend) {
+        ra[i] = *reinterpret_cast<const double2*>(X + gm * K + gk);
+        if (Xref) {
+          const double2 xr = *reinterpret_cast<const double2*>(Xref + gm * K + gk);
+          ra[i].x -= xr.x;
+          ra[i].y -= xr.y;
+        }
+      } else {
+        ra[i] = make_double2(0.0, 0.0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
@@ -373,6 +382,7 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const double* __restrict__ X,
+                                                          const double* __restrict__ Xref,
                                                           const uint16_t* __restrict__ Oh,
                                                           const uint16_t* __restrict__ Ol,
                                                           double* __restrict__ C, int64_t M,
@@ -407,8 +417,16 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const double* __restri
       const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
       const int64_t gm = m0 + r;
       const int gk = k0 + kc;
-      ra[i] = (gm < M && gk < kend) ? *reinterpret_cast<const double2*>(X + gm * K + gk)
-                                    : make_double2(0.0, 0.0);
+      if (gm < M && gk < kend) {
+        ra[i] = *reinterpret_cast<const double2*>(X + gm * K + gk);
+        if (Xref) {
+          const double2 xr = *reinterpret_cast<const double2*>(Xref + gm * K + gk);
+          ra[i].x -= xr.x;
+          ra[i].y -= xr.y;
+        }
+      } else {
+        ra[i] = make_double2(0.0, 0.0);
+      }
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
@@ -528,6 +546,12 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
     const double f = a.feq[v];
     double s = 0.0;
     for (int z = 0; z < a.splits; ++z) s += a.acc[z * sstride + base + v];
+    if (a.anchor_mode == 2) {
+      s += a.accref[base + v];
+    } else if (a.anchor_mode == 1) {
+      a.accref[base + v] = s;
+      a.xref[base + v] = a.h[base + v];
+    }
     const double lp = s + dUc * a.Kc[v];
     const double hk = a.h[base + v] + dUc * 2.0 * v3 * f;
     const double L = del * (lp - a.nu[v] * hk);
@@ -787,14 +811,14 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
       hipLaunchKernelGGL((gemm_f64_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
   } else if (g.precision == 1) {
     if (g.tile == 0)
-      hipLaunchKernelGGL((gemm_f32_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.op32, g.acc, g.M, g.N, g.K, kps);
+      hipLaunchKernelGGL((gemm_f32_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.Xref, g.op32, g.acc, g.M, g.N, g.K, kps);
     else
-      hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.op32, g.acc, g.M, g.N, g.K, kps);
+      hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.Xref, g.op32, g.acc, g.M, g.N, g.K, kps);
   } else {
     if (g.tile == 0)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.Xref, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
     else
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.Xref, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
   }
   return hipGetLastError();
 }

@@ -63,7 +63,8 @@ class GeometryDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("N", ctypes.c_double), ("eps", ctypes.c_double),
                 ("max_it", ctypes.c_int32), ("project", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("refresh_every", ctypes.c_int32)]
 
 
 class SolveResult(ctypes.Structure):
@@ -269,7 +270,7 @@ def diffusion_correct(plan, geom, mom_half, amom, N, U_out=None, dU_out=None, st
 
 
 def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False,
-          check_every=4, use_graph=True, stream=None, raise_not_converged=True):
+          check_every=4, use_graph=True, stream=None, raise_not_converged=True, refresh_every=0):
     """Run sis_solve; returns a dict of numpy arrays (M, Q, iters, residual, U, q)."""
     import numpy as np
     nc, ns = geom.n_cells, geom.n_cases
@@ -280,7 +281,7 @@ def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False
                     it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), res.ctypes.data_as(_D),
                     U.ctypes.data_as(_D), q.ctypes.data_as(_D), 0.0, 0)
     o = SolveOpts(SCHEME_SIS if scheme == "SIS" else SCHEME_CIS, float(N), float(eps), int(max_it),
-                  1 if project else 0, int(check_every), 1 if use_graph else 0)
+                  1 if project else 0, int(check_every), 1 if use_graph else 0, int(refresh_every))
     code = lib().sis_solve(plan.handle, geom.handle, ctypes.byref(o), ctypes.byref(r), _stream(stream))
     if code != SIS_OK and not (code == SIS_E_NOT_CONVERGED and not raise_not_converged):
         check(code)
@@ -288,18 +289,19 @@ def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False
                 total_iters=r.total_iters, status=code)
 
 
-def _opts(scheme, N, eps, max_it, project, check_every, use_graph):
+def _opts(scheme, N, eps, max_it, project, check_every, use_graph, refresh_every=0):
     return SolveOpts(SCHEME_SIS if scheme == "SIS" else SCHEME_CIS, float(N), float(eps),
-                     int(max_it), 1 if project else 0, int(check_every), 1 if use_graph else 0)
+                     int(max_it), 1 if project else 0, int(check_every), 1 if use_graph else 0,
+                     int(refresh_every))
 
 
 class State:
     """Persistent iteration state of sis_solve (sis_state_* entry points)."""
 
     def __init__(self, plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False,
-                 use_graph=True, stream=None):
+                 use_graph=True, stream=None, refresh_every=0):
         self.plan, self.geom = plan, geom
-        o = _opts(scheme, N, eps, max_it, project, 4, use_graph)
+        o = _opts(scheme, N, eps, max_it, project, 4, use_graph, refresh_every)
         h = ctypes.c_void_p()
         check(lib().sis_state_create(plan.handle, geom.handle, ctypes.byref(o), _stream(stream),
                                      ctypes.byref(h)))

@@ -242,3 +242,30 @@ def test_collide_mixed_precision_error_and_projection(precision, tol):
         assert rel(lh[c], ref.ravel()) < tol
         for psi in collision.invariants(g):
             assert abs(g.integrate(psi * lh[c].reshape(g.feq.shape))) < 1e-13 * np.max(np.abs(lh[c]))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mixed_solve_with_fp64_refresh_matches_fp64(precision):
+    """Low-precision contraction with FP64 anchors every 8 iterations: flow
+    rates within 1e-8 of the FP64 solve with the same projection setting
+    (target 1e-5), same convergence."""
+    say("mixed solve", precision)
+    n_v, l_v, m = 16, 6.0, 6
+    p = sis.Plan(n_v, l_v, m_angle=m)
+    xs = [inputs.nodes_tanh(16)] * 4
+    deltas, flows = [1.0, 10.0, 100.0, 10.0], [1, 1, 1, 2]
+    geom = sis.Geometry(p, xs, deltas, flows)
+    refs = {pr: sis.solve(p, geom, scheme="SIS", eps=1e-10, max_it=300, project=pr)
+            for pr in (False, True)}
+    p.set_precision(precision)
+    for project in (False, True):
+        ref = refs[project]
+        r = sis.solve(p, geom, scheme="SIS", eps=1e-10, max_it=300, project=project)
+        say(precision, project, r["iters"], ref["iters"])
+        assert np.all(np.abs(r["M"] - ref["M"]) < 1e-8 * np.abs(ref["M"]))
+        assert np.all(np.abs(r["Q"] - ref["Q"]) < 1e-8 * np.abs(ref["Q"]))
+        assert np.all(np.abs(r["iters"] - ref["iters"]) <= 3)
+    # refresh every iteration == the FP64 path
+    r1 = sis.solve(p, geom, scheme="SIS", eps=1e-10, max_it=300, refresh_every=1)
+    assert np.array_equal(r1["iters"], refs[False]["iters"])
+    assert np.all(np.abs(r1["M"] - refs[False]["M"]) < 1e-12 * np.abs(refs[False]["M"]))
