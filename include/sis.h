@@ -57,7 +57,7 @@ enum { SIS_PREC_FP64 = 0, SIS_PREC_FP32 = 1, SIS_PREC_BF16X3 = 2 };
 /* Source terms S of Sec. 2 with X_P = X_T = -1.                             */
 enum { SIS_FLOW_NONE = 0, SIS_FLOW_POISEUILLE = 1, SIS_FLOW_TRANSPIRATION = 2 };
 enum { SIS_SCHEME_CIS = 0, SIS_SCHEME_SIS = 1 };
-enum { SIS_GEOM_PLANAR_HALF = 0 };
+enum { SIS_GEOM_PLANAR_HALF = 0, SIS_GEOM_DUCT_QUARTER = 1, SIS_GEOM_PERIODIC_2D = 2 };
 
 const char* sis_last_error(void);   /* thread-local; valid until the next call on this thread */
 int32_t sis_version(void);          /* 100 * major + minor                                    */
@@ -125,19 +125,38 @@ sis_status sis_host_tables(const sis_velocity_desc* desc, double* feq, double* n
 sis_status sis_plan_set_precision(sis_plan_t plan, int32_t precision, hipStream_t stream);
 
 /* ------------------------------------------------------------------ geometry
- * Device-resident spatial geometry for a batch of independent cases.
- * SIS_GEOM_PLANAR_HALF: case c is the half channel -1/2 <= x1 <= 0 with
- * nodes x1[node_offset[c] .. node_offset[c+1]) (strictly increasing,
- * first -1/2 = diffuse wall, last 0 = specular symmetry plane, >= 2 nodes).
- * One spatial cell per node; cells of all cases concatenated in case order.
- * delta[c], flow[c] (SIS_FLOW_*) are per case.  Host arrays; copied.        */
+ * Device-resident spatial geometry for a batch of independent cases.  One
+ * spatial cell per node (planar) or per fluid cell (2-D); cells of all cases
+ * are concatenated in case order.  delta[c], flow[c] (SIS_FLOW_*) are per
+ * case.  All arrays are HOST memory and are copied.
+ *
+ * SIS_GEOM_PLANAR_HALF (Sec. 2.4): case c is the half channel
+ *   -1/2 <= x1 <= 0 with nodes x1[node_offset[c] .. node_offset[c+1])
+ *   (strictly increasing, first -1/2 = diffuse wall, last 0 = specular
+ *   symmetry plane, >= 2 nodes).
+ * SIS_GEOM_DUCT_QUARTER (Sec. 2.4, 5.3): case c is the quarter of a
+ *   rectangular duct, n1[c] x n2[c] cells with faces face1 (n1+1 values,
+ *   from the wall to the symmetry plane x1 = 0) and face2 (n2+1 values),
+ *   concatenated over cases; walls at the first faces, symmetry planes at
+ *   the last.
+ * SIS_GEOM_PERIODIC_2D (Sec. 3.2): periodic cell with faces face1/face2 and a
+ *   staircase solid mask solid (n1*n2 bytes per case, i major, 1 = solid);
+ *   solid faces reflect diffusely.
+ * 2-D cells are numbered per case in row-major (i, j) order over fluid
+ * cells.  Sweep moments have 8 entries per cell in 2-D (4 planar): see
+ * sis_geometry_moment_stride.                                               */
 typedef struct {
-  int32_t kind;                 /* SIS_GEOM_*                    */
+  int32_t kind;                 /* SIS_GEOM_*                                   */
   int32_t n_cases;
-  const int64_t* node_offset;   /* [n_cases + 1], node_offset[0] = 0 */
-  const double*  x1;            /* [node_offset[n_cases]]        */
-  const double*  delta;         /* [n_cases], >= 0               */
-  const int32_t* flow;          /* [n_cases]                     */
+  const int64_t* node_offset;   /* planar: [n_cases + 1], node_offset[0] = 0    */
+  const double*  x1;            /* planar: [node_offset[n_cases]]               */
+  const double*  delta;         /* [n_cases], >= 0                              */
+  const int32_t* flow;          /* [n_cases]                                    */
+  const int32_t* n1;            /* 2-D: [n_cases] cells along x1 (>= 2)         */
+  const int32_t* n2;            /* 2-D: [n_cases] cells along x2 (>= 2)         */
+  const double*  face1;         /* 2-D: concatenated faces, n1[c]+1 per case    */
+  const double*  face2;         /* 2-D: concatenated faces, n2[c]+1 per case    */
+  const uint8_t* solid;         /* 2-D: concatenated masks or NULL (no solids)  */
 } sis_geometry_desc;
 typedef struct sis_geom* sis_geom_t;
 
@@ -145,6 +164,7 @@ sis_status sis_geometry_create(sis_plan_t plan, const sis_geometry_desc* desc,
                                hipStream_t stream, sis_geom_t* out);
 sis_status sis_geometry_destroy(sis_geom_t geom);
 int64_t    sis_geometry_cells(sis_geom_t geom);
+int32_t    sis_geometry_moment_stride(sis_geom_t geom);   /* 4 planar, 8 in 2-D; -1 if NULL */
 
 /* ------------------------------------------------------------------ compute
  * sis_collide -- collision step of one outer iteration for n_cells cells
@@ -166,12 +186,18 @@ sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const 
                        const double* delta, const int32_t* flow, int32_t project,
                        double* rhs_out, double* lh_out, double* amom_out, hipStream_t stream);
 
-/* sis_transport_sweep -- solve delta nu h + v1 dh/dx1 = rhs per velocity
- * (eq. syn_LBE / eq. LBE_iteration) by second-order upwind differences, first
- * order at the first step from each boundary; v1 > 0: h = 0 at the wall,
- * march to x1 = 0; v1 < 0: specular h(0, v1) = h(0, -v1), march to the wall.
- * rhs, h_half_out: [cells][n3].  mom_out (nullable): [cells][4] =
- * { U3, q3, G1 = F_201/4, P13 } of h_half (midpoint sums, weight dv^3).     */
+/* sis_transport_sweep -- solve delta nu h + v . grad h = rhs per velocity
+ * (eq. syn_LBE / eq. LBE_iteration) by second-order upwind differences.
+ * Planar: first order at the first step from each boundary; v1 > 0: h = 0
+ * at the wall, march to x1 = 0; v1 < 0: specular h(0, v1) = h(0, -v1), march
+ * to the wall.  mom_out (nullable): [cells][4] = { U3, q3, G1 = F_201/4, P13 }.
+ * 2-D: quadrants (+,+), (-,+), (+,-), (-,-); two upwind points per axis
+ * (first order when a wall/solid face is the only one; the face carries
+ * h = 0), mirror ghosts at symmetry planes.  PERIODIC_2D reads the values
+ * across a periodic edge from h_half_out on entry (the previous iterate), so
+ * h_half_out is in/out there.  mom_out: [cells][8] =
+ * { U3, q3, G1, G12 = F_111/4, G2 = F_021/4, P13, P23, 0 }.
+ * rhs, h_half_out: [cells][n3]; moments are midpoint sums with weight dv^3.   */
 sis_status sis_transport_sweep(sis_plan_t plan, sis_geom_t geom, const double* rhs,
                                double* h_half_out, double* mom_out, hipStream_t stream);
 
@@ -179,8 +205,13 @@ sis_status sis_transport_sweep(sis_plan_t plan, sis_geom_t geom, const double* r
 sis_status sis_moments(sis_plan_t plan, int64_t n_cells, const double* h, double* mom_out,
                        hipStream_t stream);
 
-/* sis_diffusion_correct -- planar form of the SIS velocity equation
- * (eq. first_order with the tuning parameter N, Sec. 2.5):
+/* sis_diffusion_correct -- the SIS velocity equation.
+ * 2-D (eq. diffusion_LBE with N): lap U = -N delta [Poiseuille]
+ *   - (d11 G1 + 2 d12 G12 + d22 G2) + d1 A1 + d2 A2 in finite-volume form,
+ *   U = U3(h_half) on fluid cells next to a wall or solid, solved by
+ *   Jacobi-preconditioned conjugate gradients to a relative residual 1e-13;
+ *   mom_half [cells][8], amom [cells][4] (A2 = amom[2] + N delta amom[3]).
+ * Planar form (eq. first_order with the tuning parameter N, Sec. 2.5):
  *   d(U + G1)/dx1 = -N delta x1 [Poiseuille] + A1,   A1 = amom[0] + N delta amom[1],
  * marched from the wall with the upwind stencil (first order at the first
  * step), U at the wall = U3 of h_half.  mom_half: [cells][4] from the sweep;

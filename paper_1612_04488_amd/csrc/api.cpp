@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "geom2d.h"
 #include "kernels.h"
 #include "planner.h"
 #include "sis.h"
@@ -107,9 +108,24 @@ struct sis_geom {
   double* delta_cell = nullptr;
   int32_t* flow_cell = nullptr;
   int32_t* case_of_cell = nullptr;
+  // 2-D tables (kinds DUCT_QUARTER, PERIODIC_2D)
+  bool two_d = false;
+  sis::Tables2D t2;
+  int32_t *d_n1 = nullptr, *d_n2 = nullptr, *d_gcell = nullptr, *d_sref = nullptr, *d_nb = nullptr;
+  int64_t* d_goff = nullptr;
+  int8_t *d_skind = nullptr, *d_dflag = nullptr, *d_nbm = nullptr;
+  double *d_scoef = nullptr, *d_npos = nullptr, *d_fw = nullptr, *d_width = nullptr, *d_cpos = nullptr,
+         *d_dA = nullptr, *d_area = nullptr;
+  double* work = nullptr;        // [grid][10] diffusion workspace
+  int32_t* have_x = nullptr;     // [n_cases]
+  int32_t* cg_iters = nullptr;   // [n_cases]
+  int mom_stride() const { return two_d ? 8 : 4; }
   ~sis_geom() {
     dfree(off); dfree(x); dfree(coef); dfree(delta_case); dfree(flow_case);
     dfree(delta_cell); dfree(flow_cell); dfree(case_of_cell);
+    dfree(d_n1); dfree(d_n2); dfree(d_gcell); dfree(d_sref); dfree(d_nb); dfree(d_goff);
+    dfree(d_skind); dfree(d_dflag); dfree(d_nbm); dfree(d_scoef); dfree(d_npos); dfree(d_fw);
+    dfree(d_width); dfree(d_cpos); dfree(d_dA); dfree(d_area); dfree(work); dfree(have_x); dfree(cg_iters);
   }
 };
 
@@ -250,7 +266,29 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
 }
 
 sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, double* mom,
-                     const int32_t* case_active, hipStream_t s) {
+                     const int32_t* case_active, hipStream_t s, const int32_t* cell_active = nullptr) {
+  if (g->two_d) {
+    sis::Sweep2DArgs a{};
+    a.n = p->n;
+    a.n3 = p->n3;
+    a.n_cases = g->n_cases;
+    a.n1 = g->d_n1;
+    a.n2 = g->d_n2;
+    a.grid_off = g->d_goff;
+    a.gcell = g->d_gcell;
+    a.coef = g->d_scoef;
+    a.ref = g->d_sref;
+    a.kind = g->d_skind;
+    a.delta_case = g->delta_case;
+    a.v1d = p->v1d;
+    a.nu = p->nu;
+    a.rhs = rhs;
+    a.h = h;
+    a.case_active = case_active;
+    HIP_TRY(sis::launch_sweep2d(a, s));
+    if (mom) HIP_TRY(sis::launch_moments2d(p->n, p->n3, g->n_cells, p->v1d, h, p->w, cell_active, mom, s));
+    return SIS_OK;
+  }
   const int W = (p->n3 / 2 + 63) / 64;
   HIP_TRY(p->ws_part.ensure(static_cast<size_t>(g->n_cells) * 8 * W * sizeof(double)));
   sis::SweepArgs a{};
@@ -274,8 +312,138 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
   return SIS_OK;
 }
 
+sis::Diff2DArgs diff2d_args(sis_plan* p, sis_geom* g, const double* mom, const double* amom, double N) {
+  sis::Diff2DArgs a{};
+  a.n_cases = g->n_cases;
+  a.n2 = g->d_n2;
+  a.grid_off = g->d_goff;
+  a.dflag = g->d_dflag;
+  a.gcell = g->d_gcell;
+  a.nb = g->d_nb;
+  a.nbm = g->d_nbm;
+  a.npos = g->d_npos;
+  a.fw = g->d_fw;
+  a.width = g->d_width;
+  a.cpos = g->d_cpos;
+  a.dA = g->d_dA;
+  a.area = g->d_area;
+  a.delta_case = g->delta_case;
+  a.flow_case = g->flow_case;
+  a.mom = mom;
+  a.amom = amom;
+  a.N = N;
+  a.sis = 1;
+  a.cU = p->cU;
+  a.cq = p->cq;
+  a.work = g->work;
+  a.have_x = g->have_x;
+  a.tol = 1e-13;
+  a.max_iter = 20000;
+  a.cg_iters = g->cg_iters;
+  return a;
+}
+
 sis_status check_plan(sis_plan_t p) {
   if (!p) return fail(SIS_E_INVALID, "null plan");
+  return SIS_OK;
+}
+
+}  // namespace
+
+
+namespace {
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
+  hipError_t e = dmalloc(dst, src.size());
+  if (e != hipSuccess) return e;
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream_t stream, sis_geom_t* out) {
+  if (!d->n1 || !d->n2 || !d->face1 || !d->face2 || !d->delta || !d->flow)
+    return fail(SIS_E_INVALID, "null 2-D geometry array");
+  std::vector<sis::Case2D> cases(d->n_cases);
+  int64_t f1o = 0, f2o = 0, so = 0;
+  for (int c = 0; c < d->n_cases; ++c) {
+    sis::Case2D& k = cases[c];
+    k.n1 = d->n1[c];
+    k.n2 = d->n2[c];
+    if (k.n1 < 2 || k.n2 < 2 || k.n1 > 4096 || k.n2 > 4096)
+      return fail(SIS_E_SHAPE, "case %d: n1, n2 must be in [2, 4096]", c);
+    k.f1.assign(d->face1 + f1o, d->face1 + f1o + k.n1 + 1);
+    k.f2.assign(d->face2 + f2o, d->face2 + f2o + k.n2 + 1);
+    f1o += k.n1 + 1;
+    f2o += k.n2 + 1;
+    if (d->kind == SIS_GEOM_DUCT_QUARTER) {
+      k.bc[0] = sis::kWall; k.bc[1] = sis::kSym; k.bc[2] = sis::kWall; k.bc[3] = sis::kSym;
+    } else {
+      for (int q = 0; q < 4; ++q) k.bc[q] = sis::kPeriodic;
+    }
+    if (d->solid) {
+      k.solid.assign(d->solid + so, d->solid + so + static_cast<int64_t>(k.n1) * k.n2);
+      so += static_cast<int64_t>(k.n1) * k.n2;
+    }
+    if (!(d->delta[c] >= 0.0) || !std::isfinite(d->delta[c])) return fail(SIS_E_INVALID, "case %d delta must be >= 0", c);
+    if (d->flow[c] < 0 || d->flow[c] > 2) return fail(SIS_E_INVALID, "case %d flow code %d", c, d->flow[c]);
+  }
+  auto* g = new sis_geom();
+  g->plan = p;
+  g->kind = d->kind;
+  g->n_cases = d->n_cases;
+  g->two_d = true;
+  std::string err;
+  if (!sis::build_tables_2d(cases, g->t2, err)) { delete g; return fail(SIS_E_INVALID, "%s", err.c_str()); }
+  const sis::Tables2D& t = g->t2;
+  g->n_cells = t.n_cells;
+  g->h_off = t.cell_off;
+  g->h_delta.assign(d->delta, d->delta + d->n_cases);
+  g->h_flow.assign(d->flow, d->flow + d->n_cases);
+  std::vector<double> dcell(t.n_cells);
+  std::vector<int32_t> fcell(t.n_cells);
+  for (int64_t i = 0; i < t.n_cells; ++i) {
+    dcell[i] = d->delta[t.cell_case[i]];
+    fcell[i] = d->flow[t.cell_case[i]];
+  }
+#define G2_TRY(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      delete g;                                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s", #expr,        \
+                  hipGetErrorString(e_));                                                      \
+    }                                                                                          \
+  } while (0)
+  G2_TRY(upload(&g->off, t.cell_off, stream));
+  G2_TRY(upload(&g->d_n1, t.n1, stream));
+  G2_TRY(upload(&g->d_n2, t.n2, stream));
+  G2_TRY(upload(&g->d_goff, t.grid_off, stream));
+  G2_TRY(upload(&g->d_gcell, t.gcell, stream));
+  G2_TRY(upload(&g->d_scoef, t.st_coef, stream));
+  G2_TRY(upload(&g->d_sref, t.st_ref, stream));
+  G2_TRY(upload(&g->d_skind, t.st_kind, stream));
+  G2_TRY(upload(&g->d_dflag, t.dflag, stream));
+  G2_TRY(upload(&g->d_nb, t.nb, stream));
+  G2_TRY(upload(&g->d_nbm, t.nbm, stream));
+  G2_TRY(upload(&g->d_npos, t.npos, stream));
+  G2_TRY(upload(&g->d_fw, t.fw, stream));
+  G2_TRY(upload(&g->d_width, t.width, stream));
+  G2_TRY(upload(&g->d_cpos, t.cpos, stream));
+  G2_TRY(upload(&g->d_dA, t.dA, stream));
+  G2_TRY(upload(&g->d_area, t.area, stream));
+  G2_TRY(upload(&g->delta_case, g->h_delta, stream));
+  G2_TRY(upload(&g->flow_case, g->h_flow, stream));
+  G2_TRY(upload(&g->delta_cell, dcell, stream));
+  G2_TRY(upload(&g->flow_cell, fcell, stream));
+  G2_TRY(upload(&g->case_of_cell, t.cell_case, stream));
+  G2_TRY(dmalloc(&g->work, static_cast<size_t>(t.n_grid) * 10));
+  G2_TRY(upload(&g->have_x, std::vector<int32_t>(d->n_cases, 0), stream));
+  G2_TRY(upload(&g->cg_iters, std::vector<int32_t>(d->n_cases, 0), stream));
+  G2_TRY(hipStreamSynchronize(stream));
+#undef G2_TRY
+  *out = g;
+  g_err.clear();
   return SIS_OK;
 }
 
@@ -490,8 +658,10 @@ sis_status sis_geometry_create(sis_plan_t p, const sis_geometry_desc* d, hipStre
   if (sis_status st = check_plan(p)) return st;
   if (!d || !out) return fail(SIS_E_INVALID, "null argument");
   *out = nullptr;
-  if (d->kind != SIS_GEOM_PLANAR_HALF) return fail(SIS_E_UNSUPPORTED, "geometry kind %d not supported", d->kind);
   if (d->n_cases < 1) return fail(SIS_E_INVALID, "n_cases must be >= 1");
+  if (d->kind == SIS_GEOM_DUCT_QUARTER || d->kind == SIS_GEOM_PERIODIC_2D)
+    return create_geometry_2d(p, d, stream, out);
+  if (d->kind != SIS_GEOM_PLANAR_HALF) return fail(SIS_E_UNSUPPORTED, "geometry kind %d not supported", d->kind);
   if (!d->node_offset || !d->x1 || !d->delta || !d->flow) return fail(SIS_E_INVALID, "null geometry array");
   if (d->node_offset[0] != 0) return fail(SIS_E_INVALID, "node_offset[0] must be 0");
   auto* g = new sis_geom();
@@ -588,6 +758,7 @@ sis_status sis_geometry_destroy(sis_geom_t g) {
 }
 
 int64_t sis_geometry_cells(sis_geom_t g) { return g ? g->n_cells : -1; }
+int32_t sis_geometry_moment_stride(sis_geom_t g) { return g ? g->mom_stride() : -1; }
 
 sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,
                        const double* delta, const int32_t* flow, int32_t project, double* rhs_out,
@@ -627,6 +798,13 @@ sis_status sis_diffusion_correct(sis_plan_t p, sis_geom_t g, const double* mom_h
   if (!g || g->plan != p) return fail(SIS_E_INVALID, "geometry does not belong to this plan");
   if (!mom_half) return fail(SIS_E_INVALID, "mom_half must be non-null");
   if (!std::isfinite(N)) return fail(SIS_E_INVALID, "N must be finite");
+  if (g->two_d) {
+    sis::Diff2DArgs a = diff2d_args(p, g, mom_half, amom, N > 0.0 ? N : p->nubar);
+    a.U = U_out;
+    a.dU = dU_out;
+    HIP_TRY(sis::launch_diffusion2d(a, stream));
+    return SIS_OK;
+  }
   sis::DiffusionArgs a{};
   a.n_cases = g->n_cases;
   a.node_off = g->off;
@@ -693,7 +871,22 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
                                   g->flow_cell, b->o.project, b->rhs, nullptr, b->amom, b->lact, s,
                                   prec, mode, b->xref, b->accref))
     return st;
-  if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s)) return st;
+  if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s, b->lact)) return st;
+  if (g->two_d) {
+    sis::Diff2DArgs a = diff2d_args(p, g, b->mom, b->amom, b->Npen);
+    a.sis = sis ? 1 : 0;
+    a.U = nullptr;
+    a.ufield = b->U;
+    a.dU = b->dU;
+    a.qfield = b->q;
+    a.state = b->state;
+    a.iters = b->iters;
+    a.case_active = b->cact;
+    a.eps = b->o.eps;
+    HIP_TRY(sis::launch_diffusion2d(a, s));
+    HIP_TRY(sis::launch_expand_active(b->cact, g->case_of_cell, g->n_cells, b->lact, s));
+    return SIS_OK;
+  }
   sis::DiffusionArgs a{};
   a.n_cases = g->n_cases;
   a.node_off = g->off;
@@ -729,6 +922,7 @@ sis_status state_init(sis_state* b, hipStream_t s) {
   HIP_TRY(hipMemsetAsync(b->q, 0, nc * 8, s));
   HIP_TRY(hipMemsetAsync(b->state, 0, ncase * 4 * 8, s));
   HIP_TRY(hipMemsetAsync(b->iters, 0, ncase * 4, s));
+  if (b->g->two_d) HIP_TRY(hipMemsetAsync(b->g->have_x, 0, ncase * 4, s));
   std::vector<int32_t> ones(std::max<int64_t>(nc, ncase), 1);
   HIP_TRY(hipMemcpyAsync(b->cact, ones.data(), ncase * 4, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(b->lact, ones.data(), nc * 4, hipMemcpyHostToDevice, s));
@@ -776,7 +970,7 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   ST_TRY(dmalloc(&b->h, static_cast<size_t>(nc) * n3));
   ST_TRY(dmalloc(&b->rhs, static_cast<size_t>(nc) * n3));
   ST_TRY(dmalloc(&b->amom, nc * 4));
-  ST_TRY(dmalloc(&b->mom, nc * 4));
+  ST_TRY(dmalloc(&b->mom, nc * g->mom_stride()));
   ST_TRY(dmalloc(&b->dU, nc));
   ST_TRY(dmalloc(&b->U, nc));
   ST_TRY(dmalloc(&b->q, nc));
@@ -793,7 +987,7 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
     choose_gemm(nc, n3, &tile, &splits);
     if (splits > 1) ST_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
     const int W = (n3 / 2 + 63) / 64;
-    ST_TRY(p->ws_part.ensure(static_cast<size_t>(nc) * 8 * W * 8));
+    if (!g->two_d) ST_TRY(p->ws_part.ensure(static_cast<size_t>(nc) * 8 * W * 8));
   }
   hipStream_t s = stream;
   if (o->use_graph) {

@@ -113,6 +113,65 @@ struct DiffusionArgs {
 };
 hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------- 2-D cross sections
+struct Sweep2DArgs {
+  int n, n3, n_cases;
+  const int32_t* n1;
+  const int32_t* n2;
+  const int64_t* grid_off;
+  const int32_t* gcell;      // [grid] global fluid cell or -1
+  const double* coef;        // [cell][2][2][3]
+  const int32_t* ref;        // [cell][2][2][2]
+  const int8_t* kind;        // [cell][2][2][2]
+  const double* delta_case;
+  const double* v1d;
+  const double* nu;
+  const double* rhs;
+  double* h;                 // in: previous iterate (lagged periodic values), out: new
+  const int32_t* case_active;
+};
+hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s);
+// mom[cell][8] = {U3, q3, G1, G12, G2, P13, P23, 0}
+hipError_t launch_moments2d(int n, int n3, int64_t n_cells, const double* v1d, const double* h,
+                            double w, const int32_t* cell_active, double* mom, hipStream_t s);
+
+struct Diff2DArgs {
+  int n_cases;
+  const int32_t* n2;
+  const int64_t* grid_off;
+  const int8_t* dflag;
+  const int32_t* gcell;
+  const int32_t* nb;
+  const int8_t* nbm;
+  const double* npos;
+  const double* fw;
+  const double* width;
+  const double* cpos;
+  const double* dA;
+  const double* area;
+  const double* delta_case;
+  const int32_t* flow_case;
+  const double* mom;         // [cell][8]
+  const double* amom;        // [cell][4] or null
+  double N;
+  int sis;
+  double cU, cq;
+  double* work;              // [grid][10]
+  int32_t* have_x;           // [n_cases]: warm start available
+  double tol;
+  int max_iter;
+  double* U;                 // [cell] diffusion solution or null
+  double* dU;                // [cell] or null
+  double* ufield;            // [cell] U3 of the new iterate or null
+  double* qfield;            // [cell] q3 of the new iterate or null
+  double* state;             // [n_cases][4] or null
+  int32_t* iters;
+  int32_t* case_active;
+  double eps;
+  int32_t* cg_iters;         // [n_cases] or null
+};
+hipError_t launch_diffusion2d(const Diff2DArgs& a, hipStream_t s);
+
 // cell_active[c] = case_active[case_of_cell[c]]
 hipError_t launch_expand_active(const int32_t* case_active, const int32_t* case_of_cell,
                                 int64_t n_cells, int32_t* cell_active, hipStream_t s);

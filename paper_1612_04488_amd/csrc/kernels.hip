@@ -762,6 +762,292 @@ __global__ __launch_bounds__(64) void diffusion1d_kernel(DiffusionArgs a) {
   }
 }
 
+
+// ------------------------------------------------------------------ 2-D sweep
+// One thread per velocity quadruple (+-|v1|, +-|v2|, v3) of one case; the
+// quadrants are swept in the order (+,+), (-,+), (+,-), (-,-), rows in the
+// v2 direction, cells in the v1 direction.  Upwind references read the
+// sweep buffer: cells already updated in this quadrant, mirror ghosts of an
+// earlier quadrant, or (periodic wrap) the previous iterate.
+__global__ __launch_bounds__(256) void sweep2d_kernel(Sweep2DArgs a) {
+  const int cs = blockIdx.y;
+  if (a.case_active && !a.case_active[cs]) return;
+  const int n = a.n, hn = n / 2, n3 = a.n3;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= hn * hn * n) return;
+  const int jq1 = t / (hn * n), jq2 = (t / n) % hn, j3 = t % n;
+  const int n1 = a.n1[cs], n2 = a.n2[cs];
+  const int64_t g0 = a.grid_off[cs];
+  const double del = a.delta_case[cs];
+  for (int q = 0; q < 4; ++q) {
+    const int s1 = (q & 1) ? -1 : 1, s2 = (q & 2) ? -1 : 1;
+    const int j1 = s1 > 0 ? hn + jq1 : hn - 1 - jq1;
+    const int j2 = s2 > 0 ? hn + jq2 : hn - 1 - jq2;
+    const int v = (j1 * n + j2) * n + j3;
+    const int vm1 = ((n - 1 - j1) * n + j2) * n + j3;
+    const int vm2 = (j1 * n + (n - 1 - j2)) * n + j3;
+    const double av1 = fabs(a.v1d[j1]), av2 = fabs(a.v1d[j2]);
+    const double dnu = del * a.nu[v];
+    const int sg1 = s1 > 0 ? 0 : 1, sg2 = s2 > 0 ? 0 : 1;
+    for (int jj = 0; jj < n2; ++jj) {
+      const int j = s2 > 0 ? jj : n2 - 1 - jj;
+      for (int ii = 0; ii < n1; ++ii) {
+        const int i = s1 > 0 ? ii : n1 - 1 - ii;
+        const int cell = a.gcell[g0 + static_cast<int64_t>(i) * n2 + j];
+        if (cell < 0) continue;
+        const int64_t o1 = (static_cast<int64_t>(cell) * 2 + 0) * 2 + sg1;
+        const int64_t o2 = (static_cast<int64_t>(cell) * 2 + 1) * 2 + sg2;
+        double acc = a.rhs[static_cast<int64_t>(cell) * n3 + v];
+        const double c1[3] = {a.coef[o1 * 3], a.coef[o1 * 3 + 1], a.coef[o1 * 3 + 2]};
+        const double c2[3] = {a.coef[o2 * 3], a.coef[o2 * 3 + 1], a.coef[o2 * 3 + 2]};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int8_t k1 = a.kind[o1 * 2 + k];
+          if (k1) {
+            const int64_t r = a.ref[o1 * 2 + k];
+            acc -= av1 * c1[k + 1] * a.h[r * n3 + (k1 == 2 ? vm1 : v)];
+          }
+          const int8_t k2 = a.kind[o2 * 2 + k];
+          if (k2) {
+            const int64_t r = a.ref[o2 * 2 + k];
+            acc -= av2 * c2[k + 1] * a.h[r * n3 + (k2 == 2 ? vm2 : v)];
+          }
+        }
+        a.h[static_cast<int64_t>(cell) * n3 + v] = acc / (dnu + av1 * c1[0] + av2 * c2[0]);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void moments2d_kernel(int n, int n3, const double* __restrict__ v1d,
+                                                        const double* __restrict__ h, double w,
+                                                        const int32_t* __restrict__ active,
+                                                        double* __restrict__ mom) {
+  __shared__ double sh[4 * 7];
+  const int64_t c = blockIdx.x;
+  if (active && !active[c]) return;
+  const int nn = n * n;
+  double m[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int v = threadIdx.x; v < n3; v += blockDim.x) {
+    const double v1 = v1d[v / nn], v2 = v1d[(v / n) % n], v3 = v1d[v % n];
+    const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+    const double x = w * h[c * n3 + v];
+    m[0] += v3 * x;
+    m[1] += (vsq - 2.5) * v3 * x;
+    m[2] += v3 * (2.0 * v1 * v1 - 1.0) * x;
+    m[3] += 2.0 * v1 * v2 * v3 * x;
+    m[4] += v3 * (2.0 * v2 * v2 - 1.0) * x;
+    m[5] += 2.0 * v1 * v3 * x;
+    m[6] += 2.0 * v2 * v3 * x;
+  }
+  block_sum<7>(m, sh);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 7; ++k) mom[c * 8 + k] = m[k];
+    mom[c * 8 + 7] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------ 2-D diffusion
+// Finite-volume form of the SIS velocity equation on one case per workgroup,
+// Jacobi-preconditioned conjugate gradients in FP64, then flow rates.
+constexpr int kD2Threads = 1024;
+
+__device__ inline double par_sign(int bits, int p1, int p2) {
+  return ((bits & 1) ? p1 : 1) * ((bits & 2) ? p2 : 1);
+}
+
+template <int K>
+__device__ inline void block_sum_big(double (&v)[K], double* sh /* >= 16*K */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) sh[wave * K + k] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w * K + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
+  __shared__ double sh[16 * 3];
+  const int cs = blockIdx.x;
+  if (a.case_active && !a.case_active[cs]) return;
+  const int64_t g0 = a.grid_off[cs];
+  const int ng = static_cast<int>(a.grid_off[cs + 1] - g0);
+  const double del = a.delta_case[cs];
+  const bool pois = a.flow_case[cs] == 1;
+  double* W = a.work + g0 * 10;      // per grid cell: Uh G1 G12 G2 A1 A2 x r p Ap
+  const bool warm = a.have_x && a.have_x[cs];
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    const int cell = a.gcell[g0 + g];
+    double* w = W + static_cast<int64_t>(g) * 10;
+    if (cell >= 0) {
+      const double* m = a.mom + static_cast<int64_t>(cell) * 8;
+      w[0] = m[0]; w[1] = m[2]; w[2] = m[3]; w[3] = m[4];
+      if (a.amom) {
+        const double* am = a.amom + static_cast<int64_t>(cell) * 4;
+        w[4] = am[0] + a.N * del * am[1];
+        w[5] = am[2] + a.N * del * am[3];
+      } else {
+        w[4] = 0.0; w[5] = 0.0;
+      }
+      if (!warm) w[6] = m[0];
+    } else {
+      for (int k = 0; k < 6; ++k) w[k] = 0.0;
+      w[6] = 0.0;
+    }
+    w[7] = 0.0; w[8] = 0.0; w[9] = 0.0;
+  }
+  __syncthreads();
+  int it = 0;
+  if (a.sis) {
+    // right side, initial residual, preconditioned direction
+    double red[3] = {0.0, 0.0, 0.0};   // r.z, b.b, r.r
+    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+      const int64_t G = g0 + g;
+      if (a.dflag[G] != 2) continue;
+      double* w = W + static_cast<int64_t>(g) * 10;
+      const int32_t* nbr = a.nb + G * 8;
+      const int8_t* bits = a.nbm + G * 8;
+      const double* np = a.npos + G * 4;
+      const double xc = a.cpos[G * 2], yc = a.cpos[G * 2 + 1];
+      auto val = [&](int q, int f, int p1, int p2) {
+        const int r = nbr[q];
+        return r < 0 ? 0.0 : par_sign(bits[q], p1, p2) * W[static_cast<int64_t>(r) * 10 + f];
+      };
+      const double xE = np[0], xW = np[1], yN = np[2], yS = np[3];
+      const double w1 = a.width[G * 2], w2 = a.width[G * 2 + 1];
+      auto d11 = [&](int f, int p1, int p2) {
+        return ((val(0, f, p1, p2) - w[f]) / (xE - xc) - (w[f] - val(1, f, p1, p2)) / (xc - xW)) / w1;
+      };
+      auto d22 = [&](int f, int p1, int p2) {
+        return ((val(2, f, p1, p2) - w[f]) / (yN - yc) - (w[f] - val(3, f, p1, p2)) / (yc - yS)) / w2;
+      };
+      double rhs = pois ? -a.N * del : 0.0;
+      const double cross = ((val(4, 2, -1, -1) - val(6, 2, -1, -1)) / (yN - yS) -
+                            (val(5, 2, -1, -1) - val(7, 2, -1, -1)) / (yN - yS)) / (xE - xW);
+      rhs -= d11(1, 1, 1) + 2.0 * cross + d22(3, 1, 1);
+      rhs += (val(0, 4, -1, 1) - val(1, 4, -1, 1)) / (xE - xW);
+      rhs += (val(2, 5, 1, -1) - val(3, 5, 1, -1)) / (yN - yS);
+      double b = -rhs * a.dA[G];
+      double diag = 0.0, Ax = 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const double fw = a.fw[G * 4 + q];
+        if (fw == 0.0) continue;
+        const int r = nbr[q];
+        diag += fw;
+        if (a.dflag[g0 + r] == 2) Ax -= fw * W[static_cast<int64_t>(r) * 10 + 6];
+        else b += fw * W[static_cast<int64_t>(r) * 10 + 0];
+      }
+      Ax += diag * w[6];
+      const double r0 = b - Ax;
+      w[7] = r0;
+      w[8] = r0 / diag;
+      w[9] = b;     // keep b for the norm only during setup
+      red[0] += r0 * r0 / diag;
+      red[1] += b * b;
+      red[2] += r0 * r0;
+    }
+    block_sum_big<3>(red, sh);
+    double rz = red[0];
+    const double bnorm = sqrt(red[1]);
+    double rnorm = sqrt(red[2]);
+    while (rnorm > a.tol * bnorm && it < a.max_iter) {
+      // Ap and p.Ap
+      double pap[1] = {0.0};
+      for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+        const int64_t G = g0 + g;
+        if (a.dflag[G] != 2) continue;
+        double* w = W + static_cast<int64_t>(g) * 10;
+        double diag = 0.0, Ap = 0.0;
+        for (int q = 0; q < 4; ++q) {
+          const double fw = a.fw[G * 4 + q];
+          if (fw == 0.0) continue;
+          const int r = a.nb[G * 8 + q];
+          diag += fw;
+          if (a.dflag[g0 + r] == 2) Ap -= fw * W[static_cast<int64_t>(r) * 10 + 8];
+        }
+        Ap += diag * w[8];
+        w[9] = Ap;
+        pap[0] += w[8] * Ap;
+      }
+      block_sum_big<1>(pap, sh);
+      const double alpha = rz / pap[0];
+      double nr[2] = {0.0, 0.0};
+      for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+        const int64_t G = g0 + g;
+        if (a.dflag[G] != 2) continue;
+        double* w = W + static_cast<int64_t>(g) * 10;
+        double diag = 0.0;
+        for (int q = 0; q < 4; ++q) diag += a.fw[G * 4 + q];
+        w[6] += alpha * w[8];
+        w[7] -= alpha * w[9];
+        nr[0] += w[7] * w[7] / diag;
+        nr[1] += w[7] * w[7];
+      }
+      block_sum_big<2>(nr, sh);
+      const double beta = nr[0] / rz;
+      rz = nr[0];
+      rnorm = sqrt(nr[1]);
+      for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+        const int64_t G = g0 + g;
+        if (a.dflag[G] != 2) continue;
+        double* w = W + static_cast<int64_t>(g) * 10;
+        double diag = 0.0;
+        for (int q = 0; q < 4; ++q) diag += a.fw[G * 4 + q];
+        w[8] = w[7] / diag + beta * w[8];
+      }
+      __syncthreads();
+      ++it;
+    }
+  }
+  // outputs and flow rates
+  double fr[2] = {0.0, 0.0};
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    const int64_t G = g0 + g;
+    const int cell = a.gcell[G];
+    if (cell < 0) continue;
+    const double* w = W + static_cast<int64_t>(g) * 10;
+    const double Uh = w[0];
+    const double U = (a.sis && a.dflag[G] == 2) ? w[6] : Uh;
+    const double dU = U - Uh;
+    const double Un = Uh + dU * a.cU;
+    const double qn = a.mom[static_cast<int64_t>(cell) * 8 + 1] + dU * a.cq;
+    if (a.U) a.U[cell] = U;
+    if (a.dU) a.dU[cell] = dU;
+    if (a.ufield) a.ufield[cell] = Un;
+    if (a.qfield) a.qfield[cell] = qn;
+    fr[0] += Un * a.dA[G];
+    fr[1] += qn * a.dA[G];
+  }
+  block_sum_big<2>(fr, sh);
+  if (threadIdx.x == 0) {
+    if (a.have_x) a.have_x[cs] = a.sis ? 1 : 0;
+    if (a.cg_iters) a.cg_iters[cs] = it;
+    if (a.state) {
+      const double M = fr[0] / a.area[cs], Q = fr[1] / a.area[cs];
+      double* st = a.state + cs * 4;
+      const double dM = fabs(M - st[0]) / fmax(fabs(M), 1e-300);
+      const double dQ = fabs(Q - st[1]) / fmax(fabs(Q), 1e-300);
+      const double res = fmax(dM, dQ);
+      st[0] = M;
+      st[1] = Q;
+      st[2] = (M != M || Q != Q) ? __builtin_nan("") : res;
+      const int k = a.iters[cs] + 1;
+      a.iters[cs] = k;
+      if (!(res >= a.eps) || M != M || Q != Q) a.case_active[cs] = 0;
+      st[3] = static_cast<double>(k);
+    }
+  }
+}
+
 __global__ void expand_active_kernel(const int32_t* __restrict__ case_active,
                                      const int32_t* __restrict__ case_of_cell, int64_t n_cells,
                                      int32_t* __restrict__ cell_active) {
@@ -848,6 +1134,27 @@ hipError_t launch_moments(int n, int n3, int64_t n_cells, const double* v1d, con
 
 hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(diffusion1d_kernel, dim3(a.n_cases), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+
+hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
+  const int hn = a.n / 2;
+  const int count = hn * hn * a.n;
+  dim3 grid((count + 255) / 256, a.n_cases);
+  hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments2d(int n, int n3, int64_t n_cells, const double* v1d, const double* h,
+                            double w, const int32_t* cell_active, double* mom, hipStream_t s) {
+  hipLaunchKernelGGL(moments2d_kernel, dim3(static_cast<unsigned>(n_cells)), dim3(256), 0, s, n, n3, v1d, h,
+                     w, cell_active, mom);
+  return hipGetLastError();
+}
+
+hipError_t launch_diffusion2d(const Diff2DArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(diffusion2d_kernel, dim3(a.n_cases), dim3(kD2Threads), 0, s, a);
   return hipGetLastError();
 }
 

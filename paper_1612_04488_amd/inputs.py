@@ -71,3 +71,69 @@ PLANAR_BATCH = dict(name="planar-hs-32v-100cells-8cases", n_v=32, l_v=6.0, n_pad
 def workload_nodes(w):
     f = {"uniform": nodes_uniform, "tanh": nodes_tanh, "smoothstep": nodes_smoothstep}[w["grid"]]
     return [f(w["sections"]) for _ in w["deltas"]]
+
+
+# --------------------------------------------------------------- 2-D cross sections
+def duct_faces(n, length, ratio=1.05):
+    """n cells from the wall (-length) to the centre (0), sides growing by `ratio`."""
+    w0 = length * (ratio - 1.0) / (ratio ** n - 1.0) if ratio != 1.0 else length / n
+    f = np.concatenate([[0.0], np.cumsum(w0 * ratio ** np.arange(n))]) - length
+    f[-1] = 0.0
+    return f
+
+
+def porous_discs(n=128, solid_fraction=0.4, r_max=0.1, r_ratio=10.0, seed=SEED, max_tries=200000):
+    """Periodic unit cell with non-overlapping discs (random sequential addition,
+    radii log-uniform in [r_max / r_ratio, r_max]) until the staircase solid
+    fraction on an n x n grid reaches `solid_fraction`.  Returns (mask, discs)."""
+    rng = np.random.default_rng(seed)
+    xc = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(xc, xc, indexing="ij")
+    mask = np.zeros((n, n), bool)
+    discs = []
+    for _ in range(max_tries):
+        r = r_max * r_ratio ** (-rng.uniform(0.0, 1.0))
+        p = rng.uniform(0.0, 1.0, size=2)
+        ok = True
+        for (q, s) in discs:
+            d = np.abs(p - q)
+            d = np.minimum(d, 1.0 - d)
+            if np.hypot(d[0], d[1]) < r + s:
+                ok = False
+                break
+        if not ok:
+            continue
+        discs.append((p, r))
+        dx = np.abs(X - p[0])
+        dx = np.minimum(dx, 1.0 - dx)
+        dy = np.abs(Y - p[1])
+        dy = np.minimum(dy, 1.0 - dy)
+        mask |= dx * dx + dy * dy <= r * r
+        if mask.mean() >= solid_fraction:
+            break
+    return mask, discs
+
+
+# Quarter rectangular ducts of aspect ratio 1 and 2 (shorter side = 1), 64 x 64
+# geometric (1.05) cells, inverse-power-law gas (viscosity index 0.81), 24^3
+# velocities padded to 48^3, M = 8, delta in {1, 10, 50}: 6 cases.
+DUCT_IPL = dict(name="duct-ipl081-24v-64x64-6cases", n_v=24, l_v=6.0, n_pad=48, m_angle=8,
+                kernel="ipl", visc_index=0.81, cells=64, aspect=[1, 1, 1, 2, 2, 2],
+                deltas=[1.0, 10.0, 50.0] * 2, flows=[1] * 6)
+# Periodic porous unit cell, 128^2 staircase discs (porosity 0.6), hard spheres,
+# 24^3 velocities padded to 48^3, M = 8, delta in {1, 10}.
+POROUS_HS = dict(name="porous-hs-24v-128sq-2cases", n_v=24, l_v=6.0, n_pad=48, m_angle=8,
+                 kernel="hs", cells=128, deltas=[1.0, 10.0], flows=[1, 1])
+
+
+def duct_cases(w):
+    out = []
+    for ar in w["aspect"]:
+        out.append((duct_faces(w["cells"], 0.5), duct_faces(w["cells"], 0.5 * ar), None))
+    return out
+
+
+def porous_cases(w):
+    mask, _ = porous_discs(w["cells"])
+    f = np.linspace(0.0, 1.0, w["cells"] + 1)
+    return [(f, f, mask) for _ in w["deltas"]]

@@ -26,7 +26,7 @@ PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
 FLOW_NONE, FLOW_POISEUILLE, FLOW_TRANSPIRATION = 0, 1, 2
 SCHEME_CIS, SCHEME_SIS = 0, 1
-GEOM_PLANAR_HALF = 0
+GEOM_PLANAR_HALF, GEOM_DUCT_QUARTER, GEOM_PERIODIC_2D = 0, 1, 2
 
 
 class SisError(RuntimeError):
@@ -57,7 +57,12 @@ class GeometryDesc(ctypes.Structure):
                 ("node_offset", ctypes.POINTER(ctypes.c_int64)),
                 ("x1", ctypes.POINTER(ctypes.c_double)),
                 ("delta", ctypes.POINTER(ctypes.c_double)),
-                ("flow", ctypes.POINTER(ctypes.c_int32))]
+                ("flow", ctypes.POINTER(ctypes.c_int32)),
+                ("n1", ctypes.POINTER(ctypes.c_int32)),
+                ("n2", ctypes.POINTER(ctypes.c_int32)),
+                ("face1", ctypes.POINTER(ctypes.c_double)),
+                ("face2", ctypes.POINTER(ctypes.c_double)),
+                ("solid", ctypes.POINTER(ctypes.c_uint8))]
 
 
 class SolveOpts(ctypes.Structure):
@@ -89,6 +94,7 @@ _SIGS = {
     "sis_geometry_create": (ctypes.c_int32, [_P, ctypes.POINTER(GeometryDesc), _P, ctypes.POINTER(_P)]),
     "sis_geometry_destroy": (ctypes.c_int32, [_P]),
     "sis_geometry_cells": (ctypes.c_int64, [_P]),
+    "sis_geometry_moment_stride": (ctypes.c_int32, [_P]),
     "sis_collide": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     "sis_transport_sweep": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
     "sis_moments": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P]),
@@ -241,11 +247,65 @@ class Geometry:
                          self._x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self._d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self._f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self.mom_stride = 4
         h = ctypes.c_void_p()
         check(lib().sis_geometry_create(plan.handle, ctypes.byref(d), _stream(stream), ctypes.byref(h)))
         self.handle = h
         self.n_cells = int(off[-1])
         self.n_cases = len(xs)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sis_geometry_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Geometry2D:
+    """Quarter ducts (kind "duct") or periodic porous cells (kind "periodic").
+
+    cases: list of (face1, face2, solid-or-None); solid is an (n1, n2) bool
+    array (True = solid).  Fluid cells are numbered per case in row-major
+    (i, j) order.
+    """
+
+    def __init__(self, plan, kind, cases, deltas, flows, stream=None):
+        import numpy as np
+        self.plan = plan
+        k = GEOM_DUCT_QUARTER if kind == "duct" else GEOM_PERIODIC_2D
+        n1 = np.array([len(c[0]) - 1 for c in cases], np.int32)
+        n2 = np.array([len(c[1]) - 1 for c in cases], np.int32)
+        f1 = np.ascontiguousarray(np.concatenate([np.asarray(c[0], np.float64) for c in cases]))
+        f2 = np.ascontiguousarray(np.concatenate([np.asarray(c[1], np.float64) for c in cases]))
+        has_solid = any(c[2] is not None for c in cases)
+        solid = None
+        if has_solid:
+            solid = np.ascontiguousarray(np.concatenate([
+                (np.zeros((a, b), np.uint8) if c[2] is None else np.asarray(c[2], np.uint8)).ravel()
+                for a, b, c in zip(n1, n2, cases)]))
+        self._keep = (n1, n2, f1, f2, solid)
+        self._d = np.ascontiguousarray(np.asarray(deltas, np.float64))
+        self._f = np.ascontiguousarray(np.asarray(flows, np.int32))
+        I32 = ctypes.POINTER(ctypes.c_int32)
+        D = ctypes.POINTER(ctypes.c_double)
+        d = GeometryDesc(k, len(cases), None, None, self._d.ctypes.data_as(D), self._f.ctypes.data_as(I32),
+                         n1.ctypes.data_as(I32), n2.ctypes.data_as(I32), f1.ctypes.data_as(D),
+                         f2.ctypes.data_as(D),
+                         solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if has_solid else None)
+        h = ctypes.c_void_p()
+        check(lib().sis_geometry_create(plan.handle, ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.n_cells = int(lib().sis_geometry_cells(h))
+        self.n_cases = len(cases)
+        fl = [int(np.sum(1 - (np.zeros((a, b)) if c[2] is None else np.asarray(c[2], int))))
+              for a, b, c in zip(n1, n2, cases)]
+        self.offsets = np.concatenate([[0], np.cumsum(fl)]).astype(np.int64)
+        self.mom_stride = 8
 
     def close(self):
         if getattr(self, "handle", None):

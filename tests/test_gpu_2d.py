@@ -1,0 +1,135 @@
+"""GPU parity of the 2-D cross-section path (quarter ducts, periodic porous
+cells) against the oracle, through the C ABI."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import collision, duct
+from oracle.velocity import POISEUILLE, TRANSPIRATION, VelocityGrid
+from paper_1612_04488_amd import inputs, sis
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[gpu-2d]", *a, flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def plan(n_v, l_v, m, kernel="hs"):
+    return sis.Plan(n_v, l_v, m_angle=m, kernel=kernel, visc_index=0.81)
+
+
+@functools.lru_cache(maxsize=None)
+def fsm(n_v, l_v, m, alpha=1.0):
+    return collision.FSM(VelocityGrid(n_v, l_v), m_angle=m, alpha=alpha)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def small_porous(n, seed):
+    rng = np.random.default_rng(seed)
+    m = np.zeros((n, n), bool)
+    for _ in range(3):
+        i, j = rng.integers(0, n, 2)
+        m[i:i + 2, j:j + 3] = True
+    return m
+
+
+def oracle_grids(kind, cases):
+    if kind == "duct":
+        return [duct.Grid2D(c[0], c[1], (duct.WALL, duct.SYM, duct.WALL, duct.SYM)) for c in cases]
+    return [duct.Grid2D(c[0], c[1], (duct.PERIODIC,) * 4, c[2]) for c in cases]
+
+
+CASES = {
+    "duct": [(inputs.duct_faces(7, 0.5), inputs.duct_faces(7, 0.5), None),
+             (inputs.duct_faces(5, 0.5), inputs.duct_faces(9, 1.0), None)],
+    "periodic": [(np.linspace(0, 1, 11), np.linspace(0, 1, 9), small_porous(10, 1)[:, :8]),
+                 (np.linspace(0, 1, 9), np.linspace(0, 1, 9), small_porous(8, 2))],
+}
+
+
+@pytest.mark.parametrize("kind", ["duct", "periodic"])
+def test_sweep2d_and_moments_parity(kind):
+    n_v, l_v, m = 8, 4.0, 3
+    say("sweep2d", kind)
+    p = plan(n_v, l_v, m)
+    cases = CASES[kind]
+    deltas, flows = [1.0, 7.0], [1, 2]
+    geom = sis.Geometry2D(p, kind, cases, deltas, flows)
+    f = fsm(n_v, l_v, m)
+    vg = f.grid
+    grids = oracle_grids(kind, cases)
+    nc = geom.n_cells
+    assert nc == sum(len(g.cells) for g in grids)
+    rhs = inputs.rough_h(n_v, l_v, nc) + inputs.smooth_h(n_v, l_v, nc, seed=5)
+    hprev = inputs.rough_h(n_v, l_v, nc, seed=9)
+    hd = dev(hprev.reshape(nc, -1))
+    mom = torch.empty((nc, 8), dtype=torch.float64, device=DEV)
+    sis.transport_sweep(p, geom, dev(rhs.reshape(nc, -1)), hd, mom)
+    torch.cuda.synchronize()
+    hd, mom = hd.cpu().numpy(), mom.cpu().numpy()
+    o = geom.offsets
+    for c, g in enumerate(grids):
+        s = slice(o[c], o[c + 1])
+        ref = duct.sweep_2d(rhs[s], deltas[c] * f.nu, g, vg, hprev[s])
+        assert rel(hd[s].reshape(ref.shape), ref) < 1e-12, c
+        mref = duct.moments_2d(vg, ref)
+        assert np.max(np.abs(mom[s, :7] - mref)) < 1e-12 * np.max(np.abs(mref)), c
+
+
+@pytest.mark.parametrize("kind", ["duct", "periodic"])
+def test_diffusion2d_parity(kind):
+    n_v, l_v, m = 8, 4.0, 3
+    say("diffusion2d", kind)
+    p = plan(n_v, l_v, m)
+    cases = CASES[kind]
+    deltas, flows = [2.0, 30.0], [1, 2]
+    geom = sis.Geometry2D(p, kind, cases, deltas, flows)
+    grids = oracle_grids(kind, cases)
+    nc = geom.n_cells
+    rng = np.random.default_rng(4)
+    mom = rng.standard_normal((nc, 8))
+    amom = rng.standard_normal((nc, 4))
+    N = 1.25
+    U = torch.empty(nc, dtype=torch.float64, device=DEV)
+    dU = torch.empty_like(U)
+    sis.diffusion_correct(p, geom, dev(mom), dev(amom), N, U, dU)
+    torch.cuda.synchronize()
+    U, dU = U.cpu().numpy(), dU.cpu().numpy()
+    o = geom.offsets
+    for c, g in enumerate(grids):
+        s = slice(o[c], o[c + 1])
+        ref = duct.diffusion_2d(g, mom[s], amom[s], deltas[c], N, flows[c])
+        assert rel(U[s], ref) < 1e-10, c
+        assert rel(dU[s], ref - mom[s, 0]) < 1e-9, c
+
+
+@pytest.mark.parametrize("kind,scheme", [("duct", "SIS"), ("duct", "CIS"), ("periodic", "SIS")])
+def test_solve2d_matches_oracle(kind, scheme):
+    n_v, l_v, m = 8, 4.0, 3
+    say("solve2d", kind, scheme)
+    p = plan(n_v, l_v, m)
+    cases = CASES[kind][:1]
+    deltas, flows = [1.0], [1]
+    geom = sis.Geometry2D(p, kind, cases, deltas, flows)
+    r = sis.solve(p, geom, scheme=scheme, eps=1e-9, max_it=300)
+    f = fsm(n_v, l_v, m)
+    g = oracle_grids(kind, cases)[0]
+    ref = duct.solve_2d(f, g, 1.0, POISEUILLE, scheme, N=f.nubar(), eps=1e-9, max_it=300)
+    say("gpu", r["M"], r["Q"], r["iters"], "oracle", ref["M"], ref["Q"], ref["iters"])
+    assert int(r["iters"][0]) == ref["iters"]
+    assert abs(r["M"][0] - ref["M"]) < 1e-10 * abs(ref["M"])
+    assert abs(r["Q"][0] - ref["Q"]) < 1e-10 * abs(ref["Q"])
