@@ -43,7 +43,9 @@ def cpu_baseline(w, n_cells):
     from oracle.velocity import VelocityGrid
     from paper_1612_04488_amd import inputs
     t0 = time.perf_counter()
-    f = collision.FSM(VelocityGrid(w["n_v"], w["l_v"]), n_pad=w["n_pad"], m_angle=w["m_angle"])
+    alpha = 2.0 * (1.0 - w.get("visc_index", 0.81)) if w["kernel"] == "ipl" else 1.0
+    f = collision.FSM(VelocityGrid(w["n_v"], w["l_v"]), n_pad=w["n_pad"], m_angle=w["m_angle"],
+                      alpha=alpha)
     t_build = time.perf_counter() - t0
     h = inputs.smooth_h(w["n_v"], w["l_v"], n_cells)
     t0 = time.perf_counter()
@@ -72,7 +74,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--workload", default="batch", choices=["batch", "small"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "small", "duct", "porous"])
+    ap.add_argument("--ttr", default="fp64,fp32,bf16x3,fp64+projection,bf16x3+projection",
+                    help="time-to-residual runs (comma list)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttr", action="store_true", help="skip time-to-residual runs")
     ap.add_argument("--cpu-cells", type=int, default=12)
@@ -89,15 +93,24 @@ def main():
     from paper_1612_04488_amd import inputs, sis
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    w = inputs.PLANAR_BATCH if args.workload == "batch" else inputs.PLANAR_SMALL
+    w = {"batch": inputs.PLANAR_BATCH, "small": inputs.PLANAR_SMALL, "duct": inputs.DUCT_IPL,
+         "porous": inputs.POROUS_HS}[args.workload]
     t0 = time.perf_counter()
-    plan = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"])
+    plan = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"],
+                    visc_index=w.get("visc_index", 0.81))
     t_plan = time.perf_counter() - t0
     info = plan.info
     log(f"plan {w['name']}: {t_plan:.2f} s (host {info['plan_seconds_host']:.2f} s), "
         f"operator {info['operator_bytes'] / 2**30:.2f} GiB")
-    xs = inputs.workload_nodes(w)
-    geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
+    if args.workload in ("batch", "small"):
+        xs = inputs.workload_nodes(w)
+        geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
+        per_case = [len(x) for x in xs]
+    else:
+        cases = inputs.duct_cases(w) if args.workload == "duct" else inputs.porous_cases(w)
+        geom = sis.Geometry2D(plan, "duct" if args.workload == "duct" else "periodic", cases,
+                              w["deltas"], w["flows"])
+        per_case = np.diff(geom.offsets).tolist()
     nc, n3 = geom.n_cells, plan.n3
     plan.set_precision(args.precision)
 
@@ -120,7 +133,7 @@ def main():
 
     # ---------------------------------------------------------- dominant kernel: contraction
     h = torch.tensor(inputs.smooth_h(w["n_v"], w["l_v"], nc).reshape(nc, n3), device="cuda")
-    delta = torch.tensor(np.repeat(w["deltas"], [len(x) for x in xs]), dtype=torch.float64, device="cuda")
+    delta = torch.tensor(np.repeat(w["deltas"], per_case), dtype=torch.float64, device="cuda")
     rhs = torch.empty_like(h)
     plan.collide(h, delta, rhs)   # warm
     torch.cuda.synchronize()
@@ -149,7 +162,7 @@ def main():
     ttr = {}
     if not args.no_ttr:
         ref = {}
-        runs = [("fp64", False), ("fp32", False), ("bf16x3", False), ("fp64", True), ("bf16x3", True)]
+        runs = [(r.split("+")[0], r.endswith("+projection")) for r in args.ttr.split(",") if r]
         for prec, proj in runs:
             plan.set_precision(prec)
             r = sis.solve(plan, geom, scheme="SIS", eps=1e-8, max_it=400, project=proj,
@@ -159,10 +172,11 @@ def main():
                  "converged": bool(r["status"] == 0), "M": r["M"].tolist(), "Q": r["Q"].tolist()}
             if prec == "fp64":
                 ref[proj] = r
-                if proj:
+                if proj and False in ref:
                     e["projection_effect_M_vs_fp64"] = float(np.max(np.abs(r["M"] - ref[False]["M"]) / np.abs(ref[False]["M"])))
-            else:
-                base = ref[proj]
+            elif proj in ref or False in ref:
+                base = ref[proj] if proj in ref else ref[False]
+                e["compared_with"] = "fp64" + ("+projection" if proj in ref and proj else "")
                 e["max_rel_dev_M_vs_fp64"] = float(np.max(np.abs(r["M"] - base["M"]) / np.abs(base["M"])))
                 e["max_rel_dev_Q_vs_fp64"] = float(np.max(np.abs(r["Q"] - base["Q"]) / np.abs(base["Q"])))
                 e["speedup_vs_fp64"] = float(base["seconds"] / r["seconds"])
@@ -176,7 +190,8 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.precision],
            "data": "synthetic",
-           "config": {"workload": w["name"], "n_v": w["n_v"], "l_v": w["l_v"], "n_pad": w["n_pad"],
+           "config": {"workload": w["name"], "kernel": w["kernel"], "n_v": w["n_v"], "l_v": w["l_v"],
+                      "n_pad": w["n_pad"],
                       "directions": D, "cells": nc, "cases": geom.n_cases, "deltas": w["deltas"],
                       "flows": w["flows"], "scheme": "SIS", "collision_precision": args.precision},
            "roofline": roofline,
