@@ -108,3 +108,45 @@ def sigma_quadrature_L(v, poly, b0, nr=96, nu_ang=(24, 48), ns=(8, 16), rmax=Non
         br = (poly(vp) + poly(vsp)) @ wsg - 4.0 * math.pi * (pv + poly(vs))
         total += wri * ri ** 2 * ri * np.sum(wom * f(vs) * br)
     return b0 * f(v) * total
+
+
+def sigma_quadrature_mix_L(v, a_, polys, masses, diameters, chi, b0, scale,
+                           nr=96, nu_ang=(24, 48), ns=(8, 16)):
+    """Binary hard-sphere mixture: L_a(h)(v) at one point v for h_s = f_s p_s.
+
+    Plain sigma representation of the linearized operator of eq. Boltzmann_lin
+    (no Carleman form, no truncation, no spectral step): with m_a |v'|^2 +
+    m_b |v*'|^2 = m_a |v|^2 + m_b |v*|^2 the Maxwellians factor out,
+      L_a = scale sum_b b_ab f_a(v) int dv* f_b(v*) |u| int dsigma
+            [p_a(v') + p_b(v*') - p_a(v) - p_b(v*)],
+      v' = v - mu_b u + mu_b |u| sigma,  v*' = v* + mu_a u - mu_a |u| sigma,
+    u = v - v*, mu_b = m_b/(m_a + m_b), mu_a = 1 - mu_b, b_ab = b0 (d_ab/d_A)^2.
+    polys: two callables (species A, B) mapping (..., 3) velocities to p_s.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    m = np.asarray(masses, float)
+    d = np.asarray(diameters, float)
+    x = np.asarray(chi, float)
+    av = m / m[0]
+    f = [lambda w, s=s: x[s] * (av[s] / math.pi) ** 1.5 * np.exp(-av[s] * np.sum(w * w, axis=-1))
+         for s in range(2)]
+    om, wom = sphere_rule(*nu_ang)
+    sg, wsg = sphere_rule(*ns)
+    pa_v = polys[a_](v)
+    out = 0.0
+    for b_ in range(2):
+        mub = m[b_] / (m[a_] + m[b_])
+        mua = 1.0 - mub
+        bab = b0 * (0.5 * (d[a_] + d[b_]) / d[0]) ** 2
+        rmax = np.linalg.norm(v) + 9.0 / math.sqrt(av[b_])
+        r, wr = _gauss(0.0, rmax, nr)
+        total = 0.0
+        for ri, wri in zip(r, wr):
+            u = ri * om
+            vs = v - u
+            vp = (v - mub * u)[:, None, :] + mub * ri * sg[None, :, :]
+            vsp = (vs + mua * u)[:, None, :] - mua * ri * sg[None, :, :]
+            br = (polys[a_](vp) + polys[b_](vsp)) @ wsg - 4.0 * math.pi * (pa_v + polys[b_](vs))
+            total += wri * ri ** 2 * ri * np.sum(wom * f[b_](vs) * br)
+        out += bab * total
+    return scale * f[a_](v) * out
