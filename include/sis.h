@@ -89,6 +89,15 @@ typedef struct {
   int32_t kernel;     /* SIS_KERNEL_*                                                  */
   double  visc_index; /* IPL viscosity index w: alpha = 2 (1 - w), gamma = 0           */
   int32_t n_threads;  /* host threads for table construction (0 -> hardware count)    */
+  /* Binary gas mixture (Sec. 5), hard spheres only.  n_species = 0 or 1: one gas
+   * (the fields below are ignored).  n_species = 2: species A, B with masses,
+   * diameters (any common unit) and molar fractions chi (> 0, sum 1); velocities
+   * in units of A's most probable speed; see "mixtures" below.                   */
+  int32_t n_species;
+  double  mass[2];
+  double  diam[2];
+  double  chi[2];
+  int32_t m_rho;      /* Gauss nodes on [0, R] of the rho integral of unequal-mass pairs (0 -> 16) */
 } sis_velocity_desc;
 
 typedef struct {
@@ -97,25 +106,49 @@ typedef struct {
   double  alpha, gamma;
   int64_t operator_bytes;                /* device bytes of the FP64 operator                */
   double  plan_seconds_host, plan_seconds_device;
+  int32_t n_species;                     /* 1 or 2                                           */
+  int32_t n_dof;                         /* n_species * n3: unknowns per spatial cell        */
+  double  nubar_b;                       /* mixture: int nu_B f_B / chi_B (nubar is A's)     */
+  double  viscosity_ratio;               /* mixture: mu_mix / mu_A (first Chapman-Enskog)    */
+  double  flow_factor;                   /* mixture: sqrt(m / m_A), m = chi_A m_A + chi_B m_B */
 } sis_plan_info;
 
+/* Mixtures (n_species = 2).  Unknowns per spatial cell: h = (h_A, h_B),
+ * stored [cell][species][n3] (n_dof = 2 n3 doubles per cell).  Operator
+ * (eq. Boltzmann_lin; the mixture FSM the paper cites, in a Carleman form
+ * for unequal masses with 2mu = 2 m_b/(m_a+m_b), kappa = (m_a-m_b)/(m_a+m_b)):
+ *   L+_a = sum_b Q+_ab(f_a, h_b) + Q+_ab(h_a, f_b) - f_a F^-1[beta_ab F h_b],
+ *   Q+_ab(g,h) = 4 b_ab sum_p W_p int_{-R}^{R} |rho| g(v + 2mu rho e_p) (psi_p h)(v - kappa rho e_p) drho,
+ *   b_ab = b0 ((d_a + d_b)/(2 d_A))^2, beta_ab = 4 b_ab sum_p W_p phi_p psi_p,
+ *   nu_a = sum_b F^-1[beta_ab F f_b],  f_a = chi_a (m_a/(pi m_A))^{3/2} e^{-m_a v^2/m_A};
+ * the rho integral is phi_p in closed form for equal masses and an m_rho-point
+ * Gauss-Legendre rule on [0, R] (mirrored) otherwise.  delta is normalised
+ * with the mixture viscosity (first Chapman-Enskog, hard spheres) and the
+ * mixture most probable speed: every table carries sqrt(m_A/m) mu_mix/mu_A.
+ * Supported: planar geometry, Poiseuille flow (SIS_FLOW_POISEUILLE or NONE),
+ * no invariant projection.  Per-cell arrays of the compute calls become
+ * per (cell, species) as stated at each call.                               */
+
 /* Build the tables on the host (threads) and assemble the operator on the
- * current device with `stream`.  Synchronous.  Owns ~8 n3^2 bytes of device
- * memory plus tables.                                                        */
+ * current device with `stream`.  Synchronous.  Owns ~8 n_dof^2 bytes of
+ * device memory plus tables.                                                 */
 sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, sis_plan_t* out);
 sis_status sis_plan_destroy(sis_plan_t plan);
 sis_status sis_plan_query(sis_plan_t plan, sis_plan_info* out);
 
 /* Copy plan tables to HOST arrays (any may be NULL):
- * v1d[n_v], feq[n3], nu[n3] (delta = 1), op[n3*n3] (row-major, row = output
- * velocity; the L+ matrix at delta = 1).  Synchronous.                     */
+ * v1d[n_v], feq[n_species][n3], nu[n_species][n3] (delta = 1),
+ * op[n_dof*n_dof] (row-major, row = output (species, velocity); the L+ matrix
+ * at delta = 1).  Synchronous.                                             */
 sis_status sis_plan_tables(sis_plan_t plan, double* v1d, double* feq, double* nu, double* op);
 
 /* Host-only table construction (no device needed): the delta = 1 collision
  * frequency nu_eq[n3], the equilibrium feq[n3], and optionally the
  * f_eq-fields A_p = F^-1[psi_p F f_eq], B_p = F^-1[phi_p F f_eq] on the n3
  * grid for every direction p ([n_dir][n3] each), as used by the assembly.
- * Arrays are HOST memory, any may be NULL.  Reports b0 and nubar.           */
+ * Arrays are HOST memory, any may be NULL.  Reports b0 and nubar.
+ * Mixtures: feq and nu are [2][n3], nubar points to 2 doubles (A, B), A and
+ * B must be NULL.                                                           */
 sis_status sis_host_tables(const sis_velocity_desc* desc, double* feq, double* nu,
                            double* A, double* B, double* b0, double* nubar);
 
@@ -181,7 +214,11 @@ int32_t    sis_geometry_moment_stride(sis_geom_t geom);   /* 4 planar, 8 in 2-D;
  * (and L+): L -= f_eq sum_i c_i psi_i, c = Gram^-1 m, m_i = sum w psi_i L,
  * psi in {1, v1, v2, v3, |v|^2}.
  * delta[n_cells] and flow[n_cells] (int32) are DEVICE arrays; flow may be NULL.
- * Arithmetic of the contraction per sis_plan_set_precision; rest FP64.      */
+ * Arithmetic of the contraction per sis_plan_set_precision; rest FP64.
+ * Mixtures: h, rhs_out, lh_out are [n_cells][2][n3], dU is [n_cells][2]
+ * (correction h_a += dU_a 2 (m_a/m_A) v3 f_a; the correction of both species
+ * enters L+ of each), amom_out is [n_cells][2][4]; S_a = v3 f_a for
+ * Poiseuille, 0 otherwise; project must be 0.                               */
 sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const double* dU,
                        const double* delta, const int32_t* flow, int32_t project,
                        double* rhs_out, double* lh_out, double* amom_out, hipStream_t stream);
@@ -197,11 +234,15 @@ sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const 
  * across a periodic edge from h_half_out on entry (the previous iterate), so
  * h_half_out is in/out there.  mom_out: [cells][8] =
  * { U3, q3, G1, G12 = F_111/4, G2 = F_021/4, P13, P23, 0 }.
- * rhs, h_half_out: [cells][n3]; moments are midpoint sums with weight dv^3.   */
+ * rhs, h_half_out: [cells][n3]; moments are midpoint sums with weight dv^3.
+ * Mixtures (planar): each species is swept with its own nu_a; rhs, h_half_out
+ * [cells][2][n3]; mom_out [cells][2][4] = { int v3 h_a, q_a =
+ * int (m_a v^2/m_A - 5/2) v3 h_a, G1, P_a13 = 2 (m_a/m_A) int v1 v3 h_a }.    */
 sis_status sis_transport_sweep(sis_plan_t plan, sis_geom_t geom, const double* rhs,
                                double* h_half_out, double* mom_out, hipStream_t stream);
 
-/* sis_moments -- { U3, q3, G1, P13 } of h[n_cells][n3] -> mom_out[n_cells][4]. */
+/* sis_moments -- { U3, q3, G1, P13 } of h[n_cells][n3] -> mom_out[n_cells][4]
+ * (mixtures: h[n_cells][2][n3] -> mom_out[n_cells][2][4] as for the sweep). */
 sis_status sis_moments(sis_plan_t plan, int64_t n_cells, const double* h, double* mom_out,
                        hipStream_t stream);
 
@@ -217,7 +258,14 @@ sis_status sis_moments(sis_plan_t plan, int64_t n_cells, const double* h, double
  * step), U at the wall = U3 of h_half.  mom_half: [cells][4] from the sweep;
  * amom: [cells][4] from sis_collide (NULL -> A1 = 0).  N <= 0 -> nubar.
  * Outputs U_out[cells] and dU_out[cells] = U - U3(h_half) (the correction
- * amplitude of eq. guided), both nullable.                                   */
+ * amplitude of eq. guided), both nullable.
+ * Mixtures (eqs. LBE2_true2, LBE2_true1 integrated once from the symmetry
+ * plane, same march; U_a = int v3 h_a / chi_a):
+ *   chi_B d(U_B)/dx1 + d(G1_B)/dx1 = -N_B delta (m_A/m_B) P_B13 + A_B,
+ *   chi_A d(U_A)/dx1 + d(G1_A)/dx1 = -N_A delta (x1 - P_B13) + A_A,
+ * A_a = amom[c][a][0] + N_a delta amom[c][a][1], P_B13 from mom_half;
+ * N <= 0 -> N_a = int nu_a f_a / chi_a, else N_A = N_B = N.  mom_half,
+ * amom [cells][2][4]; U_out, dU_out [cells][2].                               */
 sis_status sis_diffusion_correct(sis_plan_t plan, sis_geom_t geom, const double* mom_half,
                                  const double* amom, double N, double* U_out, double* dU_out,
                                  hipStream_t stream);
@@ -248,6 +296,8 @@ typedef struct {
                             iteration).  Ignored in FP64.                    */
 } sis_solve_opts;
 
+/* Mixtures: M, Q are [n_cases][2] (M_a = sqrt(m/m_A) 2 int U_a dx1, Q_a
+ * likewise with q_a; all four must meet eps), U, q are [cells][2].          */
 typedef struct {
   double*  M;            /* [n_cases] mass flow rate                                   */
   double*  Q;            /* [n_cases] heat flow rate                                   */

@@ -47,7 +47,7 @@ import numpy as np
 from .collision import _phi_hs, b0_unit, directions, psi_factor
 from .velocity import VelocityGrid
 
-NE_AR = dict(masses=(20.1797, 39.948), diameters=(0.72, 1.0))
+NE_AR = dict(masses=(20.18, 39.95), diameters=(0.72, 1.0))
 
 
 def viscosity_ratio(masses, diameters, chi):

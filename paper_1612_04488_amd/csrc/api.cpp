@@ -12,6 +12,7 @@
 
 #include "geom2d.h"
 #include "kernels.h"
+#include "mixture.h"
 #include "planner.h"
 #include "sis.h"
 
@@ -72,14 +73,19 @@ struct sis_plan {
   double lv = 0, dv = 0, w = 0, b0 = 0, R = 0, nubar = 0, alpha = 1, gamma = 0;
   double host_s = 0, dev_s = 0;
   int precision = SIS_PREC_FP64;
-  double* op = nullptr;         // [n3][n3] L+ at delta = 1
+  // species: 1 (one gas) or 2 (binary mixture); rows of the operator are (species, velocity)
+  int nsp = 1, ndof = 0;
+  double mass_ratio[2] = {1.0, 1.0}, chi[2] = {1.0, 0.0}, nubar_s[2] = {0.0, 0.0};
+  double cU_s[2] = {0.0, 0.0}, cq_s[2] = {0.0, 0.0};
+  double flow_factor = 1.0, visc_ratio = 1.0;
+  double* op = nullptr;         // [ndof][ndof] L+ at delta = 1
   float* op32 = nullptr;
   uint16_t* ophi = nullptr;
   uint16_t* oplo = nullptr;
   double* v1d = nullptr;        // [n]
-  double* feq = nullptr;        // [n3]
-  double* nu = nullptr;         // [n3]
-  double* Kc = nullptr;         // [n3] L+(2 v3 feq)
+  double* feq = nullptr;        // [nsp][n3]
+  double* nu = nullptr;         // [nsp][n3]
+  double* Kc = nullptr;         // [nsp][ndof] L+ of the correction shape of each species
   double* gram_inv = nullptr;   // [25]
   double cU = 0, cq = 0;        // U3, q3 of 2 v3 feq
   std::vector<double> h_v1d, h_feq, h_nu;
@@ -167,7 +173,35 @@ sis_status validate_desc(const sis_velocity_desc* d) {
     return fail(SIS_E_UNSUPPORTED, "unknown collision kernel %d", d->kernel);
   if (d->kernel == SIS_KERNEL_IPL && !(d->visc_index >= 0.5 && d->visc_index <= 1.0))
     return fail(SIS_E_INVALID, "IPL viscosity index must be in [0.5, 1]");
+  if (d->n_species < 0 || d->n_species > 2) return fail(SIS_E_UNSUPPORTED, "n_species must be 1 or 2");
+  if (d->n_species == 2) {
+    if (d->kernel != SIS_KERNEL_HARD_SPHERE) return fail(SIS_E_UNSUPPORTED, "mixtures support hard spheres only");
+    for (int s = 0; s < 2; ++s) {
+      if (!(d->mass[s] > 0.0) || !std::isfinite(d->mass[s])) return fail(SIS_E_INVALID, "mass[%d] must be positive", s);
+      if (!(d->diam[s] > 0.0) || !std::isfinite(d->diam[s])) return fail(SIS_E_INVALID, "diam[%d] must be positive", s);
+      if (!(d->chi[s] > 0.0 && d->chi[s] < 1.0)) return fail(SIS_E_INVALID, "chi[%d] must be in (0, 1)", s);
+    }
+    if (std::fabs(d->chi[0] + d->chi[1] - 1.0) > 1e-12) return fail(SIS_E_INVALID, "chi must sum to 1");
+    if (d->m_rho < 0 || d->m_rho > 64) return fail(SIS_E_INVALID, "m_rho must be in [0, 64]");
+  }
   return SIS_OK;
+}
+
+sis::MixDesc mix_desc(const sis_velocity_desc* d) {
+  sis::MixDesc m;
+  m.n_v = d->n_v;
+  m.l_v = d->l_v;
+  m.n_pad = d->n_pad;
+  m.m_angle = d->m_angle;
+  m.m_rho = d->m_rho > 0 ? d->m_rho : 16;
+  m.r_trunc = d->r_trunc;
+  for (int s = 0; s < 2; ++s) {
+    m.mass[s] = d->mass[s];
+    m.diam[s] = d->diam[s];
+    m.chi[s] = d->chi[s];
+  }
+  m.n_threads = d->n_threads;
+  return m;
 }
 
 sis::TableDesc table_desc(const sis_velocity_desc* d) {
@@ -200,10 +234,10 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
                        double* accref = nullptr) {
   if (precision < 0) precision = p->precision;
   int tile, splits;
-  choose_gemm(n_cells, p->n3, &tile, &splits);
+  choose_gemm(n_cells, p->ndof, &tile, &splits);
   double* acc = rhs;
   if (splits > 1) {
-    HIP_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * n_cells * p->n3 * sizeof(double)));
+    HIP_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * n_cells * p->ndof * sizeof(double)));
     acc = static_cast<double*>(p->ws_acc.p);
   }
   sis::GemmArgs g{};
@@ -216,8 +250,8 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   g.oplo = p->oplo;
   g.acc = acc;
   g.M = n_cells;
-  g.N = p->n3;
-  g.K = p->n3;
+  g.N = p->ndof;
+  g.K = p->ndof;
   g.splits = splits;
   g.tile = tile;
   if (p->timing) {
@@ -240,7 +274,10 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   sis::FinishArgs f{};
   f.n = p->n;
   f.n3 = p->n3;
-  f.n_cells = n_cells;
+  f.nsp = p->nsp;
+  f.mass_ratio[0] = p->mass_ratio[0];
+  f.mass_ratio[1] = p->mass_ratio[1];
+  f.n_cells = n_cells * p->nsp;
   f.splits = splits;
   f.acc = acc;
   f.h = h;
@@ -290,10 +327,13 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     return SIS_OK;
   }
   const int W = (p->n3 / 2 + 63) / 64;
-  HIP_TRY(p->ws_part.ensure(static_cast<size_t>(g->n_cells) * 8 * W * sizeof(double)));
+  HIP_TRY(p->ws_part.ensure(static_cast<size_t>(g->n_cells) * p->nsp * 8 * W * sizeof(double)));
   sis::SweepArgs a{};
   a.n = p->n;
   a.n3 = p->n3;
+  a.nsp = p->nsp;
+  a.mass_ratio[0] = p->mass_ratio[0];
+  a.mass_ratio[1] = p->mass_ratio[1];
   a.n_cases = g->n_cases;
   a.node_off = g->off;
   a.coef = g->coef;
@@ -308,7 +348,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
   a.w = p->w;
   a.max_nodes = g->max_nodes;
   HIP_TRY(sis::launch_sweep1d(a, s));
-  if (mom) HIP_TRY(sis::launch_reduce_partials(a.part, W, g->n_cells, mom, s));
+  if (mom) HIP_TRY(sis::launch_reduce_partials(a.part, W, g->n_cells * p->nsp, mom, s));
   return SIS_OK;
 }
 
@@ -346,6 +386,19 @@ sis::Diff2DArgs diff2d_args(sis_plan* p, sis_geom* g, const double* mom, const d
 sis_status check_plan(sis_plan_t p) {
   if (!p) return fail(SIS_E_INVALID, "null plan");
   return SIS_OK;
+}
+
+// Species fields of the planar velocity equation(s); N <= 0 -> nubar of each species.
+void set_species(sis::DiffusionArgs& a, const sis_plan* p, double N) {
+  a.nsp = p->nsp;
+  for (int s = 0; s < 2; ++s) {
+    a.chi[s] = p->chi[s];
+    a.mass_ratio[s] = p->mass_ratio[s];
+    a.Ns[s] = N > 0.0 ? N : p->nubar_s[s];
+    a.cUs[s] = p->cU_s[s];
+    a.cqs[s] = p->cq_s[s];
+  }
+  a.flow_factor = p->flow_factor;
 }
 
 }  // namespace
@@ -447,6 +500,167 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
   return SIS_OK;
 }
 
+
+// Binary-mixture plan: 2 x 2 blocks of n3 x n3, each assembled from the
+// equal-mass (closed-form phi) terms or the rho-quadrature terms of the
+// unequal-mass gain, plus the loss.  Cross terms are built on the host in
+// chunks and accumulated on the device while the next chunk is built.
+sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, sis_plan_t* out) {
+  auto t0 = std::chrono::steady_clock::now();
+  const sis::MixDesc md = mix_desc(desc);
+  sis::MixTables t;
+  std::string err;
+  if (!sis::build_mix_base(md, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
+  sis_plan* p = new sis_plan();
+  HIP_TRY(hipGetDevice(&p->device));
+  const int n = t.n, n3 = t.n3, D = t.D, nd3 = t.nd3;
+  p->n = n;
+  p->n3 = n3;
+  p->np = t.np;
+  p->D = D;
+  p->m_angle = desc->m_angle;
+  p->lv = t.lv;
+  p->dv = t.dv;
+  p->w = t.dv * t.dv * t.dv;
+  p->b0 = t.b0;
+  p->R = t.R;
+  p->alpha = 1.0;
+  p->gamma = 0.0;
+  p->nsp = 2;
+  p->ndof = 2 * n3;
+  for (int s = 0; s < 2; ++s) {
+    p->mass_ratio[s] = t.a[s];
+    p->chi[s] = t.chi[s];
+    p->nubar_s[s] = t.nubar[s];
+  }
+  p->nubar = t.nubar[0];
+  p->flow_factor = std::sqrt(t.mbar_over_mA);
+  p->visc_ratio = sis::mix_viscosity_ratio(md.mass, md.diam, md.chi);
+  p->h_v1d = t.v1d;
+  p->h_feq = t.feq;
+  p->h_nu = t.nu;
+  const int64_t ndof = p->ndof;
+  const int chunk = 64;  // (direction, rho) items per host/device round
+  const size_t tabX = static_cast<size_t>(std::max(2 * chunk, D)) * n3;
+  const size_t tabY = static_cast<size_t>(std::max(2 * chunk, 2 * D)) * nd3;
+  double *dX = nullptr, *dY = nullptr, *dbr = nullptr;
+  auto cleanup = [&]() { dfree(dX); dfree(dY); dfree(dbr); };
+#define MIX_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      (void)hipStreamSynchronize(stream);                                                    \
+      cleanup();                                                                             \
+      delete p;                                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s", #expr,      \
+                  hipGetErrorString(e_));                                                    \
+    }                                                                                        \
+  } while (0)
+  MIX_TRY(dmalloc(&dX, tabX));
+  MIX_TRY(dmalloc(&dY, tabY));
+  MIX_TRY(dmalloc(&dbr, nd3));
+  MIX_TRY(dmalloc(&p->op, static_cast<size_t>(ndof) * ndof));
+  MIX_TRY(dmalloc(&p->v1d, n));
+  MIX_TRY(dmalloc(&p->feq, 2 * n3));
+  MIX_TRY(dmalloc(&p->nu, 2 * n3));
+  MIX_TRY(dmalloc(&p->Kc, 2 * ndof));
+  MIX_TRY(dmalloc(&p->gram_inv, 25));
+  MIX_TRY(hipMemcpyAsync(p->v1d, t.v1d.data(), n * 8, hipMemcpyHostToDevice, stream));
+  MIX_TRY(hipMemcpyAsync(p->feq, t.feq.data(), 2 * n3 * 8, hipMemcpyHostToDevice, stream));
+  MIX_TRY(hipMemcpyAsync(p->nu, t.nu.data(), 2 * n3 * 8, hipMemcpyHostToDevice, stream));
+  MIX_TRY(hipMemcpyAsync(dbr, t.beta_r.data(), nd3 * 8, hipMemcpyHostToDevice, stream));
+  MIX_TRY(hipMemsetAsync(p->op, 0, static_cast<size_t>(ndof) * ndof * 8, stream));
+  auto block = [&](int a, int b) { return p->op + static_cast<size_t>(a) * n3 * ndof + static_cast<size_t>(b) * n3; };
+  // loss terms: block (a, b) -= scale C_ab f_a(i) beta_r(i - j)
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      MIX_TRY(sis::launch_assemble(n, 0, nullptr, nullptr, p->feq + static_cast<size_t>(a) * n3,
+                                   t.scale * t.C[a][b], dbr, block(a, b), ndof, 1, stream));
+  // equal-mass pairs: closed-form phi terms with the shared kernels Psi_p, Phi_p
+  MIX_TRY(hipMemcpyAsync(dY, t.Psi.data(), static_cast<size_t>(D) * nd3 * 8, hipMemcpyHostToDevice, stream));
+  MIX_TRY(hipMemcpyAsync(dY + static_cast<size_t>(D) * nd3, t.Phi.data(), static_cast<size_t>(D) * nd3 * 8,
+                         hipMemcpyHostToDevice, stream));
+  std::vector<double> hx(tabX), hy;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      if (t.kappa[a][b] != 0.0) continue;
+      for (int kind = 0; kind < 2; ++kind) {
+        // kind 0: Q+_ab(f_a, h_b) -> block (a, b), X = phi-field of f_a, Y = Psi
+        // kind 1: Q+_ab(h_a, f_b) -> block (a, a), X = psi-field of f_b, Y = Phi
+        const std::vector<double>& F = kind == 0 ? t.Fphi[a] : t.Fpsi[b];
+        MIX_TRY(hipStreamSynchronize(stream));
+        for (int q = 0; q < D; ++q) {
+          const double sc = t.scale * t.C[a][b] * t.W[q];
+          for (int i = 0; i < n3; ++i) hx[static_cast<size_t>(q) * n3 + i] = sc * F[static_cast<size_t>(q) * n3 + i];
+        }
+        MIX_TRY(hipMemcpyAsync(dX, hx.data(), static_cast<size_t>(D) * n3 * 8, hipMemcpyHostToDevice, stream));
+        MIX_TRY(sis::launch_assemble(n, D, dX, dY + (kind == 0 ? 0 : static_cast<size_t>(D) * nd3), nullptr, 0.0,
+                                     nullptr, kind == 0 ? block(a, b) : block(a, a), ndof, 1, stream));
+      }
+    }
+  // unequal-mass pairs: rho-quadrature terms, in chunks
+  hy.resize(static_cast<size_t>(2 * chunk) * nd3);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      if (t.kappa[a][b] == 0.0) continue;
+      const int items = D * t.m_rho;
+      for (int kind = 0; kind < 2; ++kind)
+        for (int q0 = 0; q0 < items; q0 += chunk) {
+          const int q1 = std::min(items, q0 + chunk);
+          sis::build_mix_cross_terms(t, a, b, kind, q0, q1, hx.data(), hy.data(), md.n_threads);
+          MIX_TRY(hipStreamSynchronize(stream));  // previous chunk has consumed dX, dY
+          const size_t T = 2 * static_cast<size_t>(q1 - q0);
+          MIX_TRY(hipMemcpyAsync(dX, hx.data(), T * n3 * 8, hipMemcpyHostToDevice, stream));
+          MIX_TRY(hipMemcpyAsync(dY, hy.data(), T * nd3 * 8, hipMemcpyHostToDevice, stream));
+          MIX_TRY(sis::launch_assemble(n, static_cast<int>(T), dX, dY, nullptr, 0.0, nullptr,
+                                       kind == 0 ? block(a, b) : block(a, a), ndof, 1, stream));
+        }
+    }
+  // correction shapes 2 (m_s/m_A) v3 f_s and their L+ (two-row contraction)
+  std::vector<double> corr(2 * static_cast<size_t>(ndof), 0.0);
+  for (int s = 0; s < 2; ++s) {
+    double cu = 0.0, cq = 0.0;
+    for (int i0 = 0; i0 < n; ++i0)
+      for (int i1 = 0; i1 < n; ++i1)
+        for (int i2 = 0; i2 < n; ++i2) {
+          const int i = (i0 * n + i1) * n + i2;
+          const double v1 = t.v1d[i0], v2 = t.v1d[i1], v3 = t.v1d[i2];
+          const double c = 2.0 * t.a[s] * v3 * t.feq[static_cast<size_t>(s) * n3 + i];
+          corr[static_cast<size_t>(s) * ndof + static_cast<size_t>(s) * n3 + i] = c;
+          cu += p->w * v3 * c;
+          cq += p->w * (t.a[s] * (v1 * v1 + v2 * v2 + v3 * v3) - 2.5) * v3 * c;
+        }
+    p->cU_s[s] = cu / t.chi[s];
+    p->cq_s[s] = cq;
+  }
+  p->cU = p->cU_s[0];
+  p->cq = p->cq_s[0];
+  MIX_TRY(hipStreamSynchronize(stream));
+  MIX_TRY(hipMemcpyAsync(dX, corr.data(), corr.size() * 8, hipMemcpyHostToDevice, stream));
+  {
+    sis::GemmArgs g{};
+    g.precision = 0;
+    g.X = dX;
+    g.op64 = p->op;
+    g.acc = p->Kc;
+    g.M = 2;
+    g.N = static_cast<int>(ndof);
+    g.K = static_cast<int>(ndof);
+    g.splits = 1;
+    g.tile = 1;
+    MIX_TRY(sis::launch_gemm(g, stream));
+  }
+  MIX_TRY(hipStreamSynchronize(stream));
+  cleanup();
+#undef MIX_TRY
+  auto t1 = std::chrono::steady_clock::now();
+  p->host_s = 0.0;
+  p->dev_s = std::chrono::duration<double>(t1 - t0).count();
+  *out = p;
+  g_err.clear();
+  return SIS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -458,8 +672,19 @@ sis_status sis_host_tables(const sis_velocity_desc* desc, double* feq, double* n
                            double* B, double* b0, double* nubar) {
   sis_status st = validate_desc(desc);
   if (st) return st;
-  sis::HostTables t;
   std::string err;
+  if (desc->n_species == 2) {
+    if (A || B) return fail(SIS_E_UNSUPPORTED, "A/B fields are not reported for mixtures");
+    sis::MixTables mt;
+    if (!sis::build_mix_base(mix_desc(desc), mt, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
+    if (feq) std::memcpy(feq, mt.feq.data(), mt.feq.size() * sizeof(double));
+    if (nu) std::memcpy(nu, mt.nu.data(), mt.nu.size() * sizeof(double));
+    if (b0) *b0 = mt.b0;
+    if (nubar) { nubar[0] = mt.nubar[0]; nubar[1] = mt.nubar[1]; }
+    g_err.clear();
+    return SIS_OK;
+  }
+  sis::HostTables t;
   if (!sis::build_host_tables(table_desc(desc), false, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
   if (feq) std::memcpy(feq, t.feq.data(), t.n3 * sizeof(double));
   if (nu) std::memcpy(nu, t.nu.data(), t.n3 * sizeof(double));
@@ -476,6 +701,7 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   *out = nullptr;
   sis_status st = validate_desc(desc);
   if (st) return st;
+  if (desc->n_species == 2) return create_mix_plan(desc, stream, out);
   auto t0 = std::chrono::steady_clock::now();
   sis::HostTables t;
   std::string err;
@@ -495,6 +721,9 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   p->b0 = t.b0;
   p->R = t.R;
   p->nubar = t.nubar;
+  p->nsp = 1;
+  p->ndof = t.n3;
+  p->nubar_s[0] = t.nubar;
   p->alpha = t.alpha;
   p->gamma = t.gamma;
   p->h_v1d = t.v1d;
@@ -510,8 +739,9 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
       t.B[static_cast<size_t>(d) * n3 + i] *= sc;
     }
   }
-  double *dPsi = nullptr, *dPhi = nullptr, *dA = nullptr, *dB = nullptr, *dbr = nullptr;
-  auto cleanup = [&]() { dfree(dPsi); dfree(dPhi); dfree(dA); dfree(dB); dfree(dbr); };
+  // term tables of the assembly: X = [B_p; A_p] (scaled), Y = [Psi_p; Phi_p]
+  double *dX = nullptr, *dY = nullptr, *dbr = nullptr;
+  auto cleanup = [&]() { dfree(dX); dfree(dY); dfree(dbr); };
 #define PLAN_TRY(expr)                                                                       \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
@@ -522,10 +752,9 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
                   hipGetErrorString(e_));                                                    \
     }                                                                                        \
   } while (0)
-  PLAN_TRY(dmalloc(&dPsi, t.Psi.size()));
-  PLAN_TRY(dmalloc(&dPhi, t.Phi.size()));
-  PLAN_TRY(dmalloc(&dA, t.A.size()));
-  PLAN_TRY(dmalloc(&dB, t.B.size()));
+  const size_t tabX = static_cast<size_t>(D) * n3, tabY = static_cast<size_t>(D) * t.nd3;
+  PLAN_TRY(dmalloc(&dX, 2 * tabX));
+  PLAN_TRY(dmalloc(&dY, 2 * tabY));
   PLAN_TRY(dmalloc(&dbr, t.beta_r.size()));
   PLAN_TRY(dmalloc(&p->op, static_cast<size_t>(n3) * n3));
   PLAN_TRY(dmalloc(&p->v1d, n));
@@ -533,10 +762,10 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   PLAN_TRY(dmalloc(&p->nu, n3));
   PLAN_TRY(dmalloc(&p->Kc, n3));
   PLAN_TRY(dmalloc(&p->gram_inv, 25));
-  PLAN_TRY(hipMemcpyAsync(dPsi, t.Psi.data(), t.Psi.size() * 8, hipMemcpyHostToDevice, stream));
-  PLAN_TRY(hipMemcpyAsync(dPhi, t.Phi.data(), t.Phi.size() * 8, hipMemcpyHostToDevice, stream));
-  PLAN_TRY(hipMemcpyAsync(dA, t.A.data(), t.A.size() * 8, hipMemcpyHostToDevice, stream));
-  PLAN_TRY(hipMemcpyAsync(dB, t.B.data(), t.B.size() * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dY, t.Psi.data(), tabY * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dY + tabY, t.Phi.data(), tabY * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dX, t.B.data(), tabX * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dX + tabX, t.A.data(), tabX * 8, hipMemcpyHostToDevice, stream));
   PLAN_TRY(hipMemcpyAsync(dbr, t.beta_r.data(), t.beta_r.size() * 8, hipMemcpyHostToDevice, stream));
   PLAN_TRY(hipMemcpyAsync(p->v1d, t.v1d.data(), n * 8, hipMemcpyHostToDevice, stream));
   PLAN_TRY(hipMemcpyAsync(p->feq, t.feq.data(), n3 * 8, hipMemcpyHostToDevice, stream));
@@ -557,6 +786,8 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
         p->cU += p->w * v3 * corr[i];
         p->cq += p->w * (psi[4] - 2.5) * v3 * corr[i];
       }
+  p->cU_s[0] = p->cU;
+  p->cq_s[0] = p->cq;
   if (!invert5(G, Gi)) {
     cleanup();
     delete p;
@@ -564,9 +795,9 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   }
   PLAN_TRY(hipMemcpyAsync(p->gram_inv, Gi, 25 * 8, hipMemcpyHostToDevice, stream));
 
-  PLAN_TRY(sis::launch_assemble(n, D, dPsi, dPhi, dA, dB, p->feq, dbr, p->op, stream));
+  PLAN_TRY(sis::launch_assemble(n, 2 * D, dX, dY, p->feq, 1.0, dbr, p->op, n3, 0, stream));
   // Kc = L+(2 v3 feq): one-row contraction against the operator
-  double* dcorr = dA;  // reuse (large enough)
+  double* dcorr = dX;  // reuse (large enough)
   PLAN_TRY(hipMemcpyAsync(dcorr, corr.data(), n3 * 8, hipMemcpyHostToDevice, stream));
   {
     sis::GemmArgs g{};
@@ -613,7 +844,12 @@ sis_status sis_plan_query(sis_plan_t p, sis_plan_info* out) {
   out->nubar = p->nubar;
   out->alpha = p->alpha;
   out->gamma = p->gamma;
-  out->operator_bytes = static_cast<int64_t>(p->n3) * p->n3 * 8;
+  out->operator_bytes = static_cast<int64_t>(p->ndof) * p->ndof * 8;
+  out->n_species = p->nsp;
+  out->n_dof = p->ndof;
+  out->nubar_b = p->nsp == 2 ? p->nubar_s[1] : 0.0;
+  out->viscosity_ratio = p->visc_ratio;
+  out->flow_factor = p->flow_factor;
   out->plan_seconds_host = p->host_s;
   out->plan_seconds_device = p->dev_s;
   return SIS_OK;
@@ -622,15 +858,15 @@ sis_status sis_plan_query(sis_plan_t p, sis_plan_info* out) {
 sis_status sis_plan_tables(sis_plan_t p, double* v1d, double* feq, double* nu, double* op) {
   if (sis_status st = check_plan(p)) return st;
   if (v1d) std::memcpy(v1d, p->h_v1d.data(), p->n * 8);
-  if (feq) std::memcpy(feq, p->h_feq.data(), p->n3 * 8);
-  if (nu) std::memcpy(nu, p->h_nu.data(), p->n3 * 8);
-  if (op) HIP_TRY(hipMemcpy(op, p->op, static_cast<size_t>(p->n3) * p->n3 * 8, hipMemcpyDeviceToHost));
+  if (feq) std::memcpy(feq, p->h_feq.data(), static_cast<size_t>(p->nsp) * p->n3 * 8);
+  if (nu) std::memcpy(nu, p->h_nu.data(), static_cast<size_t>(p->nsp) * p->n3 * 8);
+  if (op) HIP_TRY(hipMemcpy(op, p->op, static_cast<size_t>(p->ndof) * p->ndof * 8, hipMemcpyDeviceToHost));
   return SIS_OK;
 }
 
 sis_status sis_plan_set_precision(sis_plan_t p, int32_t precision, hipStream_t stream) {
   if (sis_status st = check_plan(p)) return st;
-  const int64_t cnt = static_cast<int64_t>(p->n3) * p->n3;
+  const int64_t cnt = static_cast<int64_t>(p->ndof) * p->ndof;
   if (precision == SIS_PREC_FP64) {
   } else if (precision == SIS_PREC_FP32) {
     if (!p->op32) {
@@ -659,6 +895,12 @@ sis_status sis_geometry_create(sis_plan_t p, const sis_geometry_desc* d, hipStre
   if (!d || !out) return fail(SIS_E_INVALID, "null argument");
   *out = nullptr;
   if (d->n_cases < 1) return fail(SIS_E_INVALID, "n_cases must be >= 1");
+  if (p->nsp == 2) {
+    if (d->kind != SIS_GEOM_PLANAR_HALF) return fail(SIS_E_UNSUPPORTED, "mixtures support the planar geometry only");
+    for (int c = 0; c < d->n_cases; ++c)
+      if (d->flow && d->flow[c] != SIS_FLOW_NONE && d->flow[c] != SIS_FLOW_POISEUILLE)
+        return fail(SIS_E_UNSUPPORTED, "mixtures support Poiseuille flow only (case %d)", c);
+  }
   if (d->kind == SIS_GEOM_DUCT_QUARTER || d->kind == SIS_GEOM_PERIODIC_2D)
     return create_geometry_2d(p, d, stream, out);
   if (d->kind != SIS_GEOM_PLANAR_HALF) return fail(SIS_E_UNSUPPORTED, "geometry kind %d not supported", d->kind);
@@ -770,6 +1012,7 @@ sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const dou
   if (!h || !delta || !rhs_out) return fail(SIS_E_INVALID, "h, delta and rhs_out must be non-null");
   if (!aligned16(h) || !aligned16(rhs_out)) return fail(SIS_E_INVALID, "h and rhs_out must be 16-byte aligned");
   if (h == rhs_out) return fail(SIS_E_INVALID, "rhs_out must not alias h");
+  if (project && p->nsp != 1) return fail(SIS_E_UNSUPPORTED, "invariant projection is for one gas only");
   return run_collide(p, n_cells, h, dU, delta, flow, project, rhs_out, lh_out, amom_out, nullptr, stream);
 }
 
@@ -787,7 +1030,8 @@ sis_status sis_moments(sis_plan_t p, int64_t n_cells, const double* h, double* m
   if (n_cells < 0) return fail(SIS_E_SHAPE, "n_cells must be >= 0");
   if (n_cells == 0) return SIS_OK;
   if (!h || !mom_out) return fail(SIS_E_INVALID, "null array");
-  HIP_TRY(sis::launch_moments(p->n, p->n3, n_cells, p->v1d, h, p->w, mom_out, stream));
+  HIP_TRY(sis::launch_moments(p->n, p->n3, p->nsp, p->mass_ratio, n_cells * p->nsp, p->v1d, h, p->w, mom_out,
+                              stream));
   return SIS_OK;
 }
 
@@ -820,6 +1064,7 @@ sis_status sis_diffusion_correct(sis_plan_t p, sis_geom_t g, const double* mom_h
   a.cq = p->cq;
   a.U = U_out;
   a.dU = dU_out;
+  set_species(a, p, N);
   HIP_TRY(sis::launch_diffusion1d(a, stream));
   return SIS_OK;
 }
@@ -908,6 +1153,7 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
   a.case_active = b->cact;
   a.qfield = b->q;
   a.eps = b->o.eps;
+  set_species(a, p, b->o.N);
   HIP_TRY(sis::launch_diffusion1d(a, s));
   HIP_TRY(sis::launch_expand_active(b->cact, g->case_of_cell, g->n_cells, b->lact, s));
   return SIS_OK;
@@ -916,11 +1162,12 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
 sis_status state_init(sis_state* b, hipStream_t s) {
   const int64_t nc = b->g->n_cells;
   const int ncase = b->g->n_cases;
-  HIP_TRY(hipMemsetAsync(b->h, 0, static_cast<size_t>(nc) * b->p->n3 * 8, s));
-  HIP_TRY(hipMemsetAsync(b->dU, 0, nc * 8, s));
-  HIP_TRY(hipMemsetAsync(b->U, 0, nc * 8, s));
-  HIP_TRY(hipMemsetAsync(b->q, 0, nc * 8, s));
-  HIP_TRY(hipMemsetAsync(b->state, 0, ncase * 4 * 8, s));
+  const int nsp = b->p->nsp;
+  HIP_TRY(hipMemsetAsync(b->h, 0, static_cast<size_t>(nc) * b->p->ndof * 8, s));
+  HIP_TRY(hipMemsetAsync(b->dU, 0, nc * nsp * 8, s));
+  HIP_TRY(hipMemsetAsync(b->U, 0, nc * nsp * 8, s));
+  HIP_TRY(hipMemsetAsync(b->q, 0, nc * nsp * 8, s));
+  HIP_TRY(hipMemsetAsync(b->state, 0, ncase * (2 * nsp + 2) * 8, s));
   HIP_TRY(hipMemsetAsync(b->iters, 0, ncase * 4, s));
   if (b->g->two_d) HIP_TRY(hipMemsetAsync(b->g->have_x, 0, ncase * 4, s));
   std::vector<int32_t> ones(std::max<int64_t>(nc, ncase), 1);
@@ -957,7 +1204,9 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   b->Npen = o->N > 0.0 ? o->N : p->nubar;
   const int64_t nc = g->n_cells;
   const int ncase = g->n_cases;
-  const int n3 = p->n3;
+  const int n3 = p->ndof;  // unknowns per cell
+  const int nsp = p->nsp;
+  if (nsp == 2 && o->project) { delete b; return fail(SIS_E_UNSUPPORTED, "invariant projection is for one gas only"); }
 #define ST_TRY(expr)                                                                            \
   do {                                                                                          \
     hipError_t e_ = (expr);                                                                     \
@@ -969,12 +1218,12 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   } while (0)
   ST_TRY(dmalloc(&b->h, static_cast<size_t>(nc) * n3));
   ST_TRY(dmalloc(&b->rhs, static_cast<size_t>(nc) * n3));
-  ST_TRY(dmalloc(&b->amom, nc * 4));
-  ST_TRY(dmalloc(&b->mom, nc * g->mom_stride()));
-  ST_TRY(dmalloc(&b->dU, nc));
-  ST_TRY(dmalloc(&b->U, nc));
-  ST_TRY(dmalloc(&b->q, nc));
-  ST_TRY(dmalloc(&b->state, ncase * 4));
+  ST_TRY(dmalloc(&b->amom, nc * 4 * nsp));
+  ST_TRY(dmalloc(&b->mom, nc * g->mom_stride() * nsp));
+  ST_TRY(dmalloc(&b->dU, nc * nsp));
+  ST_TRY(dmalloc(&b->U, nc * nsp));
+  ST_TRY(dmalloc(&b->q, nc * nsp));
+  ST_TRY(dmalloc(&b->state, ncase * (2 * nsp + 2)));
   ST_TRY(dmalloc(&b->iters, ncase));
   ST_TRY(dmalloc(&b->cact, ncase));
   ST_TRY(dmalloc(&b->lact, nc));
@@ -986,8 +1235,8 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
     int tile, splits;
     choose_gemm(nc, n3, &tile, &splits);
     if (splits > 1) ST_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
-    const int W = (n3 / 2 + 63) / 64;
-    if (!g->two_d) ST_TRY(p->ws_part.ensure(static_cast<size_t>(nc) * 8 * W * 8));
+    const int W = (p->n3 / 2 + 63) / 64;
+    if (!g->two_d) ST_TRY(p->ws_part.ensure(static_cast<size_t>(nc) * nsp * 8 * W * 8));
   }
   hipStream_t s = stream;
   if (o->use_graph) {
@@ -1049,21 +1298,25 @@ sis_status sis_state_results(sis_state_t b, sis_solve_result* r, hipStream_t str
   if (!b || !r) return fail(SIS_E_INVALID, "null argument");
   const int ncase = b->g->n_cases;
   const int64_t nc = b->g->n_cells;
+  const int nsp = b->p->nsp, ss = 2 * nsp + 2;  // state: M[nsp], Q[nsp], residual, iterations
   HIP_TRY(hipStreamSynchronize(stream));
-  std::vector<double> st(static_cast<size_t>(ncase) * 4);
+  std::vector<double> st(static_cast<size_t>(ncase) * ss);
   std::vector<int32_t> hit(ncase);
-  HIP_TRY(hipMemcpy(st.data(), b->state, ncase * 4 * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(st.data(), b->state, ncase * ss * 8, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(hit.data(), b->iters, ncase * 4, hipMemcpyDeviceToHost));
-  if (r->U) HIP_TRY(hipMemcpy(r->U, b->U, nc * 8, hipMemcpyDeviceToHost));
-  if (r->q) HIP_TRY(hipMemcpy(r->q, b->q, nc * 8, hipMemcpyDeviceToHost));
+  if (r->U) HIP_TRY(hipMemcpy(r->U, b->U, nc * nsp * 8, hipMemcpyDeviceToHost));
+  if (r->q) HIP_TRY(hipMemcpy(r->q, b->q, nc * nsp * 8, hipMemcpyDeviceToHost));
   bool nan = false, notconv = false;
   for (int c = 0; c < ncase; ++c) {
-    if (r->M) r->M[c] = st[c * 4 + 0];
-    if (r->Q) r->Q[c] = st[c * 4 + 1];
-    if (r->residual) r->residual[c] = st[c * 4 + 2];
+    for (int s = 0; s < nsp; ++s) {
+      const double M = st[c * ss + s], Q = st[c * ss + nsp + s];
+      if (r->M) r->M[c * nsp + s] = M;
+      if (r->Q) r->Q[c * nsp + s] = Q;
+      if (!std::isfinite(M) || !std::isfinite(Q)) nan = true;
+    }
+    if (r->residual) r->residual[c] = st[c * ss + 2 * nsp];
     if (r->iters) r->iters[c] = hit[c];
-    if (!std::isfinite(st[c * 4 + 0]) || !std::isfinite(st[c * 4 + 1])) nan = true;
-    if (!(st[c * 4 + 2] < b->o.eps)) notconv = true;
+    if (!(st[c * ss + 2 * nsp] < b->o.eps)) notconv = true;
   }
   r->seconds = 0.0;
   r->total_iters = b->total;

@@ -6,10 +6,12 @@
 
 namespace sis {
 
-// Operator assembly: op[i][j] = sum_p [Bs_p(i) Psi_p(i-j) + As_p(i) Phi_p(i-j)] - feq(i) beta_r(i-j)
-// (As, Bs pre-scaled by 4 b0 W_p).  n3 x n3 row-major output.
-hipError_t launch_assemble(int n, int D, const double* Psi, const double* Phi, const double* As,
-                           const double* Bs, const double* feq, const double* beta_r, double* op,
+// Operator assembly on one n^3 x n^3 block (row stride ldo):
+//   op[i][j] = (accumulate ? op[i][j] : 0) + sum_t X_t(i) Y_t(i - j)
+//              - loss_coef feq(i) beta_r(i - j)          (loss skipped if feq is null)
+// X: [T][n^3] fields, Y: [T][(2n-1)^3] real-space kernels on the difference grid.
+hipError_t launch_assemble(int n, int T, const double* X, const double* Y, const double* feq,
+                           double loss_coef, const double* beta_r, double* op, int64_t ldo, int accumulate,
                            hipStream_t s);
 
 // op2 = op (double) rounded to float / split into bf16 hi + lo.
@@ -36,23 +38,26 @@ struct GemmArgs {
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 int gemm_k_per_split(int K, int splits);
 
+// Rows are (cell, species) pairs of n3 values: row = cell * nsp + species.
 struct FinishArgs {
   int n, n3;
-  int64_t n_cells;
+  int nsp;                 // species per cell (1 or 2)
+  double mass_ratio[2];    // m_s / m_A (1 for one gas)
+  int64_t n_cells;         // rows = cells * nsp
   int splits;
-  const double* acc;       // [splits][n_cells][n3]
-  const double* h;         // [n_cells][n3]
-  const double* dU;        // [n_cells] or null
-  const double* delta;     // [n_cells]
-  const int32_t* flow;     // [n_cells] or null
-  int project;
+  const double* acc;       // [splits][rows][n3]
+  const double* h;         // [rows][n3]
+  const double* dU;        // [rows] or null
+  const double* delta;     // [cells]
+  const int32_t* flow;     // [cells] or null
+  int project;             // one gas only
   const double* v1d;       // [n]
-  const double* feq;       // [n3]
-  const double* nu;        // [n3]
-  const double* Kc;        // [n3]  L+_1(2 v3 feq)
+  const double* feq;       // [nsp][n3]
+  const double* nu;        // [nsp][n3]
+  const double* Kc;        // [nsp][nsp][n3]: L+_1 of the correction 2 (m_q/m_A) v3 f_q of species q
   const double* gram_inv;  // [25]
   double w;
-  const int32_t* active;   // [n_cells] or null: skip cells with active == 0
+  const int32_t* active;   // [cells] or null: skip cells with active == 0
   // FP64-anchored defect correction (solver only; mode 0 = off):
   //  mode 1 (refresh):     acc is op*h in FP64; store accref = acc, xref = h
   //  mode 2 (incremental): acc is op~*(h - xref); use accref + acc
@@ -67,15 +72,17 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 
 struct SweepArgs {
   int n, n3;
+  int nsp;                   // species per cell; grid.z runs over species
+  double mass_ratio[2];      // m_s / m_A: weights of q3 and P13
   int n_cases;
   const int64_t* node_off;   // [n_cases+1]
   const double* coef;        // [cells][6]: backward a,b,c ; forward a,b,c
   const double* delta_case;  // [n_cases]
   const double* v1d;         // [n]
-  const double* nu;          // [n3]
-  const double* rhs;         // [cells][n3]
-  double* h;                 // [cells][n3]
-  double* part;              // [cells][2][4][W] wave partials of {U3, q3, G1, P13}
+  const double* nu;          // [nsp][n3]
+  const double* rhs;         // [cells][nsp][n3]
+  double* h;                 // [cells][nsp][n3]
+  double* part;              // [cells][nsp][2][4][W] wave partials of {U3, q3, G1, P13}
   int W;                     // waves per case = n3 / 128
   const int32_t* case_active;// [n_cases] or null
   double w;
@@ -85,9 +92,10 @@ hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s);
 // mom[cell][4] = sum over the wave partials (fixed order)
 hipError_t launch_reduce_partials(const double* part, int W, int64_t n_cells, double* mom,
                                   hipStream_t s);
-// mom[cell][4] = {U3, q3, G1, P13} of h directly
-hipError_t launch_moments(int n, int n3, int64_t n_cells, const double* v1d, const double* h,
-                          double w, double* mom, hipStream_t s);
+// mom[row][4] = {U3, q3, G1, P13} of h[row][n3] directly (rows = cells * nsp;
+// q3 and P13 weighted with the mass ratio of the row's species)
+hipError_t launch_moments(int n, int n3, int nsp, const double* mass_ratio, int64_t n_rows, const double* v1d,
+                          const double* h, double w, double* mom, hipStream_t s);
 
 struct DiffusionArgs {
   int n_cases;
@@ -110,6 +118,11 @@ struct DiffusionArgs {
   double* qfield;            // [cells] q3 of the new iterate or null
   double* ufield;            // [cells] U3 of the new iterate or null
   double eps;
+  // binary mixture (nsp == 2): arrays above are per (cell, species) row,
+  // state is [n_cases][6] = {M_A, M_B, Q_A, Q_B, residual, iterations}
+  int nsp;
+  double chi[2], mass_ratio[2], Ns[2], cUs[2], cqs[2];
+  double flow_factor;        // sqrt(m / m_A)
 };
 hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s);
 

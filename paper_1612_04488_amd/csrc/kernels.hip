@@ -49,44 +49,39 @@ __device__ inline void block_sum(double (&v)[K], double* sh /* >= 4*K */) {
 }
 
 // ------------------------------------------------------------------ assemble
-constexpr int kAsmPB = 8;      // directions staged per LDS round
+constexpr int kAsmPB = 8;      // terms staged per LDS round
 constexpr int kAsmOuts = 7;    // outputs per thread (n^2 <= 256 * 7)
 
-__global__ __launch_bounds__(256) void assemble_kernel(int n, int D, const double* __restrict__ Psi,
-                                                       const double* __restrict__ Phi,
-                                                       const double* __restrict__ As,
-                                                       const double* __restrict__ Bs,
-                                                       const double* __restrict__ feq,
+// One workgroup per (i0 i1, j0 j1) pair of velocity rows: the n x n outputs
+// (i2, j2) share the difference row (d0, d1) of every kernel table.
+__global__ __launch_bounds__(256) void assemble_kernel(int n, int T, const double* __restrict__ X,
+                                                       const double* __restrict__ Y,
+                                                       const double* __restrict__ feq, double lossc,
                                                        const double* __restrict__ beta_r,
-                                                       double* __restrict__ op) {
+                                                       double* __restrict__ op, int64_t ldo, int accumulate) {
   const int nd = 2 * n - 1;
   const int n3 = n * n * n;
   const int bi = blockIdx.x, bj = blockIdx.y;
   const int i0 = bi / n, i1 = bi % n, j0 = bj / n, j1 = bj % n;
   const int d0 = i0 - j0 + n - 1, d1 = i1 - j1 + n - 1;
   extern __shared__ double sm[];
-  double* sPsi = sm;
-  double* sPhi = sm + kAsmPB * nd;
-  double* sA = sm + 2 * kAsmPB * nd;
-  double* sB = sA + kAsmPB * n;
+  double* sY = sm;
+  double* sX = sm + kAsmPB * nd;
   const int nout = n * n;
   double acc[kAsmOuts];
 #pragma unroll
   for (int k = 0; k < kAsmOuts; ++k) acc[k] = 0.0;
   const size_t row = (static_cast<size_t>(d0) * nd + d1) * nd;
-  for (int p0 = 0; p0 < D; p0 += kAsmPB) {
-    const int pb = min(kAsmPB, D - p0);
-    for (int q = threadIdx.x; q < pb * nd; q += blockDim.x) {
-      const int pp = q / nd, r = q % nd;
-      const size_t src = static_cast<size_t>(p0 + pp) * nd * nd * nd + row + r;
-      sPsi[pp * nd + r] = Psi[src];
-      sPhi[pp * nd + r] = Phi[src];
+  const size_t nd3 = static_cast<size_t>(nd) * nd * nd;
+  for (int t0 = 0; t0 < T; t0 += kAsmPB) {
+    const int tb = min(kAsmPB, T - t0);
+    for (int q = threadIdx.x; q < tb * nd; q += blockDim.x) {
+      const int tt = q / nd, r = q % nd;
+      sY[tt * nd + r] = Y[static_cast<size_t>(t0 + tt) * nd3 + row + r];
     }
-    for (int q = threadIdx.x; q < pb * n; q += blockDim.x) {
-      const int pp = q / n, r = q % n;
-      const size_t src = static_cast<size_t>(p0 + pp) * n3 + static_cast<size_t>(bi) * n + r;
-      sA[pp * n + r] = As[src];
-      sB[pp * n + r] = Bs[src];
+    for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
+      const int tt = q / n, r = q % n;
+      sX[tt * n + r] = X[static_cast<size_t>(t0 + tt) * n3 + static_cast<size_t>(bi) * n + r];
     }
     __syncthreads();
 #pragma unroll
@@ -95,8 +90,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(int n, int D, const doubl
       if (o < nout) {
         const int i2 = o / n, j2 = o % n, dd = i2 - j2 + n - 1;
         double a = acc[k];
-        for (int pp = 0; pp < pb; ++pp)
-          a += sB[pp * n + i2] * sPsi[pp * nd + dd] + sA[pp * n + i2] * sPhi[pp * nd + dd];
+        for (int tt = 0; tt < tb; ++tt) a += sX[tt * n + i2] * sY[tt * nd + dd];
         acc[k] = a;
       }
     }
@@ -108,7 +102,10 @@ __global__ __launch_bounds__(256) void assemble_kernel(int n, int D, const doubl
     if (o < nout) {
       const int i2 = o / n, j2 = o % n, dd = i2 - j2 + n - 1;
       const int ii = bi * n + i2, jj = bj * n + j2;
-      op[static_cast<size_t>(ii) * n3 + jj] = acc[k] - feq[ii] * beta_r[row + dd];
+      double v = acc[k];
+      if (feq) v -= lossc * feq[ii] * beta_r[row + dd];
+      double* dst = op + static_cast<size_t>(ii) * ldo + jj;
+      *dst = accumulate ? *dst + v : v;
     }
   }
 }
@@ -528,12 +525,17 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const double* __restri
 __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
   __shared__ double sh[4 * 9];
   __shared__ double coef[5];
-  const int64_t c = blockIdx.x;
-  if (a.active && !a.active[c]) return;
+  const int64_t c = blockIdx.x;  // (cell, species) row of n3 values
+  const int nsp = a.nsp, sp = static_cast<int>(c % nsp);
+  const int64_t cell = c / nsp;
+  if (a.active && !a.active[cell]) return;
   const int n = a.n, n3 = a.n3, nn = n * n;
-  const double del = a.delta[c];
-  const int fl = a.flow ? a.flow[c] : 0;
+  const double del = a.delta[cell];
+  const int fl = a.flow ? a.flow[cell] : 0;
   const double dUc = a.dU ? a.dU[c] : 0.0;
+  const double ms = a.mass_ratio[sp];
+  const double* feq = a.feq + static_cast<int64_t>(sp) * n3;
+  const double* nu = a.nu + static_cast<int64_t>(sp) * n3;
   const int64_t base = c * n3;
   const int64_t sstride = a.n_cells * static_cast<int64_t>(n3);
   double m[9];
@@ -543,7 +545,7 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
     const int j1 = v / nn, j2 = (v / n) % n, j3 = v % n;
     const double v1 = a.v1d[j1], v2 = a.v1d[j2], v3 = a.v1d[j3];
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
-    const double f = a.feq[v];
+    const double f = feq[v];
     double s = 0.0;
     for (int z = 0; z < a.splits; ++z) s += a.acc[z * sstride + base + v];
     if (a.anchor_mode == 2) {
@@ -552,12 +554,15 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
       a.accref[base + v] = s;
       a.xref[base + v] = a.h[base + v];
     }
-    const double lp = s + dUc * a.Kc[v];
-    const double hk = a.h[base + v] + dUc * 2.0 * v3 * f;
-    const double L = del * (lp - a.nu[v] * hk);
+    // L+ of the corrected iterate: the correction of every species of the cell enters
+    double lp = s;
+    if (a.dU)
+      for (int q = 0; q < nsp; ++q) lp += a.dU[cell * nsp + q] * a.Kc[(static_cast<int64_t>(q) * nsp + sp) * n3 + v];
+    const double hk = a.h[base + v] + dUc * 2.0 * ms * v3 * f;
+    const double L = del * (lp - nu[v] * hk);
     double S = 0.0;
     if (fl == 1) S = v3 * f;
-    else if (fl == 2) S = v3 * (vsq - 2.5) * f;
+    else if (fl == 2 && nsp == 1) S = v3 * (vsq - 2.5) * f;
     a.rhs[base + v] = del * lp + S;
     if (a.lh) a.lh[base + v] = L;
     const double wL = a.w * L;
@@ -583,7 +588,7 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
       const int j1 = v / nn, j2 = (v / n) % n, j3 = v % n;
       const double v1 = a.v1d[j1], v2 = a.v1d[j2], v3 = a.v1d[j3];
       const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
-      const double corr = a.feq[v] * (coef[0] + coef[1] * v1 + coef[2] * v2 + coef[3] * v3 + coef[4] * vsq);
+      const double corr = feq[v] * (coef[0] + coef[1] * v1 + coef[2] * v2 + coef[3] * v3 + coef[4] * vsq);
       a.rhs[base + v] -= corr;
       if (a.lh) a.lh[base + v] -= corr;
     }
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
 // ------------------------------------------------------------------ sweep
 // One thread per velocity pair (v1 > 0 index jp, mirror jm) of one case.
 __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
-  const int cs = blockIdx.y;
+  const int cs = blockIdx.y, sp = blockIdx.z, nsp = a.nsp;
   if (a.case_active && !a.case_active[cs]) return;
   const int n = a.n, nn = n * n, half = a.n3 / 2, n3 = a.n3;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -616,16 +621,20 @@ __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
   const double v2 = a.v1d[r / n], v3 = a.v1d[r % n];
   const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
   const double del = a.delta_case[cs];
-  const double dnp = del * a.nu[vp], dnm = del * a.nu[vm];
+  const double* nu = a.nu + static_cast<int64_t>(sp) * n3;
+  const double dnp = del * nu[vp], dnm = del * nu[vm];
+  const double ms = a.mass_ratio[sp];
   const double z = valid ? 1.0 : 0.0;
-  const double wU = z * a.w * v3, wq = z * a.w * (vsq - 2.5) * v3;
-  const double wG = z * a.w * v3 * (2.0 * v1 * v1 - 1.0), wP = z * 2.0 * a.w * v1 * v3;
+  const double wU = z * a.w * v3, wq = z * a.w * (ms * vsq - 2.5) * v3;
+  const double wG = z * a.w * v3 * (2.0 * v1 * v1 - 1.0), wP = z * 2.0 * ms * a.w * v1 * v3;
   const int W = a.W;
+  // row of (cell, species) in the [cell][species][n3] arrays
+  auto row = [&](int64_t cell) { return (cell * nsp + sp) * static_cast<int64_t>(n3); };
   auto put = [&](int64_t cell, int pass, double h) {
     const double s0 = wave_sum(wU * h), s1 = wave_sum(wq * h), s2 = wave_sum(wG * h);
     const double s3 = wave_sum((pass == 0 ? wP : -wP) * h);
     if (writer) {
-      double* p = a.part + ((cell * 2 + pass) * 4) * W + wave;
+      double* p = a.part + (((cell * nsp + sp) * 2 + pass) * 4) * W + wave;
       p[0] = s0;
       p[W] = s1;
       p[2 * W] = s2;
@@ -634,14 +643,14 @@ __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
   };
   // v1 > 0: wall value 0, march towards the symmetry plane
   double h1 = 0.0, h2 = 0.0;
-  if (valid) a.h[c0 * n3 + vp] = 0.0;
+  if (valid) a.h[row(c0) + vp] = 0.0;
   put(c0, 0, 0.0);
   for (int i = 1; i < nodes; ++i) {
     const int64_t cell = c0 + i;
     const double ca = a.coef[cell * 6 + 0], cb = a.coef[cell * 6 + 1], cc = a.coef[cell * 6 + 2];
-    const double rhs = valid ? a.rhs[cell * n3 + vp] : 0.0;
+    const double rhs = valid ? a.rhs[row(cell) + vp] : 0.0;
     const double val = (rhs - v1 * (cb * h1 + cc * h2)) / (dnp + v1 * ca);
-    if (valid) a.h[cell * n3 + vp] = val;
+    if (valid) a.h[row(cell) + vp] = val;
     h2 = h1;
     h1 = val;
     put(cell, 0, val);
@@ -649,14 +658,14 @@ __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
   // v1 < 0: specular reflection at the last node, march to the wall
   const int64_t last = c0 + nodes - 1;
   double g1 = h1, g2 = 0.0;
-  if (valid) a.h[last * n3 + vm] = g1;
+  if (valid) a.h[row(last) + vm] = g1;
   put(last, 1, g1);
   for (int i = nodes - 2; i >= 0; --i) {
     const int64_t cell = c0 + i;
     const double ca = a.coef[cell * 6 + 3], cb = a.coef[cell * 6 + 4], cc = a.coef[cell * 6 + 5];
-    const double rhs = valid ? a.rhs[cell * n3 + vm] : 0.0;
+    const double rhs = valid ? a.rhs[row(cell) + vm] : 0.0;
     const double val = (rhs - v1 * (cb * g1 + cc * g2)) / (dnm + v1 * ca);
-    if (valid) a.h[cell * n3 + vm] = val;
+    if (valid) a.h[row(cell) + vm] = val;
     g2 = g1;
     g1 = val;
     put(cell, 1, val);
@@ -679,11 +688,13 @@ __global__ __launch_bounds__(64) void reduce_partials_kernel(const double* __res
   }
 }
 
-__global__ __launch_bounds__(256) void moments_kernel(int n, int n3, const double* __restrict__ v1d,
+__global__ __launch_bounds__(256) void moments_kernel(int n, int n3, int nsp, double ms0, double ms1,
+                                                      const double* __restrict__ v1d,
                                                       const double* __restrict__ h, double w,
                                                       double* __restrict__ mom) {
   __shared__ double sh[4 * 4];
-  const int64_t c = blockIdx.x;
+  const int64_t c = blockIdx.x;  // (cell, species) row
+  const double ms = (c % nsp) == 0 ? ms0 : ms1;
   const int nn = n * n;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
   for (int v = threadIdx.x; v < n3; v += blockDim.x) {
@@ -691,9 +702,9 @@ __global__ __launch_bounds__(256) void moments_kernel(int n, int n3, const doubl
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
     const double x = w * h[c * n3 + v];
     m[0] += v3 * x;
-    m[1] += (vsq - 2.5) * v3 * x;
+    m[1] += (ms * vsq - 2.5) * v3 * x;
     m[2] += v3 * (2.0 * v1 * v1 - 1.0) * x;
-    m[3] += 2.0 * v1 * v3 * x;
+    m[3] += 2.0 * ms * v1 * v3 * x;
   }
   block_sum<4>(m, sh);
   if (threadIdx.x == 0)
@@ -762,6 +773,79 @@ __global__ __launch_bounds__(64) void diffusion1d_kernel(DiffusionArgs a) {
   }
 }
 
+
+// Binary mixture (planar): the velocity equations of species B (own shear
+// stress) and A (total stress minus B's), integrated once from the symmetry
+// plane and marched from the wall; rows are (cell, species) with species A
+// first.  mom[row][4] = {int v3 h, q, G1, P13}; U is per unit molar fraction.
+__global__ __launch_bounds__(64) void diffusion1d_mix_kernel(DiffusionArgs a) {
+  const int cs = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  if (a.case_active && !a.case_active[cs]) return;
+  const int64_t c0 = a.node_off[cs];
+  const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
+  const double del = a.delta_case[cs];
+  const double pois = a.flow_case[cs] == 1 ? 1.0 : 0.0;
+  double y1[2] = {0.0, 0.0}, y2[2] = {0.0, 0.0};
+  double Mr[2] = {0.0, 0.0}, Qr[2] = {0.0, 0.0}, Up[2] = {0.0, 0.0}, qp[2] = {0.0, 0.0}, xp = 0.0;
+  for (int i = 0; i < nodes; ++i) {
+    const int64_t cell = c0 + i;
+    const double x = a.x[cell];
+    const double PB = a.mom[(cell * 2 + 1) * 4 + 3];
+    for (int s = 0; s < 2; ++s) {
+      const int64_t r = cell * 2 + s;
+      const double chi = a.chi[s];
+      const double Uh = a.mom[r * 4 + 0] / chi, qh = a.mom[r * 4 + 1], G = a.mom[r * 4 + 2];
+      double dU = 0.0, Usol = Uh;
+      if (a.sis) {
+        double y;
+        if (i == 0) {
+          y = chi * Uh + G;
+        } else {
+          const double Nd = a.Ns[s] * del;
+          double A = 0.0;
+          if (a.amom) A = a.amom[r * 4 + 0] + Nd * a.amom[r * 4 + 1];
+          const double src = s == 1 ? A - Nd * PB / a.mass_ratio[1] : A - Nd * (pois * x - PB);
+          const double ca = a.coef[cell * 6 + 0], cb = a.coef[cell * 6 + 1], cc = a.coef[cell * 6 + 2];
+          y = (src - cb * y1[s] - cc * y2[s]) / ca;
+        }
+        y2[s] = y1[s];
+        y1[s] = y;
+        Usol = (y - G) / chi;
+        dU = Usol - Uh;
+      }
+      const double Un = Uh + dU * a.cUs[s], qn = qh + dU * a.cqs[s];
+      if (a.U) a.U[r] = Usol;
+      if (a.dU) a.dU[r] = dU;
+      if (a.qfield) a.qfield[r] = qn;
+      if (a.ufield) a.ufield[r] = Un;
+      if (i > 0) {
+        Mr[s] += 0.5 * (Un + Up[s]) * (x - xp);
+        Qr[s] += 0.5 * (qn + qp[s]) * (x - xp);
+      }
+      Up[s] = Un;
+      qp[s] = qn;
+    }
+    xp = x;
+  }
+  if (a.state) {
+    double* st = a.state + cs * 6;  // M_A, M_B, Q_A, Q_B, residual, iterations
+    double res = 0.0;
+    bool bad = false;
+    for (int s = 0; s < 2; ++s) {
+      const double M = 2.0 * a.flow_factor * Mr[s], Q = 2.0 * a.flow_factor * Qr[s];
+      res = fmax(res, fmax(fabs(M - st[s]) / fmax(fabs(M), 1e-300), fabs(Q - st[2 + s]) / fmax(fabs(Q), 1e-300)));
+      bad = bad || M != M || Q != Q;
+      st[s] = M;
+      st[2 + s] = Q;
+    }
+    st[4] = bad ? __builtin_nan("") : res;
+    const int it = a.iters[cs] + 1;
+    a.iters[cs] = it;
+    if (!(res >= a.eps) || bad) a.case_active[cs] = 0;
+    st[5] = static_cast<double>(it);
+  }
+}
 
 // ------------------------------------------------------------------ 2-D sweep
 // One thread per velocity quadruple (+-|v1|, +-|v2|, v3) of one case; the
@@ -1058,13 +1142,14 @@ __global__ void expand_active_kernel(const int32_t* __restrict__ case_active,
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_assemble(int n, int D, const double* Psi, const double* Phi, const double* As,
-                           const double* Bs, const double* feq, const double* beta_r, double* op,
+hipError_t launch_assemble(int n, int T, const double* X, const double* Y, const double* feq,
+                           double loss_coef, const double* beta_r, double* op, int64_t ldo, int accumulate,
                            hipStream_t s) {
   const int nd = 2 * n - 1;
-  const size_t shm = static_cast<size_t>(kAsmPB) * (2 * nd + 2 * n) * sizeof(double);
+  const size_t shm = static_cast<size_t>(kAsmPB) * (nd + n) * sizeof(double);
   dim3 grid(n * n, n * n);
-  hipLaunchKernelGGL(assemble_kernel, grid, dim3(256), shm, s, n, D, Psi, Phi, As, Bs, feq, beta_r, op);
+  hipLaunchKernelGGL(assemble_kernel, grid, dim3(256), shm, s, n, T, X, Y, feq, loss_coef, beta_r, op, ldo,
+                     accumulate);
   return hipGetLastError();
 }
 
@@ -1116,7 +1201,7 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
 
 hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s) {
   const int half = a.n3 / 2;
-  dim3 grid((half + 255) / 256, a.n_cases);
+  dim3 grid((half + 255) / 256, a.n_cases, a.nsp);
   hipLaunchKernelGGL(sweep1d_kernel, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -1126,14 +1211,19 @@ hipError_t launch_reduce_partials(const double* part, int W, int64_t n_cells, do
   return hipGetLastError();
 }
 
-hipError_t launch_moments(int n, int n3, int64_t n_cells, const double* v1d, const double* h,
-                          double w, double* mom, hipStream_t s) {
-  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>(n_cells)), dim3(256), 0, s, n, n3, v1d, h, w, mom);
+hipError_t launch_moments(int n, int n3, int nsp, const double* mass_ratio, int64_t n_rows, const double* v1d,
+                          const double* h, double w, double* mom, hipStream_t s) {
+  const double m0 = mass_ratio ? mass_ratio[0] : 1.0, m1 = mass_ratio && nsp > 1 ? mass_ratio[1] : 1.0;
+  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>(n_rows)), dim3(256), 0, s, n, n3, nsp, m0, m1, v1d,
+                     h, w, mom);
   return hipGetLastError();
 }
 
 hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(diffusion1d_kernel, dim3(a.n_cases), dim3(64), 0, s, a);
+  if (a.nsp == 2)
+    hipLaunchKernelGGL(diffusion1d_mix_kernel, dim3(a.n_cases), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(diffusion1d_kernel, dim3(a.n_cases), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@
 // DFTs (only the needed outputs are formed).
 #include "planner.h"
 
+#include "pruned_dft.h"
+
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -162,6 +164,49 @@ double b0_unit(double alpha, double gamma) {
   return 1.0 / k;
 }
 
+double phi_hs(double s, double R, double Lp) {
+  // 2 int_0^R rho cos(b rho) d rho, b = pi s / Lp; power series for small b R
+  const double b = std::fabs(kPi * s / Lp);
+  const double x = b * R;
+  if (x < 0.5) {
+    double term = 1.0, acc = 0.5;
+    for (int k = 1; k < 12; ++k) {
+      term *= -(x * x) / ((2.0 * k - 1.0) * (2.0 * k));
+      acc += term / (2.0 * k + 2.0);
+    }
+    return 2.0 * R * R * acc;
+  }
+  return 2.0 * (R * std::sin(x) / b + (std::cos(x) - 1.0) / (b * b));
+}
+
+double psi_hs(double t, double R, double Lp) {
+  // 2 pi int_0^R rho J0(pi rho t / Lp) d rho = 2 pi R^2 J1(c) / c
+  const double c = kPi * R * t / Lp;
+  if (c == 0.0) return kPi * R * R;
+  return 2.0 * kPi * R * R * ::j1(c) / c;
+}
+
+bool half_sphere_directions(int M, std::vector<double>& ex, std::vector<double>& ey, std::vector<double>& ez,
+                            std::vector<double>& W) {
+  Quadrature gl;
+  if (!gauss_jacobi(M, 0.0, 0.0, gl)) return false;
+  const int D = M * M;
+  ex.resize(D);
+  ey.resize(D);
+  ez.resize(D);
+  W.resize(D);
+  for (int a = 0; a < M; ++a)
+    for (int b = 0; b < M; ++b) {
+      const double th = 0.5 * kPi * (gl.x[a] + 1.0), ph = 0.5 * kPi * (gl.x[b] + 1.0);
+      const int p = a * M + b;
+      ex[p] = std::sin(th) * std::cos(ph);
+      ey[p] = std::sin(th) * std::sin(ph);
+      ez[p] = std::cos(th);
+      W[p] = (0.5 * kPi * gl.w[a]) * (0.5 * kPi * gl.w[b]) * std::sin(th);
+    }
+  return true;
+}
+
 namespace {
 
 struct Radial {
@@ -171,29 +216,14 @@ struct Radial {
 
   double phi(double s) const {
     const double b = std::fabs(kPi * s / Lp);
-    if (phi_closed) {  // 2 int_0^R rho cos(b rho) d rho
-      const double x = b * R;
-      if (x < 0.5) {
-        double term = 1.0, acc = 0.5;
-        for (int k = 1; k < 12; ++k) {
-          term *= -(x * x) / ((2.0 * k - 1.0) * (2.0 * k));
-          acc += term / (2.0 * k + 2.0);
-        }
-        return 2.0 * R * R * acc;
-      }
-      return 2.0 * (R * std::sin(x) / b + (std::cos(x) - 1.0) / (b * b));
-    }
+    if (phi_closed) return phi_hs(s, R, Lp);
     double acc = 0.0;
     for (size_t k = 0; k < qphi.x.size(); ++k) acc += qphi.w[k] * std::cos(b * qphi.x[k]);
     return 2.0 * acc;
   }
 
   double psi(double t) const {
-    const double c = kPi * R * t / Lp;
-    if (psi_closed) {
-      if (c == 0.0) return kPi * R * R;
-      return 2.0 * kPi * R * R * ::j1(c) / c;
-    }
+    if (psi_closed) return psi_hs(t, R, Lp);
     const double b = kPi * t / Lp;
     double acc = 0.0;
     for (size_t k = 0; k < qpsi.x.size(); ++k) acc += qpsi.w[k] * ::j0(b * qpsi.x[k]);
@@ -213,63 +243,6 @@ bool mapped_rule(int n, double a, double R, Quadrature& q) {
   }
   return true;
 }
-
-// Pruned separable inverse DFT:  out[a0][a1][a2] = Re sum_k T[k0][k1][k2] E[k0][a0] E[k1][a1] E[k2][a2]
-// with E given as (re, im) arrays [np][m].
-struct Pruned {
-  int np, m;
-  std::vector<double> er, ei;  // [np][m]
-  std::vector<double> x1r, x1i, x2r, x2i;
-
-  void run(const double* T, double* out) {
-    const int n2 = np * np;
-    x1r.assign(static_cast<size_t>(n2) * m, 0.0);
-    x1i.assign(static_cast<size_t>(n2) * m, 0.0);
-    for (int q = 0; q < n2; ++q) {
-      const double* t = T + static_cast<size_t>(q) * np;
-      double* r = &x1r[static_cast<size_t>(q) * m];
-      double* im = &x1i[static_cast<size_t>(q) * m];
-      for (int k2 = 0; k2 < np; ++k2) {
-        const double tv = t[k2];
-        if (tv == 0.0) continue;
-        const double* a = &er[static_cast<size_t>(k2) * m];
-        const double* b = &ei[static_cast<size_t>(k2) * m];
-        for (int j = 0; j < m; ++j) {
-          r[j] += tv * a[j];
-          im[j] += tv * b[j];
-        }
-      }
-    }
-    const size_t mm = static_cast<size_t>(m) * m;
-    x2r.assign(np * mm, 0.0);
-    x2i.assign(np * mm, 0.0);
-    for (int k0 = 0; k0 < np; ++k0) {
-      for (int k1 = 0; k1 < np; ++k1) {
-        const double* ar = &x1r[(static_cast<size_t>(k0) * np + k1) * m];
-        const double* ai = &x1i[(static_cast<size_t>(k0) * np + k1) * m];
-        for (int a1 = 0; a1 < m; ++a1) {
-          const double cr = er[static_cast<size_t>(k1) * m + a1], ci = ei[static_cast<size_t>(k1) * m + a1];
-          double* yr = &x2r[k0 * mm + static_cast<size_t>(a1) * m];
-          double* yi = &x2i[k0 * mm + static_cast<size_t>(a1) * m];
-          for (int a2 = 0; a2 < m; ++a2) {
-            yr[a2] += ar[a2] * cr - ai[a2] * ci;
-            yi[a2] += ar[a2] * ci + ai[a2] * cr;
-          }
-        }
-      }
-    }
-    std::fill(out, out + static_cast<size_t>(m) * mm, 0.0);
-    for (int k0 = 0; k0 < np; ++k0) {
-      const double* yr = &x2r[k0 * mm];
-      const double* yi = &x2i[k0 * mm];
-      for (int a0 = 0; a0 < m; ++a0) {
-        const double cr = er[static_cast<size_t>(k0) * m + a0], ci = ei[static_cast<size_t>(k0) * m + a0];
-        double* o = out + a0 * mm;
-        for (size_t j = 0; j < mm; ++j) o[j] += yr[j] * cr - yi[j] * ci;
-      }
-    }
-  }
-};
 
 }  // namespace
 
@@ -302,21 +275,9 @@ bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std
       for (int c = 0; c < n; ++c) t.feq[(a * n + b) * n + c] = g1[a] * g1[b] * g1[c];
 
   // directions
-  Quadrature gl;
-  if (!gauss_jacobi(d.m_angle, 0.0, 0.0, gl)) { err = "Gauss-Legendre failed"; return false; }
-  const int M = d.m_angle;
-  t.D = M * M;
-  std::vector<double> ex(t.D), ey(t.D), ez(t.D);
-  t.W.resize(t.D);
-  for (int a = 0; a < M; ++a)
-    for (int b = 0; b < M; ++b) {
-      const double th = 0.5 * kPi * (gl.x[a] + 1.0), ph = 0.5 * kPi * (gl.x[b] + 1.0);
-      const int p = a * M + b;
-      ex[p] = std::sin(th) * std::cos(ph);
-      ey[p] = std::sin(th) * std::sin(ph);
-      ez[p] = std::cos(th);
-      t.W[p] = (0.5 * kPi * gl.w[a]) * (0.5 * kPi * gl.w[b]) * std::sin(th);
-    }
+  std::vector<double> ex, ey, ez;
+  if (!half_sphere_directions(d.m_angle, ex, ey, ez, t.W)) { err = "Gauss-Legendre failed"; return false; }
+  t.D = static_cast<int>(t.W.size());
 
   // radial factors
   Radial rad;
@@ -336,43 +297,11 @@ bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std
   for (int k = 0; k < np; ++k) lsig[k] = k < np / 2 ? k : k - np;
 
   // DFT factor matrices: kernels (difference grid) and f_eq fields (n grid)
-  auto make_kernel_E = [&](Pruned& P) {
-    P.np = np;
-    P.m = t.nd;
-    P.er.resize(static_cast<size_t>(np) * t.nd);
-    P.ei.resize(static_cast<size_t>(np) * t.nd);
-    for (int k = 0; k < np; ++k)
-      for (int a = 0; a < t.nd; ++a) {
-        const long dd = a - (n - 1);
-        long m = (static_cast<long>(k) * dd) % np;
-        if (m < 0) m += np;
-        const double ang = 2.0 * kPi * static_cast<double>(m) / np;
-        P.er[static_cast<size_t>(k) * t.nd + a] = std::cos(ang) / np;
-        P.ei[static_cast<size_t>(k) * t.nd + a] = std::sin(ang) / np;
-      }
-  };
-  auto make_field_E = [&](Pruned& P) {  // G(k, i) = sum_j g_j e^{2 pi i k (i - j) / np} / np
-    P.np = np;
-    P.m = n;
-    P.er.assign(static_cast<size_t>(np) * n, 0.0);
-    P.ei.assign(static_cast<size_t>(np) * n, 0.0);
-    for (int k = 0; k < np; ++k)
-      for (int i = 0; i < n; ++i) {
-        double sr = 0.0, si = 0.0;
-        for (int j = 0; j < n; ++j) {
-          long m = (static_cast<long>(k) * (i - j)) % np;
-          if (m < 0) m += np;
-          const double ang = 2.0 * kPi * static_cast<double>(m) / np;
-          sr += g1[j] * std::cos(ang);
-          si += g1[j] * std::sin(ang);
-        }
-        P.er[static_cast<size_t>(k) * n + i] = sr / np;
-        P.ei[static_cast<size_t>(k) * n + i] = si / np;
-      }
-  };
-  Pruned protoK, protoF;
-  if (want_kernels) make_kernel_E(protoK);
-  make_field_E(protoF);
+  PrunedDFT protoK, protoF;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (want_kernels) protoK.set_kernel_axis(ax, np, n, 0.0);
+    protoF.set_field_axis(ax, np, g1, 0.0);
+  }
 
   const size_t np3 = static_cast<size_t>(np) * np * np;
   t.A.assign(static_cast<size_t>(t.D) * t.n3, 0.0);
@@ -387,7 +316,7 @@ bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std
   std::vector<std::vector<double>> beta_part(nthreads, std::vector<double>(np3, 0.0));
 
   auto worker = [&](int tid) {
-    Pruned pk = protoK, pf = protoF;
+    PrunedDFT pk = protoK, pf = protoF;
     std::vector<double> ph(np3), ps(np3);
     std::vector<double>& beta = beta_part[tid];
     for (int p = tid; p < t.D; p += nthreads) {
@@ -427,12 +356,12 @@ bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std
   for (size_t j = 0; j < np3; ++j) beta[j] *= 4.0 * t.b0;
   t.nu.assign(t.n3, 0.0);
   {
-    Pruned pf = protoF;
+    PrunedDFT pf = protoF;
     pf.run(beta.data(), t.nu.data());
   }
   if (want_kernels) {
     t.beta_r.assign(t.nd3, 0.0);
-    Pruned pk = protoK;
+    PrunedDFT pk = protoK;
     pk.run(beta.data(), t.beta_r.data());
   }
   const double w = t.dv * t.dv * t.dv;

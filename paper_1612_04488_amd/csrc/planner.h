@@ -16,6 +16,16 @@ bool gauss_jacobi(int n, double a, double b, Quadrature& q);
 // Kernel amplitude b0 for delta = 1 (first Chapman-Enskog viscosity).
 double b0_unit(double alpha, double gamma);
 
+// Hard-sphere radial factors of the fast spectral method (closed forms):
+// phi(s) = 2 int_0^R rho cos(pi rho s / Lp) d rho, psi(t) = 2 pi int_0^R rho J0(pi rho t / Lp) d rho.
+double phi_hs(double s, double R, double Lp);
+double psi_hs(double t, double R, double Lp);
+
+// M x M Gauss-Legendre directions on [0, pi]^2 (theta, phi) of the half
+// sphere with weights w_a w_b sin(theta_a); D = M^2.
+bool half_sphere_directions(int M, std::vector<double>& ex, std::vector<double>& ey, std::vector<double>& ez,
+                            std::vector<double>& W);
+
 struct TableDesc {
   int n_v = 16;
   double l_v = 6.0;

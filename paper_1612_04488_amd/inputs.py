@@ -31,6 +31,26 @@ def smooth_h(n_v, l_v, n_cells, seed=SEED, scale=1.0):
     return np.einsum("ck,kxyz->cxyz", co, basis)
 
 
+def mixture_h(n_v, l_v, n_cells, widths=(1.0, 2.0), seed=SEED, rough=False):
+    """Two-species fields, shape (n_cells, 2, n_v, n_v, n_v): species s carries
+    the envelope exp(-widths[s] |v|^2) times either the smooth seeded basis of
+    `smooth_h` or (rough=True) white noise."""
+    rng = np.random.default_rng(seed + 7)
+    v = velocity_nodes(n_v, l_v)
+    V1, V2, V3 = np.meshgrid(v, v, v, indexing="ij")
+    vsq = V1 ** 2 + V2 ** 2 + V3 ** 2
+    out = np.empty((n_cells, 2, n_v, n_v, n_v))
+    for s, w in enumerate(widths):
+        env = np.exp(-w * vsq)
+        if rough:
+            out[:, s] = rng.standard_normal((n_cells, n_v, n_v, n_v)) * env
+        else:
+            co = rng.uniform(-1.0, 1.0, size=(n_cells, 4))
+            basis = np.stack([np.ones_like(vsq), V1, vsq - 2.5, 2 * V1 ** 2 - 1]) * (V3 * env)
+            out[:, s] = np.einsum("ck,kxyz->cxyz", co, basis)
+    return out
+
+
 def rough_h(n_v, l_v, n_cells, seed=SEED):
     """Gaussian-weighted white noise (no symmetry): exercises every operator entry."""
     rng = np.random.default_rng(seed + 1)
@@ -68,9 +88,21 @@ PLANAR_BATCH = dict(name="planar-hs-32v-100cells-8cases", n_v=32, l_v=6.0, n_pad
                     deltas=[0.1, 1.0, 10.0, 100.0] * 2, flows=[1] * 4 + [2] * 4)
 
 
+# Binary Ne-Ar hard-sphere mixture (masses 20.18 : 39.95, diameters 0.72 : 1,
+# equimolar), planar Poiseuille, 200 tanh(3) sections per case, 24^3 velocities
+# on [-5, 5]^3 padded to 48^3, M = 8, 16 rho nodes, 16 deltas log-spaced in
+# [0.01, 100]: 16 cases x 201 nodes x 2 species.
+MIX_NEAR = dict(name="mixture-near-hs-24v-201nodes-16cases", n_v=24, l_v=5.0, n_pad=48, m_angle=8,
+                kernel="hs", mixture=dict(masses=(20.18, 39.95), diameters=(0.72, 1.0), chi=(0.5, 0.5),
+                                          m_rho=16),
+                sections=200, grid="tanh", deltas=[10.0 ** (-2.0 + 4.0 * j / 15.0) for j in range(16)],
+                flows=[1] * 16)
+
+
 def workload_nodes(w):
     f = {"uniform": nodes_uniform, "tanh": nodes_tanh, "smoothstep": nodes_smoothstep}[w["grid"]]
-    return [f(w["sections"]) for _ in w["deltas"]]
+    sec = w["sections"]
+    return [f(sec[i] if isinstance(sec, (list, tuple)) else sec) for i in range(len(w["deltas"]))]
 
 
 # --------------------------------------------------------------- 2-D cross sections

@@ -39,7 +39,9 @@ class VelocityDesc(ctypes.Structure):
     _fields_ = [("n_v", ctypes.c_int32), ("l_v", ctypes.c_double), ("n_pad", ctypes.c_int32),
                 ("m_angle", ctypes.c_int32), ("r_trunc", ctypes.c_double),
                 ("kernel", ctypes.c_int32), ("visc_index", ctypes.c_double),
-                ("n_threads", ctypes.c_int32)]
+                ("n_threads", ctypes.c_int32), ("n_species", ctypes.c_int32),
+                ("mass", ctypes.c_double * 2), ("diam", ctypes.c_double * 2),
+                ("chi", ctypes.c_double * 2), ("m_rho", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -49,7 +51,9 @@ class PlanInfo(ctypes.Structure):
                 ("r_trunc", ctypes.c_double), ("nubar", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("operator_bytes", ctypes.c_int64), ("plan_seconds_host", ctypes.c_double),
-                ("plan_seconds_device", ctypes.c_double)]
+                ("plan_seconds_device", ctypes.c_double), ("n_species", ctypes.c_int32),
+                ("n_dof", ctypes.c_int32), ("nubar_b", ctypes.c_double),
+                ("viscosity_ratio", ctypes.c_double), ("flow_factor", ctypes.c_double)]
 
 
 class GeometryDesc(ctypes.Structure):
@@ -120,6 +124,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1612_04488_amd.build`")
+        # PyTorch brings its own HIP runtime: load it first so that the library
+        # binds to the same runtime instance as the tensors it is handed.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -150,15 +160,31 @@ def _stream(stream):
 
 
 def velocity_desc(n_v, l_v=6.0, n_pad=0, m_angle=6, kernel="hs", visc_index=0.81,
-                  r_trunc=0.0, n_threads=0):
+                  r_trunc=0.0, n_threads=0, mixture=None):
+    """mixture: None (one gas) or dict(masses=(m_A, m_B), diameters=(d_A, d_B),
+    chi=(chi_A, chi_B), m_rho=16) for a binary hard-sphere mixture."""
     k = KERNEL_HARD_SPHERE if kernel == "hs" else KERNEL_IPL
-    return VelocityDesc(n_v, l_v, n_pad, m_angle, r_trunc, k, visc_index, n_threads)
+    d = VelocityDesc(n_v, l_v, n_pad, m_angle, r_trunc, k, visc_index, n_threads)
+    if mixture is not None:
+        d.n_species = 2
+        d.mass[:] = [float(x) for x in mixture["masses"]]
+        d.diam[:] = [float(x) for x in mixture["diameters"]]
+        d.chi[:] = [float(x) for x in mixture["chi"]]
+        d.m_rho = int(mixture.get("m_rho", 0))
+    return d
 
 
 def host_tables(desc):
-    """Host-only tables (no GPU): dict with feq, nu, A, B (numpy), b0, nubar."""
+    """Host-only tables (no GPU): dict with feq, nu, A, B (numpy), b0, nubar.
+    Mixtures: feq, nu of shape (2, n3), nubar of shape (2,), no A, B."""
     import numpy as np
     n3 = desc.n_v ** 3
+    if desc.n_species == 2:
+        feq, nu = np.zeros((2, n3)), np.zeros((2, n3))
+        b0, nubar = ctypes.c_double(), (ctypes.c_double * 2)()
+        check(lib().sis_host_tables(ctypes.byref(desc), feq.ctypes.data_as(_P), nu.ctypes.data_as(_P),
+                                    None, None, ctypes.byref(b0), ctypes.cast(nubar, _D)))
+        return dict(feq=feq, nu=nu, b0=b0.value, nubar=np.array(nubar[:]))
     D = desc.m_angle ** 2
     feq, nu = np.zeros(n3), np.zeros(n3)
     A, B = np.zeros((D, n3)), np.zeros((D, n3))
@@ -173,13 +199,16 @@ class Plan:
     """Velocity grid + assembled fast-spectral operator on the current device."""
 
     def __init__(self, n_v, l_v=6.0, n_pad=0, m_angle=6, kernel="hs", visc_index=0.81,
-                 r_trunc=0.0, n_threads=0, stream=None):
-        self.desc = velocity_desc(n_v, l_v, n_pad, m_angle, kernel, visc_index, r_trunc, n_threads)
+                 r_trunc=0.0, n_threads=0, stream=None, mixture=None):
+        self.desc = velocity_desc(n_v, l_v, n_pad, m_angle, kernel, visc_index, r_trunc, n_threads,
+                                  mixture)
         h = ctypes.c_void_p()
         check(lib().sis_plan_create(ctypes.byref(self.desc), _stream(stream), ctypes.byref(h)))
         self.handle = h
         self.n_v = n_v
         self.n3 = n_v ** 3
+        self.n_species = 2 if mixture is not None else 1
+        self.n_dof = self.n_species * self.n3
 
     def close(self):
         if getattr(self, "handle", None):
@@ -200,11 +229,14 @@ class Plan:
 
     def tables(self, operator=False):
         import numpy as np
-        v1d, feq, nu = np.zeros(self.n_v), np.zeros(self.n3), np.zeros(self.n3)
-        op = np.zeros((self.n3, self.n3)) if operator else None
+        ns = self.n_species
+        v1d, feq, nu = np.zeros(self.n_v), np.zeros(ns * self.n3), np.zeros(ns * self.n3)
+        op = np.zeros((self.n_dof, self.n_dof)) if operator else None
         check(lib().sis_plan_tables(self.handle, v1d.ctypes.data_as(_P), feq.ctypes.data_as(_P),
                                     nu.ctypes.data_as(_P),
                                     op.ctypes.data_as(_P) if operator else None))
+        if ns > 1:
+            feq, nu = feq.reshape(ns, self.n3), nu.reshape(ns, self.n3)
         return dict(v1d=v1d, feq=feq, nu=nu, op=op)
 
     def set_precision(self, precision, stream=None):
@@ -333,10 +365,10 @@ def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False
           check_every=4, use_graph=True, stream=None, raise_not_converged=True, refresh_every=0):
     """Run sis_solve; returns a dict of numpy arrays (M, Q, iters, residual, U, q)."""
     import numpy as np
-    nc, ns = geom.n_cells, geom.n_cases
-    M, Q, res = np.zeros(ns), np.zeros(ns), np.zeros(ns)
+    nc, ns, sp = geom.n_cells, geom.n_cases, plan.n_species
+    M, Q, res = np.zeros((ns, sp)), np.zeros((ns, sp)), np.zeros(ns)
     it = np.zeros(ns, dtype=np.int32)
-    U, q = np.zeros(nc), np.zeros(nc)
+    U, q = np.zeros((nc, sp)), np.zeros((nc, sp))
     r = SolveResult(M.ctypes.data_as(_D), Q.ctypes.data_as(_D),
                     it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), res.ctypes.data_as(_D),
                     U.ctypes.data_as(_D), q.ctypes.data_as(_D), 0.0, 0)
@@ -345,6 +377,8 @@ def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False
     code = lib().sis_solve(plan.handle, geom.handle, ctypes.byref(o), ctypes.byref(r), _stream(stream))
     if code != SIS_OK and not (code == SIS_E_NOT_CONVERGED and not raise_not_converged):
         check(code)
+    if sp == 1:
+        M, Q, U, q = M[:, 0], Q[:, 0], U[:, 0], q[:, 0]
     return dict(M=M, Q=Q, iters=it, residual=res, U=U, q=q, seconds=r.seconds,
                 total_iters=r.total_iters, status=code)
 
@@ -380,16 +414,18 @@ class State:
 
     def results(self, stream=None, raise_not_converged=False):
         import numpy as np
-        nc, ns = self.geom.n_cells, self.geom.n_cases
-        M, Q, res = np.zeros(ns), np.zeros(ns), np.zeros(ns)
+        nc, ns, sp = self.geom.n_cells, self.geom.n_cases, self.plan.n_species
+        M, Q, res = np.zeros((ns, sp)), np.zeros((ns, sp)), np.zeros(ns)
         it = np.zeros(ns, dtype=np.int32)
-        U, q = np.zeros(nc), np.zeros(nc)
+        U, q = np.zeros((nc, sp)), np.zeros((nc, sp))
         r = SolveResult(M.ctypes.data_as(_D), Q.ctypes.data_as(_D),
                         it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), res.ctypes.data_as(_D),
                         U.ctypes.data_as(_D), q.ctypes.data_as(_D), 0.0, 0)
         code = lib().sis_state_results(self.handle, ctypes.byref(r), _stream(stream))
         if code not in (SIS_OK, SIS_E_NOT_CONVERGED) or (code != SIS_OK and raise_not_converged):
             check(code)
+        if sp == 1:
+            M, Q, U, q = M[:, 0], Q[:, 0], U[:, 0], q[:, 0]
         return dict(M=M, Q=Q, iters=it, residual=res, U=U, q=q, total_iters=r.total_iters,
                     status=code)
 

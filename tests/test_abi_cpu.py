@@ -78,3 +78,30 @@ def test_inputs_module_is_seeded():
     # odd in v3 by construction
     assert np.allclose(a, -a[..., ::-1], atol=0.0)
     assert np.array_equal(inputs.nodes_tanh(100), inputs.nodes_tanh(100))
+
+
+@pytest.mark.parametrize("n_v,l_v,m,chi", [(8, 4.0, 4, (0.5, 0.5)), (12, 4.5, 6, (0.1, 0.9))])
+def test_mixture_host_tables_equal_oracle(n_v, l_v, m, chi):
+    """Mixture planner: f_a, nu_a (scaled by the mixture viscosity) and N_a == oracle."""
+    from oracle import mixture
+    mx = dict(masses=(20.18, 39.95), diameters=(0.72, 1.0), chi=chi, m_rho=4)
+    t = sis.host_tables(sis.velocity_desc(n_v, l_v, m_angle=m, mixture=mx))
+    o = mixture.MixtureFSM(VelocityGrid(n_v, l_v), mx["masses"], mx["diameters"], chi, m_angle=m, m_rho=4)
+    assert np.max(np.abs(t["feq"] - o.feq.reshape(2, -1))) < 1e-16
+    assert np.max(np.abs(t["nu"] - o.nu.reshape(2, -1))) < 2e-14 * np.max(np.abs(o.nu))
+    assert np.allclose(t["nubar"], o.nubar(), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("mx,msg", [
+    (dict(masses=(1.0, -1.0), diameters=(1.0, 1.0), chi=(0.5, 0.5)), "mass"),
+    (dict(masses=(1.0, 2.0), diameters=(1.0, 1.0), chi=(0.5, 0.6)), "chi"),
+    (dict(masses=(1.0, 2.0), diameters=(0.0, 1.0), chi=(0.5, 0.5)), "diam"),
+])
+def test_mixture_validation(mx, msg):
+    d = sis.velocity_desc(8, 4.0, m_angle=4, mixture=mx)
+    h = ctypes.c_void_p()
+    assert sis.lib().sis_plan_create(ctypes.byref(d), None, ctypes.byref(h)) == sis.SIS_E_INVALID
+    assert msg in sis.lib().sis_last_error().decode()
+    d = sis.velocity_desc(8, 4.0, m_angle=4, kernel="ipl",
+                          mixture=dict(masses=(1.0, 2.0), diameters=(1.0, 1.0), chi=(0.5, 0.5)))
+    assert sis.lib().sis_plan_create(ctypes.byref(d), None, ctypes.byref(h)) == sis.SIS_E_UNSUPPORTED
