@@ -42,6 +42,8 @@ def cpu_baseline(w, n_cells):
     from oracle import collision
     from oracle.velocity import VelocityGrid
     from paper_1612_04488_amd import inputs
+    if "mixture" in w:
+        return cpu_baseline_mixture(w, n_cells)
     t0 = time.perf_counter()
     alpha = 2.0 * (1.0 - w.get("visc_index", 0.81)) if w["kernel"] == "ipl" else 1.0
     f = collision.FSM(VelocityGrid(w["n_v"], w["l_v"]), n_pad=w["n_pad"], m_angle=w["m_angle"],
@@ -55,6 +57,31 @@ def cpu_baseline(w, n_cells):
     return {"value": n_cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"L(h) of {n_cells} smooth cells of the benchmark batch, one process "
                       f"(NumPy FFT, single thread); table build {t_build:.1f} s excluded",
+            "cpu": _cpu_model(), "host_cpu_count": os.cpu_count()}
+
+
+def cpu_baseline_mixture(w, n_cells):
+    """Mixture oracle: its equilibrium factor tables are built first (excluded),
+    then L_A, L_B of n_cells cells are timed."""
+    from oracle import mixture
+    from oracle.velocity import VelocityGrid
+    from paper_1612_04488_amd import inputs
+    mx = w["mixture"]
+    t0 = time.perf_counter()
+    op = mixture.MixtureFSM(VelocityGrid(w["n_v"], w["l_v"]), mx["masses"], mx["diameters"], mx["chi"],
+                            n_pad=w["n_pad"], m_angle=w["m_angle"], m_rho=mx["m_rho"])
+    for a in range(2):
+        for b in range(2):
+            op._feq_factors(a, b)
+    t_build = time.perf_counter() - t0
+    h = inputs.mixture_h(w["n_v"], w["l_v"], n_cells)
+    t0 = time.perf_counter()
+    for c in range(n_cells):
+        op.apply(h[c])
+    dt = time.perf_counter() - t0
+    return {"value": n_cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"L_A, L_B of {n_cells} cell(s) of the mixture batch, one process (NumPy FFT, "
+                      f"single thread); table and equilibrium-factor build {t_build:.1f} s excluded",
             "cpu": _cpu_model(), "host_cpu_count": os.cpu_count()}
 
 
@@ -74,7 +101,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--workload", default="batch", choices=["batch", "small", "duct", "porous"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "small", "duct", "porous", "mixture"])
     ap.add_argument("--ttr", default="fp64,fp32,bf16x3,fp64+projection,bf16x3+projection",
                     help="time-to-residual runs (comma list)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -94,15 +121,21 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = {"batch": inputs.PLANAR_BATCH, "small": inputs.PLANAR_SMALL, "duct": inputs.DUCT_IPL,
-         "porous": inputs.POROUS_HS}[args.workload]
+         "porous": inputs.POROUS_HS, "mixture": inputs.MIX_NEAR}[args.workload]
+    mix = w.get("mixture")
+    # penalty N of the SIS velocity equations: nubar for one gas, 1.5 for the
+    # mixture (the value the paper reports converging within 50 iterations)
+    Npen = 1.5 if mix else 0.0
+    if mix and args.cpu_cells == 12:
+        args.cpu_cells = 1
     t0 = time.perf_counter()
     plan = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"],
-                    visc_index=w.get("visc_index", 0.81))
+                    visc_index=w.get("visc_index", 0.81), mixture=mix)
     t_plan = time.perf_counter() - t0
     info = plan.info
     log(f"plan {w['name']}: {t_plan:.2f} s (host {info['plan_seconds_host']:.2f} s), "
         f"operator {info['operator_bytes'] / 2**30:.2f} GiB")
-    if args.workload in ("batch", "small"):
+    if args.workload in ("batch", "small", "mixture"):
         xs = inputs.workload_nodes(w)
         geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
         per_case = [len(x) for x in xs]
@@ -111,11 +144,12 @@ def main():
         geom = sis.Geometry2D(plan, "duct" if args.workload == "duct" else "periodic", cases,
                               w["deltas"], w["flows"])
         per_case = np.diff(geom.offsets).tolist()
-    nc, n3 = geom.n_cells, plan.n3
+    nc, n3 = geom.n_cells, plan.n_dof   # unknowns per spatial cell (both species for a mixture)
     plan.set_precision(args.precision)
 
     # ---------------------------------------------------------- whole-step throughput
-    state = sis.State(plan, geom, scheme="SIS", eps=0.0, max_it=1 << 30, project=args.precision != "fp64")
+    state = sis.State(plan, geom, scheme="SIS", N=Npen, eps=0.0, max_it=1 << 30,
+                      project=args.precision != "fp64" and not mix)
     state.step(args.warmup)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -132,7 +166,8 @@ def main():
     state.close()
 
     # ---------------------------------------------------------- dominant kernel: contraction
-    h = torch.tensor(inputs.smooth_h(w["n_v"], w["l_v"], nc).reshape(nc, n3), device="cuda")
+    h0 = inputs.mixture_h(w["n_v"], w["l_v"], nc) if mix else inputs.smooth_h(w["n_v"], w["l_v"], nc)
+    h = torch.tensor(h0.reshape(nc, n3), device="cuda")
     delta = torch.tensor(np.repeat(w["deltas"], per_case), dtype=torch.float64, device="cuda")
     rhs = torch.empty_like(h)
     plan.collide(h, delta, rhs)   # warm
@@ -156,16 +191,19 @@ def main():
                 "fsm_fft_flops_per_cell_update": None}
     D = info["n_dir"]
     Np3 = w["n_pad"] ** 3
-    roofline["fsm_fft_flops_per_cell_update"] = (2 * D + 2) * 2.5 * Np3 * np.log2(Np3) + 6 * D * Np3
+    if not mix:
+        roofline["fsm_fft_flops_per_cell_update"] = (2 * D + 2) * 2.5 * Np3 * np.log2(Np3) + 6 * D * Np3
 
     # ---------------------------------------------------------- time to residual 1e-8
     ttr = {}
     if not args.no_ttr:
         ref = {}
         runs = [(r.split("+")[0], r.endswith("+projection")) for r in args.ttr.split(",") if r]
+        if mix:
+            runs = [(prec, proj) for prec, proj in runs if not proj]
         for prec, proj in runs:
             plan.set_precision(prec)
-            r = sis.solve(plan, geom, scheme="SIS", eps=1e-8, max_it=400, project=proj,
+            r = sis.solve(plan, geom, scheme="SIS", N=Npen, eps=1e-8, max_it=400, project=proj,
                           raise_not_converged=False)
             key = prec + ("+projection" if proj else "")
             e = {"seconds": round(r["seconds"], 4), "iters": r["iters"].tolist(),
@@ -193,7 +231,8 @@ def main():
            "config": {"workload": w["name"], "kernel": w["kernel"], "n_v": w["n_v"], "l_v": w["l_v"],
                       "n_pad": w["n_pad"],
                       "directions": D, "cells": nc, "cases": geom.n_cases, "deltas": w["deltas"],
-                      "flows": w["flows"], "scheme": "SIS", "collision_precision": args.precision},
+                      "flows": w["flows"], "scheme": "SIS", "collision_precision": args.precision,
+                      "unknowns_per_cell": n3, "species": plan.n_species},
            "roofline": roofline,
            "plan_seconds": round(t_plan, 3),
            "time_to_residual_1e-8": ttr}
