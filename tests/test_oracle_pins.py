@@ -222,7 +222,7 @@ def test_P13_sis_cis_gap_shrinks_on_refinement():
     """SIS and CIS reach the same flow rate up to spatial discretisation error;
     the gap shrinks as the grid is refined (Sec. 2.4 reports < 0.5% at 100
     sections)."""
-    f = collision.ProjectedFSM(fsm(12, 6, 4.0))
+    f = collision.ProjectedFSM(fsm(12, 4, 4.0))
     gaps = []
     for n_s in (6, 18):
         x = tr.nodes_uniform(n_s)
@@ -237,7 +237,7 @@ def test_P13_sis_cis_gap_shrinks_on_refinement():
 def test_sis_needs_far_fewer_iterations_than_cis():
     """Table 1 trend: at delta = 10 CIS needs an order of magnitude more
     iterations than SIS (777 vs 54 in the paper)."""
-    f = collision.ProjectedFSM(fsm(12, 6, 4.0))
+    f = collision.ProjectedFSM(fsm(12, 4, 4.0))
     x = tr.nodes_uniform(5)
     rs = solver.solve_1d(f, x, 10.0, POISEUILLE, "SIS", eps=1e-8)
     rc = solver.solve_1d(f, x, 10.0, POISEUILLE, "CIS", eps=1e-8, max_it=3000)
