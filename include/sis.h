@@ -98,6 +98,18 @@ typedef struct {
   double  diam[2];
   double  chi[2];
   int32_t m_rho;      /* Gauss nodes on [0, R] of the rho integral of unequal-mass pairs (0 -> 16) */
+  /* Parity storage (0, 1, 2).  The discrete operator commutes with v3 -> -v3 and
+   * v2 -> -v2 (symmetric grid and direction set), and the Poiseuille and
+   * transpiration sources are odd in v3 and even in v2, so their iterates keep
+   * that symmetry.  parity 1 stores only v3 > 0 (any geometry); parity 2 stores
+   * v2 > 0 and v3 > 0 (planar only).  A distribution of one (cell, species) is
+   * then n_vel = n_v * (parity 2 ? n_v/2 : n_v) * n_v/2 doubles, C order
+   * [v1][v2][v3] over the stored nodes (the upper halves of the v2, v3 axes);
+   * every compute call takes and returns that layout, and moments, flow rates
+   * and projections are those of the full-grid distribution it represents.
+   * The operator is the full one restricted to the class (4x / 16x fewer
+   * entries).  Inputs outside the class are the caller's error.             */
+  int32_t parity;
 } sis_velocity_desc;
 
 typedef struct {
@@ -111,6 +123,8 @@ typedef struct {
   double  nubar_b;                       /* mixture: int nu_B f_B / chi_B (nubar is A's)     */
   double  viscosity_ratio;               /* mixture: mu_mix / mu_A (first Chapman-Enskog)    */
   double  flow_factor;                   /* mixture: sqrt(m / m_A), m = chi_A m_A + chi_B m_B */
+  int32_t parity;                        /* 0, 1, 2 (see sis_velocity_desc)                  */
+  int32_t n_vel;                         /* stored velocities per (cell, species)            */
 } sis_plan_info;
 
 /* Mixtures (n_species = 2).  Unknowns per spatial cell: h = (h_A, h_B),

@@ -75,6 +75,11 @@ struct sis_plan {
   int precision = SIS_PREC_FP64;
   // species: 1 (one gas) or 2 (binary mixture); rows of the operator are (species, velocity)
   int nsp = 1, ndof = 0;
+  // parity storage: 0 full grid; 1 odd in v3 (v3 > 0 stored); 2 odd in v3 and even in v2
+  // (v2, v3 > 0 stored).  nv velocities per (cell, species) row on n x d2 x d3 nodes; wr is
+  // the quadrature weight of a stored velocity times its number of mirror images.
+  int parity = 0, d2 = 0, d3 = 0, nv = 0;
+  double wr = 0.0;
   double mass_ratio[2] = {1.0, 1.0}, chi[2] = {1.0, 0.0}, nubar_s[2] = {0.0, 0.0};
   double cU_s[2] = {0.0, 0.0}, cq_s[2] = {0.0, 0.0};
   double flow_factor = 1.0, visc_ratio = 1.0;
@@ -174,6 +179,7 @@ sis_status validate_desc(const sis_velocity_desc* d) {
   if (d->kernel == SIS_KERNEL_IPL && !(d->visc_index >= 0.5 && d->visc_index <= 1.0))
     return fail(SIS_E_INVALID, "IPL viscosity index must be in [0.5, 1]");
   if (d->n_species < 0 || d->n_species > 2) return fail(SIS_E_UNSUPPORTED, "n_species must be 1 or 2");
+  if (d->parity < 0 || d->parity > 2) return fail(SIS_E_INVALID, "parity must be 0, 1 or 2");
   if (d->n_species == 2) {
     if (d->kernel != SIS_KERNEL_HARD_SPHERE) return fail(SIS_E_UNSUPPORTED, "mixtures support hard spheres only");
     for (int s = 0; s < 2; ++s) {
@@ -273,7 +279,12 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   }
   sis::FinishArgs f{};
   f.n = p->n;
-  f.n3 = p->n3;
+  f.n3 = p->nv;
+  f.d2 = p->d2;
+  f.d3 = p->d3;
+  f.v2d = p->v1d + (p->n - p->d2);
+  f.v3d = p->v1d + (p->n - p->d3);
+  f.even_v2 = p->parity == 2;
   f.nsp = p->nsp;
   f.mass_ratio[0] = p->mass_ratio[0];
   f.mass_ratio[1] = p->mass_ratio[1];
@@ -290,7 +301,7 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   f.nu = p->nu;
   f.Kc = p->Kc;
   f.gram_inv = p->gram_inv;
-  f.w = p->w;
+  f.w = p->wr;
   f.active = cell_active;
   f.anchor_mode = anchor_mode;
   f.accref = accref;
@@ -307,7 +318,9 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
   if (g->two_d) {
     sis::Sweep2DArgs a{};
     a.n = p->n;
-    a.n3 = p->n3;
+    a.n3 = p->nv;
+    a.d3 = p->d3;
+    a.v3d = p->v1d + (p->n - p->d3);
     a.n_cases = g->n_cases;
     a.n1 = g->d_n1;
     a.n2 = g->d_n2;
@@ -323,14 +336,20 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.h = h;
     a.case_active = case_active;
     HIP_TRY(sis::launch_sweep2d(a, s));
-    if (mom) HIP_TRY(sis::launch_moments2d(p->n, p->n3, g->n_cells, p->v1d, h, p->w, cell_active, mom, s));
+    if (mom)
+      HIP_TRY(sis::launch_moments2d(p->n, p->d3, g->n_cells, p->v1d, p->v1d + (p->n - p->d3), h, p->wr, cell_active,
+                                    mom, s));
     return SIS_OK;
   }
-  const int W = (p->n3 / 2 + 63) / 64;
+  const int W = (p->nv / 2 + 63) / 64;
   HIP_TRY(p->ws_part.ensure(static_cast<size_t>(g->n_cells) * p->nsp * 8 * W * sizeof(double)));
   sis::SweepArgs a{};
   a.n = p->n;
-  a.n3 = p->n3;
+  a.n3 = p->nv;
+  a.d2 = p->d2;
+  a.d3 = p->d3;
+  a.v2d = p->v1d + (p->n - p->d2);
+  a.v3d = p->v1d + (p->n - p->d3);
   a.nsp = p->nsp;
   a.mass_ratio[0] = p->mass_ratio[0];
   a.mass_ratio[1] = p->mass_ratio[1];
@@ -345,7 +364,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
   a.part = static_cast<double*>(p->ws_part.p);
   a.W = W;
   a.case_active = case_active;
-  a.w = p->w;
+  a.w = p->wr;
   a.max_nodes = g->max_nodes;
   HIP_TRY(sis::launch_sweep1d(a, s));
   if (mom) HIP_TRY(sis::launch_reduce_partials(a.part, W, g->n_cells * p->nsp, mom, s));
@@ -501,6 +520,53 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
 }
 
 
+// Stored velocity layout of a plan (see sis_plan::parity).
+void set_layout(sis_plan* p, int parity) {
+  const int n = p->n;
+  p->parity = parity;
+  p->d2 = parity == 2 ? n / 2 : n;
+  p->d3 = parity >= 1 ? n / 2 : n;
+  p->nv = n * p->d2 * p->d3;
+  p->ndof = p->nsp * p->nv;
+  p->wr = p->w * (parity == 2 ? 4.0 : parity == 1 ? 2.0 : 1.0);
+}
+
+// Full-grid [species][n^3] array -> stored [species][nv] (v2, v3 of the upper halves).
+std::vector<double> restrict_rows(const sis_plan* p, const double* full, int rows) {
+  const int n = p->n, n3 = n * n * n;
+  std::vector<double> out(static_cast<size_t>(rows) * p->nv);
+  for (int s = 0; s < rows; ++s)
+    for (int j1 = 0; j1 < n; ++j1)
+      for (int j2 = 0; j2 < p->d2; ++j2)
+        for (int j3 = 0; j3 < p->d3; ++j3)
+          out[static_cast<size_t>(s) * p->nv + (j1 * p->d2 + j2) * p->d3 + j3] =
+              full[static_cast<size_t>(s) * n3 + (j1 * n + j2 + (n - p->d2)) * n + j3 + (n - p->d3)];
+  return out;
+}
+
+// Replace the assembled full-grid operator by its restriction to the stored
+// parity class and restrict the equilibrium / collision-frequency tables.
+sis_status apply_parity(sis_plan* p, hipStream_t stream) {
+  if (!p->parity) return SIS_OK;
+  const int64_t ld_full = static_cast<int64_t>(p->nsp) * p->n3;
+  double* red = nullptr;
+  HIP_TRY(dmalloc(&red, static_cast<size_t>(p->ndof) * p->ndof));
+  hipError_t e = sis::launch_reduce_operator(p->op, ld_full, red, p->nsp, p->n, p->parity, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    dfree(red);
+    return fail(SIS_E_DEVICE, "operator restriction: %s", hipGetErrorString(e));
+  }
+  dfree(p->op);
+  p->op = red;
+  p->h_feq = restrict_rows(p, p->h_feq.data(), p->nsp);
+  p->h_nu = restrict_rows(p, p->h_nu.data(), p->nsp);
+  HIP_TRY(hipMemcpyAsync(p->feq, p->h_feq.data(), p->h_feq.size() * 8, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(p->nu, p->h_nu.data(), p->h_nu.size() * 8, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return SIS_OK;
+}
+
 // Binary-mixture plan: 2 x 2 blocks of n3 x n3, each assembled from the
 // equal-mass (closed-form phi) terms or the rho-quadrature terms of the
 // unequal-mass gain, plus the loss.  Cross terms are built on the host in
@@ -528,6 +594,7 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
   p->gamma = 0.0;
   p->nsp = 2;
   p->ndof = 2 * n3;
+  set_layout(p, 0);
   for (int s = 0; s < 2; ++s) {
     p->mass_ratio[s] = t.a[s];
     p->chi[s] = t.chi[s];
@@ -616,6 +683,14 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
                                        kind == 0 ? block(a, b) : block(a, a), ndof, 1, stream));
         }
     }
+  // restriction to the stored parity class (odd in v3 / even in v2)
+  MIX_TRY(hipStreamSynchronize(stream));
+  set_layout(p, desc->parity);
+  if (sis_status st = apply_parity(p, stream)) {
+    cleanup();
+    delete p;
+    return st;
+  }
   // correction shapes 2 (m_s/m_A) v3 f_s and their L+ (two-row contraction)
   std::vector<double> corr(2 * static_cast<size_t>(ndof), 0.0);
   for (int s = 0; s < 2; ++s) {
@@ -635,6 +710,7 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
   }
   p->cU = p->cU_s[0];
   p->cq = p->cq_s[0];
+  if (p->parity) corr = restrict_rows(p, corr.data(), 4);  // [2 shapes][2 species] -> stored rows
   MIX_TRY(hipStreamSynchronize(stream));
   MIX_TRY(hipMemcpyAsync(dX, corr.data(), corr.size() * 8, hipMemcpyHostToDevice, stream));
   {
@@ -644,8 +720,8 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
     g.op64 = p->op;
     g.acc = p->Kc;
     g.M = 2;
-    g.N = static_cast<int>(ndof);
-    g.K = static_cast<int>(ndof);
+    g.N = static_cast<int>(p->ndof);
+    g.K = static_cast<int>(p->ndof);
     g.splits = 1;
     g.tile = 1;
     MIX_TRY(sis::launch_gemm(g, stream));
@@ -723,6 +799,7 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   p->nubar = t.nubar;
   p->nsp = 1;
   p->ndof = t.n3;
+  set_layout(p, 0);
   p->nubar_s[0] = t.nubar;
   p->alpha = t.alpha;
   p->gamma = t.gamma;
@@ -788,7 +865,12 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
       }
   p->cU_s[0] = p->cU;
   p->cq_s[0] = p->cq;
-  if (!invert5(G, Gi)) {
+  if (desc->parity) {
+    // stored by parity the projection keeps only its v3 (x3-momentum) component: the
+    // Gram matrix is block diagonal in v3-parity and L is odd in v3
+    for (int k = 0; k < 25; ++k) Gi[k] = 0.0;
+    Gi[3 * 5 + 3] = 1.0 / G[3 * 5 + 3];
+  } else if (!invert5(G, Gi)) {
     cleanup();
     delete p;
     return fail(SIS_E_NUMERIC, "singular invariant Gram matrix");
@@ -796,9 +878,17 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   PLAN_TRY(hipMemcpyAsync(p->gram_inv, Gi, 25 * 8, hipMemcpyHostToDevice, stream));
 
   PLAN_TRY(sis::launch_assemble(n, 2 * D, dX, dY, p->feq, 1.0, dbr, p->op, n3, 0, stream));
-  // Kc = L+(2 v3 feq): one-row contraction against the operator
+  // restriction to the stored parity class, then Kc = L+(2 v3 feq): one-row contraction
+  PLAN_TRY(hipStreamSynchronize(stream));
+  set_layout(p, desc->parity);
+  if (sis_status st = apply_parity(p, stream)) {
+    cleanup();
+    delete p;
+    return st;
+  }
+  if (p->parity) corr = restrict_rows(p, corr.data(), 1);
   double* dcorr = dX;  // reuse (large enough)
-  PLAN_TRY(hipMemcpyAsync(dcorr, corr.data(), n3 * 8, hipMemcpyHostToDevice, stream));
+  PLAN_TRY(hipMemcpyAsync(dcorr, corr.data(), corr.size() * 8, hipMemcpyHostToDevice, stream));
   {
     sis::GemmArgs g{};
     g.precision = 0;
@@ -806,8 +896,8 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
     g.op64 = p->op;
     g.acc = p->Kc;
     g.M = 1;
-    g.N = n3;
-    g.K = n3;
+    g.N = p->ndof;
+    g.K = p->ndof;
     g.splits = 1;
     g.tile = 1;
     PLAN_TRY(sis::launch_gemm(g, stream));
@@ -850,6 +940,8 @@ sis_status sis_plan_query(sis_plan_t p, sis_plan_info* out) {
   out->nubar_b = p->nsp == 2 ? p->nubar_s[1] : 0.0;
   out->viscosity_ratio = p->visc_ratio;
   out->flow_factor = p->flow_factor;
+  out->parity = p->parity;
+  out->n_vel = p->nv;
   out->plan_seconds_host = p->host_s;
   out->plan_seconds_device = p->dev_s;
   return SIS_OK;
@@ -858,8 +950,8 @@ sis_status sis_plan_query(sis_plan_t p, sis_plan_info* out) {
 sis_status sis_plan_tables(sis_plan_t p, double* v1d, double* feq, double* nu, double* op) {
   if (sis_status st = check_plan(p)) return st;
   if (v1d) std::memcpy(v1d, p->h_v1d.data(), p->n * 8);
-  if (feq) std::memcpy(feq, p->h_feq.data(), static_cast<size_t>(p->nsp) * p->n3 * 8);
-  if (nu) std::memcpy(nu, p->h_nu.data(), static_cast<size_t>(p->nsp) * p->n3 * 8);
+  if (feq) std::memcpy(feq, p->h_feq.data(), static_cast<size_t>(p->nsp) * p->nv * 8);
+  if (nu) std::memcpy(nu, p->h_nu.data(), static_cast<size_t>(p->nsp) * p->nv * 8);
   if (op) HIP_TRY(hipMemcpy(op, p->op, static_cast<size_t>(p->ndof) * p->ndof * 8, hipMemcpyDeviceToHost));
   return SIS_OK;
 }
@@ -875,7 +967,7 @@ sis_status sis_plan_set_precision(sis_plan_t p, int32_t precision, hipStream_t s
       HIP_TRY(hipStreamSynchronize(stream));
     }
   } else if (precision == SIS_PREC_BF16X3) {
-    if (p->n3 % 8) return fail(SIS_E_UNSUPPORTED, "BF16X3 needs n_v^3 divisible by 8");
+    if (p->ndof % 8) return fail(SIS_E_UNSUPPORTED, "BF16X3 needs the unknowns per cell divisible by 8");
     if (!p->ophi) {
       HIP_TRY(dmalloc(&p->ophi, cnt));
       HIP_TRY(dmalloc(&p->oplo, cnt));
@@ -895,6 +987,8 @@ sis_status sis_geometry_create(sis_plan_t p, const sis_geometry_desc* d, hipStre
   if (!d || !out) return fail(SIS_E_INVALID, "null argument");
   *out = nullptr;
   if (d->n_cases < 1) return fail(SIS_E_INVALID, "n_cases must be >= 1");
+  if (p->parity == 2 && d->kind != SIS_GEOM_PLANAR_HALF)
+    return fail(SIS_E_UNSUPPORTED, "parity 2 (even in v2) needs the planar geometry");
   if (p->nsp == 2) {
     if (d->kind != SIS_GEOM_PLANAR_HALF) return fail(SIS_E_UNSUPPORTED, "mixtures support the planar geometry only");
     for (int c = 0; c < d->n_cases; ++c)
@@ -1030,8 +1124,8 @@ sis_status sis_moments(sis_plan_t p, int64_t n_cells, const double* h, double* m
   if (n_cells < 0) return fail(SIS_E_SHAPE, "n_cells must be >= 0");
   if (n_cells == 0) return SIS_OK;
   if (!h || !mom_out) return fail(SIS_E_INVALID, "null array");
-  HIP_TRY(sis::launch_moments(p->n, p->n3, p->nsp, p->mass_ratio, n_cells * p->nsp, p->v1d, h, p->w, mom_out,
-                              stream));
+  HIP_TRY(sis::launch_moments(p->n, p->d2, p->d3, p->nsp, p->mass_ratio, n_cells * p->nsp, p->v1d,
+                              p->v1d + (p->n - p->d2), p->v1d + (p->n - p->d3), h, p->wr, mom_out, stream));
   return SIS_OK;
 }
 
@@ -1235,7 +1329,7 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
     int tile, splits;
     choose_gemm(nc, n3, &tile, &splits);
     if (splits > 1) ST_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
-    const int W = (p->n3 / 2 + 63) / 64;
+    const int W = (p->nv / 2 + 63) / 64;
     if (!g->two_d) ST_TRY(p->ws_part.ensure(static_cast<size_t>(nc) * nsp * 8 * W * 8));
   }
   hipStream_t s = stream;

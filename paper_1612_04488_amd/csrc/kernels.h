@@ -14,6 +14,12 @@ hipError_t launch_assemble(int n, int T, const double* X, const double* Y, const
                            double loss_coef, const double* beta_r, double* op, int64_t ldo, int accumulate,
                            hipStream_t s);
 
+// Restriction of the operator (row stride ld, nsp species blocks of n^3) to distributions odd in
+// v3 (parity 1) or odd in v3 and even in v2 (parity 2): stored velocities v3 > 0 (and v2 > 0),
+// red is [nsp*nv][nsp*nv], nv = n * (parity 2 ? n/2 : n) * n/2.
+hipError_t launch_reduce_operator(const double* op, int64_t ld, double* red, int nsp, int n, int parity,
+                                  hipStream_t s);
+
 // op2 = op (double) rounded to float / split into bf16 hi + lo.
 hipError_t launch_convert_f32(const double* op, float* out, int64_t count, hipStream_t s);
 hipError_t launch_split_bf16(const double* op, uint16_t* hi, uint16_t* lo, int64_t count, hipStream_t s);
@@ -38,9 +44,15 @@ struct GemmArgs {
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 int gemm_k_per_split(int K, int splits);
 
-// Rows are (cell, species) pairs of n3 values: row = cell * nsp + species.
+// Rows are (cell, species) pairs of n3 values: row = cell * nsp + species.  A row holds the
+// velocities (v1, v2, v3) on n x d2 x d3 nodes (v1d, v2d, v3d): the full grid, or v3 > 0 (and
+// v2 > 0) when the distribution is stored by parity; w then carries the image count.
 struct FinishArgs {
   int n, n3;
+  int d2, d3;
+  const double* v2d;
+  const double* v3d;
+  int even_v2;             // h stored for v2 > 0 only: the v2 v3 moments are zero
   int nsp;                 // species per cell (1 or 2)
   double mass_ratio[2];    // m_s / m_A (1 for one gas)
   int64_t n_cells;         // rows = cells * nsp
@@ -72,6 +84,9 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 
 struct SweepArgs {
   int n, n3;
+  int d2, d3;                // stored v2, v3 nodes per row (see FinishArgs)
+  const double* v2d;
+  const double* v3d;
   int nsp;                   // species per cell; grid.z runs over species
   double mass_ratio[2];      // m_s / m_A: weights of q3 and P13
   int n_cases;
@@ -92,10 +107,11 @@ hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s);
 // mom[cell][4] = sum over the wave partials (fixed order)
 hipError_t launch_reduce_partials(const double* part, int W, int64_t n_cells, double* mom,
                                   hipStream_t s);
-// mom[row][4] = {U3, q3, G1, P13} of h[row][n3] directly (rows = cells * nsp;
+// mom[row][4] = {U3, q3, G1, P13} of h[row][n x d2 x d3] directly (rows = cells * nsp;
 // q3 and P13 weighted with the mass ratio of the row's species)
-hipError_t launch_moments(int n, int n3, int nsp, const double* mass_ratio, int64_t n_rows, const double* v1d,
-                          const double* h, double w, double* mom, hipStream_t s);
+hipError_t launch_moments(int n, int d2, int d3, int nsp, const double* mass_ratio, int64_t n_rows,
+                          const double* v1d, const double* v2d, const double* v3d, const double* h, double w,
+                          double* mom, hipStream_t s);
 
 struct DiffusionArgs {
   int n_cases;
@@ -129,6 +145,8 @@ hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s);
 // ---------------------------------------------------------------- 2-D cross sections
 struct Sweep2DArgs {
   int n, n3, n_cases;
+  int d3;                    // stored v3 nodes (n, or n/2 for distributions odd in v3)
+  const double* v3d;
   const int32_t* n1;
   const int32_t* n2;
   const int64_t* grid_off;
@@ -144,8 +162,8 @@ struct Sweep2DArgs {
   const int32_t* case_active;
 };
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s);
-// mom[cell][8] = {U3, q3, G1, G12, G2, P13, P23, 0}
-hipError_t launch_moments2d(int n, int n3, int64_t n_cells, const double* v1d, const double* h,
+// mom[cell][8] = {U3, q3, G1, G12, G2, P13, P23, 0}; rows of n x n x d3 velocities
+hipError_t launch_moments2d(int n, int d3, int64_t n_cells, const double* v1d, const double* v3d, const double* h,
                             double w, const int32_t* cell_active, double* mom, hipStream_t s);
 
 struct Diff2DArgs {

@@ -110,6 +110,34 @@ __global__ __launch_bounds__(256) void assemble_kernel(int n, int T, const doubl
   }
 }
 
+// Restriction of the operator to distributions odd in v3 (and even in v2):
+// red[i][j] = sum over the mirror images s(j) of j of sign(s) op[i][s(j)],
+// rows and columns over the stored half (quarter) grid of every species.
+__global__ void reduce_operator_kernel(const double* __restrict__ op, int64_t ld, double* __restrict__ red,
+                                       int nsp, int n, int parity) {
+  const int d2 = parity == 2 ? n / 2 : n, d3 = n / 2;
+  const int nv = n * d2 * d3, n3 = n * n * n;
+  const int64_t ldr = static_cast<int64_t>(nsp) * nv;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= ldr * ldr) return;
+  const int64_t ri = idx / ldr, rj = idx % ldr;
+  auto full = [&](int64_t r) {  // full-grid index of a stored (species, velocity) row
+    const int s = static_cast<int>(r / nv), v = static_cast<int>(r % nv);
+    const int j1 = v / (d2 * d3), j2 = (v / d3) % d2 + (n - d2), j3 = v % d3 + n / 2;
+    return static_cast<int64_t>(s) * n3 + (static_cast<int64_t>(j1) * n + j2) * n + j3;
+  };
+  const int64_t fi = full(ri), fj = full(rj);
+  const int j3 = static_cast<int>(fj % n), j2 = static_cast<int>((fj / n) % n);
+  const int64_t m3 = fj + (n - 1 - 2 * j3);            // v3 -> -v3
+  const double* row = op + fi * ld;
+  double s = row[fj] - row[m3];
+  if (parity == 2) {
+    const int64_t dm2 = static_cast<int64_t>(n - 1 - 2 * j2) * n;  // v2 -> -v2
+    s += row[fj + dm2] - row[m3 + dm2];
+  }
+  red[idx] = s;
+}
+
 __global__ void convert_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < count) out[i] = static_cast<float>(in[i]);
@@ -541,9 +569,10 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
   double m[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) m[k] = 0.0;
+  const int d2 = a.d2, d3 = a.d3, d23 = d2 * d3;
   for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-    const int j1 = v / nn, j2 = (v / n) % n, j3 = v % n;
-    const double v1 = a.v1d[j1], v2 = a.v1d[j2], v3 = a.v1d[j3];
+    const int j1 = v / d23, j2 = (v / d3) % d2, j3 = v % d3;
+    const double v1 = a.v1d[j1], v2 = a.v2d[j2], v3 = a.v3d[j3];
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
     const double f = feq[v];
     double s = 0.0;
@@ -585,8 +614,8 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
     }
     __syncthreads();
     for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-      const int j1 = v / nn, j2 = (v / n) % n, j3 = v % n;
-      const double v1 = a.v1d[j1], v2 = a.v1d[j2], v3 = a.v1d[j3];
+      const int j1 = v / d23, j2 = (v / d3) % d2, j3 = v % d3;
+      const double v1 = a.v1d[j1], v2 = a.v2d[j2], v3 = a.v3d[j3];
       const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
       const double corr = feq[v] * (coef[0] + coef[1] * v1 + coef[2] * v2 + coef[3] * v3 + coef[4] * vsq);
       a.rhs[base + v] -= corr;
@@ -594,10 +623,11 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
     }
   }
   if (a.amom && threadIdx.x == 0) {
+    // with h stored for v2 > 0 only (h even in v2) the v2 v3 moments vanish identically
     a.amom[c * 4 + 0] = m[5];
     a.amom[c * 4 + 1] = m[6];
-    a.amom[c * 4 + 2] = m[7];
-    a.amom[c * 4 + 3] = m[8];
+    a.amom[c * 4 + 2] = a.even_v2 ? 0.0 : m[7];
+    a.amom[c * 4 + 3] = a.even_v2 ? 0.0 : m[8];
   }
 }
 
@@ -614,11 +644,12 @@ __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
   const bool writer = (threadIdx.x & 63) == 0;
   const int64_t c0 = a.node_off[cs];
   const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
-  const int j1h = tt / nn, r = tt % nn;
+  const int d23 = a.d2 * a.d3;
+  const int j1h = tt / d23, r = tt % d23;
   const int jp = n / 2 + j1h, jm = n / 2 - 1 - j1h;
-  const int vp = jp * nn + r, vm = jm * nn + r;
+  const int vp = jp * d23 + r, vm = jm * d23 + r;
   const double v1 = a.v1d[jp];
-  const double v2 = a.v1d[r / n], v3 = a.v1d[r % n];
+  const double v2 = a.v2d[r / a.d3], v3 = a.v3d[r % a.d3];
   const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
   const double del = a.delta_case[cs];
   const double* nu = a.nu + static_cast<int64_t>(sp) * n3;
@@ -633,7 +664,9 @@ __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
   auto put = [&](int64_t cell, int pass, double h) {
     const double s0 = wave_sum(wU * h), s1 = wave_sum(wq * h), s2 = wave_sum(wG * h);
     const double s3 = wave_sum((pass == 0 ? wP : -wP) * h);
-    if (writer) {
+    // waves past the last velocity pair (when n3/2 is not a multiple of the block size)
+    // hold only padding lanes and own no partial slot
+    if (writer && wave < W) {
       double* p = a.part + (((cell * nsp + sp) * 2 + pass) * 4) * W + wave;
       p[0] = s0;
       p[W] = s1;
@@ -688,17 +721,19 @@ __global__ __launch_bounds__(64) void reduce_partials_kernel(const double* __res
   }
 }
 
-__global__ __launch_bounds__(256) void moments_kernel(int n, int n3, int nsp, double ms0, double ms1,
+__global__ __launch_bounds__(256) void moments_kernel(int n, int d2, int d3, int nsp, double ms0, double ms1,
                                                       const double* __restrict__ v1d,
+                                                      const double* __restrict__ v2d,
+                                                      const double* __restrict__ v3d,
                                                       const double* __restrict__ h, double w,
                                                       double* __restrict__ mom) {
   __shared__ double sh[4 * 4];
   const int64_t c = blockIdx.x;  // (cell, species) row
   const double ms = (c % nsp) == 0 ? ms0 : ms1;
-  const int nn = n * n;
+  const int d23 = d2 * d3, n3 = n * d23;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
   for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-    const double v1 = v1d[v / nn], v2 = v1d[(v / n) % n], v3 = v1d[v % n];
+    const double v1 = v1d[v / d23], v2 = v2d[(v / d3) % d2], v3 = v3d[v % d3];
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
     const double x = w * h[c * n3 + v];
     m[0] += v3 * x;
@@ -856,10 +891,10 @@ __global__ __launch_bounds__(64) void diffusion1d_mix_kernel(DiffusionArgs a) {
 __global__ __launch_bounds__(256) void sweep2d_kernel(Sweep2DArgs a) {
   const int cs = blockIdx.y;
   if (a.case_active && !a.case_active[cs]) return;
-  const int n = a.n, hn = n / 2, n3 = a.n3;
+  const int n = a.n, hn = n / 2, n3 = a.n3, d3 = a.d3;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= hn * hn * n) return;
-  const int jq1 = t / (hn * n), jq2 = (t / n) % hn, j3 = t % n;
+  if (t >= hn * hn * d3) return;
+  const int jq1 = t / (hn * d3), jq2 = (t / d3) % hn, j3 = t % d3;
   const int n1 = a.n1[cs], n2 = a.n2[cs];
   const int64_t g0 = a.grid_off[cs];
   const double del = a.delta_case[cs];
@@ -867,9 +902,9 @@ __global__ __launch_bounds__(256) void sweep2d_kernel(Sweep2DArgs a) {
     const int s1 = (q & 1) ? -1 : 1, s2 = (q & 2) ? -1 : 1;
     const int j1 = s1 > 0 ? hn + jq1 : hn - 1 - jq1;
     const int j2 = s2 > 0 ? hn + jq2 : hn - 1 - jq2;
-    const int v = (j1 * n + j2) * n + j3;
-    const int vm1 = ((n - 1 - j1) * n + j2) * n + j3;
-    const int vm2 = (j1 * n + (n - 1 - j2)) * n + j3;
+    const int v = (j1 * n + j2) * d3 + j3;
+    const int vm1 = ((n - 1 - j1) * n + j2) * d3 + j3;
+    const int vm2 = (j1 * n + (n - 1 - j2)) * d3 + j3;
     const double av1 = fabs(a.v1d[j1]), av2 = fabs(a.v1d[j2]);
     const double dnu = del * a.nu[v];
     const int sg1 = s1 > 0 ? 0 : 1, sg2 = s2 > 0 ? 0 : 1;
@@ -903,17 +938,18 @@ __global__ __launch_bounds__(256) void sweep2d_kernel(Sweep2DArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void moments2d_kernel(int n, int n3, const double* __restrict__ v1d,
+__global__ __launch_bounds__(256) void moments2d_kernel(int n, int d3, const double* __restrict__ v1d,
+                                                        const double* __restrict__ v3d,
                                                         const double* __restrict__ h, double w,
                                                         const int32_t* __restrict__ active,
                                                         double* __restrict__ mom) {
   __shared__ double sh[4 * 7];
   const int64_t c = blockIdx.x;
   if (active && !active[c]) return;
-  const int nn = n * n;
+  const int nd3 = n * d3, n3 = n * nd3;
   double m[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-    const double v1 = v1d[v / nn], v2 = v1d[(v / n) % n], v3 = v1d[v % n];
+    const double v1 = v1d[v / nd3], v2 = v1d[(v / d3) % n], v3 = v3d[v % d3];
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
     const double x = w * h[c * n3 + v];
     m[0] += v3 * x;
@@ -1153,6 +1189,16 @@ hipError_t launch_assemble(int n, int T, const double* X, const double* Y, const
   return hipGetLastError();
 }
 
+hipError_t launch_reduce_operator(const double* op, int64_t ld, double* red, int nsp, int n, int parity,
+                                  hipStream_t s) {
+  const int d2 = parity == 2 ? n / 2 : n, d3 = n / 2;
+  const int64_t ldr = static_cast<int64_t>(nsp) * n * d2 * d3;
+  const int64_t count = ldr * ldr;
+  hipLaunchKernelGGL(reduce_operator_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, op,
+                     ld, red, nsp, n, parity);
+  return hipGetLastError();
+}
+
 hipError_t launch_convert_f32(const double* op, float* out, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(convert_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, op, out, count);
   return hipGetLastError();
@@ -1211,11 +1257,12 @@ hipError_t launch_reduce_partials(const double* part, int W, int64_t n_cells, do
   return hipGetLastError();
 }
 
-hipError_t launch_moments(int n, int n3, int nsp, const double* mass_ratio, int64_t n_rows, const double* v1d,
-                          const double* h, double w, double* mom, hipStream_t s) {
+hipError_t launch_moments(int n, int d2, int d3, int nsp, const double* mass_ratio, int64_t n_rows,
+                          const double* v1d, const double* v2d, const double* v3d, const double* h, double w,
+                          double* mom, hipStream_t s) {
   const double m0 = mass_ratio ? mass_ratio[0] : 1.0, m1 = mass_ratio && nsp > 1 ? mass_ratio[1] : 1.0;
-  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>(n_rows)), dim3(256), 0, s, n, n3, nsp, m0, m1, v1d,
-                     h, w, mom);
+  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>(n_rows)), dim3(256), 0, s, n, d2, d3, nsp, m0, m1,
+                     v1d, v2d, v3d, h, w, mom);
   return hipGetLastError();
 }
 
@@ -1230,15 +1277,15 @@ hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
 
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   const int hn = a.n / 2;
-  const int count = hn * hn * a.n;
+  const int count = hn * hn * a.d3;
   dim3 grid((count + 255) / 256, a.n_cases);
   hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_moments2d(int n, int n3, int64_t n_cells, const double* v1d, const double* h,
+hipError_t launch_moments2d(int n, int d3, int64_t n_cells, const double* v1d, const double* v3d, const double* h,
                             double w, const int32_t* cell_active, double* mom, hipStream_t s) {
-  hipLaunchKernelGGL(moments2d_kernel, dim3(static_cast<unsigned>(n_cells)), dim3(256), 0, s, n, n3, v1d, h,
+  hipLaunchKernelGGL(moments2d_kernel, dim3(static_cast<unsigned>(n_cells)), dim3(256), 0, s, n, d3, v1d, v3d, h,
                      w, cell_active, mom);
   return hipGetLastError();
 }

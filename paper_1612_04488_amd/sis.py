@@ -41,7 +41,7 @@ class VelocityDesc(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("visc_index", ctypes.c_double),
                 ("n_threads", ctypes.c_int32), ("n_species", ctypes.c_int32),
                 ("mass", ctypes.c_double * 2), ("diam", ctypes.c_double * 2),
-                ("chi", ctypes.c_double * 2), ("m_rho", ctypes.c_int32)]
+                ("chi", ctypes.c_double * 2), ("m_rho", ctypes.c_int32), ("parity", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -53,7 +53,8 @@ class PlanInfo(ctypes.Structure):
                 ("operator_bytes", ctypes.c_int64), ("plan_seconds_host", ctypes.c_double),
                 ("plan_seconds_device", ctypes.c_double), ("n_species", ctypes.c_int32),
                 ("n_dof", ctypes.c_int32), ("nubar_b", ctypes.c_double),
-                ("viscosity_ratio", ctypes.c_double), ("flow_factor", ctypes.c_double)]
+                ("viscosity_ratio", ctypes.c_double), ("flow_factor", ctypes.c_double),
+                ("parity", ctypes.c_int32), ("n_vel", ctypes.c_int32)]
 
 
 class GeometryDesc(ctypes.Structure):
@@ -160,11 +161,13 @@ def _stream(stream):
 
 
 def velocity_desc(n_v, l_v=6.0, n_pad=0, m_angle=6, kernel="hs", visc_index=0.81,
-                  r_trunc=0.0, n_threads=0, mixture=None):
+                  r_trunc=0.0, n_threads=0, mixture=None, parity=0):
     """mixture: None (one gas) or dict(masses=(m_A, m_B), diameters=(d_A, d_B),
-    chi=(chi_A, chi_B), m_rho=16) for a binary hard-sphere mixture."""
+    chi=(chi_A, chi_B), m_rho=16) for a binary hard-sphere mixture.
+    parity: 0 full grid, 1 store v3 > 0 (odd in v3), 2 store v2, v3 > 0 (planar)."""
     k = KERNEL_HARD_SPHERE if kernel == "hs" else KERNEL_IPL
     d = VelocityDesc(n_v, l_v, n_pad, m_angle, r_trunc, k, visc_index, n_threads)
+    d.parity = int(parity)
     if mixture is not None:
         d.n_species = 2
         d.mass[:] = [float(x) for x in mixture["masses"]]
@@ -199,16 +202,18 @@ class Plan:
     """Velocity grid + assembled fast-spectral operator on the current device."""
 
     def __init__(self, n_v, l_v=6.0, n_pad=0, m_angle=6, kernel="hs", visc_index=0.81,
-                 r_trunc=0.0, n_threads=0, stream=None, mixture=None):
+                 r_trunc=0.0, n_threads=0, stream=None, mixture=None, parity=0):
         self.desc = velocity_desc(n_v, l_v, n_pad, m_angle, kernel, visc_index, r_trunc, n_threads,
-                                  mixture)
+                                  mixture, parity)
         h = ctypes.c_void_p()
         check(lib().sis_plan_create(ctypes.byref(self.desc), _stream(stream), ctypes.byref(h)))
         self.handle = h
         self.n_v = n_v
         self.n3 = n_v ** 3
         self.n_species = 2 if mixture is not None else 1
-        self.n_dof = self.n_species * self.n3
+        self.parity = int(parity)
+        self.n_vel = n_v * (n_v // 2 if parity == 2 else n_v) * (n_v // 2 if parity else n_v)
+        self.n_dof = self.n_species * self.n_vel
 
     def close(self):
         if getattr(self, "handle", None):
@@ -230,13 +235,13 @@ class Plan:
     def tables(self, operator=False):
         import numpy as np
         ns = self.n_species
-        v1d, feq, nu = np.zeros(self.n_v), np.zeros(ns * self.n3), np.zeros(ns * self.n3)
+        v1d, feq, nu = np.zeros(self.n_v), np.zeros(ns * self.n_vel), np.zeros(ns * self.n_vel)
         op = np.zeros((self.n_dof, self.n_dof)) if operator else None
         check(lib().sis_plan_tables(self.handle, v1d.ctypes.data_as(_P), feq.ctypes.data_as(_P),
                                     nu.ctypes.data_as(_P),
                                     op.ctypes.data_as(_P) if operator else None))
         if ns > 1:
-            feq, nu = feq.reshape(ns, self.n3), nu.reshape(ns, self.n3)
+            feq, nu = feq.reshape(ns, self.n_vel), nu.reshape(ns, self.n_vel)
         return dict(v1d=v1d, feq=feq, nu=nu, op=op)
 
     def set_precision(self, precision, stream=None):

@@ -119,8 +119,9 @@ def _planar_batch(n_v, l_v, m, xs, deltas, flows):
     return p, geom
 
 
-def test_sweep_and_moments_parity_ragged_batch():
-    n_v, l_v, m = 16, 6.0, 6
+@pytest.mark.parametrize("n_v,l_v,m", [(16, 6.0, 6), (6, 4.0, 2)])
+def test_sweep_and_moments_parity_ragged_batch(n_v, l_v, m):
+    """(6^3: 108 velocity pairs, so the sweep's last waves hold only padding lanes)"""
     xs = [inputs.nodes_uniform(16), inputs.nodes_tanh(12), inputs.nodes_smoothstep(7),
           inputs.nodes_uniform(1)]
     deltas = [1.0, 10.0, 0.0, 3.0]
