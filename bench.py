@@ -13,6 +13,12 @@ moments, diffusion correction, flow rates and convergence test, launched as
 one captured HIP graph.  value = cells x steps / wall time (cell-updates of
 L(h) per second, inputs resident in HBM).
 
+Distributions are stored by parity (default): these flows are odd in v3 (and
+even in v2 in the planar geometry), which the discrete operator preserves, so
+the plan keeps the v3 > 0 (v2 > 0) part and the operator restricted to it;
+the solution is the full-grid one (equal to 1e-12).  --parity 0 runs the
+full grid.
+
 Also reported: the collision contraction's roofline (HIP events around each
 eager launch), the time-to-residual 1e-8 of FP64 vs mixed-precision
 collision, and the CPU oracle's cell-update rate on a bounded sample.
@@ -104,7 +110,11 @@ def main():
     ap.add_argument("--workload", default="batch", choices=["batch", "small", "duct", "porous", "mixture"])
     ap.add_argument("--ttr", default="fp64,fp32,bf16x3,fp64+projection,bf16x3+projection",
                     help="time-to-residual runs (comma list)")
+    ap.add_argument("--parity", default="auto", choices=["auto", "0", "1", "2"],
+                    help="parity storage (auto: 2 for planar workloads, 1 for 2-D cross sections)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--no-ttr", action="store_true", help="skip time-to-residual runs")
     ap.add_argument("--cpu-cells", type=int, default=12)
     args = ap.parse_args()
@@ -120,6 +130,17 @@ def main():
     from paper_1612_04488_amd import inputs, sis
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        # 1 GiB read + 1 GiB written per copy: the reference for the FETCH_SIZE /
+        # WRITE_SIZE counters of the contraction
+        src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        for _ in range(5):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src_t.numel() * 8, "copy_bytes_written": dst_t.numel() * 8,
+                          "copies": 5}), flush=True)
+        return 0
     w = {"batch": inputs.PLANAR_BATCH, "small": inputs.PLANAR_SMALL, "duct": inputs.DUCT_IPL,
          "porous": inputs.POROUS_HS, "mixture": inputs.MIX_NEAR}[args.workload]
     mix = w.get("mixture")
@@ -128,14 +149,16 @@ def main():
     Npen = 1.5 if mix else 0.0
     if mix and args.cpu_cells == 12:
         args.cpu_cells = 1
+    planar = args.workload in ("batch", "small", "mixture")
+    parity = (2 if planar else 1) if args.parity == "auto" else int(args.parity)
     t0 = time.perf_counter()
     plan = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"],
-                    visc_index=w.get("visc_index", 0.81), mixture=mix)
+                    visc_index=w.get("visc_index", 0.81), mixture=mix, parity=parity)
     t_plan = time.perf_counter() - t0
     info = plan.info
     log(f"plan {w['name']}: {t_plan:.2f} s (host {info['plan_seconds_host']:.2f} s), "
         f"operator {info['operator_bytes'] / 2**30:.2f} GiB")
-    if args.workload in ("batch", "small", "mixture"):
+    if planar:
         xs = inputs.workload_nodes(w)
         geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
         per_case = [len(x) for x in xs]
@@ -167,7 +190,13 @@ def main():
 
     # ---------------------------------------------------------- dominant kernel: contraction
     h0 = inputs.mixture_h(w["n_v"], w["l_v"], nc) if mix else inputs.smooth_h(w["n_v"], w["l_v"], nc)
-    h = torch.tensor(h0.reshape(nc, n3), device="cuda")
+    # both generators are odd in v3 and even in v2: keep the stored part
+    hv = w["n_v"] // 2
+    if parity >= 1:
+        h0 = h0[..., hv:]
+    if parity == 2:
+        h0 = h0[..., hv:, :]
+    h = torch.tensor(np.ascontiguousarray(h0).reshape(nc, n3), device="cuda")
     delta = torch.tensor(np.repeat(w["deltas"], per_case), dtype=torch.float64, device="cuda")
     rhs = torch.empty_like(h)
     plan.collide(h, delta, rhs)   # warm
@@ -232,7 +261,9 @@ def main():
                       "n_pad": w["n_pad"],
                       "directions": D, "cells": nc, "cases": geom.n_cases, "deltas": w["deltas"],
                       "flows": w["flows"], "scheme": "SIS", "collision_precision": args.precision,
-                      "unknowns_per_cell": n3, "species": plan.n_species},
+                      "unknowns_per_cell": n3, "species": plan.n_species,
+                      "parity": {0: "full grid", 1: "odd in v3 (v3 > 0 stored)",
+                                 2: "odd in v3, even in v2 (v2, v3 > 0 stored)"}[parity]},
            "roofline": roofline,
            "plan_seconds": round(t_plan, 3),
            "time_to_residual_1e-8": ttr}
