@@ -883,18 +883,27 @@ __global__ __launch_bounds__(64) void diffusion1d_mix_kernel(DiffusionArgs a) {
 }
 
 // ------------------------------------------------------------------ 2-D sweep
-// One thread per velocity quadruple (+-|v1|, +-|v2|, v3) of one case; the
-// quadrants are swept in the order (+,+), (-,+), (+,-), (-,-), rows in the
-// v2 direction, cells in the v1 direction.  Upwind references read the
-// sweep buffer: cells already updated in this quadrant, mirror ghosts of an
-// earlier quadrant, or (periodic wrap) the previous iterate.
-__global__ __launch_bounds__(256) void sweep2d_kernel(Sweep2DArgs a) {
+// One workgroup per (case, group of kSweepV velocity quadruples (+-|v1|, +-|v2|, v3)).
+// The quadrants are swept in the order (+,+), (-,+), (+,-), (-,-).  Within a
+// quadrant every upwind reference of a cell lies on an earlier anti-diagonal of
+// the sweep order (ii + jj smaller), mirror ghosts read an earlier quadrant and
+// the wrapped periodic references read later anti-diagonals (the previous
+// iterate), so the anti-diagonals are processed in order with a workgroup
+// barrier between them and the cells of one anti-diagonal in parallel: the
+// values read are exactly those of the row-by-row sweep.
+constexpr int kSweepV = 4;       // velocity quadruples per workgroup
+constexpr int kSweepThreads = 256;
+
+__global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
   const int cs = blockIdx.y;
-  if (a.case_active && !a.case_active[cs]) return;
+  if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int n = a.n, hn = n / 2, n3 = a.n3, d3 = a.d3;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= hn * hn * d3) return;
+  const int quads = hn * hn * d3;
+  const int tq = blockIdx.x * kSweepV + threadIdx.x % kSweepV;
+  const bool vvalid = tq < quads;
+  const int t = vvalid ? tq : 0;
   const int jq1 = t / (hn * d3), jq2 = (t / d3) % hn, j3 = t % d3;
+  const int slot = threadIdx.x / kSweepV, slots = kSweepThreads / kSweepV;
   const int n1 = a.n1[cs], n2 = a.n2[cs];
   const int64_t g0 = a.grid_off[cs];
   const double del = a.delta_case[cs];
@@ -908,32 +917,39 @@ __global__ __launch_bounds__(256) void sweep2d_kernel(Sweep2DArgs a) {
     const double av1 = fabs(a.v1d[j1]), av2 = fabs(a.v1d[j2]);
     const double dnu = del * a.nu[v];
     const int sg1 = s1 > 0 ? 0 : 1, sg2 = s2 > 0 ? 0 : 1;
-    for (int jj = 0; jj < n2; ++jj) {
-      const int j = s2 > 0 ? jj : n2 - 1 - jj;
-      for (int ii = 0; ii < n1; ++ii) {
-        const int i = s1 > 0 ? ii : n1 - 1 - ii;
-        const int cell = a.gcell[g0 + static_cast<int64_t>(i) * n2 + j];
-        if (cell < 0) continue;
-        const int64_t o1 = (static_cast<int64_t>(cell) * 2 + 0) * 2 + sg1;
-        const int64_t o2 = (static_cast<int64_t>(cell) * 2 + 1) * 2 + sg2;
-        double acc = a.rhs[static_cast<int64_t>(cell) * n3 + v];
-        const double c1[3] = {a.coef[o1 * 3], a.coef[o1 * 3 + 1], a.coef[o1 * 3 + 2]};
-        const double c2[3] = {a.coef[o2 * 3], a.coef[o2 * 3 + 1], a.coef[o2 * 3 + 2]};
+    for (int d = 0; d < n1 + n2 - 1; ++d) {
+      const int lo = max(0, d - (n2 - 1)), hi = min(d, n1 - 1);   // ii range of the anti-diagonal
+      for (int c0 = lo; c0 <= hi; c0 += slots) {
+        const int ii = c0 + slot;
+        if (vvalid && ii <= hi) {
+          const int jj = d - ii;
+          const int i = s1 > 0 ? ii : n1 - 1 - ii;
+          const int j = s2 > 0 ? jj : n2 - 1 - jj;
+          const int cell = a.gcell[g0 + static_cast<int64_t>(i) * n2 + j];
+          if (cell >= 0) {
+            const int64_t o1 = (static_cast<int64_t>(cell) * 2 + 0) * 2 + sg1;
+            const int64_t o2 = (static_cast<int64_t>(cell) * 2 + 1) * 2 + sg2;
+            double acc = a.rhs[static_cast<int64_t>(cell) * n3 + v];
+            const double c1[3] = {a.coef[o1 * 3], a.coef[o1 * 3 + 1], a.coef[o1 * 3 + 2]};
+            const double c2[3] = {a.coef[o2 * 3], a.coef[o2 * 3 + 1], a.coef[o2 * 3 + 2]};
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const int8_t k1 = a.kind[o1 * 2 + k];
-          if (k1) {
-            const int64_t r = a.ref[o1 * 2 + k];
-            acc -= av1 * c1[k + 1] * a.h[r * n3 + (k1 == 2 ? vm1 : v)];
-          }
-          const int8_t k2 = a.kind[o2 * 2 + k];
-          if (k2) {
-            const int64_t r = a.ref[o2 * 2 + k];
-            acc -= av2 * c2[k + 1] * a.h[r * n3 + (k2 == 2 ? vm2 : v)];
+            for (int k = 0; k < 2; ++k) {
+              const int8_t k1 = a.kind[o1 * 2 + k];
+              if (k1) {
+                const int64_t r = a.ref[o1 * 2 + k];
+                acc -= av1 * c1[k + 1] * a.h[r * n3 + (k1 == 2 ? vm1 : v)];
+              }
+              const int8_t k2 = a.kind[o2 * 2 + k];
+              if (k2) {
+                const int64_t r = a.ref[o2 * 2 + k];
+                acc -= av2 * c2[k + 1] * a.h[r * n3 + (k2 == 2 ? vm2 : v)];
+              }
+            }
+            a.h[static_cast<int64_t>(cell) * n3 + v] = acc / (dnu + av1 * c1[0] + av2 * c2[0]);
           }
         }
-        a.h[static_cast<int64_t>(cell) * n3 + v] = acc / (dnu + av1 * c1[0] + av2 * c2[0]);
       }
+      __syncthreads();
     }
   }
 }
@@ -1278,8 +1294,8 @@ hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   const int hn = a.n / 2;
   const int count = hn * hn * a.d3;
-  dim3 grid((count + 255) / 256, a.n_cases);
-  hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(256), 0, s, a);
+  dim3 grid((count + kSweepV - 1) / kSweepV, a.n_cases);
+  hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(kSweepThreads), 0, s, a);
   return hipGetLastError();
 }
 
