@@ -94,7 +94,9 @@ struct sis_plan {
   double* gram_inv = nullptr;   // [25]
   double cU = 0, cq = 0;        // U3, q3 of 2 v3 feq
   std::vector<double> h_v1d, h_feq, h_nu;
-  Scratch ws_acc, ws_part;
+  // scratch of eager compute calls (a solver state owns its own, fixed at creation,
+  // so that the buffers its captured graphs use are never reallocated)
+  Scratch ws_acc, ws_part, ws_x;  // split-K partials, sweep partials, low-precision cell operand
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   ~sis_plan() {
@@ -237,19 +239,36 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
                        const double* delta, const int32_t* flow, int project, double* rhs,
                        double* lh, double* amom, const int32_t* cell_active, hipStream_t s,
                        int precision = -1, int anchor_mode = 0, double* xref = nullptr,
-                       double* accref = nullptr) {
+                       double* accref = nullptr, Scratch* ws_acc = nullptr, Scratch* ws_x = nullptr) {
+  if (!ws_acc) ws_acc = &p->ws_acc;
+  if (!ws_x) ws_x = &p->ws_x;
   if (precision < 0) precision = p->precision;
   int tile, splits;
   choose_gemm(n_cells, p->ndof, &tile, &splits);
   double* acc = rhs;
   if (splits > 1) {
-    HIP_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * n_cells * p->ndof * sizeof(double)));
-    acc = static_cast<double*>(p->ws_acc.p);
+    HIP_TRY(ws_acc->ensure(static_cast<size_t>(splits) * n_cells * p->ndof * sizeof(double)));
+    acc = static_cast<double*>(ws_acc->p);
   }
   sis::GemmArgs g{};
   g.precision = precision;
   g.X = h;
   g.Xref = anchor_mode == 2 ? xref : nullptr;
+  if (precision != SIS_PREC_FP64) {
+    // the cell operand (minus the anchor) rounded once per launch: 4 bytes per entry
+    const int64_t cnt = n_cells * static_cast<int64_t>(p->ndof);
+    HIP_TRY(ws_x->ensure(static_cast<size_t>(cnt) * 4));
+    if (precision == SIS_PREC_BF16X3) {
+      uint16_t* hx = static_cast<uint16_t*>(ws_x->p);
+      HIP_TRY(sis::launch_split_x(h, g.Xref, cnt, hx, hx + cnt, s));
+      g.Xh = hx;
+      g.Xl = hx + cnt;
+    } else {
+      float* fx = static_cast<float*>(ws_x->p);
+      HIP_TRY(sis::launch_convert_x_f32(h, g.Xref, cnt, fx, s));
+      g.X32 = fx;
+    }
+  }
   g.op64 = p->op;
   g.op32 = p->op32;
   g.ophi = p->ophi;
@@ -314,7 +333,9 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
 }
 
 sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, double* mom,
-                     const int32_t* case_active, hipStream_t s, const int32_t* cell_active = nullptr) {
+                     const int32_t* case_active, hipStream_t s, const int32_t* cell_active = nullptr,
+                     Scratch* ws_part = nullptr) {
+  if (!ws_part) ws_part = &p->ws_part;
   if (g->two_d) {
     sis::Sweep2DArgs a{};
     a.n = p->n;
@@ -342,7 +363,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     return SIS_OK;
   }
   const int W = (p->nv / 2 + 63) / 64;
-  HIP_TRY(p->ws_part.ensure(static_cast<size_t>(g->n_cells) * p->nsp * 8 * W * sizeof(double)));
+  HIP_TRY(ws_part->ensure(static_cast<size_t>(g->n_cells) * p->nsp * 8 * W * sizeof(double)));
   sis::SweepArgs a{};
   a.n = p->n;
   a.n3 = p->nv;
@@ -361,7 +382,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
   a.nu = p->nu;
   a.rhs = rhs;
   a.h = h;
-  a.part = static_cast<double*>(p->ws_part.p);
+  a.part = static_cast<double*>(ws_part->p);
   a.W = W;
   a.case_active = case_active;
   a.w = p->wr;
@@ -1174,6 +1195,7 @@ struct sis_state {
          *q = nullptr, *state = nullptr;
   int32_t *iters = nullptr, *cact = nullptr, *lact = nullptr;
   double *xref = nullptr, *accref = nullptr;   // FP64 anchor of the defect correction
+  Scratch ws_acc, ws_part, ws_x;               // sized at creation, used by the captured graphs
   int precision = 0, refresh = 1;
   hipStream_t cap = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};    // [0] refresh / plain, [1] incremental
@@ -1208,9 +1230,9 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
   }
   if (sis_status st = run_collide(p, g->n_cells, b->h, sis ? b->dU : nullptr, g->delta_cell,
                                   g->flow_cell, b->o.project, b->rhs, nullptr, b->amom, b->lact, s,
-                                  prec, mode, b->xref, b->accref))
+                                  prec, mode, b->xref, b->accref, &b->ws_acc, &b->ws_x))
     return st;
-  if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s, b->lact)) return st;
+  if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s, b->lact, &b->ws_part)) return st;
   if (g->two_d) {
     sis::Diff2DArgs a = diff2d_args(p, g, b->mom, b->amom, b->Npen);
     a.sis = sis ? 1 : 0;
@@ -1328,9 +1350,10 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   {
     int tile, splits;
     choose_gemm(nc, n3, &tile, &splits);
-    if (splits > 1) ST_TRY(p->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
+    if (splits > 1) ST_TRY(b->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
+    if (p->precision != SIS_PREC_FP64) ST_TRY(b->ws_x.ensure(static_cast<size_t>(nc) * n3 * 4));
     const int W = (p->nv / 2 + 63) / 64;
-    if (!g->two_d) ST_TRY(p->ws_part.ensure(static_cast<size_t>(nc) * nsp * 8 * W * 8));
+    if (!g->two_d) ST_TRY(b->ws_part.ensure(static_cast<size_t>(nc) * nsp * 8 * W * 8));
   }
   hipStream_t s = stream;
   if (o->use_graph) {

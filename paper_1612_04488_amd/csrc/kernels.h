@@ -29,8 +29,11 @@ hipError_t launch_split_bf16(const double* op, uint16_t* hi, uint16_t* lo, int64
 // are written as double for every precision.
 struct GemmArgs {
   int precision;
-  const double* X;
+  const double* X;         // FP64 cell operand (precision 0, and the FP32 path's source)
   const double* Xref;      // null, or anchor: the contraction is applied to X - Xref
+  const uint16_t* Xh;      // precision 2: X - Xref split into bf16 hi, lo [M][K] (launch_split_x)
+  const uint16_t* Xl;
+  const float* X32;        // precision 1: X - Xref rounded to FP32 [M][K] (launch_convert_x_f32)
   const double* op64;
   const float* op32;
   const uint16_t* ophi;
@@ -42,6 +45,10 @@ struct GemmArgs {
   int tile;          // tile configuration id (0 large, 1 small-M)
 };
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
+// x = X - Xref (Xref may be null) -> bf16 hi + lo, or -> FP32; count = M * K
+hipError_t launch_split_x(const double* X, const double* Xref, int64_t count, uint16_t* hi, uint16_t* lo,
+                          hipStream_t s);
+hipError_t launch_convert_x_f32(const double* X, const double* Xref, int64_t count, float* out, hipStream_t s);
 int gemm_k_per_split(int K, int splits);
 
 // Rows are (cell, species) pairs of n3 values: row = cell * nsp + species.  A row holds the

@@ -278,15 +278,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 // ------------------------------------------------------------------ FP32 MFMA GEMM
 // X is converted from double to float when staged; op is stored as float.
 template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_f32_kernel(const double* __restrict__ X,
-                                                       const double* __restrict__ Xref,
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ X,
                                                        const float* __restrict__ Op,
                                                        double* __restrict__ C, int64_t M, int N,
                                                        int K, int kps) {
   constexpr int BK = 32;
   constexpr int WAVES_N = BN / WN;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int A_LD = BM * BK / 2 / 256;   // double2 loads of X
+  constexpr int A_LD = BM * BK / 4 / 256;   // float4 loads of the (pre-rounded) cell operand
   constexpr int B_LD = BN * BK / 4 / 256;   // float4 loads of Op
   static_assert((BM / WM) * (BN / WN) == 4, "4 waves per workgroup");
   static_assert(A_LD >= 1 && B_LD >= 1, "tile too small");
@@ -301,24 +300,21 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const double* __restrict_
   const int kend = min(K, kbeg + kps);
   double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
 
-  double2 ra[A_LD];
+  float4 ra[A_LD];
   float4 rb[B_LD];
   auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
+      const int r = q / (BK / 4), kc = (q % (BK / 4)) * 4;
       const int64_t gm = m0 + r;
       const int gk = k0 + kc;
-      if (gm < M && gk < kend) {
-        ra[i] = *reinterpret_cast<const double2*>(X + gm * K + gk);
-        if (Xref) {
-          const double2 xr = *reinterpret_cast<const double2*>(Xref + gm * K + gk);
-          ra[i].x -= xr.x;
-          ra[i].y -= xr.y;
-        }
+      if (gm < M && gk + 3 < kend) {
+        ra[i] = *reinterpret_cast<const float4*>(X + gm * K + gk);
       } else {
-        ra[i] = make_double2(0.0, 0.0);
+        float t[4];
+        for (int e = 0; e < 4; ++e) t[e] = (gm < M && gk + e < kend) ? X[gm * K + gk + e] : 0.0f;
+        ra[i] = make_float4(t[0], t[1], t[2], t[3]);
       }
     }
 #pragma unroll
@@ -341,9 +337,11 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const double* __restrict_
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
-      As[buf][kc][r] = static_cast<float>(ra[i].x);
-      As[buf][kc + 1][r] = static_cast<float>(ra[i].y);
+      const int r = q / (BK / 4), kc = (q % (BK / 4)) * 4;
+      As[buf][kc][r] = ra[i].x;
+      As[buf][kc + 1][r] = ra[i].y;
+      As[buf][kc + 2][r] = ra[i].z;
+      As[buf][kc + 3][r] = ra[i].w;
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
@@ -401,29 +399,33 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const double* __restrict_
 }
 
 // ------------------------------------------------------------------ 3xBF16 MFMA GEMM
-// x ~ xh + xl, op ~ oh + ol (bf16 pairs); acc += xh*oh + xh*ol + xl*oh on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+// x ~ xh + xl, op ~ oh + ol (bf16 pairs); acc += xl*oh + xh*ol + xh*oh on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Both operands arrive as
+// bf16 hi/lo arrays contiguous in k (the cell operand is split once per launch
+// by split_x_kernel instead of once per output tile).  k-stage of 64 staged
+// through one LDS buffer per operand half; the next stage is prefetched into
+// registers while the current one feeds the MFMAs.
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const double* __restrict__ X,
-                                                          const double* __restrict__ Xref,
+__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __restrict__ Xh,
+                                                          const uint16_t* __restrict__ Xl,
                                                           const uint16_t* __restrict__ Oh,
                                                           const uint16_t* __restrict__ Ol,
                                                           double* __restrict__ C, int64_t M,
                                                           int N, int K, int kps) {
-  constexpr int BK = 32;                      // one MFMA k-step
+  constexpr int BK = 64;                      // two MFMA k-steps per stage
   constexpr int WAVES_N = BN / WN;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int A_LD = BM * BK / 2 / 256;     // double2 loads of X
-  constexpr int B_LD = BN * BK / 8 / 256;     // 8 x bf16 (16 B) loads of each op half
+  constexpr int CH = BK / 8;                  // 16-byte chunks per row and stage
+  constexpr int A_LD = (BM * CH + 255) / 256;
+  constexpr int B_LD = (BN * CH + 255) / 256;
   static_assert((BM / WM) * (BN / WN) == 4, "4 waves per workgroup");
-  static_assert(A_LD >= 1 && B_LD >= 1, "tile too small");
-  // LDS rows hold the 32 k-values of one m (or n) contiguously (+pad) so a lane
-  // reads its 8 consecutive k values as one 16-byte vector.
+  // rows hold the 64 k-values of one m (or n) contiguously (+16 B pad); a lane
+  // reads its 8 consecutive k values as one 16-byte vector
   constexpr int RS = BK + 8;
-  __shared__ uint16_t Ah[2][BM][RS], Al[2][BM][RS];
-  __shared__ uint16_t Bh[2][BN][RS], Bl[2][BN][RS];
+  __shared__ uint16_t sA[2][BM][RS];
+  __shared__ uint16_t sB[2][BN][RS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
@@ -433,67 +435,52 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const double* __restri
   const int kend = min(K, kbeg + kps);
   double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
 
-  double2 ra[A_LD];
-  uint4 rbh[B_LD], rbl[B_LD];
+  uint4 ra[2][A_LD], rb[2][B_LD];
+  auto load16 = [&](const uint16_t* base, int64_t row, int64_t rows, int gk) -> uint4 {
+    if (row < rows && gk + 7 < kend) return *reinterpret_cast<const uint4*>(base + row * K + gk);
+    uint16_t t[8];
+    for (int e = 0; e < 8; ++e) t[e] = (row < rows && gk + e < kend) ? base[row * K + gk + e] : 0;
+    return make_uint4(t[0] | (uint32_t(t[1]) << 16), t[2] | (uint32_t(t[3]) << 16), t[4] | (uint32_t(t[5]) << 16),
+                      t[6] | (uint32_t(t[7]) << 16));
+  };
   auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
-      const int64_t gm = m0 + r;
-      const int gk = k0 + kc;
-      if (gm < M && gk < kend) {
-        ra[i] = *reinterpret_cast<const double2*>(X + gm * K + gk);
-        if (Xref) {
-          const double2 xr = *reinterpret_cast<const double2*>(Xref + gm * K + gk);
-          ra[i].x -= xr.x;
-          ra[i].y -= xr.y;
-        }
-      } else {
-        ra[i] = make_double2(0.0, 0.0);
+      if (q < BM * CH) {
+        const int r = q / CH, kc = (q % CH) * 8;
+        ra[0][i] = load16(Xh, m0 + r, M, k0 + kc);
+        ra[1][i] = load16(Xl, m0 + r, M, k0 + kc);
       }
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (BK / 8), kc = (q % (BK / 8)) * 8;
-      const int gn = n0 + r;
-      const int gk = k0 + kc;
-      if (gn < N && gk + 7 < kend) {
-        rbh[i] = *reinterpret_cast<const uint4*>(Oh + static_cast<int64_t>(gn) * K + gk);
-        rbl[i] = *reinterpret_cast<const uint4*>(Ol + static_cast<int64_t>(gn) * K + gk);
-      } else {
-        uint16_t th[8], tl[8];
-        for (int e = 0; e < 8; ++e) {
-          const bool ok = gn < N && gk + e < kend;
-          th[e] = ok ? Oh[static_cast<int64_t>(gn) * K + gk + e] : 0;
-          tl[e] = ok ? Ol[static_cast<int64_t>(gn) * K + gk + e] : 0;
-        }
-        rbh[i] = make_uint4(th[0] | (uint32_t(th[1]) << 16), th[2] | (uint32_t(th[3]) << 16),
-                            th[4] | (uint32_t(th[5]) << 16), th[6] | (uint32_t(th[7]) << 16));
-        rbl[i] = make_uint4(tl[0] | (uint32_t(tl[1]) << 16), tl[2] | (uint32_t(tl[3]) << 16),
-                            tl[4] | (uint32_t(tl[5]) << 16), tl[6] | (uint32_t(tl[7]) << 16));
+      if (q < BN * CH) {
+        const int r = q / CH, kc = (q % CH) * 8;
+        rb[0][i] = load16(Oh, n0 + r, N, k0 + kc);
+        rb[1][i] = load16(Ol, n0 + r, N, k0 + kc);
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&]() {
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
-      const double x0 = ra[i].x, x1 = ra[i].y;
-      const uint16_t h0 = bf16_rne(static_cast<float>(x0)), h1 = bf16_rne(static_cast<float>(x1));
-      const uint16_t l0 = bf16_rne(static_cast<float>(x0 - static_cast<double>(bf16_to_f32(h0))));
-      const uint16_t l1 = bf16_rne(static_cast<float>(x1 - static_cast<double>(bf16_to_f32(h1))));
-      *reinterpret_cast<uint32_t*>(&Ah[buf][r][kc]) = h0 | (uint32_t(h1) << 16);
-      *reinterpret_cast<uint32_t*>(&Al[buf][r][kc]) = l0 | (uint32_t(l1) << 16);
+      if (q < BM * CH) {
+        const int r = q / CH, kc = (q % CH) * 8;
+        *reinterpret_cast<uint4*>(&sA[0][r][kc]) = ra[0][i];
+        *reinterpret_cast<uint4*>(&sA[1][r][kc]) = ra[1][i];
+      }
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (BK / 8), kc = (q % (BK / 8)) * 8;
-      *reinterpret_cast<uint4*>(&Bh[buf][r][kc]) = rbh[i];
-      *reinterpret_cast<uint4*>(&Bl[buf][r][kc]) = rbl[i];
+      if (q < BN * CH) {
+        const int r = q / CH, kc = (q % CH) * 8;
+        *reinterpret_cast<uint4*>(&sB[0][r][kc]) = rb[0][i];
+        *reinterpret_cast<uint4*>(&sB[1][r][kc]) = rb[1][i];
+      }
     }
   };
 
@@ -506,36 +493,41 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const double* __restri
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
     gload(kbeg);
-    sstore(0);
+    sstore();
   }
   __syncthreads();
   // operand layout of the 16x16x32 bf16 MFMA: lane l holds row (l % 16),
   // k = 8 * (l / 16) .. + 7
   const int rr = lane & 15, kq = (lane >> 4) * 8;
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
     if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
-    v8bf ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      ah[i] = *reinterpret_cast<const v8bf*>(&Ah[cur][wm + i * 16 + rr][kq]);
-      al[i] = *reinterpret_cast<const v8bf*>(&Al[cur][wm + i * 16 + rr][kq]);
-    }
+    for (int ks = 0; ks < BK; ks += 32) {
+      v8bf ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      bh[j] = *reinterpret_cast<const v8bf*>(&Bh[cur][wn + j * 16 + rr][kq]);
-      bl[j] = *reinterpret_cast<const v8bf*>(&Bl[cur][wn + j * 16 + rr][kq]);
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < TM; ++i) {
+        ah[i] = *reinterpret_cast<const v8bf*>(&sA[0][wm + i * 16 + rr][ks + kq]);
+        al[i] = *reinterpret_cast<const v8bf*>(&sA[1][wm + i * 16 + rr][ks + kq]);
+      }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        bh[j] = *reinterpret_cast<const v8bf*>(&sB[0][wn + j * 16 + rr][ks + kq]);
+        bl[j] = *reinterpret_cast<const v8bf*>(&sB[1][wn + j * 16 + rr][ks + kq]);
       }
-    if (kt + 1 < nk) sstore(cur ^ 1);
-    __syncthreads();
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) {
+      __syncthreads();   // every wave is done reading the stage
+      sstore();
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -547,6 +539,25 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const double* __restri
         const int gn = n0 + wn + j * 16 + (lane & 15);
         if (gm < M && gn < N) Cz[gm * N + gn] = static_cast<double>(acc[i][j][r]);
       }
+}
+
+// Cell operand of the low-precision contractions, formed once per launch:
+// x = X - Xref (Xref null: X) split into bf16 hi + lo, or rounded to FP32.
+__global__ void split_x_kernel(const double* __restrict__ X, const double* __restrict__ Xref, int64_t count,
+                               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double x = Xref ? X[i] - Xref[i] : X[i];
+  const uint16_t h = bf16_rne(static_cast<float>(x));
+  hi[i] = h;
+  lo[i] = bf16_rne(static_cast<float>(x - static_cast<double>(bf16_to_f32(h))));
+}
+
+__global__ void convert_x_f32_kernel(const double* __restrict__ X, const double* __restrict__ Xref, int64_t count,
+                                     float* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  out[i] = static_cast<float>(Xref ? X[i] - Xref[i] : X[i]);
 }
 
 // ------------------------------------------------------------------ finish
@@ -1215,6 +1226,19 @@ hipError_t launch_reduce_operator(const double* op, int64_t ld, double* red, int
   return hipGetLastError();
 }
 
+hipError_t launch_split_x(const double* X, const double* Xref, int64_t count, uint16_t* hi, uint16_t* lo,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(split_x_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, X, Xref, count,
+                     hi, lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_x_f32(const double* X, const double* Xref, int64_t count, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(convert_x_f32_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, X, Xref,
+                     count, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_convert_f32(const double* op, float* out, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(convert_f32_kernel, dim3((count + 255) / 256), dim3(256), 0, s, op, out, count);
   return hipGetLastError();
@@ -1226,7 +1250,7 @@ hipError_t launch_split_bf16(const double* op, uint16_t* hi, uint16_t* lo, int64
 }
 
 int gemm_k_per_split(int K, int splits) {
-  const int unit = 32;  // multiple of every BK
+  const int unit = 64;  // multiple of every BK
   int kps = (K + splits - 1) / splits;
   kps = (kps + unit - 1) / unit * unit;
   return kps;
@@ -1243,15 +1267,17 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
     else
       hipLaunchKernelGGL((gemm_f64_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
   } else if (g.precision == 1) {
+    if (!g.X32) return hipErrorInvalidValue;
     if (g.tile == 0)
-      hipLaunchKernelGGL((gemm_f32_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.Xref, g.op32, g.acc, g.M, g.N, g.K, kps);
+      hipLaunchKernelGGL((gemm_f32_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
     else
-      hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.Xref, g.op32, g.acc, g.M, g.N, g.K, kps);
+      hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
   } else {
+    if (!g.Xh || !g.Xl) return hipErrorInvalidValue;
     if (g.tile == 0)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.Xref, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.Xh, g.Xl, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
     else
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.Xref, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.Xh, g.Xl, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
   }
   return hipGetLastError();
 }
