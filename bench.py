@@ -210,16 +210,19 @@ def main():
         plan.collide(h, delta, rhs)
     gemm_ms, launches = plan.timing_read()
     plan.timing(False)
+    tile_rows, splits, tuned = plan.contraction_config(nc, args.precision)
     avg_ms = gemm_ms / launches
     flops = 2.0 * n3 * n3 * nc
     executed = flops * (3 if args.precision == "bf16x3" else 1)
     achieved = executed / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    log(f"contraction: {avg_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s of {peak} peak")
+    log(f"contraction: {avg_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s of {peak} peak "
+        f"(tile {tile_rows}x128, split-K {splits}, autotuned {tuned})")
     tk = TRAFFIC_KIB.get((w["name"], parity, args.precision))
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": (tk[0] + tk[1]) * 1024.0 if tk else None,
                 "kernel": f"gemm_{args.precision}", "avg_launch_ms": round(avg_ms, 4),
+                "tile": f"{tile_rows}x128", "split_k": splits, "autotuned": tuned,
                 "flops_per_launch": executed,
                 "flops_per_cell_update": 2.0 * n3 * n3,
                 "fsm_fft_flops_per_cell_update": None}

@@ -344,6 +344,15 @@ sis_status sis_state_poll(sis_state_t state, int32_t* n_active, hipStream_t stre
 sis_status sis_state_results(sis_state_t state, sis_solve_result* result, hipStream_t stream);
 sis_status sis_state_destroy(sis_state_t state);
 
+/* Contraction configuration used for n_cells cells in `precision`: the
+ * autotuner (run on the first eager sis_collide of a shape and at
+ * sis_state_create, outside stream capture) times every (tile, split-K)
+ * candidate on the device and keeps the fastest; tile_rows is the cell-tile
+ * height (128, 64 or 32; the operator tile is 128), tuned = 0 if the default
+ * heuristic is in use.                                                      */
+sis_status sis_plan_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t precision,
+                                       int32_t* tile_rows, int32_t* splits, int32_t* tuned);
+
 /* Kernel timing of the collision contraction: while enabled, every eager
  * (non-graph) contraction launch on a plan is bracketed by HIP events on its
  * stream; sis_plan_timing_read synchronises and returns the summed

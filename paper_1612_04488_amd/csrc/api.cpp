@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "geom2d.h"
@@ -99,6 +101,8 @@ struct sis_plan {
   Scratch ws_acc, ws_part, ws_x;  // split-K partials, sweep partials, low-precision cell operand
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  // tuned contraction configuration per (cells, precision): tile id, split-K
+  std::map<std::pair<int64_t, int>, std::pair<int, int>> gemm_choice;
   ~sis_plan() {
     for (auto& e : events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     dfree(op); dfree(op32); dfree(ophi); dfree(oplo);
@@ -225,7 +229,8 @@ sis::TableDesc table_desc(const sis_velocity_desc* d) {
   return t;
 }
 
-// Choose tile and split-K for a contraction of M cells against the n3 x n3 operator.
+// Default tile and split-K for a contraction of M cells against the n3 x n3
+// operator: enough workgroups (>= 1024) to fill the chip.
 void choose_gemm(int64_t M, int n3, int* tile, int* splits) {
   *tile = M >= 256 ? 0 : 1;
   const int64_t bm = *tile == 0 ? 128 : 32;
@@ -233,6 +238,85 @@ void choose_gemm(int64_t M, int n3, int* tile, int* splits) {
   int s = 1;
   while (blocks * s < 1024 && s < 16 && n3 / (s * 2) >= 256) s *= 2;
   *splits = s;
+}
+
+// Cell operand of a low-precision contraction (x = X - Xref rounded once per launch).
+sis_status prepare_lowp_operand(sis_plan* p, int precision, int64_t n_cells, const double* h, const double* xref,
+                                Scratch* ws_x, sis::GemmArgs& g, hipStream_t s) {
+  if (precision == SIS_PREC_FP64) return SIS_OK;
+  const int64_t cnt = n_cells * static_cast<int64_t>(p->ndof);
+  HIP_TRY(ws_x->ensure(static_cast<size_t>(cnt) * 4));
+  if (precision == SIS_PREC_BF16X3) {
+    uint16_t* hx = static_cast<uint16_t*>(ws_x->p);
+    HIP_TRY(sis::launch_split_x(h, xref, cnt, hx, hx + cnt, s));
+    g.Xh = hx;
+    g.Xl = hx + cnt;
+  } else {
+    float* fx = static_cast<float*>(ws_x->p);
+    HIP_TRY(sis::launch_convert_x_f32(h, xref, cnt, fx, s));
+    g.X32 = fx;
+  }
+  return SIS_OK;
+}
+
+// Autotuner of the contraction: times every (tile, split-K) candidate on the
+// actual shape (two launches each after a warm-up, HIP events on `s`) and
+// keeps the fastest per (cells, precision) in the plan.  Not callable while
+// `s` is capturing.  Candidates whose split-K partials would exceed 4 GiB are
+// skipped.
+sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scratch* ws_acc, Scratch* ws_x,
+                     hipStream_t s) {
+  const auto key = std::make_pair(M, precision);
+  if (p->gemm_choice.count(key)) return SIS_OK;
+  sis::GemmArgs g{};
+  g.precision = precision;
+  g.X = h;
+  g.op64 = p->op;
+  g.op32 = p->op32;
+  g.ophi = p->ophi;
+  g.oplo = p->oplo;
+  g.M = M;
+  g.N = p->ndof;
+  g.K = p->ndof;
+  if (sis_status st = prepare_lowp_operand(p, precision, M, h, nullptr, ws_x, g, s)) return st;
+  int dt, ds;
+  choose_gemm(M, p->ndof, &dt, &ds);
+  std::pair<int, int> best(dt, ds);
+  float best_ms = 1e30f;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int tiles[3] = {0, 2, 1};
+  const int splits[6] = {1, 2, 3, 4, 6, 8};
+  hipError_t err = hipSuccess;
+  for (int ti = 0; ti < 3 && err == hipSuccess; ++ti)
+    for (int si = 0; si < 6 && err == hipSuccess; ++si) {
+      const int sp = splits[si];
+      if (sp > 1 && sis::gemm_k_per_split(p->ndof, sp) < 256) continue;
+      const double bytes = static_cast<double>(sp) * M * p->ndof * 8.0;
+      if (bytes > 4.0 * (1 << 30)) continue;
+      err = ws_acc->ensure(static_cast<size_t>(bytes));
+      if (err != hipSuccess) break;
+      g.acc = static_cast<double*>(ws_acc->p);
+      g.tile = tiles[ti];
+      g.splits = sp;
+      err = sis::launch_gemm(g, s);
+      if (err == hipSuccess) err = hipEventRecord(e0, s);
+      for (int r = 0; r < 2 && err == hipSuccess; ++r) err = sis::launch_gemm(g, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best = std::make_pair(g.tile, sp);
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(SIS_E_DEVICE, "contraction tuning: %s", hipGetErrorString(err));
+  p->gemm_choice[key] = best;
+  return SIS_OK;
 }
 
 sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const double* dU,
@@ -244,7 +328,13 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   if (!ws_x) ws_x = &p->ws_x;
   if (precision < 0) precision = p->precision;
   int tile, splits;
-  choose_gemm(n_cells, p->ndof, &tile, &splits);
+  const auto tuned = p->gemm_choice.find(std::make_pair(n_cells, precision));
+  if (tuned != p->gemm_choice.end()) {
+    tile = tuned->second.first;
+    splits = tuned->second.second;
+  } else {
+    choose_gemm(n_cells, p->ndof, &tile, &splits);
+  }
   double* acc = rhs;
   if (splits > 1) {
     HIP_TRY(ws_acc->ensure(static_cast<size_t>(splits) * n_cells * p->ndof * sizeof(double)));
@@ -254,21 +344,7 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   g.precision = precision;
   g.X = h;
   g.Xref = anchor_mode == 2 ? xref : nullptr;
-  if (precision != SIS_PREC_FP64) {
-    // the cell operand (minus the anchor) rounded once per launch: 4 bytes per entry
-    const int64_t cnt = n_cells * static_cast<int64_t>(p->ndof);
-    HIP_TRY(ws_x->ensure(static_cast<size_t>(cnt) * 4));
-    if (precision == SIS_PREC_BF16X3) {
-      uint16_t* hx = static_cast<uint16_t*>(ws_x->p);
-      HIP_TRY(sis::launch_split_x(h, g.Xref, cnt, hx, hx + cnt, s));
-      g.Xh = hx;
-      g.Xl = hx + cnt;
-    } else {
-      float* fx = static_cast<float*>(ws_x->p);
-      HIP_TRY(sis::launch_convert_x_f32(h, g.Xref, cnt, fx, s));
-      g.X32 = fx;
-    }
-  }
+  if (sis_status st = prepare_lowp_operand(p, precision, n_cells, h, g.Xref, ws_x, g, s)) return st;
   g.op64 = p->op;
   g.op32 = p->op32;
   g.ophi = p->ophi;
@@ -1128,6 +1204,12 @@ sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const dou
   if (!aligned16(h) || !aligned16(rhs_out)) return fail(SIS_E_INVALID, "h and rhs_out must be 16-byte aligned");
   if (h == rhs_out) return fail(SIS_E_INVALID, "rhs_out must not alias h");
   if (project && p->nsp != 1) return fail(SIS_E_UNSUPPORTED, "invariant projection is for one gas only");
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cs));
+    if (cs == hipStreamCaptureStatusNone)
+      if (sis_status st = tune_gemm(p, n_cells, p->precision, h, &p->ws_acc, &p->ws_x, stream)) return st;
+  }
   return run_collide(p, n_cells, h, dU, delta, flow, project, rhs_out, lh_out, amom_out, nullptr, stream);
 }
 
@@ -1348,8 +1430,12 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
     ST_TRY(dmalloc(&b->accref, static_cast<size_t>(nc) * n3));
   }
   {
-    int tile, splits;
-    choose_gemm(nc, n3, &tile, &splits);
+    // contraction configurations of this shape (FP64 and the plan precision)
+    if (sis_status st = tune_gemm(p, nc, SIS_PREC_FP64, b->h, &b->ws_acc, &b->ws_x, stream)) { delete b; return st; }
+    if (p->precision != SIS_PREC_FP64)
+      if (sis_status st = tune_gemm(p, nc, p->precision, b->h, &b->ws_acc, &b->ws_x, stream)) { delete b; return st; }
+    int splits = std::max(p->gemm_choice[std::make_pair(nc, static_cast<int>(SIS_PREC_FP64))].second,
+                          p->gemm_choice[std::make_pair(nc, p->precision)].second);
     if (splits > 1) ST_TRY(b->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
     if (p->precision != SIS_PREC_FP64) ST_TRY(b->ws_x.ensure(static_cast<size_t>(nc) * n3 * 4));
     const int W = (p->nv / 2 + 63) / 64;
@@ -1473,6 +1559,25 @@ sis_status sis_solve(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o, sis_so
   sis_state_destroy(b);
   g_err = keep;
   return st;
+}
+
+sis_status sis_plan_contraction_config(sis_plan_t p, int64_t n_cells, int32_t precision, int32_t* tile_rows,
+                                       int32_t* splits, int32_t* tuned) {
+  if (sis_status st = check_plan(p)) return st;
+  if (!tile_rows || !splits || !tuned) return fail(SIS_E_INVALID, "null output");
+  int t, s;
+  const auto it = p->gemm_choice.find(std::make_pair(n_cells, static_cast<int>(precision)));
+  if (it != p->gemm_choice.end()) {
+    t = it->second.first;
+    s = it->second.second;
+    *tuned = 1;
+  } else {
+    choose_gemm(n_cells, p->ndof, &t, &s);
+    *tuned = 0;
+  }
+  *tile_rows = sis::gemm_tile_rows(t);
+  *splits = s;
+  return SIS_OK;
 }
 
 sis_status sis_plan_timing(sis_plan_t p, int32_t enable) {

@@ -42,8 +42,9 @@ struct GemmArgs {
   int64_t M;
   int N, K;
   int splits;        // split-K factor (grid.z)
-  int tile;          // tile configuration id (0 large, 1 small-M)
+  int tile;          // tile configuration id: 0 (128 x 128), 2 (64 x 128), 1 (32 x 128)
 };
+int gemm_tile_rows(int tile);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 // x = X - Xref (Xref may be null) -> bf16 hi + lo, or -> FP32; count = M * K
 hipError_t launch_split_x(const double* X, const double* Xref, int64_t count, uint16_t* hi, uint16_t* lo,

@@ -1256,26 +1256,34 @@ int gemm_k_per_split(int K, int splits) {
   return kps;
 }
 
+int gemm_tile_rows(int tile) { return tile == 0 ? 128 : tile == 2 ? 64 : 32; }
+
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   const int kps = gemm_k_per_split(g.K, g.splits);
   const int BN = 128;
-  const int BM = g.tile == 0 ? 128 : 32;
+  const int BM = gemm_tile_rows(g.tile);
   dim3 grid((g.N + BN - 1) / BN, static_cast<unsigned>((g.M + BM - 1) / BM), g.splits);
   if (g.precision == 0) {
     if (g.tile == 0)
       hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
+    else if (g.tile == 2)
+      hipLaunchKernelGGL((gemm_f64_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
     else
       hipLaunchKernelGGL((gemm_f64_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
   } else if (g.precision == 1) {
     if (!g.X32) return hipErrorInvalidValue;
     if (g.tile == 0)
       hipLaunchKernelGGL((gemm_f32_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
+    else if (g.tile == 2)
+      hipLaunchKernelGGL((gemm_f32_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
     else
       hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
   } else {
     if (!g.Xh || !g.Xl) return hipErrorInvalidValue;
     if (g.tile == 0)
       hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.Xh, g.Xl, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
+    else if (g.tile == 2)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.Xh, g.Xl, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
     else
       hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.Xh, g.Xl, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
   }

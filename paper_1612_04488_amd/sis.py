@@ -111,6 +111,10 @@ _SIGS = {
     "sis_state_poll": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
     "sis_state_results": (ctypes.c_int32, [_P, ctypes.POINTER(SolveResult), _P]),
     "sis_state_destroy": (ctypes.c_int32, [_P]),
+    "sis_plan_contraction_config": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32,
+                                                     ctypes.POINTER(ctypes.c_int32),
+                                                     ctypes.POINTER(ctypes.c_int32),
+                                                     ctypes.POINTER(ctypes.c_int32)]),
     "sis_plan_timing": (ctypes.c_int32, [_P, ctypes.c_int32]),
     "sis_plan_timing_read": (ctypes.c_int32, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
 }
@@ -254,6 +258,13 @@ class Plan:
         check(lib().sis_collide(self.handle, n_cells, _ptr(h), _ptr(dU), _ptr(delta), _ptr(flow),
                                 1 if project else 0, _ptr(rhs_out), _ptr(lh_out), _ptr(amom_out),
                                 _stream(stream)))
+
+    def contraction_config(self, n_cells, precision="fp64"):
+        """(tile rows, split-K, tuned) of the contraction for n_cells cells."""
+        t, s, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().sis_plan_contraction_config(self.handle, int(n_cells), PRECISIONS.get(precision, precision),
+                                                ctypes.byref(t), ctypes.byref(s), ctypes.byref(u)))
+        return t.value, s.value, bool(u.value)
 
     def timing(self, enable):
         check(lib().sis_plan_timing(self.handle, 1 if enable else 0))
