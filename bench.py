@@ -37,8 +37,10 @@ METRIC = "cell-updates/s of L(h) + time-to-residual 1e-8, mixed SIS vs FP64 plai
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 # HBM bytes per contraction launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (scaled by a 1 GiB copy: FETCH x2.0, WRITE x1.0), recorded for the kernel as it
-# stands; see profiles/gemm_f64_planar-hs-32v-808cells-parity.md.
-TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64"): (807518.6 * 2.0, 206848.0)}
+# stands, keyed by (workload, parity, precision, tile rows, split-K); a launch
+# configuration without a recorded pass reports null.  Source:
+# profiles/gemm_f64_planar-hs-32v-808cells-parity.md.
+TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4): (1750706.0 * 2.0, 206848.0)}
 HBM_GBS = 8000.0
 
 
@@ -218,7 +220,7 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     log(f"contraction: {avg_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s of {peak} peak "
         f"(tile {tile_rows}x128, split-K {splits}, autotuned {tuned})")
-    tk = TRAFFIC_KIB.get((w["name"], parity, args.precision))
+    tk = TRAFFIC_KIB.get((w["name"], parity, args.precision, tile_rows, splits))
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": (tk[0] + tk[1]) * 1024.0 if tk else None,
                 "kernel": f"gemm_{args.precision}", "avg_launch_ms": round(avg_ms, 4),

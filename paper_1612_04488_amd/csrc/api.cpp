@@ -261,9 +261,11 @@ sis_status prepare_lowp_operand(sis_plan* p, int precision, int64_t n_cells, con
 
 // Autotuner of the contraction: times every (tile, split-K) candidate on the
 // actual shape (two launches each after a warm-up, HIP events on `s`) and
-// keeps the fastest per (cells, precision) in the plan.  Not callable while
-// `s` is capturing.  Candidates whose split-K partials would exceed 4 GiB are
-// skipped.
+// keeps, per (cells, precision), the candidate with the fewest split-K
+// partials, then the tallest tile, among those within 3% of the fastest (so
+// that timing noise does not flip between near-equal configurations).  Not
+// callable while `s` is capturing.  Candidates whose split-K partials would
+// exceed 4 GiB are skipped.
 sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scratch* ws_acc, Scratch* ws_x,
                      hipStream_t s) {
   const auto key = std::make_pair(M, precision);
@@ -281,8 +283,7 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   if (sis_status st = prepare_lowp_operand(p, precision, M, h, nullptr, ws_x, g, s)) return st;
   int dt, ds;
   choose_gemm(M, p->ndof, &dt, &ds);
-  std::pair<int, int> best(dt, ds);
-  float best_ms = 1e30f;
+  std::vector<std::pair<float, std::pair<int, int>>> timed;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -307,14 +308,26 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       float ms = 0.f;
       if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-      if (err == hipSuccess && ms < best_ms) {
-        best_ms = ms;
-        best = std::make_pair(g.tile, sp);
-      }
+      if (err == hipSuccess) timed.emplace_back(ms, std::make_pair(g.tile, sp));
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return fail(SIS_E_DEVICE, "contraction tuning: %s", hipGetErrorString(err));
+  std::pair<int, int> best(dt, ds);
+  if (!timed.empty()) {
+    float fastest = timed[0].first;
+    for (const auto& c : timed) fastest = std::min(fastest, c.first);
+    int best_rows = -1, best_splits = 1 << 30;
+    for (const auto& c : timed) {
+      if (c.first > 1.03f * fastest) continue;
+      const int rows = sis::gemm_tile_rows(c.second.first), sp = c.second.second;
+      if (sp < best_splits || (sp == best_splits && rows > best_rows)) {
+        best_splits = sp;
+        best_rows = rows;
+        best = c.second;
+      }
+    }
+  }
   p->gemm_choice[key] = best;
   return SIS_OK;
 }
