@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--workload", default="batch", choices=["batch", "small", "duct", "porous", "mixture"])
+    ap.add_argument("--diffusion", default="inverse", choices=["inverse", "cg"],
+                    help="2-D velocity equation: precomputed inverse or conjugate gradients")
     ap.add_argument("--ttr", default="fp64,fp32,bf16x3,fp64+projection,bf16x3+projection",
                     help="time-to-residual runs (comma list)")
     ap.add_argument("--parity", default="auto", choices=["auto", "0", "1", "2"],
@@ -164,6 +166,8 @@ def main():
     info = plan.info
     log(f"plan {w['name']}: {t_plan:.2f} s (host {info['plan_seconds_host']:.2f} s), "
         f"operator {info['operator_bytes'] / 2**30:.2f} GiB")
+    t0 = time.perf_counter()
+    diff_info = None
     if planar:
         xs = inputs.workload_nodes(w)
         geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
@@ -173,6 +177,12 @@ def main():
         geom = sis.Geometry2D(plan, "duct" if args.workload == "duct" else "periodic", cases,
                               w["deltas"], w["flows"])
         per_case = np.diff(geom.offsets).tolist()
+        if args.diffusion == "cg":
+            geom.diffusion_solver("cg")
+        n_inv, inv_res = geom.diffusion_info()
+        diff_info = {"solver": args.diffusion, "cases_on_inverse": n_inv, "inverse_residual": inv_res}
+    t_geom = time.perf_counter() - t0
+    log(f"geometry: {t_geom:.2f} s" + (f", velocity equation {diff_info}" if diff_info else ""))
     nc, n3 = geom.n_cells, plan.n_dof   # unknowns per spatial cell (both species for a mixture)
     plan.set_precision(args.precision)
 
@@ -275,8 +285,10 @@ def main():
                       "parity": {0: "full grid", 1: "odd in v3 (v3 > 0 stored)",
                                  2: "odd in v3, even in v2 (v2, v3 > 0 stored)"}[parity]},
            "roofline": roofline,
-           "plan_seconds": round(t_plan, 3),
+           "plan_seconds": round(t_plan, 3), "geometry_seconds": round(t_geom, 3),
            "time_to_residual_1e-8": ttr}
+    if diff_info:
+        out["config"]["velocity_equation"] = diff_info
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         cb = cpu_baseline(w, args.cpu_cells)

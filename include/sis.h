@@ -58,6 +58,7 @@ enum { SIS_PREC_FP64 = 0, SIS_PREC_FP32 = 1, SIS_PREC_BF16X3 = 2 };
 enum { SIS_FLOW_NONE = 0, SIS_FLOW_POISEUILLE = 1, SIS_FLOW_TRANSPIRATION = 2 };
 enum { SIS_SCHEME_CIS = 0, SIS_SCHEME_SIS = 1 };
 enum { SIS_GEOM_PLANAR_HALF = 0, SIS_GEOM_DUCT_QUARTER = 1, SIS_GEOM_PERIODIC_2D = 2 };
+enum { SIS_DIFFUSION_CG = 0, SIS_DIFFUSION_INVERSE = 1 };
 
 const char* sis_last_error(void);   /* thread-local; valid until the next call on this thread */
 int32_t sis_version(void);          /* 100 * major + minor                                    */
@@ -213,6 +214,24 @@ sis_status sis_geometry_destroy(sis_geom_t geom);
 int64_t    sis_geometry_cells(sis_geom_t geom);
 int32_t    sis_geometry_moment_stride(sis_geom_t geom);   /* 4 planar, 8 in 2-D; -1 if NULL */
 
+/* Solver of the 2-D velocity equation (sis_diffusion_correct; the operator
+ * depends on the geometry only).  SIS_DIFFUSION_INVERSE (the default after
+ * sis_geometry_create) precomputes, per case, the dense inverse of the
+ * finite-volume operator on the case's unknown cells by Newton-Schulz
+ * iteration on the GPU (FP64 contractions, about log2(condition) + 5 steps,
+ * each 4 nu^3 flops), so that every outer iteration applies it as one
+ * matrix-vector product (nu^2 doubles read).  It holds nu^2 doubles per case
+ * (at most 16 GiB per geometry, nu <= 16384); cases beyond that, cases whose
+ * fluid has a group of unknown cells that reaches no wall or solid (the
+ * operator is singular there) and cases whose iteration does not reach a
+ * Frobenius residual ||I - S X|| < 1e-8 use the conjugate-gradient solve.
+ * SIS_DIFFUSION_CG frees the inverses and uses conjugate gradients for
+ * every case.  Planar geometries ignore the call.  Synchronises stream.
+ * sis_geometry_diffusion_info: number of cases on the inverse and the largest
+ * Frobenius residual of their (Jacobi-scaled) inverses; both nullable.        */
+sis_status sis_geometry_diffusion_solver(sis_geom_t geom, int32_t mode, hipStream_t stream);
+sis_status sis_geometry_diffusion_info(sis_geom_t geom, int32_t* n_inverse, double* residual);
+
 /* ------------------------------------------------------------------ compute
  * sis_collide -- collision step of one outer iteration for n_cells cells
  * (eq. LBE_collision applied pointwise in space, eq. syn_LBE right side,
@@ -263,8 +282,9 @@ sis_status sis_moments(sis_plan_t plan, int64_t n_cells, const double* h, double
 /* sis_diffusion_correct -- the SIS velocity equation.
  * 2-D (eq. diffusion_LBE with N): lap U = -N delta [Poiseuille]
  *   - (d11 G1 + 2 d12 G12 + d22 G2) + d1 A1 + d2 A2 in finite-volume form,
- *   U = U3(h_half) on fluid cells next to a wall or solid, solved by
- *   Jacobi-preconditioned conjugate gradients to a relative residual 1e-13;
+ *   U = U3(h_half) on fluid cells next to a wall or solid, solved with the
+ *   precomputed inverse or by Jacobi-preconditioned conjugate gradients to a
+ *   relative residual 1e-13 (sis_geometry_diffusion_solver);
  *   mom_half [cells][8], amom [cells][4] (A2 = amom[2] + N delta amom[3]).
  * Planar form (eq. first_order with the tuning parameter N, Sec. 2.5):
  *   d(U + G1)/dx1 = -N delta x1 [Poiseuille] + A1,   A1 = amom[0] + N delta amom[1],

@@ -136,8 +136,26 @@ struct sis_geom {
   double* work = nullptr;        // [grid][10] diffusion workspace
   int32_t* have_x = nullptr;     // [n_cases]
   int32_t* cg_iters = nullptr;   // [n_cases]
+  // 2-D velocity equation by a precomputed inverse (cases with h_direct[c] != 0)
+  std::vector<int32_t> h_direct;
+  int32_t *d_direct = nullptr, *d_uidx = nullptr, *d_nunk = nullptr;
+  int64_t *d_uoff = nullptr, *d_aoff = nullptr;
+  double *ainv = nullptr, *bvec = nullptr, *yvec = nullptr;
+  int max_unknown = 0, n_direct = 0;
+  double inv_residual = 0.0;     // largest ||I - X S||_F of the scaled inverses
+  void free_inverse() {
+    dfree(d_direct); dfree(d_uidx); dfree(d_nunk); dfree(d_uoff); dfree(d_aoff);
+    dfree(ainv); dfree(bvec); dfree(yvec);
+    d_direct = d_uidx = d_nunk = nullptr;
+    d_uoff = d_aoff = nullptr;
+    ainv = bvec = yvec = nullptr;
+    h_direct.clear();
+    max_unknown = n_direct = 0;
+    inv_residual = 0.0;
+  }
   int mom_stride() const { return two_d ? 8 : 4; }
   ~sis_geom() {
+    free_inverse();
     dfree(off); dfree(x); dfree(coef); dfree(delta_case); dfree(flow_case);
     dfree(delta_cell); dfree(flow_cell); dfree(case_of_cell);
     dfree(d_n1); dfree(d_n2); dfree(d_gcell); dfree(d_sref); dfree(d_nb); dfree(d_goff);
@@ -509,6 +527,17 @@ sis::Diff2DArgs diff2d_args(sis_plan* p, sis_geom* g, const double* mom, const d
   a.tol = 1e-13;
   a.max_iter = 20000;
   a.cg_iters = g->cg_iters;
+  if (g->d_direct) {
+    a.direct = g->d_direct;
+    a.uidx = g->d_uidx;
+    a.uoff = g->d_uoff;
+    a.aoff = g->d_aoff;
+    a.n_unknown = g->d_nunk;
+    a.max_unknown = g->max_unknown;
+    a.ainv = g->ainv;
+    a.bvec = g->bvec;
+    a.yvec = g->yvec;
+  }
   return a;
 }
 
@@ -541,6 +570,224 @@ hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
   if (e != hipSuccess) return e;
   if (src.empty()) return hipSuccess;
   return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// Inverse of the finite-volume velocity operator of each 2-D case, restricted to
+// its unknown cells (those with four fluid neighbours).  A = diag(sum fw) -
+// (fw to unknown neighbours) is symmetric; it is positive definite when every
+// connected group of unknowns reaches a Dirichlet cell.  With D = diag(A) and
+// S = D^-1/2 A D^-1/2 the Newton-Schulz iteration X <- X (2I - S X), X0 = I,
+// squares I - S X every step; A^-1 = D^-1/2 X D^-1/2.  Cases that are singular,
+// too large, or whose iteration stalls keep the conjugate-gradient solve.
+constexpr int64_t kInverseMaxUnknowns = 16384;
+constexpr double kInverseMaxBytes = 16.0 * 1073741824.0;
+constexpr int kNewtonSchulzMaxIter = 64;
+
+sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
+  g->free_inverse();
+  const sis::Tables2D& t = g->t2;
+  const int nc = g->n_cases;
+  std::vector<int32_t> uidx(t.n_grid, -1), nunk(nc, 0), direct(nc, 0);
+  std::vector<int64_t> uoff(nc + 1, 0), aoff(nc + 1, 0);
+  double bytes = 0.0;
+  for (int k = 0; k < nc; ++k) {
+    const int64_t g0 = t.grid_off[k], g1 = t.grid_off[k + 1];
+    for (int64_t G = g0; G < g1; ++G)
+      if (t.dflag[G] == 2) uidx[G] = nunk[k]++;
+    uoff[k + 1] = uoff[k] + nunk[k];
+    // every connected group of unknowns must touch a Dirichlet cell
+    bool ok = nunk[k] <= kInverseMaxUnknowns;
+    if (ok && nunk[k] > 0) {
+      std::vector<int32_t> comp(nunk[k], -1), stack;
+      int n_comp = 0;
+      std::vector<char> anchored;
+      for (int64_t G = g0; G < g1 && ok; ++G) {
+        if (t.dflag[G] != 2 || comp[uidx[G]] >= 0) continue;
+        bool anchor = false;
+        comp[uidx[G]] = n_comp;
+        stack.assign(1, static_cast<int32_t>(G - g0));
+        while (!stack.empty()) {
+          const int64_t H = g0 + stack.back();
+          stack.pop_back();
+          for (int q = 0; q < 4; ++q) {
+            if (t.fw[H * 4 + q] == 0.0) continue;
+            const int r = t.nb[H * 8 + q];
+            if (t.dflag[g0 + r] != 2) { anchor = true; continue; }
+            if (comp[uidx[g0 + r]] < 0) {
+              comp[uidx[g0 + r]] = n_comp;
+              stack.push_back(r);
+            }
+          }
+        }
+        ok = anchor;
+        ++n_comp;
+      }
+    }
+    const double need = static_cast<double>(nunk[k]) * nunk[k] * 8.0;
+    if (ok && bytes + need <= kInverseMaxBytes) {
+      direct[k] = 1;
+      bytes += need;
+    }
+    aoff[k + 1] = aoff[k] + (direct[k] ? static_cast<int64_t>(nunk[k]) * nunk[k] : 0);
+  }
+  int max_np = 0;
+  for (int k = 0; k < nc; ++k)
+    if (direct[k]) max_np = std::max(max_np, (nunk[k] + 1) & ~1);
+  // scratch of the iteration: S, X, P, X_next and the residual partials
+  const int kBlocks = 1024;
+  double *S = nullptr, *X = nullptr, *P = nullptr, *Xn = nullptr, *part = nullptr, *sc = nullptr, *val = nullptr;
+  int32_t* rc = nullptr;
+  auto cleanup = [&]() {
+    dfree(S); dfree(X); dfree(P); dfree(Xn); dfree(part); dfree(sc); dfree(val); dfree(rc);
+    S = X = P = Xn = part = sc = val = nullptr;
+    rc = nullptr;
+  };
+#define INV_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      cleanup();                                                                               \
+      g->free_inverse();                                                                       \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s", #expr,        \
+                  hipGetErrorString(e_));                                                      \
+    }                                                                                          \
+  } while (0)
+  const size_t mat = static_cast<size_t>(max_np) * max_np;
+  if (max_np > 0) {
+    INV_TRY(dmalloc(&S, mat));
+    INV_TRY(dmalloc(&X, mat));
+    INV_TRY(dmalloc(&P, mat));
+    INV_TRY(dmalloc(&Xn, mat));
+    INV_TRY(dmalloc(&part, kBlocks));
+    INV_TRY(dmalloc(&sc, max_np));
+    INV_TRY(dmalloc(&val, static_cast<size_t>(max_np) * 5));
+    INV_TRY(dmalloc(&rc, static_cast<size_t>(max_np) * 10));
+    INV_TRY(dmalloc(&g->ainv, static_cast<size_t>(aoff[nc])));
+  }
+  std::vector<double> h_part(kBlocks);
+  double worst = 0.0;
+  for (int k = 0; k < nc; ++k) {
+    if (!direct[k] || nunk[k] == 0) continue;
+    const int nu = nunk[k], np = (nu + 1) & ~1;
+    const int64_t g0 = t.grid_off[k], g1 = t.grid_off[k + 1];
+    // scaled entries: unit diagonal, -fw / sqrt(d_i d_j) to unknown neighbours
+    std::vector<double> dsq(np, 1.0), hs(np, 1.0);
+    for (int64_t G = g0; G < g1; ++G) {
+      if (t.dflag[G] != 2) continue;
+      double d = 0.0;
+      for (int q = 0; q < 4; ++q) d += t.fw[G * 4 + q];
+      dsq[uidx[G]] = std::sqrt(d);
+      hs[uidx[G]] = 1.0 / std::sqrt(d);
+    }
+    std::vector<int32_t> h_rc;
+    std::vector<double> h_val;
+    for (int i = 0; i < np; ++i) {
+      h_rc.push_back(i);
+      h_rc.push_back(i);
+      h_val.push_back(1.0);
+    }
+    for (int64_t G = g0; G < g1; ++G) {
+      if (t.dflag[G] != 2) continue;
+      const int i = uidx[G];
+      int cols[4];
+      double vals[4];
+      int m = 0;
+      for (int q = 0; q < 4; ++q) {
+        const double fw = t.fw[G * 4 + q];
+        if (fw == 0.0) continue;
+        const int r = t.nb[G * 8 + q];
+        if (t.dflag[g0 + r] != 2) continue;
+        const int j = uidx[g0 + r];
+        const double v = -fw * hs[i] * hs[j];
+        int e = 0;
+        while (e < m && cols[e] != j) ++e;
+        if (e == m) { cols[m] = j; vals[m] = 0.0; ++m; }
+        vals[e] += v;
+      }
+      for (int e = 0; e < m; ++e) {
+        h_rc.push_back(i);
+        h_rc.push_back(cols[e]);
+        h_val.push_back(vals[e]);
+      }
+    }
+    const int64_t ne = static_cast<int64_t>(h_val.size());
+    const size_t sq = static_cast<size_t>(np) * np;
+    INV_TRY(hipMemsetAsync(S, 0, sq * sizeof(double), s));
+    INV_TRY(hipMemcpyAsync(rc, h_rc.data(), h_rc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    INV_TRY(hipMemcpyAsync(val, h_val.data(), h_val.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    INV_TRY(hipMemcpyAsync(sc, hs.data(), np * sizeof(double), hipMemcpyHostToDevice, s));
+    INV_TRY(sis::launch_ns_scatter(S, np, rc, val, ne, s));
+    // X0 = I: the spectrum of S lies in (0, 2), so |1 - lambda| < 1
+    INV_TRY(hipMemsetAsync(X, 0, sq * sizeof(double), s));
+    INV_TRY(sis::launch_ns_scatter(X, np, rc, val, np, s));   // the unit diagonal entries come first
+    sis::GemmArgs ga{};
+    ga.precision = 0;
+    ga.M = np;
+    ga.N = np;
+    ga.K = np;
+    ga.splits = 1;
+    ga.tile = 0;
+    const int blocks = static_cast<int>(std::min<int64_t>(kBlocks, (static_cast<int64_t>(np) * np + 255) / 256));
+    int extra = -1;
+    double res = 0.0;
+    bool ok = false;
+    for (int it = 0; it < kNewtonSchulzMaxIter; ++it) {
+      ga.X = X;          // P = X S (S symmetric, so X S^T = X S)
+      ga.op64 = S;
+      ga.acc = P;
+      INV_TRY(sis::launch_gemm(ga, s));
+      INV_TRY(sis::launch_ns_residual(P, np, part, blocks, s));
+      INV_TRY(hipMemcpyAsync(h_part.data(), part, blocks * sizeof(double), hipMemcpyDeviceToHost, s));
+      INV_TRY(hipStreamSynchronize(s));
+      res = 0.0;
+      for (int b = 0; b < blocks; ++b) res += h_part[b];
+      res = std::sqrt(res);
+      if (!std::isfinite(res)) break;
+      if (extra == 0) { ok = res < 1e-8; break; }
+      if (extra < 0 && res < 0.25) extra = 4;   // 2-norm < 1/4: four squarings reach rounding level
+      if (extra > 0) --extra;
+      INV_TRY(sis::launch_ns_two_minus(P, np, s));
+      ga.X = X;          // X_next = X (2I - P)^T = X (2I - S X)
+      ga.op64 = P;
+      ga.acc = Xn;
+      INV_TRY(sis::launch_gemm(ga, s));
+      std::swap(X, Xn);
+    }
+    if (!ok) {
+      direct[k] = 0;
+      continue;
+    }
+    worst = std::max(worst, res);
+    INV_TRY(sis::launch_ns_scale(X, np, nu, sc, g->ainv + aoff[k], s));
+  }
+  INV_TRY(hipStreamSynchronize(s));
+  cleanup();
+  int n_direct = 0, max_unknown = 0;
+  for (int k = 0; k < nc; ++k)
+    if (direct[k]) {
+      ++n_direct;
+      max_unknown = std::max(max_unknown, nunk[k]);
+    }
+  if (n_direct == 0) {
+    dfree(g->ainv);
+    g->ainv = nullptr;
+    return SIS_OK;
+  }
+  INV_TRY(upload(&g->d_direct, direct, s));
+  INV_TRY(upload(&g->d_uidx, uidx, s));
+  INV_TRY(upload(&g->d_nunk, nunk, s));
+  INV_TRY(upload(&g->d_uoff, uoff, s));
+  INV_TRY(upload(&g->d_aoff, aoff, s));
+  INV_TRY(dmalloc(&g->bvec, static_cast<size_t>(uoff[nc])));
+  INV_TRY(dmalloc(&g->yvec, static_cast<size_t>(uoff[nc])));
+  INV_TRY(hipStreamSynchronize(s));
+#undef INV_TRY
+  g->h_direct = direct;
+  g->n_direct = n_direct;
+  g->max_unknown = max_unknown;
+  g->inv_residual = worst;
+  (void)p;
+  return SIS_OK;
 }
 
 sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream_t stream, sis_geom_t* out) {
@@ -624,6 +871,10 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
   G2_TRY(upload(&g->cg_iters, std::vector<int32_t>(d->n_cases, 0), stream));
   G2_TRY(hipStreamSynchronize(stream));
 #undef G2_TRY
+  if (sis_status st = build_inverse_2d(p, g, stream)) {
+    delete g;
+    return st;
+  }
   *out = g;
   g_err.clear();
   return SIS_OK;
@@ -1204,6 +1455,28 @@ sis_status sis_geometry_destroy(sis_geom_t g) {
 }
 
 int64_t sis_geometry_cells(sis_geom_t g) { return g ? g->n_cells : -1; }
+
+sis_status sis_geometry_diffusion_solver(sis_geom_t g, int32_t mode, hipStream_t stream) {
+  if (!g) return fail(SIS_E_INVALID, "null geometry");
+  if (mode != SIS_DIFFUSION_CG && mode != SIS_DIFFUSION_INVERSE)
+    return fail(SIS_E_INVALID, "diffusion solver mode %d", mode);
+  if (!g->two_d) return SIS_OK;
+  if (mode == SIS_DIFFUSION_CG) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    g->free_inverse();
+    g_err.clear();
+    return SIS_OK;
+  }
+  if (g->d_direct) return SIS_OK;
+  return build_inverse_2d(g->plan, g, stream);
+}
+
+sis_status sis_geometry_diffusion_info(sis_geom_t g, int32_t* n_inverse, double* residual) {
+  if (!g) return fail(SIS_E_INVALID, "null geometry");
+  if (n_inverse) *n_inverse = g->n_direct;
+  if (residual) *residual = g->inv_residual;
+  return SIS_OK;
+}
 int32_t sis_geometry_moment_stride(sis_geom_t g) { return g ? g->mom_stride() : -1; }
 
 sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,

@@ -208,8 +208,27 @@ struct Diff2DArgs {
   int32_t* case_active;
   double eps;
   int32_t* cg_iters;         // [n_cases] or null
+  // inverse form (cases with direct[c] != 0): A^-1 of the case's unknown cells, precomputed
+  const int32_t* direct;     // [n_cases] or null (CG for every case)
+  const int32_t* uidx;       // [grid] compact unknown index within its case, -1 otherwise
+  const int64_t* uoff;       // [n_cases] offset of the case's unknowns in bvec / yvec
+  const int64_t* aoff;       // [n_cases] offset of the case's inverse in ainv
+  const int32_t* n_unknown;  // [n_cases]
+  int max_unknown;
+  const double* ainv;        // row-major nu x nu per case
+  double* bvec;              // [unknowns]
+  double* yvec;              // [unknowns]
 };
+// CG kernel for cases without an inverse, then (if a.direct) right sides, y = A^-1 b, outputs
 hipError_t launch_diffusion2d(const Diff2DArgs& a, hipStream_t s);
+// Newton-Schulz helpers (plan time): per-block sum of squares of I - P into part[blocks];
+// P <- 2I - P; out = diag(sc) X diag(sc) (n x n of X with leading dimension ldx);
+// S[rc[2i]][rc[2i+1]] = val[i]; X <- alpha I
+hipError_t launch_ns_residual(const double* P, int n, double* part, int blocks, hipStream_t s);
+hipError_t launch_ns_two_minus(double* P, int n, hipStream_t s);
+hipError_t launch_ns_scale(const double* X, int ldx, int n, const double* sc, double* out, hipStream_t s);
+hipError_t launch_ns_scatter(double* S, int n, const int32_t* rc, const double* val, int64_t count, hipStream_t s);
+hipError_t launch_ns_init(double* X, int n, double alpha, hipStream_t s);
 
 // cell_active[c] = case_active[case_of_cell[c]]
 hipError_t launch_expand_active(const int32_t* case_active, const int32_t* case_of_cell,

@@ -1022,16 +1022,10 @@ __device__ inline void block_sum_big(double (&v)[K], double* sh /* >= 16*K */) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
-  __shared__ double sh[16 * 3];
-  const int cs = blockIdx.x;
-  if (a.case_active && !a.case_active[cs]) return;
+// Moments of the case into the workspace: per grid cell Uh G1 G12 G2 A1 A2 (x r p Ap for CG).
+__device__ void d2_fill_work(const Diff2DArgs& a, int cs, double* W, int ng, bool warm) {
   const int64_t g0 = a.grid_off[cs];
-  const int ng = static_cast<int>(a.grid_off[cs + 1] - g0);
   const double del = a.delta_case[cs];
-  const bool pois = a.flow_case[cs] == 1;
-  double* W = a.work + g0 * 10;      // per grid cell: Uh G1 G12 G2 A1 A2 x r p Ap
-  const bool warm = a.have_x && a.have_x[cs];
   for (int g = threadIdx.x; g < ng; g += blockDim.x) {
     const int cell = a.gcell[g0 + g];
     double* w = W + static_cast<int64_t>(g) * 10;
@@ -1052,6 +1046,107 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
     }
     w[7] = 0.0; w[8] = 0.0; w[9] = 0.0;
   }
+}
+
+// Right side of the finite-volume velocity equation at an unknown grid cell G
+// (Dirichlet neighbours moved to the right) and the diagonal of its row.
+__device__ double d2_rhs(const Diff2DArgs& a, int64_t g0, int64_t G, const double* W, bool pois, double del,
+                         double& diag) {
+  const int g = static_cast<int>(G - g0);
+  const double* w = W + static_cast<int64_t>(g) * 10;
+  const int32_t* nbr = a.nb + G * 8;
+  const int8_t* bits = a.nbm + G * 8;
+  const double* np = a.npos + G * 4;
+  const double xc = a.cpos[G * 2], yc = a.cpos[G * 2 + 1];
+  auto val = [&](int q, int f, int p1, int p2) {
+    const int r = nbr[q];
+    return r < 0 ? 0.0 : par_sign(bits[q], p1, p2) * W[static_cast<int64_t>(r) * 10 + f];
+  };
+  const double xE = np[0], xW = np[1], yN = np[2], yS = np[3];
+  const double w1 = a.width[G * 2], w2 = a.width[G * 2 + 1];
+  auto d11 = [&](int f, int p1, int p2) {
+    return ((val(0, f, p1, p2) - w[f]) / (xE - xc) - (w[f] - val(1, f, p1, p2)) / (xc - xW)) / w1;
+  };
+  auto d22 = [&](int f, int p1, int p2) {
+    return ((val(2, f, p1, p2) - w[f]) / (yN - yc) - (w[f] - val(3, f, p1, p2)) / (yc - yS)) / w2;
+  };
+  double rhs = pois ? -a.N * del : 0.0;
+  const double cross = ((val(4, 2, -1, -1) - val(6, 2, -1, -1)) / (yN - yS) -
+                        (val(5, 2, -1, -1) - val(7, 2, -1, -1)) / (yN - yS)) / (xE - xW);
+  rhs -= d11(1, 1, 1) + 2.0 * cross + d22(3, 1, 1);
+  rhs += (val(0, 4, -1, 1) - val(1, 4, -1, 1)) / (xE - xW);
+  rhs += (val(2, 5, 1, -1) - val(3, 5, 1, -1)) / (yN - yS);
+  double b = -rhs * a.dA[G];
+  diag = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const double fw = a.fw[G * 4 + q];
+    if (fw == 0.0) continue;
+    const int r = nbr[q];
+    diag += fw;
+    if (a.dflag[g0 + r] != 2) b += fw * W[static_cast<int64_t>(r) * 10 + 0];
+  }
+  return b;
+}
+
+// New velocity, correction, moments of h^{k+1}, flow rates and the convergence
+// test of one case.  usol: solution at the unknown cells, indexed by uoff[case]
+// + uidx (null: the CG iterate in the workspace; CIS: no solve).
+__device__ void d2_outputs(const Diff2DArgs& a, int cs, const double* W, int ng, const double* usol, int it,
+                           double* sh) {
+  const int64_t g0 = a.grid_off[cs];
+  double fr[2] = {0.0, 0.0};
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    const int64_t G = g0 + g;
+    const int cell = a.gcell[G];
+    if (cell < 0) continue;
+    const double* w = W + static_cast<int64_t>(g) * 10;
+    const double Uh = w[0];
+    double U = Uh;
+    if (a.sis && a.dflag[G] == 2) U = usol ? usol[a.uoff[cs] + a.uidx[G]] : w[6];
+    const double dU = U - Uh;
+    const double Un = Uh + dU * a.cU;
+    const double qn = a.mom[static_cast<int64_t>(cell) * 8 + 1] + dU * a.cq;
+    if (a.U) a.U[cell] = U;
+    if (a.dU) a.dU[cell] = dU;
+    if (a.ufield) a.ufield[cell] = Un;
+    if (a.qfield) a.qfield[cell] = qn;
+    fr[0] += Un * a.dA[G];
+    fr[1] += qn * a.dA[G];
+  }
+  block_sum_big<2>(fr, sh);
+  if (threadIdx.x == 0) {
+    if (a.have_x) a.have_x[cs] = a.sis ? 1 : 0;
+    if (a.cg_iters) a.cg_iters[cs] = it;
+    if (a.state) {
+      const double M = fr[0] / a.area[cs], Q = fr[1] / a.area[cs];
+      double* st = a.state + cs * 4;
+      const double dM = fabs(M - st[0]) / fmax(fabs(M), 1e-300);
+      const double dQ = fabs(Q - st[1]) / fmax(fabs(Q), 1e-300);
+      const double res = fmax(dM, dQ);
+      st[0] = M;
+      st[1] = Q;
+      st[2] = (M != M || Q != Q) ? __builtin_nan("") : res;
+      const int k = a.iters[cs] + 1;
+      a.iters[cs] = k;
+      if (!(res >= a.eps) || M != M || Q != Q) a.case_active[cs] = 0;
+      st[3] = static_cast<double>(k);
+    }
+  }
+}
+
+// Conjugate-gradient form (cases without a precomputed inverse).
+__global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
+  __shared__ double sh[16 * 3];
+  const int cs = blockIdx.x;
+  if (a.case_active && !a.case_active[cs]) return;
+  if (a.direct && a.direct[cs]) return;   // solved by the inverse path
+  const int64_t g0 = a.grid_off[cs];
+  const int ng = static_cast<int>(a.grid_off[cs + 1] - g0);
+  const double del = a.delta_case[cs];
+  const bool pois = a.flow_case[cs] == 1;
+  double* W = a.work + g0 * 10;      // per grid cell: Uh G1 G12 G2 A1 A2 x r p Ap
+  const bool warm = a.have_x && a.have_x[cs];
+  d2_fill_work(a, cs, W, ng, warm);
   __syncthreads();
   int it = 0;
   if (a.sis) {
@@ -1061,37 +1156,14 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
       const int64_t G = g0 + g;
       if (a.dflag[G] != 2) continue;
       double* w = W + static_cast<int64_t>(g) * 10;
-      const int32_t* nbr = a.nb + G * 8;
-      const int8_t* bits = a.nbm + G * 8;
-      const double* np = a.npos + G * 4;
-      const double xc = a.cpos[G * 2], yc = a.cpos[G * 2 + 1];
-      auto val = [&](int q, int f, int p1, int p2) {
-        const int r = nbr[q];
-        return r < 0 ? 0.0 : par_sign(bits[q], p1, p2) * W[static_cast<int64_t>(r) * 10 + f];
-      };
-      const double xE = np[0], xW = np[1], yN = np[2], yS = np[3];
-      const double w1 = a.width[G * 2], w2 = a.width[G * 2 + 1];
-      auto d11 = [&](int f, int p1, int p2) {
-        return ((val(0, f, p1, p2) - w[f]) / (xE - xc) - (w[f] - val(1, f, p1, p2)) / (xc - xW)) / w1;
-      };
-      auto d22 = [&](int f, int p1, int p2) {
-        return ((val(2, f, p1, p2) - w[f]) / (yN - yc) - (w[f] - val(3, f, p1, p2)) / (yc - yS)) / w2;
-      };
-      double rhs = pois ? -a.N * del : 0.0;
-      const double cross = ((val(4, 2, -1, -1) - val(6, 2, -1, -1)) / (yN - yS) -
-                            (val(5, 2, -1, -1) - val(7, 2, -1, -1)) / (yN - yS)) / (xE - xW);
-      rhs -= d11(1, 1, 1) + 2.0 * cross + d22(3, 1, 1);
-      rhs += (val(0, 4, -1, 1) - val(1, 4, -1, 1)) / (xE - xW);
-      rhs += (val(2, 5, 1, -1) - val(3, 5, 1, -1)) / (yN - yS);
-      double b = -rhs * a.dA[G];
-      double diag = 0.0, Ax = 0.0;
+      double diag;
+      const double b = d2_rhs(a, g0, G, W, pois, del, diag);
+      double Ax = 0.0;
       for (int q = 0; q < 4; ++q) {
         const double fw = a.fw[G * 4 + q];
         if (fw == 0.0) continue;
-        const int r = nbr[q];
-        diag += fw;
+        const int r = a.nb[G * 8 + q];
         if (a.dflag[g0 + r] == 2) Ax -= fw * W[static_cast<int64_t>(r) * 10 + 6];
-        else b += fw * W[static_cast<int64_t>(r) * 10 + 0];
       }
       Ax += diag * w[6];
       const double r0 = b - Ax;
@@ -1155,44 +1227,108 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
       ++it;
     }
   }
-  // outputs and flow rates
-  double fr[2] = {0.0, 0.0};
+  d2_outputs(a, cs, W, ng, nullptr, it, sh);
+}
+
+// Inverse form, step 1: right sides of the unknown cells (compact per case).
+__global__ __launch_bounds__(kD2Threads) void diffusion2d_rhs_kernel(Diff2DArgs a) {
+  const int cs = blockIdx.x;
+  if (a.case_active && !a.case_active[cs]) return;
+  if (!a.direct[cs]) return;
+  const int64_t g0 = a.grid_off[cs];
+  const int ng = static_cast<int>(a.grid_off[cs + 1] - g0);
+  const double del = a.delta_case[cs];
+  const bool pois = a.flow_case[cs] == 1;
+  double* W = a.work + g0 * 10;
+  d2_fill_work(a, cs, W, ng, true);
+  __syncthreads();
+  if (!a.sis) return;
   for (int g = threadIdx.x; g < ng; g += blockDim.x) {
     const int64_t G = g0 + g;
-    const int cell = a.gcell[G];
-    if (cell < 0) continue;
-    const double* w = W + static_cast<int64_t>(g) * 10;
-    const double Uh = w[0];
-    const double U = (a.sis && a.dflag[G] == 2) ? w[6] : Uh;
-    const double dU = U - Uh;
-    const double Un = Uh + dU * a.cU;
-    const double qn = a.mom[static_cast<int64_t>(cell) * 8 + 1] + dU * a.cq;
-    if (a.U) a.U[cell] = U;
-    if (a.dU) a.dU[cell] = dU;
-    if (a.ufield) a.ufield[cell] = Un;
-    if (a.qfield) a.qfield[cell] = qn;
-    fr[0] += Un * a.dA[G];
-    fr[1] += qn * a.dA[G];
+    if (a.dflag[G] != 2) continue;
+    double diag;
+    a.bvec[a.uoff[cs] + a.uidx[G]] = d2_rhs(a, g0, G, W, pois, del, diag);
   }
-  block_sum_big<2>(fr, sh);
+}
+
+// Inverse form, step 2: y = A^-1 b per case, one wave per row of the inverse.
+__global__ __launch_bounds__(256) void diffusion2d_gemv_kernel(Diff2DArgs a) {
+  const int cs = blockIdx.y;
+  if (a.case_active && !a.case_active[cs]) return;
+  if (!a.direct[cs] || !a.sis) return;
+  const int nu = a.n_unknown[cs];
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= nu) return;
+  const int64_t u0 = a.uoff[cs];
+  const double* Ar = a.ainv + a.aoff[cs] + static_cast<int64_t>(row) * nu;
+  const double* b = a.bvec + u0;
+  double s = 0.0;
+  for (int j = lane; j < nu; j += 64) s += Ar[j] * b[j];
+  s = wave_sum(s);
+  if (lane == 0) a.yvec[u0 + row] = s;
+}
+
+// Inverse form, step 3: outputs, flow rates, convergence.
+__global__ __launch_bounds__(kD2Threads) void diffusion2d_out_kernel(Diff2DArgs a) {
+  __shared__ double sh[16 * 3];
+  const int cs = blockIdx.x;
+  if (a.case_active && !a.case_active[cs]) return;
+  if (!a.direct[cs]) return;
+  const int64_t g0 = a.grid_off[cs];
+  const int ng = static_cast<int>(a.grid_off[cs + 1] - g0);
+  d2_outputs(a, cs, a.work + g0 * 10, ng, a.yvec, 0, sh);
+}
+
+// Newton-Schulz steps for the inverse of a Jacobi-scaled SPD matrix (plan time).
+// Per-block sum of squares of I - P (Frobenius residual, an upper bound of the 2-norm).
+__global__ void ns_residual_kernel(const double* __restrict__ P, int n, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t count = static_cast<int64_t>(n) * n;
+  double m = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = i / n, c = i % n;
+    const double e = (r == c ? 1.0 : 0.0) - P[i];
+    m += e * e;
+  }
+  m = wave_sum(m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    if (a.have_x) a.have_x[cs] = a.sis ? 1 : 0;
-    if (a.cg_iters) a.cg_iters[cs] = it;
-    if (a.state) {
-      const double M = fr[0] / a.area[cs], Q = fr[1] / a.area[cs];
-      double* st = a.state + cs * 4;
-      const double dM = fabs(M - st[0]) / fmax(fabs(M), 1e-300);
-      const double dQ = fabs(Q - st[1]) / fmax(fabs(Q), 1e-300);
-      const double res = fmax(dM, dQ);
-      st[0] = M;
-      st[1] = Q;
-      st[2] = (M != M || Q != Q) ? __builtin_nan("") : res;
-      const int k = a.iters[cs] + 1;
-      a.iters[cs] = k;
-      if (!(res >= a.eps) || M != M || Q != Q) a.case_active[cs] = 0;
-      st[3] = static_cast<double>(k);
-    }
+    double v = 0.0;
+    for (int w = 0; w < (blockDim.x >> 6); ++w) v += sh[w];
+    part[blockIdx.x] = v;
   }
+}
+
+__global__ void ns_two_minus_kernel(double* __restrict__ P, int n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(n) * n) return;
+  const int64_t r = i / n, c = i % n;
+  P[i] = (r == c ? 2.0 : 0.0) - P[i];
+}
+
+// out[r][c] = X[r][c] s[r] s[c] for r, c < n (X has leading dimension ldx, out has n)
+__global__ void ns_scale_kernel(const double* __restrict__ X, int ldx, int n, const double* __restrict__ s,
+                                double* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(n) * n) return;
+  const int64_t r = i / n, c = i % n;
+  out[i] = X[r * ldx + c] * s[r] * s[c];
+}
+
+// X = alpha I (n x n); S = I, then S[row][col] = val for the listed entries
+__global__ void ns_init_kernel(double* __restrict__ X, int n, double alpha) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(n) * n) return;
+  X[i] = (i / n == i % n) ? alpha : 0.0;
+}
+
+__global__ void ns_scatter_kernel(double* __restrict__ S, int n, const int32_t* __restrict__ rc,
+                                  const double* __restrict__ val, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  S[static_cast<int64_t>(rc[2 * i]) * n + rc[2 * i + 1]] = val[i];
 }
 
 __global__ void expand_active_kernel(const int32_t* __restrict__ case_active,
@@ -1342,6 +1478,44 @@ hipError_t launch_moments2d(int n, int d3, int64_t n_cells, const double* v1d, c
 
 hipError_t launch_diffusion2d(const Diff2DArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(diffusion2d_kernel, dim3(a.n_cases), dim3(kD2Threads), 0, s, a);
+  if (a.direct) {
+    hipLaunchKernelGGL(diffusion2d_rhs_kernel, dim3(a.n_cases), dim3(kD2Threads), 0, s, a);
+    if (a.max_unknown > 0)
+      hipLaunchKernelGGL(diffusion2d_gemv_kernel, dim3((a.max_unknown + 3) / 4, a.n_cases), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(diffusion2d_out_kernel, dim3(a.n_cases), dim3(kD2Threads), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_residual(const double* P, int n, double* part, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(ns_residual_kernel, dim3(blocks), dim3(256), 0, s, P, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_two_minus(double* P, int n, hipStream_t s) {
+  const int64_t count = static_cast<int64_t>(n) * n;
+  hipLaunchKernelGGL(ns_two_minus_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, P, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_scale(const double* X, int ldx, int n, const double* sc, double* out, hipStream_t s) {
+  const int64_t count = static_cast<int64_t>(n) * n;
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(ns_scale_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, X, ldx, n,
+                     sc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_scatter(double* S, int n, const int32_t* rc, const double* val, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(ns_scatter_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, S, n, rc,
+                     val, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_init(double* X, int n, double alpha, hipStream_t s) {
+  const int64_t count = static_cast<int64_t>(n) * n;
+  hipLaunchKernelGGL(ns_init_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, X, n, alpha);
   return hipGetLastError();
 }
 

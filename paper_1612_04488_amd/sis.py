@@ -27,6 +27,7 @@ PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
 FLOW_NONE, FLOW_POISEUILLE, FLOW_TRANSPIRATION = 0, 1, 2
 SCHEME_CIS, SCHEME_SIS = 0, 1
 GEOM_PLANAR_HALF, GEOM_DUCT_QUARTER, GEOM_PERIODIC_2D = 0, 1, 2
+DIFFUSION_CG, DIFFUSION_INVERSE = 0, 1
 
 
 class SisError(RuntimeError):
@@ -100,6 +101,8 @@ _SIGS = {
     "sis_geometry_destroy": (ctypes.c_int32, [_P]),
     "sis_geometry_cells": (ctypes.c_int64, [_P]),
     "sis_geometry_moment_stride": (ctypes.c_int32, [_P]),
+    "sis_geometry_diffusion_solver": (ctypes.c_int32, [_P, ctypes.c_int32, _P]),
+    "sis_geometry_diffusion_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
     "sis_collide": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     "sis_transport_sweep": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
     "sis_moments": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P]),
@@ -354,6 +357,18 @@ class Geometry2D:
               for a, b, c in zip(n1, n2, cases)]
         self.offsets = np.concatenate([[0], np.cumsum(fl)]).astype(np.int64)
         self.mom_stride = 8
+
+    def diffusion_solver(self, mode, stream=None):
+        """"inverse" (default: precomputed per-case inverse where it applies) or "cg"."""
+        m = {"cg": DIFFUSION_CG, "inverse": DIFFUSION_INVERSE}[mode]
+        check(lib().sis_geometry_diffusion_solver(self.handle, m, _stream(stream)))
+
+    def diffusion_info(self):
+        """(number of cases solved with the inverse, largest Frobenius residual of the inverses)."""
+        n = ctypes.c_int32()
+        r = ctypes.c_double()
+        check(lib().sis_geometry_diffusion_info(self.handle, ctypes.byref(n), ctypes.byref(r)))
+        return int(n.value), float(r.value)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -90,14 +90,19 @@ def test_sweep2d_and_moments_parity(kind):
         assert np.max(np.abs(mom[s, :7] - mref)) < 1e-12 * np.max(np.abs(mref)), c
 
 
+@pytest.mark.parametrize("solver", ["inverse", "cg"])
 @pytest.mark.parametrize("kind", ["duct", "periodic"])
-def test_diffusion2d_parity(kind):
+def test_diffusion2d_parity(kind, solver):
     n_v, l_v, m = 8, 4.0, 3
-    say("diffusion2d", kind)
+    say("diffusion2d", kind, solver)
     p = plan(n_v, l_v, m)
     cases = CASES[kind]
     deltas, flows = [2.0, 30.0], [1, 2]
     geom = sis.Geometry2D(p, kind, cases, deltas, flows)
+    geom.diffusion_solver(solver)
+    n_inv, res = geom.diffusion_info()
+    assert n_inv == (len(cases) if solver == "inverse" else 0)
+    assert res < 1e-8
     grids = oracle_grids(kind, cases)
     nc = geom.n_cells
     rng = np.random.default_rng(4)
@@ -117,14 +122,17 @@ def test_diffusion2d_parity(kind):
         assert rel(dU[s], ref - mom[s, 0]) < 1e-9, c
 
 
-@pytest.mark.parametrize("kind,scheme", [("duct", "SIS"), ("duct", "CIS"), ("periodic", "SIS")])
-def test_solve2d_matches_oracle(kind, scheme):
+@pytest.mark.parametrize("kind,scheme,solver", [("duct", "SIS", "inverse"), ("duct", "SIS", "cg"),
+                                                 ("duct", "CIS", "inverse"), ("periodic", "SIS", "inverse"),
+                                                 ("periodic", "SIS", "cg")])
+def test_solve2d_matches_oracle(kind, scheme, solver):
     n_v, l_v, m = 8, 4.0, 3
-    say("solve2d", kind, scheme)
+    say("solve2d", kind, scheme, solver)
     p = plan(n_v, l_v, m)
     cases = CASES[kind][:1]
     deltas, flows = [1.0], [1]
     geom = sis.Geometry2D(p, kind, cases, deltas, flows)
+    geom.diffusion_solver(solver)
     r = sis.solve(p, geom, scheme=scheme, eps=1e-9, max_it=300)
     f = fsm(n_v, l_v, m)
     g = oracle_grids(kind, cases)[0]
@@ -133,3 +141,56 @@ def test_solve2d_matches_oracle(kind, scheme):
     assert int(r["iters"][0]) == ref["iters"]
     assert abs(r["M"][0] - ref["M"]) < 1e-10 * abs(ref["M"])
     assert abs(r["Q"][0] - ref["Q"]) < 1e-10 * abs(ref["Q"])
+
+
+@pytest.mark.parametrize("kind", ["duct", "periodic"])
+def test_diffusion2d_inverse_at_full_size(kind):
+    """The velocity equation of the full-size cross sections (64^2 quarter
+    ducts of aspect 1 and 2; the 128^2 porous cell with its disc packing):
+    the precomputed inverse agrees with the oracle's sparse direct solve and
+    with the conjugate-gradient path.  The operator depends on the geometry
+    only, so a small velocity plan serves."""
+    say("diffusion2d full size", kind)
+    p = plan(8, 4.0, 3)
+    if kind == "duct":
+        w = inputs.DUCT_IPL
+        cases = inputs.duct_cases(w)[2:4]
+    else:
+        w = inputs.POROUS_HS
+        cases = inputs.porous_cases(w)[:1]
+    deltas, flows = [5.0] * len(cases), [1] * len(cases)
+    geom = sis.Geometry2D(p, kind, cases, deltas, flows)
+    n_inv, res = geom.diffusion_info()
+    say("inverse cases", n_inv, "residual", res)
+    assert n_inv == len(cases) and res < 1e-8
+    nc = geom.n_cells
+    rng = np.random.default_rng(12)
+    mom = rng.standard_normal((nc, 8)) * 0.1
+    mom[:, 0] += 1.0
+    amom = rng.standard_normal((nc, 4)) * 0.1
+    N = 1.1
+    out = {}
+    for solver in ("inverse", "cg"):
+        geom.diffusion_solver(solver)
+        U = torch.empty(nc, dtype=torch.float64, device=DEV)
+        sis.diffusion_correct(p, geom, dev(mom), dev(amom), N, U, None)
+        torch.cuda.synchronize()
+        out[solver] = U.cpu().numpy()
+    grids = oracle_grids(kind, cases)
+    o = geom.offsets
+    for c, g in enumerate(grids):
+        s = slice(o[c], o[c + 1])
+        ref = duct.diffusion_2d(g, mom[s], amom[s], deltas[c], N, flows[c])
+        say(c, rel(out["inverse"][s], ref), rel(out["cg"][s], ref))
+        assert rel(out["inverse"][s], ref) < 1e-10, c
+        assert rel(out["cg"][s], ref) < 1e-8, c
+
+
+def test_inverse_falls_back_on_singular_cases():
+    """A periodic cell without solids has no Dirichlet cell: its operator is
+    singular, so that case keeps the conjugate-gradient solve."""
+    p = plan(8, 4.0, 3)
+    f = np.linspace(0, 1, 7)
+    cases = [(f, f, np.zeros((6, 6), bool)), CASES["periodic"][1]]
+    geom = sis.Geometry2D(p, "periodic", cases, [1.0, 1.0], [0, 1])
+    assert geom.diffusion_info()[0] == 1
