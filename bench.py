@@ -113,7 +113,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--workload", default="batch", choices=["batch", "small", "duct", "porous", "mixture"])
+    ap.add_argument("--workload", default="batch",
+                    choices=["batch", "small", "duct", "porous", "mixture", "sierpinski"])
     ap.add_argument("--diffusion", default="inverse", choices=["inverse", "cg"],
                     help="2-D velocity equation: precomputed inverse or conjugate gradients")
     ap.add_argument("--ttr", default="fp64,fp32,bf16x3,fp64+projection,bf16x3+projection",
@@ -150,11 +151,12 @@ def main():
                           "copies": 5}), flush=True)
         return 0
     w = {"batch": inputs.PLANAR_BATCH, "small": inputs.PLANAR_SMALL, "duct": inputs.DUCT_IPL,
-         "porous": inputs.POROUS_HS, "mixture": inputs.MIX_NEAR}[args.workload]
+         "porous": inputs.POROUS_HS, "mixture": inputs.MIX_NEAR,
+         "sierpinski": inputs.SIERPINSKI_HS}[args.workload]
     mix = w.get("mixture")
     # penalty N of the SIS velocity equations: nubar for one gas, 1.5 for the
-    # mixture (the value the paper reports converging within 50 iterations)
-    Npen = 1.5 if mix else 0.0
+    # mixture and the carpets (the values the paper runs them with)
+    Npen = 1.5 if mix or args.workload == "sierpinski" else 0.0
     if mix and args.cpu_cells == 12:
         args.cpu_cells = 1
     planar = args.workload in ("batch", "small", "mixture")
@@ -173,14 +175,16 @@ def main():
         geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
         per_case = [len(x) for x in xs]
     else:
-        cases = inputs.duct_cases(w) if args.workload == "duct" else inputs.porous_cases(w)
-        geom = sis.Geometry2D(plan, "duct" if args.workload == "duct" else "periodic", cases,
+        cases = {"duct": inputs.duct_cases, "porous": inputs.porous_cases,
+                 "sierpinski": inputs.sierpinski_cases}[args.workload](w)
+        geom = sis.Geometry2D(plan, "periodic" if args.workload == "porous" else "duct", cases,
                               w["deltas"], w["flows"])
         per_case = np.diff(geom.offsets).tolist()
         if args.diffusion == "cg":
             geom.diffusion_solver("cg")
-        n_inv, inv_res = geom.diffusion_info()
-        diff_info = {"solver": args.diffusion, "cases_on_inverse": n_inv, "inverse_residual": inv_res}
+        n_inv, n_dist, inv_res = geom.diffusion_info()
+        diff_info = {"solver": args.diffusion, "cases_on_inverse": n_inv, "distinct_inverses": n_dist,
+                     "inverse_residual": inv_res}
     t_geom = time.perf_counter() - t0
     log(f"geometry: {t_geom:.2f} s" + (f", velocity equation {diff_info}" if diff_info else ""))
     nc, n3 = geom.n_cells, plan.n_dof   # unknowns per spatial cell (both species for a mixture)

@@ -220,17 +220,22 @@ int32_t    sis_geometry_moment_stride(sis_geom_t geom);   /* 4 planar, 8 in 2-D;
  * finite-volume operator on the case's unknown cells by Newton-Schulz
  * iteration on the GPU (FP64 contractions, about log2(condition) + 5 steps,
  * each 4 nu^3 flops), so that every outer iteration applies it as one
- * matrix-vector product (nu^2 doubles read).  It holds nu^2 doubles per case
- * (at most 16 GiB per geometry, nu <= 16384); cases beyond that, cases whose
+ * matrix-vector product (nu^2 doubles read).  Cases with the same cross
+ * section (same faces and solids) share one inverse, which one product per
+ * iteration applies to all of them (up to 8 per read).  It holds nu^2 doubles
+ * per distinct cross section (at most 16 GiB per geometry, nu <= 16384);
+ * cases beyond that, cases whose
  * fluid has a group of unknown cells that reaches no wall or solid (the
  * operator is singular there) and cases whose iteration does not reach a
  * Frobenius residual ||I - S X|| < 1e-8 use the conjugate-gradient solve.
  * SIS_DIFFUSION_CG frees the inverses and uses conjugate gradients for
  * every case.  Planar geometries ignore the call.  Synchronises stream.
- * sis_geometry_diffusion_info: number of cases on the inverse and the largest
- * Frobenius residual of their (Jacobi-scaled) inverses; both nullable.        */
+ * sis_geometry_diffusion_info: number of cases on the inverse, number of
+ * distinct inverses held, and the largest Frobenius residual of the
+ * (Jacobi-scaled) inverses; all nullable.                                     */
 sis_status sis_geometry_diffusion_solver(sis_geom_t geom, int32_t mode, hipStream_t stream);
-sis_status sis_geometry_diffusion_info(sis_geom_t geom, int32_t* n_inverse, double* residual);
+sis_status sis_geometry_diffusion_info(sis_geom_t geom, int32_t* n_inverse, int32_t* n_distinct,
+                                       double* residual);
 
 /* ------------------------------------------------------------------ compute
  * sis_collide -- collision step of one outer iteration for n_cells cells

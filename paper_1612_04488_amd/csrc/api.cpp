@@ -139,18 +139,20 @@ struct sis_geom {
   // 2-D velocity equation by a precomputed inverse (cases with h_direct[c] != 0)
   std::vector<int32_t> h_direct;
   int32_t *d_direct = nullptr, *d_uidx = nullptr, *d_nunk = nullptr;
-  int64_t *d_uoff = nullptr, *d_aoff = nullptr;
+  int32_t *d_grp_n = nullptr, *d_grp_size = nullptr, *d_grp_case = nullptr;
+  int64_t *d_uoff = nullptr, *d_grp_aoff = nullptr;
   double *ainv = nullptr, *bvec = nullptr, *yvec = nullptr;
-  int max_unknown = 0, n_direct = 0;
+  int max_unknown = 0, n_direct = 0, n_groups = 0, n_inverses = 0;
   double inv_residual = 0.0;     // largest ||I - X S||_F of the scaled inverses
   void free_inverse() {
-    dfree(d_direct); dfree(d_uidx); dfree(d_nunk); dfree(d_uoff); dfree(d_aoff);
+    dfree(d_direct); dfree(d_uidx); dfree(d_nunk); dfree(d_uoff);
+    dfree(d_grp_aoff); dfree(d_grp_n); dfree(d_grp_size); dfree(d_grp_case);
     dfree(ainv); dfree(bvec); dfree(yvec);
-    d_direct = d_uidx = d_nunk = nullptr;
-    d_uoff = d_aoff = nullptr;
+    d_direct = d_uidx = d_nunk = d_grp_n = d_grp_size = d_grp_case = nullptr;
+    d_uoff = d_grp_aoff = nullptr;
     ainv = bvec = yvec = nullptr;
     h_direct.clear();
-    max_unknown = n_direct = 0;
+    max_unknown = n_direct = n_groups = n_inverses = 0;
     inv_residual = 0.0;
   }
   int mom_stride() const { return two_d ? 8 : 4; }
@@ -531,9 +533,13 @@ sis::Diff2DArgs diff2d_args(sis_plan* p, sis_geom* g, const double* mom, const d
     a.direct = g->d_direct;
     a.uidx = g->d_uidx;
     a.uoff = g->d_uoff;
-    a.aoff = g->d_aoff;
     a.n_unknown = g->d_nunk;
     a.max_unknown = g->max_unknown;
+    a.n_groups = g->n_groups;
+    a.grp_aoff = g->d_grp_aoff;
+    a.grp_n = g->d_grp_n;
+    a.grp_size = g->d_grp_size;
+    a.grp_case = g->d_grp_case;
     a.ainv = g->ainv;
     a.bvec = g->bvec;
     a.yvec = g->yvec;
@@ -583,28 +589,45 @@ constexpr int64_t kInverseMaxUnknowns = 16384;
 constexpr double kInverseMaxBytes = 16.0 * 1073741824.0;
 constexpr int kNewtonSchulzMaxIter = 64;
 
+// Same velocity operator on the unknown cells of cases k and r (same cross section)?
+bool same_operator_2d(const sis::Tables2D& t, int k, int r) {
+  const int64_t gk = t.grid_off[k], gr = t.grid_off[r];
+  const int64_t n = t.grid_off[k + 1] - gk;
+  if (t.grid_off[r + 1] - gr != n) return false;
+  for (int64_t i = 0; i < n; ++i) {
+    if (t.dflag[gk + i] != t.dflag[gr + i]) return false;
+    for (int q = 0; q < 4; ++q)
+      if (t.nb[(gk + i) * 8 + q] != t.nb[(gr + i) * 8 + q] || t.fw[(gk + i) * 4 + q] != t.fw[(gr + i) * 4 + q])
+        return false;
+  }
+  return true;
+}
+
 sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
   g->free_inverse();
   const sis::Tables2D& t = g->t2;
   const int nc = g->n_cases;
-  std::vector<int32_t> uidx(t.n_grid, -1), nunk(nc, 0), direct(nc, 0);
-  std::vector<int64_t> uoff(nc + 1, 0), aoff(nc + 1, 0);
-  double bytes = 0.0;
+  std::vector<int32_t> uidx(t.n_grid, -1), nunk(nc, 0), direct(nc, 0), rep(nc, -1);
+  std::vector<int64_t> uoff(nc + 1, 0), aoff(nc, -1);
+  int64_t ainv_size = 0;
   for (int k = 0; k < nc; ++k) {
     const int64_t g0 = t.grid_off[k], g1 = t.grid_off[k + 1];
     for (int64_t G = g0; G < g1; ++G)
       if (t.dflag[G] == 2) uidx[G] = nunk[k]++;
     uoff[k + 1] = uoff[k] + nunk[k];
+    if (nunk[k] > kInverseMaxUnknowns) continue;
+    for (int r = 0; r < k && rep[k] < 0; ++r)
+      if (rep[r] == r && same_operator_2d(t, k, r)) rep[k] = r;
+    if (rep[k] >= 0) continue;
     // every connected group of unknowns must touch a Dirichlet cell
-    bool ok = nunk[k] <= kInverseMaxUnknowns;
-    if (ok && nunk[k] > 0) {
-      std::vector<int32_t> comp(nunk[k], -1), stack;
-      int n_comp = 0;
-      std::vector<char> anchored;
+    bool ok = true;
+    if (nunk[k] > 0) {
+      std::vector<char> seen(nunk[k], 0);
+      std::vector<int32_t> stack;
       for (int64_t G = g0; G < g1 && ok; ++G) {
-        if (t.dflag[G] != 2 || comp[uidx[G]] >= 0) continue;
+        if (t.dflag[G] != 2 || seen[uidx[G]]) continue;
         bool anchor = false;
-        comp[uidx[G]] = n_comp;
+        seen[uidx[G]] = 1;
         stack.assign(1, static_cast<int32_t>(G - g0));
         while (!stack.empty()) {
           const int64_t H = g0 + stack.back();
@@ -613,26 +636,25 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
             if (t.fw[H * 4 + q] == 0.0) continue;
             const int r = t.nb[H * 8 + q];
             if (t.dflag[g0 + r] != 2) { anchor = true; continue; }
-            if (comp[uidx[g0 + r]] < 0) {
-              comp[uidx[g0 + r]] = n_comp;
+            if (!seen[uidx[g0 + r]]) {
+              seen[uidx[g0 + r]] = 1;
               stack.push_back(r);
             }
           }
         }
         ok = anchor;
-        ++n_comp;
       }
     }
-    const double need = static_cast<double>(nunk[k]) * nunk[k] * 8.0;
-    if (ok && bytes + need <= kInverseMaxBytes) {
-      direct[k] = 1;
-      bytes += need;
+    const int64_t need = static_cast<int64_t>(nunk[k]) * nunk[k];
+    if (ok && (ainv_size + need) * 8.0 <= kInverseMaxBytes) {
+      rep[k] = k;
+      aoff[k] = ainv_size;
+      ainv_size += need;
     }
-    aoff[k + 1] = aoff[k] + (direct[k] ? static_cast<int64_t>(nunk[k]) * nunk[k] : 0);
   }
   int max_np = 0;
   for (int k = 0; k < nc; ++k)
-    if (direct[k]) max_np = std::max(max_np, (nunk[k] + 1) & ~1);
+    if (rep[k] == k) max_np = std::max(max_np, (nunk[k] + 1) & ~1);
   // scratch of the iteration: S, X, P, X_next and the residual partials
   const int kBlocks = 1024;
   double *S = nullptr, *X = nullptr, *P = nullptr, *Xn = nullptr, *part = nullptr, *sc = nullptr, *val = nullptr;
@@ -662,21 +684,22 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
     INV_TRY(dmalloc(&sc, max_np));
     INV_TRY(dmalloc(&val, static_cast<size_t>(max_np) * 5));
     INV_TRY(dmalloc(&rc, static_cast<size_t>(max_np) * 10));
-    INV_TRY(dmalloc(&g->ainv, static_cast<size_t>(aoff[nc])));
+    INV_TRY(dmalloc(&g->ainv, static_cast<size_t>(ainv_size)));
   }
   std::vector<double> h_part(kBlocks);
+  std::vector<char> inverted(nc, 0);
   double worst = 0.0;
   for (int k = 0; k < nc; ++k) {
-    if (!direct[k] || nunk[k] == 0) continue;
+    if (rep[k] != k) continue;
     const int nu = nunk[k], np = (nu + 1) & ~1;
+    if (nu == 0) { inverted[k] = 1; continue; }
     const int64_t g0 = t.grid_off[k], g1 = t.grid_off[k + 1];
     // scaled entries: unit diagonal, -fw / sqrt(d_i d_j) to unknown neighbours
-    std::vector<double> dsq(np, 1.0), hs(np, 1.0);
+    std::vector<double> hs(np, 1.0);
     for (int64_t G = g0; G < g1; ++G) {
       if (t.dflag[G] != 2) continue;
       double d = 0.0;
       for (int q = 0; q < 4; ++q) d += t.fw[G * 4 + q];
-      dsq[uidx[G]] = std::sqrt(d);
       hs[uidx[G]] = 1.0 / std::sqrt(d);
     }
     std::vector<int32_t> h_rc;
@@ -753,21 +776,35 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
       INV_TRY(sis::launch_gemm(ga, s));
       std::swap(X, Xn);
     }
-    if (!ok) {
-      direct[k] = 0;
-      continue;
-    }
+    if (!ok) continue;
+    inverted[k] = 1;
     worst = std::max(worst, res);
     INV_TRY(sis::launch_ns_scale(X, np, nu, sc, g->ainv + aoff[k], s));
   }
   INV_TRY(hipStreamSynchronize(s));
   cleanup();
+  // groups of at most kInverseGroup cases per shared inverse
+  std::vector<int64_t> grp_aoff;
+  std::vector<int32_t> grp_n, grp_size, grp_case;
   int n_direct = 0, max_unknown = 0;
-  for (int k = 0; k < nc; ++k)
-    if (direct[k]) {
+  for (int r = 0; r < nc; ++r) {
+    if (rep[r] != r || !inverted[r]) continue;
+    for (int k = r; k < nc; ++k) {
+      if (rep[k] != r) continue;
+      direct[k] = 1;
       ++n_direct;
+      if (nunk[k] == 0) continue;
+      if (grp_n.empty() || grp_aoff.back() != aoff[r] || grp_size.back() == sis::kInverseGroup) {
+        grp_aoff.push_back(aoff[r]);
+        grp_n.push_back(nunk[r]);
+        grp_size.push_back(0);
+        grp_case.resize(grp_case.size() + sis::kInverseGroup, k);
+      }
+      grp_case[(grp_size.size() - 1) * sis::kInverseGroup + grp_size.back()] = k;
+      ++grp_size.back();
       max_unknown = std::max(max_unknown, nunk[k]);
     }
+  }
   if (n_direct == 0) {
     dfree(g->ainv);
     g->ainv = nullptr;
@@ -777,13 +814,20 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
   INV_TRY(upload(&g->d_uidx, uidx, s));
   INV_TRY(upload(&g->d_nunk, nunk, s));
   INV_TRY(upload(&g->d_uoff, uoff, s));
-  INV_TRY(upload(&g->d_aoff, aoff, s));
+  INV_TRY(upload(&g->d_grp_aoff, grp_aoff, s));
+  INV_TRY(upload(&g->d_grp_n, grp_n, s));
+  INV_TRY(upload(&g->d_grp_size, grp_size, s));
+  INV_TRY(upload(&g->d_grp_case, grp_case, s));
   INV_TRY(dmalloc(&g->bvec, static_cast<size_t>(uoff[nc])));
   INV_TRY(dmalloc(&g->yvec, static_cast<size_t>(uoff[nc])));
+  INV_TRY(hipMemsetAsync(g->bvec, 0, std::max<int64_t>(uoff[nc], 1) * sizeof(double), s));
   INV_TRY(hipStreamSynchronize(s));
 #undef INV_TRY
   g->h_direct = direct;
   g->n_direct = n_direct;
+  g->n_groups = static_cast<int>(grp_n.size());
+  g->n_inverses = 0;
+  for (int r = 0; r < nc; ++r) g->n_inverses += (rep[r] == r && inverted[r] && nunk[r] > 0) ? 1 : 0;
   g->max_unknown = max_unknown;
   g->inv_residual = worst;
   (void)p;
@@ -1471,9 +1515,10 @@ sis_status sis_geometry_diffusion_solver(sis_geom_t g, int32_t mode, hipStream_t
   return build_inverse_2d(g->plan, g, stream);
 }
 
-sis_status sis_geometry_diffusion_info(sis_geom_t g, int32_t* n_inverse, double* residual) {
+sis_status sis_geometry_diffusion_info(sis_geom_t g, int32_t* n_inverse, int32_t* n_distinct, double* residual) {
   if (!g) return fail(SIS_E_INVALID, "null geometry");
   if (n_inverse) *n_inverse = g->n_direct;
+  if (n_distinct) *n_distinct = g->n_inverses;
   if (residual) *residual = g->inv_residual;
   return SIS_OK;
 }

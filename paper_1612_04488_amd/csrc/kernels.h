@@ -212,13 +212,20 @@ struct Diff2DArgs {
   const int32_t* direct;     // [n_cases] or null (CG for every case)
   const int32_t* uidx;       // [grid] compact unknown index within its case, -1 otherwise
   const int64_t* uoff;       // [n_cases] offset of the case's unknowns in bvec / yvec
-  const int64_t* aoff;       // [n_cases] offset of the case's inverse in ainv
   const int32_t* n_unknown;  // [n_cases]
   int max_unknown;
-  const double* ainv;        // row-major nu x nu per case
+  // cases with the same cross section share one inverse: group g holds grp_size[g] <= 8 cases
+  // grp_case[g * 8 + m], its inverse at ainv + grp_aoff[g] (row-major grp_n[g]^2)
+  int n_groups;
+  const int64_t* grp_aoff;
+  const int32_t* grp_n;
+  const int32_t* grp_size;
+  const int32_t* grp_case;
+  const double* ainv;
   double* bvec;              // [unknowns]
   double* yvec;              // [unknowns]
 };
+constexpr int kInverseGroup = 8;
 // CG kernel for cases without an inverse, then (if a.direct) right sides, y = A^-1 b, outputs
 hipError_t launch_diffusion2d(const Diff2DArgs& a, hipStream_t s);
 // Newton-Schulz helpers (plan time): per-block sum of squares of I - P into part[blocks];

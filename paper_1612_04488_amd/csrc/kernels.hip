@@ -1251,21 +1251,46 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_rhs_kernel(Diff2DArgs 
   }
 }
 
-// Inverse form, step 2: y = A^-1 b per case, one wave per row of the inverse.
+// Inverse form, step 2: y_c = A^-1 b_c for the cases c of one group (same cross section), one
+// wave per row of the shared inverse, which is read once for all of them.
+template <int G>
+__device__ void d2_gemv_rows(const Diff2DArgs& a, int grp, int row, int lane) {
+  const int nu = a.grp_n[grp];
+  const double* Ar = a.ainv + a.grp_aoff[grp] + static_cast<int64_t>(row) * nu;
+  const double* b[G];
+  double s[G];
+#pragma unroll
+  for (int m = 0; m < G; ++m) {
+    b[m] = a.bvec + a.uoff[a.grp_case[grp * kInverseGroup + m]];
+    s[m] = 0.0;
+  }
+  for (int j = lane; j < nu; j += 64) {
+    const double v = Ar[j];
+#pragma unroll
+    for (int m = 0; m < G; ++m) s[m] += v * b[m][j];
+  }
+#pragma unroll
+  for (int m = 0; m < G; ++m) {
+    const double t = wave_sum(s[m]);
+    if (lane == 0) a.yvec[a.uoff[a.grp_case[grp * kInverseGroup + m]] + row] = t;
+  }
+}
+
 __global__ __launch_bounds__(256) void diffusion2d_gemv_kernel(Diff2DArgs a) {
-  const int cs = blockIdx.y;
-  if (a.case_active && !a.case_active[cs]) return;
-  if (!a.direct[cs] || !a.sis) return;
-  const int nu = a.n_unknown[cs];
+  const int grp = blockIdx.y;
+  if (!a.sis) return;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= nu) return;
-  const int64_t u0 = a.uoff[cs];
-  const double* Ar = a.ainv + a.aoff[cs] + static_cast<int64_t>(row) * nu;
-  const double* b = a.bvec + u0;
-  double s = 0.0;
-  for (int j = lane; j < nu; j += 64) s += Ar[j] * b[j];
-  s = wave_sum(s);
-  if (lane == 0) a.yvec[u0 + row] = s;
+  if (row >= a.grp_n[grp]) return;
+  switch (a.grp_size[grp]) {
+    case 1: d2_gemv_rows<1>(a, grp, row, lane); break;
+    case 2: d2_gemv_rows<2>(a, grp, row, lane); break;
+    case 3: d2_gemv_rows<3>(a, grp, row, lane); break;
+    case 4: d2_gemv_rows<4>(a, grp, row, lane); break;
+    case 5: d2_gemv_rows<5>(a, grp, row, lane); break;
+    case 6: d2_gemv_rows<6>(a, grp, row, lane); break;
+    case 7: d2_gemv_rows<7>(a, grp, row, lane); break;
+    default: d2_gemv_rows<8>(a, grp, row, lane); break;
+  }
 }
 
 // Inverse form, step 3: outputs, flow rates, convergence.
@@ -1480,8 +1505,8 @@ hipError_t launch_diffusion2d(const Diff2DArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(diffusion2d_kernel, dim3(a.n_cases), dim3(kD2Threads), 0, s, a);
   if (a.direct) {
     hipLaunchKernelGGL(diffusion2d_rhs_kernel, dim3(a.n_cases), dim3(kD2Threads), 0, s, a);
-    if (a.max_unknown > 0)
-      hipLaunchKernelGGL(diffusion2d_gemv_kernel, dim3((a.max_unknown + 3) / 4, a.n_cases), dim3(256), 0, s, a);
+    if (a.max_unknown > 0 && a.n_groups > 0)
+      hipLaunchKernelGGL(diffusion2d_gemv_kernel, dim3((a.max_unknown + 3) / 4, a.n_groups), dim3(256), 0, s, a);
     hipLaunchKernelGGL(diffusion2d_out_kernel, dim3(a.n_cases), dim3(kD2Threads), 0, s, a);
   }
   return hipGetLastError();

@@ -169,3 +169,37 @@ def porous_cases(w):
     mask, _ = porous_discs(w["cells"])
     f = np.linspace(0.0, 1.0, w["cells"] + 1)
     return [(f, f, mask) for _ in w["deltas"]]
+
+
+# --------------------------------------------------------------- Sierpinski carpets (Sec. 3.1)
+def sierpinski_quarter(level, cells):
+    """Quarter [-1/2, 0]^2 of the Sierpinski carpet of recursion `level` on the
+    square [-1/2, 1/2]^2 (walls on its sides), `cells` uniform cells per side
+    of the quarter.  Level r removes, inside every remaining square of side
+    3^(1-r), the central square of side 3^-r; removed squares are solid.
+    Returns (face1, face2, solid) for the quarter-duct geometry (symmetry
+    planes at x1 = 0 and x2 = 0); 2 * cells must be a multiple of 3^level."""
+    n = 2 * cells
+    if n % 3 ** level:
+        raise ValueError("2 * cells must be a multiple of 3**level")
+    s = n // 3 ** level                       # cells per finest square
+    m = np.arange(cells) // s                 # finest-square index of each quarter cell
+    solid = np.zeros((cells, cells), bool)
+    for r in range(1, level + 1):
+        d = (m // 3 ** (level - r)) % 3 == 1  # r-th ternary digit is the middle one
+        solid |= d[:, None] & d[None, :]
+    f = np.linspace(-0.5, 0.0, cells + 1)
+    return f, f.copy(), solid
+
+
+# Sierpinski carpets as in the paper's Sec. 3.1: levels 1-3 on 60^2, 90^2, 135^2
+# uniform quarter cells; hard spheres, 24^3 velocities (v3 > 0 stored), N = 1.5,
+# delta in {0.1, 1, 10, 100}; the benchmark line runs level 3.
+SIERPINSKI_CELLS = {0: 45, 1: 60, 2: 90, 3: 135}
+SIERPINSKI_HS = dict(name="sierpinski-l3-hs-24v-135sq-4cases", n_v=24, l_v=6.0, n_pad=48, m_angle=8,
+                     kernel="hs", level=3, cells=135, deltas=[0.1, 1.0, 10.0, 100.0], flows=[1] * 4)
+
+
+def sierpinski_cases(w):
+    c = sierpinski_quarter(w["level"], w["cells"])
+    return [c for _ in w["deltas"]]

@@ -102,7 +102,8 @@ _SIGS = {
     "sis_geometry_cells": (ctypes.c_int64, [_P]),
     "sis_geometry_moment_stride": (ctypes.c_int32, [_P]),
     "sis_geometry_diffusion_solver": (ctypes.c_int32, [_P, ctypes.c_int32, _P]),
-    "sis_geometry_diffusion_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), _D]),
+    "sis_geometry_diffusion_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32),
+                                                     ctypes.POINTER(ctypes.c_int32), _D]),
     "sis_collide": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     "sis_transport_sweep": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
     "sis_moments": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P]),
@@ -364,11 +365,11 @@ class Geometry2D:
         check(lib().sis_geometry_diffusion_solver(self.handle, m, _stream(stream)))
 
     def diffusion_info(self):
-        """(number of cases solved with the inverse, largest Frobenius residual of the inverses)."""
-        n = ctypes.c_int32()
+        """(cases solved with the inverse, distinct inverses held, largest Frobenius residual)."""
+        n, d = ctypes.c_int32(), ctypes.c_int32()
         r = ctypes.c_double()
-        check(lib().sis_geometry_diffusion_info(self.handle, ctypes.byref(n), ctypes.byref(r)))
-        return int(n.value), float(r.value)
+        check(lib().sis_geometry_diffusion_info(self.handle, ctypes.byref(n), ctypes.byref(d), ctypes.byref(r)))
+        return int(n.value), int(d.value), float(r.value)
 
     def close(self):
         if getattr(self, "handle", None):

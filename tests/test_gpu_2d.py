@@ -100,8 +100,9 @@ def test_diffusion2d_parity(kind, solver):
     deltas, flows = [2.0, 30.0], [1, 2]
     geom = sis.Geometry2D(p, kind, cases, deltas, flows)
     geom.diffusion_solver(solver)
-    n_inv, res = geom.diffusion_info()
+    n_inv, n_dist, res = geom.diffusion_info()
     assert n_inv == (len(cases) if solver == "inverse" else 0)
+    assert n_dist == (len(cases) if solver == "inverse" else 0)
     assert res < 1e-8
     grids = oracle_grids(kind, cases)
     nc = geom.n_cells
@@ -160,9 +161,9 @@ def test_diffusion2d_inverse_at_full_size(kind):
         cases = inputs.porous_cases(w)[:1]
     deltas, flows = [5.0] * len(cases), [1] * len(cases)
     geom = sis.Geometry2D(p, kind, cases, deltas, flows)
-    n_inv, res = geom.diffusion_info()
-    say("inverse cases", n_inv, "residual", res)
-    assert n_inv == len(cases) and res < 1e-8
+    n_inv, n_dist, res = geom.diffusion_info()
+    say("inverse cases", n_inv, "distinct", n_dist, "residual", res)
+    assert n_inv == len(cases) and n_dist == len(cases) and res < 1e-8
     nc = geom.n_cells
     rng = np.random.default_rng(12)
     mom = rng.standard_normal((nc, 8)) * 0.1
@@ -193,4 +194,35 @@ def test_inverse_falls_back_on_singular_cases():
     f = np.linspace(0, 1, 7)
     cases = [(f, f, np.zeros((6, 6), bool)), CASES["periodic"][1]]
     geom = sis.Geometry2D(p, "periodic", cases, [1.0, 1.0], [0, 1])
-    assert geom.diffusion_info()[0] == 1
+    assert geom.diffusion_info()[:2] == (1, 1)
+
+
+def test_shared_inverse_for_equal_cross_sections():
+    """Cases with the same cross section share one inverse (applied to up to
+    eight right sides per read): eleven cases over two cross sections (one of
+    them nine times, so split over two reads) hold two inverses, and every
+    case's velocity matches the oracle."""
+    say("shared inverse")
+    p = plan(8, 4.0, 3)
+    base = CASES["periodic"]
+    order = [0, 1, 1, 0, 1, 1, 1, 1, 1, 1, 1]
+    cases = [base[i] for i in order]
+    deltas = [0.5 + 0.7 * k for k in range(len(cases))]
+    flows = [1, 2] * 5 + [1]
+    geom = sis.Geometry2D(p, "periodic", cases, deltas, flows)
+    n_inv, n_dist, res = geom.diffusion_info()
+    assert n_inv == len(cases) and n_dist == 2 and res < 1e-8
+    nc = geom.n_cells
+    rng = np.random.default_rng(6)
+    mom = rng.standard_normal((nc, 8))
+    amom = rng.standard_normal((nc, 4))
+    U = torch.empty(nc, dtype=torch.float64, device=DEV)
+    sis.diffusion_correct(p, geom, dev(mom), dev(amom), 1.3, U, None)
+    torch.cuda.synchronize()
+    U = U.cpu().numpy()
+    grids = oracle_grids("periodic", cases)
+    o = geom.offsets
+    for c, g in enumerate(grids):
+        s = slice(o[c], o[c + 1])
+        ref = duct.diffusion_2d(g, mom[s], amom[s], deltas[c], 1.3, flows[c])
+        assert rel(U[s], ref) < 1e-10, c

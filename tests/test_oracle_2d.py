@@ -120,3 +120,46 @@ def test_porous_generator():
             assert np.hypot(*d) >= discs[a][1] + discs[b][1]
     m2, _ = inputs.porous_discs(128)
     assert np.array_equal(mask, m2)
+
+
+def test_sierpinski_carpet_geometry():
+    """Sec. 3.1 carpets: porosity (8/9)^level exactly, each level keeps the
+    solids of the previous one, and the quarter is symmetric about its diagonal."""
+    for level, cells in inputs.SIERPINSKI_CELLS.items():
+        f1, f2, s = inputs.sierpinski_quarter(level, cells)
+        assert len(f1) == cells + 1 and f1[0] == -0.5 and f1[-1] == 0.0
+        assert abs((1.0 - s.mean()) - (8.0 / 9.0) ** level) < 1e-14
+        assert np.array_equal(s, s.T)
+        if level > 0:
+            prev = inputs.sierpinski_quarter(level - 1, cells)[2]
+            assert np.all(s[prev])
+    # level 1: the central square of side 1/3 is the corner [-1/6, 0]^2 of the quarter
+    s = inputs.sierpinski_quarter(1, 6)[2]
+    assert s[4:, 4:].all() and s.sum() == 4
+    with pytest.raises(ValueError):
+        inputs.sierpinski_quarter(2, 10)
+
+
+def test_free_molecular_sierpinski_ratios():
+    """delta = 0 on the level-1 carpet: M_T = Q_P exactly (the scheme keeps
+    Onsager's reciprocity), and the geometry-independent ratios of the
+    free-molecular limit, -Q_P/M_P = 1/2 and Q_T/M_P = 9/4 (the velocity
+    integrals factor out of the path-length integral), hold after
+    extrapolating N = 32, 48; the carpet passes less gas than the plain duct."""
+    f1, f2, s = inputs.sierpinski_quarter(1, 6)
+    bc = (duct.WALL, duct.SYM, duct.WALL, duct.SYM)
+    g = duct.Grid2D(f1, f2, bc, s)
+    g0 = duct.Grid2D(f1, f2, bc)
+    res = {}
+    for N in (32, 48):
+        op = FreeMolecular(VelocityGrid(N, 4.0))
+        rP = duct.solve_2d(op, g, 0.0, POISEUILLE, "CIS", eps=1e-12, max_it=3)
+        rT = duct.solve_2d(op, g, 0.0, TRANSPIRATION, "CIS", eps=1e-12, max_it=3)
+        assert abs(rT["M"] - rP["Q"]) < 1e-14
+        res[N] = (rP["M"], rP["Q"], rT["Q"])
+        if N == 32:
+            r0 = duct.solve_2d(op, g0, 0.0, POISEUILLE, "CIS", eps=1e-12, max_it=3)
+            assert rP["M"] < 0.7 * r0["M"]
+    M, Q, QT = [(48 * a - 32 * b) / 16 for a, b in zip(res[48], res[32])]
+    assert abs(-Q / M - 0.5) < 5e-3
+    assert abs(QT / M - 2.25) < 1e-2
