@@ -140,9 +140,10 @@ typedef struct {
  * Gauss-Legendre rule on [0, R] (mirrored) otherwise.  delta is normalised
  * with the mixture viscosity (first Chapman-Enskog, hard spheres) and the
  * mixture most probable speed: every table carries sqrt(m_A/m) mu_mix/mu_A.
- * Supported: planar geometry, Poiseuille flow (SIS_FLOW_POISEUILLE or NONE),
- * no invariant projection.  Per-cell arrays of the compute calls become
- * per (cell, species) as stated at each call.                               */
+ * Supported: planar and 2-D geometries (2-D: the velocity equations need the
+ * precomputed inverse of every case), Poiseuille flow (SIS_FLOW_POISEUILLE or
+ * NONE), no invariant projection.  Per-cell arrays of the compute calls
+ * become per (cell, species) as stated at each call.                        */
 
 /* Build the tables on the host (threads) and assemble the operator on the
  * current device with `stream`.  Synchronous.  Owns ~8 n_dof^2 bytes of
@@ -273,9 +274,11 @@ sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const 
  * h_half_out is in/out there.  mom_out: [cells][8] =
  * { U3, q3, G1, G12 = F_111/4, G2 = F_021/4, P13, P23, 0 }.
  * rhs, h_half_out: [cells][n3]; moments are midpoint sums with weight dv^3.
- * Mixtures (planar): each species is swept with its own nu_a; rhs, h_half_out
- * [cells][2][n3]; mom_out [cells][2][4] = { int v3 h_a, q_a =
- * int (m_a v^2/m_A - 5/2) v3 h_a, G1, P_a13 = 2 (m_a/m_A) int v1 v3 h_a }.    */
+ * Mixtures: each species is swept with its own nu_a; rhs, h_half_out
+ * [cells][2][n3]; planar mom_out [cells][2][4] = { int v3 h_a, q_a =
+ * int (m_a v^2/m_A - 5/2) v3 h_a, G1, P_a13 = 2 (m_a/m_A) int v1 v3 h_a };
+ * 2-D mom_out [cells][2][8] = { U3, q_a, G1, G12, G2, P_a13, P_a23, 0 } with
+ * the same mass factor in q_a and P_a13, P_a23 = 2 (m_a/m_A) int v2 v3 h_a.    */
 sis_status sis_transport_sweep(sis_plan_t plan, sis_geom_t geom, const double* rhs,
                                double* h_half_out, double* mom_out, hipStream_t stream);
 
@@ -304,7 +307,14 @@ sis_status sis_moments(sis_plan_t plan, int64_t n_cells, const double* h, double
  *   chi_A d(U_A)/dx1 + d(G1_A)/dx1 = -N_A delta (x1 - P_B13) + A_A,
  * A_a = amom[c][a][0] + N_a delta amom[c][a][1], P_B13 from mom_half;
  * N <= 0 -> N_a = int nu_a f_a / chi_a, else N_A = N_B = N.  mom_half,
- * amom [cells][2][4]; U_out, dU_out [cells][2].                               */
+ * amom [cells][2][4]; U_out, dU_out [cells][2].
+ * 2-D mixtures (eqs. LBE2_true2, LBE2_true1 as printed, one Poisson problem
+ * per species on the single-gas finite-volume operator and its inverse):
+ *   chi_B lap U_B = -N_B delta (m_A/m_B) div P_B - (d11 G1_B + 2 d12 G12_B + d22 G2_B) + d1 A1_B + d2 A2_B,
+ *   chi_A lap U_A = N_A delta (div P_B - 1) - (d11 G1_A + ...) + d1 A1_A + d2 A2_A,
+ * div P_B = d1 P_B13 + d2 P_B23 (central differences) of mom_half,
+ * A2_a = amom[c][a][2] + N_a delta amom[c][a][3]; U_a = U3_a / chi_a next to
+ * a wall or solid.  mom_half [cells][2][8], amom [cells][2][4].              */
 sis_status sis_diffusion_correct(sis_plan_t plan, sis_geom_t geom, const double* mom_half,
                                  const double* amom, double N, double* U_out, double* dU_out,
                                  hipStream_t stream);
@@ -316,7 +326,8 @@ sis_status sis_diffusion_correct(sis_plan_t plan, sis_geom_t geom, const double*
  * or max_it.  One iteration = sis_collide + sis_transport_sweep (+
  * sis_diffusion_correct for SIS) + flow rates, launched as a captured HIP
  * graph.  Converged cases are frozen while the others continue.  Results are
- * copied to HOST arrays (each nullable).  Synchronous.                      */
+ * copied to HOST arrays (each nullable).  Synchronous.  2-D: M = (1/A) sum U3 dA
+ * over the fluid cells, A the whole cross-section (solids included).        */
 typedef struct {
   int32_t scheme;        /* SIS_SCHEME_*                                   */
   double  N;             /* penalty parameter; <= 0 -> nubar (Sec. 2.5)    */
@@ -336,7 +347,8 @@ typedef struct {
 } sis_solve_opts;
 
 /* Mixtures: M, Q are [n_cases][2] (M_a = sqrt(m/m_A) 2 int U_a dx1, Q_a
- * likewise with q_a; all four must meet eps), U, q are [cells][2].          */
+ * likewise with q_a; 2-D: sqrt(m/m_A) (1/A) sum U_a dA; all four must meet
+ * eps), U, q are [cells][2].                                                */
 typedef struct {
   double*  M;            /* [n_cases] mass flow rate                                   */
   double*  Q;            /* [n_cases] heat flow rate                                   */

@@ -265,13 +265,18 @@ def _pos2(g, j):
     return 2 * plane - g.c2[-j - 1 if j < 0 else 2 * g.n2 - 1 - j]
 
 
-def diffusion_2d(g, mom, amom, delta, N, flow):
+def diffusion_2d(g, mom, amom, delta, N, flow, chi=1.0, source=None, div_p=None, div_coef=0.0):
     """Solve the discrete eq. diffusion_LBE; returns U on the fluid cells.
 
     mom: (n_fluid, >= 5) with U3, q3, G1, G12, G2 of h^{k+1/2};
     amom: (n_fluid, 4) {2 sum w v1 v3 L, 2 sum w v1 v3 h, 2 sum w v2 v3 L, 2 sum w v2 v3 h}.
+    Species form (eqs. LBE2_true2, LBE2_true1): chi lap U = source + div_coef
+    (d1 P13 + d2 P23) - (...) + d1 A1 + d2 A2 with U = U3 / chi, div_p =
+    (P13, P23) per fluid cell; source None -> -N delta for Poiseuille flow.
     """
-    Uh = _field(g, mom[:, 0])
+    Uh = _field(g, mom[:, 0] / chi)
+    if div_p is not None:
+        P13, P23 = _field(g, div_p[0]), _field(g, div_p[1])
     G1, G12, G2 = _field(g, mom[:, 2]), _field(g, mom[:, 3]), _field(g, mom[:, 4])
     A1 = _field(g, amom[:, 0] + N * delta * amom[:, 1])
     A2 = _field(g, amom[:, 2] + N * delta * amom[:, 3])
@@ -302,13 +307,17 @@ def diffusion_2d(g, mom, amom, delta, N, flow):
 
     for r, (i, j) in enumerate(cells):
         rhs = 0.0
-        if flow == POISEUILLE:
+        if source is not None:
+            rhs += source
+        elif flow == POISEUILLE:
             rhs -= N * delta
+        if div_p is not None:
+            rhs += div_coef * (d1(P13, O1, i, j) + d2(P23, O2, i, j))
         cross = (_d2_at(g, G12, O12, i + 1, j) - _d2_at(g, G12, O12, i - 1, j)) / (_pos1(g, i + 1) - _pos1(g, i - 1))
         rhs -= d11(G1, EV, i, j) + 2.0 * cross + d22(G2, EV, i, j)
         rhs += d1(A1, O1, i, j) + d2(A2, O2, i, j)
         # -lap U * dA = sum_faces (U_P - U_N) len / dist
-        bi = -rhs * g.dA[i, j]
+        bi = -(rhs / chi) * g.dA[i, j]
         diag = 0.0
         for (ii, jj, L, dist) in ((i + 1, j, g.w2[j], _pos1(g, i + 1) - g.c1[i]),
                                   (i - 1, j, g.w2[j], g.c1[i] - _pos1(g, i - 1)),

@@ -378,3 +378,108 @@ def free_molecular_1d(op):
     Q = np.array([fac * 0.5 * g.integrate((op.a[s] * g.vsq - 2.5) * g.V3 ** 2 * op.feq[s] / av)
                   for s in range(2)])
     return M, Q
+
+
+# ------------------------------------------------------------------ rectangular ducts (Sec. 5.3, Table 5)
+def sweep_2d(op, rhs, g, delta, h_prev):
+    """Each species swept over the cross section with its own delta nu_a (the
+    single-gas 2-D sweep).  rhs, h_prev: (n_fluid, 2, N, N, N)."""
+    from . import duct
+    return np.stack([duct.sweep_2d(rhs[:, s], delta * op.nu[s], g, op.grid, h_prev[:, s])
+                     for s in range(2)], axis=1)
+
+
+def moments_2d(op, h):
+    """(n, 2, 7): U3_a = int v3 h_a, q_a = int (a v^2 - 5/2) v3 h_a, G1_a, G12_a, G2_a
+    (F^a_{201}/4, F^a_{111}/4, F^a_{021}/4) and P_a13, P_a23 = 2 a int v1,2 v3 h_a."""
+    g = op.grid
+    out = np.zeros(h.shape[:2] + (7,))
+    for s in range(2):
+        hs = h[:, s]
+        out[:, s, 0] = g.U3(hs)
+        out[:, s, 1] = g.integrate((op.a[s] * g.vsq - 2.5) * g.V3 * hs)
+        out[:, s, 2] = g.G1(hs)
+        out[:, s, 3] = g.G12(hs)
+        out[:, s, 4] = g.G2(hs)
+        out[:, s, 5] = op.a[s] * g.P13(hs)
+        out[:, s, 6] = op.a[s] * g.P23(hs)
+    return out
+
+
+def velocity_2d(op, g, mom, amom, delta, N, poiseuille=True):
+    """SIS velocity equations on a cross section, eqs. LBE2_true2 (B) and
+    LBE2_true1 (A) as printed (two Poisson problems, one per species):
+      chi_B lap U_B = -N_B delta (m_A/m_B) div P_B - (d11 G1_B + 2 d12 G12_B + d22 G2_B) + d1 A1_B + d2 A2_B,
+      chi_A lap U_A = N_A delta (div P_B - 1) - (d11 G1_A + ...) + d1 A1_A + d2 A2_A,
+    with A1_a, A2_a = 2 int v1,2 v3 (L_a + N_a delta h_a^k), div P_B of h^{k+1/2},
+    U_a = U3_a / chi_a at the cells next to a wall or solid; the single-gas
+    finite-volume discretisation.  mom (n, 2, 7), amom (n, 2, 4); returns U (n, 2)."""
+    from . import duct
+    N = np.broadcast_to(np.asarray(N, float), (2,))
+    PB = (mom[:, 1, 5], mom[:, 1, 6])
+    U = np.zeros((mom.shape[0], 2))
+    for s in range(2):
+        Nd = N[s] * delta
+        if s == 1:
+            src, coef = 0.0, -Nd / op.a[1]
+        else:
+            src, coef = (-Nd if poiseuille else 0.0), Nd
+        U[:, s] = duct.diffusion_2d(g, mom[:, s], amom[:, s], delta, N[s], duct.POISEUILLE if poiseuille else 0,
+                                    chi=op.chi[s], source=src, div_p=PB, div_coef=coef)
+    return U
+
+
+def collide_2d(op, h, dU, delta, poiseuille=True):
+    """`collide_1d` with the v2 v3 moments too: amom (n, 2, 4) = {2 int v1 v3 L_a,
+    2 int v1 v3 h_a^k, 2 int v2 v3 L_a, 2 int v2 v3 h_a^k}."""
+    g = op.grid
+    rhs, L, _ = collide_1d(op, h, dU, delta, poiseuille)
+    hk = h + np.asarray(dU)[:, :, None, None, None] * correction_shapes(op)
+    amom = np.stack([2.0 * g.integrate(g.V1 * g.V3 * L), 2.0 * g.integrate(g.V1 * g.V3 * hk),
+                     2.0 * g.integrate(g.V2 * g.V3 * L), 2.0 * g.integrate(g.V2 * g.V3 * hk)], axis=-1)
+    return rhs, L, amom
+
+
+def solve_mixture_2d(op, g, delta, scheme="SIS", Npen=None, eps=1e-8, max_it=5000):
+    """Poiseuille flow of the binary mixture through a cross section from h^0 = 0:
+    `collide_2d`, `sweep_2d`, `moments_2d`; SIS: `velocity_2d` and the
+    correction h_a += 2 a_a (U_a - U_a^{k+1/2}) v3 f_a.  Flow rates
+    M_a = sqrt(m/m_A) (1/A) sum U_a dA, Q_a = sqrt(m/m_A) (1/A) sum q_a dA;
+    stop when the relative change of all four is below eps."""
+    from . import duct
+    vg = op.grid
+    N = op.nubar() if Npen is None else np.broadcast_to(np.asarray(Npen, float), (2,))
+    nf = len(g.cells)
+    corr = correction_shapes(op)
+    cU = np.array([vg.U3(corr[s]) / op.chi[s] for s in range(2)])
+    cq = np.array([vg.integrate((op.a[s] * vg.vsq - 2.5) * vg.V3 * corr[s]) for s in range(2)])
+    fac = math.sqrt(op.mbar / op.m[0])
+    h = np.zeros((nf, 2) + vg.feq.shape)
+    dU = np.zeros((nf, 2))
+    M_old = np.zeros(2)
+    Q_old = np.zeros(2)
+    converged = False
+    it = 0
+    for it in range(1, max_it + 1):
+        rhs, L, amom = collide_2d(op, h, dU, delta)
+        h = sweep_2d(op, rhs, g, delta, h)
+        mom = moments_2d(op, h)
+        U_half = mom[:, :, 0] / op.chi
+        if scheme == "SIS":
+            dU = velocity_2d(op, g, mom, amom, delta, N) - U_half
+        elif scheme == "CIS":
+            dU = np.zeros((nf, 2))
+        else:
+            raise ValueError(scheme)
+        Un = U_half + dU * cU
+        qn = mom[:, :, 1] + dU * cq
+        MQ = [duct.flow_rates_2d(g, Un[:, s], qn[:, s]) for s in range(2)]
+        M = fac * np.array([m[0] for m in MQ])
+        Q = fac * np.array([m[1] for m in MQ])
+        res = float(np.max(np.concatenate([np.abs(M - M_old) / np.maximum(np.abs(M), 1e-300),
+                                           np.abs(Q - Q_old) / np.maximum(np.abs(Q), 1e-300)])))
+        M_old, Q_old = M, Q
+        if res < eps:
+            converged = True
+            break
+    return dict(M=M, Q=Q, iters=it, converged=converged, residual=res, U=Un, q=qn, dU=dU, h_half=h, N=N)

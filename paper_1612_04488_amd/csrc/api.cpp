@@ -139,17 +139,17 @@ struct sis_geom {
   // 2-D velocity equation by a precomputed inverse (cases with h_direct[c] != 0)
   std::vector<int32_t> h_direct;
   int32_t *d_direct = nullptr, *d_uidx = nullptr, *d_nunk = nullptr;
-  int32_t *d_grp_n = nullptr, *d_grp_size = nullptr, *d_grp_case = nullptr;
-  int64_t *d_uoff = nullptr, *d_grp_aoff = nullptr;
+  int32_t *d_grp_n = nullptr, *d_grp_size = nullptr;
+  int64_t *d_uoff = nullptr, *d_grp_aoff = nullptr, *d_grp_vec = nullptr;
   double *ainv = nullptr, *bvec = nullptr, *yvec = nullptr;
   int max_unknown = 0, n_direct = 0, n_groups = 0, n_inverses = 0;
   double inv_residual = 0.0;     // largest ||I - X S||_F of the scaled inverses
   void free_inverse() {
     dfree(d_direct); dfree(d_uidx); dfree(d_nunk); dfree(d_uoff);
-    dfree(d_grp_aoff); dfree(d_grp_n); dfree(d_grp_size); dfree(d_grp_case);
+    dfree(d_grp_aoff); dfree(d_grp_n); dfree(d_grp_size); dfree(d_grp_vec);
     dfree(ainv); dfree(bvec); dfree(yvec);
-    d_direct = d_uidx = d_nunk = d_grp_n = d_grp_size = d_grp_case = nullptr;
-    d_uoff = d_grp_aoff = nullptr;
+    d_direct = d_uidx = d_nunk = d_grp_n = d_grp_size = nullptr;
+    d_uoff = d_grp_aoff = d_grp_vec = nullptr;
     ainv = bvec = yvec = nullptr;
     h_direct.clear();
     max_unknown = n_direct = n_groups = n_inverses = 0;
@@ -449,6 +449,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     sis::Sweep2DArgs a{};
     a.n = p->n;
     a.n3 = p->nv;
+    a.nsp = p->nsp;
     a.d3 = p->d3;
     a.v3d = p->v1d + (p->n - p->d3);
     a.n_cases = g->n_cases;
@@ -467,7 +468,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.case_active = case_active;
     HIP_TRY(sis::launch_sweep2d(a, s));
     if (mom)
-      HIP_TRY(sis::launch_moments2d(p->n, p->d3, g->n_cells, p->v1d, p->v1d + (p->n - p->d3), h, p->wr, cell_active,
+      HIP_TRY(sis::launch_moments2d(p->n, p->d3, p->nsp, p->mass_ratio, g->n_cells, p->v1d, p->v1d + (p->n - p->d3), h, p->wr, cell_active,
                                     mom, s));
     return SIS_OK;
   }
@@ -504,6 +505,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
 sis::Diff2DArgs diff2d_args(sis_plan* p, sis_geom* g, const double* mom, const double* amom, double N) {
   sis::Diff2DArgs a{};
   a.n_cases = g->n_cases;
+  a.n_grid = g->t2.n_grid;
   a.n2 = g->d_n2;
   a.grid_off = g->d_goff;
   a.dflag = g->d_dflag;
@@ -520,10 +522,26 @@ sis::Diff2DArgs diff2d_args(sis_plan* p, sis_geom* g, const double* mom, const d
   a.flow_case = g->flow_case;
   a.mom = mom;
   a.amom = amom;
-  a.N = N;
   a.sis = 1;
-  a.cU = p->cU;
-  a.cq = p->cq;
+  // species: N <= 0 -> nubar of each species (one gas: the caller's N)
+  a.nsp = p->nsp;
+  if (p->nsp == 1) {
+    a.chi[0] = 1.0;
+    a.mass_ratio[0] = 1.0;
+    a.Ns[0] = N;
+    a.cUs[0] = p->cU;
+    a.cqs[0] = p->cq;
+    a.flow_factor = 1.0;
+  } else {
+    for (int s = 0; s < 2; ++s) {
+      a.chi[s] = p->chi[s];
+      a.mass_ratio[s] = p->mass_ratio[s];
+      a.Ns[s] = N > 0.0 ? N : p->nubar_s[s];
+      a.cUs[s] = p->cU_s[s];
+      a.cqs[s] = p->cq_s[s];
+    }
+    a.flow_factor = p->flow_factor;
+  }
   a.work = g->work;
   a.have_x = g->have_x;
   a.tol = 1e-13;
@@ -539,7 +557,7 @@ sis::Diff2DArgs diff2d_args(sis_plan* p, sis_geom* g, const double* mom, const d
     a.grp_aoff = g->d_grp_aoff;
     a.grp_n = g->d_grp_n;
     a.grp_size = g->d_grp_size;
-    a.grp_case = g->d_grp_case;
+    a.grp_vec = g->d_grp_vec;
     a.ainv = g->ainv;
     a.bvec = g->bvec;
     a.yvec = g->yvec;
@@ -783,9 +801,10 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
   }
   INV_TRY(hipStreamSynchronize(s));
   cleanup();
-  // groups of at most kInverseGroup cases per shared inverse
-  std::vector<int64_t> grp_aoff;
-  std::vector<int32_t> grp_n, grp_size, grp_case;
+  // groups of at most kInverseGroup right sides (case, species) per shared inverse
+  const int nsp = p->nsp;
+  std::vector<int64_t> grp_aoff, grp_vec;
+  std::vector<int32_t> grp_n, grp_size;
   int n_direct = 0, max_unknown = 0;
   for (int r = 0; r < nc; ++r) {
     if (rep[r] != r || !inverted[r]) continue;
@@ -794,16 +813,24 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
       direct[k] = 1;
       ++n_direct;
       if (nunk[k] == 0) continue;
-      if (grp_n.empty() || grp_aoff.back() != aoff[r] || grp_size.back() == sis::kInverseGroup) {
-        grp_aoff.push_back(aoff[r]);
-        grp_n.push_back(nunk[r]);
-        grp_size.push_back(0);
-        grp_case.resize(grp_case.size() + sis::kInverseGroup, k);
+      for (int s = 0; s < nsp; ++s) {
+        const int64_t voff = nsp * uoff[k] + static_cast<int64_t>(s) * nunk[k];
+        if (grp_n.empty() || grp_aoff.back() != aoff[r] || grp_size.back() == sis::kInverseGroup) {
+          grp_aoff.push_back(aoff[r]);
+          grp_n.push_back(nunk[r]);
+          grp_size.push_back(0);
+          grp_vec.resize(grp_vec.size() + sis::kInverseGroup, voff);
+        }
+        grp_vec[(grp_size.size() - 1) * sis::kInverseGroup + grp_size.back()] = voff;
+        ++grp_size.back();
       }
-      grp_case[(grp_size.size() - 1) * sis::kInverseGroup + grp_size.back()] = k;
-      ++grp_size.back();
       max_unknown = std::max(max_unknown, nunk[k]);
     }
+  }
+  if (nsp == 2 && n_direct < nc) {
+    g->free_inverse();
+    return fail(SIS_E_UNSUPPORTED,
+                "2-D mixtures need the precomputed inverse of every case (a case is singular or too large)");
   }
   if (n_direct == 0) {
     dfree(g->ainv);
@@ -817,10 +844,10 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
   INV_TRY(upload(&g->d_grp_aoff, grp_aoff, s));
   INV_TRY(upload(&g->d_grp_n, grp_n, s));
   INV_TRY(upload(&g->d_grp_size, grp_size, s));
-  INV_TRY(upload(&g->d_grp_case, grp_case, s));
-  INV_TRY(dmalloc(&g->bvec, static_cast<size_t>(uoff[nc])));
-  INV_TRY(dmalloc(&g->yvec, static_cast<size_t>(uoff[nc])));
-  INV_TRY(hipMemsetAsync(g->bvec, 0, std::max<int64_t>(uoff[nc], 1) * sizeof(double), s));
+  INV_TRY(upload(&g->d_grp_vec, grp_vec, s));
+  INV_TRY(dmalloc(&g->bvec, static_cast<size_t>(nsp * uoff[nc])));
+  INV_TRY(dmalloc(&g->yvec, static_cast<size_t>(nsp * uoff[nc])));
+  INV_TRY(hipMemsetAsync(g->bvec, 0, std::max<int64_t>(nsp * uoff[nc], 1) * sizeof(double), s));
   INV_TRY(hipStreamSynchronize(s));
 #undef INV_TRY
   g->h_direct = direct;
@@ -830,7 +857,6 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
   for (int r = 0; r < nc; ++r) g->n_inverses += (rep[r] == r && inverted[r] && nunk[r] > 0) ? 1 : 0;
   g->max_unknown = max_unknown;
   g->inv_residual = worst;
-  (void)p;
   return SIS_OK;
 }
 
@@ -910,7 +936,7 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
   G2_TRY(upload(&g->delta_cell, dcell, stream));
   G2_TRY(upload(&g->flow_cell, fcell, stream));
   G2_TRY(upload(&g->case_of_cell, t.cell_case, stream));
-  G2_TRY(dmalloc(&g->work, static_cast<size_t>(t.n_grid) * 10));
+  G2_TRY(dmalloc(&g->work, static_cast<size_t>(t.n_grid) * sis::kDiffWork * p->nsp));
   G2_TRY(upload(&g->have_x, std::vector<int32_t>(d->n_cases, 0), stream));
   G2_TRY(upload(&g->cg_iters, std::vector<int32_t>(d->n_cases, 0), stream));
   G2_TRY(hipStreamSynchronize(stream));
@@ -1395,7 +1421,6 @@ sis_status sis_geometry_create(sis_plan_t p, const sis_geometry_desc* d, hipStre
   if (p->parity == 2 && d->kind != SIS_GEOM_PLANAR_HALF)
     return fail(SIS_E_UNSUPPORTED, "parity 2 (even in v2) needs the planar geometry");
   if (p->nsp == 2) {
-    if (d->kind != SIS_GEOM_PLANAR_HALF) return fail(SIS_E_UNSUPPORTED, "mixtures support the planar geometry only");
     for (int c = 0; c < d->n_cases; ++c)
       if (d->flow && d->flow[c] != SIS_FLOW_NONE && d->flow[c] != SIS_FLOW_POISEUILLE)
         return fail(SIS_E_UNSUPPORTED, "mixtures support Poiseuille flow only (case %d)", c);
@@ -1506,6 +1531,7 @@ sis_status sis_geometry_diffusion_solver(sis_geom_t g, int32_t mode, hipStream_t
     return fail(SIS_E_INVALID, "diffusion solver mode %d", mode);
   if (!g->two_d) return SIS_OK;
   if (mode == SIS_DIFFUSION_CG) {
+    if (g->plan->nsp == 2) return fail(SIS_E_UNSUPPORTED, "2-D mixtures use the precomputed inverse only");
     HIP_TRY(hipStreamSynchronize(stream));
     g->free_inverse();
     g_err.clear();
@@ -1571,7 +1597,7 @@ sis_status sis_diffusion_correct(sis_plan_t p, sis_geom_t g, const double* mom_h
   if (!mom_half) return fail(SIS_E_INVALID, "mom_half must be non-null");
   if (!std::isfinite(N)) return fail(SIS_E_INVALID, "N must be finite");
   if (g->two_d) {
-    sis::Diff2DArgs a = diff2d_args(p, g, mom_half, amom, N > 0.0 ? N : p->nubar);
+    sis::Diff2DArgs a = diff2d_args(p, g, mom_half, amom, p->nsp == 2 ? N : (N > 0.0 ? N : p->nubar));
     a.U = U_out;
     a.dU = dU_out;
     HIP_TRY(sis::launch_diffusion2d(a, stream));
@@ -1647,7 +1673,7 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
     return st;
   if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s, b->lact, &b->ws_part)) return st;
   if (g->two_d) {
-    sis::Diff2DArgs a = diff2d_args(p, g, b->mom, b->amom, b->Npen);
+    sis::Diff2DArgs a = diff2d_args(p, g, b->mom, b->amom, p->nsp == 2 ? b->o.N : b->Npen);
     a.sis = sis ? 1 : 0;
     a.U = nullptr;
     a.ufield = b->U;

@@ -153,6 +153,7 @@ hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s);
 // ---------------------------------------------------------------- 2-D cross sections
 struct Sweep2DArgs {
   int n, n3, n_cases;
+  int nsp;                   // species per cell: rows cell * nsp + s, nu of species s at nu + s * n3
   int d3;                    // stored v3 nodes (n, or n/2 for distributions odd in v3)
   const double* v3d;
   const int32_t* n1;
@@ -170,12 +171,15 @@ struct Sweep2DArgs {
   const int32_t* case_active;
 };
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s);
-// mom[cell][8] = {U3, q3, G1, G12, G2, P13, P23, 0}; rows of n x n x d3 velocities
-hipError_t launch_moments2d(int n, int d3, int64_t n_cells, const double* v1d, const double* v3d, const double* h,
-                            double w, const int32_t* cell_active, double* mom, hipStream_t s);
+// mom[cell][species][8] = {U3, q3, G1, G12, G2, P13, P23, 0}; rows of n x n x d3 velocities;
+// q3 and P13, P23 carry the species mass ratio (q3 = int (a v^2 - 5/2) v3 h, P = 2 a int v v3 h)
+hipError_t launch_moments2d(int n, int d3, int nsp, const double* mass_ratio, int64_t n_cells, const double* v1d,
+                            const double* v3d, const double* h, double w, const int32_t* cell_active, double* mom,
+                            hipStream_t s);
 
 struct Diff2DArgs {
   int n_cases;
+  int64_t n_grid;            // grid cells of all cases (species workspace stride)
   const int32_t* n2;
   const int64_t* grid_off;
   const int8_t* dflag;
@@ -190,42 +194,47 @@ struct Diff2DArgs {
   const double* area;
   const double* delta_case;
   const int32_t* flow_case;
-  const double* mom;         // [cell][8]
-  const double* amom;        // [cell][4] or null
-  double N;
+  const double* mom;         // [cell][species][8]
+  const double* amom;        // [cell][species][4] or null
   int sis;
-  double cU, cq;
-  double* work;              // [grid][10]
+  // species (one gas: nsp 1, chi 1, mass ratio 1, Ns = N, cUs/cqs = the one-gas factors)
+  int nsp;
+  double chi[2], mass_ratio[2], Ns[2], cUs[2], cqs[2];
+  double flow_factor;        // sqrt(m / m_A) (mixtures)
+  double* work;              // [species][grid][kDiffWork]
   int32_t* have_x;           // [n_cases]: warm start available
   double tol;
   int max_iter;
-  double* U;                 // [cell] diffusion solution or null
-  double* dU;                // [cell] or null
-  double* ufield;            // [cell] U3 of the new iterate or null
-  double* qfield;            // [cell] q3 of the new iterate or null
-  double* state;             // [n_cases][4] or null
+  double* U;                 // [cell][species] diffusion solution or null
+  double* dU;                // [cell][species] or null
+  double* ufield;            // [cell][species] U3 of the new iterate or null
+  double* qfield;            // [cell][species] q3 of the new iterate or null
+  double* state;             // [n_cases][2 nsp + 2] or null
   int32_t* iters;
   int32_t* case_active;
   double eps;
   int32_t* cg_iters;         // [n_cases] or null
   // inverse form (cases with direct[c] != 0): A^-1 of the case's unknown cells, precomputed
-  const int32_t* direct;     // [n_cases] or null (CG for every case)
+  const int32_t* direct;     // [n_cases] or null (CG for every case; one gas only)
   const int32_t* uidx;       // [grid] compact unknown index within its case, -1 otherwise
-  const int64_t* uoff;       // [n_cases] offset of the case's unknowns in bvec / yvec
+  const int64_t* uoff;       // [n_cases] unknowns of the earlier cases; species s of case c
+                             // has its right side / solution at nsp * uoff[c] + s * n_unknown[c]
   const int32_t* n_unknown;  // [n_cases]
   int max_unknown;
-  // cases with the same cross section share one inverse: group g holds grp_size[g] <= 8 cases
-  // grp_case[g * 8 + m], its inverse at ainv + grp_aoff[g] (row-major grp_n[g]^2)
+  // right sides with the same cross section share one inverse: group g holds grp_size[g] <= 8
+  // vectors at bvec / yvec + grp_vec[g * 8 + m], its inverse at ainv + grp_aoff[g] (grp_n[g]^2)
   int n_groups;
   const int64_t* grp_aoff;
   const int32_t* grp_n;
   const int32_t* grp_size;
-  const int32_t* grp_case;
+  const int64_t* grp_vec;
   const double* ainv;
-  double* bvec;              // [unknowns]
-  double* yvec;              // [unknowns]
+  double* bvec;              // [nsp * unknowns]
+  double* yvec;              // [nsp * unknowns]
 };
 constexpr int kInverseGroup = 8;
+// workspace per (species, grid cell): Uh G1 G12 G2 A1 A2 | CG: x r p Ap | P_B13 P_B23
+constexpr int kDiffWork = 12;
 // CG kernel for cases without an inverse, then (if a.direct) right sides, y = A^-1 b, outputs
 hipError_t launch_diffusion2d(const Diff2DArgs& a, hipStream_t s);
 // Newton-Schulz helpers (plan time): per-block sum of squares of I - P into part[blocks];

@@ -909,6 +909,8 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
   const int cs = blockIdx.y;
   if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int n = a.n, hn = n / 2, n3 = a.n3, d3 = a.d3;
+  const int nsp = a.nsp, sp = blockIdx.z;
+  const double* __restrict__ nu = a.nu + static_cast<int64_t>(sp) * n3;
   const int quads = hn * hn * d3;
   const int tq = blockIdx.x * kSweepV + threadIdx.x % kSweepV;
   const bool vvalid = tq < quads;
@@ -926,7 +928,7 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
     const int vm1 = ((n - 1 - j1) * n + j2) * d3 + j3;
     const int vm2 = (j1 * n + (n - 1 - j2)) * d3 + j3;
     const double av1 = fabs(a.v1d[j1]), av2 = fabs(a.v1d[j2]);
-    const double dnu = del * a.nu[v];
+    const double dnu = del * nu[v];
     const int sg1 = s1 > 0 ? 0 : 1, sg2 = s2 > 0 ? 0 : 1;
     for (int d = 0; d < n1 + n2 - 1; ++d) {
       const int lo = max(0, d - (n2 - 1)), hi = min(d, n1 - 1);   // ii range of the anti-diagonal
@@ -940,23 +942,24 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
           if (cell >= 0) {
             const int64_t o1 = (static_cast<int64_t>(cell) * 2 + 0) * 2 + sg1;
             const int64_t o2 = (static_cast<int64_t>(cell) * 2 + 1) * 2 + sg2;
-            double acc = a.rhs[static_cast<int64_t>(cell) * n3 + v];
+            const int64_t row = static_cast<int64_t>(cell) * nsp + sp;
+            double acc = a.rhs[row * n3 + v];
             const double c1[3] = {a.coef[o1 * 3], a.coef[o1 * 3 + 1], a.coef[o1 * 3 + 2]};
             const double c2[3] = {a.coef[o2 * 3], a.coef[o2 * 3 + 1], a.coef[o2 * 3 + 2]};
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
               const int8_t k1 = a.kind[o1 * 2 + k];
               if (k1) {
-                const int64_t r = a.ref[o1 * 2 + k];
+                const int64_t r = static_cast<int64_t>(a.ref[o1 * 2 + k]) * nsp + sp;
                 acc -= av1 * c1[k + 1] * a.h[r * n3 + (k1 == 2 ? vm1 : v)];
               }
               const int8_t k2 = a.kind[o2 * 2 + k];
               if (k2) {
-                const int64_t r = a.ref[o2 * 2 + k];
+                const int64_t r = static_cast<int64_t>(a.ref[o2 * 2 + k]) * nsp + sp;
                 acc -= av2 * c2[k + 1] * a.h[r * n3 + (k2 == 2 ? vm2 : v)];
               }
             }
-            a.h[static_cast<int64_t>(cell) * n3 + v] = acc / (dnu + av1 * c1[0] + av2 * c2[0]);
+            a.h[row * n3 + v] = acc / (dnu + av1 * c1[0] + av2 * c2[0]);
           }
         }
       }
@@ -965,14 +968,18 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void moments2d_kernel(int n, int d3, const double* __restrict__ v1d,
+// Per (cell, species) row: U3, q3 = int (a v^2 - 5/2) v3 h, G1, G12, G2, P13 = 2a int v1 v3 h,
+// P23 = 2a int v2 v3 h (a = m_s / m_A; 1 for one gas).
+__global__ __launch_bounds__(256) void moments2d_kernel(int n, int d3, int nsp, double ms0, double ms1,
+                                                        const double* __restrict__ v1d,
                                                         const double* __restrict__ v3d,
                                                         const double* __restrict__ h, double w,
                                                         const int32_t* __restrict__ active,
                                                         double* __restrict__ mom) {
   __shared__ double sh[4 * 7];
   const int64_t c = blockIdx.x;
-  if (active && !active[c]) return;
+  if (active && !active[c / nsp]) return;
+  const double ms = (c % nsp) == 0 ? ms0 : ms1;
   const int nd3 = n * d3, n3 = n * nd3;
   double m[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int v = threadIdx.x; v < n3; v += blockDim.x) {
@@ -980,12 +987,12 @@ __global__ __launch_bounds__(256) void moments2d_kernel(int n, int d3, const dou
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
     const double x = w * h[c * n3 + v];
     m[0] += v3 * x;
-    m[1] += (vsq - 2.5) * v3 * x;
+    m[1] += (ms * vsq - 2.5) * v3 * x;
     m[2] += v3 * (2.0 * v1 * v1 - 1.0) * x;
     m[3] += 2.0 * v1 * v2 * v3 * x;
     m[4] += v3 * (2.0 * v2 * v2 - 1.0) * x;
-    m[5] += 2.0 * v1 * v3 * x;
-    m[6] += 2.0 * v2 * v3 * x;
+    m[5] += 2.0 * ms * v1 * v3 * x;
+    m[6] += 2.0 * ms * v2 * v3 * x;
   }
   block_sum<7>(m, sh);
   if (threadIdx.x == 0) {
@@ -1022,45 +1029,64 @@ __device__ inline void block_sum_big(double (&v)[K], double* sh /* >= 16*K */) {
   __syncthreads();
 }
 
-// Moments of the case into the workspace: per grid cell Uh G1 G12 G2 A1 A2 (x r p Ap for CG).
-__device__ void d2_fill_work(const Diff2DArgs& a, int cs, double* W, int ng, bool warm) {
+// Workspace of species s of case cs: per grid cell Uh G1 G12 G2 A1 A2 (x r p Ap for CG)
+// and, for mixtures, P_B13 P_B23 (species B's shear stresses, in every species' slots).
+__device__ inline double* d2_work(const Diff2DArgs& a, int cs, int s) {
+  return a.work + (static_cast<int64_t>(s) * a.n_grid + a.grid_off[cs]) * kDiffWork;
+}
+
+__device__ void d2_fill_work(const Diff2DArgs& a, int cs, int s, double* W, int ng, bool warm) {
   const int64_t g0 = a.grid_off[cs];
   const double del = a.delta_case[cs];
+  const int nsp = a.nsp;
+  const double chi = a.chi[s], Nd = a.Ns[s] * del;
   for (int g = threadIdx.x; g < ng; g += blockDim.x) {
     const int cell = a.gcell[g0 + g];
-    double* w = W + static_cast<int64_t>(g) * 10;
+    double* w = W + static_cast<int64_t>(g) * kDiffWork;
     if (cell >= 0) {
-      const double* m = a.mom + static_cast<int64_t>(cell) * 8;
-      w[0] = m[0]; w[1] = m[2]; w[2] = m[3]; w[3] = m[4];
+      const int64_t row = static_cast<int64_t>(cell) * nsp + s;
+      const double* m = a.mom + row * 8;
+      w[0] = m[0] / chi; w[1] = m[2]; w[2] = m[3]; w[3] = m[4];
       if (a.amom) {
-        const double* am = a.amom + static_cast<int64_t>(cell) * 4;
-        w[4] = am[0] + a.N * del * am[1];
-        w[5] = am[2] + a.N * del * am[3];
+        const double* am = a.amom + row * 4;
+        w[4] = am[0] + Nd * am[1];
+        w[5] = am[2] + Nd * am[3];
       } else {
         w[4] = 0.0; w[5] = 0.0;
       }
-      if (!warm) w[6] = m[0];
+      if (!warm) w[6] = w[0];
+      if (nsp == 2) {
+        const double* mb = a.mom + (static_cast<int64_t>(cell) * 2 + 1) * 8;
+        w[10] = mb[5];
+        w[11] = mb[6];
+      } else {
+        w[10] = 0.0; w[11] = 0.0;
+      }
     } else {
       for (int k = 0; k < 6; ++k) w[k] = 0.0;
       w[6] = 0.0;
+      w[10] = 0.0; w[11] = 0.0;
     }
     w[7] = 0.0; w[8] = 0.0; w[9] = 0.0;
   }
 }
 
-// Right side of the finite-volume velocity equation at an unknown grid cell G
-// (Dirichlet neighbours moved to the right) and the diagonal of its row.
-__device__ double d2_rhs(const Diff2DArgs& a, int64_t g0, int64_t G, const double* W, bool pois, double del,
+// Right side of the finite-volume velocity equation of species s at an unknown grid
+// cell G (Dirichlet neighbours moved to the right) and the diagonal of its row:
+// chi_s lap U_s = source_s - (d11 G1 + 2 d12 G12 + d22 G2) + d1 A1 + d2 A2, with
+// source = -N delta [Poiseuille] for one gas; for mixtures N_A delta (div P_B - [P])
+// (species A) and -N_B delta (m_A/m_B) div P_B (species B).
+__device__ double d2_rhs(const Diff2DArgs& a, int s, int64_t g0, int64_t G, const double* W, bool pois, double del,
                          double& diag) {
   const int g = static_cast<int>(G - g0);
-  const double* w = W + static_cast<int64_t>(g) * 10;
+  const double* w = W + static_cast<int64_t>(g) * kDiffWork;
   const int32_t* nbr = a.nb + G * 8;
   const int8_t* bits = a.nbm + G * 8;
   const double* np = a.npos + G * 4;
   const double xc = a.cpos[G * 2], yc = a.cpos[G * 2 + 1];
   auto val = [&](int q, int f, int p1, int p2) {
     const int r = nbr[q];
-    return r < 0 ? 0.0 : par_sign(bits[q], p1, p2) * W[static_cast<int64_t>(r) * 10 + f];
+    return r < 0 ? 0.0 : par_sign(bits[q], p1, p2) * W[static_cast<int64_t>(r) * kDiffWork + f];
   };
   const double xE = np[0], xW = np[1], yN = np[2], yS = np[3];
   const double w1 = a.width[G * 2], w2 = a.width[G * 2 + 1];
@@ -1070,73 +1096,96 @@ __device__ double d2_rhs(const Diff2DArgs& a, int64_t g0, int64_t G, const doubl
   auto d22 = [&](int f, int p1, int p2) {
     return ((val(2, f, p1, p2) - w[f]) / (yN - yc) - (w[f] - val(3, f, p1, p2)) / (yc - yS)) / w2;
   };
-  double rhs = pois ? -a.N * del : 0.0;
+  const double Nd = a.Ns[s] * del;
+  double rhs = 0.0;
+  if (a.nsp == 1) {
+    rhs = pois ? -Nd : 0.0;
+  } else {
+    const double coef = s == 1 ? -Nd / a.mass_ratio[1] : Nd;
+    if (s == 0 && pois) rhs -= Nd;
+    rhs += coef * ((val(0, 10, -1, 1) - val(1, 10, -1, 1)) / (xE - xW) +
+                   (val(2, 11, 1, -1) - val(3, 11, 1, -1)) / (yN - yS));
+  }
   const double cross = ((val(4, 2, -1, -1) - val(6, 2, -1, -1)) / (yN - yS) -
                         (val(5, 2, -1, -1) - val(7, 2, -1, -1)) / (yN - yS)) / (xE - xW);
   rhs -= d11(1, 1, 1) + 2.0 * cross + d22(3, 1, 1);
   rhs += (val(0, 4, -1, 1) - val(1, 4, -1, 1)) / (xE - xW);
   rhs += (val(2, 5, 1, -1) - val(3, 5, 1, -1)) / (yN - yS);
-  double b = -rhs * a.dA[G];
+  double b = -(rhs / a.chi[s]) * a.dA[G];
   diag = 0.0;
   for (int q = 0; q < 4; ++q) {
     const double fw = a.fw[G * 4 + q];
     if (fw == 0.0) continue;
     const int r = nbr[q];
     diag += fw;
-    if (a.dflag[g0 + r] != 2) b += fw * W[static_cast<int64_t>(r) * 10 + 0];
+    if (a.dflag[g0 + r] != 2) b += fw * W[static_cast<int64_t>(r) * kDiffWork + 0];
   }
   return b;
 }
 
-// New velocity, correction, moments of h^{k+1}, flow rates and the convergence
-// test of one case.  usol: solution at the unknown cells, indexed by uoff[case]
-// + uidx (null: the CG iterate in the workspace; CIS: no solve).
-__device__ void d2_outputs(const Diff2DArgs& a, int cs, const double* W, int ng, const double* usol, int it,
-                           double* sh) {
+// New velocities, corrections, moments of h^{k+1}, flow rates and the convergence
+// test of one case (all species).  usol: the solutions at the unknown cells (null:
+// the CG iterate in the workspace; CIS: no solve).
+__device__ void d2_outputs(const Diff2DArgs& a, int cs, int ng, const double* usol, int it, double* sh) {
   const int64_t g0 = a.grid_off[cs];
-  double fr[2] = {0.0, 0.0};
-  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
-    const int64_t G = g0 + g;
-    const int cell = a.gcell[G];
-    if (cell < 0) continue;
-    const double* w = W + static_cast<int64_t>(g) * 10;
-    const double Uh = w[0];
-    double U = Uh;
-    if (a.sis && a.dflag[G] == 2) U = usol ? usol[a.uoff[cs] + a.uidx[G]] : w[6];
-    const double dU = U - Uh;
-    const double Un = Uh + dU * a.cU;
-    const double qn = a.mom[static_cast<int64_t>(cell) * 8 + 1] + dU * a.cq;
-    if (a.U) a.U[cell] = U;
-    if (a.dU) a.dU[cell] = dU;
-    if (a.ufield) a.ufield[cell] = Un;
-    if (a.qfield) a.qfield[cell] = qn;
-    fr[0] += Un * a.dA[G];
-    fr[1] += qn * a.dA[G];
+  const int nsp = a.nsp;
+  double fr[4] = {0.0, 0.0, 0.0, 0.0};   // (M, Q) per species
+  for (int s = 0; s < nsp; ++s) {
+    const double* W = d2_work(a, cs, s);
+    const int64_t voff = nsp * a.uoff[cs] + static_cast<int64_t>(s) * a.n_unknown[cs];
+    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+      const int64_t G = g0 + g;
+      const int cell = a.gcell[G];
+      if (cell < 0) continue;
+      const int64_t row = static_cast<int64_t>(cell) * nsp + s;
+      const double* w = W + static_cast<int64_t>(g) * kDiffWork;
+      const double Uh = w[0];
+      double U = Uh;
+      if (a.sis && a.dflag[G] == 2) U = usol ? usol[voff + a.uidx[G]] : w[6];
+      const double dU = U - Uh;
+      const double Un = Uh + dU * a.cUs[s];
+      const double qn = a.mom[row * 8 + 1] + dU * a.cqs[s];
+      if (a.U) a.U[row] = U;
+      if (a.dU) a.dU[row] = dU;
+      if (a.ufield) a.ufield[row] = Un;
+      if (a.qfield) a.qfield[row] = qn;
+      fr[2 * s] += Un * a.dA[G];
+      fr[2 * s + 1] += qn * a.dA[G];
+    }
   }
-  block_sum_big<2>(fr, sh);
+  block_sum_big<4>(fr, sh);
   if (threadIdx.x == 0) {
     if (a.have_x) a.have_x[cs] = a.sis ? 1 : 0;
     if (a.cg_iters) a.cg_iters[cs] = it;
     if (a.state) {
-      const double M = fr[0] / a.area[cs], Q = fr[1] / a.area[cs];
-      double* st = a.state + cs * 4;
-      const double dM = fabs(M - st[0]) / fmax(fabs(M), 1e-300);
-      const double dQ = fabs(Q - st[1]) / fmax(fabs(Q), 1e-300);
-      const double res = fmax(dM, dQ);
-      st[0] = M;
-      st[1] = Q;
-      st[2] = (M != M || Q != Q) ? __builtin_nan("") : res;
+      double* st = a.state + cs * (2 * nsp + 2);   // M[nsp], Q[nsp], residual, iterations
+      double res = 0.0;
+      bool bad = false;
+      for (int s = 0; s < nsp; ++s) {
+        double M = fr[2 * s] / a.area[cs], Q = fr[2 * s + 1] / a.area[cs];
+        if (nsp == 2) {
+          M *= a.flow_factor;
+          Q *= a.flow_factor;
+        }
+        const double dM = fabs(M - st[s]) / fmax(fabs(M), 1e-300);
+        const double dQ = fabs(Q - st[nsp + s]) / fmax(fabs(Q), 1e-300);
+        res = fmax(res, fmax(dM, dQ));
+        bad = bad || M != M || Q != Q;
+        st[s] = M;
+        st[nsp + s] = Q;
+      }
+      st[2 * nsp] = bad ? __builtin_nan("") : res;
       const int k = a.iters[cs] + 1;
       a.iters[cs] = k;
-      if (!(res >= a.eps) || M != M || Q != Q) a.case_active[cs] = 0;
-      st[3] = static_cast<double>(k);
+      if (!(res >= a.eps) || bad) a.case_active[cs] = 0;
+      st[2 * nsp + 1] = static_cast<double>(k);
     }
   }
 }
 
-// Conjugate-gradient form (cases without a precomputed inverse).
+// Conjugate-gradient form (one gas; cases without a precomputed inverse).
 __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
-  __shared__ double sh[16 * 3];
+  __shared__ double sh[16 * 4];
   const int cs = blockIdx.x;
   if (a.case_active && !a.case_active[cs]) return;
   if (a.direct && a.direct[cs]) return;   // solved by the inverse path
@@ -1144,9 +1193,9 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
   const int ng = static_cast<int>(a.grid_off[cs + 1] - g0);
   const double del = a.delta_case[cs];
   const bool pois = a.flow_case[cs] == 1;
-  double* W = a.work + g0 * 10;      // per grid cell: Uh G1 G12 G2 A1 A2 x r p Ap
+  double* W = d2_work(a, cs, 0);
   const bool warm = a.have_x && a.have_x[cs];
-  d2_fill_work(a, cs, W, ng, warm);
+  d2_fill_work(a, cs, 0, W, ng, warm);
   __syncthreads();
   int it = 0;
   if (a.sis) {
@@ -1155,15 +1204,15 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
     for (int g = threadIdx.x; g < ng; g += blockDim.x) {
       const int64_t G = g0 + g;
       if (a.dflag[G] != 2) continue;
-      double* w = W + static_cast<int64_t>(g) * 10;
+      double* w = W + static_cast<int64_t>(g) * kDiffWork;
       double diag;
-      const double b = d2_rhs(a, g0, G, W, pois, del, diag);
+      const double b = d2_rhs(a, 0, g0, G, W, pois, del, diag);
       double Ax = 0.0;
       for (int q = 0; q < 4; ++q) {
         const double fw = a.fw[G * 4 + q];
         if (fw == 0.0) continue;
         const int r = a.nb[G * 8 + q];
-        if (a.dflag[g0 + r] == 2) Ax -= fw * W[static_cast<int64_t>(r) * 10 + 6];
+        if (a.dflag[g0 + r] == 2) Ax -= fw * W[static_cast<int64_t>(r) * kDiffWork + 6];
       }
       Ax += diag * w[6];
       const double r0 = b - Ax;
@@ -1184,14 +1233,14 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
       for (int g = threadIdx.x; g < ng; g += blockDim.x) {
         const int64_t G = g0 + g;
         if (a.dflag[G] != 2) continue;
-        double* w = W + static_cast<int64_t>(g) * 10;
+        double* w = W + static_cast<int64_t>(g) * kDiffWork;
         double diag = 0.0, Ap = 0.0;
         for (int q = 0; q < 4; ++q) {
           const double fw = a.fw[G * 4 + q];
           if (fw == 0.0) continue;
           const int r = a.nb[G * 8 + q];
           diag += fw;
-          if (a.dflag[g0 + r] == 2) Ap -= fw * W[static_cast<int64_t>(r) * 10 + 8];
+          if (a.dflag[g0 + r] == 2) Ap -= fw * W[static_cast<int64_t>(r) * kDiffWork + 8];
         }
         Ap += diag * w[8];
         w[9] = Ap;
@@ -1203,7 +1252,7 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
       for (int g = threadIdx.x; g < ng; g += blockDim.x) {
         const int64_t G = g0 + g;
         if (a.dflag[G] != 2) continue;
-        double* w = W + static_cast<int64_t>(g) * 10;
+        double* w = W + static_cast<int64_t>(g) * kDiffWork;
         double diag = 0.0;
         for (int q = 0; q < 4; ++q) diag += a.fw[G * 4 + q];
         w[6] += alpha * w[8];
@@ -1218,7 +1267,7 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
       for (int g = threadIdx.x; g < ng; g += blockDim.x) {
         const int64_t G = g0 + g;
         if (a.dflag[G] != 2) continue;
-        double* w = W + static_cast<int64_t>(g) * 10;
+        double* w = W + static_cast<int64_t>(g) * kDiffWork;
         double diag = 0.0;
         for (int q = 0; q < 4; ++q) diag += a.fw[G * 4 + q];
         w[8] = w[7] / diag + beta * w[8];
@@ -1227,10 +1276,10 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_kernel(Diff2DArgs a) {
       ++it;
     }
   }
-  d2_outputs(a, cs, W, ng, nullptr, it, sh);
+  d2_outputs(a, cs, ng, nullptr, it, sh);
 }
 
-// Inverse form, step 1: right sides of the unknown cells (compact per case).
+// Inverse form, step 1: right sides of the unknown cells of every species (compact per case).
 __global__ __launch_bounds__(kD2Threads) void diffusion2d_rhs_kernel(Diff2DArgs a) {
   const int cs = blockIdx.x;
   if (a.case_active && !a.case_active[cs]) return;
@@ -1239,20 +1288,23 @@ __global__ __launch_bounds__(kD2Threads) void diffusion2d_rhs_kernel(Diff2DArgs 
   const int ng = static_cast<int>(a.grid_off[cs + 1] - g0);
   const double del = a.delta_case[cs];
   const bool pois = a.flow_case[cs] == 1;
-  double* W = a.work + g0 * 10;
-  d2_fill_work(a, cs, W, ng, true);
+  for (int s = 0; s < a.nsp; ++s) d2_fill_work(a, cs, s, d2_work(a, cs, s), ng, true);
   __syncthreads();
   if (!a.sis) return;
-  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
-    const int64_t G = g0 + g;
-    if (a.dflag[G] != 2) continue;
-    double diag;
-    a.bvec[a.uoff[cs] + a.uidx[G]] = d2_rhs(a, g0, G, W, pois, del, diag);
+  for (int s = 0; s < a.nsp; ++s) {
+    const double* W = d2_work(a, cs, s);
+    const int64_t voff = a.nsp * a.uoff[cs] + static_cast<int64_t>(s) * a.n_unknown[cs];
+    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+      const int64_t G = g0 + g;
+      if (a.dflag[G] != 2) continue;
+      double diag;
+      a.bvec[voff + a.uidx[G]] = d2_rhs(a, s, g0, G, W, pois, del, diag);
+    }
   }
 }
 
-// Inverse form, step 2: y_c = A^-1 b_c for the cases c of one group (same cross section), one
-// wave per row of the shared inverse, which is read once for all of them.
+// Inverse form, step 2: y = A^-1 b for the right sides of one group (same cross
+// section), one wave per row of the shared inverse, which is read once for all of them.
 template <int G>
 __device__ void d2_gemv_rows(const Diff2DArgs& a, int grp, int row, int lane) {
   const int nu = a.grp_n[grp];
@@ -1261,7 +1313,7 @@ __device__ void d2_gemv_rows(const Diff2DArgs& a, int grp, int row, int lane) {
   double s[G];
 #pragma unroll
   for (int m = 0; m < G; ++m) {
-    b[m] = a.bvec + a.uoff[a.grp_case[grp * kInverseGroup + m]];
+    b[m] = a.bvec + a.grp_vec[grp * kInverseGroup + m];
     s[m] = 0.0;
   }
   for (int j = lane; j < nu; j += 64) {
@@ -1272,7 +1324,7 @@ __device__ void d2_gemv_rows(const Diff2DArgs& a, int grp, int row, int lane) {
 #pragma unroll
   for (int m = 0; m < G; ++m) {
     const double t = wave_sum(s[m]);
-    if (lane == 0) a.yvec[a.uoff[a.grp_case[grp * kInverseGroup + m]] + row] = t;
+    if (lane == 0) a.yvec[a.grp_vec[grp * kInverseGroup + m] + row] = t;
   }
 }
 
@@ -1295,13 +1347,13 @@ __global__ __launch_bounds__(256) void diffusion2d_gemv_kernel(Diff2DArgs a) {
 
 // Inverse form, step 3: outputs, flow rates, convergence.
 __global__ __launch_bounds__(kD2Threads) void diffusion2d_out_kernel(Diff2DArgs a) {
-  __shared__ double sh[16 * 3];
+  __shared__ double sh[16 * 4];
   const int cs = blockIdx.x;
   if (a.case_active && !a.case_active[cs]) return;
   if (!a.direct[cs]) return;
   const int64_t g0 = a.grid_off[cs];
   const int ng = static_cast<int>(a.grid_off[cs + 1] - g0);
-  d2_outputs(a, cs, a.work + g0 * 10, ng, a.yvec, 0, sh);
+  d2_outputs(a, cs, ng, a.yvec, 0, sh);
 }
 
 // Newton-Schulz steps for the inverse of a Jacobi-scaled SPD matrix (plan time).
@@ -1489,15 +1541,16 @@ hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   const int hn = a.n / 2;
   const int count = hn * hn * a.d3;
-  dim3 grid((count + kSweepV - 1) / kSweepV, a.n_cases);
+  dim3 grid((count + kSweepV - 1) / kSweepV, a.n_cases, a.nsp);
   hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(kSweepThreads), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_moments2d(int n, int d3, int64_t n_cells, const double* v1d, const double* v3d, const double* h,
-                            double w, const int32_t* cell_active, double* mom, hipStream_t s) {
-  hipLaunchKernelGGL(moments2d_kernel, dim3(static_cast<unsigned>(n_cells)), dim3(256), 0, s, n, d3, v1d, v3d, h,
-                     w, cell_active, mom);
+hipError_t launch_moments2d(int n, int d3, int nsp, const double* mass_ratio, int64_t n_cells, const double* v1d,
+                            const double* v3d, const double* h, double w, const int32_t* cell_active, double* mom,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(moments2d_kernel, dim3(static_cast<unsigned>(n_cells * nsp)), dim3(256), 0, s, n, d3, nsp,
+                     mass_ratio[0], nsp > 1 ? mass_ratio[1] : 1.0, v1d, v3d, h, w, cell_active, mom);
   return hipGetLastError();
 }
 

@@ -164,3 +164,52 @@ def test_M7_sis_and_cis_share_the_fixed_point_up_to_discretisation():
         gaps.append(np.max(np.abs(rs["M"] - rc["M"]) / rc["M"]))
     assert gaps[1] < 3e-2
     assert gaps[1] < 0.3 * gaps[0]
+
+
+# ------------------------------------------------------------------ rectangular ducts (Table 5)
+def test_MD1_identical_species_in_a_duct_reduce_to_one_gas():
+    """Cross-section CIS of a mixture of identical species: M_A = M_B = M and
+    Q_a = chi_a Q of the one-gas 2-D solve, exactly (collide, 2-D sweep and
+    moments of each species, flow rates)."""
+    from oracle import duct
+    from oracle.velocity import POISEUILLE
+    g = duct.duct_quarter(3, 4, ratio=1.0)
+    vg = VelocityGrid(8, 4.0)
+    op = mixture.MixtureFSM(vg, (4.0, 4.0), (1.0, 1.0), (0.3, 0.7), m_angle=4, m_rho=4)
+    r2 = mixture.solve_mixture_2d(op, g, 1.0, scheme="CIS", eps=1e-9, max_it=200)
+    r1 = duct.solve_2d(collision.FSM(vg, m_angle=4), g, 1.0, POISEUILLE, "CIS", eps=1e-9, max_it=200)
+    assert r2["iters"] == r1["iters"]
+    assert np.allclose(r2["M"], r1["M"], rtol=1e-12, atol=0)
+    assert np.allclose(r2["Q"], [0.3 * r1["Q"], 0.7 * r1["Q"]], rtol=1e-12, atol=0)
+
+
+def test_MD2_species_velocity_equations_sum_to_the_mixture_equation():
+    """With N_A = N_B m_A/m_B the pressure-gradient terms of species B cancel
+    between eqs. LBE2_true2 and LBE2_true1, so chi_A U_A + chi_B U_B solves the
+    single-gas velocity equation with the summed moments (G, A) and wall
+    values U3_A + U3_B: an exact identity of the discrete (linear) solves that
+    fixes the sign and scale of every div P_B term, the source of A and the
+    placement of chi."""
+    from oracle import duct
+    op = mix(8, 4.0, 4, 3)
+    solid = np.zeros((5, 6), bool)
+    solid[2, 3] = True
+    g = duct.Grid2D(duct.geometric_faces(5, 0.5, 1.1), duct.geometric_faces(6, 0.5, 1.0),
+                    (duct.WALL, duct.SYM, duct.WALL, duct.SYM), solid)
+    nf = len(g.cells)
+    rng = np.random.default_rng(17)
+    mom = rng.standard_normal((nf, 2, 7))
+    amom = rng.standard_normal((nf, 2, 4))
+    delta, NB = 2.5, 1.3
+    N = (NB / op.a[1], NB)
+    U = mixture.velocity_2d(op, g, mom, amom, delta, N)
+    msum = np.zeros((nf, 7))
+    msum[:, 0] = mom[:, 0, 0] + mom[:, 1, 0]
+    msum[:, 2:5] = mom[:, 0, 2:5] + mom[:, 1, 2:5]
+    asum = np.zeros((nf, 4))
+    for s in range(2):
+        asum[:, 0] += amom[:, s, 0] + N[s] * delta * amom[:, s, 1]
+        asum[:, 2] += amom[:, s, 2] + N[s] * delta * amom[:, s, 3]
+    ref = duct.diffusion_2d(g, msum, asum, delta, N[0], duct.POISEUILLE)
+    lhs = op.chi[0] * U[:, 0] + op.chi[1] * U[:, 1]
+    assert np.max(np.abs(lhs - ref)) < 1e-11 * np.max(np.abs(ref))
