@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "small", "duct", "porous", "mixture", "sierpinski"])
+                    choices=["batch", "small", "duct", "porous", "mixture", "mixture-duct", "sierpinski"])
     ap.add_argument("--diffusion", default="inverse", choices=["inverse", "cg"],
                     help="2-D velocity equation: precomputed inverse or conjugate gradients")
     ap.add_argument("--ttr", default="fp64,fp32,bf16x3,fp64+projection,bf16x3+projection",
@@ -151,7 +151,7 @@ def main():
                           "copies": 5}), flush=True)
         return 0
     w = {"batch": inputs.PLANAR_BATCH, "small": inputs.PLANAR_SMALL, "duct": inputs.DUCT_IPL,
-         "porous": inputs.POROUS_HS, "mixture": inputs.MIX_NEAR,
+         "porous": inputs.POROUS_HS, "mixture": inputs.MIX_NEAR, "mixture-duct": inputs.MIX_DUCT,
          "sierpinski": inputs.SIERPINSKI_HS}[args.workload]
     mix = w.get("mixture")
     # penalty N of the SIS velocity equations: nubar for one gas, 1.5 for the
@@ -175,7 +175,7 @@ def main():
         geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
         per_case = [len(x) for x in xs]
     else:
-        cases = {"duct": inputs.duct_cases, "porous": inputs.porous_cases,
+        cases = {"duct": inputs.duct_cases, "porous": inputs.porous_cases, "mixture-duct": inputs.duct_cases,
                  "sierpinski": inputs.sierpinski_cases}[args.workload](w)
         geom = sis.Geometry2D(plan, "periodic" if args.workload == "porous" else "duct", cases,
                               w["deltas"], w["flows"])

@@ -152,6 +152,12 @@ def porous_discs(n=128, solid_fraction=0.4, r_max=0.1, r_ratio=10.0, seed=SEED, 
 DUCT_IPL = dict(name="duct-ipl081-24v-64x64-6cases", n_v=24, l_v=6.0, n_pad=48, m_angle=8,
                 kernel="ipl", visc_index=0.81, cells=64, aspect=[1, 1, 1, 2, 2, 2],
                 deltas=[1.0, 10.0, 50.0] * 2, flows=[1] * 6)
+# Equimolar Ne-Ar mixture in quarter ducts of aspect ratio 1 and 2 (Table 5):
+# 64 x 64 cells growing by 1.05 from the walls, 24^3 velocities on [-5, 5]^3
+# (v3 > 0 stored), M = 8, 16 rho nodes, N_a = 1.5, delta in {1, 10} per aspect ratio.
+MIX_DUCT = dict(name="mixture-duct-near-hs-24v-64x64-4cases", n_v=24, l_v=5.0, n_pad=48, m_angle=8,
+                kernel="hs", mixture=MIX_NEAR["mixture"], cells=64, aspect=[1, 1, 2, 2],
+                deltas=[1.0, 10.0, 1.0, 10.0], flows=[1] * 4)
 # Periodic porous unit cell, 128^2 staircase discs (porosity 0.6), hard spheres,
 # 24^3 velocities padded to 48^3, M = 8, delta in {1, 10}.
 POROUS_HS = dict(name="porous-hs-24v-128sq-2cases", n_v=24, l_v=6.0, n_pad=48, m_angle=8,
