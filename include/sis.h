@@ -57,7 +57,8 @@ enum { SIS_PREC_FP64 = 0, SIS_PREC_FP32 = 1, SIS_PREC_BF16X3 = 2 };
 /* Source terms S of Sec. 2 with X_P = X_T = -1.                             */
 enum { SIS_FLOW_NONE = 0, SIS_FLOW_POISEUILLE = 1, SIS_FLOW_TRANSPIRATION = 2 };
 enum { SIS_SCHEME_CIS = 0, SIS_SCHEME_SIS = 1 };
-enum { SIS_GEOM_PLANAR_HALF = 0, SIS_GEOM_DUCT_QUARTER = 1, SIS_GEOM_PERIODIC_2D = 2 };
+enum { SIS_GEOM_PLANAR_HALF = 0, SIS_GEOM_DUCT_QUARTER = 1, SIS_GEOM_PERIODIC_2D = 2, SIS_GEOM_TUBE = 3 };
+enum { SIS_GRID_CARTESIAN = 0, SIS_GRID_POLAR = 1 };
 enum { SIS_DIFFUSION_CG = 0, SIS_DIFFUSION_INVERSE = 1 };
 
 const char* sis_last_error(void);   /* thread-local; valid until the next call on this thread */
@@ -111,6 +112,25 @@ typedef struct {
    * The operator is the full one restricted to the class (4x / 16x fewer
    * entries).  Inputs outside the class are the caller's error.             */
   int32_t parity;
+  /* Velocity grid.  SIS_GRID_CARTESIAN (0): n_v^3 nodes on [-l_v, l_v]^3 as above.
+   * SIS_GRID_POLAR (1), for the tube (Sec. 4, one gas, hard spheres): at the
+   * point (r, 0) of the cross section v = (v_r cos th, v_r sin th, v_z), th the
+   * angle of the in-plane velocity from the radial direction; distributions are
+   * even in th and odd in v_z, so the stored nodes are v_r = vr_max s^2 (s the
+   * n_vr Gauss-Legendre nodes on [0, 1]), th the n_th midpoints on [0, pi] and
+   * v_z the n_vz midpoints on [0, l_v]; a row is [v_r][th][v_z] (v_z fastest,
+   * n_vel = n_vr n_th n_vz).  The collision operator is the fast spectral
+   * method of the Cartesian grids on the modes pi l / l_pad of an n_pad^3 box
+   * (l_pad = 0 -> 2 max(vr_max, l_v); n_pad = 0 -> 4 l_pad, a lattice spacing
+   * of 1/2), its transforms taken between the polar nodes (weights
+   * w_vr dth dv_z over all four mirror images) and those modes.  n_v, parity
+   * and the mixture fields are ignored.                                      */
+  int32_t grid;
+  int32_t n_vr;
+  double  vr_max;
+  int32_t n_th;
+  int32_t n_vz;
+  double  l_pad;
 } sis_velocity_desc;
 
 typedef struct {
@@ -191,6 +211,10 @@ sis_status sis_plan_set_precision(sis_plan_t plan, int32_t precision, hipStream_
  * SIS_GEOM_PERIODIC_2D (Sec. 3.2): periodic cell with faces face1/face2 and a
  *   staircase solid mask solid (n1*n2 bytes per case, i major, 1 = solid);
  *   solid faces reflect diffusely.
+ * SIS_GEOM_TUBE (Sec. 4; plans with SIS_GRID_POLAR only): case c is the tube
+ *   of unit radius, radial nodes x1[node_offset[c] .. node_offset[c+1])
+ *   (strictly increasing from r > 0 to r = 1, the diffuse wall; >= 3 nodes);
+ *   Poiseuille flow.  Moments have 8 entries per node.
  * 2-D cells are numbered per case in row-major (i, j) order over fluid
  * cells.  Sweep moments have 8 entries per cell in 2-D (4 planar): see
  * sis_geometry_moment_stride.                                               */

@@ -15,6 +15,7 @@
 #include "geom2d.h"
 #include "kernels.h"
 #include "mixture.h"
+#include "polar.h"
 #include "planner.h"
 #include "sis.h"
 
@@ -94,6 +95,12 @@ struct sis_plan {
   double* nu = nullptr;         // [nsp][n3]
   double* Kc = nullptr;         // [nsp][ndof] L+ of the correction shape of each species
   double* gram_inv = nullptr;   // [25]
+  // polar velocity grid (tube flows): per-node velocity components [3][nv], weights [nv]
+  // (both mirror images in th and v_z included), axis tables for the sweep
+  bool polar = false;
+  int n_vr = 0, n_th = 0, n_vz = 0;
+  double dth = 0.0;
+  double *vnode = nullptr, *wnode = nullptr, *d_vr = nullptr, *d_cth = nullptr, *d_sth = nullptr;
   double cU = 0, cq = 0;        // U3, q3 of 2 v3 feq
   std::vector<double> h_v1d, h_feq, h_nu;
   // scratch of eager compute calls (a solver state owns its own, fixed at creation,
@@ -107,6 +114,7 @@ struct sis_plan {
     for (auto& e : events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     dfree(op); dfree(op32); dfree(ophi); dfree(oplo);
     dfree(v1d); dfree(feq); dfree(nu); dfree(Kc); dfree(gram_inv);
+    dfree(vnode); dfree(wnode); dfree(d_vr); dfree(d_cth); dfree(d_sth);
   }
 };
 
@@ -127,6 +135,8 @@ struct sis_geom {
   int32_t* case_of_cell = nullptr;
   // 2-D tables (kinds DUCT_QUARTER, PERIODIC_2D)
   bool two_d = false;
+  bool tube = false;             // SIS_GEOM_TUBE: radial nodes, polar velocity grid
+  double *d_r = nullptr, *d_cin = nullptr, *d_cout = nullptr, *d_tw = nullptr;
   sis::Tables2D t2;
   int32_t *d_n1 = nullptr, *d_n2 = nullptr, *d_gcell = nullptr, *d_sref = nullptr, *d_nb = nullptr;
   int64_t* d_goff = nullptr;
@@ -155,9 +165,10 @@ struct sis_geom {
     max_unknown = n_direct = n_groups = n_inverses = 0;
     inv_residual = 0.0;
   }
-  int mom_stride() const { return two_d ? 8 : 4; }
+  int mom_stride() const { return (two_d || tube) ? 8 : 4; }
   ~sis_geom() {
     free_inverse();
+    dfree(d_r); dfree(d_cin); dfree(d_cout); dfree(d_tw);
     dfree(off); dfree(x); dfree(coef); dfree(delta_case); dfree(flow_case);
     dfree(delta_cell); dfree(flow_cell); dfree(case_of_cell);
     dfree(d_n1); dfree(d_n2); dfree(d_gcell); dfree(d_sref); dfree(d_nb); dfree(d_goff);
@@ -194,6 +205,16 @@ bool invert5(const double* a, double* inv) {
 
 sis_status validate_desc(const sis_velocity_desc* d) {
   if (!d) return fail(SIS_E_INVALID, "null velocity descriptor");
+  if (d->grid != SIS_GRID_CARTESIAN && d->grid != SIS_GRID_POLAR) return fail(SIS_E_INVALID, "unknown velocity grid %d", d->grid);
+  if (d->grid == SIS_GRID_POLAR) {
+    if (d->kernel != SIS_KERNEL_HARD_SPHERE) return fail(SIS_E_UNSUPPORTED, "the polar grid supports hard spheres only");
+    if (d->n_species == 2) return fail(SIS_E_UNSUPPORTED, "the polar grid supports one gas only");
+    if (d->m_angle < 1 || d->m_angle > 32) return fail(SIS_E_INVALID, "m_angle must be in [1, 32]");
+    if (!(d->l_v > 0.0) || !std::isfinite(d->l_v) || !(d->vr_max > 0.0) || !std::isfinite(d->vr_max))
+      return fail(SIS_E_INVALID, "l_v and vr_max must be positive");
+    if (d->l_pad < 0.0 || d->n_pad < 0) return fail(SIS_E_INVALID, "l_pad and n_pad must be >= 0");
+    return SIS_OK;
+  }
   if (d->n_v < 4 || d->n_v > 40 || d->n_v % 2) return fail(SIS_E_INVALID, "n_v must be even in [4, 40] (got %d)", d->n_v);
   if (!(d->l_v > 0.0) || !std::isfinite(d->l_v)) return fail(SIS_E_INVALID, "l_v must be positive");
   const int np = d->n_pad > 0 ? d->n_pad : 2 * d->n_v;
@@ -425,6 +446,8 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   f.flow = flow;
   f.project = project;
   f.v1d = p->v1d;
+  f.vnode = p->vnode;
+  f.wnode = p->wnode;
   f.feq = p->feq;
   f.nu = p->nu;
   f.Kc = p->Kc;
@@ -445,6 +468,31 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
                      const int32_t* case_active, hipStream_t s, const int32_t* cell_active = nullptr,
                      Scratch* ws_part = nullptr) {
   if (!ws_part) ws_part = &p->ws_part;
+  if (g->tube) {
+    sis::TubeSweepArgs a{};
+    a.n_vr = p->n_vr;
+    a.n_th = p->n_th;
+    a.n_vz = p->n_vz;
+    a.nv = p->nv;
+    a.n_cases = g->n_cases;
+    a.node_off = g->off;
+    a.r = g->d_r;
+    a.cin = g->d_cin;
+    a.cout = g->d_cout;
+    a.vr = p->d_vr;
+    a.cth = p->d_cth;
+    a.sth = p->d_sth;
+    a.dth = p->dth;
+    a.delta_case = g->delta_case;
+    a.nu = p->nu;
+    a.rhs = rhs;
+    a.h = h;
+    a.case_active = case_active;
+    a.max_nodes = g->max_nodes;
+    HIP_TRY(sis::launch_sweep_tube(a, s));
+    if (mom) HIP_TRY(sis::launch_moments_tube(g->n_cells, p->nv, p->vnode, p->wnode, h, cell_active, mom, s));
+    return SIS_OK;
+  }
   if (g->two_d) {
     sis::Sweep2DArgs a{};
     a.n = p->n;
@@ -500,6 +548,24 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
   HIP_TRY(sis::launch_sweep1d(a, s));
   if (mom) HIP_TRY(sis::launch_reduce_partials(a.part, W, g->n_cells * p->nsp, mom, s));
   return SIS_OK;
+}
+
+sis::TubeDiffArgs tube_diff_args(sis_plan* p, sis_geom* g, const double* mom, const double* amom, double N) {
+  sis::TubeDiffArgs a{};
+  a.n_cases = g->n_cases;
+  a.node_off = g->off;
+  a.r = g->d_r;
+  a.cin = g->d_cin;
+  a.tw = g->d_tw;
+  a.delta_case = g->delta_case;
+  a.flow_case = g->flow_case;
+  a.mom = mom;
+  a.amom = amom;
+  a.N = N;
+  a.sis = 1;
+  a.cU = p->cU;
+  a.cq = p->cq;
+  return a;
 }
 
 sis::Diff2DArgs diff2d_args(sis_plan* p, sis_geom* g, const double* mom, const double* amom, double N) {
@@ -860,6 +926,93 @@ sis_status build_inverse_2d(sis_plan* p, sis_geom* g, hipStream_t s) {
   return SIS_OK;
 }
 
+// Tube (Sec. 4): per case the radial nodes r_0 < ... < r_{n-1} = 1 (the wall), n >= 3.
+// Upwind coefficients of d/dr: inward from the nodes i, i+1, i+2 (two-point next to the
+// wall), outward from i, i-1, i-2 with the centre ghosts -r_0, -r_1; trapezoid weights of
+// 2 int_0^1 f r dr with the centre (f r = 0 there) as the first point.
+sis_status create_geometry_tube(sis_plan* p, const sis_geometry_desc* d, hipStream_t stream, sis_geom_t* out) {
+  if (!d->node_offset || !d->x1 || !d->delta || !d->flow) return fail(SIS_E_INVALID, "null geometry array");
+  if (d->node_offset[0] != 0) return fail(SIS_E_INVALID, "node_offset[0] must be 0");
+  auto* g = new sis_geom();
+  g->plan = p;
+  g->kind = d->kind;
+  g->n_cases = d->n_cases;
+  g->tube = true;
+  g->h_off.assign(d->node_offset, d->node_offset + d->n_cases + 1);
+  g->n_cells = g->h_off.back();
+  for (int c = 0; c < d->n_cases; ++c) {
+    const int64_t a = g->h_off[c], b = g->h_off[c + 1];
+    if (b - a < 3) { delete g; return fail(SIS_E_SHAPE, "case %d has fewer than 3 radial nodes", c); }
+    g->max_nodes = std::max<int>(g->max_nodes, static_cast<int>(b - a));
+    if (!(d->x1[a] > 0.0) || d->x1[b - 1] != 1.0) { delete g; return fail(SIS_E_INVALID, "case %d radial nodes must run from r > 0 to 1", c); }
+    for (int64_t i = a + 1; i < b; ++i)
+      if (!(d->x1[i] > d->x1[i - 1])) { delete g; return fail(SIS_E_INVALID, "case %d nodes not increasing", c); }
+    if (!(d->delta[c] >= 0.0) || !std::isfinite(d->delta[c])) { delete g; return fail(SIS_E_INVALID, "case %d delta must be >= 0", c); }
+    if (d->flow[c] != SIS_FLOW_NONE && d->flow[c] != SIS_FLOW_POISEUILLE) { delete g; return fail(SIS_E_UNSUPPORTED, "the tube supports Poiseuille flow only (case %d)", c); }
+  }
+  g->h_x.assign(d->x1, d->x1 + g->n_cells);
+  g->h_delta.assign(d->delta, d->delta + d->n_cases);
+  g->h_flow.assign(d->flow, d->flow + d->n_cases);
+  const int64_t nc = g->n_cells;
+  std::vector<double> cin(nc * 3, 0.0), cout(nc * 3, 0.0), tw(nc, 0.0), dcell(nc);
+  std::vector<int32_t> fcell(nc), ccell(nc);
+  auto coeffs = [](double d1, double d2, double* q) {
+    q[0] = (2.0 * d1 + d2) / (d1 * (d1 + d2));
+    q[1] = -(d1 + d2) / (d1 * d2);
+    q[2] = d1 / (d2 * (d1 + d2));
+  };
+  for (int c = 0; c < d->n_cases; ++c) {
+    const int64_t a = g->h_off[c];
+    const int n = static_cast<int>(g->h_off[c + 1] - a);
+    const double* r = d->x1 + a;
+    std::vector<double> xe(n + 2);
+    xe[0] = -r[1];
+    xe[1] = -r[0];
+    for (int i = 0; i < n; ++i) xe[i + 2] = r[i];
+    for (int i = 0; i < n; ++i) {
+      double* qi = &cin[(a + i) * 3];
+      if (i == n - 2) {
+        const double d1 = r[i] - r[i + 1];
+        qi[0] = 1.0 / d1;
+        qi[1] = -1.0 / d1;
+        qi[2] = 0.0;
+      } else if (i < n - 2) {
+        coeffs(r[i] - r[i + 1], r[i + 1] - r[i + 2], qi);
+      }
+      coeffs(xe[i + 2] - xe[i + 1], xe[i + 1] - xe[i], &cout[(a + i) * 3]);
+      const double lo = i == 0 ? 0.0 : r[i - 1], hi = i == n - 1 ? r[i] : r[i + 1];
+      tw[a + i] = r[i] * (hi - lo);
+      dcell[a + i] = d->delta[c];
+      fcell[a + i] = d->flow[c];
+      ccell[a + i] = c;
+    }
+  }
+#define TUBE_TRY(expr)                                                                         \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      delete g;                                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s", #expr,        \
+                  hipGetErrorString(e_));                                                      \
+    }                                                                                          \
+  } while (0)
+  TUBE_TRY(upload(&g->off, g->h_off, stream));
+  TUBE_TRY(upload(&g->d_r, g->h_x, stream));
+  TUBE_TRY(upload(&g->d_cin, cin, stream));
+  TUBE_TRY(upload(&g->d_cout, cout, stream));
+  TUBE_TRY(upload(&g->d_tw, tw, stream));
+  TUBE_TRY(upload(&g->delta_case, g->h_delta, stream));
+  TUBE_TRY(upload(&g->flow_case, g->h_flow, stream));
+  TUBE_TRY(upload(&g->delta_cell, dcell, stream));
+  TUBE_TRY(upload(&g->flow_cell, fcell, stream));
+  TUBE_TRY(upload(&g->case_of_cell, ccell, stream));
+  TUBE_TRY(hipStreamSynchronize(stream));
+#undef TUBE_TRY
+  *out = g;
+  g_err.clear();
+  return SIS_OK;
+}
+
 sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream_t stream, sis_geom_t* out) {
   if (!d->n1 || !d->n2 || !d->face1 || !d->face2 || !d->delta || !d->flow)
     return fail(SIS_E_INVALID, "null 2-D geometry array");
@@ -1179,6 +1332,7 @@ sis_status sis_host_tables(const sis_velocity_desc* desc, double* feq, double* n
                            double* B, double* b0, double* nubar) {
   sis_status st = validate_desc(desc);
   if (st) return st;
+  if (desc->grid == SIS_GRID_POLAR) return fail(SIS_E_UNSUPPORTED, "host tables are for the Cartesian grids");
   std::string err;
   if (desc->n_species == 2) {
     if (A || B) return fail(SIS_E_UNSUPPORTED, "A/B fields are not reported for mixtures");
@@ -1203,11 +1357,210 @@ sis_status sis_host_tables(const sis_velocity_desc* desc, double* feq, double* n
   return SIS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Polar velocity grid (tube): host tables, then the operator assembled on the device from
+// the half-space Cartesian modes l (pair weight s_l = 2, 1 for l = 0, over n_pad^3):
+//   fhat_l = sum_j w'_j f_eq 4 cos cos cos            (w' = w_base / dv_c^3)
+//   AB[i][t] = sum_l cos(xi_l . v_i) m_t(l) fhat_l s_l     (F^-1 of m_t F f_eq at the nodes)
+//   a_t(i): 4 b0 W_p B_p(i) with psi_p, 4 b0 W_p A_p(i) with phi_p, -f_eq(i) with beta
+//   C[i][l] = sum_t a_t(i) m_t(l);  op = sum_l C[i][l] s_l [cos_i c_j(l) + sin_i s_j(l)]
+// where c_j, s_j are the cos / sin parts of sum over the four mirror images of node j of
+// sign w'_j e^{i xi.v} (sign -1 for v_z -> -v_z).  Three FP64 MFMA contractions.
+sis_status create_polar_plan(const sis_velocity_desc* desc, hipStream_t stream, sis_plan_t* out) {
+  auto t0 = std::chrono::steady_clock::now();
+  sis::PolarDesc pd;
+  pd.n_vr = desc->n_vr;
+  pd.n_th = desc->n_th;
+  pd.n_vz = desc->n_vz;
+  pd.vr_max = desc->vr_max;
+  pd.vz_max = desc->l_v;
+  pd.n_pad = desc->n_pad;
+  pd.l_pad = desc->l_pad;
+  pd.m_angle = desc->m_angle;
+  pd.n_threads = desc->n_threads;
+  sis::PolarTables t;
+  std::string err;
+  if (!sis::build_polar_tables(pd, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
+  auto t1 = std::chrono::steady_clock::now();
+  sis_plan* p = new sis_plan();
+  HIP_TRY(hipGetDevice(&p->device));
+  const int nv = t.nv, nm = t.nm, Tp = t.Tp, D = t.D;
+  p->polar = true;
+  p->n = 0;
+  p->n3 = nv;
+  p->nv = nv;
+  p->ndof = nv;
+  p->nsp = 1;
+  p->np = t.np;
+  p->D = D;
+  p->m_angle = desc->m_angle;
+  p->lv = desc->l_v;
+  p->dv = t.dvc;
+  p->b0 = t.b0;
+  p->R = t.R;
+  p->n_vr = t.n_vr;
+  p->n_th = t.n_th;
+  p->n_vz = t.n_vz;
+  p->dth = 3.14159265358979323846 / t.n_th;
+  p->alpha = 1.0;
+  p->gamma = 0.0;
+  std::vector<double> wn(nv), wf(nv), wp(nv), cth(t.n_th), sth(t.n_th);
+  const double dvc3 = t.dvc * t.dvc * t.dvc;
+  for (int j = 0; j < nv; ++j) {
+    wn[j] = 4.0 * t.wbase[j];
+    wp[j] = t.wbase[j] / dvc3;
+    wf[j] = wp[j] * t.feq[j];
+  }
+  for (int k = 0; k < t.n_th; ++k) {
+    cth[k] = std::cos(t.th[k]);
+    sth[k] = std::sin(t.th[k]);
+  }
+  // coefficient sources: psi_p terms take B_p = column D + p, phi_p terms take A_p = column p
+  std::vector<int32_t> srcT(Tp, -2);
+  std::vector<double> cT(Tp, 0.0), sc(nm);
+  for (int q = 0; q < D; ++q) {
+    srcT[q] = D + q;
+    cT[q] = 4.0 * t.b0 * t.W[q];
+    srcT[D + q] = q;
+    cT[D + q] = 4.0 * t.b0 * t.W[q];
+  }
+  srcT[2 * D] = -1;
+  const double inp3 = 1.0 / (static_cast<double>(t.np) * t.np * t.np);
+  for (int m = 0; m < nm; ++m) sc[m] = t.pair[m] * inp3;
+  double *dxi = nullptr, *dsc = nullptr, *dwf = nullptr, *dwp = nullptr, *dfh = nullptr, *dmt = nullptr,
+         *dterm = nullptr, *dAB = nullptr, *daT = nullptr, *dcT = nullptr, *bufA = nullptr, *bufB = nullptr,
+         *bufC = nullptr, *dcorr = nullptr;
+  int32_t* dsrc = nullptr;
+  auto cleanup = [&]() {
+    dfree(dxi); dfree(dsc); dfree(dwf); dfree(dwp); dfree(dfh); dfree(dmt); dfree(dterm); dfree(dAB);
+    dfree(daT); dfree(dcT); dfree(bufA); dfree(bufB); dfree(bufC); dfree(dcorr); dfree(dsrc);
+  };
+#define POL_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) {                                                                    \
+      cleanup();                                                                               \
+      delete p;                                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "%s: %s", #expr,        \
+                  hipGetErrorString(e_));                                                      \
+    }                                                                                          \
+  } while (0)
+  POL_TRY(upload(&p->vnode, t.vnode, stream));
+  POL_TRY(upload(&p->wnode, wn, stream));
+  POL_TRY(upload(&p->feq, t.feq, stream));
+  POL_TRY(upload(&p->d_vr, t.vr, stream));
+  POL_TRY(upload(&p->d_cth, cth, stream));
+  POL_TRY(upload(&p->d_sth, sth, stream));
+  POL_TRY(dmalloc(&p->nu, nv));
+  POL_TRY(dmalloc(&p->op, static_cast<size_t>(nv) * nv));
+  POL_TRY(dmalloc(&p->Kc, nv));
+  POL_TRY(dmalloc(&p->gram_inv, 25));
+  POL_TRY(dmalloc(&p->v1d, 1));
+  POL_TRY(upload(&dxi, t.xi, stream));
+  POL_TRY(upload(&dsc, sc, stream));
+  POL_TRY(upload(&dwf, wf, stream));
+  POL_TRY(upload(&dwp, wp, stream));
+  POL_TRY(upload(&dsrc, srcT, stream));
+  POL_TRY(upload(&dcT, cT, stream));
+  POL_TRY(dmalloc(&dfh, nm));
+  POL_TRY(sis::launch_polar_fhat(nm, dxi, nv, p->vnode, dwf, dfh, stream));
+  // fields A_p, B_p, nu at the nodes
+  POL_TRY(upload(&dmt, t.mt_tm, stream));
+  POL_TRY(dmalloc(&dterm, static_cast<size_t>(Tp) * nm));
+  POL_TRY(sis::launch_polar_scale_terms(Tp, nm, dmt, dfh, dsc, dterm, stream));
+  POL_TRY(dmalloc(&bufA, static_cast<size_t>(nv) * nm));
+  POL_TRY(sis::launch_polar_cos(nv, nm, p->vnode, dxi, bufA, stream));
+  POL_TRY(dmalloc(&dAB, static_cast<size_t>(nv) * Tp));
+  sis::GemmArgs g{};
+  g.precision = 0;
+  g.splits = 1;
+  g.tile = 0;
+  g.X = bufA;
+  g.op64 = dterm;
+  g.acc = dAB;
+  g.M = nv;
+  g.N = Tp;
+  g.K = nm;
+  POL_TRY(sis::launch_gemm(g, stream));
+  POL_TRY(dmalloc(&daT, static_cast<size_t>(nv) * Tp));
+  POL_TRY(sis::launch_polar_coef(nv, Tp, dAB, dsrc, dcT, p->feq, 2 * D, daT, p->nu, stream));
+  // C = a m^T into bufA, then the cos / sin factors of both sides and the contraction over modes
+  POL_TRY(hipStreamSynchronize(stream));
+  dfree(dmt);
+  dmt = nullptr;
+  POL_TRY(upload(&dmt, t.mt_mm, stream));
+  g.X = daT;
+  g.op64 = dmt;
+  g.acc = bufA;
+  g.M = nv;
+  g.N = nm;
+  g.K = Tp;
+  POL_TRY(sis::launch_gemm(g, stream));
+  POL_TRY(dmalloc(&bufB, static_cast<size_t>(nv) * 2 * nm));
+  POL_TRY(dmalloc(&bufC, static_cast<size_t>(nv) * 2 * nm));
+  POL_TRY(sis::launch_polar_xc(nv, nm, p->vnode, dxi, dsc, bufA, bufB, stream));
+  POL_TRY(sis::launch_polar_op2(nv, nm, p->vnode, dxi, dwp, bufC, stream));
+  g.X = bufB;
+  g.op64 = bufC;
+  g.acc = p->op;
+  g.M = nv;
+  g.N = nv;
+  g.K = 2 * nm;
+  POL_TRY(sis::launch_gemm(g, stream));
+  // host copies of f_eq and nu; nubar, correction moments, Kc = L+(2 v_z f_eq)
+  p->h_feq = t.feq;
+  p->h_nu.assign(nv, 0.0);
+  POL_TRY(hipMemcpyAsync(p->h_nu.data(), p->nu, nv * 8, hipMemcpyDeviceToHost, stream));
+  POL_TRY(hipStreamSynchronize(stream));
+  std::vector<double> corr(nv);
+  for (int j = 0; j < nv; ++j) {
+    const double v1 = t.vnode[j], v2 = t.vnode[nv + j], v3 = t.vnode[2 * nv + j];
+    corr[j] = 2.0 * v3 * t.feq[j];
+    p->nubar += wn[j] * p->h_nu[j] * t.feq[j];
+    p->cU += wn[j] * v3 * corr[j];
+    p->cq += wn[j] * (v1 * v1 + v2 * v2 + v3 * v3 - 2.5) * v3 * corr[j];
+  }
+  p->nubar_s[0] = p->nubar;
+  p->cU_s[0] = p->cU;
+  p->cq_s[0] = p->cq;
+  POL_TRY(upload(&dcorr, corr, stream));
+  g.X = dcorr;
+  g.op64 = p->op;
+  g.acc = p->Kc;
+  g.M = 1;
+  g.N = nv;
+  g.K = nv;
+  g.tile = 1;
+  if (nv % 2) {
+    cleanup();
+    delete p;
+    return fail(SIS_E_INVALID, "polar grid: n_vr n_th n_vz must be even");
+  }
+  POL_TRY(sis::launch_gemm(g, stream));
+  POL_TRY(hipStreamSynchronize(stream));
+  cleanup();
+#undef POL_TRY
+  auto t2 = std::chrono::steady_clock::now();
+  p->host_s = std::chrono::duration<double>(t1 - t0).count();
+  p->dev_s = std::chrono::duration<double>(t2 - t1).count();
+  *out = p;
+  g_err.clear();
+  return SIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, sis_plan_t* out) {
   if (!out) return fail(SIS_E_INVALID, "null output handle");
   *out = nullptr;
   sis_status st = validate_desc(desc);
   if (st) return st;
+  if (desc->grid == SIS_GRID_POLAR) return create_polar_plan(desc, stream, out);
   if (desc->n_species == 2) return create_mix_plan(desc, stream, out);
   auto t0 = std::chrono::steady_clock::now();
   sis::HostTables t;
@@ -1425,6 +1778,9 @@ sis_status sis_geometry_create(sis_plan_t p, const sis_geometry_desc* d, hipStre
       if (d->flow && d->flow[c] != SIS_FLOW_NONE && d->flow[c] != SIS_FLOW_POISEUILLE)
         return fail(SIS_E_UNSUPPORTED, "mixtures support Poiseuille flow only (case %d)", c);
   }
+  if ((d->kind == SIS_GEOM_TUBE) != p->polar)
+    return fail(SIS_E_UNSUPPORTED, "the tube geometry and the polar velocity grid go together");
+  if (d->kind == SIS_GEOM_TUBE) return create_geometry_tube(p, d, stream, out);
   if (d->kind == SIS_GEOM_DUCT_QUARTER || d->kind == SIS_GEOM_PERIODIC_2D)
     return create_geometry_2d(p, d, stream, out);
   if (d->kind != SIS_GEOM_PLANAR_HALF) return fail(SIS_E_UNSUPPORTED, "geometry kind %d not supported", d->kind);
@@ -1561,6 +1917,7 @@ sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const dou
   if (!aligned16(h) || !aligned16(rhs_out)) return fail(SIS_E_INVALID, "h and rhs_out must be 16-byte aligned");
   if (h == rhs_out) return fail(SIS_E_INVALID, "rhs_out must not alias h");
   if (project && p->nsp != 1) return fail(SIS_E_UNSUPPORTED, "invariant projection is for one gas only");
+  if (project && p->polar) return fail(SIS_E_UNSUPPORTED, "invariant projection is for the Cartesian grids");
   {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(stream, &cs));
@@ -1584,6 +1941,10 @@ sis_status sis_moments(sis_plan_t p, int64_t n_cells, const double* h, double* m
   if (n_cells < 0) return fail(SIS_E_SHAPE, "n_cells must be >= 0");
   if (n_cells == 0) return SIS_OK;
   if (!h || !mom_out) return fail(SIS_E_INVALID, "null array");
+  if (p->polar) {
+    HIP_TRY(sis::launch_moments_tube(n_cells, p->nv, p->vnode, p->wnode, h, nullptr, mom_out, stream));
+    return SIS_OK;
+  }
   HIP_TRY(sis::launch_moments(p->n, p->d2, p->d3, p->nsp, p->mass_ratio, n_cells * p->nsp, p->v1d,
                               p->v1d + (p->n - p->d2), p->v1d + (p->n - p->d3), h, p->wr, mom_out, stream));
   return SIS_OK;
@@ -1596,6 +1957,13 @@ sis_status sis_diffusion_correct(sis_plan_t p, sis_geom_t g, const double* mom_h
   if (!g || g->plan != p) return fail(SIS_E_INVALID, "geometry does not belong to this plan");
   if (!mom_half) return fail(SIS_E_INVALID, "mom_half must be non-null");
   if (!std::isfinite(N)) return fail(SIS_E_INVALID, "N must be finite");
+  if (g->tube) {
+    sis::TubeDiffArgs a = tube_diff_args(p, g, mom_half, amom, N > 0.0 ? N : p->nubar);
+    a.U = U_out;
+    a.dU = dU_out;
+    HIP_TRY(sis::launch_diffusion_tube(a, stream));
+    return SIS_OK;
+  }
   if (g->two_d) {
     sis::Diff2DArgs a = diff2d_args(p, g, mom_half, amom, p->nsp == 2 ? N : (N > 0.0 ? N : p->nubar));
     a.U = U_out;
@@ -1672,6 +2040,21 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
                                   prec, mode, b->xref, b->accref, &b->ws_acc, &b->ws_x))
     return st;
   if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s, b->lact, &b->ws_part)) return st;
+  if (g->tube) {
+    sis::TubeDiffArgs a = tube_diff_args(p, g, b->mom, b->amom, b->Npen);
+    a.sis = sis ? 1 : 0;
+    a.U = nullptr;
+    a.ufield = b->U;
+    a.dU = b->dU;
+    a.qfield = b->q;
+    a.state = b->state;
+    a.iters = b->iters;
+    a.case_active = b->cact;
+    a.eps = b->o.eps;
+    HIP_TRY(sis::launch_diffusion_tube(a, s));
+    HIP_TRY(sis::launch_expand_active(b->cact, g->case_of_cell, g->n_cells, b->lact, s));
+    return SIS_OK;
+  }
   if (g->two_d) {
     sis::Diff2DArgs a = diff2d_args(p, g, b->mom, b->amom, p->nsp == 2 ? b->o.N : b->Npen);
     a.sis = sis ? 1 : 0;
@@ -1762,6 +2145,7 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   const int n3 = p->ndof;  // unknowns per cell
   const int nsp = p->nsp;
   if (nsp == 2 && o->project) { delete b; return fail(SIS_E_UNSUPPORTED, "invariant projection is for one gas only"); }
+  if (p->polar && o->project) { delete b; return fail(SIS_E_UNSUPPORTED, "invariant projection is for the Cartesian grids"); }
 #define ST_TRY(expr)                                                                            \
   do {                                                                                          \
     hipError_t e_ = (expr);                                                                     \

@@ -77,6 +77,10 @@ struct FinishArgs {
   const double* Kc;        // [nsp][nsp][n3]: L+_1 of the correction 2 (m_q/m_A) v3 f_q of species q
   const double* gram_inv;  // [25]
   double w;
+  // polar velocity grid: per-node velocity components [3][n3] and weights [n3] (mirror
+  // images included); null for the Cartesian grids (v1d/v2d/v3d and w)
+  const double* vnode;
+  const double* wnode;
   const int32_t* active;   // [cells] or null: skip cells with active == 0
   // FP64-anchored defect correction (solver only; mode 0 = off):
   //  mode 1 (refresh):     acc is op*h in FP64; store accref = acc, xref = h
@@ -249,5 +253,75 @@ hipError_t launch_ns_init(double* X, int n, double alpha, hipStream_t s);
 // cell_active[c] = case_active[case_of_cell[c]]
 hipError_t launch_expand_active(const int32_t* case_active, const int32_t* case_of_cell,
                                 int64_t n_cells, int32_t* cell_active, hipStream_t s);
+
+// ------------------------------------------------------------------ polar velocity grid (tube)
+// Assembly of the fast-spectral operator on polar nodes v_j (stored th, v_z > 0 halves; the
+// distribution is even in th and odd in v_z) from nm half-space Cartesian modes xi[3][nm]:
+//   fhat[m] = sum_j wf[j] 4 cos(xi0 v1) cos(xi1 v2) cos(xi2 v3)     (f_eq, even-even fold)
+//   X[i][m] = cos(xi_m . v_i)
+//   Xc[i][2m], Xc[i][2m+1] = C[i][m] s[m] {cos, sin}(xi_m . v_i)
+//   Op2[j][2m], Op2[j][2m+1] = 4 wp[j] {-sin a cos b sin c, cos a cos b sin c}  (odd-v_z fold,
+//                             a, b, c = xi0 v1_j, xi1 v2_j, xi2 v3_j)
+//   out[t][m] = mt[t][m] fhat[m] s[m]
+hipError_t launch_polar_fhat(int nm, const double* xi, int nv, const double* vnode, const double* wf, double* fhat,
+                             hipStream_t s);
+hipError_t launch_polar_cos(int nv, int nm, const double* vnode, const double* xi, double* X, hipStream_t s);
+hipError_t launch_polar_scale_terms(int Tp, int nm, const double* mt, const double* fhat, const double* sc,
+                                    double* out, hipStream_t s);
+// aT[i][t] = c[t] AB[i][src[t]] (src[t] >= 0), -feq[i] (src[t] == -1), 0 (src[t] == -2); nu[i] = AB[i][inu]
+hipError_t launch_polar_coef(int nv, int Tp, const double* AB, const int32_t* src, const double* c,
+                             const double* feq, int inu, double* aT, double* nu, hipStream_t s);
+hipError_t launch_polar_xc(int nv, int nm, const double* vnode, const double* xi, const double* sc,
+                           const double* C, double* Xc, hipStream_t s);
+hipError_t launch_polar_op2(int nv, int nm, const double* vnode, const double* xi, const double* wp, double* Op2,
+                            hipStream_t s);
+
+// Tube (Sec. 4): radial nodes r of each case (r[last] = 1, the wall), velocities of the polar
+// grid (n_vr x n_th x n_vz, v_z fastest).
+struct TubeSweepArgs {
+  int n_vr, n_th, n_vz, nv;
+  int n_cases;
+  const int64_t* node_off;   // [n_cases + 1]
+  const double* r;           // [nodes]
+  const double* cin;         // [nodes][3] inward (from larger r) coefficients of d/dr
+  const double* cout;        // [nodes][3] outward coefficients (ghosts -r_1, -r_0 at the centre)
+  const double* vr;          // [n_vr]
+  const double* cth;         // [n_th] cos th
+  const double* sth;         // [n_th] sin th
+  double dth;
+  const double* delta_case;
+  const double* nu;          // [nv]
+  const double* rhs;         // [nodes][nv]
+  double* h;                 // [nodes][nv]
+  const int32_t* case_active;
+  int max_nodes;
+};
+hipError_t launch_sweep_tube(const TubeSweepArgs& a, hipStream_t s);
+// mom[node][8] = {U3, q3, G = int v3 (2 v1^2 - 1) h, S2 = int 2 v3 (v1^2 - v2^2) h, P_rz = int 2 v1 v3 h, 0, 0, 0}
+hipError_t launch_moments_tube(int64_t n_nodes, int nv, const double* vnode, const double* wnode, const double* h,
+                               const int32_t* active, double* mom, hipStream_t s);
+struct TubeDiffArgs {
+  int n_cases;
+  const int64_t* node_off;
+  const double* r;
+  const double* cin;         // inward coefficients (as in the sweep)
+  const double* tw;          // [nodes] weights of 2 int_0^1 f r dr
+  const double* delta_case;
+  const int32_t* flow_case;
+  const double* mom;         // [nodes][8]
+  const double* amom;        // [nodes][4] or null
+  double N;
+  int sis;
+  double cU, cq;
+  double* U;
+  double* dU;
+  double* ufield;
+  double* qfield;
+  double* state;             // [n_cases][4] or null
+  int32_t* iters;
+  int32_t* case_active;
+  double eps;
+};
+hipError_t launch_diffusion_tube(const TubeDiffArgs& a, hipStream_t s);
 
 }  // namespace sis

@@ -582,8 +582,19 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
   for (int k = 0; k < 9; ++k) m[k] = 0.0;
   const int d2 = a.d2, d3 = a.d3, d23 = d2 * d3;
   for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-    const int j1 = v / d23, j2 = (v / d3) % d2, j3 = v % d3;
-    const double v1 = a.v1d[j1], v2 = a.v2d[j2], v3 = a.v3d[j3];
+    double v1, v2, v3, wv;
+    if (a.vnode) {
+      v1 = a.vnode[v];
+      v2 = a.vnode[n3 + v];
+      v3 = a.vnode[2 * n3 + v];
+      wv = a.wnode[v];
+    } else {
+      const int j1 = v / d23, j2 = (v / d3) % d2, j3 = v % d3;
+      v1 = a.v1d[j1];
+      v2 = a.v2d[j2];
+      v3 = a.v3d[j3];
+      wv = a.w;
+    }
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
     const double f = feq[v];
     double s = 0.0;
@@ -605,16 +616,16 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
     else if (fl == 2 && nsp == 1) S = v3 * (vsq - 2.5) * f;
     a.rhs[base + v] = del * lp + S;
     if (a.lh) a.lh[base + v] = L;
-    const double wL = a.w * L;
+    const double wL = wv * L;
     m[0] += wL;
     m[1] += wL * v1;
     m[2] += wL * v2;
     m[3] += wL * v3;
     m[4] += wL * vsq;
-    m[5] += 2.0 * a.w * v1 * v3 * L;
-    m[6] += 2.0 * a.w * v1 * v3 * hk;
-    m[7] += 2.0 * a.w * v2 * v3 * L;
-    m[8] += 2.0 * a.w * v2 * v3 * hk;
+    m[5] += 2.0 * wv * v1 * v3 * L;
+    m[6] += 2.0 * wv * v1 * v3 * hk;
+    m[7] += 2.0 * wv * v2 * v3 * L;
+    m[8] += 2.0 * wv * v2 * v3 * hk;
   }
   block_sum<9>(m, sh);
   if (a.project) {
@@ -1408,6 +1419,234 @@ __global__ void ns_scatter_kernel(double* __restrict__ S, int n, const int32_t* 
   S[static_cast<int64_t>(rc[2 * i]) * n + rc[2 * i + 1]] = val[i];
 }
 
+// ------------------------------------------------------------------ polar velocity grid (tube)
+__global__ void polar_fhat_kernel(int nm, const double* __restrict__ xi, int nv, const double* __restrict__ vnode,
+                                  const double* __restrict__ wf, double* __restrict__ fhat) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nm) return;
+  const double x0 = xi[m], x1 = xi[nm + m], x2 = xi[2 * nm + m];
+  double s = 0.0;
+  for (int j = 0; j < nv; ++j)
+    s += wf[j] * cos(x0 * vnode[j]) * cos(x1 * vnode[nv + j]) * cos(x2 * vnode[2 * nv + j]);
+  fhat[m] = 4.0 * s;
+}
+
+__global__ void polar_cos_kernel(int nv, int nm, const double* __restrict__ vnode, const double* __restrict__ xi,
+                                 double* __restrict__ X) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(nv) * nm) return;
+  const int i = static_cast<int>(idx / nm), m = static_cast<int>(idx % nm);
+  X[idx] = cos(xi[m] * vnode[i] + xi[nm + m] * vnode[nv + i] + xi[2 * nm + m] * vnode[2 * nv + i]);
+}
+
+__global__ void polar_scale_terms_kernel(int Tp, int nm, const double* __restrict__ mt,
+                                         const double* __restrict__ fhat, const double* __restrict__ sc,
+                                         double* __restrict__ out) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(Tp) * nm) return;
+  const int m = static_cast<int>(idx % nm);
+  out[idx] = mt[idx] * fhat[m] * sc[m];
+}
+
+__global__ void polar_coef_kernel(int nv, int Tp, const double* __restrict__ AB, const int32_t* __restrict__ srcT,
+                                  const double* __restrict__ c, const double* __restrict__ feq, int inu,
+                                  double* __restrict__ aT, double* __restrict__ nu) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(nv) * Tp) return;
+  const int i = static_cast<int>(idx / Tp), t = static_cast<int>(idx % Tp);
+  const int sidx = srcT[t];
+  aT[idx] = sidx >= 0 ? c[t] * AB[static_cast<int64_t>(i) * Tp + sidx] : (sidx == -1 ? -feq[i] : 0.0);
+  if (t == 0) nu[i] = AB[static_cast<int64_t>(i) * Tp + inu];
+}
+
+__global__ void polar_xc_kernel(int nv, int nm, const double* __restrict__ vnode, const double* __restrict__ xi,
+                                const double* __restrict__ sc, const double* __restrict__ C, double* __restrict__ Xc) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(nv) * nm) return;
+  const int i = static_cast<int>(idx / nm), m = static_cast<int>(idx % nm);
+  const double ph = xi[m] * vnode[i] + xi[nm + m] * vnode[nv + i] + xi[2 * nm + m] * vnode[2 * nv + i];
+  const double cm = C[idx] * sc[m];
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  Xc[2 * idx] = cm * cs;
+  Xc[2 * idx + 1] = cm * sn;
+}
+
+__global__ void polar_op2_kernel(int nv, int nm, const double* __restrict__ vnode, const double* __restrict__ xi,
+                                 const double* __restrict__ wp, double* __restrict__ Op2) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(nv) * nm) return;
+  const int j = static_cast<int>(idx / nm), m = static_cast<int>(idx % nm);
+  double sa, ca, sc_, cc;
+  sincos(xi[m] * vnode[j], &sa, &ca);
+  const double cb = cos(xi[nm + m] * vnode[nv + j]);
+  sincos(xi[2 * nm + m] * vnode[2 * nv + j], &sc_, &cc);
+  const double w4 = 4.0 * wp[j] * cb * sc_;
+  Op2[2 * idx] = -w4 * sa;
+  Op2[2 * idx + 1] = w4 * ca;
+}
+
+// ------------------------------------------------------------------ tube
+// One workgroup per (case, group of kTubeV (v_r, v_z) pairs).  Inward molecules
+// (th > pi/2) are swept from the wall to the centre, then outward ones from the
+// centre to the wall; in both passes a node depends on its two r-upwind nodes and
+// its two th-upwind (larger th) nodes, so the anti-diagonals of (r, th) are
+// processed in order with a workgroup barrier between them.
+constexpr int kTubeV = 8;
+constexpr int kTubeThreads = 256;
+
+__global__ __launch_bounds__(kTubeThreads) void sweep_tube_kernel(TubeSweepArgs a) {
+  const int cs = blockIdx.y;
+  if (a.case_active && !a.case_active[cs]) return;
+  const int nth = a.n_th, half = nth / 2, nvz = a.n_vz, nv = a.nv;
+  const int pairs = a.n_vr * nvz;
+  const int tq = blockIdx.x * kTubeV + threadIdx.x % kTubeV;
+  const bool valid = tq < pairs;
+  const int q = valid ? tq : 0;
+  const int ivr = q / nvz, iz = q % nvz;
+  const int slot = threadIdx.x / kTubeV, slots = kTubeThreads / kTubeV;
+  const int64_t n0 = a.node_off[cs];
+  const int n = static_cast<int>(a.node_off[cs + 1] - n0);
+  const double del = a.delta_case[cs];
+  const double vr = a.vr[ivr];
+  const double tc = 1.0 / (2.0 * a.dth);
+  auto vix = [&](int k) { return (ivr * nth + k) * nvz + iz; };
+  // wall node, inward velocities: molecules leaving a diffuse wall carry h = 0
+  for (int kk = slot; kk < half; kk += slots)
+    if (valid) a.h[(n0 + n - 1) * nv + vix(half + kk)] = 0.0;
+  __syncthreads();
+  // inward pass: ii = n - 2 - i, kk = n_th - 1 - k
+  for (int d = 0; d <= (n - 2) + (half - 1); ++d) {
+    const int lo = max(0, d - (n - 2)), hi = min(d, half - 1);
+    for (int c0 = lo; c0 <= hi; c0 += slots) {
+      const int kk = c0 + slot;
+      if (valid && kk <= hi) {
+        const int i = n - 2 - (d - kk), k = nth - 1 - kk;
+        const int64_t node = n0 + i;
+        const int v = vix(k);
+        const double c1 = vr * a.cth[k], ct = vr * a.sth[k] / a.r[node];
+        const double* cf = a.cin + node * 3;
+        double up = cf[1] * a.h[(node + 1) * nv + v];
+        if (i < n - 2) up += cf[2] * a.h[(node + 2) * nv + v];
+        double diag = del * a.nu[v] + c1 * cf[0];
+        double src = a.rhs[node * nv + v] - c1 * up;
+        if (k < nth - 1) {
+          const int k2 = min(k + 2, nth - 1);
+          diag += ct * 3.0 * tc;
+          src += ct * (4.0 * a.h[node * nv + vix(k + 1)] - a.h[node * nv + vix(k2)]) * tc;
+        }
+        a.h[node * nv + v] = src / diag;
+      }
+    }
+    __syncthreads();
+  }
+  // outward pass: kk = half - 1 - k; ghosts across the centre hold h(r, pi - th)
+  for (int d = 0; d <= (n - 1) + (half - 1); ++d) {
+    const int lo = max(0, d - (n - 1)), hi = min(d, half - 1);
+    for (int c0 = lo; c0 <= hi; c0 += slots) {
+      const int kk = c0 + slot;
+      if (valid && kk <= hi) {
+        const int i = d - kk, k = half - 1 - kk, km = nth - 1 - k;
+        const int64_t node = n0 + i;
+        const int v = vix(k);
+        const double c1 = vr * a.cth[k], ct = vr * a.sth[k] / a.r[node];
+        const double* cf = a.cout + node * 3;
+        const double y1 = i >= 1 ? a.h[(node - 1) * nv + v] : a.h[n0 * nv + vix(km)];
+        const double y2 = i >= 2 ? a.h[(node - 2) * nv + v] : a.h[(n0 + 1 - i) * nv + vix(km)];
+        const double diag = del * a.nu[v] + c1 * cf[0] + ct * 3.0 * tc;
+        const double src = a.rhs[node * nv + v] - c1 * (cf[1] * y1 + cf[2] * y2) +
+                           ct * (4.0 * a.h[node * nv + vix(k + 1)] - a.h[node * nv + vix(k + 2)]) * tc;
+        a.h[node * nv + v] = src / diag;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void moments_tube_kernel(int nv, const double* __restrict__ vnode,
+                                                           const double* __restrict__ wnode,
+                                                           const double* __restrict__ h,
+                                                           const int32_t* __restrict__ active,
+                                                           double* __restrict__ mom) {
+  __shared__ double sh[4 * 5];
+  const int64_t c = blockIdx.x;
+  if (active && !active[c]) return;
+  double m[5] = {0, 0, 0, 0, 0};
+  for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    const double v1 = vnode[v], v2 = vnode[nv + v], v3 = vnode[2 * nv + v];
+    const double x = wnode[v] * h[c * nv + v];
+    m[0] += v3 * x;
+    m[1] += (v1 * v1 + v2 * v2 + v3 * v3 - 2.5) * v3 * x;
+    m[2] += v3 * (2.0 * v1 * v1 - 1.0) * x;
+    m[3] += 2.0 * v3 * (v1 * v1 - v2 * v2) * x;
+    m[4] += 2.0 * v1 * v3 * x;
+  }
+  block_sum<5>(m, sh);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 5; ++k) mom[c * 8 + k] = m[k];
+    mom[c * 8 + 5] = 0.0;
+    mom[c * 8 + 6] = 0.0;
+    mom[c * 8 + 7] = 0.0;
+  }
+}
+
+// Velocity equation of the tube per case (one thread: a march over the radial nodes),
+// outputs, flow rates 2 int_0^1 f r dr and the convergence test.
+__global__ void diffusion_tube_kernel(TubeDiffArgs a) {
+  const int cs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cs >= a.n_cases) return;
+  if (a.case_active && !a.case_active[cs]) return;
+  const int64_t n0 = a.node_off[cs];
+  const int n = static_cast<int>(a.node_off[cs + 1] - n0);
+  const double del = a.delta_case[cs];
+  const bool pois = a.flow_case[cs] == 1;
+  const double Nd = a.N * del;
+  double y1 = 0.0, y2 = 0.0, M = 0.0, Q = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    const int64_t node = n0 + i;
+    const double* m = a.mom + node * 8;
+    const double U3 = m[0], q3 = m[1], G = m[2];
+    double dU = 0.0, U = U3;
+    if (a.sis) {
+      double y;
+      if (i == n - 1) {
+        y = U3 + G;
+      } else {
+        double A = 0.0;
+        if (a.amom) A = a.amom[node * 4 + 0] + Nd * a.amom[node * 4 + 1];
+        const double r = a.r[node];
+        const double src = A - m[3] / r - (pois ? Nd * r / 2.0 : 0.0);
+        const double* cf = a.cin + node * 3;
+        y = i == n - 2 ? (src - cf[1] * y1) / cf[0] : (src - cf[1] * y1 - cf[2] * y2) / cf[0];
+      }
+      y2 = y1;
+      y1 = y;
+      U = y - G;
+      dU = U - U3;
+    }
+    const double Un = U3 + dU * a.cU, qn = q3 + dU * a.cq;
+    if (a.U) a.U[node] = U;
+    if (a.dU) a.dU[node] = dU;
+    if (a.ufield) a.ufield[node] = Un;
+    if (a.qfield) a.qfield[node] = qn;
+    M += a.tw[node] * Un;
+    Q += a.tw[node] * qn;
+  }
+  if (a.state) {
+    double* st = a.state + cs * 4;
+    const double dM = fabs(M - st[0]) / fmax(fabs(M), 1e-300);
+    const double dQ = fabs(Q - st[1]) / fmax(fabs(Q), 1e-300);
+    const double res = fmax(dM, dQ);
+    st[0] = M;
+    st[1] = Q;
+    st[2] = (M != M || Q != Q) ? __builtin_nan("") : res;
+    const int k = a.iters[cs] + 1;
+    a.iters[cs] = k;
+    if (!(res >= a.eps) || M != M || Q != Q) a.case_active[cs] = 0;
+    st[3] = static_cast<double>(k);
+  }
+}
+
 __global__ void expand_active_kernel(const int32_t* __restrict__ case_active,
                                      const int32_t* __restrict__ case_of_cell, int64_t n_cells,
                                      int32_t* __restrict__ cell_active) {
@@ -1601,6 +1840,68 @@ hipError_t launch_expand_active(const int32_t* case_active, const int32_t* case_
                                 int64_t n_cells, int32_t* cell_active, hipStream_t s) {
   hipLaunchKernelGGL(expand_active_kernel, dim3(static_cast<unsigned>((n_cells + 255) / 256)), dim3(256), 0, s,
                      case_active, case_of_cell, n_cells, cell_active);
+  return hipGetLastError();
+}
+
+hipError_t launch_polar_fhat(int nm, const double* xi, int nv, const double* vnode, const double* wf, double* fhat,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(polar_fhat_kernel, dim3((nm + 255) / 256), dim3(256), 0, s, nm, xi, nv, vnode, wf, fhat);
+  return hipGetLastError();
+}
+
+static dim3 grid_for(int64_t count) { return dim3(static_cast<unsigned>((count + 255) / 256)); }
+
+hipError_t launch_polar_cos(int nv, int nm, const double* vnode, const double* xi, double* X, hipStream_t s) {
+  hipLaunchKernelGGL(polar_cos_kernel, grid_for(static_cast<int64_t>(nv) * nm), dim3(256), 0, s, nv, nm, vnode, xi, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_polar_scale_terms(int Tp, int nm, const double* mt, const double* fhat, const double* sc,
+                                    double* out, hipStream_t s) {
+  hipLaunchKernelGGL(polar_scale_terms_kernel, grid_for(static_cast<int64_t>(Tp) * nm), dim3(256), 0, s, Tp, nm, mt,
+                     fhat, sc, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_polar_coef(int nv, int Tp, const double* AB, const int32_t* src, const double* c,
+                             const double* feq, int inu, double* aT, double* nu, hipStream_t s) {
+  hipLaunchKernelGGL(polar_coef_kernel, grid_for(static_cast<int64_t>(nv) * Tp), dim3(256), 0, s, nv, Tp, AB, src, c,
+                     feq, inu, aT, nu);
+  return hipGetLastError();
+}
+
+hipError_t launch_polar_xc(int nv, int nm, const double* vnode, const double* xi, const double* sc,
+                           const double* C, double* Xc, hipStream_t s) {
+  hipLaunchKernelGGL(polar_xc_kernel, grid_for(static_cast<int64_t>(nv) * nm), dim3(256), 0, s, nv, nm, vnode, xi,
+                     sc, C, Xc);
+  return hipGetLastError();
+}
+
+hipError_t launch_polar_op2(int nv, int nm, const double* vnode, const double* xi, const double* wp, double* Op2,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(polar_op2_kernel, grid_for(static_cast<int64_t>(nv) * nm), dim3(256), 0, s, nv, nm, vnode, xi,
+                     wp, Op2);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_tube(const TubeSweepArgs& a, hipStream_t s) {
+  if (a.max_nodes < 3) return hipErrorInvalidValue;
+  const int pairs = a.n_vr * a.n_vz;
+  dim3 grid((pairs + kTubeV - 1) / kTubeV, a.n_cases);
+  hipLaunchKernelGGL(sweep_tube_kernel, grid, dim3(kTubeThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_tube(int64_t n_nodes, int nv, const double* vnode, const double* wnode, const double* h,
+                               const int32_t* active, double* mom, hipStream_t s) {
+  if (n_nodes == 0) return hipSuccess;
+  hipLaunchKernelGGL(moments_tube_kernel, dim3(static_cast<unsigned>(n_nodes)), dim3(256), 0, s, nv, vnode, wnode,
+                     h, active, mom);
+  return hipGetLastError();
+}
+
+hipError_t launch_diffusion_tube(const TubeDiffArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(diffusion_tube_kernel, dim3((a.n_cases + 63) / 64), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

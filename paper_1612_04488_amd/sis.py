@@ -26,7 +26,8 @@ PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
 FLOW_NONE, FLOW_POISEUILLE, FLOW_TRANSPIRATION = 0, 1, 2
 SCHEME_CIS, SCHEME_SIS = 0, 1
-GEOM_PLANAR_HALF, GEOM_DUCT_QUARTER, GEOM_PERIODIC_2D = 0, 1, 2
+GEOM_PLANAR_HALF, GEOM_DUCT_QUARTER, GEOM_PERIODIC_2D, GEOM_TUBE = 0, 1, 2, 3
+GRID_CARTESIAN, GRID_POLAR = 0, 1
 DIFFUSION_CG, DIFFUSION_INVERSE = 0, 1
 
 
@@ -42,7 +43,9 @@ class VelocityDesc(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("visc_index", ctypes.c_double),
                 ("n_threads", ctypes.c_int32), ("n_species", ctypes.c_int32),
                 ("mass", ctypes.c_double * 2), ("diam", ctypes.c_double * 2),
-                ("chi", ctypes.c_double * 2), ("m_rho", ctypes.c_int32), ("parity", ctypes.c_int32)]
+                ("chi", ctypes.c_double * 2), ("m_rho", ctypes.c_int32), ("parity", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("n_vr", ctypes.c_int32), ("vr_max", ctypes.c_double),
+                ("n_th", ctypes.c_int32), ("n_vz", ctypes.c_int32), ("l_pad", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -169,13 +172,22 @@ def _stream(stream):
 
 
 def velocity_desc(n_v, l_v=6.0, n_pad=0, m_angle=6, kernel="hs", visc_index=0.81,
-                  r_trunc=0.0, n_threads=0, mixture=None, parity=0):
+                  r_trunc=0.0, n_threads=0, mixture=None, parity=0, polar=None):
     """mixture: None (one gas) or dict(masses=(m_A, m_B), diameters=(d_A, d_B),
     chi=(chi_A, chi_B), m_rho=16) for a binary hard-sphere mixture.
-    parity: 0 full grid, 1 store v3 > 0 (odd in v3), 2 store v2, v3 > 0 (planar)."""
+    parity: 0 full grid, 1 store v3 > 0 (odd in v3), 2 store v2, v3 > 0 (planar).
+    polar: None (Cartesian n_v^3 grid) or dict(n_vr, vr_max, n_th, n_vz, l_pad=0) for
+    the tube's polar grid (v_z on [0, l_v]; n_v and parity ignored)."""
     k = KERNEL_HARD_SPHERE if kernel == "hs" else KERNEL_IPL
     d = VelocityDesc(n_v, l_v, n_pad, m_angle, r_trunc, k, visc_index, n_threads)
     d.parity = int(parity)
+    if polar is not None:
+        d.grid = GRID_POLAR
+        d.n_vr = int(polar["n_vr"])
+        d.vr_max = float(polar["vr_max"])
+        d.n_th = int(polar["n_th"])
+        d.n_vz = int(polar["n_vz"])
+        d.l_pad = float(polar.get("l_pad", 0.0))
     if mixture is not None:
         d.n_species = 2
         d.mass[:] = [float(x) for x in mixture["masses"]]
@@ -210,17 +222,24 @@ class Plan:
     """Velocity grid + assembled fast-spectral operator on the current device."""
 
     def __init__(self, n_v, l_v=6.0, n_pad=0, m_angle=6, kernel="hs", visc_index=0.81,
-                 r_trunc=0.0, n_threads=0, stream=None, mixture=None, parity=0):
+                 r_trunc=0.0, n_threads=0, stream=None, mixture=None, parity=0, polar=None):
         self.desc = velocity_desc(n_v, l_v, n_pad, m_angle, kernel, visc_index, r_trunc, n_threads,
-                                  mixture, parity)
+                                  mixture, parity, polar)
         h = ctypes.c_void_p()
         check(lib().sis_plan_create(ctypes.byref(self.desc), _stream(stream), ctypes.byref(h)))
         self.handle = h
-        self.n_v = n_v
-        self.n3 = n_v ** 3
+        self.polar = polar is not None
         self.n_species = 2 if mixture is not None else 1
-        self.parity = int(parity)
-        self.n_vel = n_v * (n_v // 2 if parity == 2 else n_v) * (n_v // 2 if parity else n_v)
+        if self.polar:
+            self.n_v = 0
+            self.parity = 0
+            self.n_vel = int(polar["n_vr"]) * int(polar["n_th"]) * int(polar["n_vz"])
+            self.n3 = self.n_vel
+        else:
+            self.n_v = n_v
+            self.n3 = n_v ** 3
+            self.parity = int(parity)
+            self.n_vel = n_v * (n_v // 2 if parity == 2 else n_v) * (n_v // 2 if parity else n_v)
         self.n_dof = self.n_species * self.n_vel
 
     def close(self):
@@ -283,9 +302,11 @@ class Plan:
 
 
 class Geometry:
-    """Planar half-channel geometry for a batch of cases (host arrays copied)."""
+    """Planar half-channel geometry for a batch of cases (host arrays copied); with
+    kind="tube" (plans on the polar grid) the cases are tubes and xs their radial
+    nodes (r > 0 increasing to the wall r = 1)."""
 
-    def __init__(self, plan, xs, deltas, flows, stream=None):
+    def __init__(self, plan, xs, deltas, flows, stream=None, kind="planar"):
         import numpy as np
         self.plan = plan
         off = np.zeros(len(xs) + 1, dtype=np.int64)
@@ -294,12 +315,12 @@ class Geometry:
         self._x = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64) for x in xs]))
         self._d = np.ascontiguousarray(np.asarray(deltas, np.float64))
         self._f = np.ascontiguousarray(np.asarray(flows, np.int32))
-        d = GeometryDesc(GEOM_PLANAR_HALF, len(xs),
+        d = GeometryDesc(GEOM_TUBE if kind == "tube" else GEOM_PLANAR_HALF, len(xs),
                          self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                          self._x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self._d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                          self._f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
-        self.mom_stride = 4
+        self.mom_stride = 8 if kind == "tube" else 4
         h = ctypes.c_void_p()
         check(lib().sis_geometry_create(plan.handle, ctypes.byref(d), _stream(stream), ctypes.byref(h)))
         self.handle = h
