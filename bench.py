@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "small", "duct", "porous", "mixture", "mixture-duct", "sierpinski"])
+                    choices=["batch", "small", "duct", "porous", "mixture", "mixture-duct", "sierpinski", "tube"])
     ap.add_argument("--diffusion", default="inverse", choices=["inverse", "cg"],
                     help="2-D velocity equation: precomputed inverse or conjugate gradients")
     ap.add_argument("--ttr", default="fp64,fp32,bf16x3,fp64+projection,bf16x3+projection",
@@ -152,7 +152,7 @@ def main():
         return 0
     w = {"batch": inputs.PLANAR_BATCH, "small": inputs.PLANAR_SMALL, "duct": inputs.DUCT_IPL,
          "porous": inputs.POROUS_HS, "mixture": inputs.MIX_NEAR, "mixture-duct": inputs.MIX_DUCT,
-         "sierpinski": inputs.SIERPINSKI_HS}[args.workload]
+         "sierpinski": inputs.SIERPINSKI_HS, "tube": inputs.TUBE_HS}[args.workload]
     mix = w.get("mixture")
     # penalty N of the SIS velocity equations: nubar for one gas, 1.5 for the
     # mixture and the carpets (the values the paper runs them with)
@@ -160,17 +160,23 @@ def main():
     if mix and args.cpu_cells == 12:
         args.cpu_cells = 1
     planar = args.workload in ("batch", "small", "mixture")
-    parity = (2 if planar else 1) if args.parity == "auto" else int(args.parity)
+    tube = args.workload == "tube"
+    parity = (2 if planar else (0 if tube else 1)) if args.parity == "auto" else int(args.parity)
     t0 = time.perf_counter()
     plan = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"],
-                    visc_index=w.get("visc_index", 0.81), mixture=mix, parity=parity)
+                    visc_index=w.get("visc_index", 0.81), mixture=mix, parity=parity, polar=w.get("polar"))
     t_plan = time.perf_counter() - t0
     info = plan.info
     log(f"plan {w['name']}: {t_plan:.2f} s (host {info['plan_seconds_host']:.2f} s), "
         f"operator {info['operator_bytes'] / 2**30:.2f} GiB")
     t0 = time.perf_counter()
     diff_info = None
-    if planar:
+    if tube:
+        xs = [inputs.tube_radial(w["radial"])] * len(w["deltas"])
+        geom = sis.Geometry(plan, xs, w["deltas"], w["flows"], kind="tube")
+        per_case = [len(x) for x in xs]
+        Npen = 1.0
+    elif planar:
         xs = inputs.workload_nodes(w)
         geom = sis.Geometry(plan, xs, w["deltas"], w["flows"])
         per_case = [len(x) for x in xs]
@@ -192,7 +198,7 @@ def main():
 
     # ---------------------------------------------------------- whole-step throughput
     state = sis.State(plan, geom, scheme="SIS", N=Npen, eps=0.0, max_it=1 << 30,
-                      project=args.precision != "fp64" and not mix)
+                      project=args.precision != "fp64" and not mix and not tube)
     state.step(args.warmup)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -209,13 +215,16 @@ def main():
     state.close()
 
     # ---------------------------------------------------------- dominant kernel: contraction
-    h0 = inputs.mixture_h(w["n_v"], w["l_v"], nc) if mix else inputs.smooth_h(w["n_v"], w["l_v"], nc)
-    # both generators are odd in v3 and even in v2: keep the stored part
-    hv = w["n_v"] // 2
-    if parity >= 1:
-        h0 = h0[..., hv:]
-    if parity == 2:
-        h0 = h0[..., hv:, :]
+    if tube:
+        h0 = inputs.tube_h(n3, nc)
+    else:
+        h0 = inputs.mixture_h(w["n_v"], w["l_v"], nc) if mix else inputs.smooth_h(w["n_v"], w["l_v"], nc)
+        # both generators are odd in v3 and even in v2: keep the stored part
+        hv = w["n_v"] // 2
+        if parity >= 1:
+            h0 = h0[..., hv:]
+        if parity == 2:
+            h0 = h0[..., hv:, :]
     h = torch.tensor(np.ascontiguousarray(h0).reshape(nc, n3), device="cuda")
     delta = torch.tensor(np.repeat(w["deltas"], per_case), dtype=torch.float64, device="cuda")
     rhs = torch.empty_like(h)
@@ -243,7 +252,7 @@ def main():
                 "flops_per_cell_update": 2.0 * n3 * n3,
                 "fsm_fft_flops_per_cell_update": None}
     D = info["n_dir"]
-    Np3 = w["n_pad"] ** 3
+    Np3 = info["n_pad"] ** 3
     if not mix:
         roofline["fsm_fft_flops_per_cell_update"] = (2 * D + 2) * 2.5 * Np3 * np.log2(Np3) + 6 * D * Np3
 
@@ -252,7 +261,7 @@ def main():
     if not args.no_ttr:
         ref = {}
         runs = [(r.split("+")[0], r.endswith("+projection")) for r in args.ttr.split(",") if r]
-        if mix:
+        if mix or tube:
             runs = [(prec, proj) for prec, proj in runs if not proj]
         for prec, proj in runs:
             plan.set_precision(prec)
@@ -293,6 +302,14 @@ def main():
            "time_to_residual_1e-8": ttr}
     if diff_info:
         out["config"]["velocity_equation"] = diff_info
+    if tube:
+        out["config"]["n_pad"] = info["n_pad"]
+        out["config"]["parity"] = "polar grid: th in [0, pi] (even), v_z > 0 (odd)"
+        out["config"]["polar"] = w["polar"]
+        out["config"]["radial_nodes"] = w["radial"]
+    if tube and not args.no_cpu_baseline:
+        log("cpu baseline: the tube oracle's dense transform matrices do not fit at the paper's polar grid; skipped")
+        args.no_cpu_baseline = True
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         cb = cpu_baseline(w, args.cpu_cells)

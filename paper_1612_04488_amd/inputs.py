@@ -209,3 +209,23 @@ SIERPINSKI_HS = dict(name="sierpinski-l3-hs-24v-135sq-4cases", n_v=24, l_v=6.0, 
 def sierpinski_cases(w):
     c = sierpinski_quarter(w["level"], w["cells"])
     return [c for _ in w["deltas"]]
+
+
+# Tube (Sec. 4, Table 3): the paper's polar grid (22 v_r nodes on (0, 4), 40 th on
+# [0, pi], 12 v_z on (0, 6); FSM on the 48^3 lattice of spacing 1/2, M = 8), 150
+# radial nodes clustered at the wall, hard spheres, N = 1, ten delta of Table 3.
+TUBE_HS = dict(name="tube-hs-polar-22x40x12-150r-10cases", n_v=0, l_v=6.0, n_pad=0, m_angle=8, kernel="hs",
+               polar=dict(n_vr=22, vr_max=4.0, n_th=40, n_vz=12), radial=150,
+               deltas=[0.01, 0.1, 0.5, 1.0, 5.0, 10.0, 20.0, 30.0, 50.0, 100.0], flows=[1] * 10)
+
+
+def tube_radial(n):
+    """Radial nodes r_i = sin(pi (i + 1) / (2 n)): clustered at the wall r = 1."""
+    return np.sin(0.5 * np.pi * (np.arange(n) + 1.0) / n)
+
+
+def tube_h(nv, n_cells, seed=SEED):
+    """Seeded smooth-magnitude fields on a polar grid row (the values do not
+    change throughput)."""
+    rng = np.random.default_rng(seed + 11)
+    return rng.uniform(-1.0, 1.0, size=(n_cells, nv)) * 1e-2
