@@ -37,10 +37,10 @@ METRIC = "cell-updates/s of L(h) + time-to-residual 1e-8, mixed SIS vs FP64 plai
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 # HBM bytes per contraction launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (scaled by a 1 GiB copy: FETCH x2.0, WRITE x1.0), recorded for the kernel as it
-# stands, keyed by (workload, parity, precision, tile rows, split-K); a launch
+# stands, keyed by (workload, parity, precision, tile rows, split-K, k-stage); a launch
 # configuration without a recorded pass reports null.  Source:
 # profiles/gemm_f64_planar-hs-32v-808cells-parity.md.
-TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4): (1750706.0 * 2.0, 206848.0)}
+TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (1750706.0 * 2.0, 206848.0)}
 HBM_GBS = 8000.0
 
 
@@ -235,22 +235,43 @@ def main():
         plan.collide(h, delta, rhs)
     gemm_ms, launches = plan.timing_read()
     plan.timing(False)
-    tile_rows, splits, tuned = plan.contraction_config(nc, args.precision)
+    tile_rows, splits, tuned, k_stage = plan.contraction_config(nc, args.precision, with_depth=True)
     avg_ms = gemm_ms / launches
     flops = 2.0 * n3 * n3 * nc
     executed = flops * (3 if args.precision == "bf16x3" else 1)
     achieved = executed / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     log(f"contraction: {avg_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s of {peak} peak "
-        f"(tile {tile_rows}x128, split-K {splits}, autotuned {tuned})")
-    tk = TRAFFIC_KIB.get((w["name"], parity, args.precision, tile_rows, splits))
+        f"(tile {tile_rows}x128, k-stage {k_stage}, split-K {splits}, autotuned {tuned})")
+    tk = TRAFFIC_KIB.get((w["name"], parity, args.precision, tile_rows, splits, k_stage))
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": (tk[0] + tk[1]) * 1024.0 if tk else None,
                 "kernel": f"gemm_{args.precision}", "avg_launch_ms": round(avg_ms, 4),
-                "tile": f"{tile_rows}x128", "split_k": splits, "autotuned": tuned,
+                "tile": f"{tile_rows}x128", "k_stage": k_stage, "split_k": splits, "autotuned": tuned,
                 "flops_per_launch": executed,
                 "flops_per_cell_update": 2.0 * n3 * n3,
                 "fsm_fft_flops_per_cell_update": None}
+    # ---------------------------------------------------------- transport sweep (HBM-bound step)
+    hh = torch.zeros_like(h)
+    mom_s = torch.empty((nc, geom.mom_stride * plan.n_species), dtype=torch.float64, device="cuda")
+    sis.transport_sweep(plan, geom, rhs, hh, mom_s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(args.steps, 5)
+    e0.record()
+    for _ in range(reps):
+        sis.transport_sweep(plan, geom, rhs, hh, mom_s)
+    e1.record()
+    torch.cuda.synchronize()
+    sweep_ms = e0.elapsed_time(e1) / reps
+    sweep_bytes = 16.0 * nc * n3          # rhs read + h written per (cell, unknown)
+    sweep = {"kernel": "sweep_tube" if tube else ("sweep1d" if planar else "sweep2d"),
+             "avg_ms_with_moments": round(sweep_ms, 4), "algorithmic_bytes": sweep_bytes,
+             "achieved": round(sweep_bytes / (sweep_ms * 1e-3) / 1e9, 1), "peak": HBM_GBS, "unit": "GB/s",
+             "frac": round(sweep_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_GBS, 4)}
+    log(f"transport sweep + moments: {sweep_ms:.3f} ms, {sweep['achieved']} GB/s of {HBM_GBS} (algorithmic 16 B "
+        f"per (cell, unknown))")
+    del hh, mom_s
     D = info["n_dir"]
     Np3 = info["n_pad"] ** 3
     if not mix:
@@ -297,7 +318,7 @@ def main():
                       "unknowns_per_cell": n3, "species": plan.n_species,
                       "parity": {0: "full grid", 1: "odd in v3 (v3 > 0 stored)",
                                  2: "odd in v3, even in v2 (v2, v3 > 0 stored)"}[parity]},
-           "roofline": roofline,
+           "roofline": roofline, "sweep": sweep,
            "plan_seconds": round(t_plan, 3), "geometry_seconds": round(t_geom, 3),
            "time_to_residual_1e-8": ttr}
     if diff_info:

@@ -408,11 +408,20 @@ sis_status sis_state_destroy(sis_state_t state);
 /* Contraction configuration used for n_cells cells in `precision`: the
  * autotuner (run on the first eager sis_collide of a shape and at
  * sis_state_create, outside stream capture) times every (tile, split-K)
- * candidate on the device and keeps the fastest; tile_rows is the cell-tile
- * height (128, 64 or 32; the operator tile is 128), tuned = 0 if the default
- * heuristic is in use.                                                      */
+ * candidate on the device and keeps, among those within 3% of the fastest,
+ * the fewest split-K partials, then the taller tile; tile_rows is the
+ * cell-tile height (128, 64 or 32; the operator tile is 128), k_stage the
+ * k-depth of its LDS stages (16, or 32 for the FP64 single-buffered
+ * variants; nullable), tuned = 0 if the default heuristic is in use.        */
 sis_status sis_plan_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t precision,
-                                       int32_t* tile_rows, int32_t* splits, int32_t* tuned);
+                                       int32_t* tile_rows, int32_t* splits, int32_t* tuned,
+                                       int32_t* k_stage);
+/* Fix the configuration for n_cells cells in `precision` instead of tuning it
+ * (reproducible runs, tests): tile_rows 128, 64 or 32 with k_stage 16, or
+ * (FP64 only) 128 or 64 with k_stage 32; splits in 1..8.  Invalid
+ * combinations return SIS_E_INVALID.                                        */
+sis_status sis_plan_set_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t precision,
+                                           int32_t tile_rows, int32_t k_stage, int32_t splits);
 
 /* Kernel timing of the collision contraction: while enabled, every eager
  * (non-graph) contraction launch on a plan is bracketed by HIP events on its

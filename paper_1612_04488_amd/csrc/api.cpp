@@ -105,7 +105,7 @@ struct sis_plan {
   std::vector<double> h_v1d, h_feq, h_nu;
   // scratch of eager compute calls (a solver state owns its own, fixed at creation,
   // so that the buffers its captured graphs use are never reallocated)
-  Scratch ws_acc, ws_part, ws_x;  // split-K partials, sweep partials, low-precision cell operand
+  Scratch ws_acc, ws_x;  // split-K partials, low-precision cell operand
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   // tuned contraction configuration per (cells, precision): tile id, split-K
@@ -328,10 +328,11 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const int tiles[3] = {0, 2, 1};
+  const int tiles[5] = {0, 2, 1, 3, 4};
+  const int n_tiles = precision == SIS_PREC_FP64 ? 5 : 3;
   const int splits[6] = {1, 2, 3, 4, 6, 8};
   hipError_t err = hipSuccess;
-  for (int ti = 0; ti < 3 && err == hipSuccess; ++ti)
+  for (int ti = 0; ti < n_tiles && err == hipSuccess; ++ti)
     for (int si = 0; si < 6 && err == hipSuccess; ++si) {
       const int sp = splits[si];
       if (sp > 1 && sis::gemm_k_per_split(p->ndof, sp) < 256) continue;
@@ -358,13 +359,17 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   if (!timed.empty()) {
     float fastest = timed[0].first;
     for (const auto& c : timed) fastest = std::min(fastest, c.first);
+    // within 3% of the fastest: fewest split-K partials, then the larger tile, then the faster
     int best_rows = -1, best_splits = 1 << 30;
+    float best_ms = 0.f;
     for (const auto& c : timed) {
       if (c.first > 1.03f * fastest) continue;
       const int rows = sis::gemm_tile_rows(c.second.first), sp = c.second.second;
-      if (sp < best_splits || (sp == best_splits && rows > best_rows)) {
+      if (sp < best_splits || (sp == best_splits && rows > best_rows) ||
+          (sp == best_splits && rows == best_rows && c.first < best_ms)) {
         best_splits = sp;
         best_rows = rows;
+        best_ms = c.first;
         best = c.second;
       }
     }
@@ -465,9 +470,7 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
 }
 
 sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, double* mom,
-                     const int32_t* case_active, hipStream_t s, const int32_t* cell_active = nullptr,
-                     Scratch* ws_part = nullptr) {
-  if (!ws_part) ws_part = &p->ws_part;
+                     const int32_t* case_active, hipStream_t s, const int32_t* cell_active = nullptr) {
   if (g->tube) {
     sis::TubeSweepArgs a{};
     a.n_vr = p->n_vr;
@@ -520,18 +523,12 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
                                     mom, s));
     return SIS_OK;
   }
-  const int W = (p->nv / 2 + 63) / 64;
-  HIP_TRY(ws_part->ensure(static_cast<size_t>(g->n_cells) * p->nsp * 8 * W * sizeof(double)));
   sis::SweepArgs a{};
   a.n = p->n;
   a.n3 = p->nv;
   a.d2 = p->d2;
   a.d3 = p->d3;
-  a.v2d = p->v1d + (p->n - p->d2);
-  a.v3d = p->v1d + (p->n - p->d3);
   a.nsp = p->nsp;
-  a.mass_ratio[0] = p->mass_ratio[0];
-  a.mass_ratio[1] = p->mass_ratio[1];
   a.n_cases = g->n_cases;
   a.node_off = g->off;
   a.coef = g->coef;
@@ -540,13 +537,11 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
   a.nu = p->nu;
   a.rhs = rhs;
   a.h = h;
-  a.part = static_cast<double*>(ws_part->p);
-  a.W = W;
   a.case_active = case_active;
-  a.w = p->wr;
-  a.max_nodes = g->max_nodes;
   HIP_TRY(sis::launch_sweep1d(a, s));
-  if (mom) HIP_TRY(sis::launch_reduce_partials(a.part, W, g->n_cells * p->nsp, mom, s));
+  if (mom)
+    HIP_TRY(sis::launch_moments(p->n, p->d2, p->d3, p->nsp, p->mass_ratio, g->n_cells * p->nsp, p->v1d,
+                                p->v1d + (p->n - p->d2), p->v1d + (p->n - p->d3), h, p->wr, mom, s));
   return SIS_OK;
 }
 
@@ -2002,7 +1997,7 @@ struct sis_state {
          *q = nullptr, *state = nullptr;
   int32_t *iters = nullptr, *cact = nullptr, *lact = nullptr;
   double *xref = nullptr, *accref = nullptr;   // FP64 anchor of the defect correction
-  Scratch ws_acc, ws_part, ws_x;               // sized at creation, used by the captured graphs
+  Scratch ws_acc, ws_x;                        // sized at creation, used by the captured graphs
   int precision = 0, refresh = 1;
   hipStream_t cap = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};    // [0] refresh / plain, [1] incremental
@@ -2039,7 +2034,7 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
                                   g->flow_cell, b->o.project, b->rhs, nullptr, b->amom, b->lact, s,
                                   prec, mode, b->xref, b->accref, &b->ws_acc, &b->ws_x))
     return st;
-  if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s, b->lact, &b->ws_part)) return st;
+  if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s, b->lact)) return st;
   if (g->tube) {
     sis::TubeDiffArgs a = tube_diff_args(p, g, b->mom, b->amom, b->Npen);
     a.sis = sis ? 1 : 0;
@@ -2179,8 +2174,6 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
                           p->gemm_choice[std::make_pair(nc, p->precision)].second);
     if (splits > 1) ST_TRY(b->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
     if (p->precision != SIS_PREC_FP64) ST_TRY(b->ws_x.ensure(static_cast<size_t>(nc) * n3 * 4));
-    const int W = (p->nv / 2 + 63) / 64;
-    if (!g->two_d) ST_TRY(b->ws_part.ensure(static_cast<size_t>(nc) * nsp * 8 * W * 8));
   }
   hipStream_t s = stream;
   if (o->use_graph) {
@@ -2302,8 +2295,21 @@ sis_status sis_solve(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o, sis_so
   return st;
 }
 
+sis_status sis_plan_set_contraction_config(sis_plan_t p, int64_t n_cells, int32_t precision, int32_t tile_rows,
+                                           int32_t k_stage, int32_t splits) {
+  if (sis_status st = check_plan(p)) return st;
+  if (precision < SIS_PREC_FP64 || precision > SIS_PREC_BF16X3) return fail(SIS_E_INVALID, "unknown precision");
+  if (splits < 1 || splits > 8) return fail(SIS_E_INVALID, "splits must be in [1, 8]");
+  int tile = -1;
+  if (k_stage == 16) tile = tile_rows == 128 ? 0 : tile_rows == 64 ? 2 : tile_rows == 32 ? 1 : -1;
+  else if (k_stage == 32 && precision == SIS_PREC_FP64) tile = tile_rows == 128 ? 3 : tile_rows == 64 ? 4 : -1;
+  if (tile < 0) return fail(SIS_E_INVALID, "no contraction tile %d x 128 with k-stage %d for this precision", tile_rows, k_stage);
+  p->gemm_choice[std::make_pair(n_cells, static_cast<int>(precision))] = std::make_pair(tile, static_cast<int>(splits));
+  return SIS_OK;
+}
+
 sis_status sis_plan_contraction_config(sis_plan_t p, int64_t n_cells, int32_t precision, int32_t* tile_rows,
-                                       int32_t* splits, int32_t* tuned) {
+                                       int32_t* splits, int32_t* tuned, int32_t* k_stage) {
   if (sis_status st = check_plan(p)) return st;
   if (!tile_rows || !splits || !tuned) return fail(SIS_E_INVALID, "null output");
   int t, s;
@@ -2318,6 +2324,7 @@ sis_status sis_plan_contraction_config(sis_plan_t p, int64_t n_cells, int32_t pr
   }
   *tile_rows = sis::gemm_tile_rows(t);
   *splits = s;
+  if (k_stage) *k_stage = sis::gemm_tile_depth(t);
   return SIS_OK;
 }
 

@@ -42,9 +42,12 @@ struct GemmArgs {
   int64_t M;
   int N, K;
   int splits;        // split-K factor (grid.z)
-  int tile;          // tile configuration id: 0 (128 x 128), 2 (64 x 128), 1 (32 x 128)
+  int tile;          // tile configuration id: 0 (128 x 128), 2 (64 x 128), 1 (32 x 128) with 16-deep
+                     // double-buffered stages; FP64 only: 3 (128 x 128), 4 (64 x 128) with 32-deep
+                     // single-buffered stages
 };
 int gemm_tile_rows(int tile);
+int gemm_tile_depth(int tile);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 // x = X - Xref (Xref may be null) -> bf16 hi + lo, or -> FP32; count = M * K
 hipError_t launch_split_x(const double* X, const double* Xref, int64_t count, uint16_t* hi, uint16_t* lo,
@@ -97,28 +100,18 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 struct SweepArgs {
   int n, n3;
   int d2, d3;                // stored v2, v3 nodes per row (see FinishArgs)
-  const double* v2d;
-  const double* v3d;
   int nsp;                   // species per cell; grid.z runs over species
-  double mass_ratio[2];      // m_s / m_A: weights of q3 and P13
   int n_cases;
   const int64_t* node_off;   // [n_cases+1]
   const double* coef;        // [cells][6]: backward a,b,c ; forward a,b,c
   const double* delta_case;  // [n_cases]
   const double* v1d;         // [n]
   const double* nu;          // [nsp][n3]
-  const double* rhs;         // [cells][nsp][n3]
+  const double* rhs;         // [cells][nsp][n3], not aliasing h
   double* h;                 // [cells][nsp][n3]
-  double* part;              // [cells][nsp][2][4][W] wave partials of {U3, q3, G1, P13}
-  int W;                     // waves per case = n3 / 128
   const int32_t* case_active;// [n_cases] or null
-  double w;
-  int max_nodes;
 };
 hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s);
-// mom[cell][4] = sum over the wave partials (fixed order)
-hipError_t launch_reduce_partials(const double* part, int W, int64_t n_cells, double* mom,
-                                  hipStream_t s);
 // mom[row][4] = {U3, q3, G1, P13} of h[row][n x d2 x d3] directly (rows = cells * nsp;
 // q3 and P13 weighted with the mass ratio of the row's species)
 hipError_t launch_moments(int n, int d2, int d3, int nsp, const double* mass_ratio, int64_t n_rows,

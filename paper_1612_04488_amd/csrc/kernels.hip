@@ -168,19 +168,23 @@ __global__ void split_bf16_kernel(const double* __restrict__ in, uint16_t* __res
 constexpr int kBK = 16;
 constexpr int kPad = 4;
 
-template <int BM, int BN, int WM, int WN>
+// BK: k-depth of a stage; NBUF = 2: double-buffered LDS (one barrier per stage), NBUF = 1:
+// one buffer (two barriers per stage, half the LDS, so deeper stages fit twice per CU);
+// PAD: row padding of the k-major LDS tiles (PAD = 1 with BK = 32 spreads the 64-lane
+// stores of 16 k-rows x 4 rows over the banks).
+template <int BM, int BN, int WM, int WN, int BK = kBK, int NBUF = 2, int PAD = kPad>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict__ X,
                                                        const double* __restrict__ Op,
                                                        double* __restrict__ C, int64_t M, int N,
                                                        int K, int kps) {
   constexpr int WAVES_N = BN / WN;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int A_LD = BM * kBK / 2 / 256;
-  constexpr int B_LD = BN * kBK / 2 / 256;
+  constexpr int A_LD = BM * BK / 2 / 256;
+  constexpr int B_LD = BN * BK / 2 / 256;
   static_assert((BM / WM) * (BN / WN) == 4, "4 waves per workgroup");
   static_assert(A_LD >= 1 && B_LD >= 1, "tile too small");
-  __shared__ double As[2][kBK][BM + kPad];
-  __shared__ double Bs[2][kBK][BN + kPad];
+  __shared__ double As[NBUF][BK][BM + PAD];
+  __shared__ double Bs[NBUF][BK][BN + PAD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
@@ -195,7 +199,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (kBK / 2), kc = (q % (kBK / 2)) * 2;
+      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
       const int64_t gm = m0 + r;
       const int gk = k0 + kc;
       ra[i] = (gm < M && gk < kend) ? *reinterpret_cast<const double2*>(X + gm * K + gk)
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (kBK / 2), kc = (q % (kBK / 2)) * 2;
+      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
       const int gn = n0 + r;
       const int gk = k0 + kc;
       rb[i] = (gn < N && gk < kend)
@@ -216,14 +220,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (kBK / 2), kc = (q % (kBK / 2)) * 2;
+      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
       As[buf][kc][r] = ra[i].x;
       As[buf][kc + 1][r] = ra[i].y;
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
       const int q = tid + 256 * i;
-      const int r = q / (kBK / 2), kc = (q % (kBK / 2)) * 2;
+      const int r = q / (BK / 2), kc = (q % (BK / 2)) * 2;
       Bs[buf][kc][r] = rb[i].x;
       Bs[buf][kc + 1][r] = rb[i].y;
     }
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  const int nk = kend > kbeg ? (kend - kbeg + kBK - 1) / kBK : 0;
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
     gload(kbeg);
     sstore(0);
@@ -243,10 +247,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
   __syncthreads();
   const int kr = lane >> 4, cc = lane & 15;
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload(kbeg + (kt + 1) * kBK);
+    const int cur = NBUF == 2 ? (kt & 1) : 0;
+    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
 #pragma unroll
-    for (int kk = 0; kk < kBK / 4; ++kk) {
+    for (int kk = 0; kk < BK / 4; ++kk) {
       double a[TM], b[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) a[i] = As[cur][kk * 4 + kr][wm + i * 16 + cc];
@@ -258,8 +262,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
-    __syncthreads();
+    if (NBUF == 2) {
+      if (kt + 1 < nk) sstore(cur ^ 1);
+      __syncthreads();
+    } else {
+      __syncthreads();           // every wave is done with the buffer
+      if (kt + 1 < nk) sstore(0);
+      __syncthreads();
+    }
   }
   // D layout of the 16x16x4 FP64 MFMA: lane l, element r -> row (l/16) + 4 r,
   // column l%16 (rows interleaved, unlike the FP32 forms)
@@ -655,91 +665,115 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
 
 // ------------------------------------------------------------------ sweep
 // One thread per velocity pair (v1 > 0 index jp, mirror jm) of one case.
+// One thread per (case, species, |v1| > 0 velocity pair): the two marches of a velocity are
+// serial in x1, so the right sides and stencil coefficients of the next kSweepChunk nodes are
+// loaded while the current ones are processed (the dependency chain then holds arithmetic
+// only).  Moments are taken afterwards by moments_kernel.
+constexpr int kSweepChunk = 8;
+
 __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
   const int cs = blockIdx.y, sp = blockIdx.z, nsp = a.nsp;
   if (a.case_active && !a.case_active[cs]) return;
-  const int n = a.n, nn = n * n, half = a.n3 / 2, n3 = a.n3;
+  const int half = a.n3 / 2, n3 = a.n3;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = t < half;
-  const int tt = valid ? t : 0;
-  const int wave = t >> 6;
-  const bool writer = (threadIdx.x & 63) == 0;
+  if (t >= half) return;
   const int64_t c0 = a.node_off[cs];
   const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
   const int d23 = a.d2 * a.d3;
-  const int j1h = tt / d23, r = tt % d23;
-  const int jp = n / 2 + j1h, jm = n / 2 - 1 - j1h;
+  const int j1h = t / d23, r = t % d23;
+  const int jp = a.n / 2 + j1h, jm = a.n / 2 - 1 - j1h;
   const int vp = jp * d23 + r, vm = jm * d23 + r;
   const double v1 = a.v1d[jp];
-  const double v2 = a.v2d[r / a.d3], v3 = a.v3d[r % a.d3];
-  const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
   const double del = a.delta_case[cs];
   const double* nu = a.nu + static_cast<int64_t>(sp) * n3;
   const double dnp = del * nu[vp], dnm = del * nu[vm];
-  const double ms = a.mass_ratio[sp];
-  const double z = valid ? 1.0 : 0.0;
-  const double wU = z * a.w * v3, wq = z * a.w * (ms * vsq - 2.5) * v3;
-  const double wG = z * a.w * v3 * (2.0 * v1 * v1 - 1.0), wP = z * 2.0 * ms * a.w * v1 * v3;
-  const int W = a.W;
+  const double* __restrict__ rhs = a.rhs;
+  double* __restrict__ h = a.h;
+  const double* __restrict__ coef = a.coef;
   // row of (cell, species) in the [cell][species][n3] arrays
   auto row = [&](int64_t cell) { return (cell * nsp + sp) * static_cast<int64_t>(n3); };
-  auto put = [&](int64_t cell, int pass, double h) {
-    const double s0 = wave_sum(wU * h), s1 = wave_sum(wq * h), s2 = wave_sum(wG * h);
-    const double s3 = wave_sum((pass == 0 ? wP : -wP) * h);
-    // waves past the last velocity pair (when n3/2 is not a multiple of the block size)
-    // hold only padding lanes and own no partial slot
-    if (writer && wave < W) {
-      double* p = a.part + (((cell * nsp + sp) * 2 + pass) * 4) * W + wave;
-      p[0] = s0;
-      p[W] = s1;
-      p[2 * W] = s2;
-      p[3 * W] = s3;
-    }
-  };
-  // v1 > 0: wall value 0, march towards the symmetry plane
+  double rc[kSweepChunk], ac[kSweepChunk], bc[kSweepChunk], cc[kSweepChunk];
+  double rn[kSweepChunk], an[kSweepChunk], bn[kSweepChunk], cn[kSweepChunk];
+  // v1 > 0: wall value 0, march towards the symmetry plane (nodes 1 .. nodes-1)
+  h[row(c0) + vp] = 0.0;
   double h1 = 0.0, h2 = 0.0;
-  if (valid) a.h[row(c0) + vp] = 0.0;
-  put(c0, 0, 0.0);
-  for (int i = 1; i < nodes; ++i) {
-    const int64_t cell = c0 + i;
-    const double ca = a.coef[cell * 6 + 0], cb = a.coef[cell * 6 + 1], cc = a.coef[cell * 6 + 2];
-    const double rhs = valid ? a.rhs[row(cell) + vp] : 0.0;
-    const double val = (rhs - v1 * (cb * h1 + cc * h2)) / (dnp + v1 * ca);
-    if (valid) a.h[row(cell) + vp] = val;
-    h2 = h1;
-    h1 = val;
-    put(cell, 0, val);
+#pragma unroll
+  for (int u = 0; u < kSweepChunk; ++u) {
+    const int i = 1 + u;
+    const int64_t cell = c0 + (i < nodes ? i : 0);
+    rc[u] = rhs[row(cell) + vp];
+    ac[u] = coef[cell * 6 + 0];
+    bc[u] = coef[cell * 6 + 1];
+    cc[u] = coef[cell * 6 + 2];
   }
-  // v1 < 0: specular reflection at the last node, march to the wall
+  for (int base = 1; base < nodes; base += kSweepChunk) {
+#pragma unroll
+    for (int u = 0; u < kSweepChunk; ++u) {
+      const int i = base + kSweepChunk + u;
+      const int64_t cell = c0 + (i < nodes ? i : 0);
+      rn[u] = rhs[row(cell) + vp];
+      an[u] = coef[cell * 6 + 0];
+      bn[u] = coef[cell * 6 + 1];
+      cn[u] = coef[cell * 6 + 2];
+    }
+#pragma unroll
+    for (int u = 0; u < kSweepChunk; ++u) {
+      const int i = base + u;
+      if (i < nodes) {
+        const double val = (rc[u] - v1 * (bc[u] * h1 + cc[u] * h2)) / (dnp + v1 * ac[u]);
+        h[row(c0 + i) + vp] = val;
+        h2 = h1;
+        h1 = val;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSweepChunk; ++u) {
+      rc[u] = rn[u];
+      ac[u] = an[u];
+      bc[u] = bn[u];
+      cc[u] = cn[u];
+    }
+  }
+  // v1 < 0: specular reflection at the last node, march to the wall (nodes nodes-2 .. 0)
   const int64_t last = c0 + nodes - 1;
   double g1 = h1, g2 = 0.0;
-  if (valid) a.h[row(last) + vm] = g1;
-  put(last, 1, g1);
-  for (int i = nodes - 2; i >= 0; --i) {
-    const int64_t cell = c0 + i;
-    const double ca = a.coef[cell * 6 + 3], cb = a.coef[cell * 6 + 4], cc = a.coef[cell * 6 + 5];
-    const double rhs = valid ? a.rhs[row(cell) + vm] : 0.0;
-    const double val = (rhs - v1 * (cb * g1 + cc * g2)) / (dnm + v1 * ca);
-    if (valid) a.h[row(cell) + vm] = val;
-    g2 = g1;
-    g1 = val;
-    put(cell, 1, val);
+  h[row(last) + vm] = g1;
+#pragma unroll
+  for (int u = 0; u < kSweepChunk; ++u) {
+    const int i = nodes - 2 - u;
+    const int64_t cell = c0 + (i >= 0 ? i : 0);
+    rc[u] = rhs[row(cell) + vm];
+    ac[u] = coef[cell * 6 + 3];
+    bc[u] = coef[cell * 6 + 4];
+    cc[u] = coef[cell * 6 + 5];
   }
-}
-
-__global__ __launch_bounds__(64) void reduce_partials_kernel(const double* __restrict__ part, int W,
-                                                             double* __restrict__ mom) {
-  // one wave per cell: lanes stride over the 2 * W partials of each moment
-  const int64_t c = blockIdx.x;
-  const int lane = threadIdx.x;
-  for (int q = 0; q < 4; ++q) {
-    double s = 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
-      const double* p = part + ((c * 2 + pass) * 4 + q) * W;
-      for (int w = lane; w < W; w += 64) s += p[w];
+  for (int base = nodes - 2; base >= 0; base -= kSweepChunk) {
+#pragma unroll
+    for (int u = 0; u < kSweepChunk; ++u) {
+      const int i = base - kSweepChunk - u;
+      const int64_t cell = c0 + (i >= 0 ? i : 0);
+      rn[u] = rhs[row(cell) + vm];
+      an[u] = coef[cell * 6 + 3];
+      bn[u] = coef[cell * 6 + 4];
+      cn[u] = coef[cell * 6 + 5];
     }
-    s = wave_sum(s);
-    if (lane == 0) mom[c * 4 + q] = s;
+#pragma unroll
+    for (int u = 0; u < kSweepChunk; ++u) {
+      const int i = base - u;
+      if (i >= 0) {
+        const double val = (rc[u] - v1 * (bc[u] * g1 + cc[u] * g2)) / (dnm + v1 * ac[u]);
+        h[row(c0 + i) + vm] = val;
+        g2 = g1;
+        g1 = val;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSweepChunk; ++u) {
+      rc[u] = rn[u];
+      ac[u] = an[u];
+      bc[u] = bn[u];
+      cc[u] = cn[u];
+    }
   }
 }
 
@@ -1708,18 +1742,25 @@ int gemm_k_per_split(int K, int splits) {
   return kps;
 }
 
-int gemm_tile_rows(int tile) { return tile == 0 ? 128 : tile == 2 ? 64 : 32; }
+int gemm_tile_rows(int tile) { return (tile == 0 || tile == 3) ? 128 : (tile == 2 || tile == 4) ? 64 : 32; }
+
+int gemm_tile_depth(int tile) { return tile >= 3 ? 32 : 16; }
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   const int kps = gemm_k_per_split(g.K, g.splits);
   const int BN = 128;
   const int BM = gemm_tile_rows(g.tile);
   dim3 grid((g.N + BN - 1) / BN, static_cast<unsigned>((g.M + BM - 1) / BM), g.splits);
+  if (g.tile >= 3 && g.precision != 0) return hipErrorInvalidValue;
   if (g.precision == 0) {
     if (g.tile == 0)
       hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
     else if (g.tile == 2)
       hipLaunchKernelGGL((gemm_f64_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
+    else if (g.tile == 3)
+      hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 64, 64, 32, 1, 1>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
+    else if (g.tile == 4)
+      hipLaunchKernelGGL((gemm_f64_kernel<64, 128, 32, 64, 32, 1, 1>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
     else
       hipLaunchKernelGGL((gemm_f64_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
   } else if (g.precision == 1) {
@@ -1751,11 +1792,6 @@ hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s) {
   const int half = a.n3 / 2;
   dim3 grid((half + 255) / 256, a.n_cases, a.nsp);
   hipLaunchKernelGGL(sweep1d_kernel, grid, dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_partials(const double* part, int W, int64_t n_cells, double* mom, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(static_cast<unsigned>(n_cells)), dim3(64), 0, s, part, W, mom);
   return hipGetLastError();
 }
 

@@ -118,7 +118,10 @@ _SIGS = {
     "sis_state_poll": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32), _P]),
     "sis_state_results": (ctypes.c_int32, [_P, ctypes.POINTER(SolveResult), _P]),
     "sis_state_destroy": (ctypes.c_int32, [_P]),
+    "sis_plan_set_contraction_config": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                         ctypes.c_int32, ctypes.c_int32]),
     "sis_plan_contraction_config": (ctypes.c_int32, [_P, ctypes.c_int64, ctypes.c_int32,
+                                                     ctypes.POINTER(ctypes.c_int32),
                                                      ctypes.POINTER(ctypes.c_int32),
                                                      ctypes.POINTER(ctypes.c_int32),
                                                      ctypes.POINTER(ctypes.c_int32)]),
@@ -282,11 +285,18 @@ class Plan:
                                 1 if project else 0, _ptr(rhs_out), _ptr(lh_out), _ptr(amom_out),
                                 _stream(stream)))
 
-    def contraction_config(self, n_cells, precision="fp64"):
-        """(tile rows, split-K, tuned) of the contraction for n_cells cells."""
-        t, s, u = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    def set_contraction_config(self, n_cells, tile_rows, k_stage, splits, precision="fp64"):
+        """Fix the contraction configuration for n_cells cells instead of tuning it."""
+        check(lib().sis_plan_set_contraction_config(self.handle, int(n_cells), PRECISIONS.get(precision, precision),
+                                                    int(tile_rows), int(k_stage), int(splits)))
+
+    def contraction_config(self, n_cells, precision="fp64", with_depth=False):
+        """(tile rows, split-K, tuned[, k-stage depth]) of the contraction for n_cells cells."""
+        t, s, u, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         check(lib().sis_plan_contraction_config(self.handle, int(n_cells), PRECISIONS.get(precision, precision),
-                                                ctypes.byref(t), ctypes.byref(s), ctypes.byref(u)))
+                                                ctypes.byref(t), ctypes.byref(s), ctypes.byref(u), ctypes.byref(k)))
+        if with_depth:
+            return t.value, s.value, bool(u.value), k.value
         return t.value, s.value, bool(u.value)
 
     def timing(self, enable):

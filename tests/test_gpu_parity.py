@@ -270,3 +270,31 @@ def test_mixed_solve_with_fp64_refresh_matches_fp64(precision):
     r1 = sis.solve(p, geom, scheme="SIS", eps=1e-10, max_it=300, refresh_every=1)
     assert np.array_equal(r1["iters"], refs[False]["iters"])
     assert np.all(np.abs(r1["M"] - refs[False]["M"]) < 1e-12 * np.abs(refs[False]["M"]))
+
+
+def test_every_contraction_configuration_gives_the_same_operator_action():
+    """Each (tile, k-stage, split-K) configuration of the FP64 contraction, fixed
+    through the ABI instead of tuned, reproduces the tuned result to rounding
+    (300 cells: a ragged last cell tile for every tile height); the 32-deep
+    stages are FP64-only."""
+    p = sis.Plan(12, 4.0, m_angle=4)
+    nc = 300
+    h = dev(inputs.rough_h(12, 4.0, nc).reshape(nc, -1))
+    delta = dev(np.full(nc, 2.0))
+    ref = torch.empty_like(h)
+    p.collide(h, delta, ref)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    configs = [(128, 16), (64, 16), (32, 16), (128, 32), (64, 32)]
+    for k, (rows, depth) in enumerate(configs):
+        for splits in (1, 3):
+            n = nc + 1 + 2 * k + (splits == 3)   # a fresh key per configuration
+            hh = torch.cat([h, h[: n - nc]])
+            p.set_contraction_config(n, rows, depth, splits)
+            out = torch.empty_like(hh)
+            p.collide(hh, torch.cat([delta, delta[: n - nc]]), out)
+            torch.cuda.synchronize()
+            assert p.contraction_config(n, with_depth=True) == (rows, splits, True, depth)
+            assert rel(out[:nc].cpu().numpy(), ref) < 1e-13, (rows, depth, splits)
+    with pytest.raises(sis.SisError):
+        p.set_contraction_config(nc, 128, 32, 1, precision="fp32")
