@@ -136,6 +136,7 @@ struct sis_geom {
   // 2-D tables (kinds DUCT_QUARTER, PERIODIC_2D)
   bool two_d = false;
   bool tube = false;             // SIS_GEOM_TUBE: radial nodes, polar velocity grid
+  int max_diag = 0;              // 2-D: largest min(n1, n2) over the cases
   double *d_r = nullptr, *d_cin = nullptr, *d_cout = nullptr, *d_tw = nullptr;
   sis::Tables2D t2;
   int32_t *d_n1 = nullptr, *d_n2 = nullptr, *d_gcell = nullptr, *d_sref = nullptr, *d_nb = nullptr;
@@ -517,6 +518,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.rhs = rhs;
     a.h = h;
     a.case_active = case_active;
+    a.max_diag = g->max_diag;
     HIP_TRY(sis::launch_sweep2d(a, s));
     if (mom)
       HIP_TRY(sis::launch_moments2d(p->n, p->d3, p->nsp, p->mass_ratio, g->n_cells, p->v1d, p->v1d + (p->n - p->d3), h, p->wr, cell_active,
@@ -1013,10 +1015,12 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
     return fail(SIS_E_INVALID, "null 2-D geometry array");
   std::vector<sis::Case2D> cases(d->n_cases);
   int64_t f1o = 0, f2o = 0, so = 0;
+  int max_diag = 0;
   for (int c = 0; c < d->n_cases; ++c) {
     sis::Case2D& k = cases[c];
     k.n1 = d->n1[c];
     k.n2 = d->n2[c];
+    max_diag = std::max(max_diag, std::min(k.n1, k.n2));
     if (k.n1 < 2 || k.n2 < 2 || k.n1 > 4096 || k.n2 > 4096)
       return fail(SIS_E_SHAPE, "case %d: n1, n2 must be in [2, 4096]", c);
     k.f1.assign(d->face1 + f1o, d->face1 + f1o + k.n1 + 1);
@@ -1040,6 +1044,7 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
   g->kind = d->kind;
   g->n_cases = d->n_cases;
   g->two_d = true;
+  g->max_diag = max_diag;
   std::string err;
   if (!sis::build_tables_2d(cases, g->t2, err)) { delete g; return fail(SIS_E_INVALID, "%s", err.c_str()); }
   const sis::Tables2D& t = g->t2;

@@ -166,6 +166,7 @@ struct Sweep2DArgs {
   const double* rhs;
   double* h;                 // in: previous iterate (lagged periodic values), out: new
   const int32_t* case_active;
+  int max_diag;              // largest min(n1, n2) over the cases (cells on an anti-diagonal)
 };
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s);
 // mom[cell][species][8] = {U3, q3, G1, G12, G2, P13, P23, 0}; rows of n x n x d3 velocities;

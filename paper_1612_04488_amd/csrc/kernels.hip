@@ -1013,6 +1013,112 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
   }
 }
 
+// Pipelined form of the same sweep for cross sections whose anti-diagonals hold at most
+// kSweepP * 64 cells (min(n1, n2) <= 128): each slot owns up to kSweepP cells of a diagonal,
+// and the read-only data of its cells on the next diagonal (cell index, stencil
+// coefficients, upwind references, right side) are loaded while the current diagonal is
+// computed, so that after each barrier only the upwind values of h are waited for.  The
+// values and the order of the updates are those of sweep2d_kernel.
+constexpr int kSweepP = 2;
+
+struct Sweep2DPoint {
+  int64_t row;          // (cell * nsp + species), -1: no fluid cell
+  double rhs, c1[3], c2[3];
+  int32_t r1[2], r2[2];
+  int8_t k1[2], k2[2];
+};
+
+__global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2DArgs a) {
+  const int cs = blockIdx.y;
+  if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
+  const int n = a.n, hn = n / 2, n3 = a.n3, d3 = a.d3;
+  const int nsp = a.nsp, sp = blockIdx.z;
+  const double* __restrict__ nu = a.nu + static_cast<int64_t>(sp) * n3;
+  const int quads = hn * hn * d3;
+  const int tq = blockIdx.x * kSweepV + threadIdx.x % kSweepV;
+  const bool vvalid = tq < quads;
+  const int t = vvalid ? tq : 0;
+  const int jq1 = t / (hn * d3), jq2 = (t / d3) % hn, j3 = t % d3;
+  const int slot = threadIdx.x / kSweepV, slots = kSweepThreads / kSweepV;
+  const int n1 = a.n1[cs], n2 = a.n2[cs];
+  const int64_t g0 = a.grid_off[cs];
+  const double del = a.delta_case[cs];
+  for (int q = 0; q < 4; ++q) {
+    const int s1 = (q & 1) ? -1 : 1, s2 = (q & 2) ? -1 : 1;
+    const int j1 = s1 > 0 ? hn + jq1 : hn - 1 - jq1;
+    const int j2 = s2 > 0 ? hn + jq2 : hn - 1 - jq2;
+    const int v = (j1 * n + j2) * d3 + j3;
+    const int vm1 = ((n - 1 - j1) * n + j2) * d3 + j3;
+    const int vm2 = (j1 * n + (n - 1 - j2)) * d3 + j3;
+    const double av1 = fabs(a.v1d[j1]), av2 = fabs(a.v1d[j2]);
+    const double dnu = del * nu[v];
+    const int sg1 = s1 > 0 ? 0 : 1, sg2 = s2 > 0 ? 0 : 1;
+    auto load = [&](int d, int p, Sweep2DPoint& pt) {
+      pt.row = -1;
+      const int lo = max(0, d - (n2 - 1)), hi = min(d, n1 - 1);
+      const int ii = lo + slot + p * slots;
+      if (!vvalid || d > n1 + n2 - 2 || ii > hi) return;
+      const int jj = d - ii;
+      const int i = s1 > 0 ? ii : n1 - 1 - ii;
+      const int j = s2 > 0 ? jj : n2 - 1 - jj;
+      const int cell = a.gcell[g0 + static_cast<int64_t>(i) * n2 + j];
+      if (cell < 0) return;
+      const int64_t o1 = (static_cast<int64_t>(cell) * 2 + 0) * 2 + sg1;
+      const int64_t o2 = (static_cast<int64_t>(cell) * 2 + 1) * 2 + sg2;
+      pt.row = static_cast<int64_t>(cell) * nsp + sp;
+      pt.rhs = a.rhs[pt.row * n3 + v];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        pt.c1[k] = a.coef[o1 * 3 + k];
+        pt.c2[k] = a.coef[o2 * 3 + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        pt.k1[k] = a.kind[o1 * 2 + k];
+        pt.k2[k] = a.kind[o2 * 2 + k];
+        pt.r1[k] = a.ref[o1 * 2 + k];
+        pt.r2[k] = a.ref[o2 * 2 + k];
+      }
+    };
+    Sweep2DPoint cur[kSweepP], nxt[kSweepP];
+#pragma unroll
+    for (int p = 0; p < kSweepP; ++p) load(0, p, cur[p]);
+    for (int d = 0; d < n1 + n2 - 1; ++d) {
+      double up[kSweepP][4];
+#pragma unroll
+      for (int p = 0; p < kSweepP; ++p) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          up[p][k] = (cur[p].row >= 0 && cur[p].k1[k])
+                         ? a.h[(static_cast<int64_t>(cur[p].r1[k]) * nsp + sp) * n3 + (cur[p].k1[k] == 2 ? vm1 : v)]
+                         : 0.0;
+          up[p][2 + k] = (cur[p].row >= 0 && cur[p].k2[k])
+                             ? a.h[(static_cast<int64_t>(cur[p].r2[k]) * nsp + sp) * n3 + (cur[p].k2[k] == 2 ? vm2 : v)]
+                             : 0.0;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < kSweepP; ++p) load(d + 1, p, nxt[p]);
+#pragma unroll
+      for (int p = 0; p < kSweepP; ++p) {
+        const Sweep2DPoint& c = cur[p];
+        if (c.row >= 0) {
+          double acc = c.rhs;
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            if (c.k1[k]) acc -= av1 * c.c1[k + 1] * up[p][k];
+            if (c.k2[k]) acc -= av2 * c.c2[k + 1] * up[p][2 + k];
+          }
+          a.h[c.row * n3 + v] = acc / (dnu + av1 * c.c1[0] + av2 * c.c2[0]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < kSweepP; ++p) cur[p] = nxt[p];
+    }
+  }
+}
+
 // Per (cell, species) row: U3, q3 = int (a v^2 - 5/2) v3 h, G1, G12, G2, P13 = 2a int v1 v3 h,
 // P23 = 2a int v2 v3 h (a = m_s / m_A; 1 for one gas).
 __global__ __launch_bounds__(256) void moments2d_kernel(int n, int d3, int nsp, double ms0, double ms1,
@@ -1817,7 +1923,10 @@ hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   const int hn = a.n / 2;
   const int count = hn * hn * a.d3;
   dim3 grid((count + kSweepV - 1) / kSweepV, a.n_cases, a.nsp);
-  hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(kSweepThreads), 0, s, a);
+  if (a.max_diag <= kSweepP * (kSweepThreads / kSweepV))
+    hipLaunchKernelGGL(sweep2d_pipelined_kernel, grid, dim3(kSweepThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(kSweepThreads), 0, s, a);
   return hipGetLastError();
 }
 
