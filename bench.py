@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--no-ttr", action="store_true", help="skip time-to-residual runs")
+    ap.add_argument("--refresh-every", type=int, default=8,
+                    help="mixed runs: FP64 anchor of the defect correction every R-th iteration")
     ap.add_argument("--cpu-cells", type=int, default=12)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -287,7 +289,8 @@ def main():
         for prec, proj in runs:
             plan.set_precision(prec)
             r = sis.solve(plan, geom, scheme="SIS", N=Npen, eps=1e-8, max_it=400, project=proj,
-                          raise_not_converged=False)
+                          raise_not_converged=False,
+                          refresh_every=args.refresh_every if prec != "fp64" else 0)
             key = prec + ("+projection" if proj else "")
             e = {"seconds": round(r["seconds"], 4), "iters": r["iters"].tolist(),
                  "converged": bool(r["status"] == 0), "M": r["M"].tolist(), "Q": r["Q"].tolist()}
@@ -301,7 +304,7 @@ def main():
                 e["max_rel_dev_M_vs_fp64"] = float(np.max(np.abs(r["M"] - base["M"]) / np.abs(base["M"])))
                 e["max_rel_dev_Q_vs_fp64"] = float(np.max(np.abs(r["Q"] - base["Q"]) / np.abs(base["Q"])))
                 e["speedup_vs_fp64"] = float(base["seconds"] / r["seconds"])
-                e["refresh_every"] = 8
+                e["refresh_every"] = args.refresh_every
             ttr[key] = e
             log(f"time-to-residual {key}: {r['seconds']:.3f} s, iters {r['iters'].tolist()}")
         plan.set_precision(args.precision)

@@ -249,19 +249,39 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = NBUF == 2 ? (kt & 1) : 0;
     if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+    // operands of k-step kk + 1 are read from LDS into the other register set
+    // while the MFMAs of k-step kk run
+    double a[2][TM], b[2][TN];
+    auto lread = [&](int kk, double* ar, double* br) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i) ar[i] = As[cur][kk * 4 + kr][wm + i * 16 + cc];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) br[j] = Bs[cur][kk * 4 + kr][wn + j * 16 + cc];
+    };
+    lread(0, a[0], b[0]);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      double a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[cur][kk * 4 + kr][wm + i * 16 + cc];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[cur][kk * 4 + kr][wn + j * 16 + cc];
+      const int c = kk & 1;
+      if (kk + 1 < BK / 4) lread(kk + 1, a[c ^ 1], b[c ^ 1]);
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][i], b[c][j], acc[i][j], 0, 0, 0);
     }
+    // Schedule of the block above (a hint to the compiler's scheduler, which otherwise sinks
+    // the reads behind the MFMAs that use the other register set): the first step's reads,
+    // then per step one MFMA, the next step's LDS reads (ds_read2: two operands each), the
+    // step's other MFMAs.
+    constexpr int kReads = (TM + 1) / 2 + (TN + 1) / 2;
+    __builtin_amdgcn_sched_group_barrier(0x100, kReads, 0);
+#pragma unroll
+    for (int kk = 0; kk + 1 < BK / 4; ++kk) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, kReads, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, TM * TN - 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
     if (NBUF == 2) {
       if (kt + 1 < nk) sstore(cur ^ 1);
       __syncthreads();
@@ -453,7 +473,31 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
     return make_uint4(t[0] | (uint32_t(t[1]) << 16), t[2] | (uint32_t(t[3]) << 16), t[4] | (uint32_t(t[5]) << 16),
                       t[6] | (uint32_t(t[7]) << 16));
   };
+  // stages that lie inside the matrices (every stage but ragged edges) load without
+  // per-chunk bounds checks; the test is uniform over the workgroup
+  const bool inside_mn = m0 + BM <= M && n0 + BN <= N;
   auto gload = [&](int k0) {
+    if (inside_mn && k0 + BK <= kend) {
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) {
+        const int q = tid + 256 * i;
+        if (q < BM * CH) {
+          const int64_t off = (m0 + q / CH) * K + k0 + (q % CH) * 8;
+          ra[0][i] = *reinterpret_cast<const uint4*>(Xh + off);
+          ra[1][i] = *reinterpret_cast<const uint4*>(Xl + off);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < B_LD; ++i) {
+        const int q = tid + 256 * i;
+        if (q < BN * CH) {
+          const int64_t off = static_cast<int64_t>(n0 + q / CH) * K + k0 + (q % CH) * 8;
+          rb[0][i] = *reinterpret_cast<const uint4*>(Oh + off);
+          rb[1][i] = *reinterpret_cast<const uint4*>(Ol + off);
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
@@ -803,52 +847,82 @@ __global__ __launch_bounds__(256) void moments_kernel(int n, int d2, int d3, int
 }
 
 // ------------------------------------------------------------------ diffusion (1-D)
-__global__ __launch_bounds__(64) void diffusion1d_kernel(DiffusionArgs a) {
+// One workgroup per case.  The march from the wall is a serial recurrence, so one
+// lane carries it; the per-node inputs (moments, source, stencil) are staged into LDS
+// by the whole workgroup in coalesced chunks and the outputs written back the same
+// way, so the march itself waits on LDS only.
+constexpr int kDiffChunk = 256;
+
+__global__ __launch_bounds__(kDiffChunk) void diffusion1d_kernel(DiffusionArgs a) {
+  __shared__ double in[8][kDiffChunk];    // Uh, qh, G1, source, ca, cb, cc, x
+  __shared__ double out[4][kDiffChunk];   // U, dU, q, U of the new iterate
   const int cs = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  if (a.case_active && !a.case_active[cs]) return;
+  if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int64_t c0 = a.node_off[cs];
   const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
   const double del = a.delta_case[cs];
   const bool pois = a.flow_case[cs] == 1;
   double y1 = 0.0, y2 = 0.0;
   double Mr = 0.0, Qr = 0.0, Up = 0.0, qp = 0.0, xp = 0.0;
-  for (int i = 0; i < nodes; ++i) {
-    const int64_t cell = c0 + i;
-    const double Uh = a.mom[cell * 4 + 0], qh = a.mom[cell * 4 + 1], G1 = a.mom[cell * 4 + 2];
-    double dU = 0.0, Usol = Uh;
-    if (a.sis) {
-      double y;
-      if (i == 0) {
-        y = Uh + G1;
-      } else {
+  for (int base = 0; base < nodes; base += kDiffChunk) {
+    const int cnt = min(kDiffChunk, nodes - base);
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int64_t cell = c0 + base + t;
+      in[0][t] = a.mom[cell * 4 + 0];
+      in[1][t] = a.mom[cell * 4 + 1];
+      in[2][t] = a.mom[cell * 4 + 2];
+      const double x = a.x[cell];
+      in[7][t] = x;
+      if (a.sis && base + t > 0) {
         double A1 = 0.0;
         if (a.amom) A1 = a.amom[cell * 4 + 0] + a.N * del * a.amom[cell * 4 + 1];
-        const double src = A1 - (pois ? a.N * del * a.x[cell] : 0.0);
-        const double ca = a.coef[cell * 6 + 0], cb = a.coef[cell * 6 + 1], cc = a.coef[cell * 6 + 2];
-        y = (src - cb * y1 - cc * y2) / ca;
+        in[3][t] = A1 - (pois ? a.N * del * x : 0.0);
+        in[4][t] = a.coef[cell * 6 + 0];
+        in[5][t] = a.coef[cell * 6 + 1];
+        in[6][t] = a.coef[cell * 6 + 2];
       }
-      y2 = y1;
-      y1 = y;
-      Usol = y - G1;
-      dU = Usol - Uh;
     }
-    // moments of h^{k+1} = h^{k+1/2} + dU 2 v3 f_eq (eq. guided)
-    const double Un = Uh + dU * a.cU, qn = qh + dU * a.cq;
-    if (a.U) a.U[cell] = Usol;
-    if (a.dU) a.dU[cell] = dU;
-    if (a.qfield) a.qfield[cell] = qn;
-    if (a.ufield) a.ufield[cell] = Un;
-    const double x = a.x[cell];
-    if (i > 0) {
-      Mr += 0.5 * (Un + Up) * (x - xp);
-      Qr += 0.5 * (qn + qp) * (x - xp);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int t = 0; t < cnt; ++t) {
+        const int i = base + t;
+        const double Uh = in[0][t], qh = in[1][t], G1 = in[2][t];
+        double dU = 0.0, Usol = Uh;
+        if (a.sis) {
+          const double y = i == 0 ? Uh + G1 : (in[3][t] - in[5][t] * y1 - in[6][t] * y2) / in[4][t];
+          y2 = y1;
+          y1 = y;
+          Usol = y - G1;
+          dU = Usol - Uh;
+        }
+        // moments of h^{k+1} = h^{k+1/2} + dU 2 v3 f_eq (eq. guided)
+        const double Un = Uh + dU * a.cU, qn = qh + dU * a.cq;
+        out[0][t] = Usol;
+        out[1][t] = dU;
+        out[2][t] = qn;
+        out[3][t] = Un;
+        const double x = in[7][t];
+        if (i > 0) {
+          Mr += 0.5 * (Un + Up) * (x - xp);
+          Qr += 0.5 * (qn + qp) * (x - xp);
+        }
+        Up = Un;
+        qp = qn;
+        xp = x;
+      }
     }
-    Up = Un;
-    qp = qn;
-    xp = x;
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int64_t cell = c0 + base + t;
+      if (a.U) a.U[cell] = out[0][t];
+      if (a.dU) a.dU[cell] = out[1][t];
+      if (a.qfield) a.qfield[cell] = out[2][t];
+      if (a.ufield) a.ufield[cell] = out[3][t];
+    }
+    // the next chunk's staging writes only in[]; the march that rewrites out[] starts
+    // after the next barrier, which every lane reaches after its stores above
   }
-  if (a.state) {
+  if (threadIdx.x == 0 && a.state) {
     const double M = 2.0 * Mr, Q = 2.0 * Qr;
     double* st = a.state + cs * 4;
     const double dM = fabs(M - st[0]) / fmax(fabs(M), 1e-300);
@@ -869,62 +943,98 @@ __global__ __launch_bounds__(64) void diffusion1d_kernel(DiffusionArgs a) {
 // stress) and A (total stress minus B's), integrated once from the symmetry
 // plane and marched from the wall; rows are (cell, species) with species A
 // first.  mom[row][4] = {int v3 h, q, G1, P13}; U is per unit molar fraction.
-__global__ __launch_bounds__(64) void diffusion1d_mix_kernel(DiffusionArgs a) {
+// The two species march independently (lane s carries species s); inputs and outputs
+// are staged through LDS as in diffusion1d_kernel.
+__global__ __launch_bounds__(kDiffChunk) void diffusion1d_mix_kernel(DiffusionArgs a) {
+  __shared__ double in_s[2][4][kDiffChunk];   // per species: Uh, qh, G, source
+  __shared__ double in_c[4][kDiffChunk];      // per node: ca, cb, cc, x
+  __shared__ double out[2][4][kDiffChunk];    // per species: U, dU, q, U of the new iterate
+  __shared__ double red[2][2];                // per species: M, Q integrals
   const int cs = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  if (a.case_active && !a.case_active[cs]) return;
+  if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int64_t c0 = a.node_off[cs];
   const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
   const double del = a.delta_case[cs];
   const double pois = a.flow_case[cs] == 1 ? 1.0 : 0.0;
-  double y1[2] = {0.0, 0.0}, y2[2] = {0.0, 0.0};
-  double Mr[2] = {0.0, 0.0}, Qr[2] = {0.0, 0.0}, Up[2] = {0.0, 0.0}, qp[2] = {0.0, 0.0}, xp = 0.0;
-  for (int i = 0; i < nodes; ++i) {
-    const int64_t cell = c0 + i;
-    const double x = a.x[cell];
-    const double PB = a.mom[(cell * 2 + 1) * 4 + 3];
-    for (int s = 0; s < 2; ++s) {
-      const int64_t r = cell * 2 + s;
-      const double chi = a.chi[s];
-      const double Uh = a.mom[r * 4 + 0] / chi, qh = a.mom[r * 4 + 1], G = a.mom[r * 4 + 2];
-      double dU = 0.0, Usol = Uh;
-      if (a.sis) {
-        double y;
-        if (i == 0) {
-          y = chi * Uh + G;
-        } else {
+  const int sp = threadIdx.x;                 // marching lane: species sp (lanes 0, 1)
+  double y1 = 0.0, y2 = 0.0;
+  double Mr = 0.0, Qr = 0.0, Up = 0.0, qp = 0.0, xp = 0.0;
+  for (int base = 0; base < nodes; base += kDiffChunk) {
+    const int cnt = min(kDiffChunk, nodes - base);
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int64_t cell = c0 + base + t;
+      const double x = a.x[cell];
+      const double PB = a.mom[(cell * 2 + 1) * 4 + 3];
+      in_c[3][t] = x;
+      if (a.sis && base + t > 0) {
+        in_c[0][t] = a.coef[cell * 6 + 0];
+        in_c[1][t] = a.coef[cell * 6 + 1];
+        in_c[2][t] = a.coef[cell * 6 + 2];
+      }
+      for (int s = 0; s < 2; ++s) {
+        const int64_t r = cell * 2 + s;
+        in_s[s][0][t] = a.mom[r * 4 + 0] / a.chi[s];
+        in_s[s][1][t] = a.mom[r * 4 + 1];
+        in_s[s][2][t] = a.mom[r * 4 + 2];
+        if (a.sis && base + t > 0) {
           const double Nd = a.Ns[s] * del;
           double A = 0.0;
           if (a.amom) A = a.amom[r * 4 + 0] + Nd * a.amom[r * 4 + 1];
-          const double src = s == 1 ? A - Nd * PB / a.mass_ratio[1] : A - Nd * (pois * x - PB);
-          const double ca = a.coef[cell * 6 + 0], cb = a.coef[cell * 6 + 1], cc = a.coef[cell * 6 + 2];
-          y = (src - cb * y1[s] - cc * y2[s]) / ca;
+          in_s[s][3][t] = s == 1 ? A - Nd * PB / a.mass_ratio[1] : A - Nd * (pois * x - PB);
         }
-        y2[s] = y1[s];
-        y1[s] = y;
-        Usol = (y - G) / chi;
-        dU = Usol - Uh;
       }
-      const double Un = Uh + dU * a.cUs[s], qn = qh + dU * a.cqs[s];
-      if (a.U) a.U[r] = Usol;
-      if (a.dU) a.dU[r] = dU;
-      if (a.qfield) a.qfield[r] = qn;
-      if (a.ufield) a.ufield[r] = Un;
-      if (i > 0) {
-        Mr[s] += 0.5 * (Un + Up[s]) * (x - xp);
-        Qr[s] += 0.5 * (qn + qp[s]) * (x - xp);
-      }
-      Up[s] = Un;
-      qp[s] = qn;
     }
-    xp = x;
+    __syncthreads();
+    if (sp < 2) {
+      const double chi = a.chi[sp];
+      for (int t = 0; t < cnt; ++t) {
+        const int i = base + t;
+        const double Uh = in_s[sp][0][t], qh = in_s[sp][1][t], G = in_s[sp][2][t];
+        double dU = 0.0, Usol = Uh;
+        if (a.sis) {
+          const double y = i == 0 ? chi * Uh + G
+                                  : (in_s[sp][3][t] - in_c[1][t] * y1 - in_c[2][t] * y2) / in_c[0][t];
+          y2 = y1;
+          y1 = y;
+          Usol = (y - G) / chi;
+          dU = Usol - Uh;
+        }
+        const double Un = Uh + dU * a.cUs[sp], qn = qh + dU * a.cqs[sp];
+        out[sp][0][t] = Usol;
+        out[sp][1][t] = dU;
+        out[sp][2][t] = qn;
+        out[sp][3][t] = Un;
+        const double x = in_c[3][t];
+        if (i > 0) {
+          Mr += 0.5 * (Un + Up) * (x - xp);
+          Qr += 0.5 * (qn + qp) * (x - xp);
+        }
+        Up = Un;
+        qp = qn;
+        xp = x;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * cnt; e += blockDim.x) {
+      const int t = e >> 1, s = e & 1;
+      const int64_t r = (c0 + base + t) * 2 + s;
+      if (a.U) a.U[r] = out[s][0][t];
+      if (a.dU) a.dU[r] = out[s][1][t];
+      if (a.qfield) a.qfield[r] = out[s][2][t];
+      if (a.ufield) a.ufield[r] = out[s][3][t];
+    }
   }
-  if (a.state) {
+  if (sp < 2) {
+    red[sp][0] = Mr;
+    red[sp][1] = Qr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && a.state) {
     double* st = a.state + cs * 6;  // M_A, M_B, Q_A, Q_B, residual, iterations
     double res = 0.0;
     bool bad = false;
     for (int s = 0; s < 2; ++s) {
-      const double M = 2.0 * a.flow_factor * Mr[s], Q = 2.0 * a.flow_factor * Qr[s];
+      const double M = 2.0 * a.flow_factor * red[s][0], Q = 2.0 * a.flow_factor * red[s][1];
       res = fmax(res, fmax(fabs(M - st[s]) / fmax(fabs(M), 1e-300), fabs(Q - st[2 + s]) / fmax(fabs(Q), 1e-300)));
       bad = bad || M != M || Q != Q;
       st[s] = M;
@@ -1730,49 +1840,79 @@ __global__ __launch_bounds__(256) void moments_tube_kernel(int nv, const double*
   }
 }
 
-// Velocity equation of the tube per case (one thread: a march over the radial nodes),
-// outputs, flow rates 2 int_0^1 f r dr and the convergence test.
-__global__ void diffusion_tube_kernel(TubeDiffArgs a) {
-  const int cs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cs >= a.n_cases) return;
-  if (a.case_active && !a.case_active[cs]) return;
+// Velocity equation of the tube, one workgroup per case: a march over the radial nodes
+// from the wall inwards (one lane; inputs and outputs staged through LDS in coalesced
+// chunks as in diffusion1d_kernel), outputs, flow rates 2 int_0^1 f r dr and the
+// convergence test.
+__global__ __launch_bounds__(kDiffChunk) void diffusion_tube_kernel(TubeDiffArgs a) {
+  __shared__ double in[8][kDiffChunk];    // U3, q3, G, source, c0, c1, c2, weight
+  __shared__ double out[4][kDiffChunk];   // U, dU, U and q of the new iterate
+  const int cs = blockIdx.x;
+  if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int64_t n0 = a.node_off[cs];
   const int n = static_cast<int>(a.node_off[cs + 1] - n0);
   const double del = a.delta_case[cs];
   const bool pois = a.flow_case[cs] == 1;
   const double Nd = a.N * del;
   double y1 = 0.0, y2 = 0.0, M = 0.0, Q = 0.0;
-  for (int i = n - 1; i >= 0; --i) {
-    const int64_t node = n0 + i;
-    const double* m = a.mom + node * 8;
-    const double U3 = m[0], q3 = m[1], G = m[2];
-    double dU = 0.0, U = U3;
-    if (a.sis) {
-      double y;
-      if (i == n - 1) {
-        y = U3 + G;
-      } else {
+  for (int end = n; end > 0; end -= kDiffChunk) {
+    const int lo = max(0, end - kDiffChunk), cnt = end - lo;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int i = lo + t;
+      const int64_t node = n0 + i;
+      const double* m = a.mom + node * 8;
+      in[0][t] = m[0];
+      in[1][t] = m[1];
+      in[2][t] = m[2];
+      in[7][t] = a.tw[node];
+      if (a.sis && i < n - 1) {
         double A = 0.0;
         if (a.amom) A = a.amom[node * 4 + 0] + Nd * a.amom[node * 4 + 1];
         const double r = a.r[node];
-        const double src = A - m[3] / r - (pois ? Nd * r / 2.0 : 0.0);
-        const double* cf = a.cin + node * 3;
-        y = i == n - 2 ? (src - cf[1] * y1) / cf[0] : (src - cf[1] * y1 - cf[2] * y2) / cf[0];
+        in[3][t] = A - m[3] / r - (pois ? Nd * r / 2.0 : 0.0);
+        in[4][t] = a.cin[node * 3 + 0];
+        in[5][t] = a.cin[node * 3 + 1];
+        in[6][t] = a.cin[node * 3 + 2];
       }
-      y2 = y1;
-      y1 = y;
-      U = y - G;
-      dU = U - U3;
     }
-    const double Un = U3 + dU * a.cU, qn = q3 + dU * a.cq;
-    if (a.U) a.U[node] = U;
-    if (a.dU) a.dU[node] = dU;
-    if (a.ufield) a.ufield[node] = Un;
-    if (a.qfield) a.qfield[node] = qn;
-    M += a.tw[node] * Un;
-    Q += a.tw[node] * qn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int t = cnt - 1; t >= 0; --t) {
+        const int i = lo + t;
+        const double U3 = in[0][t], q3 = in[1][t], G = in[2][t];
+        double dU = 0.0, U = U3;
+        if (a.sis) {
+          double y;
+          if (i == n - 1)
+            y = U3 + G;
+          else if (i == n - 2)
+            y = (in[3][t] - in[5][t] * y1) / in[4][t];
+          else
+            y = (in[3][t] - in[5][t] * y1 - in[6][t] * y2) / in[4][t];
+          y2 = y1;
+          y1 = y;
+          U = y - G;
+          dU = U - U3;
+        }
+        const double Un = U3 + dU * a.cU, qn = q3 + dU * a.cq;
+        out[0][t] = U;
+        out[1][t] = dU;
+        out[2][t] = Un;
+        out[3][t] = qn;
+        M += in[7][t] * Un;
+        Q += in[7][t] * qn;
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+      const int64_t node = n0 + lo + t;
+      if (a.U) a.U[node] = out[0][t];
+      if (a.dU) a.dU[node] = out[1][t];
+      if (a.ufield) a.ufield[node] = out[2][t];
+      if (a.qfield) a.qfield[node] = out[3][t];
+    }
   }
-  if (a.state) {
+  if (threadIdx.x == 0 && a.state) {
     double* st = a.state + cs * 4;
     const double dM = fabs(M - st[0]) / fmax(fabs(M), 1e-300);
     const double dQ = fabs(Q - st[1]) / fmax(fabs(Q), 1e-300);
@@ -1912,9 +2052,9 @@ hipError_t launch_moments(int n, int d2, int d3, int nsp, const double* mass_rat
 
 hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
   if (a.nsp == 2)
-    hipLaunchKernelGGL(diffusion1d_mix_kernel, dim3(a.n_cases), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(diffusion1d_mix_kernel, dim3(a.n_cases), dim3(kDiffChunk), 0, s, a);
   else
-    hipLaunchKernelGGL(diffusion1d_kernel, dim3(a.n_cases), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(diffusion1d_kernel, dim3(a.n_cases), dim3(kDiffChunk), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2046,7 +2186,7 @@ hipError_t launch_moments_tube(int64_t n_nodes, int nv, const double* vnode, con
 }
 
 hipError_t launch_diffusion_tube(const TubeDiffArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(diffusion_tube_kernel, dim3((a.n_cases + 63) / 64), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(diffusion_tube_kernel, dim3(a.n_cases), dim3(kDiffChunk), 0, s, a);
   return hipGetLastError();
 }
 
