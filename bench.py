@@ -40,7 +40,11 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 # stands, keyed by (workload, parity, precision, tile rows, split-K, k-stage); a launch
 # configuration without a recorded pass reports null.  Source:
 # profiles/gemm_f64_planar-hs-32v-808cells-parity.md.
-TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (1750706.0 * 2.0, 206848.0)}
+TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (1104717.6 * 2.0, 155136.0)}
+# MFMA pipe utilisation of the same configuration from its counter pass:
+# SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), and the shader clock
+# the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
+MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22)}
 HBM_GBS = 8000.0
 
 
@@ -246,8 +250,10 @@ def main():
     log(f"contraction: {avg_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s of {peak} peak "
         f"(tile {tile_rows}x128, k-stage {k_stage}, split-K {splits}, autotuned {tuned})")
     tk = TRAFFIC_KIB.get((w["name"], parity, args.precision, tile_rows, splits, k_stage))
+    mb = MFMA_BUSY.get((w["name"], parity, args.precision, tile_rows, splits, k_stage))
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": (tk[0] + tk[1]) * 1024.0 if tk else None,
+                "mfma_busy": mb[0] if mb else None, "clock_ghz_counters": mb[1] if mb else None,
                 "kernel": f"gemm_{args.precision}", "avg_launch_ms": round(avg_ms, 4),
                 "tile": f"{tile_rows}x128", "k_stage": k_stage, "split_k": splits, "autotuned": tuned,
                 "flops_per_launch": executed,

@@ -635,51 +635,83 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) m[k] = 0.0;
   const int d2 = a.d2, d3 = a.d3, d23 = d2 * d3;
-  for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-    double v1, v2, v3, wv;
-    if (a.vnode) {
-      v1 = a.vnode[v];
-      v2 = a.vnode[n3 + v];
-      v3 = a.vnode[2 * n3 + v];
-      wv = a.wnode[v];
-    } else {
-      const int j1 = v / d23, j2 = (v / d3) % d2, j3 = v % d3;
-      v1 = a.v1d[j1];
-      v2 = a.v2d[j2];
-      v3 = a.v3d[j3];
-      wv = a.w;
+  // four unknowns per lane and pass: the loads of all four (partials, h, anchor) are
+  // issued before any store (with one split the partial sum is the output row itself)
+  constexpr int U = 4;
+  const int bs = blockDim.x;
+  for (int v0 = threadIdx.x; v0 < n3; v0 += U * bs) {
+    double sv[U], hv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sv[u] = 0.0;
+      hv[u] = v0 + u * bs < n3 ? a.h[base + v0 + u * bs] : 0.0;
     }
-    const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
-    const double f = feq[v];
-    double s = 0.0;
-    for (int z = 0; z < a.splits; ++z) s += a.acc[z * sstride + base + v];
-    if (a.anchor_mode == 2) {
-      s += a.accref[base + v];
-    } else if (a.anchor_mode == 1) {
-      a.accref[base + v] = s;
-      a.xref[base + v] = a.h[base + v];
+    // split-K partials four at a time (all sixteen loads in flight), summed in split order
+    for (int z0 = 0; z0 < a.splits; z0 += 4) {
+      double t[4][U];
+#pragma unroll
+      for (int dz = 0; dz < 4; ++dz)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int v = v0 + u * bs;
+          t[dz][u] = (z0 + dz < a.splits && v < n3) ? a.acc[(z0 + dz) * sstride + base + v] : 0.0;
+        }
+#pragma unroll
+      for (int dz = 0; dz < 4; ++dz)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (z0 + dz < a.splits) sv[u] += t[dz][u];
     }
-    // L+ of the corrected iterate: the correction of every species of the cell enters
-    double lp = s;
-    if (a.dU)
-      for (int q = 0; q < nsp; ++q) lp += a.dU[cell * nsp + q] * a.Kc[(static_cast<int64_t>(q) * nsp + sp) * n3 + v];
-    const double hk = a.h[base + v] + dUc * 2.0 * ms * v3 * f;
-    const double L = del * (lp - nu[v] * hk);
-    double S = 0.0;
-    if (fl == 1) S = v3 * f;
-    else if (fl == 2 && nsp == 1) S = v3 * (vsq - 2.5) * f;
-    a.rhs[base + v] = del * lp + S;
-    if (a.lh) a.lh[base + v] = L;
-    const double wL = wv * L;
-    m[0] += wL;
-    m[1] += wL * v1;
-    m[2] += wL * v2;
-    m[3] += wL * v3;
-    m[4] += wL * vsq;
-    m[5] += 2.0 * wv * v1 * v3 * L;
-    m[6] += 2.0 * wv * v1 * v3 * hk;
-    m[7] += 2.0 * wv * v2 * v3 * L;
-    m[8] += 2.0 * wv * v2 * v3 * hk;
+    if (a.anchor_mode == 2)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (v0 + u * bs < n3) sv[u] += a.accref[base + v0 + u * bs];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int v = v0 + u * bs;
+      if (v >= n3) break;
+      double v1, v2, v3, wv;
+      if (a.vnode) {
+        v1 = a.vnode[v];
+        v2 = a.vnode[n3 + v];
+        v3 = a.vnode[2 * n3 + v];
+        wv = a.wnode[v];
+      } else {
+        const int j1 = v / d23, j2 = (v / d3) % d2, j3 = v % d3;
+        v1 = a.v1d[j1];
+        v2 = a.v2d[j2];
+        v3 = a.v3d[j3];
+        wv = a.w;
+      }
+      const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+      const double f = feq[v];
+      const double s = sv[u];
+      if (a.anchor_mode == 1) {
+        a.accref[base + v] = s;
+        a.xref[base + v] = hv[u];
+      }
+      // L+ of the corrected iterate: the correction of every species of the cell enters
+      double lp = s;
+      if (a.dU)
+        for (int q = 0; q < nsp; ++q) lp += a.dU[cell * nsp + q] * a.Kc[(static_cast<int64_t>(q) * nsp + sp) * n3 + v];
+      const double hk = hv[u] + dUc * 2.0 * ms * v3 * f;
+      const double L = del * (lp - nu[v] * hk);
+      double S = 0.0;
+      if (fl == 1) S = v3 * f;
+      else if (fl == 2 && nsp == 1) S = v3 * (vsq - 2.5) * f;
+      a.rhs[base + v] = del * lp + S;
+      if (a.lh) a.lh[base + v] = L;
+      const double wL = wv * L;
+      m[0] += wL;
+      m[1] += wL * v1;
+      m[2] += wL * v2;
+      m[3] += wL * v3;
+      m[4] += wL * vsq;
+      m[5] += 2.0 * wv * v1 * v3 * L;
+      m[6] += 2.0 * wv * v1 * v3 * hk;
+      m[7] += 2.0 * wv * v2 * v3 * L;
+      m[8] += 2.0 * wv * v2 * v3 * hk;
+    }
   }
   block_sum<9>(m, sh);
   if (a.project) {
@@ -832,6 +864,7 @@ __global__ __launch_bounds__(256) void moments_kernel(int n, int d2, int d3, int
   const double ms = (c % nsp) == 0 ? ms0 : ms1;
   const int d23 = d2 * d3, n3 = n * d23;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
   for (int v = threadIdx.x; v < n3; v += blockDim.x) {
     const double v1 = v1d[v / d23], v2 = v2d[(v / d3) % d2], v3 = v3d[v % d3];
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
