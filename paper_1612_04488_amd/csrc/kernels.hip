@@ -168,10 +168,13 @@ __global__ void split_bf16_kernel(const double* __restrict__ in, uint16_t* __res
 constexpr int kBK = 16;
 constexpr int kPad = 4;
 
-// BK: k-depth of a stage; NBUF = 2: double-buffered LDS (one barrier per stage), NBUF = 1:
-// one buffer (two barriers per stage, half the LDS, so deeper stages fit twice per CU);
-// PAD: row padding of the k-major LDS tiles (PAD = 1 with BK = 32 spreads the 64-lane
-// stores of 16 k-rows x 4 rows over the banks).
+// BK: k-depth of a stage; NBUF = 2: double-buffered LDS, software-pipelined: the next
+// stage's global loads are issued at the start of a stage and written to the other LDS buffer
+// two k-steps before its end, and the stage's one barrier sits before its last k-step's MFMAs,
+// so that the next stage's first LDS reads overlap them.  NBUF = 1: one buffer (two barriers
+// per stage, half the LDS, so deeper stages fit twice per CU).  PAD: row padding of the
+// k-major LDS tiles (PAD = 1 with BK = 32 spreads the 64-lane stores of 16 k-rows x 4 rows
+// over the banks).
 template <int BM, int BN, int WM, int WN, int BK = kBK, int NBUF = 2, int PAD = kPad>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict__ X,
                                                        const double* __restrict__ Op,
@@ -246,46 +249,75 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
   }
   __syncthreads();
   const int kr = lane >> 4, cc = lane & 15;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = NBUF == 2 ? (kt & 1) : 0;
-    if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
-    // operands of k-step kk + 1 are read from LDS into the other register set
-    // while the MFMAs of k-step kk run
+  if constexpr (NBUF == 2) {
+    static_assert((BK / 4) % 2 == 0, "an even number of k-steps per stage");
+    constexpr int KS = BK / 4, KW = KS - 2;
     double a[2][TM], b[2][TN];
-    auto lread = [&](int kk, double* ar, double* br) {
+    auto lread = [&](int buf, int kk, double* ar, double* br) {
 #pragma unroll
-      for (int i = 0; i < TM; ++i) ar[i] = As[cur][kk * 4 + kr][wm + i * 16 + cc];
+      for (int i = 0; i < TM; ++i) ar[i] = As[buf][kk * 4 + kr][wm + i * 16 + cc];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) br[j] = Bs[cur][kk * 4 + kr][wn + j * 16 + cc];
+      for (int j = 0; j < TN; ++j) br[j] = Bs[buf][kk * 4 + kr][wn + j * 16 + cc];
     };
-    lread(0, a[0], b[0]);
+    if (nk > 0) lread(0, 0, a[0], b[0]);
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      const bool more = kt + 1 < nk;
+      if (more) gload(kbeg + (kt + 1) * BK);
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int c = kk & 1;
-      if (kk + 1 < BK / 4) lread(kk + 1, a[c ^ 1], b[c ^ 1]);
+      for (int kk = 0; kk < KS; ++kk) {
+        const int c = kk & 1;
+        if (kk + 1 < KS) lread(cur, kk + 1, a[c ^ 1], b[c ^ 1]);
+        if (kk == KW && more) sstore(cur ^ 1);
+        if (kk == KS - 1) {
+          __syncthreads();       // next buffer written by every wave, this one read by every wave
+          if (more) lread(cur ^ 1, 0, a[c ^ 1], b[c ^ 1]);
+        }
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][i], b[c][j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][i], b[c][j], acc[i][j], 0, 0, 0);
+      }
     }
-    // Schedule of the block above (a hint to the compiler's scheduler, which otherwise sinks
-    // the reads behind the MFMAs that use the other register set): the first step's reads,
-    // then per step one MFMA, the next step's LDS reads (ds_read2: two operands each), the
-    // step's other MFMAs.
-    constexpr int kReads = (TM + 1) / 2 + (TN + 1) / 2;
-    __builtin_amdgcn_sched_group_barrier(0x100, kReads, 0);
+  } else {
+    static_assert(NBUF == 1, "one or two LDS buffers");
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = 0;
+      if (kt + 1 < nk) gload(kbeg + (kt + 1) * BK);
+      // operands of k-step kk + 1 are read from LDS into the other register set
+      // while the MFMAs of k-step kk run
+      double a[2][TM], b[2][TN];
+      auto lread = [&](int kk, double* ar, double* br) {
 #pragma unroll
-    for (int kk = 0; kk + 1 < BK / 4; ++kk) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        for (int i = 0; i < TM; ++i) ar[i] = As[cur][kk * 4 + kr][wm + i * 16 + cc];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) br[j] = Bs[cur][kk * 4 + kr][wn + j * 16 + cc];
+      };
+      lread(0, a[0], b[0]);
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int c = kk & 1;
+        if (kk + 1 < BK / 4) lread(kk + 1, a[c ^ 1], b[c ^ 1]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][i], b[c][j], acc[i][j], 0, 0, 0);
+      }
+      // Schedule of the block above (a hint to the compiler's scheduler, which otherwise sinks
+      // the reads behind the MFMAs that use the other register set): the first step's reads,
+      // then per step one MFMA, the next step's LDS reads (ds_read2: two operands each), the
+      // step's other MFMAs.
+      constexpr int kReads = (TM + 1) / 2 + (TN + 1) / 2;
       __builtin_amdgcn_sched_group_barrier(0x100, kReads, 0);
-      __builtin_amdgcn_sched_group_barrier(0x008, TM * TN - 1, 0);
-    }
-    __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
-    if (NBUF == 2) {
-      if (kt + 1 < nk) sstore(cur ^ 1);
-      __syncthreads();
-    } else {
+#pragma unroll
+      for (int kk = 0; kk + 1 < BK / 4; ++kk) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, kReads, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, TM * TN - 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, TM * TN, 0);
       __syncthreads();           // every wave is done with the buffer
       if (kt + 1 < nk) sstore(0);
       __syncthreads();
