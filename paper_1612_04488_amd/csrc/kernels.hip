@@ -1189,12 +1189,14 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
 }
 
 // Pipelined form of the same sweep for cross sections whose anti-diagonals hold at most
-// kSweepP * 64 cells (min(n1, n2) <= 128): each slot owns up to kSweepP cells of a diagonal,
-// and the read-only data of its cells on the next diagonal (cell index, stencil
-// coefficients, upwind references, right side) are loaded while the current diagonal is
-// computed, so that after each barrier only the upwind values of h are waited for.  The
-// values and the order of the updates are those of sweep2d_kernel.
-constexpr int kSweepP = 2;
+// P * 64 cells (min(n1, n2) <= 64 P): each slot owns up to P cells of a diagonal, and the
+// read-only data of its cells on the next diagonal (cell index, stencil coefficients,
+// upwind references, right side) are loaded while the current diagonal is computed, so
+// that after each barrier only the upwind values of h are waited for.  The values and the
+// order of the updates are those of sweep2d_kernel.  P is the smallest that covers the
+// longest anti-diagonal: the per-cell state of two diagonals sits in registers, so a
+// smaller P leaves room for more resident workgroups.
+constexpr int kSweepMaxP = 3;
 
 struct Sweep2DPoint {
   int64_t row;          // (cell * nsp + species), -1: no fluid cell
@@ -1203,6 +1205,7 @@ struct Sweep2DPoint {
   int8_t k1[2], k2[2];
 };
 
+template <int kSweepP>
 __global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2DArgs a) {
   const int cs = blockIdx.y;
   if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
@@ -2128,8 +2131,14 @@ hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   const int hn = a.n / 2;
   const int count = hn * hn * a.d3;
   dim3 grid((count + kSweepV - 1) / kSweepV, a.n_cases, a.nsp);
-  if (a.max_diag <= kSweepP * (kSweepThreads / kSweepV))
-    hipLaunchKernelGGL(sweep2d_pipelined_kernel, grid, dim3(kSweepThreads), 0, s, a);
+  const int slots = kSweepThreads / kSweepV;
+  const int P = (a.max_diag + slots - 1) / slots;
+  if (P <= 1)
+    hipLaunchKernelGGL(sweep2d_pipelined_kernel<1>, grid, dim3(kSweepThreads), 0, s, a);
+  else if (P == 2)
+    hipLaunchKernelGGL(sweep2d_pipelined_kernel<2>, grid, dim3(kSweepThreads), 0, s, a);
+  else if (P <= kSweepMaxP)
+    hipLaunchKernelGGL(sweep2d_pipelined_kernel<3>, grid, dim3(kSweepThreads), 0, s, a);
   else
     hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(kSweepThreads), 0, s, a);
   return hipGetLastError();
