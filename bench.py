@@ -38,13 +38,15 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 # HBM bytes per contraction launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (scaled by a 1 GiB copy: FETCH x2.0, WRITE x1.0), recorded for the kernel as it
 # stands, keyed by (workload, parity, precision, tile rows, split-K, k-stage); a launch
-# configuration without a recorded pass reports null.  Source:
-# profiles/gemm_f64_planar-hs-32v-808cells-parity.md.
-TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (1104717.6 * 2.0, 155136.0)}
+# configuration without a recorded pass reports null.  Sources:
+# profiles/gemm_f64_planar-hs-32v-808cells-parity.md, profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md.
+TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (1104717.6 * 2.0, 155136.0),
+               ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (43313000.0 * 2.0, 1327100.0)}
 # MFMA pipe utilisation of the same configuration from its counter pass:
 # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), and the shader clock
 # the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
-MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22)}
+MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22),
+             ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.803, 2.35)}
 HBM_GBS = 8000.0
 
 
