@@ -379,11 +379,62 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   return SIS_OK;
 }
 
+// Arguments of finish_kernel for a contraction of n_cells cells (partial sums set by the caller).
+sis::FinishArgs finish_args(const sis_plan* p, int64_t n_cells, const double* h, const double* dU,
+                            const double* delta, const int32_t* flow, int project, double* rhs, double* lh,
+                            double* amom, const int32_t* cell_active, int anchor_mode, double* xref,
+                            double* accref) {
+  sis::FinishArgs f{};
+  f.n = p->n;
+  f.n3 = p->nv;
+  f.d2 = p->d2;
+  f.d3 = p->d3;
+  f.v2d = p->v1d + (p->n - p->d2);
+  f.v3d = p->v1d + (p->n - p->d3);
+  f.even_v2 = p->parity == 2;
+  f.nsp = p->nsp;
+  f.mass_ratio[0] = p->mass_ratio[0];
+  f.mass_ratio[1] = p->mass_ratio[1];
+  f.n_cells = n_cells * p->nsp;
+  f.h = h;
+  f.dU = dU;
+  f.delta = delta;
+  f.flow = flow;
+  f.project = project;
+  f.v1d = p->v1d;
+  f.vnode = p->vnode;
+  f.wnode = p->wnode;
+  f.feq = p->feq;
+  f.nu = p->nu;
+  f.Kc = p->Kc;
+  f.gram_inv = p->gram_inv;
+  f.w = p->wr;
+  f.active = cell_active;
+  f.anchor_mode = anchor_mode;
+  f.accref = accref;
+  f.xref = xref;
+  f.rhs = rhs;
+  f.lh = lh;
+  f.amom = amom;
+  return f;
+}
+
 sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const double* dU,
                        const double* delta, const int32_t* flow, int project, double* rhs,
                        double* lh, double* amom, const int32_t* cell_active, hipStream_t s,
                        int precision = -1, int anchor_mode = 0, double* xref = nullptr,
-                       double* accref = nullptr, Scratch* ws_acc = nullptr, Scratch* ws_x = nullptr) {
+                       double* accref = nullptr, Scratch* ws_acc = nullptr, Scratch* ws_x = nullptr,
+                       bool h_is_zero = false) {
+  if (h_is_zero) {
+    // L+ h = 0 for h = 0: no contraction; finish_kernel sums no partials (the anchor, if one
+    // is being taken, becomes (0, 0))
+    sis::FinishArgs f = finish_args(p, n_cells, h, dU, delta, flow, project, rhs, lh, amom, cell_active,
+                                    anchor_mode, xref, accref);
+    f.splits = 0;
+    f.acc = nullptr;
+    HIP_TRY(sis::launch_finish(f, s));
+    return SIS_OK;
+  }
   if (!ws_acc) ws_acc = &p->ws_acc;
   if (!ws_x) ws_x = &p->ws_x;
   if (precision < 0) precision = p->precision;
@@ -432,40 +483,10 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   } else {
     HIP_TRY(sis::launch_gemm(g, s));
   }
-  sis::FinishArgs f{};
-  f.n = p->n;
-  f.n3 = p->nv;
-  f.d2 = p->d2;
-  f.d3 = p->d3;
-  f.v2d = p->v1d + (p->n - p->d2);
-  f.v3d = p->v1d + (p->n - p->d3);
-  f.even_v2 = p->parity == 2;
-  f.nsp = p->nsp;
-  f.mass_ratio[0] = p->mass_ratio[0];
-  f.mass_ratio[1] = p->mass_ratio[1];
-  f.n_cells = n_cells * p->nsp;
+  sis::FinishArgs f = finish_args(p, n_cells, h, dU, delta, flow, project, rhs, lh, amom, cell_active,
+                                  anchor_mode, xref, accref);
   f.splits = splits;
   f.acc = acc;
-  f.h = h;
-  f.dU = dU;
-  f.delta = delta;
-  f.flow = flow;
-  f.project = project;
-  f.v1d = p->v1d;
-  f.vnode = p->vnode;
-  f.wnode = p->wnode;
-  f.feq = p->feq;
-  f.nu = p->nu;
-  f.Kc = p->Kc;
-  f.gram_inv = p->gram_inv;
-  f.w = p->wr;
-  f.active = cell_active;
-  f.anchor_mode = anchor_mode;
-  f.accref = accref;
-  f.xref = xref;
-  f.rhs = rhs;
-  f.lh = lh;
-  f.amom = amom;
   HIP_TRY(sis::launch_finish(f, s));
   return SIS_OK;
 }
@@ -2023,7 +2044,7 @@ struct sis_state {
 namespace {
 
 // kind 0: plain (FP64) or refresh iteration; kind 1: incremental low-precision iteration
-sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
+sis_status state_iteration(sis_state* b, hipStream_t s, int kind, bool h_is_zero = false) {
   sis_plan* p = b->p;
   sis_geom* g = b->g;
   const bool sis = b->o.scheme == SIS_SCHEME_SIS;
@@ -2037,7 +2058,7 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind) {
   }
   if (sis_status st = run_collide(p, g->n_cells, b->h, sis ? b->dU : nullptr, g->delta_cell,
                                   g->flow_cell, b->o.project, b->rhs, nullptr, b->amom, b->lact, s,
-                                  prec, mode, b->xref, b->accref, &b->ws_acc, &b->ws_x))
+                                  prec, mode, b->xref, b->accref, &b->ws_acc, &b->ws_x, h_is_zero))
     return st;
   if (sis_status st = run_sweep(p, g, b->rhs, b->h, b->mom, b->cact, s, b->lact)) return st;
   if (g->tube) {
@@ -2215,7 +2236,10 @@ sis_status sis_state_step(sis_state_t b, int32_t n_iters, hipStream_t stream) {
   if (n_iters < 0) return fail(SIS_E_INVALID, "n_iters must be >= 0");
   for (int i = 0; i < n_iters; ++i) {
     const int kind = (b->refresh > 1 && (b->total % b->refresh) != 0) ? 1 : 0;
-    if (b->exec[kind]) {
+    if (b->total == 0) {
+      // the iteration starts from h = 0 (set by state_init): run it eagerly without the contraction
+      if (sis_status st = state_iteration(b, stream, kind, true)) return st;
+    } else if (b->exec[kind]) {
       HIP_TRY(hipGraphLaunch(b->exec[kind], stream));
     } else if (sis_status st = state_iteration(b, stream, kind)) {
       return st;
