@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--no-ttr", action="store_true", help="skip time-to-residual runs")
+    ap.add_argument("--cis-max-it", type=int, default=0,
+                    help="also run the conventional iteration (FP64) with this iteration cap")
     ap.add_argument("--refresh-every", type=int, default=8,
                     help="mixed runs: FP64 anchor of the defect correction every R-th iteration")
     ap.add_argument("--cpu-cells", type=int, default=12)
@@ -316,6 +318,17 @@ def main():
             ttr[key] = e
             log(f"time-to-residual {key}: {r['seconds']:.3f} s, iters {r['iters'].tolist()}")
         plan.set_precision(args.precision)
+    # ---------------------------------------------------------- conventional iteration (optional)
+    cis = None
+    if args.cis_max_it > 0:
+        plan.set_precision("fp64")
+        r = sis.solve(plan, geom, scheme="CIS", N=Npen, eps=1e-8, max_it=args.cis_max_it,
+                      raise_not_converged=False)
+        cis = {"seconds": round(r["seconds"], 4), "iters": r["iters"].tolist(), "max_it": args.cis_max_it,
+               "converged": [bool(x < 1e-8) for x in r["residual"]], "M": r["M"].tolist()}
+        log(f"conventional iteration (FP64, cap {args.cis_max_it}): {r['seconds']:.3f} s, "
+            f"iters {r['iters'].tolist()}")
+        plan.set_precision(args.precision)
 
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -332,6 +345,8 @@ def main():
            "roofline": roofline, "sweep": sweep,
            "plan_seconds": round(t_plan, 3), "geometry_seconds": round(t_geom, 3),
            "time_to_residual_1e-8": ttr}
+    if cis is not None:
+        out["conventional_iteration_fp64"] = cis
     if diff_info:
         out["config"]["velocity_equation"] = diff_info
     if tube:
