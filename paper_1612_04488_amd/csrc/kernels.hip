@@ -1132,7 +1132,11 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
   const int nsp = a.nsp, sp = blockIdx.z;
   const double* __restrict__ nu = a.nu + static_cast<int64_t>(sp) * n3;
   const int quads = hn * hn * d3;
-  const int tq = blockIdx.x * kSweepV + threadIdx.x % kSweepV;
+  // neighbouring velocity groups share cache lines of h and the right sides: with the group
+  // count a multiple of 8, consecutive groups go to the same XCD (dispatch is round-robin)
+  const int gx = gridDim.x;
+  const int grp = (gx % 8 == 0) ? (blockIdx.x % 8) * (gx / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int tq = grp * kSweepV + threadIdx.x % kSweepV;
   const bool vvalid = tq < quads;
   const int t = vvalid ? tq : 0;
   const int jq1 = t / (hn * d3), jq2 = (t / d3) % hn, j3 = t % d3;
@@ -1213,7 +1217,11 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2
   const int nsp = a.nsp, sp = blockIdx.z;
   const double* __restrict__ nu = a.nu + static_cast<int64_t>(sp) * n3;
   const int quads = hn * hn * d3;
-  const int tq = blockIdx.x * kSweepV + threadIdx.x % kSweepV;
+  // neighbouring velocity groups share cache lines of h and the right sides: with the group
+  // count a multiple of 8, consecutive groups go to the same XCD (dispatch is round-robin)
+  const int gx = gridDim.x;
+  const int grp = (gx % 8 == 0) ? (blockIdx.x % 8) * (gx / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int tq = grp * kSweepV + threadIdx.x % kSweepV;
   const bool vvalid = tq < quads;
   const int t = vvalid ? tq : 0;
   const int jq1 = t / (hn * d3), jq2 = (t / d3) % hn, j3 = t % d3;
