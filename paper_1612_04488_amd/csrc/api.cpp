@@ -140,6 +140,7 @@ struct sis_geom {
   double *d_r = nullptr, *d_cin = nullptr, *d_cout = nullptr, *d_tw = nullptr;
   sis::Tables2D t2;
   int32_t *d_n1 = nullptr, *d_n2 = nullptr, *d_gcell = nullptr, *d_sref = nullptr, *d_nb = nullptr;
+  uint32_t* d_srec = nullptr;    // packed stencil records of the look-ahead sweep
   int64_t* d_goff = nullptr;
   int8_t *d_skind = nullptr, *d_dflag = nullptr, *d_nbm = nullptr;
   double *d_scoef = nullptr, *d_npos = nullptr, *d_fw = nullptr, *d_width = nullptr, *d_cpos = nullptr,
@@ -172,7 +173,7 @@ struct sis_geom {
     dfree(d_r); dfree(d_cin); dfree(d_cout); dfree(d_tw);
     dfree(off); dfree(x); dfree(coef); dfree(delta_case); dfree(flow_case);
     dfree(delta_cell); dfree(flow_cell); dfree(case_of_cell);
-    dfree(d_n1); dfree(d_n2); dfree(d_gcell); dfree(d_sref); dfree(d_nb); dfree(d_goff);
+    dfree(d_n1); dfree(d_n2); dfree(d_gcell); dfree(d_sref); dfree(d_nb); dfree(d_goff); dfree(d_srec);
     dfree(d_skind); dfree(d_dflag); dfree(d_nbm); dfree(d_scoef); dfree(d_npos); dfree(d_fw);
     dfree(d_width); dfree(d_cpos); dfree(d_dA); dfree(d_area); dfree(work); dfree(have_x); dfree(cg_iters);
   }
@@ -533,6 +534,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.coef = g->d_scoef;
     a.ref = g->d_sref;
     a.kind = g->d_skind;
+    a.rec = g->d_srec;
     a.delta_case = g->delta_case;
     a.v1d = p->v1d;
     a.nu = p->nu;
@@ -1096,6 +1098,21 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
   G2_TRY(upload(&g->d_scoef, t.st_coef, stream));
   G2_TRY(upload(&g->d_sref, t.st_ref, stream));
   G2_TRY(upload(&g->d_skind, t.st_kind, stream));
+  {
+    // one 32-byte record per (cell, axis, sign): coefficients a, b, c, then the two references
+    // as (ref << 2 | kind); at least one record so that masked lanes can load a valid address
+    const size_t nrec = t.st_coef.size() / 3;
+    if (nrec / 4 >= (size_t(1) << 30)) { delete g; return fail(SIS_E_SHAPE, "more than 2^30 fluid cells"); }
+    std::vector<uint32_t> rec(std::max<size_t>(nrec, 1) * 8, 0u);
+    for (size_t o = 0; o < nrec; ++o) {
+      std::memcpy(&rec[o * 8], &t.st_coef[o * 3], 3 * sizeof(double));
+      for (int k = 0; k < 2; ++k) {
+        const int kind = t.st_kind[o * 2 + k];
+        rec[o * 8 + 6 + k] = kind == 0 ? 0u : (static_cast<uint32_t>(t.st_ref[o * 2 + k]) << 2) | static_cast<uint32_t>(kind);
+      }
+    }
+    G2_TRY(upload(&g->d_srec, rec, stream));
+  }
   G2_TRY(upload(&g->d_dflag, t.dflag, stream));
   G2_TRY(upload(&g->d_nb, t.nb, stream));
   G2_TRY(upload(&g->d_nbm, t.nbm, stream));

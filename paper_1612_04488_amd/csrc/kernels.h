@@ -160,6 +160,8 @@ struct Sweep2DArgs {
   const double* coef;        // [cell][2][2][3]
   const int32_t* ref;        // [cell][2][2][2]
   const int8_t* kind;        // [cell][2][2][2]
+  const uint32_t* rec;       // [cell][2][2] 32-byte records: the three coefficients (FP64), then
+                             // (ref << 2 | kind) of both references (0 for kind 0)
   const double* delta_case;
   const double* v1d;
   const double* nu;

@@ -1202,6 +1202,17 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_kernel(Sweep2DArgs a) {
 // smaller P leaves room for more resident workgroups.
 constexpr int kSweepMaxP = 3;
 
+// The four words lane K of each group of four lanes holds, in every lane of the group
+// (DPP quad_perm broadcast; every lane of the group must be active).
+template <int K>
+__device__ inline void quad_broadcast(const uint4& w, uint32_t* out) {
+  constexpr int ctrl = K * 0x55;   // quad_perm(K, K, K, K)
+  out[0] = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(w.x), ctrl, 0xF, 0xF, false));
+  out[1] = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(w.y), ctrl, 0xF, 0xF, false));
+  out[2] = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(w.z), ctrl, 0xF, 0xF, false));
+  out[3] = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(w.w), ctrl, 0xF, 0xF, false));
+}
+
 struct Sweep2DPoint {
   int64_t row;          // (cell * nsp + species), -1: no fluid cell
   double rhs, c1[3], c2[3];
@@ -1239,32 +1250,46 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2
     const double av1 = fabs(a.v1d[j1]), av2 = fabs(a.v1d[j2]);
     const double dnu = del * nu[v];
     const int sg1 = s1 > 0 ? 0 : 1, sg2 = s2 > 0 ? 0 : 1;
+    static_assert(kSweepV == 4, "the four lanes of a slot (one velocity each) form a DPP quad");
+    const int quad = threadIdx.x & 3;
     auto load = [&](int d, int p, Sweep2DPoint& pt) {
       pt.row = -1;
       const int lo = max(0, d - (n2 - 1)), hi = min(d, n1 - 1);
       const int ii = lo + slot + p * slots;
-      if (!vvalid || d > n1 + n2 - 2 || ii > hi) return;
-      const int jj = d - ii;
-      const int i = s1 > 0 ? ii : n1 - 1 - ii;
-      const int j = s2 > 0 ? jj : n2 - 1 - jj;
-      const int cell = a.gcell[g0 + static_cast<int64_t>(i) * n2 + j];
-      if (cell < 0) return;
-      const int64_t o1 = (static_cast<int64_t>(cell) * 2 + 0) * 2 + sg1;
-      const int64_t o2 = (static_cast<int64_t>(cell) * 2 + 1) * 2 + sg2;
-      pt.row = static_cast<int64_t>(cell) * nsp + sp;
-      pt.rhs = a.rhs[pt.row * n3 + v];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        pt.c1[k] = a.coef[o1 * 3 + k];
-        pt.c2[k] = a.coef[o2 * 3 + k];
+      int cell = -1;                     // the same for the four lanes of the quad
+      if (d <= n1 + n2 - 2 && ii <= hi) {
+        const int jj = d - ii;
+        const int i = s1 > 0 ? ii : n1 - 1 - ii;
+        const int j = s2 > 0 ? jj : n2 - 1 - jj;
+        cell = a.gcell[g0 + static_cast<int64_t>(i) * n2 + j];
       }
+      // the cell's two 32-byte stencil records (axis 1 with the sign of v1, axis 2 with the sign
+      // of v2) are loaded 16 bytes per lane and broadcast within the quad: one load instruction
+      // instead of fifteen (lanes of cells that do not exist read record 0 and discard it)
+      const int64_t o = (static_cast<int64_t>(cell >= 0 ? cell : 0) * 2 + (quad >> 1)) * 2 + ((quad >> 1) ? sg2 : sg1);
+      const uint4 w = *reinterpret_cast<const uint4*>(a.rec + o * 8 + (quad & 1) * 4);
+      uint32_t r[16];
+      quad_broadcast<0>(w, r);
+      quad_broadcast<1>(w, r + 4);
+      quad_broadcast<2>(w, r + 8);
+      quad_broadcast<3>(w, r + 12);
+      if (!vvalid || cell < 0) return;
+      auto f64 = [&](int k) { return __builtin_bit_cast(double, (static_cast<uint64_t>(r[k + 1]) << 32) | r[k]); };
+      pt.c1[0] = f64(0);
+      pt.c1[1] = f64(2);
+      pt.c1[2] = f64(4);
+      pt.c2[0] = f64(8);
+      pt.c2[1] = f64(10);
+      pt.c2[2] = f64(12);
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        pt.k1[k] = a.kind[o1 * 2 + k];
-        pt.k2[k] = a.kind[o2 * 2 + k];
-        pt.r1[k] = a.ref[o1 * 2 + k];
-        pt.r2[k] = a.ref[o2 * 2 + k];
+        pt.k1[k] = static_cast<int8_t>(r[6 + k] & 3u);
+        pt.r1[k] = static_cast<int32_t>(r[6 + k] >> 2);
+        pt.k2[k] = static_cast<int8_t>(r[14 + k] & 3u);
+        pt.r2[k] = static_cast<int32_t>(r[14 + k] >> 2);
       }
+      pt.row = static_cast<int64_t>(cell) * nsp + sp;
+      pt.rhs = a.rhs[pt.row * n3 + v];
     };
     Sweep2DPoint cur[kSweepP], nxt[kSweepP];
 #pragma unroll
