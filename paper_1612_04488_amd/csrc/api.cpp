@@ -101,6 +101,8 @@ struct sis_plan {
   int n_vr = 0, n_th = 0, n_vz = 0;
   double dth = 0.0;
   double *vnode = nullptr, *wnode = nullptr, *d_vr = nullptr, *d_cth = nullptr, *d_sth = nullptr;
+  // every grid: v1, v2, v3 [3][nv] and quadrature weight [nv] of each stored velocity
+  double *vtab = nullptr, *wtab = nullptr;
   double cU = 0, cq = 0;        // U3, q3 of 2 v3 feq
   std::vector<double> h_v1d, h_feq, h_nu;
   // scratch of eager compute calls (a solver state owns its own, fixed at creation,
@@ -114,7 +116,7 @@ struct sis_plan {
     for (auto& e : events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     dfree(op); dfree(op32); dfree(ophi); dfree(oplo);
     dfree(v1d); dfree(feq); dfree(nu); dfree(Kc); dfree(gram_inv);
-    dfree(vnode); dfree(wnode); dfree(d_vr); dfree(d_cth); dfree(d_sth);
+    dfree(vnode); dfree(wnode); dfree(d_vr); dfree(d_cth); dfree(d_sth); dfree(vtab); dfree(wtab);
   }
 };
 
@@ -386,12 +388,7 @@ sis::FinishArgs finish_args(const sis_plan* p, int64_t n_cells, const double* h,
                             double* amom, const int32_t* cell_active, int anchor_mode, double* xref,
                             double* accref) {
   sis::FinishArgs f{};
-  f.n = p->n;
   f.n3 = p->nv;
-  f.d2 = p->d2;
-  f.d3 = p->d3;
-  f.v2d = p->v1d + (p->n - p->d2);
-  f.v3d = p->v1d + (p->n - p->d3);
   f.even_v2 = p->parity == 2;
   f.nsp = p->nsp;
   f.mass_ratio[0] = p->mass_ratio[0];
@@ -402,14 +399,12 @@ sis::FinishArgs finish_args(const sis_plan* p, int64_t n_cells, const double* h,
   f.delta = delta;
   f.flow = flow;
   f.project = project;
-  f.v1d = p->v1d;
-  f.vnode = p->vnode;
-  f.wnode = p->wnode;
+  f.vtab = p->vtab;
+  f.wtab = p->wtab;
   f.feq = p->feq;
   f.nu = p->nu;
   f.Kc = p->Kc;
   f.gram_inv = p->gram_inv;
-  f.w = p->wr;
   f.active = cell_active;
   f.anchor_mode = anchor_mode;
   f.accref = accref;
@@ -1153,6 +1148,29 @@ void set_layout(sis_plan* p, int parity) {
   p->wr = p->w * (parity == 2 ? 4.0 : parity == 1 ? 2.0 : 1.0);
 }
 
+// Per-velocity tables of a Cartesian plan in its stored layout: the components of each stored
+// velocity and its weight (the images of the unstored half spaces included).
+sis_status build_velocity_tables(sis_plan* p, hipStream_t stream) {
+  const int n = p->n, d2 = p->d2, d3 = p->d3;
+  const size_t nv = static_cast<size_t>(p->nv);
+  std::vector<double> vt(3 * nv), wt(nv, p->wr);
+  for (int j1 = 0; j1 < n; ++j1)
+    for (int j2 = 0; j2 < d2; ++j2)
+      for (int j3 = 0; j3 < d3; ++j3) {
+        const size_t v = (static_cast<size_t>(j1) * d2 + j2) * d3 + j3;
+        vt[v] = p->h_v1d[j1];
+        vt[nv + v] = p->h_v1d[j2 + (n - d2)];
+        vt[2 * nv + v] = p->h_v1d[j3 + (n - d3)];
+      }
+  dfree(p->vtab);
+  dfree(p->wtab);
+  p->vtab = p->wtab = nullptr;
+  HIP_TRY(upload(&p->vtab, vt, stream));
+  HIP_TRY(upload(&p->wtab, wt, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return SIS_OK;
+}
+
 // Full-grid [species][n^3] array -> stored [species][nv] (v2, v3 of the upper halves).
 std::vector<double> restrict_rows(const sis_plan* p, const double* full, int rows) {
   const int n = p->n, n3 = n * n * n;
@@ -1309,6 +1327,11 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
   MIX_TRY(hipStreamSynchronize(stream));
   set_layout(p, desc->parity);
   if (sis_status st = apply_parity(p, stream)) {
+    cleanup();
+    delete p;
+    return st;
+  }
+  if (sis_status st = build_velocity_tables(p, stream)) {
     cleanup();
     delete p;
     return st;
@@ -1488,6 +1511,8 @@ sis_status create_polar_plan(const sis_velocity_desc* desc, hipStream_t stream, 
   } while (0)
   POL_TRY(upload(&p->vnode, t.vnode, stream));
   POL_TRY(upload(&p->wnode, wn, stream));
+  POL_TRY(upload(&p->vtab, t.vnode, stream));
+  POL_TRY(upload(&p->wtab, wn, stream));
   POL_TRY(upload(&p->feq, t.feq, stream));
   POL_TRY(upload(&p->d_vr, t.vr, stream));
   POL_TRY(upload(&p->d_cth, cth, stream));
@@ -1704,6 +1729,11 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   PLAN_TRY(hipStreamSynchronize(stream));
   set_layout(p, desc->parity);
   if (sis_status st = apply_parity(p, stream)) {
+    cleanup();
+    delete p;
+    return st;
+  }
+  if (sis_status st = build_velocity_tables(p, stream)) {
     cleanup();
     delete p;
     return st;

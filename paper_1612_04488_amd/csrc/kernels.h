@@ -59,31 +59,24 @@ int gemm_k_per_split(int K, int splits);
 // velocities (v1, v2, v3) on n x d2 x d3 nodes (v1d, v2d, v3d): the full grid, or v3 > 0 (and
 // v2 > 0) when the distribution is stored by parity; w then carries the image count.
 struct FinishArgs {
-  int n, n3;
-  int d2, d3;
-  const double* v2d;
-  const double* v3d;
+  int n3;                  // stored velocities per (cell, species) row
   int even_v2;             // h stored for v2 > 0 only: the v2 v3 moments are zero
   int nsp;                 // species per cell (1 or 2)
   double mass_ratio[2];    // m_s / m_A (1 for one gas)
   int64_t n_cells;         // rows = cells * nsp
-  int splits;
+  int splits;              // split-K partial sums in acc (0: the contraction is zero)
   const double* acc;       // [splits][rows][n3]
   const double* h;         // [rows][n3]
   const double* dU;        // [rows] or null
   const double* delta;     // [cells]
   const int32_t* flow;     // [cells] or null
   int project;             // one gas only
-  const double* v1d;       // [n]
+  const double* vtab;      // [3][n3] v1, v2, v3 of each stored velocity
+  const double* wtab;      // [n3] its quadrature weight (images of unstored half spaces included)
   const double* feq;       // [nsp][n3]
   const double* nu;        // [nsp][n3]
   const double* Kc;        // [nsp][nsp][n3]: L+_1 of the correction 2 (m_q/m_A) v3 f_q of species q
   const double* gram_inv;  // [25]
-  double w;
-  // polar velocity grid: per-node velocity components [3][n3] and weights [n3] (mirror
-  // images included); null for the Cartesian grids (v1d/v2d/v3d and w)
-  const double* vnode;
-  const double* wnode;
   const int32_t* active;   // [cells] or null: skip cells with active == 0
   // FP64-anchored defect correction (solver only; mode 0 = off):
   //  mode 1 (refresh):     acc is op*h in FP64; store accref = acc, xref = h

@@ -654,95 +654,161 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
   const int nsp = a.nsp, sp = static_cast<int>(c % nsp);
   const int64_t cell = c / nsp;
   if (a.active && !a.active[cell]) return;
-  const int n = a.n, n3 = a.n3, nn = n * n;
+  const int n3 = a.n3;
   const double del = a.delta[cell];
   const int fl = a.flow ? a.flow[cell] : 0;
   const double dUc = a.dU ? a.dU[c] : 0.0;
+  const double dUq0 = a.dU ? a.dU[cell * nsp] : 0.0;
+  const double dUq1 = (a.dU && nsp > 1) ? a.dU[cell * nsp + 1] : 0.0;
   const double ms = a.mass_ratio[sp];
   const double* feq = a.feq + static_cast<int64_t>(sp) * n3;
   const double* nu = a.nu + static_cast<int64_t>(sp) * n3;
+  // L+ of the correction shapes of species 0 and 1 seen by species sp
+  const double* kc0 = a.Kc + static_cast<int64_t>(sp) * n3;
+  const double* kc1 = a.Kc + static_cast<int64_t>(nsp + sp) * n3;
+  const double* vt1 = a.vtab;
+  const double* vt2 = a.vtab + n3;
+  const double* vt3 = a.vtab + 2 * static_cast<int64_t>(n3);
   const int64_t base = c * n3;
   const int64_t sstride = a.n_cells * static_cast<int64_t>(n3);
   double m[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) m[k] = 0.0;
-  const int d2 = a.d2, d3 = a.d3, d23 = d2 * d3;
-  // four unknowns per lane and pass: the loads of all four (partials, h, anchor) are
-  // issued before any store (with one split the partial sum is the output row itself)
+  // one unknown: s = L+ h (partial sums and anchor), hv = h; returns the right side and L h
+  auto unknown = [&](double s, double hv, double v1, double v2, double v3, double wv, double f, double nuv,
+                     double k0, double k1, double& r, double& L) {
+    const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
+    // L+ of the corrected iterate: the correction of every species of the cell enters
+    double lp = s;
+    if (a.dU) {
+      lp += dUq0 * k0;
+      if (nsp > 1) lp += dUq1 * k1;
+    }
+    const double hk = hv + dUc * 2.0 * ms * v3 * f;
+    L = del * (lp - nuv * hk);
+    double S = 0.0;
+    if (fl == 1) S = v3 * f;
+    else if (fl == 2 && nsp == 1) S = v3 * (vsq - 2.5) * f;
+    r = del * lp + S;
+    const double wL = wv * L;
+    m[0] += wL;
+    m[1] += wL * v1;
+    m[2] += wL * v2;
+    m[3] += wL * v3;
+    m[4] += wL * vsq;
+    m[5] += 2.0 * wv * v1 * v3 * L;
+    m[6] += 2.0 * wv * v1 * v3 * hk;
+    m[7] += 2.0 * wv * v2 * v3 * L;
+    m[8] += 2.0 * wv * v2 * v3 * hk;
+  };
+  // U pairs (or unknowns) per lane and pass: the loads of all of them (partials, h, anchor) are
+  // issued before any store (with one split the partial sum is the output row itself).  Rows
+  // of even length are read and written in 16-byte pairs: the kernel is bound by its count of
+  // vector-memory instructions.
   constexpr int U = 4;
   const int bs = blockDim.x;
-  for (int v0 = threadIdx.x; v0 < n3; v0 += U * bs) {
-    double sv[U], hv[U];
+  if ((n3 & 1) == 0) {
+    constexpr int UP = U / 2;      // pairs per lane and pass
+    const int np = n3 >> 1;
+    auto d2p = [](const double* ptr) { return reinterpret_cast<const double2*>(ptr); };
+    for (int p0 = threadIdx.x; p0 < np; p0 += UP * bs) {
+      double2 sv[UP], hv[UP];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      sv[u] = 0.0;
-      hv[u] = v0 + u * bs < n3 ? a.h[base + v0 + u * bs] : 0.0;
-    }
-    // split-K partials four at a time (all sixteen loads in flight), summed in split order
-    for (int z0 = 0; z0 < a.splits; z0 += 4) {
-      double t[4][U];
+      for (int u = 0; u < UP; ++u) {
+        sv[u] = make_double2(0.0, 0.0);
+        hv[u] = p0 + u * bs < np ? d2p(a.h + base)[p0 + u * bs] : make_double2(0.0, 0.0);
+      }
+      // split-K partials four at a time, summed in split order
+      for (int z0 = 0; z0 < a.splits; z0 += 4) {
+        double2 t[4][UP];
 #pragma unroll
-      for (int dz = 0; dz < 4; ++dz)
+        for (int dz = 0; dz < 4; ++dz)
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int v = v0 + u * bs;
-          t[dz][u] = (z0 + dz < a.splits && v < n3) ? a.acc[(z0 + dz) * sstride + base + v] : 0.0;
+          for (int u = 0; u < UP; ++u) {
+            const int pp = p0 + u * bs;
+            t[dz][u] = (z0 + dz < a.splits && pp < np) ? d2p(a.acc + (z0 + dz) * sstride + base)[pp]
+                                                       : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+        for (int dz = 0; dz < 4; ++dz)
+#pragma unroll
+          for (int u = 0; u < UP; ++u)
+            if (z0 + dz < a.splits) {
+              sv[u].x += t[dz][u].x;
+              sv[u].y += t[dz][u].y;
+            }
+      }
+      if (a.anchor_mode == 2)
+#pragma unroll
+        for (int u = 0; u < UP; ++u)
+          if (p0 + u * bs < np) {
+            const double2 r = d2p(a.accref + base)[p0 + u * bs];
+            sv[u].x += r.x;
+            sv[u].y += r.y;
+          }
+#pragma unroll
+      for (int u = 0; u < UP; ++u) {
+        const int pp = p0 + u * bs;
+        if (pp >= np) break;
+        const double2 V1 = d2p(vt1)[pp], V2 = d2p(vt2)[pp], V3 = d2p(vt3)[pp], W = d2p(a.wtab)[pp];
+        const double2 F = d2p(feq)[pp], NU = d2p(nu)[pp];
+        double2 K0 = make_double2(0.0, 0.0), K1 = make_double2(0.0, 0.0);
+        if (a.dU) {
+          K0 = d2p(kc0)[pp];
+          if (nsp > 1) K1 = d2p(kc1)[pp];
         }
+        if (a.anchor_mode == 1) {
+          reinterpret_cast<double2*>(a.accref + base)[pp] = sv[u];
+          reinterpret_cast<double2*>(a.xref + base)[pp] = hv[u];
+        }
+        double2 R, L;
+        unknown(sv[u].x, hv[u].x, V1.x, V2.x, V3.x, W.x, F.x, NU.x, K0.x, K1.x, R.x, L.x);
+        unknown(sv[u].y, hv[u].y, V1.y, V2.y, V3.y, W.y, F.y, NU.y, K0.y, K1.y, R.y, L.y);
+        reinterpret_cast<double2*>(a.rhs + base)[pp] = R;
+        if (a.lh) reinterpret_cast<double2*>(a.lh + base)[pp] = L;
+      }
+    }
+  } else {
+    for (int v0 = threadIdx.x; v0 < n3; v0 += U * bs) {
+      double sv[U], hv[U];
 #pragma unroll
-      for (int dz = 0; dz < 4; ++dz)
+      for (int u = 0; u < U; ++u) {
+        sv[u] = 0.0;
+        hv[u] = v0 + u * bs < n3 ? a.h[base + v0 + u * bs] : 0.0;
+      }
+      for (int z0 = 0; z0 < a.splits; z0 += 4) {
+        double t[4][U];
+#pragma unroll
+        for (int dz = 0; dz < 4; ++dz)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * bs;
+            t[dz][u] = (z0 + dz < a.splits && v < n3) ? a.acc[(z0 + dz) * sstride + base + v] : 0.0;
+          }
+#pragma unroll
+        for (int dz = 0; dz < 4; ++dz)
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (z0 + dz < a.splits) sv[u] += t[dz][u];
+      }
+      if (a.anchor_mode == 2)
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (z0 + dz < a.splits) sv[u] += t[dz][u];
-    }
-    if (a.anchor_mode == 2)
+          if (v0 + u * bs < n3) sv[u] += a.accref[base + v0 + u * bs];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (v0 + u * bs < n3) sv[u] += a.accref[base + v0 + u * bs];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int v = v0 + u * bs;
-      if (v >= n3) break;
-      double v1, v2, v3, wv;
-      if (a.vnode) {
-        v1 = a.vnode[v];
-        v2 = a.vnode[n3 + v];
-        v3 = a.vnode[2 * n3 + v];
-        wv = a.wnode[v];
-      } else {
-        const int j1 = v / d23, j2 = (v / d3) % d2, j3 = v % d3;
-        v1 = a.v1d[j1];
-        v2 = a.v2d[j2];
-        v3 = a.v3d[j3];
-        wv = a.w;
+      for (int u = 0; u < U; ++u) {
+        const int v = v0 + u * bs;
+        if (v >= n3) break;
+        if (a.anchor_mode == 1) {
+          a.accref[base + v] = sv[u];
+          a.xref[base + v] = hv[u];
+        }
+        double r, L;
+        unknown(sv[u], hv[u], vt1[v], vt2[v], vt3[v], a.wtab[v], feq[v], nu[v], a.dU ? kc0[v] : 0.0,
+                (a.dU && nsp > 1) ? kc1[v] : 0.0, r, L);
+        a.rhs[base + v] = r;
+        if (a.lh) a.lh[base + v] = L;
       }
-      const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
-      const double f = feq[v];
-      const double s = sv[u];
-      if (a.anchor_mode == 1) {
-        a.accref[base + v] = s;
-        a.xref[base + v] = hv[u];
-      }
-      // L+ of the corrected iterate: the correction of every species of the cell enters
-      double lp = s;
-      if (a.dU)
-        for (int q = 0; q < nsp; ++q) lp += a.dU[cell * nsp + q] * a.Kc[(static_cast<int64_t>(q) * nsp + sp) * n3 + v];
-      const double hk = hv[u] + dUc * 2.0 * ms * v3 * f;
-      const double L = del * (lp - nu[v] * hk);
-      double S = 0.0;
-      if (fl == 1) S = v3 * f;
-      else if (fl == 2 && nsp == 1) S = v3 * (vsq - 2.5) * f;
-      a.rhs[base + v] = del * lp + S;
-      if (a.lh) a.lh[base + v] = L;
-      const double wL = wv * L;
-      m[0] += wL;
-      m[1] += wL * v1;
-      m[2] += wL * v2;
-      m[3] += wL * v3;
-      m[4] += wL * vsq;
-      m[5] += 2.0 * wv * v1 * v3 * L;
-      m[6] += 2.0 * wv * v1 * v3 * hk;
-      m[7] += 2.0 * wv * v2 * v3 * L;
-      m[8] += 2.0 * wv * v2 * v3 * hk;
     }
   }
   block_sum<9>(m, sh);
@@ -754,8 +820,7 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
     }
     __syncthreads();
     for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-      const int j1 = v / d23, j2 = (v / d3) % d2, j3 = v % d3;
-      const double v1 = a.v1d[j1], v2 = a.v2d[j2], v3 = a.v3d[j3];
+      const double v1 = vt1[v], v2 = vt2[v], v3 = vt3[v];
       const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
       const double corr = feq[v] * (coef[0] + coef[1] * v1 + coef[2] * v2 + coef[3] * v3 + coef[4] * vsq);
       a.rhs[base + v] -= corr;
