@@ -539,8 +539,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.max_diag = g->max_diag;
     HIP_TRY(sis::launch_sweep2d(a, s));
     if (mom)
-      HIP_TRY(sis::launch_moments2d(p->n, p->d3, p->nsp, p->mass_ratio, g->n_cells, p->v1d, p->v1d + (p->n - p->d3), h, p->wr, cell_active,
-                                    mom, s));
+      HIP_TRY(sis::launch_moments2d(p->nv, p->nsp, p->mass_ratio, g->n_cells, p->vtab, h, p->wr, cell_active, mom, s));
     return SIS_OK;
   }
   sis::SweepArgs a{};
@@ -560,8 +559,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
   a.case_active = case_active;
   HIP_TRY(sis::launch_sweep1d(a, s));
   if (mom)
-    HIP_TRY(sis::launch_moments(p->n, p->d2, p->d3, p->nsp, p->mass_ratio, g->n_cells * p->nsp, p->v1d,
-                                p->v1d + (p->n - p->d2), p->v1d + (p->n - p->d3), h, p->wr, mom, s));
+    HIP_TRY(sis::launch_moments(p->nv, p->nsp, p->mass_ratio, g->n_cells * p->nsp, p->vtab, h, p->wr, mom, s));
   return SIS_OK;
 }
 
@@ -2013,8 +2011,7 @@ sis_status sis_moments(sis_plan_t p, int64_t n_cells, const double* h, double* m
     HIP_TRY(sis::launch_moments_tube(n_cells, p->nv, p->vnode, p->wnode, h, nullptr, mom_out, stream));
     return SIS_OK;
   }
-  HIP_TRY(sis::launch_moments(p->n, p->d2, p->d3, p->nsp, p->mass_ratio, n_cells * p->nsp, p->v1d,
-                              p->v1d + (p->n - p->d2), p->v1d + (p->n - p->d3), h, p->wr, mom_out, stream));
+  HIP_TRY(sis::launch_moments(p->nv, p->nsp, p->mass_ratio, n_cells * p->nsp, p->vtab, h, p->wr, mom_out, stream));
   return SIS_OK;
 }
 

@@ -107,9 +107,8 @@ struct SweepArgs {
 hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s);
 // mom[row][4] = {U3, q3, G1, P13} of h[row][n x d2 x d3] directly (rows = cells * nsp;
 // q3 and P13 weighted with the mass ratio of the row's species)
-hipError_t launch_moments(int n, int d2, int d3, int nsp, const double* mass_ratio, int64_t n_rows,
-                          const double* v1d, const double* v2d, const double* v3d, const double* h, double w,
-                          double* mom, hipStream_t s);
+hipError_t launch_moments(int n3, int nsp, const double* mass_ratio, int64_t n_rows, const double* vtab,
+                          const double* h, double w, double* mom, hipStream_t s);
 
 struct DiffusionArgs {
   int n_cases;
@@ -166,9 +165,8 @@ struct Sweep2DArgs {
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s);
 // mom[cell][species][8] = {U3, q3, G1, G12, G2, P13, P23, 0}; rows of n x n x d3 velocities;
 // q3 and P13, P23 carry the species mass ratio (q3 = int (a v^2 - 5/2) v3 h, P = 2 a int v v3 h)
-hipError_t launch_moments2d(int n, int d3, int nsp, const double* mass_ratio, int64_t n_cells, const double* v1d,
-                            const double* v3d, const double* h, double w, const int32_t* cell_active, double* mom,
-                            hipStream_t s);
+hipError_t launch_moments2d(int n3, int nsp, const double* mass_ratio, int64_t n_cells, const double* vtab,
+                            const double* h, double w, const int32_t* cell_active, double* mom, hipStream_t s);
 
 struct Diff2DArgs {
   int n_cases;

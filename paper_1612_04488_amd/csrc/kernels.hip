@@ -950,27 +950,46 @@ __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
   }
 }
 
-__global__ __launch_bounds__(256) void moments_kernel(int n, int d2, int d3, int nsp, double ms0, double ms1,
-                                                      const double* __restrict__ v1d,
-                                                      const double* __restrict__ v2d,
-                                                      const double* __restrict__ v3d,
+// Calls f(v1, v2, v3, h) for every unknown of row `row` (n3 values): in 16-byte pairs for
+// rows of even length (the moment kernels are bound by their count of memory instructions).
+template <typename F>
+__device__ inline void for_row(int n3, const double* __restrict__ vtab, const double* __restrict__ h, int64_t row,
+                               F&& f) {
+  const double* hr = h + row * n3;
+  if ((n3 & 1) == 0) {
+    const int np = n3 >> 1;
+    const double2* h2 = reinterpret_cast<const double2*>(hr);
+    const double2* a1 = reinterpret_cast<const double2*>(vtab);
+    const double2* a2 = reinterpret_cast<const double2*>(vtab + n3);
+    const double2* a3 = reinterpret_cast<const double2*>(vtab + 2 * static_cast<int64_t>(n3));
+#pragma unroll 2
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+      const double2 x = h2[p], v1 = a1[p], v2 = a2[p], v3 = a3[p];
+      f(v1.x, v2.x, v3.x, x.x);
+      f(v1.y, v2.y, v3.y, x.y);
+    }
+  } else {
+    for (int v = threadIdx.x; v < n3; v += blockDim.x)
+      f(vtab[v], vtab[n3 + v], vtab[2 * static_cast<int64_t>(n3) + v], hr[v]);
+  }
+}
+
+__global__ __launch_bounds__(256) void moments_kernel(int n3, int nsp, double ms0, double ms1,
+                                                      const double* __restrict__ vtab,
                                                       const double* __restrict__ h, double w,
                                                       double* __restrict__ mom) {
   __shared__ double sh[4 * 4];
   const int64_t c = blockIdx.x;  // (cell, species) row
   const double ms = (c % nsp) == 0 ? ms0 : ms1;
-  const int d23 = d2 * d3, n3 = n * d23;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-    const double v1 = v1d[v / d23], v2 = v2d[(v / d3) % d2], v3 = v3d[v % d3];
+  for_row(n3, vtab, h, c, [&](double v1, double v2, double v3, double hv) {
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
-    const double x = w * h[c * n3 + v];
+    const double x = w * hv;
     m[0] += v3 * x;
     m[1] += (ms * vsq - 2.5) * v3 * x;
     m[2] += v3 * (2.0 * v1 * v1 - 1.0) * x;
     m[3] += 2.0 * ms * v1 * v3 * x;
-  }
+  });
   block_sum<4>(m, sh);
   if (threadIdx.x == 0)
     for (int k = 0; k < 4; ++k) mom[c * 4 + k] = m[k];
@@ -1397,9 +1416,8 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2
 
 // Per (cell, species) row: U3, q3 = int (a v^2 - 5/2) v3 h, G1, G12, G2, P13 = 2a int v1 v3 h,
 // P23 = 2a int v2 v3 h (a = m_s / m_A; 1 for one gas).
-__global__ __launch_bounds__(256) void moments2d_kernel(int n, int d3, int nsp, double ms0, double ms1,
-                                                        const double* __restrict__ v1d,
-                                                        const double* __restrict__ v3d,
+__global__ __launch_bounds__(256) void moments2d_kernel(int n3, int nsp, double ms0, double ms1,
+                                                        const double* __restrict__ vtab,
                                                         const double* __restrict__ h, double w,
                                                         const int32_t* __restrict__ active,
                                                         double* __restrict__ mom) {
@@ -1407,12 +1425,10 @@ __global__ __launch_bounds__(256) void moments2d_kernel(int n, int d3, int nsp, 
   const int64_t c = blockIdx.x;
   if (active && !active[c / nsp]) return;
   const double ms = (c % nsp) == 0 ? ms0 : ms1;
-  const int nd3 = n * d3, n3 = n * nd3;
   double m[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int v = threadIdx.x; v < n3; v += blockDim.x) {
-    const double v1 = v1d[v / nd3], v2 = v1d[(v / d3) % n], v3 = v3d[v % d3];
+  for_row(n3, vtab, h, c, [&](double v1, double v2, double v3, double hv) {
     const double vsq = v1 * v1 + v2 * v2 + v3 * v3;
-    const double x = w * h[c * n3 + v];
+    const double x = w * hv;
     m[0] += v3 * x;
     m[1] += (ms * vsq - 2.5) * v3 * x;
     m[2] += v3 * (2.0 * v1 * v1 - 1.0) * x;
@@ -1420,7 +1436,7 @@ __global__ __launch_bounds__(256) void moments2d_kernel(int n, int d3, int nsp, 
     m[4] += v3 * (2.0 * v2 * v2 - 1.0) * x;
     m[5] += 2.0 * ms * v1 * v3 * x;
     m[6] += 2.0 * ms * v2 * v3 * x;
-  }
+  });
   block_sum<7>(m, sh);
   if (threadIdx.x == 0) {
     for (int k = 0; k < 7; ++k) mom[c * 8 + k] = m[k];
@@ -2207,12 +2223,11 @@ hipError_t launch_sweep1d(const SweepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_moments(int n, int d2, int d3, int nsp, const double* mass_ratio, int64_t n_rows,
-                          const double* v1d, const double* v2d, const double* v3d, const double* h, double w,
-                          double* mom, hipStream_t s) {
+hipError_t launch_moments(int n3, int nsp, const double* mass_ratio, int64_t n_rows, const double* vtab,
+                          const double* h, double w, double* mom, hipStream_t s) {
   const double m0 = mass_ratio ? mass_ratio[0] : 1.0, m1 = mass_ratio && nsp > 1 ? mass_ratio[1] : 1.0;
-  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>(n_rows)), dim3(256), 0, s, n, d2, d3, nsp, m0, m1,
-                     v1d, v2d, v3d, h, w, mom);
+  hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>(n_rows)), dim3(256), 0, s, n3, nsp, m0, m1, vtab, h,
+                     w, mom);
   return hipGetLastError();
 }
 
@@ -2242,11 +2257,10 @@ hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_moments2d(int n, int d3, int nsp, const double* mass_ratio, int64_t n_cells, const double* v1d,
-                            const double* v3d, const double* h, double w, const int32_t* cell_active, double* mom,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(moments2d_kernel, dim3(static_cast<unsigned>(n_cells * nsp)), dim3(256), 0, s, n, d3, nsp,
-                     mass_ratio[0], nsp > 1 ? mass_ratio[1] : 1.0, v1d, v3d, h, w, cell_active, mom);
+hipError_t launch_moments2d(int n3, int nsp, const double* mass_ratio, int64_t n_cells, const double* vtab,
+                            const double* h, double w, const int32_t* cell_active, double* mom, hipStream_t s) {
+  hipLaunchKernelGGL(moments2d_kernel, dim3(static_cast<unsigned>(n_cells * nsp)), dim3(256), 0, s, n3, nsp,
+                     mass_ratio[0], nsp > 1 ? mass_ratio[1] : 1.0, vtab, h, w, cell_active, mom);
   return hipGetLastError();
 }
 
