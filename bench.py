@@ -41,11 +41,13 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 # configuration without a recorded pass reports null.  Sources:
 # profiles/gemm_f64_planar-hs-32v-808cells-parity.md, profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md.
 TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (1116445.9 * 2.0, 155136.0),
+               ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (1546552.0 * 2.0, 206848.0),
                ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (42415887.6 * 2.0, 1327104.0)}
 # MFMA pipe utilisation of the same configuration from its counter pass:
 # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), and the shader clock
 # the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
 MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22),
+             ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (0.788, 2.09),
              ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.801, 2.35)}
 HBM_GBS = 8000.0
 
