@@ -141,8 +141,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is "
-                                   "described in DESIGN.md but not implemented",
+        print(json.dumps({"error": "the benchmark runs on exactly one GPU; sharding the cases over "
+                                   "several GPUs is not implemented",
                           "n_gpus": args.gpus}))
         return 2
 
