@@ -45,7 +45,7 @@ enum {
   SIS_E_OOM = -4,           /* device or host allocation failed               */
   SIS_E_NOT_CONVERGED = -5, /* sis_solve hit max_it; results are still filled */
   SIS_E_NUMERIC = -6,       /* NaN/Inf detected in a flow rate                */
-  SIS_E_UNSUPPORTED = -7    /* valid request this build does not implement    */
+  SIS_E_UNSUPPORTED = -7    /* valid request the library does not implement   */
 };
 
 /* Collision kernels: B = b0 |u|^alpha sin^(alpha+gamma-1)(theta/2) cos^-gamma(theta/2)
