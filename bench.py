@@ -34,7 +34,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s of L(h) + time-to-residual 1e-8, mixed SIS vs FP64 plain"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}
 # HBM bytes per contraction launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (scaled by a 1 GiB copy: FETCH x2.0, WRITE x1.0), recorded for the kernel as it
 # stands, keyed by (workload, parity, precision, tile rows, split-K, k-stage); a launch
@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16"])
     ap.add_argument("--workload", default="batch",
                     choices=["batch", "small", "duct", "porous", "mixture", "mixture-duct", "sierpinski", "tube"])
     ap.add_argument("--diffusion", default="inverse", choices=["inverse", "cg"],
@@ -298,6 +298,10 @@ def main():
         runs = [(r.split("+")[0], r.endswith("+projection")) for r in args.ttr.split(",") if r]
         if mix or tube:
             runs = [(prec, proj) for prec, proj in runs if not proj]
+        if mix:
+            # one bf16 product is too coarse for the species blocks of the mixture operator
+            # (heat flux off by 1e-3 against FP64); the mixture runs FP32 and 3xBF16 only
+            runs = [(prec, proj) for prec, proj in runs if prec != "bf16"]
         for prec, proj in runs:
             plan.set_precision(prec)
             r = sis.solve(plan, geom, scheme="SIS", N=Npen, eps=1e-8, max_it=400, project=proj,
@@ -335,7 +339,7 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[args.precision],
+           "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16": "bf16+f64"}[args.precision],
            "data": "synthetic",
            "config": {"workload": w["name"], "kernel": w["kernel"], "n_v": w["n_v"], "l_v": w["l_v"],
                       "n_pad": w["n_pad"],

@@ -52,8 +52,14 @@ enum {
  * (sigma representation, deflection angle theta), b0 set by the first
  * Chapman-Enskog viscosity so that delta = p0 l / (mu v_m).                */
 enum { SIS_KERNEL_HARD_SPHERE = 0, SIS_KERNEL_IPL = 1 };
-/* Arithmetic of the collision contraction (everything else is FP64).       */
-enum { SIS_PREC_FP64 = 0, SIS_PREC_FP32 = 1, SIS_PREC_BF16X3 = 2 };
+/* Arithmetic of the collision contraction (everything else is FP64).
+ * BF16X3: both operands split into bf16 hi + lo, products hi*hi + hi*lo +
+ * lo*hi, FP32 accumulation.  BF16: the hi*hi product alone (about 3 decimal
+ * digits); meant for sis_solve with FP64 anchors (refresh_every), where the
+ * low-precision contraction only acts on the change since the last anchor
+ * (one gas: flow rates within ~1e-6 of FP64; for mixtures the heat flux
+ * deviates by ~1e-3, use BF16X3).                                           */
+enum { SIS_PREC_FP64 = 0, SIS_PREC_FP32 = 1, SIS_PREC_BF16X3 = 2, SIS_PREC_BF16 = 3 };
 /* Source terms S of Sec. 2 with X_P = X_T = -1.                             */
 enum { SIS_FLOW_NONE = 0, SIS_FLOW_POISEUILLE = 1, SIS_FLOW_TRANSPIRATION = 2 };
 enum { SIS_SCHEME_CIS = 0, SIS_SCHEME_SIS = 1 };

@@ -296,6 +296,11 @@ sis_status prepare_lowp_operand(sis_plan* p, int precision, int64_t n_cells, con
     HIP_TRY(sis::launch_split_x(h, xref, cnt, hx, hx + cnt, s));
     g.Xh = hx;
     g.Xl = hx + cnt;
+  } else if (precision == SIS_PREC_BF16) {
+    uint16_t* hx = static_cast<uint16_t*>(ws_x->p);
+    HIP_TRY(sis::launch_split_x(h, xref, cnt, hx, nullptr, s));
+    g.Xh = hx;
+    g.Xl = nullptr;
   } else {
     float* fx = static_cast<float*>(ws_x->p);
     HIP_TRY(sis::launch_convert_x_f32(h, xref, cnt, fx, s));
@@ -1816,8 +1821,8 @@ sis_status sis_plan_set_precision(sis_plan_t p, int32_t precision, hipStream_t s
       HIP_TRY(sis::launch_convert_f32(p->op, p->op32, cnt, stream));
       HIP_TRY(hipStreamSynchronize(stream));
     }
-  } else if (precision == SIS_PREC_BF16X3) {
-    if (p->ndof % 8) return fail(SIS_E_UNSUPPORTED, "BF16X3 needs the unknowns per cell divisible by 8");
+  } else if (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) {
+    if (p->ndof % 8) return fail(SIS_E_UNSUPPORTED, "the BF16 contractions need the unknowns per cell divisible by 8");
     if (!p->ophi) {
       HIP_TRY(dmalloc(&p->ophi, cnt));
       HIP_TRY(dmalloc(&p->oplo, cnt));
@@ -2371,7 +2376,7 @@ sis_status sis_solve(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o, sis_so
 sis_status sis_plan_set_contraction_config(sis_plan_t p, int64_t n_cells, int32_t precision, int32_t tile_rows,
                                            int32_t k_stage, int32_t splits) {
   if (sis_status st = check_plan(p)) return st;
-  if (precision < SIS_PREC_FP64 || precision > SIS_PREC_BF16X3) return fail(SIS_E_INVALID, "unknown precision");
+  if (precision < SIS_PREC_FP64 || precision > SIS_PREC_BF16) return fail(SIS_E_INVALID, "unknown precision");
   if (splits < 1 || splits > 8) return fail(SIS_E_INVALID, "splits must be in [1, 8]");
   int tile = -1;
   if (k_stage == 16) tile = tile_rows == 128 ? 0 : tile_rows == 64 ? 2 : tile_rows == 32 ? 1 : -1;

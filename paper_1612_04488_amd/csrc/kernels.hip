@@ -469,7 +469,8 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
 // registers while the current one feeds the MFMAs.
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-template <int BM, int BN, int WM, int WN>
+// NPROD = 1: the hi*hi product alone (lo arrays unused, neither loaded nor staged).
+template <int BM, int BN, int WM, int WN, int NPROD = 3>
 __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __restrict__ Xh,
                                                           const uint16_t* __restrict__ Xl,
                                                           const uint16_t* __restrict__ Oh,
@@ -486,8 +487,8 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
   // rows hold the 64 k-values of one m (or n) contiguously (+16 B pad); a lane
   // reads its 8 consecutive k values as one 16-byte vector
   constexpr int RS = BK + 8;
-  __shared__ uint16_t sA[2][BM][RS];
-  __shared__ uint16_t sB[2][BN][RS];
+  __shared__ uint16_t sA[NPROD == 3 ? 2 : 1][BM][RS];
+  __shared__ uint16_t sB[NPROD == 3 ? 2 : 1][BN][RS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
@@ -516,7 +517,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
         if (q < BM * CH) {
           const int64_t off = (m0 + q / CH) * K + k0 + (q % CH) * 8;
           ra[0][i] = *reinterpret_cast<const uint4*>(Xh + off);
-          ra[1][i] = *reinterpret_cast<const uint4*>(Xl + off);
+          if constexpr (NPROD == 3) ra[1][i] = *reinterpret_cast<const uint4*>(Xl + off);
         }
       }
 #pragma unroll
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
         if (q < BN * CH) {
           const int64_t off = static_cast<int64_t>(n0 + q / CH) * K + k0 + (q % CH) * 8;
           rb[0][i] = *reinterpret_cast<const uint4*>(Oh + off);
-          rb[1][i] = *reinterpret_cast<const uint4*>(Ol + off);
+          if constexpr (NPROD == 3) rb[1][i] = *reinterpret_cast<const uint4*>(Ol + off);
         }
       }
       return;
@@ -536,7 +537,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
       if (q < BM * CH) {
         const int r = q / CH, kc = (q % CH) * 8;
         ra[0][i] = load16(Xh, m0 + r, M, k0 + kc);
-        ra[1][i] = load16(Xl, m0 + r, M, k0 + kc);
+        if constexpr (NPROD == 3) ra[1][i] = load16(Xl, m0 + r, M, k0 + kc);
       }
     }
 #pragma unroll
@@ -545,7 +546,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
       if (q < BN * CH) {
         const int r = q / CH, kc = (q % CH) * 8;
         rb[0][i] = load16(Oh, n0 + r, N, k0 + kc);
-        rb[1][i] = load16(Ol, n0 + r, N, k0 + kc);
+        if constexpr (NPROD == 3) rb[1][i] = load16(Ol, n0 + r, N, k0 + kc);
       }
     }
   };
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
       if (q < BM * CH) {
         const int r = q / CH, kc = (q % CH) * 8;
         *reinterpret_cast<uint4*>(&sA[0][r][kc]) = ra[0][i];
-        *reinterpret_cast<uint4*>(&sA[1][r][kc]) = ra[1][i];
+        if constexpr (NPROD == 3) *reinterpret_cast<uint4*>(&sA[NPROD == 3 ? 1 : 0][r][kc]) = ra[1][i];
       }
     }
 #pragma unroll
@@ -565,7 +566,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
       if (q < BN * CH) {
         const int r = q / CH, kc = (q % CH) * 8;
         *reinterpret_cast<uint4*>(&sB[0][r][kc]) = rb[0][i];
-        *reinterpret_cast<uint4*>(&sB[1][r][kc]) = rb[1][i];
+        if constexpr (NPROD == 3) *reinterpret_cast<uint4*>(&sB[NPROD == 3 ? 1 : 0][r][kc]) = rb[1][i];
       }
     }
   };
@@ -593,19 +594,21 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         ah[i] = *reinterpret_cast<const v8bf*>(&sA[0][wm + i * 16 + rr][ks + kq]);
-        al[i] = *reinterpret_cast<const v8bf*>(&sA[1][wm + i * 16 + rr][ks + kq]);
+        if constexpr (NPROD == 3) al[i] = *reinterpret_cast<const v8bf*>(&sA[NPROD == 3 ? 1 : 0][wm + i * 16 + rr][ks + kq]);
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         bh[j] = *reinterpret_cast<const v8bf*>(&sB[0][wn + j * 16 + rr][ks + kq]);
-        bl[j] = *reinterpret_cast<const v8bf*>(&sB[1][wn + j * 16 + rr][ks + kq]);
+        if constexpr (NPROD == 3) bl[j] = *reinterpret_cast<const v8bf*>(&sB[NPROD == 3 ? 1 : 0][wn + j * 16 + rr][ks + kq]);
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          if constexpr (NPROD == 3) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          }
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
     }
@@ -636,7 +639,7 @@ __global__ void split_x_kernel(const double* __restrict__ X, const double* __res
   const double x = Xref ? X[i] - Xref[i] : X[i];
   const uint16_t h = bf16_rne(static_cast<float>(x));
   hi[i] = h;
-  lo[i] = bf16_rne(static_cast<float>(x - static_cast<double>(bf16_to_f32(h))));
+  if (lo) lo[i] = bf16_rne(static_cast<float>(x - static_cast<double>(bf16_to_f32(h))));
 }
 
 __global__ void convert_x_f32_kernel(const double* __restrict__ X, const double* __restrict__ Xref, int64_t count,
@@ -2199,6 +2202,14 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
       hipLaunchKernelGGL((gemm_f32_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
     else
       hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
+  } else if (g.precision == 3) {
+    if (!g.Xh) return hipErrorInvalidValue;
+    if (g.tile == 0)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64, 1>), grid, dim3(256), 0, s, g.Xh, g.Xh, g.ophi, g.ophi, g.acc, g.M, g.N, g.K, kps);
+    else if (g.tile == 2)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64, 1>), grid, dim3(256), 0, s, g.Xh, g.Xh, g.ophi, g.ophi, g.acc, g.M, g.N, g.K, kps);
+    else
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32, 1>), grid, dim3(256), 0, s, g.Xh, g.Xh, g.ophi, g.ophi, g.acc, g.M, g.N, g.K, kps);
   } else {
     if (!g.Xh || !g.Xl) return hipErrorInvalidValue;
     if (g.tile == 0)

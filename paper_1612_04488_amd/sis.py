@@ -22,8 +22,8 @@ SIS_E_UNSUPPORTED = -7
 
 KERNEL_HARD_SPHERE = 0
 KERNEL_IPL = 1
-PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3}
+PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "bf16": PREC_BF16}
 FLOW_NONE, FLOW_POISEUILLE, FLOW_TRANSPIRATION = 0, 1, 2
 SCHEME_CIS, SCHEME_SIS = 0, 1
 GEOM_PLANAR_HALF, GEOM_DUCT_QUARTER, GEOM_PERIODIC_2D, GEOM_TUBE = 0, 1, 2, 3

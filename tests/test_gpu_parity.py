@@ -221,7 +221,7 @@ def test_solve_max_it_reports_not_converged():
 
 
 # ------------------------------------------------------------------ mixed precision
-@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("bf16x3", 5e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("bf16x3", 5e-4), ("bf16", 2e-2)])
 def test_collide_mixed_precision_error_and_projection(precision, tol):
     n_v, l_v, m = 16, 6.0, 6
     say("mixed", precision)
@@ -270,6 +270,28 @@ def test_mixed_solve_with_fp64_refresh_matches_fp64(precision):
     r1 = sis.solve(p, geom, scheme="SIS", eps=1e-10, max_it=300, refresh_every=1)
     assert np.array_equal(r1["iters"], refs[False]["iters"])
     assert np.all(np.abs(r1["M"] - refs[False]["M"]) < 1e-12 * np.abs(refs[False]["M"]))
+
+
+def test_bf16_solve_with_fp64_anchors_matches_fp64():
+    """One bf16 product (hi*hi, about 3 decimal digits) with FP64 anchors
+    every 8 iterations: the low-precision contraction only acts on the change
+    since the last anchor, so one-gas flow rates land within 1e-6 of the FP64
+    solve (target 1e-5) in nearly the same number of iterations at the
+    residual 1e-8 of the benchmark (at 1e-10 the low-precision noise slows the
+    last digits: 84 instead of 56 iterations at delta = 100)."""
+    n_v, l_v, m = 16, 6.0, 6
+    p = sis.Plan(n_v, l_v, m_angle=m)
+    xs = [inputs.nodes_tanh(16)] * 4
+    deltas, flows = [1.0, 10.0, 100.0, 10.0], [1, 1, 1, 2]
+    geom = sis.Geometry(p, xs, deltas, flows)
+    ref = sis.solve(p, geom, scheme="SIS", eps=1e-8, max_it=300)
+    p.set_precision("bf16")
+    r = sis.solve(p, geom, scheme="SIS", eps=1e-8, max_it=300)
+    say("bf16", r["iters"], ref["iters"], np.max(np.abs(r["M"] / ref["M"] - 1)), np.max(np.abs(r["Q"] / ref["Q"] - 1)))
+    assert r["status"] == 0
+    assert np.all(np.abs(r["M"] - ref["M"]) < 1e-6 * np.abs(ref["M"]))
+    assert np.all(np.abs(r["Q"] - ref["Q"]) < 1e-6 * np.abs(ref["Q"]))
+    assert np.all(np.abs(r["iters"] - ref["iters"]) <= 5)
 
 
 def test_every_contraction_configuration_gives_the_same_operator_action():
