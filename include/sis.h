@@ -283,6 +283,8 @@ sis_status sis_geometry_diffusion_info(sis_geom_t geom, int32_t* n_inverse, int3
  * (and L+): L -= f_eq sum_i c_i psi_i, c = Gram^-1 m, m_i = sum w psi_i L,
  * psi in {1, v1, v2, v3, |v|^2}.
  * delta[n_cells] and flow[n_cells] (int32) are DEVICE arrays; flow may be NULL.
+ * h and rhs_out must be 16-byte aligned (the contraction reads h in 16-byte
+ * vectors; SIS_E_INVALID otherwise); lh_out may have any 8-byte alignment.
  * Arithmetic of the contraction per sis_plan_set_precision; rest FP64.
  * Mixtures: h, rhs_out, lh_out are [n_cells][2][n3], dU is [n_cells][2]
  * (correction h_a += dU_a 2 (m_a/m_A) v3 f_a; the correction of both species

@@ -710,7 +710,14 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
   // vector-memory instructions.
   constexpr int U = 4;
   const int bs = blockDim.x;
-  if ((n3 & 1) == 0) {
+  // pairs need 16-byte alignment of every row touched (caller arrays may be offset views)
+  const uintptr_t align = reinterpret_cast<uintptr_t>(a.h + base) | reinterpret_cast<uintptr_t>(a.rhs + base) |
+                          (a.lh ? reinterpret_cast<uintptr_t>(a.lh + base) : 0) |
+                          (a.splits > 0 ? reinterpret_cast<uintptr_t>(a.acc + base) |
+                                              reinterpret_cast<uintptr_t>(a.acc + sstride) : 0) |
+                          (a.anchor_mode ? reinterpret_cast<uintptr_t>(a.accref + base) |
+                                               reinterpret_cast<uintptr_t>(a.xref + base) : 0);
+  if ((n3 & 1) == 0 && (align & 15) == 0) {
     constexpr int UP = U / 2;      // pairs per lane and pass
     const int np = n3 >> 1;
     auto d2p = [](const double* ptr) { return reinterpret_cast<const double2*>(ptr); };
@@ -959,7 +966,7 @@ template <typename F>
 __device__ inline void for_row(int n3, const double* __restrict__ vtab, const double* __restrict__ h, int64_t row,
                                F&& f) {
   const double* hr = h + row * n3;
-  if ((n3 & 1) == 0) {
+  if ((n3 & 1) == 0 && (reinterpret_cast<uintptr_t>(hr) & 15) == 0) {
     const int np = n3 >> 1;
     const double2* h2 = reinterpret_cast<const double2*>(hr);
     const double2* a1 = reinterpret_cast<const double2*>(vtab);

@@ -112,6 +112,38 @@ def test_collide_empty_batch_is_noop():
     p.collide(z, torch.empty(0, dtype=torch.float64, device=DEV), torch.empty_like(z))
 
 
+def test_offset_views_rejected_or_handled():
+    """h and rhs_out must be 16-byte aligned (the contraction reads h in
+    16-byte vectors): an offset view is rejected before anything runs.  An
+    lh_out or a moments input that starts 8 bytes past a 16-byte boundary
+    takes the element-wise paths of finish_kernel and the moment kernels:
+    same results as on aligned arrays."""
+    p = gpu_plan(8, 4.0, 3)
+    nv, nc = p.n_vel, 5
+    h = dev(inputs.rough_h(8, 4.0, nc).reshape(nc, -1))
+    delta = dev(np.linspace(0.5, 3.0, nc))
+    dU = dev(np.linspace(-0.1, 0.1, nc))
+    ref, lref = torch.empty_like(h), torch.empty_like(h)
+    p.collide(h, delta, ref, dU=dU, lh_out=lref)
+    mref = torch.empty((nc, 4), dtype=torch.float64, device=DEV)
+    p.moments(h, mref)
+    hb = torch.zeros(nc * nv + 1, dtype=torch.float64, device=DEV)
+    hv = hb[1:].view(nc, nv)
+    hv.copy_(h)
+    with pytest.raises(sis.SisError):
+        p.collide(hv, delta, torch.empty_like(h), dU=dU)
+    lb = torch.zeros(nc * nv + 1, dtype=torch.float64, device=DEV)
+    lv = lb[1:].view(nc, nv)
+    out = torch.empty_like(h)
+    p.collide(h, delta, out, dU=dU, lh_out=lv)
+    mom = torch.empty((nc, 4), dtype=torch.float64, device=DEV)
+    p.moments(hv, mom)
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), ref.cpu().numpy()) < 1e-13
+    assert rel(lv.cpu().numpy(), lref.cpu().numpy()) < 1e-13
+    assert rel(mom.cpu().numpy(), mref.cpu().numpy()) < 1e-13
+
+
 # ------------------------------------------------------------------ sweep, moments, diffusion
 def _planar_batch(n_v, l_v, m, xs, deltas, flows):
     p = gpu_plan(n_v, l_v, m)
