@@ -135,8 +135,8 @@ def main():
     ap.add_argument("--no-ttr", action="store_true", help="skip time-to-residual runs")
     ap.add_argument("--cis-max-it", type=int, default=0,
                     help="also run the conventional iteration (FP64) with this iteration cap")
-    ap.add_argument("--refresh-every", type=int, default=8,
-                    help="mixed runs: FP64 anchor of the defect correction every R-th iteration")
+    ap.add_argument("--refresh-every", type=int, default=16,
+                    help="mixed runs: FP64 anchors of the defect correction at iterations R/2, 3R/2, ...")
     ap.add_argument("--cpu-cells", type=int, default=12)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -368,14 +368,15 @@ typedef struct {
   int32_t project;       /* invariant projection of L in sis_collide       */
   int32_t check_every;   /* host convergence poll period (0 -> 4)          */
   int32_t use_graph;     /* capture one iteration in a HIP graph (0/1)     */
-  int32_t refresh_every; /* with a low-precision contraction (FP32/BF16X3):
-                            every refresh_every-th iteration (from the first)
-                            applies the operator in FP64 and stores the anchor
-                            (x_a, L+ x_a); the others apply the low-precision
-                            operator to x - x_a only:  L+ x ~ L+ x_a + L~+ (x - x_a).
-                            0 -> 8; 1 -> every iteration FP64; < 0 -> no
-                            anchors (plain low-precision contraction every
-                            iteration).  Ignored in FP64.                    */
+  int32_t refresh_every; /* with a low-precision contraction (FP32/BF16X3/
+                            BF16): iterations 0 (h = 0) and R/2, 3R/2, ... for
+                            R = refresh_every apply the operator in FP64 and
+                            store the anchor (x_a, L+ x_a); the others apply
+                            the low-precision operator to x - x_a only:
+                            L+ x ~ L+ x_a + L~+ (x - x_a).  0 -> 16; 1 -> every
+                            iteration FP64; < 0 -> no anchors (plain
+                            low-precision contraction every iteration).
+                            Ignored in FP64.                                 */
 } sis_solve_opts;
 
 /* Mixtures: M, Q are [n_cases][2] (M_a = sqrt(m/m_A) 2 int U_a dx1, Q_a

@@ -2206,9 +2206,9 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
   b->o = *o;
   b->precision = p->precision;
   // refresh: 0 = plain contraction in the plan precision every iteration,
-  //          1 = FP64 every iteration, R > 1 = FP64 anchor every R-th iteration
+  //          1 = FP64 every iteration, R > 1 = FP64 anchors at iterations 0, R/2, 3R/2, ...
   b->refresh = p->precision == SIS_PREC_FP64 ? 0
-               : (o->refresh_every < 0 ? 0 : (o->refresh_every == 0 ? 8 : o->refresh_every));
+               : (o->refresh_every < 0 ? 0 : (o->refresh_every == 0 ? 16 : o->refresh_every));
   b->Npen = o->N > 0.0 ? o->N : p->nubar;
   const int64_t nc = g->n_cells;
   const int ncase = g->n_cases;
@@ -2284,7 +2284,10 @@ sis_status sis_state_step(sis_state_t b, int32_t n_iters, hipStream_t stream) {
   if (!b) return fail(SIS_E_INVALID, "null state");
   if (n_iters < 0) return fail(SIS_E_INVALID, "n_iters must be >= 0");
   for (int i = 0; i < n_iters; ++i) {
-    const int kind = (b->refresh > 1 && (b->total % b->refresh) != 0) ? 1 : 0;
+    // FP64 anchors at iteration 0 (h = 0, free) and at R/2, 3R/2, ...: a case that converges
+    // within R iterations is still anchored once after the start
+    const bool anchor = b->total == 0 || (b->refresh > 1 && b->total % b->refresh == b->refresh / 2);
+    const int kind = (b->refresh > 1 && !anchor) ? 1 : 0;
     if (b->total == 0) {
       // the iteration starts from h = 0 (set by state_init): run it eagerly without the contraction
       if (sis_status st = state_iteration(b, stream, kind, true)) return st;

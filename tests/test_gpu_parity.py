@@ -279,9 +279,9 @@ def test_collide_mixed_precision_error_and_projection(precision, tol):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_mixed_solve_with_fp64_refresh_matches_fp64(precision):
-    """Low-precision contraction with FP64 anchors every 8 iterations: flow
-    rates within 1e-8 of the FP64 solve with the same projection setting
-    (target 1e-5), same convergence."""
+    """Low-precision contraction with FP64 anchors (default interval: anchors
+    at iterations 8, 24, 40, ...): flow rates within 1e-8 of the FP64 solve
+    with the same projection setting (target 1e-5), same convergence."""
     say("mixed solve", precision)
     n_v, l_v, m = 16, 6.0, 6
     p = sis.Plan(n_v, l_v, m_angle=m)
@@ -306,7 +306,7 @@ def test_mixed_solve_with_fp64_refresh_matches_fp64(precision):
 
 def test_bf16_solve_with_fp64_anchors_matches_fp64():
     """One bf16 product (hi*hi, about 3 decimal digits) with FP64 anchors
-    every 8 iterations: the low-precision contraction only acts on the change
+    (default interval): the low-precision contraction only acts on the change
     since the last anchor, so one-gas flow rates land within 1e-6 of the FP64
     solve (target 1e-5) in nearly the same number of iterations at the
     residual 1e-8 of the benchmark (at 1e-10 the low-precision noise slows the
