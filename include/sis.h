@@ -420,15 +420,16 @@ sis_status sis_state_destroy(sis_state_t state);
  * candidate on the device and keeps, among those within 3% of the fastest,
  * the fewest split-K partials, then the taller tile; tile_rows is the
  * cell-tile height (128, 64 or 32; the operator tile is 128), k_stage the
- * k-depth of its LDS stages (16, or 32 for the FP64 single-buffered
- * variants; nullable), tuned = 0 if the default heuristic is in use.        */
+ * k-depth of its LDS stages (FP64 and FP32: 16, or 32 for the FP64
+ * single-buffered variants; BF16X3 and BF16: 64; nullable), tuned = 0 if
+ * the default heuristic is in use.                                          */
 sis_status sis_plan_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t precision,
                                        int32_t* tile_rows, int32_t* splits, int32_t* tuned,
                                        int32_t* k_stage);
 /* Fix the configuration for n_cells cells in `precision` instead of tuning it
- * (reproducible runs, tests): tile_rows 128, 64 or 32 with k_stage 16, or
- * (FP64 only) 128 or 64 with k_stage 32; splits in 1..8.  Invalid
- * combinations return SIS_E_INVALID.                                        */
+ * (reproducible runs, tests): tile_rows 128, 64 or 32 with k_stage 16
+ * (FP64, FP32) or 64 (BF16X3, BF16), or (FP64 only) 128 or 64 with k_stage
+ * 32; splits in 1..8.  Invalid combinations return SIS_E_INVALID.          */
 sis_status sis_plan_set_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t precision,
                                            int32_t tile_rows, int32_t k_stage, int32_t splits);
 

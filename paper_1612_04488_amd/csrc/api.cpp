@@ -2382,8 +2382,13 @@ sis_status sis_plan_set_contraction_config(sis_plan_t p, int64_t n_cells, int32_
   if (precision < SIS_PREC_FP64 || precision > SIS_PREC_BF16) return fail(SIS_E_INVALID, "unknown precision");
   if (splits < 1 || splits > 8) return fail(SIS_E_INVALID, "splits must be in [1, 8]");
   int tile = -1;
-  if (k_stage == 16) tile = tile_rows == 128 ? 0 : tile_rows == 64 ? 2 : tile_rows == 32 ? 1 : -1;
-  else if (k_stage == 32 && precision == SIS_PREC_FP64) tile = tile_rows == 128 ? 3 : tile_rows == 64 ? 4 : -1;
+  if (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) {
+    if (k_stage == 64) tile = tile_rows == 128 ? 0 : tile_rows == 64 ? 2 : tile_rows == 32 ? 1 : -1;
+  } else if (k_stage == 16) {
+    tile = tile_rows == 128 ? 0 : tile_rows == 64 ? 2 : tile_rows == 32 ? 1 : -1;
+  } else if (k_stage == 32 && precision == SIS_PREC_FP64) {
+    tile = tile_rows == 128 ? 3 : tile_rows == 64 ? 4 : -1;
+  }
   if (tile < 0) return fail(SIS_E_INVALID, "no contraction tile %d x 128 with k-stage %d for this precision", tile_rows, k_stage);
   p->gemm_choice[std::make_pair(n_cells, static_cast<int>(precision))] = std::make_pair(tile, static_cast<int>(splits));
   return SIS_OK;
@@ -2405,7 +2410,7 @@ sis_status sis_plan_contraction_config(sis_plan_t p, int64_t n_cells, int32_t pr
   }
   *tile_rows = sis::gemm_tile_rows(t);
   *splits = s;
-  if (k_stage) *k_stage = sis::gemm_tile_depth(t);
+  if (k_stage) *k_stage = sis::gemm_tile_depth(t, precision);
   return SIS_OK;
 }
 

@@ -47,7 +47,7 @@ struct GemmArgs {
                      // single-buffered stages
 };
 int gemm_tile_rows(int tile);
-int gemm_tile_depth(int tile);
+int gemm_tile_depth(int tile, int precision);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 // x = X - Xref (Xref may be null) -> bf16 hi + lo, or -> FP32; count = M * K
 hipError_t launch_split_x(const double* X, const double* Xref, int64_t count, uint16_t* hi, uint16_t* lo,

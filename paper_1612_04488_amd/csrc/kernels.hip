@@ -2182,7 +2182,10 @@ int gemm_k_per_split(int K, int splits) {
 
 int gemm_tile_rows(int tile) { return (tile == 0 || tile == 3) ? 128 : (tile == 2 || tile == 4) ? 64 : 32; }
 
-int gemm_tile_depth(int tile) { return tile >= 3 ? 32 : 16; }
+int gemm_tile_depth(int tile, int precision) {
+  if (precision >= 2) return 64;   // bf16 forms: both operands staged in 64-deep stages
+  return tile >= 3 ? 32 : 16;
+}
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   const int kps = gemm_k_per_split(g.K, g.splits);

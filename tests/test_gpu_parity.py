@@ -326,6 +326,44 @@ def test_bf16_solve_with_fp64_anchors_matches_fp64():
     assert np.all(np.abs(r["iters"] - ref["iters"]) <= 5)
 
 
+def test_bf16_contraction_configurations_agree():
+    """Every tile of the two bf16 contractions (k-stage 64), fixed through the ABI:
+    each output element runs the same MFMA sequence whatever the tile height, so at
+    equal split-K the tiles agree to the last bit, and all stay within the form's
+    error of the FP64 contraction.  n3 = 864 leaves the last 64-deep stage half
+    past the k range and 300 cells a ragged last cell tile."""
+    p = sis.Plan(12, 4.0, m_angle=4, parity=1)
+    nc = 300
+    h0 = inputs.rough_h(12, 4.0, nc)[..., 6:]
+    h = dev(np.ascontiguousarray(h0).reshape(nc, -1))
+    assert h.shape[1] == 864
+    delta = dev(np.full(nc, 2.0))
+    ref = torch.empty_like(h)
+    p.collide(h, delta, ref)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    for prec, tol in (("bf16x3", 5e-4), ("bf16", 2e-2)):
+        p.set_precision(prec)
+        for splits in (1, 3):
+            outs = {}
+            for rows, depth in ((128, 64), (64, 64), (32, 64)):
+                p.set_contraction_config(nc, rows, depth, splits, precision=prec)
+                out = torch.empty_like(h)
+                p.collide(h, delta, out)
+                torch.cuda.synchronize()
+                assert p.contraction_config(nc, prec, with_depth=True) == (rows, splits, True, depth)
+                outs[(rows, depth)] = out.cpu().numpy()
+                assert np.all(np.isfinite(outs[(rows, depth)]))
+                assert rel(outs[(rows, depth)], ref) < tol, (prec, rows, depth, splits)
+            base = outs[(128, 64)]
+            for key, o in outs.items():
+                assert np.array_equal(o, base), (prec, key, splits, rel(o, base))
+    with pytest.raises(sis.SisError):
+        p.set_contraction_config(nc, 128, 16, 1, precision="bf16x3")
+    with pytest.raises(sis.SisError):
+        p.set_contraction_config(nc, 128, 64, 1, precision="fp64")
+
+
 def test_every_contraction_configuration_gives_the_same_operator_action():
     """Each (tile, k-stage, split-K) configuration of the FP64 contraction, fixed
     through the ABI instead of tuned, reproduces the tuned result to rounding
