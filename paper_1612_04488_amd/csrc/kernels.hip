@@ -492,8 +492,21 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
-  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM;
-  const int n0 = blockIdx.x * BN;
+  // XCD-aware tile order.  Workgroups go to the 8 XCDs round-robin in dispatch
+  // order, so each XCD's L2 would otherwise see cell and operator tiles from
+  // all over the grid.  Each XCD instead takes a contiguous run of the tile
+  // sequence, walked in groups of kGroup cell-tile rows (cell tile fastest), so
+  // the workgroups resident on one XCD share a few cell and operator tiles per
+  // k-stage.  A permutation of the tiles: results are unchanged.
+  constexpr int kGroup = 8;
+  const int gx = gridDim.x, gy = gridDim.y, total = gx * gy;
+  int b = blockIdx.y * gx + blockIdx.x;
+  if (total % 8 == 0) b = (b % 8) * (total / 8) + b / 8;
+  const int first_y = (b / (kGroup * gx)) * kGroup;
+  const int rows_in_group = min(kGroup, gy - first_y);
+  const int in_group = b - first_y * gx;
+  const int64_t m0 = static_cast<int64_t>(first_y + in_group % rows_in_group) * BM;
+  const int n0 = (in_group / rows_in_group) * BN;
   const int kbeg = blockIdx.z * kps;
   const int kend = min(K, kbeg + kps);
   double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;

@@ -326,14 +326,17 @@ def test_bf16_solve_with_fp64_anchors_matches_fp64():
     assert np.all(np.abs(r["iters"] - ref["iters"]) <= 5)
 
 
-def test_bf16_contraction_configurations_agree():
+@pytest.mark.parametrize("nc", [300, 1000])
+def test_bf16_contraction_configurations_agree(nc):
     """Every tile of the two bf16 contractions (k-stage 64), fixed through the ABI:
-    each output element runs the same MFMA sequence whatever the tile height, so at
-    equal split-K the tiles agree to the last bit, and all stay within the form's
-    error of the FP64 contraction.  n3 = 864 leaves the last 64-deep stage half
-    past the k range and 300 cells a ragged last cell tile."""
+    each output element runs the same MFMA sequence whatever the tile height and
+    the order in which tiles are assigned to XCDs, so at equal split-K the tiles
+    agree to the last bit, and all stay within the form's error of the FP64
+    contraction.  n3 = 864 leaves the last 64-deep stage half past the k range;
+    both cell counts leave a ragged last cell tile, and with 1000 cells every
+    tile height gives a tile count divisible by the 8 XCDs (the per-XCD runs of
+    the tile order) while 300 cells give counts that are not."""
     p = sis.Plan(12, 4.0, m_angle=4, parity=1)
-    nc = 300
     h0 = inputs.rough_h(12, 4.0, nc)[..., 6:]
     h = dev(np.ascontiguousarray(h0).reshape(nc, -1))
     assert h.shape[1] == 864
