@@ -175,6 +175,24 @@ constexpr int kPad = 4;
 // per stage, half the LDS, so deeper stages fit twice per CU).  PAD: row padding of the
 // k-major LDS tiles (PAD = 1 with BK = 32 spreads the 64-lane stores of 16 k-rows x 4 rows
 // over the banks).
+// XCD-aware tile order of the contractions.  Workgroups go to the 8 XCDs
+// round-robin in dispatch order, so each XCD's L2 would otherwise see cell and
+// operator tiles from all over the grid.  Each XCD instead takes a contiguous
+// run of the tile sequence, walked in groups of kGroup cell-tile rows (cell
+// tile fastest), so the workgroups resident on one XCD share a few cell and
+// operator tiles per k-stage.  A permutation of the (x, y) tiles: results are
+// unchanged.  Returns the cell tile in .y and the operator tile in .x.
+__device__ inline int2 xcd_tile() {
+  constexpr int kGroup = 8;
+  const int gx = gridDim.x, gy = gridDim.y, total = gx * gy;
+  int b = blockIdx.y * gx + blockIdx.x;
+  if (total % 8 == 0) b = (b % 8) * (total / 8) + b / 8;
+  const int first_y = (b / (kGroup * gx)) * kGroup;
+  const int rows_in_group = min(kGroup, gy - first_y);
+  const int in_group = b - first_y * gx;
+  return make_int2(in_group / rows_in_group, first_y + in_group % rows_in_group);
+}
+
 template <int BM, int BN, int WM, int WN, int BK = kBK, int NBUF = 2, int PAD = kPad>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict__ X,
                                                        const double* __restrict__ Op,
@@ -191,6 +209,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+  // plain grid order: the MFMA-bound FP64 tiles measured no faster (planar batch slower) with xcd_tile()
   const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM;
   const int n0 = blockIdx.x * BN;
   const int kbeg = blockIdx.z * kps;
@@ -492,21 +511,9 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
-  // XCD-aware tile order.  Workgroups go to the 8 XCDs round-robin in dispatch
-  // order, so each XCD's L2 would otherwise see cell and operator tiles from
-  // all over the grid.  Each XCD instead takes a contiguous run of the tile
-  // sequence, walked in groups of kGroup cell-tile rows (cell tile fastest), so
-  // the workgroups resident on one XCD share a few cell and operator tiles per
-  // k-stage.  A permutation of the tiles: results are unchanged.
-  constexpr int kGroup = 8;
-  const int gx = gridDim.x, gy = gridDim.y, total = gx * gy;
-  int b = blockIdx.y * gx + blockIdx.x;
-  if (total % 8 == 0) b = (b % 8) * (total / 8) + b / 8;
-  const int first_y = (b / (kGroup * gx)) * kGroup;
-  const int rows_in_group = min(kGroup, gy - first_y);
-  const int in_group = b - first_y * gx;
-  const int64_t m0 = static_cast<int64_t>(first_y + in_group % rows_in_group) * BM;
-  const int n0 = (in_group / rows_in_group) * BN;
+  const int2 tile = xcd_tile();
+  const int64_t m0 = static_cast<int64_t>(tile.y) * BM;
+  const int n0 = tile.x * BN;
   const int kbeg = blockIdx.z * kps;
   const int kend = min(K, kbeg + kps);
   double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
