@@ -44,18 +44,22 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16": 2500.0}
 TRAFFIC_KIB = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (1116445.9 * 2.0, 155136.0),
                ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (1546552.0 * 2.0, 206848.0),
                ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (42415887.6 * 2.0, 1327104.0),
-               ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 3, 64): (568784.0 * 2.0, 155136.0),
-               ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 1, 64): (6551414.1 * 2.0, 1327104.0),
-               ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 2, 64): (7517366.8 * 2.0, 2654208.0)}
+               ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 3, 64): (526484.1 * 2.0, 157824.0),
+               ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 4, 64): (639093.9 * 2.0, 210432.0),
+               ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 6, 64): (576400.5 * 2.0, 315648.0),
+               ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 1, 64): (6582009.6 * 2.0, 1347840.0),
+               ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 2, 64): (7447376.5 * 2.0, 2695680.0)}
 # MFMA pipe utilisation of the same configuration from its counter pass:
 # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), and the shader clock
 # the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
 MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22),
              ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (0.788, 2.09),
              ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.801, 2.35),
-             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 3, 64): (0.322, 2.16),
-             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 1, 64): (0.469, 1.95),
-             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 2, 64): (0.444, 2.39)}
+             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 3, 64): (0.324, 2.40),
+             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 4, 64): (0.336, 2.42),
+             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 6, 64): (0.357, 2.12),
+             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 1, 64): (0.449, 2.35),
+             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 2, 64): (0.496, 1.91)}
 HBM_GBS = 8000.0
 
 

@@ -490,7 +490,7 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // NPROD = 1: the hi*hi product alone (lo arrays unused, neither loaded nor staged).
 template <int BM, int BN, int WM, int WN, int NPROD = 3>
-__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __restrict__ Xh,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kernel(const uint16_t* __restrict__ Xh,
                                                           const uint16_t* __restrict__ Xl,
                                                           const uint16_t* __restrict__ Oh,
                                                           const uint16_t* __restrict__ Ol,
@@ -503,14 +503,25 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
   constexpr int A_LD = (BM * CH + 255) / 256;
   constexpr int B_LD = (BN * CH + 255) / 256;
   static_assert((BM / WM) * (BN / WN) == 4, "4 waves per workgroup");
-  // rows hold the 64 k-values of one m (or n) contiguously (+16 B pad); a lane
-  // reads its 8 consecutive k values as one 16-byte vector
-  constexpr int RS = BK + 8;
+  // rows hold the 64 k-values of one m (or n) as eight 16-byte chunks, chunk c
+  // of row r stored at slot c ^ ((r / 2) % 8): the 16 rows one MFMA operand read
+  // touches and the two rows a 16-lane group of staging writes fills each
+  // cover distinct banks.  A lane reads its 8 consecutive k values as one
+  // 16-byte vector.
+  constexpr int RS = BK;
+  static_assert(CH == 8, "eight 16-byte chunks per row");
   __shared__ uint16_t sA[NPROD == 3 ? 2 : 1][BM][RS];
   __shared__ uint16_t sB[NPROD == 3 ? 2 : 1][BN][RS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
+  // Swizzled slots are per-thread constants.  Staging: thread q = tid + 256 i
+  // writes chunk tid % 8 of row tid / 8 + 32 i, so (row / 2) % 8 = (tid / 16) % 8.
+  // Operand reads: rows wm + 16 i + lane % 16 (wm, 16 i multiples of 16), chunk
+  // ks / 8 + lane / 16.
+  const int wslot = ((tid & 7) ^ ((tid >> 4) & 7)) << 3;
+  const int rsw = (lane & 15) >> 1;
+  const int rslot0 = ((lane >> 4) ^ rsw) << 3, rslot1 = ((4 + (lane >> 4)) ^ rsw) << 3;
   const int2 tile = xcd_tile();
   const int64_t m0 = static_cast<int64_t>(tile.y) * BM;
   const int n0 = tile.x * BN;
@@ -575,7 +586,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
       if (q < BM * CH) {
-        const int r = q / CH, kc = (q % CH) * 8;
+        const int r = q / CH, kc = wslot;
         *reinterpret_cast<uint4*>(&sA[0][r][kc]) = ra[0][i];
         if constexpr (NPROD == 3) *reinterpret_cast<uint4*>(&sA[NPROD == 3 ? 1 : 0][r][kc]) = ra[1][i];
       }
@@ -584,7 +595,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
     for (int i = 0; i < B_LD; ++i) {
       const int q = tid + 256 * i;
       if (q < BN * CH) {
-        const int r = q / CH, kc = (q % CH) * 8;
+        const int r = q / CH, kc = wslot;
         *reinterpret_cast<uint4*>(&sB[0][r][kc]) = rb[0][i];
         if constexpr (NPROD == 3) *reinterpret_cast<uint4*>(&sB[NPROD == 3 ? 1 : 0][r][kc]) = rb[1][i];
       }
@@ -613,13 +624,15 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(const uint16_t* __rest
       v8bf ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        ah[i] = *reinterpret_cast<const v8bf*>(&sA[0][wm + i * 16 + rr][ks + kq]);
-        if constexpr (NPROD == 3) al[i] = *reinterpret_cast<const v8bf*>(&sA[NPROD == 3 ? 1 : 0][wm + i * 16 + rr][ks + kq]);
+        const int r = wm + i * 16 + rr, c = ks == 0 ? rslot0 : rslot1;
+        ah[i] = *reinterpret_cast<const v8bf*>(&sA[0][r][c]);
+        if constexpr (NPROD == 3) al[i] = *reinterpret_cast<const v8bf*>(&sA[NPROD == 3 ? 1 : 0][r][c]);
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        bh[j] = *reinterpret_cast<const v8bf*>(&sB[0][wn + j * 16 + rr][ks + kq]);
-        if constexpr (NPROD == 3) bl[j] = *reinterpret_cast<const v8bf*>(&sB[NPROD == 3 ? 1 : 0][wn + j * 16 + rr][ks + kq]);
+        const int r = wn + j * 16 + rr, c = ks == 0 ? rslot0 : rslot1;
+        bh[j] = *reinterpret_cast<const v8bf*>(&sB[0][r][c]);
+        if constexpr (NPROD == 3) bl[j] = *reinterpret_cast<const v8bf*>(&sB[NPROD == 3 ? 1 : 0][r][c]);
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
