@@ -162,3 +162,34 @@ def test_mixed_precision_with_parity():
         r = _planar_solve(p, *args, eps=1e-10, max_it=300)
         assert rel(r["M"], ref["M"]) < 1e-5 and rel(r["Q"], ref["Q"]) < 1e-5, prec
     p.set_precision("fp64")
+
+
+@pytest.mark.parametrize("workload", ["planar-batch", "duct"])
+def test_benchmark_size_collide_matches_oracle_on_sampled_cells(workload):
+    """The contraction at the benchmark's full size and launch configuration
+    (planar batch: 32^3 velocities padded to 64^3, M = 12, 808 cells, v2, v3 > 0
+    stored; duct: IPL 24^3 padded to 48^3, M = 8, 6 x 64^2 cells, v3 > 0 stored;
+    the tuned tile and split-K, as bench.py times it), checked against the
+    oracle's FFT form of L+ on sampled cells."""
+    w = inputs.PLANAR_BATCH if workload == "planar-batch" else inputs.DUCT_IPL
+    parity = 2 if workload == "planar-batch" else 1
+    nc = (sum(len(x) for x in inputs.workload_nodes(w)) if workload == "planar-batch"
+          else w["cells"] ** 2 * len(w["aspect"]))
+    say("benchmark-size collide", workload, nc)
+    p = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"],
+                 visc_index=w.get("visc_index", 0.81), parity=parity)
+    h = inputs.smooth_h(w["n_v"], w["l_v"], nc)   # odd in v3, even in v2
+    delta = np.resize(np.asarray(w["deltas"], dtype=np.float64), nc)
+    hs = dev(stored(h, parity).reshape(nc, -1))
+    rhs = torch.empty_like(hs)
+    p.collide(hs, dev(delta), rhs)
+    torch.cuda.synchronize()
+    rows, splits, tuned, depth = p.contraction_config(nc, with_depth=True)
+    say("configuration", rows, splits, tuned, depth)
+    assert tuned
+    alpha = 2.0 * (1.0 - w.get("visc_index", 0.81)) if w["kernel"] == "ipl" else 1.0
+    f = collision.FSM(VelocityGrid(w["n_v"], w["l_v"]), n_pad=w["n_pad"], m_angle=w["m_angle"], alpha=alpha)
+    for c in (0, nc // 2 + 1, nc - 1):
+        ref = stored(delta[c] * f.lplus(h[c]), parity).ravel()
+        got = rhs[c].cpu().numpy()
+        assert rel(got, ref) < 1e-11, (workload, c, rel(got, ref))
