@@ -226,3 +226,41 @@ def test_shared_inverse_for_equal_cross_sections():
         s = slice(o[c], o[c + 1])
         ref = duct.diffusion_2d(g, mom[s], amom[s], deltas[c], 1.3, flows[c])
         assert rel(U[s], ref) < 1e-10, c
+
+
+def test_sweep2d_at_benchmark_size():
+    """The 2-D sweep and moments at the duct benchmark's size and storage: 64 x 64
+    quarter cross sections of aspect ratio 1 and 2, IPL 24^3 velocities with
+    v3 > 0 stored, the launch configuration bench.py times.  The sweep couples no
+    velocities, so the oracle's full-grid sweep restricted to v3 > 0 is the
+    reference; inputs odd in v3 (as the solver's state) make the stored-half
+    moments equal the full-grid ones."""
+    w = inputs.DUCT_IPL
+    say("sweep2d benchmark size")
+    p = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"],
+                 visc_index=w["visc_index"], parity=1)
+    all_cases = inputs.duct_cases(w)
+    cases = [all_cases[0], all_cases[3]]
+    deltas, flows = [1.0, 50.0], [1, 1]
+    geom = sis.Geometry2D(p, "duct", cases, deltas, flows)
+    f = collision.FSM(VelocityGrid(w["n_v"], w["l_v"]), n_pad=w["n_pad"], m_angle=w["m_angle"],
+                      alpha=2.0 * (1.0 - w["visc_index"]))
+    vg = f.grid
+    grids = oracle_grids("duct", cases)
+    nc = geom.n_cells
+    assert nc == 2 * w["cells"] ** 2
+    rhs = inputs.smooth_h(w["n_v"], w["l_v"], nc, seed=5)
+    hprev = inputs.smooth_h(w["n_v"], w["l_v"], nc, seed=9)
+    half = w["n_v"] // 2
+    hd = dev(np.ascontiguousarray(hprev[..., half:]).reshape(nc, -1))
+    mom = torch.empty((nc, 8), dtype=torch.float64, device=DEV)
+    sis.transport_sweep(p, geom, dev(np.ascontiguousarray(rhs[..., half:]).reshape(nc, -1)), hd, mom)
+    torch.cuda.synchronize()
+    hd, mom = hd.cpu().numpy(), mom.cpu().numpy()
+    o = geom.offsets
+    for c, g in enumerate(grids):
+        s = slice(o[c], o[c + 1])
+        ref = duct.sweep_2d(rhs[s], deltas[c] * f.nu, g, vg, hprev[s])
+        assert rel(hd[s], ref[..., half:].reshape(o[c + 1] - o[c], -1)) < 1e-12, c
+        mref = duct.moments_2d(vg, ref)
+        assert np.max(np.abs(mom[s, :7] - mref)) < 1e-12 * np.max(np.abs(mref)), c
