@@ -183,6 +183,43 @@ def test_sweep_and_moments_parity_ragged_batch(n_v, l_v, m):
         assert np.max(np.abs(mom2[o[c]:o[c + 1]] - mref)) < 1e-12 * sc, c
 
 
+def test_sweep_and_moments_at_benchmark_size():
+    """The planar sweep, fused moments and moment kernel at the benchmark's size
+    and storage: 8 cases of 101 tanh nodes, 32^3 velocities on [-6, 6]^3 with v2,
+    v3 > 0 stored, the launch configuration bench.py times.  The sweep couples no
+    velocities, so the oracle's full-grid sweep restricted to the stored quarter
+    is the reference; inputs odd in v3 and even in v2 (as the solver's state)
+    make the stored-quarter moments equal the full-grid ones."""
+    w = inputs.PLANAR_BATCH
+    say("sweep benchmark size")
+    p = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"], parity=2)
+    xs = inputs.workload_nodes(w)
+    geom = sis.Geometry(p, xs, w["deltas"], w["flows"])
+    f = collision.FSM(VelocityGrid(w["n_v"], w["l_v"]), n_pad=w["n_pad"], m_angle=w["m_angle"])
+    g = f.grid
+    nc = geom.n_cells
+    assert nc == 808
+    half = w["n_v"] // 2
+    rhs = inputs.smooth_h(w["n_v"], w["l_v"], nc, seed=3)
+    rd = dev(np.ascontiguousarray(rhs[..., half:, half:]).reshape(nc, -1))
+    hh = torch.empty_like(rd)
+    mom = torch.empty((nc, 4), dtype=torch.float64, device=DEV)
+    mom2 = torch.empty_like(mom)
+    sis.transport_sweep(p, geom, rd, hh, mom)
+    p.moments(hh, mom2)
+    torch.cuda.synchronize()
+    hh, mom, mom2 = hh.cpu().numpy(), mom.cpu().numpy(), mom2.cpu().numpy()
+    o = geom.offsets
+    for c, x in enumerate(xs):
+        ref = tr.sweep_1d(rhs[o[c]:o[c + 1]], w["deltas"][c] * f.nu, x, g)
+        got = hh[o[c]:o[c + 1]]
+        assert rel(got, ref[..., half:, half:].reshape(o[c + 1] - o[c], -1)) < 1e-12, c
+        mref = np.stack([g.U3(ref), g.q3(ref), g.G1(ref), g.P13(ref)], axis=1)
+        sc = np.max(np.abs(mref))
+        assert np.max(np.abs(mom[o[c]:o[c + 1]] - mref)) < 1e-12 * sc, c
+        assert np.max(np.abs(mom2[o[c]:o[c + 1]] - mref)) < 1e-12 * sc, c
+
+
 def test_diffusion_correct_parity():
     n_v, l_v, m = 8, 4.0, 3
     xs = [inputs.nodes_tanh(20), inputs.nodes_uniform(5)]
