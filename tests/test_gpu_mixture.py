@@ -211,3 +211,36 @@ def test_mix_table4_equimolar_ne_ar():
         assert abs(r["M"][c][0] - row[2]) < tol * row[2]
         assert abs(r["M"][c][1] - row[3]) < tol * row[3]
         assert r["iters"][c] <= 2 * row[1]
+
+
+def test_mix_collide_at_benchmark_size():
+    """The mixture contraction at the benchmark's size and launch configuration:
+    Ne-Ar near hard spheres, 2 x 24^3 velocities on [-5, 5]^3 padded to 48^3,
+    M = 8, 16 rho nodes, 16 cases x 201 nodes = 3216 cells, v2, v3 > 0 stored,
+    the tuned tile and split-K.  The oracle's L+ (about half a minute per cell on
+    one core) is checked on one sampled cell."""
+    w = inputs.MIX_NEAR
+    mx = w["mixture"]
+    nc = sum(len(x) for x in inputs.workload_nodes(w))
+    assert nc == 3216
+    say("mixture benchmark size: plan")
+    p = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"],
+                 mixture=mx, parity=2)
+    half = w["n_v"] // 2
+    h = inputs.mixture_h(w["n_v"], w["l_v"], nc)   # odd in v3, even in v2
+    delta = np.resize(np.asarray(w["deltas"], dtype=np.float64), nc)
+    hd = dev(np.ascontiguousarray(h[..., half:, half:]).reshape(nc, -1))
+    rhs = torch.empty_like(hd)
+    p.collide(hd, dev(delta), rhs)
+    torch.cuda.synchronize()
+    rows, splits, tuned, depth = p.contraction_config(nc, with_depth=True)
+    say("mixture benchmark size: configuration", rows, splits, tuned, depth)
+    assert tuned
+    c = nc // 2 + 7
+    got = rhs[c].cpu().numpy()
+    say("mixture benchmark size: oracle L+ of cell", c)
+    o = mixture.MixtureFSM(VelocityGrid(w["n_v"], w["l_v"]), mx["masses"], mx["diameters"], mx["chi"],
+                           n_pad=w["n_pad"], m_angle=w["m_angle"], m_rho=mx["m_rho"])
+    ref = delta[c] * o.lplus(h[c])
+    say("mixture benchmark size: oracle done")
+    assert rel(got, np.ascontiguousarray(ref[..., half:, half:]).ravel()) < 1e-11, rel(got, ref[..., half:, half:].ravel())
