@@ -341,6 +341,36 @@ def test_mixed_solve_with_fp64_refresh_matches_fp64(precision):
     assert np.all(np.abs(r1["M"] - refs[False]["M"]) < 1e-12 * np.abs(refs[False]["M"]))
 
 
+@pytest.mark.parametrize("workload", ["planar-batch", "duct"])
+def test_mixed_solve_at_benchmark_size_matches_fp64(workload):
+    """The benchmark's time-to-residual solves at full size (planar batch: 8 cases
+    of 101 nodes, 32^3 velocities, v2, v3 > 0 stored; duct: 6 quarter sections of
+    64^2 cells, IPL 24^3, v3 > 0 stored), eps = 1e-8: the 3xBF16 contraction with
+    FP64 anchors at the default interval converges with FP64's iteration counts
+    (within 2) and its flow rates within 1e-6 of the FP64 solve (target 1e-5)."""
+    if workload == "planar-batch":
+        w, parity = inputs.PLANAR_BATCH, 2
+    else:
+        w, parity = inputs.DUCT_IPL, 1
+    say("mixed solve at benchmark size", workload)
+    p = sis.Plan(w["n_v"], w["l_v"], n_pad=w["n_pad"], m_angle=w["m_angle"], kernel=w["kernel"],
+                 visc_index=w.get("visc_index", 0.81), parity=parity)
+    if workload == "planar-batch":
+        geom = sis.Geometry(p, inputs.workload_nodes(w), w["deltas"], w["flows"])
+    else:
+        geom = sis.Geometry2D(p, "duct", inputs.duct_cases(w), w["deltas"], w["flows"])
+    out = {}
+    for prec in ("fp64", "bf16x3"):
+        p.set_precision(prec)
+        out[prec] = sis.solve(p, geom, scheme="SIS", eps=1e-8, max_it=400)
+        say(prec, out[prec]["iters"].tolist())
+    ref, r = out["fp64"], out["bf16x3"]
+    assert r["status"] == 0 and ref["status"] == 0
+    assert np.all(np.abs(r["M"] - ref["M"]) < 1e-6 * np.abs(ref["M"]))
+    assert np.all(np.abs(r["Q"] - ref["Q"]) < 1e-6 * np.abs(ref["Q"]))
+    assert np.all(np.abs(r["iters"] - ref["iters"]) <= 2)
+
+
 def test_bf16_solve_with_fp64_anchors_matches_fp64():
     """One bf16 product (hi*hi, about 3 decimal digits) with FP64 anchors
     (default interval): the low-precision contraction only acts on the change
