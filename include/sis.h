@@ -56,9 +56,12 @@ enum { SIS_KERNEL_HARD_SPHERE = 0, SIS_KERNEL_IPL = 1 };
  * BF16X3: both operands split into bf16 hi + lo, products hi*hi + hi*lo +
  * lo*hi, FP32 accumulation.  BF16: the hi*hi product alone (about 3 decimal
  * digits); meant for sis_solve with FP64 anchors (refresh_every), where the
- * low-precision contraction only acts on the change since the last anchor
- * (one gas: flow rates within ~1e-6 of FP64; for mixtures the heat flux
- * deviates by ~1e-3, use BF16X3).                                           */
+ * low-precision contraction only acts on the change since the last anchor.
+ * Measured worst cases against FP64 at eps = 1e-8: one gas on planar and duct
+ * workloads ~1e-7 in the flow rates, the Sierpinski-carpet heat flux 2.8e-5
+ * (above the 1e-5 bound of the mixed forms), so BF16 is outside every
+ * mixed-precision accuracy claim; BF16X3 is the mixed form.  Two-species plans
+ * reject BF16 (SIS_E_UNSUPPORTED: the species blocks deviate by ~1e-3).       */
 enum { SIS_PREC_FP64 = 0, SIS_PREC_FP32 = 1, SIS_PREC_BF16X3 = 2, SIS_PREC_BF16 = 3 };
 /* Source terms S of Sec. 2 with X_P = X_T = -1.                             */
 enum { SIS_FLOW_NONE = 0, SIS_FLOW_POISEUILLE = 1, SIS_FLOW_TRANSPIRATION = 2 };
@@ -244,6 +247,12 @@ sis_status sis_geometry_create(sis_plan_t plan, const sis_geometry_desc* desc,
 sis_status sis_geometry_destroy(sis_geom_t geom);
 int64_t    sis_geometry_cells(sis_geom_t geom);
 int32_t    sis_geometry_moment_stride(sis_geom_t geom);   /* 4 planar, 8 in 2-D; -1 if NULL */
+/* Form of the 2-D transport sweep this geometry launches (diagnostic; the
+ * results do not depend on it): anti-diagonal wavefronts with P = 1, 2 or 3
+ * cells of an anti-diagonal per thread slot (P = ceil(min(n1, n2)/64) over the
+ * cases), or 0 for the row-ordered sweep that serves anti-diagonals longer than
+ * 192 cells.  -1 for planar and tube geometries or NULL.                       */
+int32_t    sis_geometry_sweep_form(sis_geom_t geom);
 
 /* Solver of the 2-D velocity equation (sis_diffusion_correct; the operator
  * depends on the geometry only).  SIS_DIFFUSION_INVERSE (the default after
@@ -314,8 +323,16 @@ sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const 
 sis_status sis_transport_sweep(sis_plan_t plan, sis_geom_t geom, const double* rhs,
                                double* h_half_out, double* mom_out, hipStream_t stream);
 
-/* sis_moments -- { U3, q3, G1, P13 } of h[n_cells][n3] -> mom_out[n_cells][4]
- * (mixtures: h[n_cells][2][n3] -> mom_out[n_cells][2][4] as for the sweep). */
+/* sis_moments -- macroscopic moments of the perturbation h (midpoint sums with
+ * the velocity weight, over the full grid h represents):
+ *   U3 = int v3 h (the velocity of Sec. 2), q3 = int (|v|^2 - 5/2) v3 h (the heat
+ *   flux of Sec. 2), G1 = int v3 (2 v1^2 - 1) h = F_201 / 4 (the Hermite moment
+ *   of Sec. 2.1 that eqs. diffusion_LBE and first_order carry), P13 = 2 int v1 v3 h
+ *   (the shear stress of Sec. 2.1);
+ * h[n_cells][n_vel] -> mom_out[n_cells][4] = { U3, q3, G1, P13 }.  Mixtures
+ * (Sec. 5): h[n_cells][2][n_vel] -> mom_out[n_cells][2][4] with the mass
+ * factors of the sweep's moments.  Errors: SIS_E_INVALID for NULL pointers or
+ * n_cells < 0; nothing is enqueued then.                                       */
 sis_status sis_moments(sis_plan_t plan, int64_t n_cells, const double* h, double* mom_out,
                        hipStream_t stream);
 
@@ -352,10 +369,13 @@ sis_status sis_diffusion_correct(sis_plan_t plan, sis_geom_t geom, const double*
                                  hipStream_t stream);
 
 /* ------------------------------------------------------------------ solver
- * sis_solve -- CIS or SIS outer iterations from h = 0 for every case of a
- * geometry until the relative change of both flow rates M = 2 int U3 dx1 and
- * Q = 2 int q3 dx1 between consecutive iterations is below eps (per case),
- * or max_it.  One iteration = sis_collide + sis_transport_sweep (+
+ * sis_solve -- CIS (the conventional iteration, eq. LBE_iteration of Sec. 2.2)
+ * or SIS (eq. syn_LBE of Sec. 2.2 followed by the velocity equation and the
+ * correction of eq. guided, with the tuning parameter N of Sec. 2.5) outer
+ * iterations from h = 0 for every case of a geometry until the relative change
+ * of both flow rates M = 2 int U3 dx1 and Q = 2 int q3 dx1 (the flow rates of
+ * Sec. 2) between consecutive iterations is below eps (per case; the stop rule
+ * of Sec. 2.4, which uses eps = 1e-10), or max_it.  One iteration = sis_collide + sis_transport_sweep (+
  * sis_diffusion_correct for SIS) + flow rates, launched as a captured HIP
  * graph.  Converged cases are frozen while the others continue.  Results are
  * copied to HOST arrays (each nullable).  Synchronous.  2-D: M = (1/A) sum U3 dA

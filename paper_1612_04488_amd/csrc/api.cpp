@@ -1823,6 +1823,9 @@ sis_status sis_plan_set_precision(sis_plan_t p, int32_t precision, hipStream_t s
     }
   } else if (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) {
     if (p->ndof % 8) return fail(SIS_E_UNSUPPORTED, "the BF16 contractions need the unknowns per cell divisible by 8");
+    if (precision == SIS_PREC_BF16 && p->nsp == 2)
+      return fail(SIS_E_UNSUPPORTED, "the one-product BF16 contraction is not offered for two-species plans "
+                                     "(the species blocks deviate by ~1e-3 in the heat flux); use BF16X3");
     if (!p->ophi) {
       HIP_TRY(dmalloc(&p->ophi, cnt));
       HIP_TRY(dmalloc(&p->oplo, cnt));
@@ -1976,6 +1979,11 @@ sis_status sis_geometry_diffusion_info(sis_geom_t g, int32_t* n_inverse, int32_t
   return SIS_OK;
 }
 int32_t sis_geometry_moment_stride(sis_geom_t g) { return g ? g->mom_stride() : -1; }
+
+int32_t sis_geometry_sweep_form(sis_geom_t g) {
+  if (!g || !g->two_d) return -1;
+  return sis::sweep2d_form(g->max_diag);
+}
 
 sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,
                        const double* delta, const int32_t* flow, int32_t project, double* rhs_out,

@@ -163,6 +163,9 @@ struct Sweep2DArgs {
   int max_diag;              // largest min(n1, n2) over the cases (cells on an anti-diagonal)
 };
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s);
+// Kernel form launch_sweep2d takes for anti-diagonals of up to max_diag cells: the
+// cells per slot P (1..3) of sweep2d_pipelined_kernel<P>, or 0 for sweep2d_kernel.
+int sweep2d_form(int max_diag);
 // mom[cell][species][8] = {U3, q3, G1, G12, G2, P13, P23, 0}; rows of n x n x d3 velocities;
 // q3 and P13, P23 carry the species mass ratio (q3 = int (a v^2 - 5/2) v3 h, P = 2 a int v v3 h)
 hipError_t launch_moments2d(int n3, int nsp, const double* mass_ratio, int64_t n_cells, const double* vtab,

@@ -2294,17 +2294,22 @@ hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
 }
 
 
+int sweep2d_form(int max_diag) {
+  const int slots = kSweepThreads / kSweepV;
+  const int P = (max_diag + slots - 1) / slots;
+  return P <= 1 ? 1 : (P <= kSweepMaxP ? P : 0);
+}
+
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   const int hn = a.n / 2;
   const int count = hn * hn * a.d3;
   dim3 grid((count + kSweepV - 1) / kSweepV, a.n_cases, a.nsp);
-  const int slots = kSweepThreads / kSweepV;
-  const int P = (a.max_diag + slots - 1) / slots;
-  if (P <= 1)
+  const int P = sweep2d_form(a.max_diag);
+  if (P == 1)
     hipLaunchKernelGGL(sweep2d_pipelined_kernel<1>, grid, dim3(kSweepThreads), 0, s, a);
   else if (P == 2)
     hipLaunchKernelGGL(sweep2d_pipelined_kernel<2>, grid, dim3(kSweepThreads), 0, s, a);
-  else if (P <= kSweepMaxP)
+  else if (P == 3)
     hipLaunchKernelGGL(sweep2d_pipelined_kernel<3>, grid, dim3(kSweepThreads), 0, s, a);
   else
     hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(kSweepThreads), 0, s, a);

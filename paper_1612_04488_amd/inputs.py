@@ -99,6 +99,13 @@ MIX_NEAR = dict(name="mixture-near-hs-24v-201nodes-16cases", n_v=24, l_v=5.0, n_
                 flows=[1] * 16)
 
 
+# The mixture batch with uneven per-case grids (Sec. 5, Table 4 setting): the same
+# gas and 16 deltas, 100 + round(100 j / 15) tanh(3) sections for case j (101 to
+# 201 nodes), all cases in one batch.
+MIX_RAGGED = dict(MIX_NEAR, name="mixture-near-hs-24v-101to201nodes-16cases",
+                  sections=[100 + round(100 * j / 15) for j in range(16)])
+
+
 def workload_nodes(w):
     f = {"uniform": nodes_uniform, "tanh": nodes_tanh, "smoothstep": nodes_smoothstep}[w["grid"]]
     sec = w["sections"]

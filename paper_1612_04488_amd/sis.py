@@ -104,6 +104,7 @@ _SIGS = {
     "sis_geometry_destroy": (ctypes.c_int32, [_P]),
     "sis_geometry_cells": (ctypes.c_int64, [_P]),
     "sis_geometry_moment_stride": (ctypes.c_int32, [_P]),
+    "sis_geometry_sweep_form": (ctypes.c_int32, [_P]),
     "sis_geometry_diffusion_solver": (ctypes.c_int32, [_P, ctypes.c_int32, _P]),
     "sis_geometry_diffusion_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32),
                                                      ctypes.POINTER(ctypes.c_int32), _D]),
@@ -389,6 +390,11 @@ class Geometry2D:
               for a, b, c in zip(n1, n2, cases)]
         self.offsets = np.concatenate([[0], np.cumsum(fl)]).astype(np.int64)
         self.mom_stride = 8
+
+    def sweep_form(self):
+        """Kernel form of the 2-D sweep: cells per slot P (1..3) of the anti-diagonal
+        sweep, or 0 for the row-ordered sweep (anti-diagonals over 192 cells)."""
+        return int(lib().sis_geometry_sweep_form(self.handle))
 
     def diffusion_solver(self, mode, stream=None):
         """"inverse" (default: precomputed per-case inverse where it applies) or "cg"."""

@@ -264,3 +264,48 @@ def test_sweep2d_at_benchmark_size():
         assert rel(hd[s], ref[..., half:].reshape(o[c + 1] - o[c], -1)) < 1e-12, c
         mref = duct.moments_2d(vg, ref)
         assert np.max(np.abs(mom[s, :7] - mref)) < 1e-12 * np.max(np.abs(mref)), c
+
+
+def _large_sweep_case(name):
+    """Cross sections that select each wide form of the 2-D sweep: the porous
+    benchmark's 128^2 disc mask (Sec. 3.2; two cells per slot), the level-3
+    Sierpinski quarter on 135^2 cells (Sec. 3.1; three per slot) and a 200^2
+    quarter duct (Sec. 2.4; anti-diagonals over 192 cells: the row-ordered
+    sweep)."""
+    if name == "porous128":
+        f, _, mask = inputs.porous_cases(inputs.POROUS_HS)[0]
+        return "periodic", [(f, f, mask)], 2
+    if name == "carpet135":
+        return "duct", [inputs.sierpinski_quarter(3, 135)], 3
+    f = inputs.duct_faces(200, 0.5)
+    return "duct", [(f, f, None)], 0
+
+
+@pytest.mark.parametrize("name", ["porous128", "carpet135", "duct200"])
+def test_sweep2d_wide_forms_parity(name):
+    """Every wide form of the 2-D sweep the benchmarks run, element by element
+    over all cells against the oracle's sweep, on a small velocity grid (8^3) so
+    that the oracle stays cheap; the geometry reports which form it launches."""
+    n_v, l_v, m = 8, 4.0, 3
+    kind, cases, form = _large_sweep_case(name)
+    say("sweep2d wide form", name)
+    p = plan(n_v, l_v, m)
+    deltas, flows = [3.0], [1]
+    geom = sis.Geometry2D(p, kind, cases, deltas, flows)
+    assert geom.sweep_form() == form
+    f = fsm(n_v, l_v, m)
+    vg = f.grid
+    g = oracle_grids(kind, cases)[0]
+    nc = geom.n_cells
+    assert nc == len(g.cells)
+    rhs = inputs.smooth_h(n_v, l_v, nc, seed=5) + 0.1 * inputs.rough_h(n_v, l_v, nc, seed=3)
+    hprev = inputs.rough_h(n_v, l_v, nc, seed=9)
+    hd = dev(hprev.reshape(nc, -1))
+    mom = torch.empty((nc, 8), dtype=torch.float64, device=DEV)
+    sis.transport_sweep(p, geom, dev(rhs.reshape(nc, -1)), hd, mom)
+    torch.cuda.synchronize()
+    hd, mom = hd.cpu().numpy(), mom.cpu().numpy()
+    ref = duct.sweep_2d(rhs, deltas[0] * f.nu, g, vg, hprev)
+    assert rel(hd.reshape(ref.shape), ref) < 1e-12
+    mref = duct.moments_2d(vg, ref)
+    assert np.max(np.abs(mom[:, :7] - mref)) < 1e-12 * np.max(np.abs(mref))

@@ -190,6 +190,11 @@ def test_mix_rejects_unsupported_requests():
     xs, geom = _mix_geometry(p, [4], [1.0])
     with pytest.raises(sis.SisError):
         sis.solve(p, geom, project=True)
+    # the one-product BF16 contraction is one gas only (species blocks deviate ~1e-3)
+    with pytest.raises(sis.SisError) as e:
+        p.set_precision("bf16")
+    assert e.value.code == sis.SIS_E_UNSUPPORTED
+    p.set_precision("fp64")
 
 
 def test_mix_table4_equimolar_ne_ar():
