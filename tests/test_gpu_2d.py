@@ -49,7 +49,7 @@ def small_porous(n, seed):
 
 def oracle_grids(kind, cases):
     if kind == "duct":
-        return [duct.Grid2D(c[0], c[1], (duct.WALL, duct.SYM, duct.WALL, duct.SYM)) for c in cases]
+        return [duct.Grid2D(c[0], c[1], (duct.WALL, duct.SYM, duct.WALL, duct.SYM), c[2]) for c in cases]
     return [duct.Grid2D(c[0], c[1], (duct.PERIODIC,) * 4, c[2]) for c in cases]
 
 
