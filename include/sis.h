@@ -303,6 +303,40 @@ sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const 
                        const double* delta, const int32_t* flow, int32_t project,
                        double* rhs_out, double* lh_out, double* amom_out, hipStream_t stream);
 
+/* sis_collide_fsm -- the same collision step as sis_collide (same arguments,
+ * layouts, outputs and errors), with L+ evaluated per cell by the fast spectral
+ * method's transforms instead of the assembled operator (eq. LBE_collision with
+ * the FSM the paper cites in Sec. 2.4; the Carleman form of the plan comment):
+ * per cell the pruned forward DFT of h^k onto the n_pad^3 modes (half spectrum,
+ * Nyquist modes dropped), then for each of the 2D + 1 terms (psi_p and phi_p of
+ * every direction, and the loss multiplier beta) the product with the term's
+ * multiplier, the pruned inverse DFT back to the stored velocities and the
+ * product with the term's f_eq field (4 b0 W_p F^-1[phi_p F f_eq],
+ * 4 b0 W_p F^-1[psi_p F f_eq], -f_eq), summed over the terms.  Every DFT is
+ * separable and runs as small complex GEMMs on the FP64 MFMA with LDS-staged
+ * operands; FP64 regardless of sis_plan_set_precision.  One-gas Cartesian plans
+ * only (SIS_E_UNSUPPORTED otherwise, and for grids whose per-cell outputs exceed
+ * 64 x 16 x 16 stored velocities, e.g. n_v = 24 without parity storage).  The
+ * first call evaluates the multipliers on the device (T n_pad/2 (n_pad - 1)^2
+ * doubles, plan-owned) and allocates scratch (spectra and per-slab partial sums
+ * of up to ~2 GiB of cells at a time): not capturable (SIS_E_UNSUPPORTED while
+ * the stream is capturing).  Timed by sis_plan_timing like the contraction
+ * (read with sis_plan_fsm_timing_read: whole calls).                           */
+sis_status sis_collide_fsm(sis_plan_t plan, int64_t n_cells, const double* h, const double* dU,
+                           const double* delta, const int32_t* flow, int32_t project,
+                           double* rhs_out, double* lh_out, double* amom_out, hipStream_t stream);
+/* Executed flops of one cell update of sis_collide_fsm (every MFMA issued,
+ * padding included), its l1-slab width (modes per workgroup of the inverse
+ * transforms) and the device bytes of its tables; all nullable.             */
+sis_status sis_plan_fsm_info(sis_plan_t plan, double* flops_per_cell, int32_t* slab_l1, int64_t* table_bytes);
+/* l1 modes per inverse-transform workgroup (1..8; default: the widest whose LDS
+ * lets two workgroups share a CU).  Results do not depend on it beyond rounding
+ * order.                                                                     */
+sis_status sis_plan_set_fsm_slab(sis_plan_t plan, int32_t slab_l1);
+/* Summed milliseconds and number of sis_collide_fsm calls timed since
+ * sis_plan_timing enabled timing (synchronises).                              */
+sis_status sis_plan_fsm_timing_read(sis_plan_t plan, double* ms, int64_t* calls);
+
 /* sis_transport_sweep -- solve delta nu h + v . grad h = rhs per velocity
  * (eq. syn_LBE / eq. LBE_iteration) by second-order upwind differences.
  * Planar: first order at the first step from each boundary; v1 > 0: h = 0

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsis.so")
 
-SOURCES = ["kernels.hip", "api.cpp", "planner.cpp", "geom2d.cpp", "mixture.cpp", "polar.cpp"]
+SOURCES = ["kernels.hip", "fsm.hip", "api.cpp", "planner.cpp", "geom2d.cpp", "mixture.cpp", "polar.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument",

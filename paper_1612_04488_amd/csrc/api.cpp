@@ -12,6 +12,7 @@
 #include <utility>
 #include <vector>
 
+#include "fsm.h"
 #include "geom2d.h"
 #include "kernels.h"
 #include "mixture.h"
@@ -44,6 +45,14 @@ sis_status fail(sis_status code, const char* fmt, ...) {
 template <class T>
 hipError_t dmalloc(T** p, size_t count) {
   return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+}
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
+  hipError_t e = dmalloc(dst, src.size());
+  if (e != hipSuccess) return e;
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
 void dfree(void* p) {
@@ -110,10 +119,29 @@ struct sis_plan {
   Scratch ws_acc, ws_x;  // split-K partials, low-precision cell operand
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  // per-cell transform path (sis_collide_fsm; one gas, Cartesian grid): factor matrices and
+  // f_eq fields [T][nv] from plan creation, multipliers and L+ of the correction shape on
+  // first use
+  bool fsm_ok = false, fsm_ready = false;
+  sis::FsmDims fsm_d{};
+  sis::FsmFactors fsm_f{};
+  int fsm_slab = 0;
+  double* fsm_fac = nullptr;    // the 12 planar factor arrays
+  double* fsm_field = nullptr;  // [T][nv]
+  double* fsm_mult = nullptr;   // [T][Q][L][L]
+  double* fsm_Kc = nullptr;     // [nv]
+  double* fsm_dirs = nullptr;   // [D][3], then W [D]
+  double* fsm_rad = nullptr;    // radial nodes and weights
+  sis::RadialRule fsm_rule;
+  std::vector<double> fsm_corr; // correction shape 2 v3 f_eq (stored layout)
+  Scratch fsm_S, fsm_acc;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> fsm_events;
   // tuned contraction configuration per (cells, precision): tile id, split-K
   std::map<std::pair<int64_t, int>, std::pair<int, int>> gemm_choice;
   ~sis_plan() {
     for (auto& e : events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    for (auto& e : fsm_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    dfree(fsm_fac); dfree(fsm_field); dfree(fsm_mult); dfree(fsm_Kc); dfree(fsm_dirs); dfree(fsm_rad);
     dfree(op); dfree(op32); dfree(ophi); dfree(oplo);
     dfree(v1d); dfree(feq); dfree(nu); dfree(Kc); dfree(gram_inv);
     dfree(vnode); dfree(wnode); dfree(d_vr); dfree(d_cth); dfree(d_sth); dfree(vtab); dfree(wtab);
@@ -492,6 +520,84 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   return SIS_OK;
 }
 
+// Per-cell transform path: cells in chunks (spectra and per-slab partial sums in the plan's
+// scratch, at most ~2 GiB per chunk): forward DFTs, the inverse DFTs of every term with their
+// field products, then finish_kernel sums the slabs' partials and applies the epilogue.
+sis_status run_fsm_chunks(sis_plan* p, int64_t n_cells, const double* h, const double* dU, const double* delta,
+                          const int32_t* flow, int project, double* rhs, double* lh, double* amom,
+                          const double* Kc, hipStream_t s) {
+  const sis::FsmDims& d = p->fsm_d;
+  const int slabs = sis::fsm_slab_count(d, p->fsm_slab);
+  const int64_t per_s = static_cast<int64_t>(d.L) * 2 * d.Q * d.L;
+  const int64_t per_a = static_cast<int64_t>(slabs) * d.nv;
+  // cells per chunk: ~2 GiB of spectra and partials, at most 65535 (the grid's y extent)
+  const int64_t chunk = std::max<int64_t>(
+      1, std::min<int64_t>({n_cells, int64_t(65535), (int64_t(2) << 30) / (8 * (per_s + per_a))}));
+  HIP_TRY(p->fsm_S.ensure(static_cast<size_t>(chunk * per_s) * 8));
+  HIP_TRY(p->fsm_acc.ensure(static_cast<size_t>(chunk * per_a) * 8));
+  double* S = static_cast<double*>(p->fsm_S.p);
+  double* acc = static_cast<double*>(p->fsm_acc.p);
+  const int64_t nv = d.nv;
+  for (int64_t c0 = 0; c0 < n_cells; c0 += chunk) {
+    const int64_t nc = std::min(chunk, n_cells - c0);
+    HIP_TRY(sis::launch_fsm_forward(d, p->fsm_f, nc, h + c0 * nv, S, s));
+    HIP_TRY(sis::launch_fsm_inverse(d, p->fsm_f, p->fsm_slab, nc, S, p->fsm_mult, p->fsm_field, acc, s));
+    sis::FinishArgs f = finish_args(p, nc, h + c0 * nv, dU ? dU + c0 : nullptr, delta + c0, flow ? flow + c0 : nullptr,
+                                    project, rhs + c0 * nv, lh ? lh + c0 * nv : nullptr, amom ? amom + c0 * 4 : nullptr,
+                                    nullptr, 0, nullptr, nullptr);
+    f.Kc = Kc;
+    f.splits = slabs;
+    f.acc = acc;
+    HIP_TRY(sis::launch_finish(f, s));
+  }
+  return SIS_OK;
+}
+
+// Multipliers on the device and L+ of the correction shape by the transform path itself.
+sis_status ensure_fsm(sis_plan* p, hipStream_t s) {
+  if (p->fsm_ready) return SIS_OK;
+  const sis::FsmDims& d = p->fsm_d;
+  const int64_t qll = static_cast<int64_t>(d.Q) * d.L * d.L;
+  if (!p->fsm_mult) HIP_TRY(dmalloc(&p->fsm_mult, static_cast<size_t>(d.T) * qll));
+  sis::FsmMultArgs m{};
+  m.d = d;
+  m.D = p->D;
+  m.b0 = p->b0;
+  m.R = p->fsm_rule.R;
+  m.Lp = p->fsm_rule.Lp;
+  m.dirs = p->fsm_dirs;
+  m.W = p->fsm_dirs + 3 * p->D;
+  m.phi_closed = p->fsm_rule.phi_closed;
+  m.psi_closed = p->fsm_rule.psi_closed;
+  m.n_phi = static_cast<int>(p->fsm_rule.phi_x.size());
+  m.n_psi = static_cast<int>(p->fsm_rule.psi_x.size());
+  m.phi_x = p->fsm_rad;
+  m.phi_w = p->fsm_rad + m.n_phi;
+  m.psi_x = p->fsm_rad + 2 * m.n_phi;
+  m.psi_w = p->fsm_rad + 2 * m.n_phi + m.n_psi;
+  m.mult = p->fsm_mult;
+  HIP_TRY(sis::launch_fsm_multipliers(m, s));
+  if (!p->fsm_Kc) HIP_TRY(dmalloc(&p->fsm_Kc, d.nv));
+  double *dc = nullptr, *one = nullptr;
+  auto cleanup = [&]() { dfree(dc); dfree(one); };
+  hipError_t e = upload(&dc, p->fsm_corr, s);
+  const std::vector<double> v1(1, 1.0);
+  if (e == hipSuccess) e = upload(&one, v1, s);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(SIS_E_DEVICE, "transform path tables: %s", hipGetErrorString(e));
+  }
+  // rhs of one cell at delta = 1 with no source and no correction is L+ of that cell
+  sis_status st = run_fsm_chunks(p, 1, dc, nullptr, one, nullptr, 0, p->fsm_Kc, nullptr, nullptr, p->Kc, s);
+  if (st == SIS_OK) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(SIS_E_DEVICE, "transform path tables: %s", hipGetErrorString(e));
+  }
+  cleanup();
+  if (st == SIS_OK) p->fsm_ready = true;
+  return st;
+}
+
 sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, double* mom,
                      const int32_t* case_active, hipStream_t s, const int32_t* cell_active = nullptr) {
   if (g->tube) {
@@ -671,14 +777,6 @@ void set_species(sis::DiffusionArgs& a, const sis_plan* p, double N) {
 
 
 namespace {
-
-template <class T>
-hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
-  hipError_t e = dmalloc(dst, src.size());
-  if (e != hipSuccess) return e;
-  if (src.empty()) return hipSuccess;
-  return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
-}
 
 // Inverse of the finite-volume velocity operator of each 2-D case, restricted to
 // its unknown cells (those with four fluid neighbours).  A = diag(sum fw) -
@@ -1617,6 +1715,133 @@ sis_status create_polar_plan(const sis_velocity_desc* desc, hipStream_t stream, 
   return SIS_OK;
 }
 
+// Exact phase pi q / P of the centred DFT: q = l (2 j + 1 - n) reduced mod 2P.
+void fsm_phase(int l, int j, int n, int P, double& c, double& sn) {
+  const double kPi = 3.14159265358979323846;
+  long q = static_cast<long>(l) * (2 * j + 1 - n);
+  q %= 2L * P;
+  if (q < 0) q += 2L * P;
+  const double ang = kPi * static_cast<double>(q) / P;
+  c = std::cos(ang);
+  sn = std::sin(ang);
+}
+
+// Factor matrices and f_eq fields of the per-cell transform path (tables of a one-gas
+// Cartesian plan; fields are the planner's A_p, B_p scaled by 4 b0 W_p).
+sis_status build_fsm_static(sis_plan* p, const sis::HostTables& t, const sis_velocity_desc* desc,
+                            hipStream_t stream) {
+  sis::FsmDims d{};
+  d.n = p->n;
+  d.P = p->np;
+  d.L = p->np - 1;
+  d.Q = p->np / 2;
+  d.n2 = p->d2;
+  d.n3 = p->d3;
+  d.nv = p->nv;
+  d.T = 2 * p->D + 1;
+  p->fsm_d = d;
+  if (sis::fsm_unsupported(d)) return SIS_OK;   // sis_collide_fsm reports it
+  const int n = d.n, P = d.P, L = d.L, Q = d.Q, half = P / 2 - 1;
+  const int o2 = n - d.n2, o3 = n - d.n3;        // first stored node on axes 2, 3
+  const size_t sz[6] = {static_cast<size_t>(L) * n, static_cast<size_t>(L) * d.n2, static_cast<size_t>(Q) * d.n3,
+                        static_cast<size_t>(n) * L, static_cast<size_t>(d.n2) * L, static_cast<size_t>(d.n3) * Q};
+  size_t total = 0;
+  for (size_t k : sz) total += 2 * k;
+  std::vector<double> fac(total);
+  double* a[12];
+  {
+    size_t off = 0;
+    for (int k = 0; k < 6; ++k) {
+      a[2 * k] = fac.data() + off;
+      a[2 * k + 1] = fac.data() + off + sz[k];
+      off += 2 * sz[k];
+    }
+  }
+  double c, sn;
+  // forward: F1 [L][n], F2 [L][n2], F3 [Q][n3] with the images folded in
+  for (int li = 0; li < L; ++li)
+    for (int j = 0; j < n; ++j) {
+      fsm_phase(li - half, j, n, P, c, sn);
+      a[0][li * n + j] = c;
+      a[1][li * n + j] = -sn;
+    }
+  for (int li = 0; li < L; ++li)
+    for (int s2 = 0; s2 < d.n2; ++s2) {
+      fsm_phase(li - half, s2 + o2, n, P, c, sn);
+      const bool even = p->parity == 2;   // images v2 -> -v2 with sign +1
+      a[2][li * d.n2 + s2] = even ? 2.0 * c : c;
+      a[3][li * d.n2 + s2] = even ? 0.0 : -sn;
+    }
+  for (int l3 = 0; l3 < Q; ++l3)
+    for (int s3 = 0; s3 < d.n3; ++s3) {
+      fsm_phase(l3, s3 + o3, n, P, c, sn);
+      const bool odd = p->parity >= 1;    // images v3 -> -v3 with sign -1
+      a[4][l3 * d.n3 + s3] = odd ? 0.0 : c;
+      a[5][l3 * d.n3 + s3] = odd ? -2.0 * sn : -sn;
+    }
+  // inverse: E1 [n][L], E2 [n2][L], E3 [n3][Q] (2 for l3 > 0: the conjugate half)
+  for (int j = 0; j < n; ++j)
+    for (int li = 0; li < L; ++li) {
+      fsm_phase(li - half, j, n, P, c, sn);
+      a[6][j * L + li] = c;
+      a[7][j * L + li] = sn;
+    }
+  for (int s2 = 0; s2 < d.n2; ++s2)
+    for (int li = 0; li < L; ++li) {
+      fsm_phase(li - half, s2 + o2, n, P, c, sn);
+      a[8][s2 * L + li] = c;
+      a[9][s2 * L + li] = sn;
+    }
+  for (int s3 = 0; s3 < d.n3; ++s3)
+    for (int l3 = 0; l3 < Q; ++l3) {
+      fsm_phase(l3, s3 + o3, n, P, c, sn);
+      const double w = l3 == 0 ? 1.0 : 2.0;
+      a[10][s3 * Q + l3] = w * c;
+      a[11][s3 * Q + l3] = w * sn;
+    }
+  HIP_TRY(upload(&p->fsm_fac, fac, stream));
+  const double* dev[12];
+  for (int k = 0; k < 12; ++k) dev[k] = p->fsm_fac + (a[k] - fac.data());
+  p->fsm_f = sis::FsmFactors{dev[0], dev[1], dev[2], dev[3], dev[4], dev[5],
+                             dev[6], dev[7], dev[8], dev[9], dev[10], dev[11]};
+  // fields [T][nv]: B_p, A_p (already x 4 b0 W_p), -f_eq; all / P^3 (the inverse DFT's scale)
+  const double inv = 1.0 / (static_cast<double>(P) * P * P);
+  const int T = d.T, n3f = t.n3;
+  std::vector<double> full(static_cast<size_t>(T) * n3f);
+  for (int q = 0; q < p->D; ++q)
+    for (int i = 0; i < n3f; ++i) {
+      full[static_cast<size_t>(2 * q) * n3f + i] = t.B[static_cast<size_t>(q) * n3f + i] * inv;
+      full[static_cast<size_t>(2 * q + 1) * n3f + i] = t.A[static_cast<size_t>(q) * n3f + i] * inv;
+    }
+  for (int i = 0; i < n3f; ++i) full[static_cast<size_t>(2 * p->D) * n3f + i] = -t.feq[i] * inv;
+  std::vector<double> field = p->parity ? restrict_rows(p, full.data(), T) : full;
+  HIP_TRY(upload(&p->fsm_field, field, stream));
+  // directions and weights, radial rule (for the multipliers, evaluated on first use)
+  std::vector<double> ex, ey, ez, W;
+  if (!sis::half_sphere_directions(desc->m_angle, ex, ey, ez, W)) return fail(SIS_E_NUMERIC, "directions");
+  std::vector<double> dw(4 * p->D);
+  for (int q = 0; q < p->D; ++q) {
+    dw[3 * q] = ex[q];
+    dw[3 * q + 1] = ey[q];
+    dw[3 * q + 2] = ez[q];
+    dw[3 * p->D + q] = W[q];
+  }
+  HIP_TRY(upload(&p->fsm_dirs, dw, stream));
+  std::string err;
+  if (!sis::radial_rule(table_desc(desc), p->fsm_rule, err)) return fail(SIS_E_NUMERIC, "%s", err.c_str());
+  std::vector<double> rad;
+  for (double x : p->fsm_rule.phi_x) rad.push_back(x);
+  for (double x : p->fsm_rule.phi_w) rad.push_back(x);
+  for (double x : p->fsm_rule.psi_x) rad.push_back(x);
+  for (double x : p->fsm_rule.psi_w) rad.push_back(x);
+  if (rad.empty()) rad.push_back(0.0);
+  HIP_TRY(upload(&p->fsm_rad, rad, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  p->fsm_slab = sis::fsm_default_slab(d);
+  p->fsm_ok = true;
+  return SIS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1742,6 +1967,12 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
     return st;
   }
   if (p->parity) corr = restrict_rows(p, corr.data(), 1);
+  p->fsm_corr = corr;
+  if (sis_status st = build_fsm_static(p, t, desc, stream)) {
+    cleanup();
+    delete p;
+    return st;
+  }
   double* dcorr = dX;  // reuse (large enough)
   PLAN_TRY(hipMemcpyAsync(dcorr, corr.data(), corr.size() * 8, hipMemcpyHostToDevice, stream));
   {
@@ -2004,6 +2235,74 @@ sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const dou
       if (sis_status st = tune_gemm(p, n_cells, p->precision, h, &p->ws_acc, &p->ws_x, stream)) return st;
   }
   return run_collide(p, n_cells, h, dU, delta, flow, project, rhs_out, lh_out, amom_out, nullptr, stream);
+}
+
+sis_status sis_collide_fsm(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,
+                           const double* delta, const int32_t* flow, int32_t project, double* rhs_out,
+                           double* lh_out, double* amom_out, hipStream_t stream) {
+  if (sis_status st = check_plan(p)) return st;
+  if (p->nsp != 1 || p->polar) return fail(SIS_E_UNSUPPORTED, "the per-cell transform path serves one-gas Cartesian plans");
+  if (!p->fsm_ok) {
+    const char* why = sis::fsm_unsupported(p->fsm_d);
+    return fail(SIS_E_UNSUPPORTED, "%s", why ? why : "per-cell transform path unavailable");
+  }
+  if (n_cells < 0) return fail(SIS_E_SHAPE, "n_cells must be >= 0");
+  if (n_cells == 0) return SIS_OK;
+  if (n_cells > (int64_t(1) << 31)) return fail(SIS_E_SHAPE, "n_cells too large");
+  if (!h || !delta || !rhs_out) return fail(SIS_E_INVALID, "h, delta and rhs_out must be non-null");
+  if (h == rhs_out) return fail(SIS_E_INVALID, "rhs_out must not alias h");
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+      return fail(SIS_E_UNSUPPORTED, "sis_collide_fsm allocates its scratch on first use: not capturable");
+  }
+  if (sis_status st = ensure_fsm(p, stream)) return st;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (p->timing) {
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    p->fsm_events.emplace_back(a, b);
+    HIP_TRY(hipEventRecord(a, stream));
+  }
+  if (sis_status st = run_fsm_chunks(p, n_cells, h, dU, delta, flow, project, rhs_out, lh_out, amom_out, p->fsm_Kc,
+                                     stream))
+    return st;
+  if (p->timing) HIP_TRY(hipEventRecord(b, stream));
+  return SIS_OK;
+}
+
+sis_status sis_plan_fsm_info(sis_plan_t p, double* flops_per_cell, int32_t* slab_l1, int64_t* table_bytes) {
+  if (sis_status st = check_plan(p)) return st;
+  if (!p->fsm_ok) return fail(SIS_E_UNSUPPORTED, "no per-cell transform path on this plan");
+  const sis::FsmDims& d = p->fsm_d;
+  if (flops_per_cell) *flops_per_cell = sis::fsm_flops_per_cell(d, p->fsm_slab);
+  if (slab_l1) *slab_l1 = p->fsm_slab;
+  if (table_bytes)
+    *table_bytes = 8 * (static_cast<int64_t>(d.T) * d.Q * d.L * d.L + static_cast<int64_t>(d.T) * d.nv);
+  return SIS_OK;
+}
+
+sis_status sis_plan_set_fsm_slab(sis_plan_t p, int32_t slab_l1) {
+  if (sis_status st = check_plan(p)) return st;
+  if (!p->fsm_ok) return fail(SIS_E_UNSUPPORTED, "no per-cell transform path on this plan");
+  if (slab_l1 < 1 || slab_l1 > 8) return fail(SIS_E_INVALID, "slab_l1 must be in 1..8");
+  p->fsm_slab = slab_l1;
+  return SIS_OK;
+}
+
+sis_status sis_plan_fsm_timing_read(sis_plan_t p, double* ms, int64_t* calls) {
+  if (sis_status st = check_plan(p)) return st;
+  double tot = 0.0;
+  for (auto& e : p->fsm_events) {
+    HIP_TRY(hipEventSynchronize(e.second));
+    float m = 0.f;
+    HIP_TRY(hipEventElapsedTime(&m, e.first, e.second));
+    tot += m;
+  }
+  if (ms) *ms = tot;
+  if (calls) *calls = static_cast<int64_t>(p->fsm_events.size());
+  return SIS_OK;
 }
 
 sis_status sis_transport_sweep(sis_plan_t p, sis_geom_t g, const double* rhs, double* h_half_out,
@@ -2426,6 +2725,8 @@ sis_status sis_plan_timing(sis_plan_t p, int32_t enable) {
   if (sis_status st = check_plan(p)) return st;
   for (auto& e : p->events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
   p->events.clear();
+  for (auto& e : p->fsm_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  p->fsm_events.clear();
   p->timing = enable != 0;
   return SIS_OK;
 }

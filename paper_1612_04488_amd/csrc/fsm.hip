@@ -1,0 +1,457 @@
+// The fast spectral method (the collision evaluation the paper cites for eq.
+// LBE_collision) applied per cell on the device: a pruned forward DFT of each
+// cell's distribution, then for every one of the 2D + 1 terms its multiplier,
+// a pruned inverse DFT back to the stored velocities and the product with the
+// term's f_eq field, summed over the terms.  Every DFT is separable: each axis
+// is a small dense complex GEMM against a factor matrix, run on the FP64 MFMA
+// (v_mfma_f64_16x16x4) with the operands staged in LDS.  Declarations in fsm.h.
+#include "fsm.h"
+
+#include <algorithm>
+
+namespace sis {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kThreads = 256;   // four wave64s
+
+__device__ inline v4d mfma(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// C(m, n) = sum_{k < K} A(m, k) B(k, n) for the 16 x 16 NT block at (m0, n0),
+// complex planar: la(m, k, re, im), lb(k, n, re, im) fetch the operands (zero
+// outside the matrices).  Lane l holds, for tile j and element r, the entry
+// (m0 + l/16 + 4r, n0 + 16 j + l%16) (the 16x16x4 FP64 layout: A from lane
+// (row l%16, k l/16), B from lane (k l/16, column l%16)).
+template <int NT, class LA, class LB>
+__device__ inline void cgemm_block(int K, int m0, int n0, LA la, LB lb, v4d (&cr)[NT], v4d (&ci)[NT]) {
+  const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    cr[j] = v4d{0.0, 0.0, 0.0, 0.0};
+    ci[j] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    double ar, ai;
+    la(m0 + cc, k0 + kr, ar, ai);
+    const double nai = -ai;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      double br, bi;
+      lb(k0 + kr, n0 + 16 * j + cc, br, bi);
+      cr[j] = mfma(ar, br, cr[j]);
+      ci[j] = mfma(ar, bi, ci[j]);
+      cr[j] = mfma(nai, bi, cr[j]);
+      ci[j] = mfma(ai, br, ci[j]);
+    }
+  }
+}
+
+// Every (16 x 16 NT) block of an M x N complex product, blocks dealt round-robin
+// to the four waves; st(m, n, re, im) stores the entries inside the matrix.
+template <int NT, class LA, class LB, class ST>
+__device__ inline void cgemm(int M, int N, int K, LA la, LB lb, ST st) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+  const int mb = (M + 15) / 16, nbk = (N + 16 * NT - 1) / (16 * NT);
+  for (int blk = wave; blk < mb * nbk; blk += 4) {
+    const int m0 = (blk / nbk) * 16, n0 = (blk % nbk) * 16 * NT;
+    v4d cr[NT], ci[NT];
+    cgemm_block<NT>(K, m0, n0, la, lb, cr, ci);
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + kr + 4 * r, n = n0 + 16 * j + cc;
+        if (m < M && n < N) st(m, n, cr[j][r], ci[j][r]);
+      }
+  }
+}
+
+// ---------------------------------------------------------------- multipliers
+__device__ double phi_closed(double s, double R, double Lp) {
+  // 2 int_0^R rho cos(b rho) d rho, b = |pi s / Lp|; power series for small b R
+  const double b = fabs(M_PI * s / Lp);
+  const double x = b * R;
+  if (x < 0.5) {
+    double term = 1.0, acc = 0.5;
+    for (int k = 1; k < 12; ++k) {
+      term *= -(x * x) / ((2.0 * k - 1.0) * (2.0 * k));
+      acc += term / (2.0 * k + 2.0);
+    }
+    return 2.0 * R * R * acc;
+  }
+  return 2.0 * (R * sin(x) / b + (cos(x) - 1.0) / (b * b));
+}
+
+__global__ __launch_bounds__(256) void fsm_mult_kernel(FsmMultArgs a) {
+  const FsmDims d = a.d;
+  const int64_t qll = static_cast<int64_t>(d.Q) * d.L * d.L;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= qll) return;
+  const int l2i = static_cast<int>(idx % d.L);
+  const int l1i = static_cast<int>((idx / d.L) % d.L);
+  const int l3 = static_cast<int>(idx / (static_cast<int64_t>(d.L) * d.L));
+  const double l1 = l1i - (d.P / 2 - 1), l2 = l2i - (d.P / 2 - 1), l3d = l3;
+  double beta = 0.0;
+  for (int p = 0; p < a.D; ++p) {
+    const double ex = a.dirs[3 * p], ey = a.dirs[3 * p + 1], ez = a.dirs[3 * p + 2];
+    const double s = l1 * ex + l2 * ey + l3d * ez;
+    const double q0 = l1 - s * ex, q1 = l2 - s * ey, q2 = l3d - s * ez;
+    const double perp = sqrt(fmax(q0 * q0 + q1 * q1 + q2 * q2, 0.0));
+    double ph, ps;
+    if (a.phi_closed) {
+      ph = phi_closed(s, a.R, a.Lp);
+    } else {
+      const double b = fabs(M_PI * s / a.Lp);
+      double acc = 0.0;
+      for (int k = 0; k < a.n_phi; ++k) acc += a.phi_w[k] * cos(b * a.phi_x[k]);
+      ph = 2.0 * acc;
+    }
+    if (a.psi_closed) {
+      const double c = M_PI * a.R * perp / a.Lp;
+      ps = c == 0.0 ? M_PI * a.R * a.R : 2.0 * M_PI * a.R * a.R * j1(c) / c;
+    } else {
+      const double b = M_PI * perp / a.Lp;
+      double acc = 0.0;
+      for (int k = 0; k < a.n_psi; ++k) acc += a.psi_w[k] * j0(b * a.psi_x[k]);
+      ps = 2.0 * M_PI * acc;
+    }
+    a.mult[static_cast<int64_t>(2 * p) * qll + idx] = ps;
+    a.mult[static_cast<int64_t>(2 * p + 1) * qll + idx] = ph;
+    beta += a.W[p] * ph * ps;
+  }
+  a.mult[static_cast<int64_t>(2 * a.D) * qll + idx] = 4.0 * a.b0 * beta;
+}
+
+// ---------------------------------------------------------------- forward
+// One workgroup per (cell, chunk of B3 l3 modes):
+//   T1(l3, j1, s2) = sum_s3 F3(l3, s3) h(j1, s2, s3)
+//   T2(l3, l2, j1) = sum_s2 F2(l2, s2) T1(l3, j1, s2)
+//   S(l1, l3, l2)  = sum_j1 F1(l1, j1) T2(l3, l2, j1)
+__global__ __launch_bounds__(kThreads) void fsm_forward_kernel(FsmDims d, FsmFactors f, int B3,
+                                                               const double* __restrict__ h,
+                                                               double* __restrict__ S) {
+  extern __shared__ double sm[];
+  const int64_t cell = blockIdx.y;
+  const int q0 = blockIdx.x * B3;
+  const int nq = min(B3, d.Q - q0);
+  const int n = d.n, n2 = d.n2, n3 = d.n3, L = d.L, Q = d.Q;
+  double* T1r = sm;                      // [B3][n][n2]
+  double* T1i = T1r + B3 * n * n2;
+  double* T2r = T1i + B3 * n * n2;       // [B3][L][n]
+  double* T2i = T2r + B3 * L * n;
+  const double* hc = h + cell * d.nv;
+  {
+    const int M = nq, K = n3, N = n * n2;
+    auto la = [&](int m, int k, double& re, double& im) {
+      const bool ok = m < M && k < K;
+      re = ok ? f.f3r[(q0 + m) * n3 + k] : 0.0;
+      im = ok ? f.f3i[(q0 + m) * n3 + k] : 0.0;
+    };
+    auto lb = [&](int k, int c, double& re, double& im) {
+      re = (k < K && c < N) ? hc[static_cast<int64_t>(c) * n3 + k] : 0.0;
+      im = 0.0;
+    };
+    auto st = [&](int m, int c, double re, double im) {
+      T1r[m * N + c] = re;
+      T1i[m * N + c] = im;
+    };
+    cgemm<2>(M, N, K, la, lb, st);
+  }
+  __syncthreads();
+  {
+    const int M = L, K = n2, N = nq * n;   // column c = (l3c, j1)
+    auto la = [&](int m, int k, double& re, double& im) {
+      const bool ok = m < M && k < K;
+      re = ok ? f.f2r[m * n2 + k] : 0.0;
+      im = ok ? f.f2i[m * n2 + k] : 0.0;
+    };
+    auto lb = [&](int k, int c, double& re, double& im) {
+      const bool ok = k < K && c < N;
+      re = ok ? T1r[c * n2 + k] : 0.0;
+      im = ok ? T1i[c * n2 + k] : 0.0;
+    };
+    auto st = [&](int m, int c, double re, double im) {
+      const int l3c = c / n, j1 = c - l3c * n;
+      T2r[(l3c * L + m) * n + j1] = re;
+      T2i[(l3c * L + m) * n + j1] = im;
+    };
+    cgemm<2>(M, N, K, la, lb, st);
+  }
+  __syncthreads();
+  {
+    const int M = L, K = n, N = nq * L;    // column c = (l3c, l2)
+    auto la = [&](int m, int k, double& re, double& im) {
+      const bool ok = m < M && k < K;
+      re = ok ? f.f1r[m * n + k] : 0.0;
+      im = ok ? f.f1i[m * n + k] : 0.0;
+    };
+    auto lb = [&](int k, int c, double& re, double& im) {
+      const bool ok = k < K && c < N;
+      re = ok ? T2r[c * n + k] : 0.0;
+      im = ok ? T2i[c * n + k] : 0.0;
+    };
+    double* Sc = S + cell * static_cast<int64_t>(L) * 2 * Q * L;
+    auto st = [&](int m, int c, double re, double im) {
+      const int l3c = c / L, l2 = c - l3c * L;
+      const int64_t o = (static_cast<int64_t>(m) * 2 * Q + (q0 + l3c)) * L + l2;
+      Sc[o] = re;
+      Sc[o + static_cast<int64_t>(Q) * L] = im;
+    };
+    cgemm<2>(M, N, K, la, lb, st);
+  }
+}
+
+// ---------------------------------------------------------------- inverse
+// One workgroup per (cell, slab of B1 l1 modes).  The slab of the spectrum stays
+// in LDS for all terms; per term t:
+//   stage 1  Y1(s3, b, l2) = sum_l3 E3(s3, l3) m_t(l3, l1, l2) S(l1, l3, l2)
+//   stage 2  Y2(b, s2, s3) = sum_l2 E2(s2, l2) Y1(s3, b, l2)
+//   stage 3  G(j1, s2, s3) += field_t(j1, s2, s3) Re sum_b E1(j1, l1) Y2(b, s2, s3)
+// (l1 = l10 + b).  G stays in registers: stage-3 tile q of wave w is tile w + 4q.
+template <int MAXG>
+__global__ __launch_bounds__(kThreads) void fsm_inverse_kernel(FsmDims d, FsmFactors f, int B1,
+                                                               const double* __restrict__ S,
+                                                               const double* __restrict__ mult,
+                                                               const double* __restrict__ field,
+                                                               double* __restrict__ accp, int64_t n_cells) {
+  extern __shared__ double sm[];
+  const int slab = blockIdx.x;
+  const int64_t cell = blockIdx.y;
+  const int n = d.n, n2 = d.n2, n3 = d.n3, L = d.L, Q = d.Q;
+  const int l10 = slab * B1, nb = min(B1, L - l10);
+  const int NB = B1 * L;
+  double* Sr = sm;                 // [Q][B1][L]
+  double* Si = Sr + Q * NB;
+  double* Y1r = Si + Q * NB;       // [n3][B1][L]
+  double* Y1i = Y1r + n3 * NB;
+  const int N3c = n2 * n3;
+  double* Y2r = Y1i + n3 * NB;     // [B1][n2][n3]
+  double* Y2i = Y2r + B1 * N3c;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+
+  const double* Sc = S + (cell * L + l10) * 2 * static_cast<int64_t>(Q) * L;
+  for (int i = threadIdx.x; i < nb * 2 * Q * L; i += kThreads) {
+    const int l2 = i % L;
+    int r = i / L;
+    const int l3 = r % Q;
+    r /= Q;
+    const int ri = r & 1, b = r >> 1;
+    (ri ? Si : Sr)[l3 * NB + b * L + l2] = Sc[i];
+  }
+  __syncthreads();
+
+  const int nb3 = (N3c + 15) / 16;
+  const int tiles3 = ((n + 15) / 16) * nb3;
+  v4d G[MAXG];
+#pragma unroll
+  for (int q = 0; q < MAXG; ++q) G[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int64_t qll = static_cast<int64_t>(Q) * L * L;
+
+  for (int t = 0; t < d.T; ++t) {
+    const double* mt = mult + t * qll + static_cast<int64_t>(l10) * L;
+    {
+      const int M = n3, K = Q, N = nb * L;
+      auto la = [&](int m, int k, double& re, double& im) {
+        const bool ok = m < M && k < K;
+        re = ok ? f.e3r[m * Q + k] : 0.0;
+        im = ok ? f.e3i[m * Q + k] : 0.0;
+      };
+      auto lb = [&](int k, int c, double& re, double& im) {
+        if (k < K && c < N) {
+          const double mv = mt[static_cast<int64_t>(k) * L * L + c];
+          re = mv * Sr[k * NB + c];
+          im = mv * Si[k * NB + c];
+        } else {
+          re = im = 0.0;
+        }
+      };
+      auto st = [&](int m, int c, double re, double im) {
+        Y1r[m * NB + c] = re;
+        Y1i[m * NB + c] = im;
+      };
+      cgemm<1>(M, N, K, la, lb, st);
+    }
+    __syncthreads();
+    {
+      const int M = n2, K = L, N = n3;
+      const int mb = (M + 15) / 16, nbk = (N + 15) / 16;
+      for (int blk = wave; blk < nb * mb * nbk; blk += 4) {
+        const int b = blk / (mb * nbk), rem = blk - b * mb * nbk;
+        const int m0 = (rem / nbk) * 16, n0 = (rem % nbk) * 16;
+        auto la = [&](int m, int k, double& re, double& im) {
+          const bool ok = m < M && k < K;
+          re = ok ? f.e2r[m * L + k] : 0.0;
+          im = ok ? f.e2i[m * L + k] : 0.0;
+        };
+        auto lb = [&](int k, int c, double& re, double& im) {
+          const bool ok = k < K && c < N;
+          re = ok ? Y1r[c * NB + b * L + k] : 0.0;
+          im = ok ? Y1i[c * NB + b * L + k] : 0.0;
+        };
+        v4d cr[1], ci[1];
+        cgemm_block<1>(K, m0, n0, la, lb, cr, ci);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + kr + 4 * r, c = n0 + cc;
+          if (m < M && c < N) {
+            Y2r[(b * n2 + m) * n3 + c] = cr[0][r];
+            Y2i[(b * n2 + m) * n3 + c] = ci[0][r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const double* ft = field + static_cast<int64_t>(t) * d.nv;
+#pragma unroll
+      for (int q = 0; q < MAXG; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile < tiles3) {
+          const int m0 = (tile / nb3) * 16, n0 = (tile % nb3) * 16;
+          v4d o = v4d{0.0, 0.0, 0.0, 0.0};
+          for (int k0 = 0; k0 < 2 * B1; k0 += 4) {
+            const int kk = k0 + kr;
+            const int ri = kk / B1, b = kk - ri * B1;
+            const bool okk = kk < 2 * B1 && b < nb;
+            double av = 0.0, bv = 0.0;
+            if (okk && m0 + cc < n) {
+              const int e = (m0 + cc) * L + l10 + b;
+              av = ri ? -f.e1i[e] : f.e1r[e];
+            }
+            if (okk && n0 + cc < N3c) bv = (ri ? Y2i : Y2r)[b * N3c + n0 + cc];
+            o = mfma(av, bv, o);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j1 = m0 + kr + 4 * r, c = n0 + cc;
+            if (j1 < n && c < N3c) G[q][r] += ft[j1 * N3c + c] * o[r];
+          }
+        }
+      }
+    }
+  }
+  double* out = accp + (static_cast<int64_t>(slab) * n_cells + cell) * d.nv;
+#pragma unroll
+  for (int q = 0; q < MAXG; ++q) {
+    const int tile = wave + 4 * q;
+    if (tile < tiles3) {
+      const int m0 = (tile / nb3) * 16, n0 = (tile % nb3) * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j1 = m0 + kr + 4 * r, c = n0 + cc;
+        if (j1 < n && c < N3c) out[j1 * N3c + c] = G[q][r];
+      }
+    }
+  }
+}
+
+int stage3_tiles_per_wave(const FsmDims& d) {
+  const int tiles = ((d.n + 15) / 16) * ((d.n2 * d.n3 + 15) / 16);
+  return (tiles + 3) / 4;
+}
+
+size_t forward_lds_bytes(const FsmDims& d, int B3) {
+  return static_cast<size_t>(2 * B3 * d.n * d.n2 + 2 * B3 * d.L * d.n) * sizeof(double);
+}
+
+// l3 modes per forward workgroup: the most (up to 4) whose LDS fits two workgroups per CU
+int forward_chunk(const FsmDims& d) {
+  int B3 = 4;
+  while (B3 > 1 && forward_lds_bytes(d, B3) > 80 * 1024) --B3;
+  return B3;
+}
+
+size_t inverse_lds_bytes(const FsmDims& d, int B1) {
+  const size_t NB = static_cast<size_t>(B1) * d.L;
+  return (2 * d.Q * NB + 2 * d.n3 * NB + 2 * static_cast<size_t>(B1) * d.n2 * d.n3) * sizeof(double);
+}
+
+constexpr size_t kLdsMax = 160 * 1024;
+
+}  // namespace
+
+hipError_t launch_fsm_multipliers(const FsmMultArgs& a, hipStream_t s) {
+  const int64_t qll = static_cast<int64_t>(a.d.Q) * a.d.L * a.d.L;
+  hipLaunchKernelGGL(fsm_mult_kernel, dim3(static_cast<unsigned>((qll + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fsm_forward(const FsmDims& d, const FsmFactors& f, int64_t n_cells, const double* h, double* S,
+                              hipStream_t s) {
+  if (n_cells <= 0) return hipSuccess;
+  const int B3 = forward_chunk(d);
+  const size_t lds = forward_lds_bytes(d, B3);
+  if (lds > kLdsMax) return hipErrorInvalidValue;
+  dim3 grid((d.Q + B3 - 1) / B3, static_cast<unsigned>(n_cells));
+  hipLaunchKernelGGL(fsm_forward_kernel, grid, dim3(kThreads), lds, s, d, f, B3, h, S);
+  return hipGetLastError();
+}
+
+int fsm_slab_count(const FsmDims& d, int slab_l1) { return (d.L + slab_l1 - 1) / slab_l1; }
+
+int fsm_default_slab(const FsmDims& d) {
+  int B1 = 4;
+  while (B1 > 1 && inverse_lds_bytes(d, B1) > 80 * 1024) --B1;
+  return B1;
+}
+
+const char* fsm_unsupported(const FsmDims& d) {
+  if (stage3_tiles_per_wave(d) > 16)
+    return "the per-cell transform path holds at most 64 x 16 x 16 outputs per cell (use parity storage)";
+  if (inverse_lds_bytes(d, 1) > kLdsMax || forward_lds_bytes(d, 1) > kLdsMax)
+    return "velocity grid too large for the per-cell transform path";
+  return nullptr;
+}
+
+hipError_t launch_fsm_inverse(const FsmDims& d, const FsmFactors& f, int slab_l1, int64_t n_cells, const double* S,
+                              const double* mult, const double* field, double* acc, hipStream_t s) {
+  if (n_cells <= 0) return hipSuccess;
+  const size_t lds = inverse_lds_bytes(d, slab_l1);
+  if (lds > kLdsMax) return hipErrorInvalidValue;
+  dim3 grid(fsm_slab_count(d, slab_l1), static_cast<unsigned>(n_cells));
+  const int g = stage3_tiles_per_wave(d);
+  if (g <= 4)
+    hipLaunchKernelGGL(fsm_inverse_kernel<4>, grid, dim3(kThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
+                       n_cells);
+  else if (g <= 8)
+    hipLaunchKernelGGL(fsm_inverse_kernel<8>, grid, dim3(kThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
+                       n_cells);
+  else if (g <= 12)
+    hipLaunchKernelGGL(fsm_inverse_kernel<12>, grid, dim3(kThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
+                       n_cells);
+  else if (g <= 16)
+    hipLaunchKernelGGL(fsm_inverse_kernel<16>, grid, dim3(kThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
+                       n_cells);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+double fsm_flops_per_cell(const FsmDims& d, int slab_l1) {
+  // MFMAs issued (2048 flops each): forward stages, then per slab and term the three inverse stages
+  auto t16 = [](int x) { return static_cast<double>((x + 15) / 16); };
+  auto k4 = [](int x) { return static_cast<double>((x + 3) / 4); };
+  double fwd = 0.0;
+  const int B3 = forward_chunk(d);
+  for (int q0 = 0; q0 < d.Q; q0 += B3) {
+    const int nq = std::min(B3, d.Q - q0);
+    fwd += t16(nq) * t16(d.n * d.n2) * k4(d.n3) * 4.0;
+    fwd += t16(d.L) * t16(nq * d.n) * k4(d.n2) * 4.0;
+    fwd += t16(d.L) * t16(nq * d.L) * k4(d.n) * 4.0;
+  }
+  double inv = 0.0;
+  const int slabs = fsm_slab_count(d, slab_l1);
+  for (int sl = 0; sl < slabs; ++sl) {
+    const int nb = std::min(slab_l1, d.L - sl * slab_l1);
+    const double s1 = t16(d.n3) * t16(nb * d.L) * k4(d.Q) * 4.0;
+    const double s2 = nb * t16(d.n2) * t16(d.n3) * k4(d.L) * 4.0;
+    const double s3 = t16(d.n) * t16(d.n2 * d.n3) * k4(2 * slab_l1);
+    inv += d.T * (s1 + s2 + s3);
+  }
+  return 2048.0 * (fwd + inv);
+}
+
+}  // namespace sis

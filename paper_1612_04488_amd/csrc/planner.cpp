@@ -244,7 +244,38 @@ bool mapped_rule(int n, double a, double R, Quadrature& q) {
   return true;
 }
 
+bool radial_setup(const TableDesc& d, Radial& rad, std::string& err) {
+  const int n = d.n_v;
+  const int np = d.n_pad > 0 ? d.n_pad : 2 * n;
+  const double dv = 2.0 * d.l_v / n;
+  rad.Lp = np * dv / 2.0;
+  rad.R = d.r_trunc > 0.0 ? d.r_trunc : 4.0 * rad.Lp / (3.0 + std::sqrt(2.0));
+  rad.a_phi = d.alpha + d.gamma;
+  rad.gamma = d.gamma;
+  rad.phi_closed = std::fabs(rad.a_phi - 1.0) < 1e-15;
+  rad.psi_closed = d.gamma == 0.0;
+  const double smax = std::sqrt(3.0) * 0.5 * np + 1.0;
+  const int nq = 48 + static_cast<int>(0.8 * kPi * smax * rad.R / rad.Lp);
+  if (!rad.phi_closed && !mapped_rule(nq, rad.a_phi, rad.R, rad.qphi)) { err = "Gauss-Jacobi failed"; return false; }
+  if (!rad.psi_closed && !mapped_rule(nq, 1.0 - d.gamma, rad.R, rad.qpsi)) { err = "Gauss-Jacobi failed"; return false; }
+  return true;
+}
+
 }  // namespace
+
+bool radial_rule(const TableDesc& d, RadialRule& r, std::string& err) {
+  Radial rad;
+  if (!radial_setup(d, rad, err)) return false;
+  r.R = rad.R;
+  r.Lp = rad.Lp;
+  r.phi_closed = rad.phi_closed;
+  r.psi_closed = rad.psi_closed;
+  r.phi_x = rad.qphi.x;
+  r.phi_w = rad.qphi.w;
+  r.psi_x = rad.qpsi.x;
+  r.psi_w = rad.qpsi.w;
+  return true;
+}
 
 bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std::string& err) {
   const int n = d.n_v;
@@ -281,16 +312,7 @@ bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std
 
   // radial factors
   Radial rad;
-  rad.R = t.R;
-  rad.Lp = t.Lp;
-  rad.a_phi = d.alpha + d.gamma;
-  rad.gamma = d.gamma;
-  rad.phi_closed = std::fabs(rad.a_phi - 1.0) < 1e-15;
-  rad.psi_closed = d.gamma == 0.0;
-  const double smax = std::sqrt(3.0) * 0.5 * np + 1.0;
-  const int nq = 48 + static_cast<int>(0.8 * kPi * smax * t.R / t.Lp);
-  if (!rad.phi_closed && !mapped_rule(nq, rad.a_phi, t.R, rad.qphi)) { err = "Gauss-Jacobi failed"; return false; }
-  if (!rad.psi_closed && !mapped_rule(nq, 1.0 - d.gamma, t.R, rad.qpsi)) { err = "Gauss-Jacobi failed"; return false; }
+  if (!radial_setup(d, rad, err)) return false;
 
   // signed modes per index; Nyquist flag
   std::vector<int> lsig(np);

@@ -47,6 +47,17 @@ struct HostTables {
   std::vector<double> beta_r;       // [nd3]    real-space loss kernel F^-1[beta]
 };
 
+// Radial factors phi(s), psi(t) as the planner evaluates them: closed forms for
+// alpha + gamma = 1 (phi) and gamma = 0 (psi), else Gauss-Jacobi rules mapped to
+// [0, R] with the weight rho^(alpha+gamma) (phi) or rho^(1-gamma) (psi):
+//   phi(s) = 2 sum_k w_k cos(|pi s / Lp| x_k),  psi(t) = 2 pi sum_k w_k J0(pi t x_k / Lp).
+struct RadialRule {
+  double R = 0, Lp = 0;
+  bool phi_closed = true, psi_closed = true;
+  std::vector<double> phi_x, phi_w, psi_x, psi_w;
+};
+bool radial_rule(const TableDesc& d, RadialRule& r, std::string& err);
+
 // Build all tables.  want_kernels = false skips Psi/Phi/beta_r (cheaper).
 bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std::string& err);
 

@@ -109,6 +109,10 @@ _SIGS = {
     "sis_geometry_diffusion_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32),
                                                      ctypes.POINTER(ctypes.c_int32), _D]),
     "sis_collide": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
+    "sis_collide_fsm": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
+    "sis_plan_fsm_info": (ctypes.c_int32, [_P, _D, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
+    "sis_plan_set_fsm_slab": (ctypes.c_int32, [_P, ctypes.c_int32]),
+    "sis_plan_fsm_timing_read": (ctypes.c_int32, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
     "sis_transport_sweep": (ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
     "sis_moments": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P]),
     "sis_diffusion_correct": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_double, _P, _P, _P]),
@@ -286,6 +290,23 @@ class Plan:
                                 1 if project else 0, _ptr(rhs_out), _ptr(lh_out), _ptr(amom_out),
                                 _stream(stream)))
 
+    def collide_fsm(self, h, delta, rhs_out, dU=None, flow=None, project=False, lh_out=None,
+                    amom_out=None, stream=None):
+        """sis_collide with L+ from the per-cell transforms of the fast spectral method."""
+        n_cells = h.shape[0]
+        check(lib().sis_collide_fsm(self.handle, n_cells, _ptr(h), _ptr(dU), _ptr(delta), _ptr(flow),
+                                    1 if project else 0, _ptr(rhs_out), _ptr(lh_out), _ptr(amom_out),
+                                    _stream(stream)))
+
+    def fsm_info(self):
+        """Executed flops per cell update, l1-slab width and table bytes of the transform path."""
+        f, s, b = ctypes.c_double(), ctypes.c_int32(), ctypes.c_int64()
+        check(lib().sis_plan_fsm_info(self.handle, ctypes.byref(f), ctypes.byref(s), ctypes.byref(b)))
+        return {"flops_per_cell": f.value, "slab_l1": s.value, "table_bytes": b.value}
+
+    def set_fsm_slab(self, slab_l1):
+        check(lib().sis_plan_set_fsm_slab(self.handle, int(slab_l1)))
+
     def set_contraction_config(self, n_cells, tile_rows, k_stage, splits, precision="fp64"):
         """Fix the contraction configuration for n_cells cells instead of tuning it."""
         check(lib().sis_plan_set_contraction_config(self.handle, int(n_cells), PRECISIONS.get(precision, precision),
@@ -303,9 +324,12 @@ class Plan:
     def timing(self, enable):
         check(lib().sis_plan_timing(self.handle, 1 if enable else 0))
 
-    def timing_read(self):
+    def timing_read(self, fsm=False):
+        """(summed ms, launches) of the timed contractions, or with fsm=True of the
+        timed sis_collide_fsm calls."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
-        check(lib().sis_plan_timing_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        fn = lib().sis_plan_fsm_timing_read if fsm else lib().sis_plan_timing_read
+        check(fn(self.handle, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
     def moments(self, h, mom_out, stream=None):
