@@ -2286,7 +2286,8 @@ sis_status sis_plan_fsm_info(sis_plan_t p, double* flops_per_cell, int32_t* slab
 sis_status sis_plan_set_fsm_slab(sis_plan_t p, int32_t slab_l1) {
   if (sis_status st = check_plan(p)) return st;
   if (!p->fsm_ok) return fail(SIS_E_UNSUPPORTED, "no per-cell transform path on this plan");
-  if (slab_l1 < 1 || slab_l1 > 8) return fail(SIS_E_INVALID, "slab_l1 must be in 1..8");
+  if (slab_l1 < 1 || slab_l1 > 8 || !sis::fsm_slab_fits(p->fsm_d, slab_l1))
+    return fail(SIS_E_INVALID, "slab_l1 must be in 1..8 with the inverse transforms' LDS within 160 KiB");
   p->fsm_slab = slab_l1;
   return SIS_OK;
 }

@@ -63,6 +63,8 @@ hipError_t launch_fsm_forward(const FsmDims& d, const FsmFactors& f, int64_t n_c
 // slabs' partial sums add up to L+ of each cell at delta = 1.
 int fsm_slab_count(const FsmDims& d, int slab_l1);
 int fsm_default_slab(const FsmDims& d);
+// whether the inverse kernel's LDS holds a slab of slab_l1 modes
+bool fsm_slab_fits(const FsmDims& d, int slab_l1);
 // 0 if the dimensions are within what the inverse kernel holds in registers
 // (stage-3 output tiles per wave), else the reason.
 const char* fsm_unsupported(const FsmDims& d);

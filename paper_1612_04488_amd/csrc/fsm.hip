@@ -205,14 +205,22 @@ __global__ __launch_bounds__(kThreads) void fsm_forward_kernel(FsmDims d, FsmFac
 }
 
 // ---------------------------------------------------------------- inverse
-// One workgroup per (cell, slab of B1 l1 modes).  The slab of the spectrum stays
-// in LDS for all terms; per term t:
+// One workgroup per (cell, slab of B1 l1 modes).  The slab of the spectrum and the
+// factor matrices stay in LDS for all terms; per term t:
 //   stage 1  Y1(s3, b, l2) = sum_l3 E3(s3, l3) m_t(l3, l1, l2) S(l1, l3, l2)
-//   stage 2  Y2(b, s2, s3) = sum_l2 E2(s2, l2) Y1(s3, b, l2)
+//   stage 2  Y2(b, s2, s3) = sum_l2 Y1(s3, b, l2) E2(s2, l2)      (rows (s3, b))
 //   stage 3  G(j1, s2, s3) += field_t(j1, s2, s3) Re sum_b E1(j1, l1) Y2(b, s2, s3)
-// (l1 = l10 + b).  G stays in registers: stage-3 tile q of wave w is tile w + 4q.
+// (l1 = l10 + b).  Each block's operands for all its k-steps (stage 1) or four
+// k-steps at a time (stage 2) are loaded before its MFMAs, so one load latency is
+// paid per block or chunk, not per k-step.  G stays in registers: stage-3 tile q
+// of wave w is tile w + 4q.
+constexpr int kKs1 = 8;   // stage-1 k-steps held in registers: Q <= 32 (n_pad <= 64)
+
+constexpr int kInvWaves = 8;
+constexpr int kInvThreads = 64 * kInvWaves;
+
 template <int MAXG>
-__global__ __launch_bounds__(kThreads) void fsm_inverse_kernel(FsmDims d, FsmFactors f, int B1,
+__global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, FsmFactors f, int B1,
                                                                const double* __restrict__ S,
                                                                const double* __restrict__ mult,
                                                                const double* __restrict__ field,
@@ -223,23 +231,42 @@ __global__ __launch_bounds__(kThreads) void fsm_inverse_kernel(FsmDims d, FsmFac
   const int n = d.n, n2 = d.n2, n3 = d.n3, L = d.L, Q = d.Q;
   const int l10 = slab * B1, nb = min(B1, L - l10);
   const int NB = B1 * L;
+  const int N3c = n2 * n3;
   double* Sr = sm;                 // [Q][B1][L]
   double* Si = Sr + Q * NB;
   double* Y1r = Si + Q * NB;       // [n3][B1][L]
   double* Y1i = Y1r + n3 * NB;
-  const int N3c = n2 * n3;
   double* Y2r = Y1i + n3 * NB;     // [B1][n2][n3]
   double* Y2i = Y2r + B1 * N3c;
+  double* E3r = Y2i + B1 * N3c;    // [n3][Q]
+  double* E3i = E3r + n3 * Q;
+  double* E2r = E3i + n3 * Q;      // [n2][L]
+  double* E2i = E2r + n2 * L;
+  double* E1r = E2i + n2 * L;      // [n][B1] (the slab's columns)
+  double* E1i = E1r + n * B1;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
 
   const double* Sc = S + (cell * L + l10) * 2 * static_cast<int64_t>(Q) * L;
-  for (int i = threadIdx.x; i < nb * 2 * Q * L; i += kThreads) {
+  for (int i = threadIdx.x; i < nb * 2 * Q * L; i += kInvThreads) {
     const int l2 = i % L;
     int r = i / L;
     const int l3 = r % Q;
     r /= Q;
     const int ri = r & 1, b = r >> 1;
     (ri ? Si : Sr)[l3 * NB + b * L + l2] = Sc[i];
+  }
+  for (int i = threadIdx.x; i < n3 * Q; i += kInvThreads) {
+    E3r[i] = f.e3r[i];
+    E3i[i] = f.e3i[i];
+  }
+  for (int i = threadIdx.x; i < n2 * L; i += kInvThreads) {
+    E2r[i] = f.e2r[i];
+    E2i[i] = f.e2i[i];
+  }
+  for (int i = threadIdx.x; i < n * B1; i += kInvThreads) {
+    const int j1 = i / B1, b = i - j1 * B1;
+    E1r[i] = b < nb ? f.e1r[j1 * L + l10 + b] : 0.0;
+    E1i[i] = b < nb ? f.e1i[j1 * L + l10 + b] : 0.0;
   }
   __syncthreads();
 
@@ -248,57 +275,87 @@ __global__ __launch_bounds__(kThreads) void fsm_inverse_kernel(FsmDims d, FsmFac
   v4d G[MAXG];
 #pragma unroll
   for (int q = 0; q < MAXG; ++q) G[q] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int64_t qll = static_cast<int64_t>(Q) * L * L;
+  const int64_t LL = static_cast<int64_t>(L) * L;
+  const int64_t qll = static_cast<int64_t>(Q) * LL;
+  const int nks1 = (Q + 3) / 4, nks2 = (L + 3) / 4;
 
   for (int t = 0; t < d.T; ++t) {
     const double* mt = mult + t * qll + static_cast<int64_t>(l10) * L;
     {
-      const int M = n3, K = Q, N = nb * L;
-      auto la = [&](int m, int k, double& re, double& im) {
-        const bool ok = m < M && k < K;
-        re = ok ? f.e3r[m * Q + k] : 0.0;
-        im = ok ? f.e3i[m * Q + k] : 0.0;
-      };
-      auto lb = [&](int k, int c, double& re, double& im) {
-        if (k < K && c < N) {
-          const double mv = mt[static_cast<int64_t>(k) * L * L + c];
-          re = mv * Sr[k * NB + c];
-          im = mv * Si[k * NB + c];
-        } else {
-          re = im = 0.0;
+      // stage 1: M = n3, N = nb L, K = Q
+      const int M = n3, N = nb * L;
+      const int mb = (M + 15) / 16, nbk = (N + 15) / 16;
+      for (int blk = wave; blk < mb * nbk; blk += kInvWaves) {
+        const int m0 = (blk / nbk) * 16, n0 = (blk % nbk) * 16;
+        const int m = m0 + cc, c = n0 + cc;
+        double ar[kKs1], ai[kKs1], br[kKs1], bi[kKs1];
+#pragma unroll
+        for (int ks = 0; ks < kKs1; ++ks) {
+          const int k = ks * 4 + kr;
+          const bool oka = ks < nks1 && k < Q && m < M;
+          const bool okb = ks < nks1 && k < Q && c < N;
+          ar[ks] = oka ? E3r[m * Q + k] : 0.0;
+          ai[ks] = oka ? -E3i[m * Q + k] : 0.0;   // negated: the imaginary product enters cr with a minus
+          const double mv = okb ? mt[k * LL + c] : 0.0;
+          br[ks] = okb ? mv * Sr[k * NB + c] : 0.0;
+          bi[ks] = okb ? mv * Si[k * NB + c] : 0.0;
         }
-      };
-      auto st = [&](int m, int c, double re, double im) {
-        Y1r[m * NB + c] = re;
-        Y1i[m * NB + c] = im;
-      };
-      cgemm<1>(M, N, K, la, lb, st);
+        v4d cr = v4d{0.0, 0.0, 0.0, 0.0}, ci = cr;
+#pragma unroll
+        for (int ks = 0; ks < kKs1; ++ks)
+          if (ks < nks1) {
+            cr = mfma(ar[ks], br[ks], cr);
+            ci = mfma(ar[ks], bi[ks], ci);
+            cr = mfma(ai[ks], bi[ks], cr);
+            ci = mfma(-ai[ks], br[ks], ci);
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + kr + 4 * r;
+          if (row < M && c < N) {
+            Y1r[row * NB + c] = cr[r];
+            Y1i[row * NB + c] = ci[r];
+          }
+        }
+      }
     }
     __syncthreads();
     {
-      const int M = n2, K = L, N = n3;
+      // stage 2: rows r = (s3, b) (M = n3 B1), columns s2 (N = n2), K = L
+      const int M = n3 * B1, N = n2;
       const int mb = (M + 15) / 16, nbk = (N + 15) / 16;
-      for (int blk = wave; blk < nb * mb * nbk; blk += 4) {
-        const int b = blk / (mb * nbk), rem = blk - b * mb * nbk;
-        const int m0 = (rem / nbk) * 16, n0 = (rem % nbk) * 16;
-        auto la = [&](int m, int k, double& re, double& im) {
-          const bool ok = m < M && k < K;
-          re = ok ? f.e2r[m * L + k] : 0.0;
-          im = ok ? f.e2i[m * L + k] : 0.0;
-        };
-        auto lb = [&](int k, int c, double& re, double& im) {
-          const bool ok = k < K && c < N;
-          re = ok ? Y1r[c * NB + b * L + k] : 0.0;
-          im = ok ? Y1i[c * NB + b * L + k] : 0.0;
-        };
-        v4d cr[1], ci[1];
-        cgemm_block<1>(K, m0, n0, la, lb, cr, ci);
+      for (int blk = wave; blk < mb * nbk; blk += kInvWaves) {
+        const int m0 = (blk / nbk) * 16, n0 = (blk % nbk) * 16;
+        const int r = m0 + cc, s2 = n0 + cc;
+        const bool rowok = r < M && (r % B1) < nb, colok = s2 < N;
+        v4d cr = v4d{0.0, 0.0, 0.0, 0.0}, ci = cr;
+        for (int kc = 0; kc < nks2; kc += 4) {
+          double ar[4], ai[4], br[4], bi[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + kr + 4 * r, c = n0 + cc;
-          if (m < M && c < N) {
-            Y2r[(b * n2 + m) * n3 + c] = cr[0][r];
-            Y2i[(b * n2 + m) * n3 + c] = ci[0][r];
+          for (int u = 0; u < 4; ++u) {
+            const int k = (kc + u) * 4 + kr;
+            const bool ok = kc + u < nks2 && k < L;
+            ar[u] = ok && rowok ? Y1r[r * L + k] : 0.0;
+            ai[u] = ok && rowok ? Y1i[r * L + k] : 0.0;
+            br[u] = ok && colok ? E2r[s2 * L + k] : 0.0;
+            bi[u] = ok && colok ? E2i[s2 * L + k] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (kc + u < nks2) {
+              cr = mfma(ar[u], br[u], cr);
+              ci = mfma(ar[u], bi[u], ci);
+              cr = mfma(-ai[u], bi[u], cr);
+              ci = mfma(ai[u], br[u], ci);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = m0 + kr + 4 * q, col = n0 + cc;
+          const int s3 = row / B1, b = row - s3 * B1;
+          if (row < M && b < nb && col < N) {
+            Y2r[(b * n2 + col) * n3 + s3] = cr[q];
+            Y2i[(b * n2 + col) * n3 + s3] = ci[q];
           }
         }
       }
@@ -308,27 +365,27 @@ __global__ __launch_bounds__(kThreads) void fsm_inverse_kernel(FsmDims d, FsmFac
       const double* ft = field + static_cast<int64_t>(t) * d.nv;
 #pragma unroll
       for (int q = 0; q < MAXG; ++q) {
-        const int tile = wave + 4 * q;
+        const int tile = wave + kInvWaves * q;
         if (tile < tiles3) {
           const int m0 = (tile / nb3) * 16, n0 = (tile % nb3) * 16;
+          double fv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j1 = m0 + kr + 4 * r, c = n0 + cc;
+            fv[r] = (j1 < n && c < N3c) ? ft[j1 * N3c + c] : 0.0;
+          }
           v4d o = v4d{0.0, 0.0, 0.0, 0.0};
           for (int k0 = 0; k0 < 2 * B1; k0 += 4) {
             const int kk = k0 + kr;
             const int ri = kk / B1, b = kk - ri * B1;
             const bool okk = kk < 2 * B1 && b < nb;
             double av = 0.0, bv = 0.0;
-            if (okk && m0 + cc < n) {
-              const int e = (m0 + cc) * L + l10 + b;
-              av = ri ? -f.e1i[e] : f.e1r[e];
-            }
+            if (okk && m0 + cc < n) av = ri ? -E1i[(m0 + cc) * B1 + b] : E1r[(m0 + cc) * B1 + b];
             if (okk && n0 + cc < N3c) bv = (ri ? Y2i : Y2r)[b * N3c + n0 + cc];
             o = mfma(av, bv, o);
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int j1 = m0 + kr + 4 * r, c = n0 + cc;
-            if (j1 < n && c < N3c) G[q][r] += ft[j1 * N3c + c] * o[r];
-          }
+          for (int r = 0; r < 4; ++r) G[q][r] += fv[r] * o[r];
         }
       }
     }
@@ -336,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void fsm_inverse_kernel(FsmDims d, FsmFac
   double* out = accp + (static_cast<int64_t>(slab) * n_cells + cell) * d.nv;
 #pragma unroll
   for (int q = 0; q < MAXG; ++q) {
-    const int tile = wave + 4 * q;
+    const int tile = wave + kInvWaves * q;
     if (tile < tiles3) {
       const int m0 = (tile / nb3) * 16, n0 = (tile % nb3) * 16;
 #pragma unroll
@@ -350,7 +407,7 @@ __global__ __launch_bounds__(kThreads) void fsm_inverse_kernel(FsmDims d, FsmFac
 
 int stage3_tiles_per_wave(const FsmDims& d) {
   const int tiles = ((d.n + 15) / 16) * ((d.n2 * d.n3 + 15) / 16);
-  return (tiles + 3) / 4;
+  return (tiles + kInvWaves - 1) / kInvWaves;
 }
 
 size_t forward_lds_bytes(const FsmDims& d, int B3) {
@@ -366,7 +423,9 @@ int forward_chunk(const FsmDims& d) {
 
 size_t inverse_lds_bytes(const FsmDims& d, int B1) {
   const size_t NB = static_cast<size_t>(B1) * d.L;
-  return (2 * d.Q * NB + 2 * d.n3 * NB + 2 * static_cast<size_t>(B1) * d.n2 * d.n3) * sizeof(double);
+  return (2 * d.Q * NB + 2 * d.n3 * NB + 2 * static_cast<size_t>(B1) * d.n2 * d.n3 +
+          2 * static_cast<size_t>(d.n3) * d.Q + 2 * static_cast<size_t>(d.n2) * d.L + 2 * static_cast<size_t>(d.n) * B1) *
+         sizeof(double);
 }
 
 constexpr size_t kLdsMax = 160 * 1024;
@@ -394,13 +453,18 @@ int fsm_slab_count(const FsmDims& d, int slab_l1) { return (d.L + slab_l1 - 1) /
 
 int fsm_default_slab(const FsmDims& d) {
   int B1 = 4;
-  while (B1 > 1 && inverse_lds_bytes(d, B1) > 80 * 1024) --B1;
+  while (B1 > 1 && inverse_lds_bytes(d, B1) > kLdsMax) --B1;
   return B1;
 }
 
+bool fsm_slab_fits(const FsmDims& d, int slab_l1) {
+  return slab_l1 >= 1 && slab_l1 <= d.L && inverse_lds_bytes(d, slab_l1) <= kLdsMax;
+}
+
 const char* fsm_unsupported(const FsmDims& d) {
-  if (stage3_tiles_per_wave(d) > 16)
+  if (stage3_tiles_per_wave(d) > 8)
     return "the per-cell transform path holds at most 64 x 16 x 16 outputs per cell (use parity storage)";
+  if (d.Q > 4 * kKs1) return "the per-cell transform path takes n_pad <= 64";
   if (inverse_lds_bytes(d, 1) > kLdsMax || forward_lds_bytes(d, 1) > kLdsMax)
     return "velocity grid too large for the per-cell transform path";
   return nullptr;
@@ -413,17 +477,17 @@ hipError_t launch_fsm_inverse(const FsmDims& d, const FsmFactors& f, int slab_l1
   if (lds > kLdsMax) return hipErrorInvalidValue;
   dim3 grid(fsm_slab_count(d, slab_l1), static_cast<unsigned>(n_cells));
   const int g = stage3_tiles_per_wave(d);
-  if (g <= 4)
-    hipLaunchKernelGGL(fsm_inverse_kernel<4>, grid, dim3(kThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
+  if (g <= 2)
+    hipLaunchKernelGGL(fsm_inverse_kernel<2>, grid, dim3(kInvThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
+                       n_cells);
+  else if (g <= 4)
+    hipLaunchKernelGGL(fsm_inverse_kernel<4>, grid, dim3(kInvThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
+                       n_cells);
+  else if (g <= 6)
+    hipLaunchKernelGGL(fsm_inverse_kernel<6>, grid, dim3(kInvThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
                        n_cells);
   else if (g <= 8)
-    hipLaunchKernelGGL(fsm_inverse_kernel<8>, grid, dim3(kThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
-                       n_cells);
-  else if (g <= 12)
-    hipLaunchKernelGGL(fsm_inverse_kernel<12>, grid, dim3(kThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
-                       n_cells);
-  else if (g <= 16)
-    hipLaunchKernelGGL(fsm_inverse_kernel<16>, grid, dim3(kThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
+    hipLaunchKernelGGL(fsm_inverse_kernel<8>, grid, dim3(kInvThreads), lds, s, d, f, slab_l1, S, mult, field, acc,
                        n_cells);
   else
     return hipErrorInvalidValue;
@@ -447,7 +511,7 @@ double fsm_flops_per_cell(const FsmDims& d, int slab_l1) {
   for (int sl = 0; sl < slabs; ++sl) {
     const int nb = std::min(slab_l1, d.L - sl * slab_l1);
     const double s1 = t16(d.n3) * t16(nb * d.L) * k4(d.Q) * 4.0;
-    const double s2 = nb * t16(d.n2) * t16(d.n3) * k4(d.L) * 4.0;
+    const double s2 = t16(d.n3 * slab_l1) * t16(d.n2) * k4(d.L) * 4.0;
     const double s3 = t16(d.n) * t16(d.n2 * d.n3) * k4(2 * slab_l1);
     inv += d.T * (s1 + s2 + s3);
   }
