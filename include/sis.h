@@ -303,6 +303,23 @@ sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const 
                        const double* delta, const int32_t* flow, int32_t project,
                        double* rhs_out, double* lh_out, double* amom_out, hipStream_t stream);
 
+/* sis_collide_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the collision step of sis_collide (same arguments, layouts, outputs and
+ * errors) that calls no hipMalloc, hipFree or allocating routine.  Its workspace
+ * (the low-precision copy of h for FP32 / BF16X3 / BF16 plans, then the split-K
+ * partial sums) is a fixed 64 MiB device array inside the library, one per GPU,
+ * held until the process ends.  It runs the plan's contraction configuration for
+ * this n_cells and precision (tuned by an earlier sis_collide, else the default
+ * heuristic; it never tunes), with the split-K count lowered until the partials
+ * fit; a low-precision operand of more than 64 MiB (n_cells * n_dof * 4 bytes)
+ * is rejected with SIS_E_SHAPE before anything is enqueued.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads, other plans) race and must be ordered by the caller.              */
+sis_status sis_collide_noalloc(sis_plan_t plan, int64_t n_cells, const double* h, const double* dU,
+                               const double* delta, const int32_t* flow, int32_t project,
+                               double* rhs_out, double* lh_out, double* amom_out, hipStream_t stream);
+
 /* sis_collide_fsm -- the same collision step as sis_collide (same arguments,
  * layouts, outputs and errors), with L+ evaluated per cell by the fast spectral
  * method's transforms instead of the assembled operator (eq. LBE_collision with

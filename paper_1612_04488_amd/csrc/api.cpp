@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -76,6 +77,34 @@ struct Scratch {
   }
   ~Scratch() { dfree(p); }
 };
+
+// Workspace of sis_collide_noalloc: a file-scope device array (one copy per GPU,
+// held until the process ends), so that the call allocates nothing.  Host code
+// never uses the array's name as an address: static_scratch() returns the device
+// address from hipGetSymbolAddress, looked up once per device with that device
+// current.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -2235,6 +2264,76 @@ sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const dou
       if (sis_status st = tune_gemm(p, n_cells, p->precision, h, &p->ws_acc, &p->ws_x, stream)) return st;
   }
   return run_collide(p, n_cells, h, dU, delta, flow, project, rhs_out, lh_out, amom_out, nullptr, stream);
+}
+
+sis_status sis_collide_noalloc(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,
+                               const double* delta, const int32_t* flow, int32_t project, double* rhs_out,
+                               double* lh_out, double* amom_out, hipStream_t stream) {
+  if (sis_status st = check_plan(p)) return st;
+  if (n_cells < 0) return fail(SIS_E_SHAPE, "n_cells must be >= 0");
+  if (n_cells == 0) return SIS_OK;
+  if (n_cells > (int64_t(1) << 31)) return fail(SIS_E_SHAPE, "n_cells too large");
+  if (!h || !delta || !rhs_out) return fail(SIS_E_INVALID, "h, delta and rhs_out must be non-null");
+  if (!aligned16(h) || !aligned16(rhs_out)) return fail(SIS_E_INVALID, "h and rhs_out must be 16-byte aligned");
+  if (h == rhs_out) return fail(SIS_E_INVALID, "rhs_out must not alias h");
+  if (project && p->nsp != 1) return fail(SIS_E_UNSUPPORTED, "invariant projection is for one gas only");
+  if (project && p->polar) return fail(SIS_E_UNSUPPORTED, "invariant projection is for the Cartesian grids");
+  // the plan's configuration for this shape (tuned by earlier sis_collide calls, else the
+  // default heuristic); no tuning here, since tuning allocates
+  const int precision = p->precision;
+  int tile, splits;
+  const auto tuned = p->gemm_choice.find(std::make_pair(n_cells, precision));
+  if (tuned != p->gemm_choice.end()) {
+    tile = tuned->second.first;
+    splits = tuned->second.second;
+  } else {
+    choose_gemm(n_cells, p->ndof, &tile, &splits);
+  }
+  const int64_t cnt = n_cells * static_cast<int64_t>(p->ndof);
+  // low-precision cell operand first in the scratch (4 bytes per unknown), then the split-K
+  // partials; the split count is lowered until the partials fit (one split needs none)
+  const size_t xbytes = precision == SIS_PREC_FP64 ? 0 : ((static_cast<size_t>(cnt) * 4 + 255) / 256) * 256;
+  if (xbytes > kStaticScratchBytes)
+    return fail(SIS_E_SHAPE, "sis_collide_noalloc: the low-precision cell operand needs %zu bytes, more than its "
+                             "%zu-byte workspace (use fewer cells per call)", xbytes, kStaticScratchBytes);
+  while (splits > 1 && xbytes + static_cast<size_t>(splits) * cnt * sizeof(double) > kStaticScratchBytes) --splits;
+  void* base = nullptr;
+  {
+    const hipError_t e = static_scratch(&base);
+    if (e != hipSuccess) return fail(SIS_E_DEVICE, "workspace address: %s", hipGetErrorString(e));
+  }
+  unsigned char* ws = static_cast<unsigned char*>(base);
+  sis::GemmArgs g{};
+  g.precision = precision;
+  g.X = h;
+  if (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) {
+    uint16_t* hx = reinterpret_cast<uint16_t*>(ws);
+    HIP_TRY(sis::launch_split_x(h, nullptr, cnt, hx, precision == SIS_PREC_BF16X3 ? hx + cnt : nullptr, stream));
+    g.Xh = hx;
+    g.Xl = precision == SIS_PREC_BF16X3 ? hx + cnt : nullptr;
+  } else if (precision == SIS_PREC_FP32) {
+    float* fx = reinterpret_cast<float*>(ws);
+    HIP_TRY(sis::launch_convert_x_f32(h, nullptr, cnt, fx, stream));
+    g.X32 = fx;
+  }
+  double* acc = splits > 1 ? reinterpret_cast<double*>(ws + xbytes) : rhs_out;
+  g.op64 = p->op;
+  g.op32 = p->op32;
+  g.ophi = p->ophi;
+  g.oplo = p->oplo;
+  g.acc = acc;
+  g.M = n_cells;
+  g.N = p->ndof;
+  g.K = p->ndof;
+  g.splits = splits;
+  g.tile = tile;
+  HIP_TRY(sis::launch_gemm(g, stream));
+  sis::FinishArgs f = finish_args(p, n_cells, h, dU, delta, flow, project, rhs_out, lh_out, amom_out, nullptr, 0,
+                                  nullptr, nullptr);
+  f.splits = splits;
+  f.acc = acc;
+  HIP_TRY(sis::launch_finish(f, stream));
+  return SIS_OK;
 }
 
 sis_status sis_collide_fsm(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,

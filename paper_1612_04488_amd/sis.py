@@ -109,6 +109,7 @@ _SIGS = {
     "sis_geometry_diffusion_info": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32),
                                                      ctypes.POINTER(ctypes.c_int32), _D]),
     "sis_collide": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
+    "sis_collide_noalloc": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     "sis_collide_fsm": (ctypes.c_int32, [_P, ctypes.c_int64, _P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P]),
     "sis_plan_fsm_info": (ctypes.c_int32, [_P, _D, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "sis_plan_set_fsm_slab": (ctypes.c_int32, [_P, ctypes.c_int32]),
@@ -289,6 +290,14 @@ class Plan:
         check(lib().sis_collide(self.handle, n_cells, _ptr(h), _ptr(dU), _ptr(delta), _ptr(flow),
                                 1 if project else 0, _ptr(rhs_out), _ptr(lh_out), _ptr(amom_out),
                                 _stream(stream)))
+
+    def collide_noalloc(self, h, delta, rhs_out, dU=None, flow=None, project=False, lh_out=None,
+                        amom_out=None, stream=None):
+        """sis_collide with the library's fixed device workspace (no allocation)."""
+        n_cells = h.shape[0]
+        check(lib().sis_collide_noalloc(self.handle, n_cells, _ptr(h), _ptr(dU), _ptr(delta), _ptr(flow),
+                                        1 if project else 0, _ptr(rhs_out), _ptr(lh_out), _ptr(amom_out),
+                                        _stream(stream)))
 
     def collide_fsm(self, h, delta, rhs_out, dU=None, flow=None, project=False, lh_out=None,
                     amom_out=None, stream=None):
