@@ -6,7 +6,8 @@
   form must equal it to rounding: this pins the pointwise-product /
   convolution bookkeeping, the zero extension, the Nyquist handling and the
   normalisation of the FFT implementation.
-* `sigma_quadrature_L`: L(h)(v) from the plain definition eq. LBE_collision
+* `sigma_quadrature_L` (hard spheres) and `sigma_quadrature_L_ipl` (inverse
+  power law, any alpha with gamma = 0): L(h)(v) from the plain definition eq. LBE_collision
   (sigma representation, hard spheres B = b0 |u|) for h = f_eq p(v) with p a
   polynomial: with f(v') f(v*') = f(v) f(v*),
   L(h)(v) = b0 f(v) int dv* f(v*) |u| int dsigma [p(v') + p(v*') - p(v) - p(v*)],
@@ -107,6 +108,57 @@ def sigma_quadrature_L(v, poly, b0, nr=96, nu_ang=(24, 48), ns=(8, 16), rmax=Non
         vsp = G[:, None, :] - 0.5 * ri * sg[None, :, :]
         br = (poly(vp) + poly(vsp)) @ wsg - 4.0 * math.pi * (pv + poly(vs))
         total += wri * ri ** 2 * ri * np.sum(wom * f(vs) * br)
+    return b0 * f(v) * total
+
+
+def _jacobi_gauss(n, a):
+    """Nodes and weights of int_{-1}^{1} (1 - x)^a g(x) dx (Gauss-Jacobi)."""
+    from scipy import special
+    return special.roots_jacobi(n, a, 0.0)
+
+
+def sigma_quadrature_L_ipl(v, poly, b0, alpha, nr=96, nu_ang=(24, 48), nx=32, nphi=48, rmax=None):
+    """L(f_eq p)(v) at one point v from eq. LBE_collision for the kernel
+    B = b0 |u|^alpha sin^(alpha-1)(theta/2) (sigma representation, gamma = 0;
+    hard spheres at alpha = 1):
+      L(h)(v) = f(v) int dv* f(v*) int dsigma B [p(v') + p(v*') - p(v) - p(v*)],
+      v', v*' = (v + v*)/2 +- |u| sigma / 2,  cos theta = sigma . u/|u|.
+    sigma is parametrised about u: x = cos theta by a Gauss-Jacobi rule whose
+    weight (1 - x)^((alpha-1)/2) carries the grazing-angle factor
+    sin^(alpha-1)(theta/2) = ((1 - x)/2)^((alpha-1)/2), and the azimuth by the
+    periodic trapezoid rule; u = v - v* by Gauss rules in |u| and direction.
+    No FSM choice (truncation, directions, padding, spectral step) enters."""
+    v = np.asarray(v, dtype=np.float64)
+    rmax = rmax or (np.linalg.norm(v) + 8.0)
+    r, wr = _gauss(0.0, rmax, nr)
+    om, wom = sphere_rule(*nu_ang)
+    a = 0.5 * (alpha - 1.0)
+    x, wx = _jacobi_gauss(nx, a)
+    wx = wx * 2.0 ** (-a)                         # ((1 - x)/2)^a = 2^-a (1 - x)^a
+    ph = 2.0 * math.pi * np.arange(nphi) / nphi
+    wsig = np.outer(wx, np.full(nphi, 2.0 * math.pi / nphi)).ravel()   # over (x, phi)
+    sx = np.sqrt(np.maximum(1.0 - x * x, 0.0))
+    f = lambda y: np.exp(-np.sum(y * y, axis=-1)) / math.pi ** 1.5
+    pv = poly(v)
+    # orthonormal frame (om, e1, e2) for every direction of u
+    t = np.where(np.abs(om[:, 2:3]) < 0.9, np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]]))
+    e1 = np.cross(om, t)
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(om, e1)
+    # sigma[u-direction, (x, phi), 3]
+    sig = (x[None, :, None, None] * om[:, None, None, :]
+           + (sx[:, None] * np.cos(ph)[None, :])[None, :, :, None] * e1[:, None, None, :]
+           + (sx[:, None] * np.sin(ph)[None, :])[None, :, :, None] * e2[:, None, None, :])
+    sig = sig.reshape(len(om), -1, 3)
+    total = 0.0
+    for ri, wri in zip(r, wr):
+        u = ri * om
+        vs = v - u
+        G = 0.5 * (v + vs)
+        vp = G[:, None, :] + 0.5 * ri * sig
+        vsp = G[:, None, :] - 0.5 * ri * sig
+        br = (poly(vp) + poly(vsp)) @ wsig - np.sum(wsig) * (pv + poly(vs))
+        total += wri * ri ** 2 * ri ** alpha * np.sum(wom * f(vs) * br)
     return b0 * f(v) * total
 
 
