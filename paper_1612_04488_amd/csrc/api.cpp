@@ -582,30 +582,11 @@ sis_status run_fsm_chunks(sis_plan* p, int64_t n_cells, const double* h, const d
   return SIS_OK;
 }
 
-// Multipliers on the device and L+ of the correction shape by the transform path itself.
+// L+ of the correction shape by the transform path itself (the multipliers and fields are
+// built with the plan).
 sis_status ensure_fsm(sis_plan* p, hipStream_t s) {
   if (p->fsm_ready) return SIS_OK;
   const sis::FsmDims& d = p->fsm_d;
-  const int64_t qll = static_cast<int64_t>(d.Q) * d.L * d.L;
-  if (!p->fsm_mult) HIP_TRY(dmalloc(&p->fsm_mult, static_cast<size_t>(d.T) * qll));
-  sis::FsmMultArgs m{};
-  m.d = d;
-  m.D = p->D;
-  m.b0 = p->b0;
-  m.R = p->fsm_rule.R;
-  m.Lp = p->fsm_rule.Lp;
-  m.dirs = p->fsm_dirs;
-  m.W = p->fsm_dirs + 3 * p->D;
-  m.phi_closed = p->fsm_rule.phi_closed;
-  m.psi_closed = p->fsm_rule.psi_closed;
-  m.n_phi = static_cast<int>(p->fsm_rule.phi_x.size());
-  m.n_psi = static_cast<int>(p->fsm_rule.psi_x.size());
-  m.phi_x = p->fsm_rad;
-  m.phi_w = p->fsm_rad + m.n_phi;
-  m.psi_x = p->fsm_rad + 2 * m.n_phi;
-  m.psi_w = p->fsm_rad + 2 * m.n_phi + m.n_psi;
-  m.mult = p->fsm_mult;
-  HIP_TRY(sis::launch_fsm_multipliers(m, s));
   if (!p->fsm_Kc) HIP_TRY(dmalloc(&p->fsm_Kc, d.nv));
   double *dc = nullptr, *one = nullptr;
   auto cleanup = [&]() { dfree(dc); dfree(one); };
@@ -1744,10 +1725,9 @@ sis_status create_polar_plan(const sis_velocity_desc* desc, hipStream_t stream, 
   return SIS_OK;
 }
 
-// Exact phase pi q / P of the centred DFT: q = l (2 j + 1 - n) reduced mod 2P.
-void fsm_phase(int l, int j, int n, int P, double& c, double& sn) {
+// cos, sin of the exact phase pi q / P (q reduced mod 2P in integers).
+void phase_q(long q, int P, double& c, double& sn) {
   const double kPi = 3.14159265358979323846;
-  long q = static_cast<long>(l) * (2 * j + 1 - n);
   q %= 2L * P;
   if (q < 0) q += 2L * P;
   const double ang = kPi * static_cast<double>(q) / P;
@@ -1755,18 +1735,24 @@ void fsm_phase(int l, int j, int n, int P, double& c, double& sn) {
   sn = std::sin(ang);
 }
 
-// Factor matrices and f_eq fields of the per-cell transform path (tables of a one-gas
-// Cartesian plan; fields are the planner's A_p, B_p scaled by 4 b0 W_p).
-sis_status build_fsm_static(sis_plan* p, const sis::HostTables& t, const sis_velocity_desc* desc,
-                            hipStream_t stream) {
+// Phase xi_l v_j of the centred DFT: v_j = (j + 1/2 - n/2) dv, xi_l = pi l / L_p, so
+// xi_l v_j = pi l (2 j + 1 - n) / P.
+void fsm_phase(int l, int j, int n, int P, double& c, double& sn) {
+  phase_q(static_cast<long>(l) * (2 * j + 1 - n), P, c, sn);
+}
+
+// Factor matrices and f_eq fields of the per-cell transform path (one-gas Cartesian plan
+// with the given parity storage).  dX holds the full-grid fields of the assembly,
+// [B_p; A_p] already scaled by 4 b0 W_p; dfeq the full-grid f_eq.
+sis_status build_fsm_static(sis_plan* p, int parity, const double* dX, const double* dfeq, hipStream_t stream) {
   sis::FsmDims d{};
   d.n = p->n;
   d.P = p->np;
   d.L = p->np - 1;
   d.Q = p->np / 2;
-  d.n2 = p->d2;
-  d.n3 = p->d3;
-  d.nv = p->nv;
+  d.n2 = parity == 2 ? p->n / 2 : p->n;
+  d.n3 = parity >= 1 ? p->n / 2 : p->n;
+  d.nv = d.n * d.n2 * d.n3;
   d.T = 2 * p->D + 1;
   p->fsm_d = d;
   if (sis::fsm_unsupported(d)) return SIS_OK;   // sis_collide_fsm reports it
@@ -1797,14 +1783,14 @@ sis_status build_fsm_static(sis_plan* p, const sis::HostTables& t, const sis_vel
   for (int li = 0; li < L; ++li)
     for (int s2 = 0; s2 < d.n2; ++s2) {
       fsm_phase(li - half, s2 + o2, n, P, c, sn);
-      const bool even = p->parity == 2;   // images v2 -> -v2 with sign +1
+      const bool even = parity == 2;      // images v2 -> -v2 with sign +1
       a[2][li * d.n2 + s2] = even ? 2.0 * c : c;
       a[3][li * d.n2 + s2] = even ? 0.0 : -sn;
     }
   for (int l3 = 0; l3 < Q; ++l3)
     for (int s3 = 0; s3 < d.n3; ++s3) {
       fsm_phase(l3, s3 + o3, n, P, c, sn);
-      const bool odd = p->parity >= 1;    // images v3 -> -v3 with sign -1
+      const bool odd = parity >= 1;       // images v3 -> -v3 with sign -1
       a[4][l3 * d.n3 + s3] = odd ? 0.0 : c;
       a[5][l3 * d.n3 + s3] = odd ? -2.0 * sn : -sn;
     }
@@ -1833,19 +1819,29 @@ sis_status build_fsm_static(sis_plan* p, const sis::HostTables& t, const sis_vel
   for (int k = 0; k < 12; ++k) dev[k] = p->fsm_fac + (a[k] - fac.data());
   p->fsm_f = sis::FsmFactors{dev[0], dev[1], dev[2], dev[3], dev[4], dev[5],
                              dev[6], dev[7], dev[8], dev[9], dev[10], dev[11]};
-  // fields [T][nv]: B_p, A_p (already x 4 b0 W_p), -f_eq; all / P^3 (the inverse DFT's scale)
-  const double inv = 1.0 / (static_cast<double>(P) * P * P);
-  const int T = d.T, n3f = t.n3;
-  std::vector<double> full(static_cast<size_t>(T) * n3f);
-  for (int q = 0; q < p->D; ++q)
-    for (int i = 0; i < n3f; ++i) {
-      full[static_cast<size_t>(2 * q) * n3f + i] = t.B[static_cast<size_t>(q) * n3f + i] * inv;
-      full[static_cast<size_t>(2 * q + 1) * n3f + i] = t.A[static_cast<size_t>(q) * n3f + i] * inv;
-    }
-  for (int i = 0; i < n3f; ++i) full[static_cast<size_t>(2 * p->D) * n3f + i] = -t.feq[i] * inv;
-  std::vector<double> field = p->parity ? restrict_rows(p, full.data(), T) : full;
-  HIP_TRY(upload(&p->fsm_field, field, stream));
-  // directions and weights, radial rule (for the multipliers, evaluated on first use)
+  // fields [T][nv] of the stored velocities: term 2p (multiplier psi_p) carries B_p, term
+  // 2p + 1 (phi_p) carries A_p, the loss term -f_eq; all / P^3 (the inverse DFT's scale)
+  std::vector<int> src(d.T);
+  for (int q = 0; q < p->D; ++q) {
+    src[2 * q] = q;
+    src[2 * q + 1] = p->D + q;
+  }
+  src[2 * p->D] = -1;
+  int* dsrc = nullptr;
+  HIP_TRY(upload(&dsrc, src, stream));
+  hipError_t e = dmalloc(&p->fsm_field, static_cast<size_t>(d.T) * d.nv);
+  if (e == hipSuccess)
+    e = sis::launch_fsm_gather(d, d.T, dX, dsrc, dfeq, 1.0 / (static_cast<double>(P) * P * P), p->fsm_field, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  dfree(dsrc);
+  if (e != hipSuccess) return fail(SIS_E_DEVICE, "transform path tables: %s", hipGetErrorString(e));
+  p->fsm_slab = sis::fsm_default_slab(d);
+  p->fsm_ok = true;
+  return SIS_OK;
+}
+
+// Directions, weights, the radial rule and the multipliers [T][Q][L][L] on the device.
+sis_status build_fsm_multipliers(sis_plan* p, const sis_velocity_desc* desc, hipStream_t stream) {
   std::vector<double> ex, ey, ez, W;
   if (!sis::half_sphere_directions(desc->m_angle, ex, ey, ez, W)) return fail(SIS_E_NUMERIC, "directions");
   std::vector<double> dw(4 * p->D);
@@ -1865,9 +1861,151 @@ sis_status build_fsm_static(sis_plan* p, const sis::HostTables& t, const sis_vel
   for (double x : p->fsm_rule.psi_w) rad.push_back(x);
   if (rad.empty()) rad.push_back(0.0);
   HIP_TRY(upload(&p->fsm_rad, rad, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  p->fsm_slab = sis::fsm_default_slab(d);
-  p->fsm_ok = true;
+  sis::FsmDims d{};
+  d.n = p->n;
+  d.P = p->np;
+  d.L = p->np - 1;
+  d.Q = p->np / 2;
+  d.n2 = d.n3 = p->n;
+  d.nv = p->n3;
+  d.T = 2 * p->D + 1;
+  const int64_t qll = static_cast<int64_t>(d.Q) * d.L * d.L;
+  HIP_TRY(dmalloc(&p->fsm_mult, static_cast<size_t>(d.T) * qll));
+  sis::FsmMultArgs m{};
+  m.d = d;
+  m.D = p->D;
+  m.b0 = p->b0;
+  m.R = p->fsm_rule.R;
+  m.Lp = p->fsm_rule.Lp;
+  m.dirs = p->fsm_dirs;
+  m.W = p->fsm_dirs + 3 * p->D;
+  m.phi_closed = p->fsm_rule.phi_closed;
+  m.psi_closed = p->fsm_rule.psi_closed;
+  m.n_phi = static_cast<int>(p->fsm_rule.phi_x.size());
+  m.n_psi = static_cast<int>(p->fsm_rule.psi_x.size());
+  m.phi_x = p->fsm_rad;
+  m.phi_w = p->fsm_rad + m.n_phi;
+  m.psi_x = p->fsm_rad + 2 * m.n_phi;
+  m.psi_w = p->fsm_rad + 2 * m.n_phi + m.n_psi;
+  m.mult = p->fsm_mult;
+  HIP_TRY(sis::launch_fsm_multipliers(m, stream));
+  return SIS_OK;
+}
+
+// Tables of the assembly by the fast spectral method's own transforms on the device: with
+// the multipliers m_t, the spectrum fhat of the zero-extended f_eq (separable, on the host)
+// and pruned inverse DFTs onto the velocity nodes and the difference grid,
+//   dX = [B_p; A_p] x 4 b0 W_p and nu  (fields F^-1[m_t fhat] on the n^3 nodes),
+//   dY = [Psi_p; Phi_p] and beta_r     (kernels F^-1[m_t] on d in [-(n-1), n-1]^3).
+sis_status build_tables_device(sis_plan* p, const sis::HostTables& t, double* dX, double* dY, hipStream_t stream) {
+  const int n = t.n, P = t.np, L = P - 1, Q = P / 2, half = P / 2 - 1, D = t.D, T = 2 * D + 1, nd = t.nd;
+  sis::FsmDims d{};
+  d.n = n;
+  d.P = P;
+  d.L = L;
+  d.Q = Q;
+  d.n2 = d.n3 = n;
+  d.nv = t.n3;
+  d.T = T;
+  // spectrum of the zero-extended f_eq: g(l) = sum_j e^{-v_j^2}/sqrt(pi) cos(xi_l v_j) per axis
+  std::vector<double> gl(L), gq(Q);
+  const double spi = std::sqrt(3.14159265358979323846);
+  double c, sn;
+  for (int li = 0; li < L; ++li) {
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {
+      fsm_phase(li - half, j, n, P, c, sn);
+      acc += std::exp(-t.v1d[j] * t.v1d[j]) / spi * c;
+    }
+    gl[li] = acc;
+  }
+  for (int l3 = 0; l3 < Q; ++l3) gq[l3] = gl[l3 + half];
+  std::vector<double> X(static_cast<size_t>(L) * 2 * Q * L, 0.0);
+  for (int l1 = 0; l1 < L; ++l1)
+    for (int l3 = 0; l3 < Q; ++l3)
+      for (int l2 = 0; l2 < L; ++l2) X[(static_cast<size_t>(l1) * 2 * Q + l3) * L + l2] = gl[l1] * gq[l3] * gl[l2];
+  // inverse factor matrices: velocity nodes (n) and the difference grid (2n - 1)
+  auto factors = [&](int m, bool diff, std::vector<double>& e1, std::vector<double>& e3) {
+    e1.assign(2 * static_cast<size_t>(m) * L, 0.0);
+    e3.assign(2 * static_cast<size_t>(m) * Q, 0.0);
+    for (int a = 0; a < m; ++a) {
+      for (int li = 0; li < L; ++li) {
+        const int l = li - half;
+        if (diff) phase_q(2L * l * (a - (n - 1)), P, c, sn);
+        else fsm_phase(l, a, n, P, c, sn);
+        e1[static_cast<size_t>(a) * L + li] = c;
+        e1[static_cast<size_t>(m) * L + static_cast<size_t>(a) * L + li] = sn;
+      }
+      for (int l3 = 0; l3 < Q; ++l3) {
+        if (diff) phase_q(2L * l3 * (a - (n - 1)), P, c, sn);
+        else fsm_phase(l3, a, n, P, c, sn);
+        const double w = l3 == 0 ? 1.0 : 2.0;
+        e3[static_cast<size_t>(a) * Q + l3] = w * c;
+        e3[static_cast<size_t>(m) * Q + static_cast<size_t>(a) * Q + l3] = w * sn;
+      }
+    }
+  };
+  std::vector<double> ev1, ev3, ed1, ed3;
+  factors(n, false, ev1, ev3);
+  factors(nd, true, ed1, ed3);
+  const double inv = 1.0 / (static_cast<double>(P) * P * P);
+  std::vector<int> slotF(T), slotK(T);
+  std::vector<double> scF(T), scK(T, inv);
+  for (int q = 0; q < D; ++q) {
+    slotF[2 * q + 1] = q;       // B_p = F^-1[phi_p fhat]
+    slotF[2 * q] = D + q;       // A_p = F^-1[psi_p fhat]
+    scF[2 * q] = scF[2 * q + 1] = 4.0 * t.b0 * t.W[q] * inv;
+    slotK[2 * q] = q;           // Psi_p
+    slotK[2 * q + 1] = D + q;   // Phi_p
+  }
+  slotF[2 * D] = slotK[2 * D] = 2 * D;   // nu, beta_r
+  scF[2 * D] = inv;
+  double *dXf = nullptr, *dv1 = nullptr, *dv3 = nullptr, *dd1 = nullptr, *dd3 = nullptr, *dsc = nullptr;
+  int* dsl = nullptr;
+  auto cleanup = [&]() { dfree(dXf); dfree(dv1); dfree(dv3); dfree(dd1); dfree(dd3); dfree(dsc); dfree(dsl); };
+  std::vector<double> sc(scF);
+  sc.insert(sc.end(), scK.begin(), scK.end());
+  std::vector<int> sl(slotF);
+  sl.insert(sl.end(), slotK.begin(), slotK.end());
+  hipError_t e = upload(&dXf, X, stream);
+  if (e == hipSuccess) e = upload(&dv1, ev1, stream);
+  if (e == hipSuccess) e = upload(&dv3, ev3, stream);
+  if (e == hipSuccess) e = upload(&dd1, ed1, stream);
+  if (e == hipSuccess) e = upload(&dd3, ed3, stream);
+  if (e == hipSuccess) e = upload(&dsc, sc, stream);
+  if (e == hipSuccess) e = upload(&dsl, sl, stream);
+  if (e == hipSuccess) {
+    sis::FsmTableArgs a{};
+    a.d = d;
+    a.mult = p->fsm_mult;
+    a.t0 = 0;
+    a.nt = T;
+    // fields on the velocity nodes
+    a.m1 = a.m2 = a.m3 = n;
+    a.e1r = a.e2r = dv1;
+    a.e1i = a.e2i = dv1 + static_cast<size_t>(n) * L;
+    a.e3r = dv3;
+    a.e3i = dv3 + static_cast<size_t>(n) * Q;
+    a.X = dXf;
+    a.slot = dsl;
+    a.scale = dsc;
+    a.out = dX;
+    e = sis::launch_fsm_tables(a, stream);
+    // kernels on the difference grid
+    a.m1 = a.m2 = a.m3 = nd;
+    a.e1r = a.e2r = dd1;
+    a.e1i = a.e2i = dd1 + static_cast<size_t>(nd) * L;
+    a.e3r = dd3;
+    a.e3i = dd3 + static_cast<size_t>(nd) * Q;
+    a.X = nullptr;
+    a.slot = dsl + T;
+    a.scale = dsc + T;
+    a.out = dY;
+    if (e == hipSuccess) e = sis::launch_fsm_tables(a, stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  cleanup();
+  if (e != hipSuccess) return fail(SIS_E_DEVICE, "device tables: %s", hipGetErrorString(e));
   return SIS_OK;
 }
 
@@ -1885,7 +2023,20 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   auto t0 = std::chrono::steady_clock::now();
   sis::HostTables t;
   std::string err;
-  if (!sis::build_host_tables(table_desc(desc), true, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
+  const sis::TableDesc td = table_desc(desc);
+  if (!sis::build_grid_tables(td, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
+  // the transforms of the tables run on the device when the table kernel's LDS holds the
+  // modes (n_pad <= 100 or so); otherwise the host planner builds them
+  bool device_tables;
+  {
+    sis::FsmDims dd{};
+    dd.n = t.n;
+    dd.P = t.np;
+    dd.L = t.np - 1;
+    dd.Q = t.np / 2;
+    device_tables = sis::fsm_tables_fit(dd, t.nd);
+  }
+  if (!device_tables && !sis::build_host_tables(td, true, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
   auto t1 = std::chrono::steady_clock::now();
 
   sis_plan* p = new sis_plan();
@@ -1900,29 +2051,19 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   p->w = t.dv * t.dv * t.dv;
   p->b0 = t.b0;
   p->R = t.R;
-  p->nubar = t.nubar;
   p->nsp = 1;
   p->ndof = t.n3;
   set_layout(p, 0);
-  p->nubar_s[0] = t.nubar;
   p->alpha = t.alpha;
   p->gamma = t.gamma;
   p->h_v1d = t.v1d;
   p->h_feq = t.feq;
-  p->h_nu = t.nu;
   const int n = t.n, n3 = t.n3, D = t.D;
 
-  // pre-scale the f_eq fields by 4 b0 W_p
-  for (int d = 0; d < D; ++d) {
-    const double sc = 4.0 * t.b0 * t.W[d];
-    for (int i = 0; i < n3; ++i) {
-      t.A[static_cast<size_t>(d) * n3 + i] *= sc;
-      t.B[static_cast<size_t>(d) * n3 + i] *= sc;
-    }
-  }
-  // term tables of the assembly: X = [B_p; A_p] (scaled), Y = [Psi_p; Phi_p]
-  double *dX = nullptr, *dY = nullptr, *dbr = nullptr;
-  auto cleanup = [&]() { dfree(dX); dfree(dY); dfree(dbr); };
+  // term tables of the assembly: X = [B_p; A_p] (scaled by 4 b0 W_p) and nu, Y = [Psi_p; Phi_p]
+  // and beta_r
+  double *dX = nullptr, *dY = nullptr;
+  auto cleanup = [&]() { dfree(dX); dfree(dY); };
 #define PLAN_TRY(expr)                                                                       \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
@@ -1933,24 +2074,54 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
                   hipGetErrorString(e_));                                                    \
     }                                                                                        \
   } while (0)
+#define PLAN_ST(expr)          \
+  do {                         \
+    sis_status st_ = (expr);   \
+    if (st_ != SIS_OK) {       \
+      cleanup();               \
+      delete p;                \
+      return st_;              \
+    }                          \
+  } while (0)
   const size_t tabX = static_cast<size_t>(D) * n3, tabY = static_cast<size_t>(D) * t.nd3;
-  PLAN_TRY(dmalloc(&dX, 2 * tabX));
-  PLAN_TRY(dmalloc(&dY, 2 * tabY));
-  PLAN_TRY(dmalloc(&dbr, t.beta_r.size()));
+  PLAN_TRY(dmalloc(&dX, 2 * tabX + n3));
+  PLAN_TRY(dmalloc(&dY, 2 * tabY + t.nd3));
   PLAN_TRY(dmalloc(&p->op, static_cast<size_t>(n3) * n3));
   PLAN_TRY(dmalloc(&p->v1d, n));
   PLAN_TRY(dmalloc(&p->feq, n3));
   PLAN_TRY(dmalloc(&p->nu, n3));
   PLAN_TRY(dmalloc(&p->Kc, n3));
   PLAN_TRY(dmalloc(&p->gram_inv, 25));
-  PLAN_TRY(hipMemcpyAsync(dY, t.Psi.data(), tabY * 8, hipMemcpyHostToDevice, stream));
-  PLAN_TRY(hipMemcpyAsync(dY + tabY, t.Phi.data(), tabY * 8, hipMemcpyHostToDevice, stream));
-  PLAN_TRY(hipMemcpyAsync(dX, t.B.data(), tabX * 8, hipMemcpyHostToDevice, stream));
-  PLAN_TRY(hipMemcpyAsync(dX + tabX, t.A.data(), tabX * 8, hipMemcpyHostToDevice, stream));
-  PLAN_TRY(hipMemcpyAsync(dbr, t.beta_r.data(), t.beta_r.size() * 8, hipMemcpyHostToDevice, stream));
   PLAN_TRY(hipMemcpyAsync(p->v1d, t.v1d.data(), n * 8, hipMemcpyHostToDevice, stream));
   PLAN_TRY(hipMemcpyAsync(p->feq, t.feq.data(), n3 * 8, hipMemcpyHostToDevice, stream));
+  if (device_tables) {
+    PLAN_ST(build_fsm_multipliers(p, desc, stream));
+    PLAN_ST(build_tables_device(p, t, dX, dY, stream));
+    t.nu.resize(n3);
+    PLAN_TRY(hipMemcpy(t.nu.data(), dX + 2 * tabX, n3 * 8, hipMemcpyDeviceToHost));
+    double nb = 0.0;
+    for (int i = 0; i < n3; ++i) nb += p->w * t.nu[i] * t.feq[i];
+    t.nubar = nb;
+  } else {
+    for (int d = 0; d < D; ++d) {
+      const double sc = 4.0 * t.b0 * t.W[d];
+      for (int i = 0; i < n3; ++i) {
+        t.A[static_cast<size_t>(d) * n3 + i] *= sc;
+        t.B[static_cast<size_t>(d) * n3 + i] *= sc;
+      }
+    }
+    PLAN_TRY(hipMemcpyAsync(dY, t.Psi.data(), tabY * 8, hipMemcpyHostToDevice, stream));
+    PLAN_TRY(hipMemcpyAsync(dY + tabY, t.Phi.data(), tabY * 8, hipMemcpyHostToDevice, stream));
+    PLAN_TRY(hipMemcpyAsync(dY + 2 * tabY, t.beta_r.data(), t.beta_r.size() * 8, hipMemcpyHostToDevice, stream));
+    PLAN_TRY(hipMemcpyAsync(dX, t.B.data(), tabX * 8, hipMemcpyHostToDevice, stream));
+    PLAN_TRY(hipMemcpyAsync(dX + tabX, t.A.data(), tabX * 8, hipMemcpyHostToDevice, stream));
+  }
+  p->nubar = t.nubar;
+  p->nubar_s[0] = t.nubar;
+  p->h_nu = t.nu;
   PLAN_TRY(hipMemcpyAsync(p->nu, t.nu.data(), n3 * 8, hipMemcpyHostToDevice, stream));
+  if (device_tables) PLAN_ST(build_fsm_static(p, desc->parity, dX, p->feq, stream));
+  const double* dbr = dY + 2 * tabY;
 
   // Gram matrix of the invariants {1, v1, v2, v3, |v|^2} with weight w f_eq
   double G[25] = {0}, Gi[25];
@@ -1997,11 +2168,6 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   }
   if (p->parity) corr = restrict_rows(p, corr.data(), 1);
   p->fsm_corr = corr;
-  if (sis_status st = build_fsm_static(p, t, desc, stream)) {
-    cleanup();
-    delete p;
-    return st;
-  }
   double* dcorr = dX;  // reuse (large enough)
   PLAN_TRY(hipMemcpyAsync(dcorr, corr.data(), corr.size() * 8, hipMemcpyHostToDevice, stream));
   {
@@ -2020,6 +2186,7 @@ sis_status sis_plan_create(const sis_velocity_desc* desc, hipStream_t stream, si
   PLAN_TRY(hipStreamSynchronize(stream));
   cleanup();
 #undef PLAN_TRY
+#undef PLAN_ST
   auto t2 = std::chrono::steady_clock::now();
   p->host_s = std::chrono::duration<double>(t1 - t0).count();
   p->dev_s = std::chrono::duration<double>(t2 - t1).count();

@@ -70,6 +70,33 @@ bool fsm_slab_fits(const FsmDims& d, int slab_l1);
 const char* fsm_unsupported(const FsmDims& d);
 hipError_t launch_fsm_inverse(const FsmDims& d, const FsmFactors& f, int slab_l1, int64_t n_cells, const double* S,
                               const double* mult, const double* field, double* acc, hipStream_t s);
+// Per-term pruned inverse DFTs of the multipliers (plan-time tables), times a
+// spectrum X (layout of S, one cell) or X = 1 when X is null:
+//   out[slot[t]][a1][a2][a3] = scale[t] Re sum_l E1(a1, l1) E2(a2, l2) E3(a3, l3) m_t(l) X(l)
+// for the terms t in [t0, t0 + nt), on output nodes given by the factor matrices
+// E1 [m1][L], E2 [m2][L], E3 [m3][Q] (E3 doubled for l3 > 0 as in FsmFactors).
+// Terms with slot[t] < 0 are skipped.
+struct FsmTableArgs {
+  FsmDims d;
+  int m1, m2, m3;
+  const double *e1r, *e1i, *e2r, *e2i, *e3r, *e3i;
+  const double* mult;
+  const double* X;
+  const int* slot;      // [T]
+  const double* scale;  // [T]
+  double* out;
+  int t0, nt;
+};
+hipError_t launch_fsm_tables(const FsmTableArgs& a, hipStream_t s);
+// whether launch_fsm_tables holds the modes of d and m2 output nodes on axis 2 in LDS
+bool fsm_tables_fit(const FsmDims& d, int m2);
+
+// Field table of the per-cell path from full-grid rows: for t < nrows,
+//   out[t][v] = scale * (src[t] >= 0 ? in[src[t]][full(v)] : -feq[full(v)])
+// over the stored velocities v of d (full(v): index of v on the n^3 grid).
+hipError_t launch_fsm_gather(const FsmDims& d, int nrows, const double* in, const int* src, const double* feq,
+                             double scale, double* out, hipStream_t s);
+
 // Executed flops of one cell update (every MFMA issued, padding included)
 double fsm_flops_per_cell(const FsmDims& d, int slab_l1);
 

@@ -405,6 +405,113 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
   }
 }
 
+// ---------------------------------------------------------------- plan tables
+// One workgroup per (term, slab of K1 output rows a1):
+//   Z(a1, l3, l2)  = sum_l1 E1(a1, l1) m_t(l3, l1, l2) X(l1, l3, l2)
+//   W(a1, l3, a2)  = sum_l2 Z(a1, l3, l2) E2(a2, l2)
+//   O(a1, a2, a3)  = Re sum_l3 W(a1, l3, a2) E3(a3, l3)
+__global__ __launch_bounds__(kThreads) void fsm_table_kernel(FsmTableArgs a, int K1) {
+  extern __shared__ double sm[];
+  const FsmDims d = a.d;
+  const int t = a.t0 + blockIdx.y;
+  const int slot = a.slot[t];
+  if (slot < 0) return;
+  const int L = d.L, Q = d.Q, m2 = a.m2, m3 = a.m3;
+  const int r0 = blockIdx.x * K1, kr1 = min(K1, a.m1 - r0);
+  double* Zr = sm;                    // [K1][Q][L]
+  double* Zi = Zr + K1 * Q * L;
+  double* Wr = Zi + K1 * Q * L;       // [K1][Q][m2]
+  double* Wi = Wr + K1 * Q * m2;
+  const int64_t LL = static_cast<int64_t>(L) * L;
+  const double* mt = a.mult + static_cast<int64_t>(t) * Q * LL;
+  const int64_t sQL = static_cast<int64_t>(Q) * L;
+  {
+    const int M = kr1, K = L, N = Q * L;   // column c = (l3, l2)
+    auto la = [&](int m, int k, double& re, double& im) {
+      const bool ok = m < M && k < K;
+      re = ok ? a.e1r[(r0 + m) * L + k] : 0.0;
+      im = ok ? a.e1i[(r0 + m) * L + k] : 0.0;
+    };
+    auto lb = [&](int k, int c, double& re, double& im) {
+      if (k < K && c < N) {
+        const int l3 = c / L, l2 = c - l3 * L;
+        const double mv = mt[l3 * LL + static_cast<int64_t>(k) * L + l2];
+        if (a.X) {
+          const int64_t o = (static_cast<int64_t>(k) * 2 * Q + l3) * L + l2;
+          re = mv * a.X[o];
+          im = mv * a.X[o + sQL];
+        } else {
+          re = mv;
+          im = 0.0;
+        }
+      } else {
+        re = im = 0.0;
+      }
+    };
+    auto st = [&](int m, int c, double re, double im) {
+      Zr[m * N + c] = re;
+      Zi[m * N + c] = im;
+    };
+    cgemm<2>(M, N, K, la, lb, st);
+  }
+  __syncthreads();
+  {
+    const int M = kr1 * Q, K = L, N = m2;  // row r = (a1, l3)
+    auto la = [&](int m, int k, double& re, double& im) {
+      const bool ok = m < M && k < K;
+      re = ok ? Zr[m * L + k] : 0.0;
+      im = ok ? Zi[m * L + k] : 0.0;
+    };
+    auto lb = [&](int k, int c, double& re, double& im) {
+      const bool ok = k < K && c < N;
+      re = ok ? a.e2r[c * L + k] : 0.0;
+      im = ok ? a.e2i[c * L + k] : 0.0;
+    };
+    auto st = [&](int m, int c, double re, double im) {
+      Wr[m * m2 + c] = re;
+      Wi[m * m2 + c] = im;
+    };
+    cgemm<2>(M, N, K, la, lb, st);
+  }
+  __syncthreads();
+  {
+    const int M = kr1 * m2, K = Q, N = m3;  // row r = (a1, a2)
+    auto la = [&](int m, int k, double& re, double& im) {
+      const bool ok = m < M && k < K;
+      const int a1 = ok ? m / m2 : 0, a2 = m - a1 * m2;
+      re = ok ? Wr[(a1 * Q + k) * m2 + a2] : 0.0;
+      im = ok ? Wi[(a1 * Q + k) * m2 + a2] : 0.0;
+    };
+    auto lb = [&](int k, int c, double& re, double& im) {
+      const bool ok = k < K && c < N;
+      re = ok ? a.e3r[c * Q + k] : 0.0;
+      im = ok ? a.e3i[c * Q + k] : 0.0;
+    };
+    const double sc = a.scale[t];
+    double* out = a.out + static_cast<int64_t>(slot) * a.m1 * m2 * m3;
+    auto st = [&](int m, int c, double re, double) {
+      out[(static_cast<int64_t>(r0) * m2 + m) * m3 + c] = sc * re;
+    };
+    cgemm<2>(M, N, K, la, lb, st);
+  }
+}
+
+__global__ void fsm_gather_kernel(FsmDims d, int nrows, const double* __restrict__ in, const int* __restrict__ src,
+                                  const double* __restrict__ feq, double scale, double* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(nrows) * d.nv) return;
+  const int t = static_cast<int>(i / d.nv), v = static_cast<int>(i - static_cast<int64_t>(t) * d.nv);
+  const int s3 = v % d.n3, s2 = (v / d.n3) % d.n2, j1 = v / (d.n3 * d.n2);
+  const int n = d.n;
+  const int64_t full = (static_cast<int64_t>(j1) * n + s2 + (n - d.n2)) * n + s3 + (n - d.n3);
+  const int r = src[t];
+  out[i] = scale * (r >= 0 ? in[static_cast<int64_t>(r) * n * n * n + full] : -feq[full]);
+}
+
+size_t table_lds_bytes(const FsmDims& d, int m2, int K1) {
+  return static_cast<size_t>(2 * K1 * d.Q * d.L + 2 * K1 * d.Q * m2) * sizeof(double);
+}
+
 int stage3_tiles_per_wave(const FsmDims& d) {
   const int tiles = ((d.n + 15) / 16) * ((d.n2 * d.n3 + 15) / 16);
   return (tiles + kInvWaves - 1) / kInvWaves;
@@ -446,6 +553,28 @@ hipError_t launch_fsm_forward(const FsmDims& d, const FsmFactors& f, int64_t n_c
   if (lds > kLdsMax) return hipErrorInvalidValue;
   dim3 grid((d.Q + B3 - 1) / B3, static_cast<unsigned>(n_cells));
   hipLaunchKernelGGL(fsm_forward_kernel, grid, dim3(kThreads), lds, s, d, f, B3, h, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_fsm_gather(const FsmDims& d, int nrows, const double* in, const int* src, const double* feq,
+                             double scale, double* out, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(nrows) * d.nv;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fsm_gather_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, d, nrows,
+                     in, src, feq, scale, out);
+  return hipGetLastError();
+}
+
+bool fsm_tables_fit(const FsmDims& d, int m2) { return table_lds_bytes(d, m2, 1) <= kLdsMax; }
+
+hipError_t launch_fsm_tables(const FsmTableArgs& a, hipStream_t s) {
+  if (a.nt <= 0) return hipSuccess;
+  int K1 = 4;
+  while (K1 > 1 && table_lds_bytes(a.d, a.m2, K1) > kLdsMax) --K1;
+  const size_t lds = table_lds_bytes(a.d, a.m2, K1);
+  if (lds > kLdsMax) return hipErrorInvalidValue;
+  dim3 grid((a.m1 + K1 - 1) / K1, a.nt);
+  hipLaunchKernelGGL(fsm_table_kernel, grid, dim3(kThreads), lds, s, a, K1);
   return hipGetLastError();
 }
 

@@ -277,6 +277,37 @@ bool radial_rule(const TableDesc& d, RadialRule& r, std::string& err) {
   return true;
 }
 
+bool build_grid_tables(const TableDesc& d, HostTables& t, std::string& err) {
+  const int n = d.n_v;
+  const int np = d.n_pad > 0 ? d.n_pad : 2 * n;
+  t.n = n;
+  t.n3 = n * n * n;
+  t.np = np;
+  t.nd = 2 * n - 1;
+  t.nd3 = t.nd * t.nd * t.nd;
+  t.lv = d.l_v;
+  t.dv = 2.0 * d.l_v / n;
+  t.Lp = np * t.dv / 2.0;
+  t.R = d.r_trunc > 0.0 ? d.r_trunc : 4.0 * t.Lp / (3.0 + std::sqrt(2.0));
+  t.alpha = d.alpha;
+  t.gamma = d.gamma;
+  t.b0 = b0_unit(d.alpha, d.gamma);
+  t.v1d.resize(n);
+  std::vector<double> g1(n);
+  for (int j = 0; j < n; ++j) {
+    t.v1d[j] = -d.l_v + (j + 0.5) * t.dv;
+    g1[j] = std::exp(-t.v1d[j] * t.v1d[j]) / std::sqrt(kPi);
+  }
+  t.feq.resize(t.n3);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      for (int c = 0; c < n; ++c) t.feq[(a * n + b) * n + c] = g1[a] * g1[b] * g1[c];
+  std::vector<double> ex, ey, ez;
+  if (!half_sphere_directions(d.m_angle, ex, ey, ez, t.W)) { err = "Gauss-Legendre failed"; return false; }
+  t.D = static_cast<int>(t.W.size());
+  return true;
+}
+
 bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std::string& err) {
   const int n = d.n_v;
   const int np = d.n_pad > 0 ? d.n_pad : 2 * n;

@@ -58,6 +58,10 @@ struct RadialRule {
 };
 bool radial_rule(const TableDesc& d, RadialRule& r, std::string& err);
 
+// Grid, equilibrium, b0, Lp, R and direction weights only (no transforms): fills
+// n, n3, np, nd, nd3, lv, dv, Lp, R, alpha, gamma, b0, D, v1d, feq, W.
+bool build_grid_tables(const TableDesc& d, HostTables& t, std::string& err);
+
 // Build all tables.  want_kernels = false skips Psi/Phi/beta_r (cheaper).
 bool build_host_tables(const TableDesc& d, bool want_kernels, HostTables& t, std::string& err);
 
