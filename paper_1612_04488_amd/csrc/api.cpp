@@ -56,6 +56,22 @@ hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t s) {
   return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
+// cos, sin of the exact phase pi q / P (q reduced mod 2P in integers).
+void phase_q(long q, int P, double& c, double& sn) {
+  const double kPi = 3.14159265358979323846;
+  q %= 2L * P;
+  if (q < 0) q += 2L * P;
+  const double ang = kPi * static_cast<double>(q) / P;
+  c = std::cos(ang);
+  sn = std::sin(ang);
+}
+
+// Phase xi_l v_j of the centred DFT: v_j = (j + 1/2 - n/2) dv, xi_l = pi l / L_p, so
+// xi_l v_j = pi l (2 j + 1 - n) / P.
+void fsm_phase(int l, int j, int n, int P, double& c, double& sn) {
+  phase_q(static_cast<long>(l) * (2 * j + 1 - n), P, c, sn);
+}
+
 void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
@@ -1322,12 +1338,365 @@ sis_status apply_parity(sis_plan* p, hipStream_t stream) {
 // equal-mass (closed-form phi) terms or the rho-quadrature terms of the
 // unequal-mass gain, plus the loss.  Cross terms are built on the host in
 // chunks and accumulated on the device while the next chunk is built.
+// Inverse factor matrices (re block then im block) of the velocity nodes (diff = false, m = n)
+// or the difference grid (diff = true, m = 2n - 1) over the modes of an n_pad = P box:
+// e1 [m][L] for axes 1, 2 and e3 [m][Q] (doubled for l3 > 0) for axis 3.
+void inverse_factors(int n, int P, int m, bool diff, std::vector<double>& e1, std::vector<double>& e3) {
+  const int L = P - 1, Q = P / 2, half = P / 2 - 1;
+  e1.assign(2 * static_cast<size_t>(m) * L, 0.0);
+  e3.assign(2 * static_cast<size_t>(m) * Q, 0.0);
+  double c, sn;
+  for (int a = 0; a < m; ++a) {
+    for (int li = 0; li < L; ++li) {
+      const int l = li - half;
+      if (diff) phase_q(2L * l * (a - (n - 1)), P, c, sn);
+      else fsm_phase(l, a, n, P, c, sn);
+      e1[static_cast<size_t>(a) * L + li] = c;
+      e1[static_cast<size_t>(m) * L + static_cast<size_t>(a) * L + li] = sn;
+    }
+    for (int l3 = 0; l3 < Q; ++l3) {
+      if (diff) phase_q(2L * l3 * (a - (n - 1)), P, c, sn);
+      else fsm_phase(l3, a, n, P, c, sn);
+      const double w = l3 == 0 ? 1.0 : 2.0;
+      e3[static_cast<size_t>(a) * Q + l3] = w * c;
+      e3[static_cast<size_t>(m) * Q + static_cast<size_t>(a) * Q + l3] = w * sn;
+    }
+  }
+}
+
+// Spectrum of a zero-extended separable even profile, prod_k ghat(l_k), in the layout of a
+// transform-path spectrum ([L][re, im][Q][L]; real).
+std::vector<double> separable_spectrum(const std::vector<double>& g, int n, int P) {
+  const int L = P - 1, Q = P / 2, half = P / 2 - 1;
+  std::vector<double> gl(L);
+  double c, sn;
+  for (int li = 0; li < L; ++li) {
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {
+      fsm_phase(li - half, j, n, P, c, sn);
+      acc += g[j] * c;
+    }
+    gl[li] = acc;
+  }
+  std::vector<double> X(static_cast<size_t>(L) * 2 * Q * L, 0.0);
+  for (int l1 = 0; l1 < L; ++l1)
+    for (int l3 = 0; l3 < Q; ++l3)
+      for (int l2 = 0; l2 < L; ++l2) X[(static_cast<size_t>(l1) * 2 * Q + l3) * L + l2] = gl[l1] * gl[l3 + half] * gl[l2];
+  return X;
+}
+
+// The binary-mixture operator assembled from term tables built on the device: the hard-sphere
+// multipliers, pruned inverse DFTs for the unshifted kernels Psi_p, Phi_p, beta_r and the
+// species fields, and for every (direction, rho node, sign) of the unequal-mass pairs the
+// shifted kernel or field (per-term factor matrices) with the separable band-limited factor.
+// Fills p->op (full grid, zeroed by the caller), the host nu tables and nubar of t.
+sis_status mix_tables_device(sis_plan* p, sis::MixTables& t, hipStream_t stream) {
+  const int n = t.n, P = t.np, L = P - 1, Q = P / 2, D = t.D, nd = t.nd, T1 = 2 * D + 1;
+  const int64_t n3 = t.n3, nd3 = t.nd3, ndof = p->ndof;
+  std::vector<void*> owned;
+  auto cleanup = [&]() { for (void* q : owned) dfree(q); owned.clear(); };
+  auto ua = [&](auto** dst, const auto& v) -> hipError_t {
+    hipError_t e = upload(dst, v, stream);
+    if (e == hipSuccess) owned.push_back(*dst);
+    return e;
+  };
+  auto al = [&](double** dst, size_t count) -> hipError_t {
+    hipError_t e = dmalloc(dst, count);
+    if (e == hipSuccess) owned.push_back(*dst);
+    return e;
+  };
+#define MT_TRY(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      (void)hipStreamSynchronize(stream);                                                     \
+      cleanup();                                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? SIS_E_OOM : SIS_E_DEVICE, "mixture tables: %s: %s", #expr, \
+                  hipGetErrorString(e_));                                                     \
+    }                                                                                         \
+  } while (0)
+  sis::FsmDims d{};
+  d.n = n;
+  d.P = P;
+  d.L = L;
+  d.Q = Q;
+  d.n2 = d.n3 = n;
+  d.nv = static_cast<int>(n3);
+  d.T = T1;
+  // hard-sphere multipliers psi_p, phi_p, beta = 4 b0 sum_p W_p phi_p psi_p
+  std::vector<double> dw(4 * D);
+  for (int q = 0; q < D; ++q) {
+    dw[3 * q] = t.ex[q];
+    dw[3 * q + 1] = t.ey[q];
+    dw[3 * q + 2] = t.ez[q];
+    dw[3 * D + q] = t.W[q];
+  }
+  double *ddir = nullptr, *dmult = nullptr;
+  MT_TRY(ua(&ddir, dw));
+  const int64_t qll = static_cast<int64_t>(Q) * L * L;
+  MT_TRY(al(&dmult, static_cast<size_t>(T1) * qll));
+  {
+    sis::FsmMultArgs m{};
+    m.d = d;
+    m.D = D;
+    m.b0 = t.b0;
+    m.R = t.R;
+    m.Lp = t.Lp;
+    m.dirs = ddir;
+    m.W = ddir + 3 * D;
+    m.phi_closed = m.psi_closed = 1;
+    m.mult = dmult;
+    MT_TRY(sis::launch_fsm_multipliers(m, stream));
+  }
+  // unshifted kernels and the species fields
+  std::vector<double> ev1, ev3, ed1, ed3;
+  inverse_factors(n, P, n, false, ev1, ev3);
+  inverse_factors(n, P, nd, true, ed1, ed3);
+  double *dv1 = nullptr, *dv3 = nullptr, *dd1 = nullptr, *dd3 = nullptr, *dK = nullptr, *dF[2] = {nullptr, nullptr};
+  double *dS[2] = {nullptr, nullptr}, *dsc = nullptr;
+  int *dslK = nullptr, *dslF = nullptr;
+  MT_TRY(ua(&dv1, ev1));
+  MT_TRY(ua(&dv3, ev3));
+  MT_TRY(ua(&dd1, ed1));
+  MT_TRY(ua(&dd3, ed3));
+  std::vector<int> slK(T1), slF(T1);
+  for (int q = 0; q < D; ++q) {
+    slK[2 * q] = q;           // Psi_p
+    slK[2 * q + 1] = D + q;   // Phi_p
+    slF[2 * q] = D + q;       // Fpsi_s
+    slF[2 * q + 1] = q;       // Fphi_s
+  }
+  slK[2 * D] = slF[2 * D] = 2 * D;   // beta_r, 4 b0 F^-1[sum W phi psi F f_s]
+  MT_TRY(ua(&dslK, slK));
+  MT_TRY(ua(&dslF, slF));
+  const std::vector<double> scT(T1, 1.0 / (static_cast<double>(P) * P * P));
+  MT_TRY(ua(&dsc, scT));
+  MT_TRY(al(&dK, static_cast<size_t>(T1) * nd3));
+  std::vector<double> spec[2];
+  for (int s = 0; s < 2; ++s) {
+    spec[s] = separable_spectrum(t.prof[s], n, P);
+    MT_TRY(ua(&dS[s], spec[s]));
+    MT_TRY(al(&dF[s], static_cast<size_t>(T1) * n3));
+  }
+  sis::FsmTableArgs a{};
+  a.d = d;
+  a.mult = dmult;
+  a.scale = dsc;
+  a.t0 = 0;
+  a.nt = T1;
+  a.m1 = a.m2 = a.m3 = nd;
+  a.e1r = a.e2r = dd1;
+  a.e1i = a.e2i = dd1 + static_cast<size_t>(nd) * L;
+  a.e3r = dd3;
+  a.e3i = dd3 + static_cast<size_t>(nd) * Q;
+  a.slot = dslK;
+  a.out = dK;
+  MT_TRY(sis::launch_fsm_tables(a, stream));
+  a.m1 = a.m2 = a.m3 = n;
+  a.e1r = a.e2r = dv1;
+  a.e1i = a.e2i = dv1 + static_cast<size_t>(n) * L;
+  a.e3r = dv3;
+  a.e3i = dv3 + static_cast<size_t>(n) * Q;
+  a.slot = dslF;
+  for (int s = 0; s < 2; ++s) {
+    a.X = dS[s];
+    a.out = dF[s];
+    MT_TRY(sis::launch_fsm_tables(a, stream));
+  }
+  // collision frequencies nu_a = scale sum_b (C_ab / 4 b0) (4 b0 F^-1[beta F f_b]) and nubar
+  std::vector<double> nuu(2 * n3);
+  MT_TRY(hipStreamSynchronize(stream));
+  for (int s = 0; s < 2; ++s)
+    MT_TRY(hipMemcpy(nuu.data() + s * n3, dF[s] + 2 * D * n3, n3 * 8, hipMemcpyDeviceToHost));
+  const double inv4b0 = 1.0 / (4.0 * t.b0);
+  t.nu.assign(2 * n3, 0.0);
+  for (int s = 0; s < 2; ++s) {
+    double nb = 0.0;
+    for (int64_t i = 0; i < n3; ++i) {
+      const double v = t.scale * inv4b0 * (t.C[s][0] * nuu[i] + t.C[s][1] * nuu[n3 + i]);
+      t.nu[s * n3 + i] = v;
+      nb += p->w * v * t.feq[s * n3 + i];
+    }
+    t.nubar[s] = nb / t.chi[s];
+  }
+  auto block = [&](int ra, int cb) { return p->op + static_cast<size_t>(ra) * n3 * ndof + static_cast<size_t>(cb) * n3; };
+  // loss terms: block (a, b) -= scale C_ab f_a(i) beta_r(i - j)
+  for (int ra = 0; ra < 2; ++ra)
+    for (int cb = 0; cb < 2; ++cb)
+      MT_TRY(sis::launch_assemble(n, 0, nullptr, nullptr, p->feq + static_cast<size_t>(ra) * n3,
+                                  t.scale * t.C[ra][cb] * inv4b0, dK + 2 * D * nd3, block(ra, cb), ndof, 1, stream));
+  // equal-mass pairs: closed-form phi terms with the shared kernels Psi_p, Phi_p
+  double* dXw = nullptr;
+  int* dsrc = nullptr;
+  double* dsw = nullptr;
+  MT_TRY(al(&dXw, static_cast<size_t>(D) * n3));
+  std::vector<int> srcv(D);
+  std::vector<double> swv(D);
+  int* dsrcbuf = nullptr;
+  double* dswbuf = nullptr;
+  MT_TRY(dmalloc(&dsrcbuf, D));
+  owned.push_back(dsrcbuf);
+  MT_TRY(al(&dswbuf, D));
+  dsrc = dsrcbuf;
+  dsw = dswbuf;
+  for (int ra = 0; ra < 2; ++ra)
+    for (int cb = 0; cb < 2; ++cb) {
+      if (t.kappa[ra][cb] != 0.0) continue;
+      for (int kind = 0; kind < 2; ++kind) {
+        // kind 0: Q+_ab(f_a, h_b) -> block (a, b), X = phi-field of f_a, Y = Psi_p
+        // kind 1: Q+_ab(h_a, f_b) -> block (a, a), X = psi-field of f_b, Y = Phi_p
+        for (int q = 0; q < D; ++q) {
+          srcv[q] = kind == 0 ? q : D + q;
+          swv[q] = t.scale * t.C[ra][cb] * t.W[q];
+        }
+        MT_TRY(hipStreamSynchronize(stream));   // the previous round has consumed dXw, dsrc, dsw
+        MT_TRY(hipMemcpyAsync(dsrc, srcv.data(), D * sizeof(int), hipMemcpyHostToDevice, stream));
+        MT_TRY(hipMemcpyAsync(dsw, swv.data(), D * sizeof(double), hipMemcpyHostToDevice, stream));
+        MT_TRY(sis::launch_scale_rows(D, n3, kind == 0 ? dF[ra] : dF[cb], dsrc, dsw, dXw, stream));
+        MT_TRY(sis::launch_assemble(n, D, dXw, dK + (kind == 0 ? 0 : static_cast<size_t>(D) * nd3), nullptr, 0.0,
+                                    nullptr, kind == 0 ? block(ra, cb) : block(ra, ra), ndof, 1, stream));
+      }
+    }
+  // unequal-mass pairs: every (direction p, rho node r, sign) is a term with shifts
+  // zp = 2mu rho e_p / dv (of the f-argument) and zm = -kappa rho e_p / dv (of the psi-argument)
+  const int items = D * t.m_rho * 2;
+  const int CH = std::min(items, 512);
+  double *dXc = nullptr, *dYc = nullptr, *dE1 = nullptr, *dE2 = nullptr, *dE3 = nullptr, *dSp = nullptr;
+  double *dz = nullptr, *dzp = nullptr, *dwt = nullptr, *dscl = nullptr, *dones = nullptr;
+  int *dmrow = nullptr, *dslot = nullptr, *dbv = nullptr, *dbd = nullptr;
+  bool any_cross = false;
+  for (int ra = 0; ra < 2; ++ra)
+    for (int cb = 0; cb < 2; ++cb) any_cross = any_cross || t.kappa[ra][cb] != 0.0;
+  if (any_cross) {
+    MT_TRY(al(&dXc, static_cast<size_t>(CH) * n3));
+    MT_TRY(al(&dYc, static_cast<size_t>(CH) * nd3));
+    MT_TRY(al(&dE1, 2 * static_cast<size_t>(CH) * nd * L));
+    MT_TRY(al(&dE2, 2 * static_cast<size_t>(CH) * nd * L));
+    MT_TRY(al(&dE3, 2 * static_cast<size_t>(CH) * nd * Q));
+    MT_TRY(al(&dSp, static_cast<size_t>(CH) * 3 * nd));
+    MT_TRY(al(&dz, 6 * static_cast<size_t>(CH)));
+    MT_TRY(al(&dzp, 3 * static_cast<size_t>(CH)));
+    MT_TRY(al(&dwt, static_cast<size_t>(CH)));
+    MT_TRY(al(&dscl, static_cast<size_t>(CH)));
+    int* tmp = nullptr;
+    MT_TRY(dmalloc(&tmp, CH));
+    owned.push_back(tmp);
+    dmrow = tmp;
+    MT_TRY(dmalloc(&tmp, CH));
+    owned.push_back(tmp);
+    dslot = tmp;
+    std::vector<int> bv(n), bd(nd), sl(CH);
+    for (int i = 0; i < n; ++i) bv[i] = 2 * i + 1 - n;
+    for (int i = 0; i < nd; ++i) bd[i] = 2 * (i - (n - 1));
+    for (int i = 0; i < CH; ++i) sl[i] = i;
+    MT_TRY(upload(&dbv, bv, stream));
+    owned.push_back(dbv);
+    MT_TRY(upload(&dbd, bd, stream));
+    owned.push_back(dbd);
+    MT_TRY(hipMemcpyAsync(dslot, sl.data(), CH * sizeof(int), hipMemcpyHostToDevice, stream));
+  }
+  double* dprof[2] = {nullptr, nullptr};
+  for (int s = 0; s < 2 && any_cross; ++s) MT_TRY(ua(&dprof[s], t.prof[s]));
+  const std::vector<double> ones(CH, 1.0);
+  if (any_cross) MT_TRY(ua(&dones, ones));
+  std::vector<double> zv(6 * static_cast<size_t>(CH)), zp(3 * static_cast<size_t>(CH)), wv(CH), scv(CH);
+  std::vector<int> mr(CH);
+  const double invP3 = 1.0 / (static_cast<double>(P) * P * P);
+  for (int ra = 0; ra < 2; ++ra)
+    for (int cb = 0; cb < 2; ++cb) {
+      if (t.kappa[ra][cb] == 0.0) continue;
+      const double tm = t.two_mu[ra][cb], kap = t.kappa[ra][cb];
+      for (int kind = 0; kind < 2; ++kind)
+        for (int q0 = 0; q0 < items; q0 += CH) {
+          const int nt = std::min(CH, items - q0);
+          MT_TRY(hipStreamSynchronize(stream));   // the previous chunk (and its copies) are done
+          for (int i = 0; i < nt; ++i) {
+            const int q = q0 + i;                  // q = (p m_rho + r) 2 + sign
+            const int sgn = (q & 1) ? -1 : 1, pr = q >> 1, pp = pr / t.m_rho, r = pr % t.m_rho;
+            const double rho = sgn * t.rho[r];
+            const double e[3] = {t.ex[pp], t.ey[pp], t.ez[pp]};
+            for (int k = 0; k < 3; ++k) {
+              zv[6 * i + k] = tm * rho * e[k] / t.dv;        // zp
+              zv[6 * i + 3 + k] = -kap * rho * e[k] / t.dv;  // zm
+            }
+            wv[i] = t.scale * t.C[ra][cb] * t.W[pp] * t.wr[r] * t.rho[r];
+            mr[i] = 2 * pp;                        // psi_p
+            scv[i] = kind == 0 ? invP3 : wv[i] * invP3;
+            for (int k = 0; k < 3; ++k) zp[3 * i + k] = zv[6 * i + k];
+          }
+          MT_TRY(hipMemcpyAsync(dz, zv.data(), 6 * nt * 8, hipMemcpyHostToDevice, stream));
+          MT_TRY(hipMemcpyAsync(dwt, wv.data(), nt * 8, hipMemcpyHostToDevice, stream));
+          MT_TRY(hipMemcpyAsync(dscl, scv.data(), nt * 8, hipMemcpyHostToDevice, stream));
+          MT_TRY(hipMemcpyAsync(dmrow, mr.data(), nt * sizeof(int), hipMemcpyHostToDevice, stream));
+          const bool kern = kind == 0;               // shifted transform on the difference grid
+          const int m = kern ? nd : n;
+          const int* base = kern ? dbd : dbv;
+          // per-term factor matrices with the psi-argument shift zm (axes 1, 2, 3)
+          MT_TRY(sis::launch_fsm_shift_factors(nt, m, L, -(P / 2 - 1), 0, base, dz + 3, 6, P, dE1,
+                                               dE1 + static_cast<size_t>(nt) * m * L, stream));
+          MT_TRY(sis::launch_fsm_shift_factors(nt, m, L, -(P / 2 - 1), 0, base, dz + 4, 6, P, dE2,
+                                               dE2 + static_cast<size_t>(nt) * m * L, stream));
+          MT_TRY(sis::launch_fsm_shift_factors(nt, m, Q, 0, 1, base, dz + 5, 6, P, dE3,
+                                               dE3 + static_cast<size_t>(nt) * m * Q, stream));
+          sis::FsmTableArgs b{};
+          b.d = d;
+          b.m1 = b.m2 = b.m3 = m;
+          b.e1r = dE1;
+          b.e1i = dE1 + static_cast<size_t>(nt) * m * L;
+          b.e2r = dE2;
+          b.e2i = dE2 + static_cast<size_t>(nt) * m * L;
+          b.e3r = dE3;
+          b.e3i = dE3 + static_cast<size_t>(nt) * m * Q;
+          b.e1_ts = b.e2_ts = static_cast<int64_t>(m) * L;
+          b.e3_ts = static_cast<int64_t>(m) * Q;
+          b.mult = dmult;
+          b.mrow = dmrow;
+          b.X = kern ? nullptr : dS[cb];
+          b.slot = dslot;
+          b.scale = dscl;
+          b.out = kern ? dYc : dXc;
+          b.t0 = 0;
+          b.nt = nt;
+          MT_TRY(sis::launch_fsm_tables(b, stream));
+          // the separable factor: kind 0 the shifted band-limited f_a on the nodes (x w), kind 1
+          // the shifted band-limited delta on the difference grid
+          MT_TRY(hipMemcpyAsync(dzp, zp.data(), 3 * nt * 8, hipMemcpyHostToDevice, stream));
+          if (kern) {
+            MT_TRY(sis::launch_band_profiles(nt, n, 0, dprof[ra], n, dzp, P, dSp, stream));
+            MT_TRY(sis::launch_separable(nt, n, dSp, dwt, dXc, stream));
+          } else {
+            MT_TRY(sis::launch_band_profiles(nt, nd, -(n - 1), nullptr, 0, dzp, P, dSp, stream));
+            MT_TRY(sis::launch_separable(nt, nd, dSp, dones, dYc, stream));
+          }
+          MT_TRY(sis::launch_assemble(n, nt, dXc, dYc, nullptr, 0.0, nullptr,
+                                      kind == 0 ? block(ra, cb) : block(ra, ra), ndof, 1, stream));
+        }
+    }
+  MT_TRY(hipStreamSynchronize(stream));
+  cleanup();
+#undef MT_TRY
+  return SIS_OK;
+}
+
 sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, sis_plan_t* out) {
   auto t0 = std::chrono::steady_clock::now();
   const sis::MixDesc md = mix_desc(desc);
   sis::MixTables t;
   std::string err;
-  if (!sis::build_mix_base(md, t, err)) return fail(SIS_E_INVALID, "%s", err.c_str());
+  // the transforms of the tables run on the device when the table kernel's LDS holds the
+  // modes; otherwise the host planner builds them
+  bool device_tables;
+  {
+    const int nn = md.n_v, np = md.n_pad > 0 ? md.n_pad : 2 * md.n_v;
+    sis::FsmDims dd{};
+    dd.n = nn;
+    dd.P = np;
+    dd.L = np - 1;
+    dd.Q = np / 2;
+    device_tables = sis::fsm_tables_fit(dd, 2 * nn - 1);
+  }
+  if (!(device_tables ? sis::build_mix_grid(md, t, err) : sis::build_mix_base(md, t, err)))
+    return fail(SIS_E_INVALID, "%s", err.c_str());
   sis_plan* p = new sis_plan();
   HIP_TRY(hipGetDevice(&p->device));
   const int n = t.n, n3 = t.n3, D = t.D, nd3 = t.nd3;
@@ -1349,14 +1718,11 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
   for (int s = 0; s < 2; ++s) {
     p->mass_ratio[s] = t.a[s];
     p->chi[s] = t.chi[s];
-    p->nubar_s[s] = t.nubar[s];
   }
-  p->nubar = t.nubar[0];
   p->flow_factor = std::sqrt(t.mbar_over_mA);
   p->visc_ratio = sis::mix_viscosity_ratio(md.mass, md.diam, md.chi);
   p->h_v1d = t.v1d;
   p->h_feq = t.feq;
-  p->h_nu = t.nu;
   const int64_t ndof = p->ndof;
   const int chunk = 64;  // (direction, rho) items per host/device round
   const size_t tabX = static_cast<size_t>(std::max(2 * chunk, D)) * n3;
@@ -1374,9 +1740,6 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
                   hipGetErrorString(e_));                                                    \
     }                                                                                        \
   } while (0)
-  MIX_TRY(dmalloc(&dX, tabX));
-  MIX_TRY(dmalloc(&dY, tabY));
-  MIX_TRY(dmalloc(&dbr, nd3));
   MIX_TRY(dmalloc(&p->op, static_cast<size_t>(ndof) * ndof));
   MIX_TRY(dmalloc(&p->v1d, n));
   MIX_TRY(dmalloc(&p->feq, 2 * n3));
@@ -1385,55 +1748,69 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
   MIX_TRY(dmalloc(&p->gram_inv, 25));
   MIX_TRY(hipMemcpyAsync(p->v1d, t.v1d.data(), n * 8, hipMemcpyHostToDevice, stream));
   MIX_TRY(hipMemcpyAsync(p->feq, t.feq.data(), 2 * n3 * 8, hipMemcpyHostToDevice, stream));
-  MIX_TRY(hipMemcpyAsync(p->nu, t.nu.data(), 2 * n3 * 8, hipMemcpyHostToDevice, stream));
-  MIX_TRY(hipMemcpyAsync(dbr, t.beta_r.data(), nd3 * 8, hipMemcpyHostToDevice, stream));
   MIX_TRY(hipMemsetAsync(p->op, 0, static_cast<size_t>(ndof) * ndof * 8, stream));
-  auto block = [&](int a, int b) { return p->op + static_cast<size_t>(a) * n3 * ndof + static_cast<size_t>(b) * n3; };
-  // loss terms: block (a, b) -= scale C_ab f_a(i) beta_r(i - j)
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      MIX_TRY(sis::launch_assemble(n, 0, nullptr, nullptr, p->feq + static_cast<size_t>(a) * n3,
-                                   t.scale * t.C[a][b], dbr, block(a, b), ndof, 1, stream));
-  // equal-mass pairs: closed-form phi terms with the shared kernels Psi_p, Phi_p
-  MIX_TRY(hipMemcpyAsync(dY, t.Psi.data(), static_cast<size_t>(D) * nd3 * 8, hipMemcpyHostToDevice, stream));
-  MIX_TRY(hipMemcpyAsync(dY + static_cast<size_t>(D) * nd3, t.Phi.data(), static_cast<size_t>(D) * nd3 * 8,
-                         hipMemcpyHostToDevice, stream));
-  std::vector<double> hx(tabX), hy;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      if (t.kappa[a][b] != 0.0) continue;
-      for (int kind = 0; kind < 2; ++kind) {
-        // kind 0: Q+_ab(f_a, h_b) -> block (a, b), X = phi-field of f_a, Y = Psi
-        // kind 1: Q+_ab(h_a, f_b) -> block (a, a), X = psi-field of f_b, Y = Phi
-        const std::vector<double>& F = kind == 0 ? t.Fphi[a] : t.Fpsi[b];
-        MIX_TRY(hipStreamSynchronize(stream));
-        for (int q = 0; q < D; ++q) {
-          const double sc = t.scale * t.C[a][b] * t.W[q];
-          for (int i = 0; i < n3; ++i) hx[static_cast<size_t>(q) * n3 + i] = sc * F[static_cast<size_t>(q) * n3 + i];
+  if (device_tables) {
+    if (sis_status st = mix_tables_device(p, t, stream)) {
+      cleanup();
+      delete p;
+      return st;
+    }
+  } else {
+    MIX_TRY(dmalloc(&dX, tabX));
+    MIX_TRY(dmalloc(&dY, tabY));
+    MIX_TRY(dmalloc(&dbr, nd3));
+    MIX_TRY(hipMemcpyAsync(dbr, t.beta_r.data(), nd3 * 8, hipMemcpyHostToDevice, stream));
+    auto block = [&](int a, int b) { return p->op + static_cast<size_t>(a) * n3 * ndof + static_cast<size_t>(b) * n3; };
+    // loss terms: block (a, b) -= scale C_ab f_a(i) beta_r(i - j)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        MIX_TRY(sis::launch_assemble(n, 0, nullptr, nullptr, p->feq + static_cast<size_t>(a) * n3,
+                                     t.scale * t.C[a][b], dbr, block(a, b), ndof, 1, stream));
+    // equal-mass pairs: closed-form phi terms with the shared kernels Psi_p, Phi_p
+    MIX_TRY(hipMemcpyAsync(dY, t.Psi.data(), static_cast<size_t>(D) * nd3 * 8, hipMemcpyHostToDevice, stream));
+    MIX_TRY(hipMemcpyAsync(dY + static_cast<size_t>(D) * nd3, t.Phi.data(), static_cast<size_t>(D) * nd3 * 8,
+                           hipMemcpyHostToDevice, stream));
+    std::vector<double> hx(tabX), hy;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        if (t.kappa[a][b] != 0.0) continue;
+        for (int kind = 0; kind < 2; ++kind) {
+          // kind 0: Q+_ab(f_a, h_b) -> block (a, b), X = phi-field of f_a, Y = Psi
+          // kind 1: Q+_ab(h_a, f_b) -> block (a, a), X = psi-field of f_b, Y = Phi
+          const std::vector<double>& F = kind == 0 ? t.Fphi[a] : t.Fpsi[b];
+          MIX_TRY(hipStreamSynchronize(stream));
+          for (int q = 0; q < D; ++q) {
+            const double sc = t.scale * t.C[a][b] * t.W[q];
+            for (int i = 0; i < n3; ++i) hx[static_cast<size_t>(q) * n3 + i] = sc * F[static_cast<size_t>(q) * n3 + i];
+          }
+          MIX_TRY(hipMemcpyAsync(dX, hx.data(), static_cast<size_t>(D) * n3 * 8, hipMemcpyHostToDevice, stream));
+          MIX_TRY(sis::launch_assemble(n, D, dX, dY + (kind == 0 ? 0 : static_cast<size_t>(D) * nd3), nullptr, 0.0,
+                                       nullptr, kind == 0 ? block(a, b) : block(a, a), ndof, 1, stream));
         }
-        MIX_TRY(hipMemcpyAsync(dX, hx.data(), static_cast<size_t>(D) * n3 * 8, hipMemcpyHostToDevice, stream));
-        MIX_TRY(sis::launch_assemble(n, D, dX, dY + (kind == 0 ? 0 : static_cast<size_t>(D) * nd3), nullptr, 0.0,
-                                     nullptr, kind == 0 ? block(a, b) : block(a, a), ndof, 1, stream));
       }
-    }
-  // unequal-mass pairs: rho-quadrature terms, in chunks
-  hy.resize(static_cast<size_t>(2 * chunk) * nd3);
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      if (t.kappa[a][b] == 0.0) continue;
-      const int items = D * t.m_rho;
-      for (int kind = 0; kind < 2; ++kind)
-        for (int q0 = 0; q0 < items; q0 += chunk) {
-          const int q1 = std::min(items, q0 + chunk);
-          sis::build_mix_cross_terms(t, a, b, kind, q0, q1, hx.data(), hy.data(), md.n_threads);
-          MIX_TRY(hipStreamSynchronize(stream));  // previous chunk has consumed dX, dY
-          const size_t T = 2 * static_cast<size_t>(q1 - q0);
-          MIX_TRY(hipMemcpyAsync(dX, hx.data(), T * n3 * 8, hipMemcpyHostToDevice, stream));
-          MIX_TRY(hipMemcpyAsync(dY, hy.data(), T * nd3 * 8, hipMemcpyHostToDevice, stream));
-          MIX_TRY(sis::launch_assemble(n, static_cast<int>(T), dX, dY, nullptr, 0.0, nullptr,
-                                       kind == 0 ? block(a, b) : block(a, a), ndof, 1, stream));
-        }
-    }
+    // unequal-mass pairs: rho-quadrature terms, in chunks
+    hy.resize(static_cast<size_t>(2 * chunk) * nd3);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        if (t.kappa[a][b] == 0.0) continue;
+        const int items = D * t.m_rho;
+        for (int kind = 0; kind < 2; ++kind)
+          for (int q0 = 0; q0 < items; q0 += chunk) {
+            const int q1 = std::min(items, q0 + chunk);
+            sis::build_mix_cross_terms(t, a, b, kind, q0, q1, hx.data(), hy.data(), md.n_threads);
+            MIX_TRY(hipStreamSynchronize(stream));  // previous chunk has consumed dX, dY
+            const size_t T = 2 * static_cast<size_t>(q1 - q0);
+            MIX_TRY(hipMemcpyAsync(dX, hx.data(), T * n3 * 8, hipMemcpyHostToDevice, stream));
+            MIX_TRY(hipMemcpyAsync(dY, hy.data(), T * nd3 * 8, hipMemcpyHostToDevice, stream));
+            MIX_TRY(sis::launch_assemble(n, static_cast<int>(T), dX, dY, nullptr, 0.0, nullptr,
+                                         kind == 0 ? block(a, b) : block(a, a), ndof, 1, stream));
+          }
+      }
+  }
+  for (int s = 0; s < 2; ++s) p->nubar_s[s] = t.nubar[s];
+  p->nubar = t.nubar[0];
+  p->h_nu = t.nu;
+  MIX_TRY(hipMemcpyAsync(p->nu, t.nu.data(), 2 * n3 * 8, hipMemcpyHostToDevice, stream));
   // restriction to the stored parity class (odd in v3 / even in v2)
   MIX_TRY(hipStreamSynchronize(stream));
   set_layout(p, desc->parity);
@@ -1468,6 +1845,7 @@ sis_status create_mix_plan(const sis_velocity_desc* desc, hipStream_t stream, si
   p->cq = p->cq_s[0];
   if (p->parity) corr = restrict_rows(p, corr.data(), 4);  // [2 shapes][2 species] -> stored rows
   MIX_TRY(hipStreamSynchronize(stream));
+  if (!dX) MIX_TRY(dmalloc(&dX, corr.size()));
   MIX_TRY(hipMemcpyAsync(dX, corr.data(), corr.size() * 8, hipMemcpyHostToDevice, stream));
   {
     sis::GemmArgs g{};
@@ -1723,22 +2101,6 @@ sis_status create_polar_plan(const sis_velocity_desc* desc, hipStream_t stream, 
   *out = p;
   g_err.clear();
   return SIS_OK;
-}
-
-// cos, sin of the exact phase pi q / P (q reduced mod 2P in integers).
-void phase_q(long q, int P, double& c, double& sn) {
-  const double kPi = 3.14159265358979323846;
-  q %= 2L * P;
-  if (q < 0) q += 2L * P;
-  const double ang = kPi * static_cast<double>(q) / P;
-  c = std::cos(ang);
-  sn = std::sin(ang);
-}
-
-// Phase xi_l v_j of the centred DFT: v_j = (j + 1/2 - n/2) dv, xi_l = pi l / L_p, so
-// xi_l v_j = pi l (2 j + 1 - n) / P.
-void fsm_phase(int l, int j, int n, int P, double& c, double& sn) {
-  phase_q(static_cast<long>(l) * (2 * j + 1 - n), P, c, sn);
 }
 
 // Factor matrices and f_eq fields of the per-cell transform path (one-gas Cartesian plan

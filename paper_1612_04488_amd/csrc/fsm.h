@@ -80,7 +80,9 @@ struct FsmTableArgs {
   FsmDims d;
   int m1, m2, m3;
   const double *e1r, *e1i, *e2r, *e2i, *e3r, *e3i;
+  int64_t e1_ts, e2_ts, e3_ts;  // per-term strides of the factor arrays (0: one set for all terms)
   const double* mult;
+  const int* mrow;      // [T] multiplier row of each term, or null (row t)
   const double* X;
   const int* slot;      // [T]
   const double* scale;  // [T]
@@ -90,6 +92,24 @@ struct FsmTableArgs {
 hipError_t launch_fsm_tables(const FsmTableArgs& a, hipStream_t s);
 // whether launch_fsm_tables holds the modes of d and m2 output nodes on axis 2 in LDS
 bool fsm_tables_fit(const FsmDims& d, int m2);
+
+// Shifted factor matrices of nt terms on m nodes and nl modes l = lmin .. lmin + nl - 1:
+//   e[t][a][k] = w(l) e^{i pi l (base[a] + 2 shift[t]) / P},  w = 1, or (doubled != 0) 2 for l > 0,
+// re and im parts in er, ei ([nt][m][nl] each); base[a] are integers (2a + 1 - n for the velocity
+// nodes, 2(a - (n - 1)) for the difference grid), shift[t] in grid spacings.
+hipError_t launch_fsm_shift_factors(int nt, int m, int nl, int lmin, int doubled, const int* base, const double* shift,
+                                    int shift_stride, int P, double* er, double* ei, hipStream_t s);
+
+// One-dimensional band-limited profiles of nt terms on three axes:
+//   S[t][k][a] = sum_{j < ng} g[j] D_P(off + a - j + z[t][k])   (ng = 0: D_P(off + a + z[t][k])),
+// D_P(w) = (1/P) sum over the non-Nyquist modes l of e^{2 pi i l w / P}; and their products
+//   out[t][a0][a1][a2] = w[t] S[t][0][a0] S[t][1][a1] S[t][2][a2].
+hipError_t launch_band_profiles(int nt, int m, int off, const double* g, int ng, const double* z, int P, double* S,
+                                hipStream_t s);
+hipError_t launch_separable(int nt, int m, const double* S, const double* w, double* out, hipStream_t s);
+// out[t][i] = s[t] in[src[t]][i], i < len
+hipError_t launch_scale_rows(int nt, int64_t len, const double* in, const int* src, const double* sc, double* out,
+                             hipStream_t s);
 
 // Field table of the per-cell path from full-grid rows: for t < nrows,
 //   out[t][v] = scale * (src[t] >= 0 ? in[src[t]][full(v)] : -feq[full(v)])

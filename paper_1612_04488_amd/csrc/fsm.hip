@@ -417,20 +417,26 @@ __global__ __launch_bounds__(kThreads) void fsm_table_kernel(FsmTableArgs a, int
   const int slot = a.slot[t];
   if (slot < 0) return;
   const int L = d.L, Q = d.Q, m2 = a.m2, m3 = a.m3;
+  const double* e1r = a.e1r + t * a.e1_ts;
+  const double* e1i = a.e1i + t * a.e1_ts;
+  const double* e2r = a.e2r + t * a.e2_ts;
+  const double* e2i = a.e2i + t * a.e2_ts;
+  const double* e3r = a.e3r + t * a.e3_ts;
+  const double* e3i = a.e3i + t * a.e3_ts;
   const int r0 = blockIdx.x * K1, kr1 = min(K1, a.m1 - r0);
   double* Zr = sm;                    // [K1][Q][L]
   double* Zi = Zr + K1 * Q * L;
   double* Wr = Zi + K1 * Q * L;       // [K1][Q][m2]
   double* Wi = Wr + K1 * Q * m2;
   const int64_t LL = static_cast<int64_t>(L) * L;
-  const double* mt = a.mult + static_cast<int64_t>(t) * Q * LL;
+  const double* mt = a.mult + static_cast<int64_t>(a.mrow ? a.mrow[t] : t) * Q * LL;
   const int64_t sQL = static_cast<int64_t>(Q) * L;
   {
     const int M = kr1, K = L, N = Q * L;   // column c = (l3, l2)
     auto la = [&](int m, int k, double& re, double& im) {
       const bool ok = m < M && k < K;
-      re = ok ? a.e1r[(r0 + m) * L + k] : 0.0;
-      im = ok ? a.e1i[(r0 + m) * L + k] : 0.0;
+      re = ok ? e1r[(r0 + m) * L + k] : 0.0;
+      im = ok ? e1i[(r0 + m) * L + k] : 0.0;
     };
     auto lb = [&](int k, int c, double& re, double& im) {
       if (k < K && c < N) {
@@ -464,8 +470,8 @@ __global__ __launch_bounds__(kThreads) void fsm_table_kernel(FsmTableArgs a, int
     };
     auto lb = [&](int k, int c, double& re, double& im) {
       const bool ok = k < K && c < N;
-      re = ok ? a.e2r[c * L + k] : 0.0;
-      im = ok ? a.e2i[c * L + k] : 0.0;
+      re = ok ? e2r[c * L + k] : 0.0;
+      im = ok ? e2i[c * L + k] : 0.0;
     };
     auto st = [&](int m, int c, double re, double im) {
       Wr[m * m2 + c] = re;
@@ -484,8 +490,8 @@ __global__ __launch_bounds__(kThreads) void fsm_table_kernel(FsmTableArgs a, int
     };
     auto lb = [&](int k, int c, double& re, double& im) {
       const bool ok = k < K && c < N;
-      re = ok ? a.e3r[c * Q + k] : 0.0;
-      im = ok ? a.e3i[c * Q + k] : 0.0;
+      re = ok ? e3r[c * Q + k] : 0.0;
+      im = ok ? e3i[c * Q + k] : 0.0;
     };
     const double sc = a.scale[t];
     double* out = a.out + static_cast<int64_t>(slot) * a.m1 * m2 * m3;
@@ -506,6 +512,62 @@ __global__ void fsm_gather_kernel(FsmDims d, int nrows, const double* __restrict
   const int64_t full = (static_cast<int64_t>(j1) * n + s2 + (n - d.n2)) * n + s3 + (n - d.n3);
   const int r = src[t];
   out[i] = scale * (r >= 0 ? in[static_cast<int64_t>(r) * n * n * n + full] : -feq[full]);
+}
+
+__global__ void fsm_shift_factor_kernel(int nt, int m, int nl, int lmin, int doubled, const int* __restrict__ base,
+                                        const double* __restrict__ shift, int shift_stride, int P,
+                                        double* __restrict__ er, double* __restrict__ ei) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(nt) * m * nl) return;
+  const int k = static_cast<int>(i % nl), a = static_cast<int>((i / nl) % m), t = static_cast<int>(i / (static_cast<int64_t>(nl) * m));
+  const int l = lmin + k;
+  // the angle pi q / P with q = l (base + 2 z) reduced mod 2P before the sine and cosine
+  double q = l * (base[a] + 2.0 * shift[static_cast<int64_t>(t) * shift_stride]);
+  q -= 2.0 * P * floor(q / (2.0 * P));
+  const double ang = M_PI * q / P;
+  const double w = (doubled && l > 0) ? 2.0 : 1.0;
+  er[i] = w * cos(ang);
+  ei[i] = w * sin(ang);
+}
+
+__global__ void band_profile_kernel(int nt, int m, int off, const double* __restrict__ g, int ng,
+                                    const double* __restrict__ z, int P, double* __restrict__ S) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= static_cast<int64_t>(nt) * 3 * m) return;
+  const int a = static_cast<int>(i % m), k = static_cast<int>((i / m) % 3), t = static_cast<int>(i / (3 * m));
+  const double zz = z[3 * t + k];
+  auto dirichlet = [&](double w) {
+    double s = 1.0;
+    for (int l = 1; l < P / 2; ++l) s += 2.0 * cos(2.0 * M_PI * l * w / P);
+    return s / P;
+  };
+  double acc = 0.0;
+  if (ng == 0) {
+    acc = dirichlet(off + a + zz);
+  } else {
+    for (int j = 0; j < ng; ++j) acc += g[j] * dirichlet(off + a - j + zz);
+  }
+  S[i] = acc;
+}
+
+__global__ void separable_kernel(int nt, int m, const double* __restrict__ S, const double* __restrict__ w,
+                                 double* __restrict__ out) {
+  const int64_t m3 = static_cast<int64_t>(m) * m * m;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nt * m3) return;
+  const int t = static_cast<int>(i / m3);
+  const int64_t r = i - t * m3;
+  const int a0 = static_cast<int>(r / (m * m)), a1 = static_cast<int>((r / m) % m), a2 = static_cast<int>(r % m);
+  const double* St = S + static_cast<int64_t>(t) * 3 * m;
+  out[i] = w[t] * St[a0] * St[m + a1] * St[2 * m + a2];
+}
+
+__global__ void scale_rows_kernel(int nt, int64_t len, const double* __restrict__ in, const int* __restrict__ src,
+                                  const double* __restrict__ sc, double* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nt * len) return;
+  const int t = static_cast<int>(i / len);
+  out[i] = sc[t] * in[static_cast<int64_t>(src[t]) * len + (i - t * len)];
 }
 
 size_t table_lds_bytes(const FsmDims& d, int m2, int K1) {
@@ -562,6 +624,41 @@ hipError_t launch_fsm_gather(const FsmDims& d, int nrows, const double* in, cons
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(fsm_gather_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, d, nrows,
                      in, src, feq, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fsm_shift_factors(int nt, int m, int nl, int lmin, int doubled, const int* base, const double* shift,
+                                    int shift_stride, int P, double* er, double* ei, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(nt) * m * nl;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fsm_shift_factor_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, nt, m,
+                     nl, lmin, doubled, base, shift, shift_stride, P, er, ei);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_profiles(int nt, int m, int off, const double* g, int ng, const double* z, int P, double* S,
+                                hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(nt) * 3 * m;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(band_profile_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, nt, m, off,
+                     g, ng, z, P, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_separable(int nt, int m, const double* S, const double* w, double* out, hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(nt) * m * m * m;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(separable_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, nt, m, S, w,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_rows(int nt, int64_t len, const double* in, const int* src, const double* sc, double* out,
+                             hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(nt) * len;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, s, nt, len, in,
+                     src, sc, out);
   return hipGetLastError();
 }
 

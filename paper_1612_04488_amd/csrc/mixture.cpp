@@ -72,7 +72,7 @@ double mix_viscosity_ratio(const double mass[2], const double diam[2], const dou
   return chi[0] * y0 + chi[1] * y1;
 }
 
-bool build_mix_base(const MixDesc& d, MixTables& t, std::string& err) {
+bool build_mix_grid(const MixDesc& d, MixTables& t, std::string& err) {
   const int n = d.n_v;
   const int np = d.n_pad > 0 ? d.n_pad : 2 * n;
   t.n = n;
@@ -126,6 +126,12 @@ bool build_mix_base(const MixDesc& d, MixTables& t, std::string& err) {
     }
   }
 
+  return true;
+}
+
+bool build_mix_base(const MixDesc& d, MixTables& t, std::string& err) {
+  if (!build_mix_grid(d, t, err)) return false;
+  const int n = t.n, np = t.np;
   PrunedDFT protoK, protoF[2];
   for (int ax = 0; ax < 3; ++ax) {
     protoK.set_kernel_axis(ax, np, n, 0.0);

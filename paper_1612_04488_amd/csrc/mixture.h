@@ -49,6 +49,10 @@ struct MixTables {
   std::vector<double> beta_r;              // [nd3] F^-1[sum_p W_p phi_p psi_p] (unscaled)
 };
 
+// Velocity grid, equilibria, directions, rho nodes and the pair constants only (no
+// transforms: Psi, Phi, Fphi, Fpsi, beta_r, nu and nubar are left empty).
+bool build_mix_grid(const MixDesc& d, MixTables& t, std::string& err);
+
 // Velocity grid, equilibria, collision frequencies, kappa = 0 tables.
 bool build_mix_base(const MixDesc& d, MixTables& t, std::string& err);
 
