@@ -212,10 +212,13 @@ struct sis_geom {
   bool two_d = false;
   bool tube = false;             // SIS_GEOM_TUBE: radial nodes, polar velocity grid
   int max_diag = 0;              // 2-D: largest min(n1, n2) over the cases
+  int max_n2 = 0;                // 2-D: largest n2 over the cases
   double *d_r = nullptr, *d_cin = nullptr, *d_cout = nullptr, *d_tw = nullptr;
   sis::Tables2D t2;
   int32_t *d_n1 = nullptr, *d_n2 = nullptr, *d_gcell = nullptr, *d_sref = nullptr, *d_nb = nullptr;
   uint32_t* d_srec = nullptr;    // packed stencil records of the look-ahead sweep
+  uint32_t* d_grec = nullptr;    // the same in grid order, for the row-blocked sweep
+  int64_t* d_growb = nullptr;    // [grid] byte offset of the cell's first row in h, or -1 (solid)
   int64_t* d_goff = nullptr;
   int8_t *d_skind = nullptr, *d_dflag = nullptr, *d_nbm = nullptr;
   double *d_scoef = nullptr, *d_npos = nullptr, *d_fw = nullptr, *d_width = nullptr, *d_cpos = nullptr,
@@ -248,7 +251,7 @@ struct sis_geom {
     dfree(d_r); dfree(d_cin); dfree(d_cout); dfree(d_tw);
     dfree(off); dfree(x); dfree(coef); dfree(delta_case); dfree(flow_case);
     dfree(delta_cell); dfree(flow_cell); dfree(case_of_cell);
-    dfree(d_n1); dfree(d_n2); dfree(d_gcell); dfree(d_sref); dfree(d_nb); dfree(d_goff); dfree(d_srec);
+    dfree(d_n1); dfree(d_n2); dfree(d_gcell); dfree(d_sref); dfree(d_nb); dfree(d_goff); dfree(d_srec); dfree(d_grec); dfree(d_growb);
     dfree(d_skind); dfree(d_dflag); dfree(d_nbm); dfree(d_scoef); dfree(d_npos); dfree(d_fw);
     dfree(d_width); dfree(d_cpos); dfree(d_dA); dfree(d_area); dfree(work); dfree(have_x); dfree(cg_iters);
   }
@@ -667,6 +670,9 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.ref = g->d_sref;
     a.kind = g->d_skind;
     a.rec = g->d_srec;
+    a.grec = g->d_grec;
+    a.growb = g->d_growb;
+    a.grid_none = g->t2.n_grid;
     a.delta_case = g->delta_case;
     a.v1d = p->v1d;
     a.nu = p->nu;
@@ -674,6 +680,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.h = h;
     a.case_active = case_active;
     a.max_diag = g->max_diag;
+    a.max_n2 = g->max_n2;
     HIP_TRY(sis::launch_sweep2d(a, s));
     if (mom)
       HIP_TRY(sis::launch_moments2d(p->nv, p->nsp, p->mass_ratio, g->n_cells, p->vtab, h, p->wr, cell_active, mom, s));
@@ -1160,12 +1167,13 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
     return fail(SIS_E_INVALID, "null 2-D geometry array");
   std::vector<sis::Case2D> cases(d->n_cases);
   int64_t f1o = 0, f2o = 0, so = 0;
-  int max_diag = 0;
+  int max_diag = 0, max_n2 = 0;
   for (int c = 0; c < d->n_cases; ++c) {
     sis::Case2D& k = cases[c];
     k.n1 = d->n1[c];
     k.n2 = d->n2[c];
     max_diag = std::max(max_diag, std::min(k.n1, k.n2));
+    max_n2 = std::max(max_n2, k.n2);
     if (k.n1 < 2 || k.n2 < 2 || k.n1 > 4096 || k.n2 > 4096)
       return fail(SIS_E_SHAPE, "case %d: n1, n2 must be in [2, 4096]", c);
     k.f1.assign(d->face1 + f1o, d->face1 + f1o + k.n1 + 1);
@@ -1190,6 +1198,7 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
   g->n_cases = d->n_cases;
   g->two_d = true;
   g->max_diag = max_diag;
+  g->max_n2 = max_n2;
   std::string err;
   if (!sis::build_tables_2d(cases, g->t2, err)) { delete g; return fail(SIS_E_INVALID, "%s", err.c_str()); }
   const sis::Tables2D& t = g->t2;
@@ -1220,21 +1229,43 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
   G2_TRY(upload(&g->d_scoef, t.st_coef, stream));
   G2_TRY(upload(&g->d_sref, t.st_ref, stream));
   G2_TRY(upload(&g->d_skind, t.st_kind, stream));
-  {
-    // one 32-byte record per (cell, axis, sign): coefficients a, b, c, then the two references
-    // as (ref << 2 | kind); at least one record so that masked lanes can load a valid address
-    const size_t nrec = t.st_coef.size() / 3;
-    if (nrec / 4 >= (size_t(1) << 30)) { delete g; return fail(SIS_E_SHAPE, "more than 2^30 fluid cells"); }
-    std::vector<uint32_t> rec(std::max<size_t>(nrec, 1) * 8, 0u);
-    for (size_t o = 0; o < nrec; ++o) {
-      std::memcpy(&rec[o * 8], &t.st_coef[o * 3], 3 * sizeof(double));
-      for (int k = 0; k < 2; ++k) {
-        const int kind = t.st_kind[o * 2 + k];
-        rec[o * 8 + 6 + k] = kind == 0 ? 0u : (static_cast<uint32_t>(t.st_ref[o * 2 + k]) << 2) | static_cast<uint32_t>(kind);
-      }
+  // one 32-byte record per (cell, axis, sign): coefficients a, b, c, then the two references
+  // as (ref << 2 | kind); at least one record so that masked lanes can load a valid address.
+  // The row-blocked sweep reads the same records in grid order, with the coefficient of a
+  // reference of kind 0 (wall or solid face, h = 0) set to 0 and zero records at solid cells.
+  const size_t nrec = t.st_coef.size() / 3;
+  if (nrec / 4 >= (size_t(1) << 30)) { delete g; return fail(SIS_E_SHAPE, "more than 2^30 fluid cells"); }
+  std::vector<uint32_t> rec(std::max<size_t>(nrec, 1) * 8, 0u);
+  for (size_t o = 0; o < nrec; ++o) {
+    std::memcpy(&rec[o * 8], &t.st_coef[o * 3], 3 * sizeof(double));
+    for (int k = 0; k < 2; ++k) {
+      const int kind = t.st_kind[o * 2 + k];
+      rec[o * 8 + 6 + k] = kind == 0 ? 0u : (static_cast<uint32_t>(t.st_ref[o * 2 + k]) << 2) | static_cast<uint32_t>(kind);
     }
-    G2_TRY(upload(&g->d_srec, rec, stream));
   }
+  G2_TRY(upload(&g->d_srec, rec, stream));
+  // (solid cells: a = 1, so that the placeholder update the sweep computes there stays finite;
+  // one more solid entry at index n_grid stands for positions outside the grid)
+  std::vector<uint32_t> grec(static_cast<size_t>(t.n_grid + 1) * 4 * 8, 0u);
+  std::vector<int64_t> growb(t.n_grid + 1, -1);
+  for (int64_t gi = 0; gi <= t.n_grid; ++gi) {
+    const int32_t cell = gi < t.n_grid ? t.gcell[gi] : -1;
+    for (int o = 0; o < 4; ++o) {
+      uint32_t* dst = &grec[(static_cast<size_t>(gi) * 4 + o) * 8];
+      if (cell < 0) {
+        const double one = 1.0;
+        std::memcpy(dst, &one, sizeof(double));
+        continue;
+      }
+      const uint32_t* src = &rec[(static_cast<size_t>(cell) * 4 + o) * 8];
+      std::memcpy(dst, src, 8 * sizeof(uint32_t));
+      for (int k = 0; k < 2; ++k)
+        if (src[6 + k] == 0u) { dst[2 + 2 * k] = 0u; dst[3 + 2 * k] = 0u; }
+    }
+    if (cell >= 0) growb[gi] = static_cast<int64_t>(cell) * p->nsp * p->nv * static_cast<int64_t>(sizeof(double));
+  }
+  G2_TRY(upload(&g->d_grec, grec, stream));
+  G2_TRY(upload(&g->d_growb, growb, stream));
   G2_TRY(upload(&g->d_dflag, t.dflag, stream));
   G2_TRY(upload(&g->d_nb, t.nb, stream));
   G2_TRY(upload(&g->d_nbm, t.nbm, stream));
@@ -2771,7 +2802,7 @@ int32_t sis_geometry_moment_stride(sis_geom_t g) { return g ? g->mom_stride() : 
 
 int32_t sis_geometry_sweep_form(sis_geom_t g) {
   if (!g || !g->two_d) return -1;
-  return sis::sweep2d_form(g->max_diag);
+  return sis::sweep2d_form(g->max_diag, g->max_n2);
 }
 
 sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,

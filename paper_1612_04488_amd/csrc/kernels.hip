@@ -1457,6 +1457,235 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2
   }
 }
 
+// Row-blocked form of the same sweep, for cross sections of up to kRowWaves * kRowWidthMax
+// cells along axis 2.  A lane owns one velocity quadruple, and every value it reads during
+// the sweep belongs to that quadruple: in-quadrant upwind cells (this sweep), mirror ghosts
+// (the quadrant with the mirrored axis's sign flipped: this sweep if it came earlier, else
+// the previous iterate) and periodic wraps (cells later in the sweep order: the previous
+// iterate).  Any order in which each cell follows its upwind cells along both axes
+// therefore reads the values the anti-diagonal order reads; the update of each cell is the
+// same expression in the same order (a reference of kind 0 enters with coefficient 0 in
+// place of being skipped), so the results agree to the sign of zeros.
+//
+// A workgroup holds W waves of 64 quadruples each, of one case and species, and sweeps the
+// four quadrants in the same order.  Within a quadrant the cells are taken in the sweep's
+// orientation (row r, column c counted from the upwind corner); the columns are split into
+// W blocks of cw <= CW, and at step s wave w processes row s - w of its block, column by
+// column.  The two values left of the block come from wave w - 1 through LDS (written at
+// step s - 1, double-buffered by step parity), the two rows above are the lane's registers,
+// and only references that leave the grid (rows and columns 0 and 1: mirror ghosts and
+// periodic wraps) are read from h.  A block row's uniform data (grid-ordered stencil records
+// and cell indices) is loaded one word per lane three rows ahead and kept in a ring of three
+// LDS slots per wave, read back by broadcast (coefficients) or into scalar registers (cell
+// indices, reference words) where needed; the right sides and the out-of-grid references
+// of axis 2 are loaded one row ahead.  Registers that receive loads alternate between two
+// sets (the step loop is unrolled by two), so that no register copy waits for a load.
+// Between steps the waves exchange only LDS, so the barrier does not wait for the stores of
+// h; the full barrier at the end of a quadrant makes them visible to the mirror reads of
+// the next.
+constexpr int kRowWaves = 16;
+constexpr int kRowWidth = 4;      // columns per wave and row
+
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ inline double rec_f64(const uint32_t* __restrict__ r, int k) {
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(r[2 * k + 1]) << 32) | r[2 * k]);
+}
+
+__global__ __launch_bounds__(64 * kRowWaves) void sweep2d_rows_kernel(
+    Sweep2DArgs a, const uint32_t* __restrict__ grec, const int64_t* __restrict__ growb,
+    const double* __restrict__ rhs, double* __restrict__ h) {
+  constexpr int CW = kRowWidth;
+  constexpr int kRowWords = 18 * CW;                // 16 record words and a 64-bit row offset per cell
+  constexpr int kRegs = (kRowWords + 63) / 64;
+  __shared__ double carry[2][kRowWaves][2][64];
+  __shared__ __align__(16) uint32_t stage[kRowWaves][3][kRegs * 64];
+  __shared__ double edge1[kRowWaves][3][CW][64];    // out-of-grid axis-1 references of rows 0, 1
+  const int cs = blockIdx.y;
+  if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
+  const int W = blockDim.x >> 6, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int n = a.n, hn = n / 2, n3 = a.n3, d3 = a.d3;
+  const int nsp = a.nsp, sp = blockIdx.z;
+  const double* __restrict__ nu = a.nu + static_cast<int64_t>(sp) * n3;
+  const int64_t row_elems = static_cast<int64_t>(nsp) * n3;
+  // rows of species sp: cell c's row at byte offset growb (c * row_elems doubles)
+  const char* __restrict__ rhs_s = reinterpret_cast<const char*>(rhs + static_cast<int64_t>(sp) * n3);
+  char* __restrict__ h_s = reinterpret_cast<char*>(h + static_cast<int64_t>(sp) * n3);
+  const int quads = hn * hn * d3;
+  const int tq = blockIdx.x * 64 + lane;
+  const bool vvalid = tq < quads;
+  const int t = vvalid ? tq : 0;
+  const int jq1 = t / (hn * d3), jq2 = (t / d3) % hn, j3 = t % d3;
+  const int n1 = a.n1[cs], n2 = a.n2[cs];
+  const int64_t g0 = a.grid_off[cs];
+  const double del = a.delta_case[cs];
+  const int cw = (n2 + W - 1) / W;                   // <= CW (checked by the launcher)
+  const int jb0 = min(w * cw, n2), nb = min(cw, n2 - jb0);
+  // every wave runs every step (rows outside [0, n1) are placeholders: no cells, nothing
+  // stored), an even number of them for the two-step loop body
+  const int steps = (n1 + W) & ~1;
+  for (int q = 0; q < 4; ++q) {
+    const int s1 = (q & 1) ? -1 : 1, s2 = (q & 2) ? -1 : 1;
+    const int j1 = s1 > 0 ? hn + jq1 : hn - 1 - jq1;
+    const int j2 = s2 > 0 ? hn + jq2 : hn - 1 - jq2;
+    const int v = (j1 * n + j2) * d3 + j3;
+    const int vm1 = ((n - 1 - j1) * n + j2) * d3 + j3;
+    const int vm2 = (j1 * n + (n - 1 - j2)) * d3 + j3;
+    const uint32_t vb = v * 8u;
+    const double av1 = fabs(a.v1d[j1]), av2 = fabs(a.v1d[j2]);
+    const double dnu = del * nu[v];
+    const int sg1 = s1 > 0 ? 0 : 1, sg2 = s2 > 0 ? 0 : 1;
+    // grid index of the block's column k in oriented row r: rbase(r) + dj k
+    const int dj = s2, jstart = s2 > 0 ? jb0 : n2 - 1 - jb0;
+    auto rbase = [&](int r) { return g0 + static_cast<int64_t>(s1 > 0 ? r : n1 - 1 - r) * n2 + jstart; };
+    // Staging slot of row r (r >= -kRowWaves): 16 record words per cell (axis 1 with the sign
+    // of v1, then axis 2 with the sign of v2), then the cells' 64-bit row offsets (-1: none),
+    // one word per lane.  Where there is no cell (outside the block or the grid) the words are
+    // read from the tables' extra solid entry (a = 1, no references, offset -1): every lane
+    // loads, and uses the word as loaded, so that all steps issue the same memory
+    // instructions, the waits for them stay counted, and nothing waits before the barrier.
+    auto slot = [&](int r) { return (r + 3 * kRowWaves) % 3; };
+    auto load_row = [&](int r, uint32_t (&sv)[kRegs]) {
+      const bool rv = r >= 0 && r < n1;
+      const int64_t gb = rbase(rv ? r : 0);
+#pragma unroll
+      for (int u = 0; u < kRegs; ++u) {
+        const int x = 64 * u + lane;
+        const bool isrec = x < 16 * CW;
+        const int k = isrec ? x >> 4 : (x - 16 * CW) >> 1, d = x & 15, axis = d >> 3;
+        const int64_t gk = rv && k < nb ? gb + dj * k : a.grid_none;
+        sv[u] = isrec ? grec[(gk * 4 + axis * 2 + (axis ? sg2 : sg1)) * 8 + (d & 7)]
+                      : reinterpret_cast<const uint32_t*>(growb + gk)[x & 1];
+      }
+    };
+    auto put_row = [&](int r, const uint32_t (&sv)[kRegs]) {
+#pragma unroll
+      for (int u = 0; u < kRegs; ++u) stage[w][slot(r)][64 * u + lane] = sv[u];
+    };
+    auto coef = [&](int r, int k, int wd) {
+      return *reinterpret_cast<const double*>(&stage[w][slot(r)][16 * k + wd]);
+    };
+    auto word = [&](int r, int i) { return __builtin_amdgcn_readfirstlane(stage[w][slot(r)][i]); };
+    auto row_off = [&](int r, int k) {
+      return static_cast<int64_t>((static_cast<uint64_t>(word(r, 16 * CW + 2 * k + 1)) << 32) | word(r, 16 * CW + 2 * k));
+    };
+    // Loaded values are used as loaded: where there is no cell or no reference (kind 0), a
+    // finite value of cell 0's row stands in and meets a zero coefficient or a discarded
+    // update, so that no select waits for the load before the barrier.
+    auto load_rhs = [&](int r, double (&rr)[CW]) {
+#pragma unroll
+      for (int k = 0; k < CW; ++k) {
+        const int64_t o = row_off(r, k);
+        rr[k] = *reinterpret_cast<const double*>(rhs_s + (o >= 0 ? o : 0) + vb);
+      }
+    };
+    auto ref_at = [&](uint32_t x, int vmir) {
+      const int64_t c = x & 3u ? static_cast<int64_t>(x >> 2) : 0;
+      return reinterpret_cast<const double*>(h_s)[c * row_elems + ((x & 3u) == 2 ? vmir : v)];
+    };
+    // out-of-grid axis-2 references: column c, reference st (one and two cells upwind), of the
+    // block's first two columns if it holds them
+    auto load_edge = [&](int r, double (&ge)[3]) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int c = e == 2 ? 1 : 0, st = e == 0 ? 0 : 1;
+        const bool mine = c >= jb0 && c < jb0 + nb;
+        ge[e] = ref_at(mine ? word(r, 16 * (c - jb0) + 14 + st) : 0u, vm2);
+      }
+    };
+    // out-of-grid axis-1 references: rows 0 (both) and 1 (the second), read when row 0 comes
+#pragma unroll
+    for (int k = 0; k < CW; ++k) {
+      const bool have = k < nb;
+      const uint32_t* p0 = grec + ((have ? rbase(0) + dj * k : a.grid_none) * 4 + sg1) * 8;
+      const uint32_t* p1 = grec + ((have ? rbase(1) + dj * k : a.grid_none) * 4 + sg1) * 8;
+      edge1[w][0][k][lane] = ref_at(p0[6], vm1);
+      edge1[w][1][k][lane] = ref_at(p0[7], vm1);
+      edge1[w][2][k][lane] = ref_at(p1[7], vm1);
+    }
+    double pr1[CW], pr2[CW];              // rows r - 1, r - 2 of the block
+    uint32_t sA[kRegs], sB[kRegs];        // staging words of row r + 2 (A / B alternate)
+    double rA[CW], rB[CW], eA[3], eB[3];  // right sides and edge references of a row
+    const int r0 = -w;                    // the wave's row at step 0
+    load_row(r0, sA);
+    load_row(r0 + 1, sB);
+    put_row(r0, sA);
+    put_row(r0 + 1, sB);
+    load_row(r0 + 2, sA);
+    load_rhs(r0, rA);
+    load_edge(r0, eA);
+    // step s: row r = s - w with (rc, ec) of row r and the staging words sc of row r + 2 loaded
+    // by the previous step; loads sn of row r + 3 and (rn, en) of row r + 1.  Calls alternate
+    // the A / B sets.
+    auto step = [&](int s, double (&rc)[CW], double (&ec)[3], uint32_t (&sc)[kRegs], double (&rn)[CW],
+                    double (&en)[3], uint32_t (&sn)[kRegs]) {
+      const int r = s - w;
+      put_row(r + 2, sc);
+      load_row(r + 3, sn);
+      load_rhs(r + 1, rn);
+      load_edge(r + 1, en);
+      if (r == 0) {
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+          pr1[k] = edge1[w][0][k][lane];
+          pr2[k] = edge1[w][1][k][lane];
+        }
+      } else if (r == 1) {
+#pragma unroll
+        for (int k = 0; k < CW; ++k) pr2[k] = edge1[w][2][k][lane];
+      }
+      double p1 = 0.0, p2 = 0.0;              // columns c - 1, c - 2 of this row
+      if (w > 0) {
+        p1 = carry[(s - 1) & 1][w - 1][0][lane];
+        p2 = carry[(s - 1) & 1][w - 1][1][lane];
+      }
+      if (jb0 == 0) {
+        p1 = ec[0];
+        p2 = ec[1];
+      }
+      const double in1 = p1, in2 = p2;
+      double hv[CW];
+#pragma unroll
+      for (int k = 0; k < CW; ++k) {
+        if (jb0 + k == 1) p2 = ec[2];
+        double acc = rc[k] - av1 * coef(r, k, 2) * pr1[k];
+        acc -= av2 * coef(r, k, 10) * p1;
+        acc -= av1 * coef(r, k, 4) * pr2[k];
+        acc -= av2 * coef(r, k, 12) * p2;
+        hv[k] = acc / (dnu + av1 * coef(r, k, 0) + av2 * coef(r, k, 8));
+        const int64_t o = row_off(r, k);
+        if (vvalid && o >= 0) *reinterpret_cast<double*>(h_s + o + vb) = hv[k];   // per-lane predicate
+        p2 = p1;
+        p1 = hv[k];
+        pr2[k] = pr1[k];
+        pr1[k] = hv[k];
+      }
+      if (nb < CW) {                          // the carry is the block's last two columns
+        p1 = in1;
+        p2 = in2;
+#pragma unroll
+        for (int k = 0; k < CW; ++k)
+          if (k < nb) {
+            p2 = p1;
+            p1 = hv[k];
+          }
+      }
+      carry[s & 1][w][0][lane] = p1;
+      carry[s & 1][w][1][lane] = p2;
+      lds_barrier();
+    };
+    for (int s = 0; s < steps; s += 2) {
+      step(s, rA, eA, sA, rB, eB, sB);
+      step(s + 1, rB, eB, sB, rA, eA, sA);
+    }
+    __syncthreads();
+  }
+}
+
 // Per (cell, species) row: U3, q3 = int (a v^2 - 5/2) v3 h, G1, G12, G2, P13 = 2a int v1 v3 h,
 // P23 = 2a int v2 v3 h (a = m_s / m_A; 1 for one gas).
 __global__ __launch_bounds__(256) void moments2d_kernel(int n3, int nsp, double ms0, double ms1,
@@ -2294,25 +2523,33 @@ hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
 }
 
 
-int sweep2d_form(int max_diag) {
+int sweep2d_form(int max_diag, int max_n2) {
+  if (max_n2 <= kRowWaves * kRowWidth) return 1;
   const int slots = kSweepThreads / kSweepV;
-  const int P = (max_diag + slots - 1) / slots;
-  return P <= 1 ? 1 : (P <= kSweepMaxP ? P : 0);
+  return (max_diag + slots - 1) / slots <= kSweepMaxP ? 2 : 3;
 }
 
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   const int hn = a.n / 2;
   const int count = hn * hn * a.d3;
+  const int form = sweep2d_form(a.max_diag, a.max_n2);
+  if (form == 1) {
+    const int W = (a.max_n2 + kRowWidth - 1) / kRowWidth;
+    dim3 grid((count + 63) / 64, a.n_cases, a.nsp);
+    hipLaunchKernelGGL(sweep2d_rows_kernel, grid, dim3(64 * W), 0, s, a, a.grec, a.growb, a.rhs, a.h);
+    return hipGetLastError();
+  }
   dim3 grid((count + kSweepV - 1) / kSweepV, a.n_cases, a.nsp);
-  const int P = sweep2d_form(a.max_diag);
-  if (P == 1)
+  const int slots = kSweepThreads / kSweepV;
+  const int P = (a.max_diag + slots - 1) / slots;
+  if (form == 3)
+    hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(kSweepThreads), 0, s, a);
+  else if (P <= 1)
     hipLaunchKernelGGL(sweep2d_pipelined_kernel<1>, grid, dim3(kSweepThreads), 0, s, a);
   else if (P == 2)
     hipLaunchKernelGGL(sweep2d_pipelined_kernel<2>, grid, dim3(kSweepThreads), 0, s, a);
-  else if (P == 3)
-    hipLaunchKernelGGL(sweep2d_pipelined_kernel<3>, grid, dim3(kSweepThreads), 0, s, a);
   else
-    hipLaunchKernelGGL(sweep2d_kernel, grid, dim3(kSweepThreads), 0, s, a);
+    hipLaunchKernelGGL(sweep2d_pipelined_kernel<3>, grid, dim3(kSweepThreads), 0, s, a);
   return hipGetLastError();
 }
 

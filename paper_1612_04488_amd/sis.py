@@ -425,8 +425,8 @@ class Geometry2D:
         self.mom_stride = 8
 
     def sweep_form(self):
-        """Kernel form of the 2-D sweep: cells per slot P (1..3) of the anti-diagonal
-        sweep, or 0 for the row-ordered sweep (anti-diagonals over 192 cells)."""
+        """Kernel form of the 2-D sweep: 1 row-blocked (every case at most 128
+        cells along axis 2), 2 pipelined anti-diagonal, 3 plain anti-diagonal."""
         return int(lib().sis_geometry_sweep_form(self.handle))
 
     def diffusion_solver(self, mode, stream=None):

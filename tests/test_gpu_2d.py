@@ -267,37 +267,51 @@ def test_sweep2d_at_benchmark_size():
 
 
 def _large_sweep_case(name):
-    """Cross sections that select each wide form of the 2-D sweep: the porous
-    benchmark's 128^2 disc mask (Sec. 3.2; two cells per slot), the level-3
-    Sierpinski quarter on 135^2 cells (Sec. 3.1; three per slot) and a 200^2
-    quarter duct (Sec. 2.4; anti-diagonals over 192 cells: the row-ordered
-    sweep)."""
+    """Cross sections that select each form of the 2-D sweep.  Row-blocked (at
+    most 64 cells along axis 2): a 64^2 periodic disc mask (Sec. 3.2; solids,
+    periodic wraps at rows and columns 0 and 1), the level-3 Sierpinski quarter
+    on 54^2 cells (Sec. 3.1; solids, mirror ghosts) and a ragged batch of quarter
+    ducts of 64 x 64, 12 x 10 and 9 x 3 cells (blocks of one column and empty
+    blocks).  Pipelined anti-diagonal: the porous benchmark's 128^2 disc mask
+    (two cells per slot) and the level-3 Sierpinski quarter on 135^2 cells (three
+    per slot).  Plain anti-diagonal: a 200^2 quarter duct (Sec. 2.4;
+    anti-diagonals over 192 cells)."""
+    if name == "porous64":
+        mask, _ = inputs.porous_discs(64)
+        f = np.linspace(0.0, 1.0, 65)
+        return "periodic", [(f, f, mask)], 1
+    if name == "carpet54":
+        return "duct", [inputs.sierpinski_quarter(3, 54)], 1
+    if name == "ragged":
+        return "duct", [(inputs.duct_faces(64, 0.5), inputs.duct_faces(64, 0.5), None),
+                        (inputs.duct_faces(12, 0.5), inputs.duct_faces(10, 1.0), None),
+                        (inputs.duct_faces(9, 0.5), inputs.duct_faces(3, 0.25), None)], 1
     if name == "porous128":
         f, _, mask = inputs.porous_cases(inputs.POROUS_HS)[0]
         return "periodic", [(f, f, mask)], 2
     if name == "carpet135":
-        return "duct", [inputs.sierpinski_quarter(3, 135)], 3
+        return "duct", [inputs.sierpinski_quarter(3, 135)], 2
     f = inputs.duct_faces(200, 0.5)
-    return "duct", [(f, f, None)], 0
+    return "duct", [(f, f, None)], 3
 
 
-@pytest.mark.parametrize("name", ["porous128", "carpet135", "duct200"])
-def test_sweep2d_wide_forms_parity(name):
-    """Every wide form of the 2-D sweep the benchmarks run, element by element
-    over all cells against the oracle's sweep, on a small velocity grid (8^3) so
-    that the oracle stays cheap; the geometry reports which form it launches."""
+@pytest.mark.parametrize("name", ["porous64", "carpet54", "ragged", "porous128", "carpet135", "duct200"])
+def test_sweep2d_forms_parity(name):
+    """Every form of the 2-D sweep, element by element over all cells against
+    the oracle's sweep, on a small velocity grid (8^3) so that the oracle stays
+    cheap; the geometry reports which form it launches."""
     n_v, l_v, m = 8, 4.0, 3
     kind, cases, form = _large_sweep_case(name)
-    say("sweep2d wide form", name)
+    say("sweep2d form", name)
     p = plan(n_v, l_v, m)
-    deltas, flows = [3.0], [1]
+    deltas, flows = [3.0, 0.0, 0.5][:len(cases)], [1] * len(cases)
     geom = sis.Geometry2D(p, kind, cases, deltas, flows)
     assert geom.sweep_form() == form
     f = fsm(n_v, l_v, m)
     vg = f.grid
-    g = oracle_grids(kind, cases)[0]
+    grids = oracle_grids(kind, cases)
     nc = geom.n_cells
-    assert nc == len(g.cells)
+    assert nc == sum(len(g.cells) for g in grids)
     rhs = inputs.smooth_h(n_v, l_v, nc, seed=5) + 0.1 * inputs.rough_h(n_v, l_v, nc, seed=3)
     hprev = inputs.rough_h(n_v, l_v, nc, seed=9)
     hd = dev(hprev.reshape(nc, -1))
@@ -305,7 +319,10 @@ def test_sweep2d_wide_forms_parity(name):
     sis.transport_sweep(p, geom, dev(rhs.reshape(nc, -1)), hd, mom)
     torch.cuda.synchronize()
     hd, mom = hd.cpu().numpy(), mom.cpu().numpy()
-    ref = duct.sweep_2d(rhs, deltas[0] * f.nu, g, vg, hprev)
-    assert rel(hd.reshape(ref.shape), ref) < 1e-12
-    mref = duct.moments_2d(vg, ref)
-    assert np.max(np.abs(mom[:, :7] - mref)) < 1e-12 * np.max(np.abs(mref))
+    o = geom.offsets
+    for c, g in enumerate(grids):
+        s = slice(o[c], o[c + 1])
+        ref = duct.sweep_2d(rhs[s], deltas[c] * f.nu, g, vg, hprev[s])
+        assert rel(hd[s].reshape(ref.shape), ref) < 1e-12, c
+        mref = duct.moments_2d(vg, ref)
+        assert np.max(np.abs(mom[s, :7] - mref)) < 1e-12 * np.max(np.abs(mref)), c
