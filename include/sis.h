@@ -249,9 +249,10 @@ int64_t    sis_geometry_cells(sis_geom_t geom);
 int32_t    sis_geometry_moment_stride(sis_geom_t geom);   /* 4 planar, 8 in 2-D; -1 if NULL */
 /* Form of the 2-D transport sweep this geometry launches (diagnostic; the
  * results do not depend on it): 1 the row-blocked sweep (every case at most 128
- * cells along axis 2: one velocity quadruple per lane, columns split over up to
- * 16 waves), else anti-diagonal wavefronts: 2 pipelined (anti-diagonals of up
- * to 192 cells), 3 plain.  -1 for planar and tube geometries or NULL.          */
+ * cells along axis 2 and the distributions under 2 GiB: one velocity quadruple
+ * per lane, columns split over up to 16 waves), else anti-diagonal wavefronts:
+ * 2 pipelined (anti-diagonals of up to 192 cells), 3 plain.  -1 for planar and
+ * tube geometries or NULL.                                                      */
 int32_t    sis_geometry_sweep_form(sis_geom_t geom);
 
 /* Solver of the 2-D velocity equation (sis_diffusion_correct; the operator

@@ -218,7 +218,7 @@ struct sis_geom {
   int32_t *d_n1 = nullptr, *d_n2 = nullptr, *d_gcell = nullptr, *d_sref = nullptr, *d_nb = nullptr;
   uint32_t* d_srec = nullptr;    // packed stencil records of the look-ahead sweep
   uint32_t* d_grec = nullptr;    // the same in grid order, for the row-blocked sweep
-  int64_t* d_growb = nullptr;    // [grid] byte offset of the cell's first row in h, or -1 (solid)
+  uint32_t* d_growb = nullptr;   // [grid + 1] byte offset of the cell's first row in h, or ~0 (solid)
   int64_t* d_goff = nullptr;
   int8_t *d_skind = nullptr, *d_dflag = nullptr, *d_nbm = nullptr;
   double *d_scoef = nullptr, *d_npos = nullptr, *d_fw = nullptr, *d_width = nullptr, *d_cpos = nullptr,
@@ -673,6 +673,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.grec = g->d_grec;
     a.growb = g->d_growb;
     a.grid_none = g->t2.n_grid;
+    a.row_bytes_total = g->n_cells * static_cast<int64_t>(p->nsp) * p->nv * static_cast<int64_t>(sizeof(double));
     a.delta_case = g->delta_case;
     a.v1d = p->v1d;
     a.nu = p->nu;
@@ -1247,7 +1248,7 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
   // (solid cells: a = 1, so that the placeholder update the sweep computes there stays finite;
   // one more solid entry at index n_grid stands for positions outside the grid)
   std::vector<uint32_t> grec(static_cast<size_t>(t.n_grid + 1) * 4 * 8, 0u);
-  std::vector<int64_t> growb(t.n_grid + 1, -1);
+  std::vector<uint32_t> growb(t.n_grid + 1, 0xffffffffu);
   for (int64_t gi = 0; gi <= t.n_grid; ++gi) {
     const int32_t cell = gi < t.n_grid ? t.gcell[gi] : -1;
     for (int o = 0; o < 4; ++o) {
@@ -1262,7 +1263,8 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
       for (int k = 0; k < 2; ++k)
         if (src[6 + k] == 0u) { dst[2 + 2 * k] = 0u; dst[3 + 2 * k] = 0u; }
     }
-    if (cell >= 0) growb[gi] = static_cast<int64_t>(cell) * p->nsp * p->nv * static_cast<int64_t>(sizeof(double));
+    const int64_t off = static_cast<int64_t>(cell) * p->nsp * p->nv * static_cast<int64_t>(sizeof(double));
+    if (cell >= 0 && off < (int64_t(1) << 31)) growb[gi] = static_cast<uint32_t>(off);
   }
   G2_TRY(upload(&g->d_grec, grec, stream));
   G2_TRY(upload(&g->d_growb, growb, stream));
@@ -2802,7 +2804,7 @@ int32_t sis_geometry_moment_stride(sis_geom_t g) { return g ? g->mom_stride() : 
 
 int32_t sis_geometry_sweep_form(sis_geom_t g) {
   if (!g || !g->two_d) return -1;
-  return sis::sweep2d_form(g->max_diag, g->max_n2);
+  return sis::sweep2d_form(g->max_diag, g->max_n2, g->n_cells * static_cast<int64_t>(g->plan->nsp) * g->plan->nv * 8);
 }
 
 sis_status sis_collide(sis_plan_t p, int64_t n_cells, const double* h, const double* dU,

@@ -156,10 +156,11 @@ struct Sweep2DArgs {
                              // (ref << 2 | kind) of both references (0 for kind 0)
   const uint32_t* grec;      // [grid + 1][2][2] the records in grid order, coefficients of kind-0
                              // references set to 0; at solid cells a = 1, the rest 0
-  const int64_t* growb;      // [grid] byte offset of the cell's first row (species 0) in h and
-                             // rhs, -1 at solid cells
+  const uint32_t* growb;     // [grid + 1] byte offset of the cell's first row (species 0) in h and
+                             // rhs, 0xffffffff at solid cells (valid while h is under 2 GiB)
   int64_t grid_none;         // index of the extra solid entry of grec and growb (positions
                              // outside the grid)
+  int64_t row_bytes_total;   // bytes of h (all cells and species)
   const double* delta_case;
   const double* v1d;
   const double* nu;
@@ -170,10 +171,10 @@ struct Sweep2DArgs {
   int max_n2;                // largest n2 over the cases
 };
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s);
-// Kernel form launch_sweep2d takes: 1 sweep2d_rows_kernel (max_n2 <= 64), else for
-// anti-diagonals of up to max_diag cells 2 sweep2d_pipelined_kernel (max_diag <= 192) or
-// 3 sweep2d_kernel.
-int sweep2d_form(int max_diag, int max_n2);
+// Kernel form launch_sweep2d takes: 1 sweep2d_rows_kernel (max_n2 <= 128 and h under 2 GiB),
+// else for anti-diagonals of up to max_diag cells 2 sweep2d_pipelined_kernel (max_diag <= 192)
+// or 3 sweep2d_kernel.
+int sweep2d_form(int max_diag, int max_n2, int64_t row_bytes_total);
 // mom[cell][species][8] = {U3, q3, G1, G12, G2, P13, P23, 0}; rows of n x n x d3 velocities;
 // q3 and P13, P23 carry the species mass ratio (q3 = int (a v^2 - 5/2) v3 h, P = 2 a int v v3 h)
 hipError_t launch_moments2d(int n3, int nsp, const double* mass_ratio, int64_t n_cells, const double* vtab,

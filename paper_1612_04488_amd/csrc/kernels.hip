@@ -1457,7 +1457,7 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2
   }
 }
 
-// Row-blocked form of the same sweep, for cross sections of up to kRowWaves * kRowWidthMax
+// Row-blocked form of the same sweep, for cross sections of up to kRowWaves * kRowWidth = 64
 // cells along axis 2.  A lane owns one velocity quadruple, and every value it reads during
 // the sweep belongs to that quadruple: in-quadrant upwind cells (this sweep), mirror ghosts
 // (the quadrant with the mirrored axis's sign flipped: this sweep if it came earlier, else
@@ -1470,64 +1470,92 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2
 // A workgroup holds W waves of 64 quadruples each, of one case and species, and sweeps the
 // four quadrants in the same order.  Within a quadrant the cells are taken in the sweep's
 // orientation (row r, column c counted from the upwind corner); the columns are split into
-// W blocks of cw <= CW, and at step s wave w processes row s - w of its block, column by
-// column.  The two values left of the block come from wave w - 1 through LDS (written at
-// step s - 1, double-buffered by step parity), the two rows above are the lane's registers,
-// and only references that leave the grid (rows and columns 0 and 1: mirror ghosts and
-// periodic wraps) are read from h.  A block row's uniform data (grid-ordered stencil records
-// and cell indices) is loaded one word per lane three rows ahead and kept in a ring of three
-// LDS slots per wave, read back by broadcast (coefficients) or into scalar registers (cell
-// indices, reference words) where needed; the right sides and the out-of-grid references
-// of axis 2 are loaded one row ahead.  Registers that receive loads alternate between two
-// sets (the step loop is unrolled by two), so that no register copy waits for a load.
-// Between steps the waves exchange only LDS, so the barrier does not wait for the stores of
-// h; the full barrier at the end of a quadrant makes them visible to the mirror reads of
-// the next.
+// W blocks of cw <= kRowWidth, and at step s wave w processes row s - w of its block, column
+// by column (rows outside the grid, before and after a wave's turn, are placeholders: the
+// same instructions, nothing stored).  The two values left of the block come from wave w - 1
+// through LDS (written at step s - 1, double-buffered by step parity), the two rows above
+// are the lane's registers, and only references that leave the grid are read from h: those
+// of rows 0 and 1 (axis 1) into LDS when the quadrant starts, those of columns 0 and 1
+// (axis 2) a row ahead.  A block row's uniform data (grid-ordered stencil records and 64-bit
+// row offsets) is loaded one word per lane three rows ahead into a ring of three LDS slots
+// per wave and read back by broadcast (coefficients) or into scalar registers (offsets,
+// reference words); the right sides are loaded a row ahead.  Registers that receive loads
+// alternate between two sets (the step loop is unrolled by two), so that no register copy
+// waits for a load.  Solid and missing cells get a finite placeholder update (a = 1) that is
+// not stored.  Between steps the waves exchange only LDS, so the barrier does not wait for
+// the stores of h; the full barrier at the end of a quadrant makes them visible to the
+// mirror reads of the next.
 constexpr int kRowWaves = 16;
-constexpr int kRowWidth = 4;      // columns per wave and row
+constexpr int kRowSpinMax = 1 << 22; // bound on a wave's wait for its neighbour (never reached)
 
-__device__ inline void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
+// Waits until *flag >= target (a counter another wave of the workgroup advances), then
+// orders the LDS reads that follow after the writes published before the counter.
+__device__ inline void lds_wait_at_least(const int* flag, int target) {
+  for (int it = 0; it < kRowSpinMax; ++it) {
+    if (__builtin_amdgcn_readfirstlane(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) >=
+        target)
+      break;
+    __builtin_amdgcn_s_sleep(1);
+  }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__device__ inline double rec_f64(const uint32_t* __restrict__ r, int k) {
-  return __builtin_bit_cast(double, (static_cast<uint64_t>(r[2 * k + 1]) << 32) | r[2 * k]);
+// Publishes value in *flag after the wave's earlier LDS accesses.
+__device__ inline void lds_publish(int* flag, int value) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <int CW>
 __global__ __launch_bounds__(64 * kRowWaves) void sweep2d_rows_kernel(
-    Sweep2DArgs a, const uint32_t* __restrict__ grec, const int64_t* __restrict__ growb,
+    Sweep2DArgs a, const uint32_t* __restrict__ grec, const uint32_t* __restrict__ growb,
     const double* __restrict__ rhs, double* __restrict__ h) {
-  constexpr int CW = kRowWidth;
-  constexpr int kRowWords = 18 * CW;                // 16 record words and a 64-bit row offset per cell
+  // right sides are loaded two rows ahead for 4 columns per wave, one row ahead for 8 (registers)
+  constexpr int kAhead = CW == 4 ? 2 : 1;
+  constexpr int kRowWords = 17 * CW;                // 16 record words and a row offset per cell
   constexpr int kRegs = (kRowWords + 63) / 64;
-  __shared__ double carry[2][kRowWaves][2][64];
-  __shared__ __align__(16) uint32_t stage[kRowWaves][3][kRegs * 64];
-  __shared__ double edge1[kRowWaves][3][CW][64];    // out-of-grid axis-1 references of rows 0, 1
-  const int cs = blockIdx.y;
+  __shared__ double carry[2][kRowWaves][2][64];     // [row parity][wave][column c - 1, c - 2][lane]
+  __shared__ __align__(16) uint32_t stage[kRowWaves][4][kRegs * 64];
+  __shared__ double row1[kRowWaves][CW][64];        // second out-of-grid axis-1 reference of row 1
+  __shared__ int published[kRowWaves];              // rows whose carry the wave has written
+  __shared__ int consumed[kRowWaves];               // rows of its left neighbour's carry it has read
+  const int n = a.n, hn = n / 2, n3 = a.n3, d3 = a.d3;
+  const int nsp = a.nsp;
+  const int quads = hn * hn * d3, groups = (quads + 63) / 64;
+  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2); numbering
+  // them so that consecutive velocity groups of a case share an XCD lets the cache lines they
+  // share (their 512-byte segments of a row are not line-aligned) be fetched once.
+  const int nwg = gridDim.x, lin = blockIdx.x, per = nwg / 8, rem = nwg % 8, xcd = lin % 8, slot = lin / 8;
+  const int logical = xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  const int grp = logical % groups, cs = (logical / groups) % a.n_cases, sp = logical / (groups * a.n_cases);
   if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int W = blockDim.x >> 6, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int n = a.n, hn = n / 2, n3 = a.n3, d3 = a.d3;
-  const int nsp = a.nsp, sp = blockIdx.z;
   const double* __restrict__ nu = a.nu + static_cast<int64_t>(sp) * n3;
-  const int64_t row_elems = static_cast<int64_t>(nsp) * n3;
-  // rows of species sp: cell c's row at byte offset growb (c * row_elems doubles)
-  const char* __restrict__ rhs_s = reinterpret_cast<const char*>(rhs + static_cast<int64_t>(sp) * n3);
-  char* __restrict__ h_s = reinterpret_cast<char*>(h + static_cast<int64_t>(sp) * n3);
-  const int quads = hn * hn * d3;
-  const int tq = blockIdx.x * 64 + lane;
-  const bool vvalid = tq < quads;
-  const int t = vvalid ? tq : 0;
+  const uint32_t row_bytes = static_cast<uint32_t>(nsp * n3 * 8);
+  // Rows of species sp through buffer descriptors: cell c's row at byte offset growb (a 32-bit
+  // scalar offset; the launcher checks that h fits), the lane's velocity in the vector offset.
+  // A cell that is not there (solid, outside the grid) uses the empty descriptor: its loads
+  // return 0 and its stores are dropped.
+  const __amdgpu_buffer_rsrc_t rs_rhs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(rhs + static_cast<int64_t>(sp) * n3), 0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_h =
+      __builtin_amdgcn_make_buffer_rsrc(h + static_cast<int64_t>(sp) * n3, 0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_none = __builtin_amdgcn_make_buffer_rsrc(h, 0, 0, 0x00020000);
+  // lanes past the last quadruple repeat the last one (same wave, same values, same stores)
+  const int tq = grp * 64 + lane;
+  const int t = tq < quads ? tq : quads - 1;
   const int jq1 = t / (hn * d3), jq2 = (t / d3) % hn, j3 = t % d3;
   const int n1 = a.n1[cs], n2 = a.n2[cs];
   const int64_t g0 = a.grid_off[cs];
   const double del = a.delta_case[cs];
   const int cw = (n2 + W - 1) / W;                   // <= CW (checked by the launcher)
   const int jb0 = min(w * cw, n2), nb = min(cw, n2 - jb0);
-  // every wave runs every step (rows outside [0, n1) are placeholders: no cells, nothing
-  // stored), an even number of them for the two-step loop body
-  const int steps = (n1 + W) & ~1;
+  const int rows = (n1 + 1) & ~1;                    // an even count: row n1 of odd n1 is a placeholder
+  auto ld = [&](const __amdgpu_buffer_rsrc_t& rs, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+  };
   for (int q = 0; q < 4; ++q) {
     const int s1 = (q & 1) ? -1 : 1, s2 = (q & 2) ? -1 : 1;
     const int j1 = s1 > 0 ? hn + jq1 : hn - 1 - jq1;
@@ -1535,57 +1563,55 @@ __global__ __launch_bounds__(64 * kRowWaves) void sweep2d_rows_kernel(
     const int v = (j1 * n + j2) * d3 + j3;
     const int vm1 = ((n - 1 - j1) * n + j2) * d3 + j3;
     const int vm2 = (j1 * n + (n - 1 - j2)) * d3 + j3;
-    const uint32_t vb = v * 8u;
+    const uint32_t vb = v * 8u, vm1b = vm1 * 8u, vm2b = vm2 * 8u;
     const double av1 = fabs(a.v1d[j1]), av2 = fabs(a.v1d[j2]);
     const double dnu = del * nu[v];
     const int sg1 = s1 > 0 ? 0 : 1, sg2 = s2 > 0 ? 0 : 1;
+    if (lane == 0) {
+      published[w] = 0;
+      consumed[w] = 0;
+    }
+    __syncthreads();
     // grid index of the block's column k in oriented row r: rbase(r) + dj k
     const int dj = s2, jstart = s2 > 0 ? jb0 : n2 - 1 - jb0;
     auto rbase = [&](int r) { return g0 + static_cast<int64_t>(s1 > 0 ? r : n1 - 1 - r) * n2 + jstart; };
-    // Staging slot of row r (r >= -kRowWaves): 16 record words per cell (axis 1 with the sign
-    // of v1, then axis 2 with the sign of v2), then the cells' 64-bit row offsets (-1: none),
-    // one word per lane.  Where there is no cell (outside the block or the grid) the words are
-    // read from the tables' extra solid entry (a = 1, no references, offset -1): every lane
-    // loads, and uses the word as loaded, so that all steps issue the same memory
-    // instructions, the waits for them stay counted, and nothing waits before the barrier.
-    auto slot = [&](int r) { return (r + 3 * kRowWaves) % 3; };
+    // Staging slot of row r: 16 record words per cell (axis 1 with the sign of v1, then axis 2
+    // with the sign of v2), then the cells' row offsets (0xffffffff: none), one word per lane.
+    // Where there is no cell (outside the block or the grid) the words are read from the
+    // tables' extra solid entry (a = 1, no references, no row): every lane loads, and uses
+    // the word as loaded, so that all rows issue the same memory instructions and the waits
+    // for them stay counted.
     auto load_row = [&](int r, uint32_t (&sv)[kRegs]) {
-      const bool rv = r >= 0 && r < n1;
+      const bool rv = r < n1;
       const int64_t gb = rbase(rv ? r : 0);
 #pragma unroll
       for (int u = 0; u < kRegs; ++u) {
         const int x = 64 * u + lane;
         const bool isrec = x < 16 * CW;
-        const int k = isrec ? x >> 4 : (x - 16 * CW) >> 1, d = x & 15, axis = d >> 3;
+        const int k = isrec ? x >> 4 : x - 16 * CW, d = x & 15, axis = d >> 3;
         const int64_t gk = rv && k < nb ? gb + dj * k : a.grid_none;
-        sv[u] = isrec ? grec[(gk * 4 + axis * 2 + (axis ? sg2 : sg1)) * 8 + (d & 7)]
-                      : reinterpret_cast<const uint32_t*>(growb + gk)[x & 1];
+        sv[u] = isrec ? grec[(gk * 4 + axis * 2 + (axis ? sg2 : sg1)) * 8 + (d & 7)] : growb[gk];
       }
     };
     auto put_row = [&](int r, const uint32_t (&sv)[kRegs]) {
 #pragma unroll
-      for (int u = 0; u < kRegs; ++u) stage[w][slot(r)][64 * u + lane] = sv[u];
+      for (int u = 0; u < kRegs; ++u) stage[w][r & 3][64 * u + lane] = sv[u];
     };
     auto coef = [&](int r, int k, int wd) {
-      return *reinterpret_cast<const double*>(&stage[w][slot(r)][16 * k + wd]);
+      return *reinterpret_cast<const double*>(&stage[w][r & 3][16 * k + wd]);
     };
-    auto word = [&](int r, int i) { return __builtin_amdgcn_readfirstlane(stage[w][slot(r)][i]); };
-    auto row_off = [&](int r, int k) {
-      return static_cast<int64_t>((static_cast<uint64_t>(word(r, 16 * CW + 2 * k + 1)) << 32) | word(r, 16 * CW + 2 * k));
-    };
-    // Loaded values are used as loaded: where there is no cell or no reference (kind 0), a
-    // finite value of cell 0's row stands in and meets a zero coefficient or a discarded
-    // update, so that no select waits for the load before the barrier.
+    auto word = [&](int r, int i) { return __builtin_amdgcn_readfirstlane(stage[w][r & 3][i]); };
+    auto row_of = [&](int r, int k) { return word(r, 16 * CW + k); };
     auto load_rhs = [&](int r, double (&rr)[CW]) {
 #pragma unroll
       for (int k = 0; k < CW; ++k) {
-        const int64_t o = row_off(r, k);
-        rr[k] = *reinterpret_cast<const double*>(rhs_s + (o >= 0 ? o : 0) + vb);
+        const uint32_t o = row_of(r, k);
+        rr[k] = ld(o != 0xffffffffu ? rs_rhs : rs_none, vb, o);
       }
     };
-    auto ref_at = [&](uint32_t x, int vmir) {
-      const int64_t c = x & 3u ? static_cast<int64_t>(x >> 2) : 0;
-      return reinterpret_cast<const double*>(h_s)[c * row_elems + ((x & 3u) == 2 ? vmir : v)];
+    // value of a reference word (ref << 2 | kind) at the lane's velocity (mirrored for kind 2)
+    auto ref_at = [&](uint32_t x, uint32_t vmir) {
+      return ld(x & 3u ? rs_h : rs_none, (x & 3u) == 2 ? vmir : vb, (x >> 2) * row_bytes);
     };
     // out-of-grid axis-2 references: column c, reference st (one and two cells upwind), of the
     // block's first two columns if it holds them
@@ -1594,77 +1620,89 @@ __global__ __launch_bounds__(64 * kRowWaves) void sweep2d_rows_kernel(
       for (int e = 0; e < 3; ++e) {
         const int c = e == 2 ? 1 : 0, st = e == 0 ? 0 : 1;
         const bool mine = c >= jb0 && c < jb0 + nb;
-        ge[e] = ref_at(mine ? word(r, 16 * (c - jb0) + 14 + st) : 0u, vm2);
+        ge[e] = ref_at(mine ? word(r, 16 * (c - jb0) + 14 + st) : 0u, vm2b);
       }
     };
-    // out-of-grid axis-1 references: rows 0 (both) and 1 (the second), read when row 0 comes
+    // out-of-grid axis-1 references take the places of rows r - 1, r - 2: both of row 0 in
+    // pr1, pr2, the second one of row 1 in LDS until row 1
+    double pr1[CW], pr2[CW];              // rows r - 1, r - 2 of the block
 #pragma unroll
     for (int k = 0; k < CW; ++k) {
       const bool have = k < nb;
       const uint32_t* p0 = grec + ((have ? rbase(0) + dj * k : a.grid_none) * 4 + sg1) * 8;
       const uint32_t* p1 = grec + ((have ? rbase(1) + dj * k : a.grid_none) * 4 + sg1) * 8;
-      edge1[w][0][k][lane] = ref_at(p0[6], vm1);
-      edge1[w][1][k][lane] = ref_at(p0[7], vm1);
-      edge1[w][2][k][lane] = ref_at(p1[7], vm1);
+      pr1[k] = ref_at(p0[6], vm1b);
+      pr2[k] = ref_at(p0[7], vm1b);
+      row1[w][k][lane] = ref_at(p1[7], vm1b);
     }
-    double pr1[CW], pr2[CW];              // rows r - 1, r - 2 of the block
-    uint32_t sA[kRegs], sB[kRegs];        // staging words of row r + 2 (A / B alternate)
-    double rA[CW], rB[CW], eA[3], eB[3];  // right sides and edge references of a row
-    const int r0 = -w;                    // the wave's row at step 0
-    load_row(r0, sA);
-    load_row(r0 + 1, sB);
-    put_row(r0, sA);
-    put_row(r0 + 1, sB);
-    load_row(r0 + 2, sA);
-    load_rhs(r0, rA);
-    load_edge(r0, eA);
-    // step s: row r = s - w with (rc, ec) of row r and the staging words sc of row r + 2 loaded
-    // by the previous step; loads sn of row r + 3 and (rn, en) of row r + 1.  Calls alternate
-    // the A / B sets.
-    auto step = [&](int s, double (&rc)[CW], double (&ec)[3], uint32_t (&sc)[kRegs], double (&rn)[CW],
-                    double (&en)[3], uint32_t (&sn)[kRegs]) {
-      const int r = s - w;
-      put_row(r + 2, sc);
-      load_row(r + 3, sn);
-      load_rhs(r + 1, rn);
-      load_edge(r + 1, en);
-      if (r == 0) {
+    uint32_t sA[kRegs], sB[kRegs];        // staging words of row r + 3 (A / B alternate)
+    double rA[CW], rB[CW], eA[3], eB[3];  // right sides and edge references of even / odd rows
+    load_row(0, sA);
+    load_row(1, sB);
+    put_row(0, sA);
+    put_row(1, sB);
+    load_row(2, sA);
+    put_row(2, sA);
+    load_row(3, sB);
+    load_rhs(0, rA);
+    load_edge(0, eA);
+    if (kAhead == 2) {
+      load_rhs(1, rB);
+      load_edge(1, eB);
+    }
+    // row r with (rc, ec) of row r, loaded kAhead rows earlier, and the staging words ss of row
+    // r + 3 loaded by the previous row; stages them, loads row r + 4's words into sn and, once
+    // this row's are consumed, row r + kAhead's right sides and edge references into (rn, en)
+    // (the same registers two rows ahead; the other set one row ahead).  Calls alternate the
+    // A / B sets.
+    auto row = [&](int r, double (&rc)[CW], double (&ec)[3], double (&rn)[CW], double (&en)[3],
+                   uint32_t (&ss)[kRegs], uint32_t (&sn)[kRegs]) {
+      put_row(r + 3, ss);
+      load_row(r + 4, sn);
+      if (__builtin_expect(r == 1, 0)) {
 #pragma unroll
-        for (int k = 0; k < CW; ++k) {
-          pr1[k] = edge1[w][0][k][lane];
-          pr2[k] = edge1[w][1][k][lane];
-        }
-      } else if (r == 1) {
-#pragma unroll
-        for (int k = 0; k < CW; ++k) pr2[k] = edge1[w][2][k][lane];
+        for (int k = 0; k < CW; ++k) pr2[k] = row1[w][k][lane];
       }
+      double acc0[CW];
+#pragma unroll
+      for (int k = 0; k < CW; ++k) acc0[k] = rc[k] - av1 * coef(r, k, 2) * pr1[k];
+      const double e0 = ec[0], e1 = ec[1], e2 = ec[2];
+      load_rhs(r + kAhead, rn);
+      load_edge(r + kAhead, en);
       double p1 = 0.0, p2 = 0.0;              // columns c - 1, c - 2 of this row
       if (w > 0) {
-        p1 = carry[(s - 1) & 1][w - 1][0][lane];
-        p2 = carry[(s - 1) & 1][w - 1][1][lane];
+        lds_wait_at_least(&published[w - 1], r + 1);
+        p1 = carry[r & 1][w - 1][0][lane];
+        p2 = carry[r & 1][w - 1][1][lane];
+        lds_publish(&consumed[w], r + 1);
       }
-      if (jb0 == 0) {
-        p1 = ec[0];
-        p2 = ec[1];
+      if (__builtin_expect(jb0 == 0, 0)) {
+        p1 = e0;
+        p2 = e1;
       }
       const double in1 = p1, in2 = p2;
+      // column 1's second reference leaves the grid: it replaces the shifted value at k = 1
+      // (block from column 0) or k = 0 (block from column 1)
+      const double p2k1 = jb0 == 0 ? e2 : in1;
+      if (__builtin_expect(jb0 == 1, 0)) p2 = e2;
       double hv[CW];
 #pragma unroll
       for (int k = 0; k < CW; ++k) {
-        if (jb0 + k == 1) p2 = ec[2];
-        double acc = rc[k] - av1 * coef(r, k, 2) * pr1[k];
+        if (k == 1) p2 = p2k1;
+        double acc = acc0[k];
         acc -= av2 * coef(r, k, 10) * p1;
         acc -= av1 * coef(r, k, 4) * pr2[k];
         acc -= av2 * coef(r, k, 12) * p2;
         hv[k] = acc / (dnu + av1 * coef(r, k, 0) + av2 * coef(r, k, 8));
-        const int64_t o = row_off(r, k);
-        if (vvalid && o >= 0) *reinterpret_cast<double*>(h_s + o + vb) = hv[k];   // per-lane predicate
+        const uint32_t o = row_of(r, k);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, hv[k]), o != 0xffffffffu ? rs_h : rs_none,
+                                              vb, o, 0);
         p2 = p1;
         p1 = hv[k];
         pr2[k] = pr1[k];
         pr1[k] = hv[k];
       }
-      if (nb < CW) {                          // the carry is the block's last two columns
+      if (__builtin_expect(nb < CW, 0)) {     // the carry is the block's last two columns
         p1 = in1;
         p2 = in2;
 #pragma unroll
@@ -1674,13 +1712,23 @@ __global__ __launch_bounds__(64 * kRowWaves) void sweep2d_rows_kernel(
             p1 = hv[k];
           }
       }
-      carry[s & 1][w][0][lane] = p1;
-      carry[s & 1][w][1][lane] = p2;
-      lds_barrier();
+      if (w < W - 1) {
+        lds_wait_at_least(&consumed[w + 1], r - 1);  // its read of row r - 2 (same parity) is done
+        carry[r & 1][w][0][lane] = p1;
+        carry[r & 1][w][1][lane] = p2;
+        lds_publish(&published[w], r + 1);
+      }
     };
-    for (int s = 0; s < steps; s += 2) {
-      step(s, rA, eA, sA, rB, eB, sB);
-      step(s + 1, rB, eB, sB, rA, eA, sA);
+    if (kAhead == 2) {
+      for (int r = 0; r < rows; r += 2) {
+        row(r, rA, eA, rA, eA, sB, sA);
+        row(r + 1, rB, eB, rB, eB, sA, sB);
+      }
+    } else {
+      for (int r = 0; r < rows; r += 2) {
+        row(r, rA, eA, rB, eB, sB, sA);
+        row(r + 1, rB, eB, rA, eA, sA, sB);
+      }
     }
     __syncthreads();
   }
@@ -1870,7 +1918,9 @@ __device__ void d2_outputs(const Diff2DArgs& a, int cs, int ng, const double* us
   }
   block_sum_big<4>(fr, sh);
   if (threadIdx.x == 0) {
-    if (a.have_x) a.have_x[cs] = a.sis ? 1 : 0;
+    // the CG iterate in the workspace is a valid warm start only after a CG solve (the
+    // inverse path leaves the workspace's iterate untouched)
+    if (a.have_x) a.have_x[cs] = (a.sis && !usol) ? 1 : 0;
     if (a.cg_iters) a.cg_iters[cs] = it;
     if (a.state) {
       double* st = a.state + cs * (2 * nsp + 2);   // M[nsp], Q[nsp], residual, iterations
@@ -2523,8 +2573,8 @@ hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s) {
 }
 
 
-int sweep2d_form(int max_diag, int max_n2) {
-  if (max_n2 <= kRowWaves * kRowWidth) return 1;
+int sweep2d_form(int max_diag, int max_n2, int64_t row_bytes_total) {
+  if (max_n2 <= kRowWaves * 8 && row_bytes_total < (int64_t(1) << 31)) return 1;
   const int slots = kSweepThreads / kSweepV;
   return (max_diag + slots - 1) / slots <= kSweepMaxP ? 2 : 3;
 }
@@ -2532,11 +2582,15 @@ int sweep2d_form(int max_diag, int max_n2) {
 hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   const int hn = a.n / 2;
   const int count = hn * hn * a.d3;
-  const int form = sweep2d_form(a.max_diag, a.max_n2);
+  const int form = sweep2d_form(a.max_diag, a.max_n2, a.row_bytes_total);
   if (form == 1) {
-    const int W = (a.max_n2 + kRowWidth - 1) / kRowWidth;
-    dim3 grid((count + 63) / 64, a.n_cases, a.nsp);
-    hipLaunchKernelGGL(sweep2d_rows_kernel, grid, dim3(64 * W), 0, s, a, a.grec, a.growb, a.rhs, a.h);
+    const int cwmax = a.max_n2 <= kRowWaves * 4 ? 4 : 8;
+    const int W = (a.max_n2 + cwmax - 1) / cwmax;
+    dim3 grid(((count + 63) / 64) * a.n_cases * a.nsp);
+    if (cwmax == 4)
+      hipLaunchKernelGGL(sweep2d_rows_kernel<4>, grid, dim3(64 * W), 0, s, a, a.grec, a.growb, a.rhs, a.h);
+    else
+      hipLaunchKernelGGL(sweep2d_rows_kernel<8>, grid, dim3(64 * W), 0, s, a, a.grec, a.growb, a.rhs, a.h);
     return hipGetLastError();
   }
   dim3 grid((count + kSweepV - 1) / kSweepV, a.n_cases, a.nsp);

@@ -426,7 +426,8 @@ class Geometry2D:
 
     def sweep_form(self):
         """Kernel form of the 2-D sweep: 1 row-blocked (every case at most 128
-        cells along axis 2), 2 pipelined anti-diagonal, 3 plain anti-diagonal."""
+        cells along axis 2, distributions under 2 GiB), 2 pipelined anti-diagonal,
+        3 plain anti-diagonal."""
         return int(lib().sis_geometry_sweep_form(self.handle))
 
     def diffusion_solver(self, mode, stream=None):

@@ -267,15 +267,16 @@ def test_sweep2d_at_benchmark_size():
 
 
 def _large_sweep_case(name):
-    """Cross sections that select each form of the 2-D sweep.  Row-blocked (at
-    most 64 cells along axis 2): a 64^2 periodic disc mask (Sec. 3.2; solids,
-    periodic wraps at rows and columns 0 and 1), the level-3 Sierpinski quarter
-    on 54^2 cells (Sec. 3.1; solids, mirror ghosts) and a ragged batch of quarter
-    ducts of 64 x 64, 12 x 10 and 9 x 3 cells (blocks of one column and empty
-    blocks).  Pipelined anti-diagonal: the porous benchmark's 128^2 disc mask
-    (two cells per slot) and the level-3 Sierpinski quarter on 135^2 cells (three
-    per slot).  Plain anti-diagonal: a 200^2 quarter duct (Sec. 2.4;
-    anti-diagonals over 192 cells)."""
+    """Cross sections that select each form of the 2-D sweep.  Row-blocked with
+    4 columns per wave (at most 64 cells along axis 2): a 64^2 periodic disc mask
+    (Sec. 3.2; solids, periodic wraps at rows and columns 0 and 1), the level-3
+    Sierpinski quarter on 54^2 cells (Sec. 3.1; solids, mirror ghosts) and a
+    ragged batch of quarter ducts of 64 x 64, 12 x 10 and 9 x 3 cells (blocks of
+    one column and empty blocks); with 8 columns per wave: the porous benchmark's
+    128^2 disc mask.  Pipelined anti-diagonal (more than 128 cells along axis 2):
+    the level-3 Sierpinski quarter on 135^2 cells (three cells per slot).  Plain
+    anti-diagonal: a 200^2 quarter duct (Sec. 2.4; anti-diagonals over 192
+    cells)."""
     if name == "porous64":
         mask, _ = inputs.porous_discs(64)
         f = np.linspace(0.0, 1.0, 65)
@@ -288,7 +289,7 @@ def _large_sweep_case(name):
                         (inputs.duct_faces(9, 0.5), inputs.duct_faces(3, 0.25), None)], 1
     if name == "porous128":
         f, _, mask = inputs.porous_cases(inputs.POROUS_HS)[0]
-        return "periodic", [(f, f, mask)], 2
+        return "periodic", [(f, f, mask)], 1
     if name == "carpet135":
         return "duct", [inputs.sierpinski_quarter(3, 135)], 2
     f = inputs.duct_faces(200, 0.5)
