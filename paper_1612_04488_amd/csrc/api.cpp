@@ -213,6 +213,7 @@ struct sis_geom {
   bool tube = false;             // SIS_GEOM_TUBE: radial nodes, polar velocity grid
   int max_diag = 0;              // 2-D: largest min(n1, n2) over the cases
   int max_n2 = 0;                // 2-D: largest n2 over the cases
+  bool no_mirror = false;        // 2-D: no stencil reference is a mirror ghost
   double *d_r = nullptr, *d_cin = nullptr, *d_cout = nullptr, *d_tw = nullptr;
   sis::Tables2D t2;
   int32_t *d_n1 = nullptr, *d_n2 = nullptr, *d_gcell = nullptr, *d_sref = nullptr, *d_nb = nullptr;
@@ -674,6 +675,7 @@ sis_status run_sweep(sis_plan* p, sis_geom* g, const double* rhs, double* h, dou
     a.growb = g->d_growb;
     a.grid_none = g->t2.n_grid;
     a.row_bytes_total = g->n_cells * static_cast<int64_t>(p->nsp) * p->nv * static_cast<int64_t>(sizeof(double));
+    a.quad_split = g->no_mirror ? 1 : 0;
     a.delta_case = g->delta_case;
     a.v1d = p->v1d;
     a.nu = p->nu;
@@ -1245,6 +1247,8 @@ sis_status create_geometry_2d(sis_plan* p, const sis_geometry_desc* d, hipStream
     }
   }
   G2_TRY(upload(&g->d_srec, rec, stream));
+  g->no_mirror = true;
+  for (int8_t kind : t.st_kind) g->no_mirror = g->no_mirror && kind != 2;
   // (solid cells: a = 1, so that the placeholder update the sweep computes there stays finite;
   // one more solid entry at index n_grid stands for positions outside the grid)
   std::vector<uint32_t> grec(static_cast<size_t>(t.n_grid + 1) * 4 * 8, 0u);

@@ -161,6 +161,7 @@ struct Sweep2DArgs {
   int64_t grid_none;         // index of the extra solid entry of grec and growb (positions
                              // outside the grid)
   int64_t row_bytes_total;   // bytes of h (all cells and species)
+  int quad_split;            // no mirror ghosts: the four quadrants are independent
   const double* delta_case;
   const double* v1d;
   const double* nu;

@@ -1457,34 +1457,37 @@ __global__ __launch_bounds__(kSweepThreads) void sweep2d_pipelined_kernel(Sweep2
   }
 }
 
-// Row-blocked form of the same sweep, for cross sections of up to kRowWaves * kRowWidth = 64
-// cells along axis 2.  A lane owns one velocity quadruple, and every value it reads during
-// the sweep belongs to that quadruple: in-quadrant upwind cells (this sweep), mirror ghosts
-// (the quadrant with the mirrored axis's sign flipped: this sweep if it came earlier, else
-// the previous iterate) and periodic wraps (cells later in the sweep order: the previous
-// iterate).  Any order in which each cell follows its upwind cells along both axes
-// therefore reads the values the anti-diagonal order reads; the update of each cell is the
-// same expression in the same order (a reference of kind 0 enters with coefficient 0 in
-// place of being skipped), so the results agree to the sign of zeros.
+// Row-blocked form of the same sweep, for cross sections of up to 128 cells along axis 2
+// whose distributions fit 2 GiB (32-bit row offsets).  A lane owns one velocity quadruple,
+// and every value it reads during the sweep belongs to that quadruple: in-quadrant upwind
+// cells (this sweep), mirror ghosts (the quadrant with the mirrored axis's sign flipped: this
+// sweep if it came earlier, else the previous iterate) and periodic wraps (cells later in the
+// sweep order: the previous iterate).  Any order in which each cell follows its upwind cells
+// along both axes therefore reads the values the anti-diagonal order reads; the update of
+// each cell is the same expression in the same order (a reference of kind 0 enters with
+// coefficient 0 in place of being skipped), so the results agree to the sign of zeros.
 //
-// A workgroup holds W waves of 64 quadruples each, of one case and species, and sweeps the
-// four quadrants in the same order.  Within a quadrant the cells are taken in the sweep's
-// orientation (row r, column c counted from the upwind corner); the columns are split into
-// W blocks of cw <= kRowWidth, and at step s wave w processes row s - w of its block, column
-// by column (rows outside the grid, before and after a wave's turn, are placeholders: the
-// same instructions, nothing stored).  The two values left of the block come from wave w - 1
-// through LDS (written at step s - 1, double-buffered by step parity), the two rows above
-// are the lane's registers, and only references that leave the grid are read from h: those
-// of rows 0 and 1 (axis 1) into LDS when the quadrant starts, those of columns 0 and 1
-// (axis 2) a row ahead.  A block row's uniform data (grid-ordered stencil records and 64-bit
-// row offsets) is loaded one word per lane three rows ahead into a ring of three LDS slots
-// per wave and read back by broadcast (coefficients) or into scalar registers (offsets,
-// reference words); the right sides are loaded a row ahead.  Registers that receive loads
-// alternate between two sets (the step loop is unrolled by two), so that no register copy
-// waits for a load.  Solid and missing cells get a finite placeholder update (a = 1) that is
-// not stored.  Between steps the waves exchange only LDS, so the barrier does not wait for
-// the stores of h; the full barrier at the end of a quadrant makes them visible to the
-// mirror reads of the next.
+// A workgroup holds W <= 16 waves of 64 quadruples each, of one case and species, and sweeps
+// the four quadrants in the same order (one workgroup per quadrant where no reference is a
+// mirror ghost: then the quadrants do not read each other).  Within a quadrant the cells are
+// taken in the sweep's orientation (row r, column c counted from the upwind corner); the
+// columns are split into W blocks of cw <= CW (4 or 8) columns, and each wave runs over all
+// rows of its block, column by column.  The two values left of the block come from wave
+// w - 1 through LDS, double-buffered by row parity and handed on by two counters per wave
+// (rows published, rows of the left neighbour's values read) instead of a workgroup barrier,
+// so the waves run skewed by about a row each.  The two rows above are the lane's registers;
+// only references that leave the grid are read from h: those of rows 0 and 1 (axis 1) when
+// the quadrant starts, those of columns 0 and 1 (axis 2) with the right sides.  A block
+// row's uniform data (grid-ordered stencil records and 32-bit row offsets) is loaded one word
+// per lane four rows ahead into a ring of four LDS slots per wave and read back by broadcast
+// (coefficients) or into scalar registers (offsets, reference words); the right sides are
+// loaded two rows (CW = 4) or one row (CW = 8) ahead into registers that alternate between
+// two sets (the row loop is unrolled by two), so that no register copy waits for a load.
+// Rows of h and of the right sides are addressed through buffer descriptors, the row offset
+// as the scalar offset: a solid or missing cell uses an empty descriptor, whose loads return
+// 0 and whose stores are dropped, and gets a finite placeholder update (a = 1).  Lanes past
+// the last quadruple repeat it (same values, same stores).  The full barrier at the end of a
+// quadrant makes its stores visible to the mirror reads of the next.
 constexpr int kRowWaves = 16;
 constexpr int kRowSpinMax = 1 << 22; // bound on a wave's wait for its neighbour (never reached)
 
@@ -1529,7 +1532,11 @@ __global__ __launch_bounds__(64 * kRowWaves) void sweep2d_rows_kernel(
   // share (their 512-byte segments of a row are not line-aligned) be fetched once.
   const int nwg = gridDim.x, lin = blockIdx.x, per = nwg / 8, rem = nwg % 8, xcd = lin % 8, slot = lin / 8;
   const int logical = xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
-  const int grp = logical % groups, cs = (logical / groups) % a.n_cases, sp = logical / (groups * a.n_cases);
+  const int grp = logical % groups, cs = (logical / groups) % a.n_cases;
+  const int sp = (logical / (groups * a.n_cases)) % nsp;
+  // without mirror ghosts the quadrants do not read each other: one workgroup per quadrant
+  const int qsplit = logical / (groups * a.n_cases * nsp);
+  const int q0 = a.quad_split ? qsplit : 0, q1 = a.quad_split ? qsplit + 1 : 4;
   if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int W = blockDim.x >> 6, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const double* __restrict__ nu = a.nu + static_cast<int64_t>(sp) * n3;
@@ -1556,7 +1563,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void sweep2d_rows_kernel(
   auto ld = [&](const __amdgpu_buffer_rsrc_t& rs, uint32_t vo, uint32_t so) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
   };
-  for (int q = 0; q < 4; ++q) {
+  for (int q = q0; q < q1; ++q) {
     const int s1 = (q & 1) ? -1 : 1, s2 = (q & 2) ? -1 : 1;
     const int j1 = s1 > 0 ? hn + jq1 : hn - 1 - jq1;
     const int j2 = s2 > 0 ? hn + jq2 : hn - 1 - jq2;
@@ -2586,7 +2593,7 @@ hipError_t launch_sweep2d(const Sweep2DArgs& a, hipStream_t s) {
   if (form == 1) {
     const int cwmax = a.max_n2 <= kRowWaves * 4 ? 4 : 8;
     const int W = (a.max_n2 + cwmax - 1) / cwmax;
-    dim3 grid(((count + 63) / 64) * a.n_cases * a.nsp);
+    dim3 grid(((count + 63) / 64) * a.n_cases * a.nsp * (a.quad_split ? 4 : 1));
     if (cwmax == 4)
       hipLaunchKernelGGL(sweep2d_rows_kernel<4>, grid, dim3(64 * W), 0, s, a, a.grec, a.growb, a.rhs, a.h);
     else
