@@ -75,9 +75,34 @@ def sis_map(K, nu, grid, delta, N):
     return C + np.outer(corr, row)
 
 
-def spectral_radius(T, P=None):
-    if P is not None:
-        T = P @ T @ P
+def symmetry_basis(grid):
+    """Orthonormal basis Q (columns) of the range of `symmetry_projector`:
+    one column (e_i + e_m2(i) - e_m3(i) - e_m23(i)) / 2 per node i with
+    v2 > 0, v3 > 0, so that Q Q^T is the projector (even n: no node on the
+    mirror planes)."""
+    n = grid.n
+    if n % 2:
+        raise ValueError("symmetry_basis needs an even number of nodes per axis")
+    idx = np.arange(n ** 3).reshape(n, n, n)
+    h = n // 2
+    i = idx[:, h:, h:].ravel()
+    m2 = idx[:, h - 1::-1, h:].ravel()
+    m3 = idx[:, h:, h - 1::-1].ravel()
+    m23 = idx[:, h - 1::-1, h - 1::-1].ravel()
+    Q = np.zeros((n ** 3, i.size))
+    c = np.arange(i.size)
+    Q[i, c] = 0.5
+    Q[m2, c] = 0.5
+    Q[m3, c] = -0.5
+    Q[m23, c] = -0.5
+    return Q
+
+
+def spectral_radius(T, Q=None):
+    """Largest |eigenvalue| of T, or of T restricted to the span of the
+    orthonormal columns Q (the nonzero spectrum of Q Q^T T Q Q^T)."""
+    if Q is not None:
+        T = Q.T @ T @ Q
     return float(np.max(np.abs(np.linalg.eigvals(T))))
 
 
