@@ -50,28 +50,13 @@ TRAFFIC_KIB = {
     ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16):
         (1546552.0 * 2.0, 206848.0, "profiles/gemm_f64_planar-hs-32v-808cells-parity.md"),
     ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16):
-        (42415887.6 * 2.0, 1327104.0, "profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md"),
-    ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 3, 64):
-        (526484.1 * 2.0, 157824.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases.md"),
-    ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 4, 64):
-        (639093.9 * 2.0, 210432.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases.md"),
-    ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 6, 64):
-        (576400.5 * 2.0, 315648.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases.md"),
-    ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 1, 64):
-        (6582009.6 * 2.0, 1347840.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases.md"),
-    ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 2, 64):
-        (7447376.5 * 2.0, 2695680.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases.md")}
+        (42415887.6 * 2.0, 1327104.0, "profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md")}
 # MFMA pipe utilisation of the same configuration from its counter pass:
 # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), and the shader clock
 # the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
 MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22),
              ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (0.788, 2.09),
-             ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.801, 2.35),
-             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 3, 64): (0.324, 2.40),
-             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 4, 64): (0.336, 2.42),
-             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 128, 6, 64): (0.357, 2.12),
-             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 1, 64): (0.449, 2.35),
-             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 128, 2, 64): (0.496, 1.91)}
+             ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.801, 2.35)}
 HBM_GBS = 8000.0
 # worker processes of the CPU baseline: the host's cores, at most the 16 that a
 # one-GPU share of the box holds
@@ -314,8 +299,9 @@ def contraction_roofline(W, precision, reps):
     executed = flops * (3 if precision == "bf16x3" else 1)
     achieved = executed / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[precision]
-    log(f"contraction: {avg_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s of {peak} peak "
-        f"(tile {tile_rows}x128, k-stage {k_stage}, split-K {splits}, autotuned {tuned})")
+    tile = "256x256" if tile_rows == 256 else f"{tile_rows}x128"
+    log(f"contraction ({precision}): {avg_ms:.3f} ms/launch, {achieved:.1f} TFLOP/s of {peak} peak "
+        f"(tile {tile}, k-stage {k_stage}, split-K {splits}, autotuned {tuned})")
     ck = (W["w"]["name"], W["parity"], precision, tile_rows, splits, k_stage)
     tk, mb = TRAFFIC_KIB.get(ck), MFMA_BUSY.get(ck)
     info = W["info"]
@@ -324,7 +310,7 @@ def contraction_roofline(W, precision, reps):
             "mfma_busy": mb[0] if mb else None, "clock_ghz_counters": mb[1] if mb else None,
             "counters_source": tk[2] if tk else None,
             "kernel": f"gemm_{precision}", "avg_launch_ms": round(avg_ms, 4),
-            "tile": f"{tile_rows}x128", "k_stage": k_stage, "split_k": splits, "autotuned": tuned,
+            "tile": tile, "k_stage": k_stage, "split_k": splits, "autotuned": tuned,
             "work_per_unit": "2 n_dof^2 flops per cell update (the dense operator of L+ applied to one cell)",
             "flops_per_launch": executed, "flops_per_cell_update": 2.0 * n3 * n3}
     if not W["mix"] and not W["tube"]:
@@ -527,6 +513,12 @@ def main():
     value = nc * args.steps / wall
     reps = max(args.steps, 5)
     roofline, h, delta, rhs = contraction_roofline(W, args.precision, reps)
+    lowp = None
+    if args.precision == "fp64" and not W["tube"]:
+        # the 3xBF16 contraction of the mixed-precision solves, on the same batch
+        lowp, lh, ld, lr = contraction_roofline(W, "bf16x3", reps)
+        del lh, ld, lr
+        W["plan"].set_precision(args.precision)
     sweep = sweep_rate(W, rhs, reps)
     del rhs
     fsm = None
@@ -555,7 +547,7 @@ def main():
            "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16": "bf16+f64"}[args.precision],
            "data": "synthetic",
            "config": config_of(W, args.precision),
-           "roofline": roofline, "sweep": sweep,
+           "roofline": roofline, "bf16x3_contraction": lowp, "sweep": sweep,
            "plan_seconds": round(W["t_plan"], 3), "geometry_seconds": round(W["t_geom"], 3),
            "time_to_residual_1e-8": ttr}
     if "fp64" in ttr:
@@ -575,10 +567,15 @@ def main():
         ew, _ = step_rate(E, "fp64", args.steps, args.warmup)
         er, eh, ed, erhs = contraction_roofline(E, "fp64", reps)
         del eh, ed, erhs
+        elp = None
+        if not E["tube"]:
+            elp, eh, ed, erhs = contraction_roofline(E, "bf16x3", reps)
+            del eh, ed, erhs
+            E["plan"].set_precision("fp64")
         et = ttr_runs(E, [("fp64", False), ("bf16x3", False)], args.refresh_every) if not args.no_ttr else {}
         extras[E["w"]["name"]] = {
             "value": en * args.steps / ew, "unit": "cell-updates/s", "ms_per_step": ew * 1e3 / args.steps,
-            "config": config_of(E, "fp64"), "roofline": er,
+            "config": config_of(E, "fp64"), "roofline": er, "bf16x3_contraction": elp,
             "plan_seconds": round(E["t_plan"], 3), "time_to_residual_1e-8": et}
         E["plan"].close()
         E["geom"].close()

@@ -313,8 +313,9 @@ sis_status sis_collide(sis_plan_t plan, int64_t n_cells, const double* h, const 
  * held until the process ends.  It runs the plan's contraction configuration for
  * this n_cells and precision (tuned by an earlier sis_collide, else the default
  * heuristic; it never tunes), with the split-K count lowered until the partials
- * fit; a low-precision operand of more than 64 MiB (n_cells * n_dof * 4 bytes)
- * is rejected with SIS_E_SHAPE before anything is enqueued.  Every call on a GPU
+ * fit; a low-precision operand of more than 64 MiB (n_cells * n_dof * 4 bytes
+ * for FP32; n_cells * Kp * 4 bytes for BF16X3 / BF16, Kp = n_dof rounded up to
+ * 64) is rejected with SIS_E_SHAPE before anything is enqueued.  Every call on a GPU
  * shares that GPU's array: calls that overlap on one GPU (other streams, other
  * threads, other plans) race and must be ordered by the caller.              */
 sis_status sis_collide_noalloc(sis_plan_t plan, int64_t n_cells, const double* h, const double* dU,
@@ -491,17 +492,22 @@ sis_status sis_state_destroy(sis_state_t state);
  * sis_state_create, outside stream capture) times every (tile, split-K)
  * candidate on the device and keeps, among those within 3% of the fastest,
  * the fewest split-K partials, then the taller tile; tile_rows is the
- * cell-tile height (128, 64 or 32; the operator tile is 128), k_stage the
- * k-depth of its LDS stages (FP64 and FP32: 16, or 32 for the FP64
- * single-buffered variants; BF16X3 and BF16: 64; nullable), tuned = 0 if
- * the default heuristic is in use.                                          */
+ * cell-tile height (128, 64 or 32, the operator tile 128; or 256 for the
+ * BF16X3 256 x 256 tile), k_stage the k-depth of its LDS stages (FP64 and
+ * FP32: 16, or 32 for the FP64 single-buffered variants; BF16X3 and BF16:
+ * 64, or 32 for the 256 x 256 tile; nullable), tuned = 0 if the default
+ * heuristic is in use.                                                      */
 sis_status sis_plan_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t precision,
                                        int32_t* tile_rows, int32_t* splits, int32_t* tuned,
                                        int32_t* k_stage);
 /* Fix the configuration for n_cells cells in `precision` instead of tuning it
  * (reproducible runs, tests): tile_rows 128, 64 or 32 with k_stage 16
  * (FP64, FP32) or 64 (BF16X3, BF16), or (FP64 only) 128 or 64 with k_stage
- * 32; splits in 1..8.  Invalid combinations return SIS_E_INVALID.          */
+ * 32, or (BF16X3 only) 256 with k_stage 32 (256 cells x 256 operator rows
+ * per tile; SIS_E_UNSUPPORTED when a bf16 pair array of the cells or of the
+ * operator would reach 4 GiB); splits in 1..8.  Invalid combinations return
+ * SIS_E_INVALID.  At equal splits every BF16X3 tile gives bit-identical
+ * results.                                                                  */
 sis_status sis_plan_set_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t precision,
                                            int32_t tile_rows, int32_t k_stage, int32_t splits);
 

@@ -142,8 +142,7 @@ struct sis_plan {
   double flow_factor = 1.0, visc_ratio = 1.0;
   double* op = nullptr;         // [ndof][ndof] L+ at delta = 1
   float* op32 = nullptr;
-  uint16_t* ophi = nullptr;
-  uint16_t* oplo = nullptr;
+  uint16_t* opp = nullptr;   // the operator in the bf16 pair layout (ndof rows)
   double* v1d = nullptr;        // [n]
   double* feq = nullptr;        // [nsp][n3]
   double* nu = nullptr;         // [nsp][n3]
@@ -187,7 +186,7 @@ struct sis_plan {
     for (auto& e : events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     for (auto& e : fsm_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     dfree(fsm_fac); dfree(fsm_field); dfree(fsm_mult); dfree(fsm_Kc); dfree(fsm_dirs); dfree(fsm_rad);
-    dfree(op); dfree(op32); dfree(ophi); dfree(oplo);
+    dfree(op); dfree(op32); dfree(opp);
     dfree(v1d); dfree(feq); dfree(nu); dfree(Kc); dfree(gram_inv);
     dfree(vnode); dfree(wnode); dfree(d_vr); dfree(d_cth); dfree(d_sth); dfree(vtab); dfree(wtab);
   }
@@ -367,18 +366,14 @@ sis_status prepare_lowp_operand(sis_plan* p, int precision, int64_t n_cells, con
                                 Scratch* ws_x, sis::GemmArgs& g, hipStream_t s) {
   if (precision == SIS_PREC_FP64) return SIS_OK;
   const int64_t cnt = n_cells * static_cast<int64_t>(p->ndof);
-  HIP_TRY(ws_x->ensure(static_cast<size_t>(cnt) * 4));
-  if (precision == SIS_PREC_BF16X3) {
+  if (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) {
+    // pair layout: 2 Kp bf16 per cell, 4 bytes per padded unknown
+    HIP_TRY(ws_x->ensure(static_cast<size_t>(n_cells) * sis::pair_stride(p->ndof) * 4));
     uint16_t* hx = static_cast<uint16_t*>(ws_x->p);
-    HIP_TRY(sis::launch_split_x(h, xref, cnt, hx, hx + cnt, s));
-    g.Xh = hx;
-    g.Xl = hx + cnt;
-  } else if (precision == SIS_PREC_BF16) {
-    uint16_t* hx = static_cast<uint16_t*>(ws_x->p);
-    HIP_TRY(sis::launch_split_x(h, xref, cnt, hx, nullptr, s));
-    g.Xh = hx;
-    g.Xl = nullptr;
+    HIP_TRY(sis::launch_split_pairs(h, xref, n_cells, p->ndof, hx, precision == SIS_PREC_BF16X3, s));
+    g.Xp = hx;
   } else {
+    HIP_TRY(ws_x->ensure(static_cast<size_t>(cnt) * 4));
     float* fx = static_cast<float*>(ws_x->p);
     HIP_TRY(sis::launch_convert_x_f32(h, xref, cnt, fx, s));
     g.X32 = fx;
@@ -402,8 +397,7 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   g.X = h;
   g.op64 = p->op;
   g.op32 = p->op32;
-  g.ophi = p->ophi;
-  g.oplo = p->oplo;
+  g.opp = p->opp;
   g.M = M;
   g.N = p->ndof;
   g.K = p->ndof;
@@ -414,11 +408,14 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const int tiles[5] = {0, 2, 1, 3, 4};
-  const int n_tiles = precision == SIS_PREC_FP64 ? 5 : 3;
+  // candidates: FP64 tiles 0, 2, 1, 3, 4; FP32 and BF16 tiles 0, 2, 1; BF16X3 tiles 0, 2, 1 and the
+  // 256 x 256 tile 5 where its pair arrays take 32-bit offsets
+  std::vector<int> tiles = {0, 2, 1};
+  if (precision == SIS_PREC_FP64) tiles.insert(tiles.end(), {3, 4});
+  if (precision == SIS_PREC_BF16X3 && sis::gemm_wide_fits(M, p->ndof, p->ndof)) tiles.push_back(5);
   const int splits[6] = {1, 2, 3, 4, 6, 8};
   hipError_t err = hipSuccess;
-  for (int ti = 0; ti < n_tiles && err == hipSuccess; ++ti)
+  for (size_t ti = 0; ti < tiles.size() && err == hipSuccess; ++ti)
     for (int si = 0; si < 6 && err == hipSuccess; ++si) {
       const int sp = splits[si];
       if (sp > 1 && sis::gemm_k_per_split(p->ndof, sp) < 256) continue;
@@ -536,8 +533,7 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   if (sis_status st = prepare_lowp_operand(p, precision, n_cells, h, g.Xref, ws_x, g, s)) return st;
   g.op64 = p->op;
   g.op32 = p->op32;
-  g.ophi = p->ophi;
-  g.oplo = p->oplo;
+  g.opp = p->opp;
   g.acc = acc;
   g.M = n_cells;
   g.N = p->ndof;
@@ -2652,10 +2648,9 @@ sis_status sis_plan_set_precision(sis_plan_t p, int32_t precision, hipStream_t s
     if (precision == SIS_PREC_BF16 && p->nsp == 2)
       return fail(SIS_E_UNSUPPORTED, "the one-product BF16 contraction is not offered for two-species plans "
                                      "(the species blocks deviate by ~1e-3 in the heat flux); use BF16X3");
-    if (!p->ophi) {
-      HIP_TRY(dmalloc(&p->ophi, cnt));
-      HIP_TRY(dmalloc(&p->oplo, cnt));
-      HIP_TRY(sis::launch_split_bf16(p->op, p->ophi, p->oplo, cnt, stream));
+    if (!p->opp) {
+      HIP_TRY(dmalloc(&p->opp, static_cast<int64_t>(p->ndof) * 2 * sis::pair_stride(p->ndof)));
+      HIP_TRY(sis::launch_split_pairs(p->op, nullptr, p->ndof, p->ndof, p->opp, 1, stream));
       HIP_TRY(hipStreamSynchronize(stream));
     }
   } else {
@@ -2858,7 +2853,9 @@ sis_status sis_collide_noalloc(sis_plan_t p, int64_t n_cells, const double* h, c
   const int64_t cnt = n_cells * static_cast<int64_t>(p->ndof);
   // low-precision cell operand first in the scratch (4 bytes per unknown), then the split-K
   // partials; the split count is lowered until the partials fit (one split needs none)
-  const size_t xbytes = precision == SIS_PREC_FP64 ? 0 : ((static_cast<size_t>(cnt) * 4 + 255) / 256) * 256;
+  // FP32: 4 bytes per unknown; the bf16 forms: 4 bytes per padded unknown (pair layout)
+  const int64_t xcnt = precision == SIS_PREC_FP32 ? cnt : n_cells * static_cast<int64_t>(sis::pair_stride(p->ndof));
+  const size_t xbytes = precision == SIS_PREC_FP64 ? 0 : ((static_cast<size_t>(xcnt) * 4 + 255) / 256) * 256;
   if (xbytes > kStaticScratchBytes)
     return fail(SIS_E_SHAPE, "sis_collide_noalloc: the low-precision cell operand needs %zu bytes, more than its "
                              "%zu-byte workspace (use fewer cells per call)", xbytes, kStaticScratchBytes);
@@ -2874,9 +2871,8 @@ sis_status sis_collide_noalloc(sis_plan_t p, int64_t n_cells, const double* h, c
   g.X = h;
   if (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) {
     uint16_t* hx = reinterpret_cast<uint16_t*>(ws);
-    HIP_TRY(sis::launch_split_x(h, nullptr, cnt, hx, precision == SIS_PREC_BF16X3 ? hx + cnt : nullptr, stream));
-    g.Xh = hx;
-    g.Xl = precision == SIS_PREC_BF16X3 ? hx + cnt : nullptr;
+    HIP_TRY(sis::launch_split_pairs(h, nullptr, n_cells, p->ndof, hx, precision == SIS_PREC_BF16X3, stream));
+    g.Xp = hx;
   } else if (precision == SIS_PREC_FP32) {
     float* fx = reinterpret_cast<float*>(ws);
     HIP_TRY(sis::launch_convert_x_f32(h, nullptr, cnt, fx, stream));
@@ -2885,8 +2881,7 @@ sis_status sis_collide_noalloc(sis_plan_t p, int64_t n_cells, const double* h, c
   double* acc = splits > 1 ? reinterpret_cast<double*>(ws + xbytes) : rhs_out;
   g.op64 = p->op;
   g.op32 = p->op32;
-  g.ophi = p->ophi;
-  g.oplo = p->oplo;
+  g.opp = p->opp;
   g.acc = acc;
   g.M = n_cells;
   g.N = p->ndof;
@@ -3221,7 +3216,8 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
     int splits = std::max(p->gemm_choice[std::make_pair(nc, static_cast<int>(SIS_PREC_FP64))].second,
                           p->gemm_choice[std::make_pair(nc, p->precision)].second);
     if (splits > 1) ST_TRY(b->ws_acc.ensure(static_cast<size_t>(splits) * nc * n3 * 8));
-    if (p->precision != SIS_PREC_FP64) ST_TRY(b->ws_x.ensure(static_cast<size_t>(nc) * n3 * 4));
+    if (p->precision != SIS_PREC_FP64)
+      ST_TRY(b->ws_x.ensure(static_cast<size_t>(nc) * (p->precision == SIS_PREC_FP32 ? n3 : sis::pair_stride(n3)) * 4));
   }
   hipStream_t s = stream;
   if (o->use_graph) {
@@ -3355,14 +3351,18 @@ sis_status sis_plan_set_contraction_config(sis_plan_t p, int64_t n_cells, int32_
   if (precision < SIS_PREC_FP64 || precision > SIS_PREC_BF16) return fail(SIS_E_INVALID, "unknown precision");
   if (splits < 1 || splits > 8) return fail(SIS_E_INVALID, "splits must be in [1, 8]");
   int tile = -1;
-  if (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) {
+  if (precision == SIS_PREC_BF16X3 && tile_rows == 256 && k_stage == 32) {
+    tile = 5;
+  } else if (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) {
     if (k_stage == 64) tile = tile_rows == 128 ? 0 : tile_rows == 64 ? 2 : tile_rows == 32 ? 1 : -1;
   } else if (k_stage == 16) {
     tile = tile_rows == 128 ? 0 : tile_rows == 64 ? 2 : tile_rows == 32 ? 1 : -1;
   } else if (k_stage == 32 && precision == SIS_PREC_FP64) {
     tile = tile_rows == 128 ? 3 : tile_rows == 64 ? 4 : -1;
   }
-  if (tile < 0) return fail(SIS_E_INVALID, "no contraction tile %d x 128 with k-stage %d for this precision", tile_rows, k_stage);
+  if (tile < 0) return fail(SIS_E_INVALID, "no contraction tile of %d rows with k-stage %d for this precision", tile_rows, k_stage);
+  if (tile == 5 && !sis::gemm_wide_fits(n_cells, p->ndof, p->ndof))
+    return fail(SIS_E_UNSUPPORTED, "the 256 x 256 tile needs both bf16 pair arrays under 4 GiB");
   p->gemm_choice[std::make_pair(n_cells, static_cast<int>(precision))] = std::make_pair(tile, static_cast<int>(splits));
   return SIS_OK;
 }

@@ -20,38 +20,48 @@ hipError_t launch_assemble(int n, int T, const double* X, const double* Y, const
 hipError_t launch_reduce_operator(const double* op, int64_t ld, double* red, int nsp, int n, int parity,
                                   hipStream_t s);
 
-// op2 = op (double) rounded to float / split into bf16 hi + lo.
+// op2 = op (double) rounded to float.
 hipError_t launch_convert_f32(const double* op, float* out, int64_t count, hipStream_t s);
-hipError_t launch_split_bf16(const double* op, uint16_t* hi, uint16_t* lo, int64_t count, hipStream_t s);
+
+// BF16 pair layout of the low-precision contraction operands: rows of K values
+// stored with Kp = pair_stride(K) (K rounded up to 64); row r occupies 2 Kp bf16
+// at P + 2 Kp r, and each block of 32 k-values holds the 32 hi parts, then their
+// 32 lo parts; entries k >= K are zero.  launch_split_pairs writes
+// x = X - Xref (Xref may be null) for rows x K doubles: hi = RNE(x),
+// lo = RNE(x - hi), or lo = 0 when with_lo is 0.  P holds rows * 2 Kp bf16.
+int pair_stride(int K);
+hipError_t launch_split_pairs(const double* X, const double* Xref, int64_t rows, int K, uint16_t* P, int with_lo,
+                              hipStream_t s);
 
 // Contraction acc[z][m][n] = sum_{k in split z} X[m][k] * op[n][k]  (op stored n x k).
-// precision: 0 fp64 (op64), 1 fp32 (op32), 2 bf16x3 (ophi/oplo).  Accumulators
-// are written as double for every precision.
+// precision: 0 fp64 (op64), 1 fp32 (op32), 2 bf16x3, 3 bf16 (hi products only)
+// (Xp, opp in the pair layout).  Accumulators are written as double for every
+// precision.
 struct GemmArgs {
   int precision;
   const double* X;         // FP64 cell operand (precision 0, and the FP32 path's source)
   const double* Xref;      // null, or anchor: the contraction is applied to X - Xref
-  const uint16_t* Xh;      // precision 2: X - Xref split into bf16 hi, lo [M][K] (launch_split_x)
-  const uint16_t* Xl;
+  const uint16_t* Xp;      // precisions 2, 3: X - Xref in the pair layout, M rows (launch_split_pairs)
   const float* X32;        // precision 1: X - Xref rounded to FP32 [M][K] (launch_convert_x_f32)
   const double* op64;
   const float* op32;
-  const uint16_t* ophi;
-  const uint16_t* oplo;
+  const uint16_t* opp;     // precisions 2, 3: the operator in the pair layout, N rows
   double* acc;
   int64_t M;
   int N, K;
   int splits;        // split-K factor (grid.z)
   int tile;          // tile configuration id: 0 (128 x 128), 2 (64 x 128), 1 (32 x 128) with 16-deep
-                     // double-buffered stages; FP64 only: 3 (128 x 128), 4 (64 x 128) with 32-deep
-                     // single-buffered stages
+                     // double-buffered stages (64-deep single-buffered for the bf16 forms); FP64 only:
+                     // 3 (128 x 128), 4 (64 x 128) with 32-deep single-buffered stages; BF16X3 only:
+                     // 5 (256 x 256, 32-deep LDS-DMA stages in two buffers; gemm_wide_fits)
 };
 int gemm_tile_rows(int tile);
 int gemm_tile_depth(int tile, int precision);
+// whether the 256 x 256 BF16X3 tile takes M cells against N operator rows of K
+// (both pair arrays under 4 GiB: its loads use 32-bit offsets)
+bool gemm_wide_fits(int64_t M, int N, int K);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
-// x = X - Xref (Xref may be null) -> bf16 hi + lo, or -> FP32; count = M * K
-hipError_t launch_split_x(const double* X, const double* Xref, int64_t count, uint16_t* hi, uint16_t* lo,
-                          hipStream_t s);
+// x = X - Xref (Xref may be null) -> FP32; count = M * K
 hipError_t launch_convert_x_f32(const double* X, const double* Xref, int64_t count, float* out, hipStream_t s);
 int gemm_k_per_split(int K, int splits);
 

@@ -150,15 +150,25 @@ __device__ inline uint16_t bf16_rne(float f) {
 }
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
-__global__ void split_bf16_kernel(const double* __restrict__ in, uint16_t* __restrict__ hi,
-                                  uint16_t* __restrict__ lo, int64_t count) {
+// BF16 pair layout of the low-precision contraction operands (rows of K values,
+// stored with Kp = K rounded up to 64): row r occupies 2 Kp bf16, and each block of
+// 32 k-values holds its 32 hi parts followed by their 32 lo parts, so that one
+// 128-byte line carries everything a 32-deep stage needs of the row.  Entries
+// k >= K are zero in both halves.  x = X - Xref (Xref null: X); hi = RNE(x),
+// lo = RNE(x - hi), or lo = 0 when with_lo is 0.
+__global__ void split_pairs_kernel(const double* __restrict__ X, const double* __restrict__ Xref, int64_t rows,
+                                   int K, int Kp, uint16_t* __restrict__ P, int with_lo) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < count) {
-    const double x = in[i];
-    const uint16_t h = bf16_rne(static_cast<float>(x));
-    hi[i] = h;
-    lo[i] = bf16_rne(static_cast<float>(x - static_cast<double>(bf16_to_f32(h))));
-  }
+  if (i >= rows * Kp) return;
+  const int64_t r = i / Kp;
+  const int k = static_cast<int>(i - r * Kp);
+  double x = 0.0;
+  if (k < K) x = Xref ? X[r * K + k] - Xref[r * K + k] : X[r * K + k];
+  const uint16_t h = bf16_rne(static_cast<float>(x));
+  const uint16_t l = with_lo ? bf16_rne(static_cast<float>(x - static_cast<double>(bf16_to_f32(h)))) : 0;
+  uint16_t* row = P + r * 2 * Kp + (k >> 5) * 64 + (k & 31);
+  row[0] = h;
+  row[32] = l;
 }
 
 // ------------------------------------------------------------------ FP64 MFMA GEMM
@@ -481,27 +491,26 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
 
 // ------------------------------------------------------------------ 3xBF16 MFMA GEMM
 // x ~ xh + xl, op ~ oh + ol (bf16 pairs); acc += xl*oh + xh*ol + xh*oh on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Both operands arrive as
-// bf16 hi/lo arrays contiguous in k (the cell operand is split once per launch
-// by split_x_kernel instead of once per output tile).  k-stage of 64 staged
-// through one LDS buffer per operand half; the next stage is prefetched into
-// registers while the current one feeds the MFMAs.
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Both operands arrive in the
+// pair layout of split_pairs_kernel (the cell operand is split once per launch
+// instead of once per output tile; Kp is a multiple of 64, so every stage is
+// full).  k-stage of 64 staged through one LDS buffer per operand half; the next
+// stage is prefetched into registers while the current one feeds the MFMAs.
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// NPROD = 1: the hi*hi product alone (lo arrays unused, neither loaded nor staged).
+// NPROD = 1: the hi*hi product alone (lo halves neither loaded nor staged).
 template <int BM, int BN, int WM, int WN, int NPROD = 3>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kernel(const uint16_t* __restrict__ Xh,
-                                                          const uint16_t* __restrict__ Xl,
-                                                          const uint16_t* __restrict__ Oh,
-                                                          const uint16_t* __restrict__ Ol,
-                                                          double* __restrict__ C, int64_t M,
-                                                          int N, int K, int kps) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kernel(
+    const uint16_t* __restrict__ Xp, const uint16_t* __restrict__ Op, double* __restrict__ C, int64_t M, int N, int Kp,
+    int kps) {
   constexpr int BK = 64;                      // two MFMA k-steps per stage
   constexpr int WAVES_N = BN / WN;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int CH = BK / 8;                  // 16-byte chunks per row and stage
-  constexpr int A_LD = (BM * CH + 255) / 256;
-  constexpr int B_LD = (BN * CH + 255) / 256;
+  constexpr int A_LD = BM * CH / 256;
+  constexpr int B_LD = BN * CH / 256;
+  static_assert(BM * CH % 256 == 0 && BN * CH % 256 == 0, "whole staging passes");
   static_assert((BM / WM) * (BN / WN) == 4, "4 waves per workgroup");
   // rows hold the 64 k-values of one m (or n) as eight 16-byte chunks, chunk c
   // of row r stored at slot c ^ ((r / 2) % 8): the 16 rows one MFMA operand read
@@ -526,79 +535,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
   const int64_t m0 = static_cast<int64_t>(tile.y) * BM;
   const int n0 = tile.x * BN;
   const int kbeg = blockIdx.z * kps;
-  const int kend = min(K, kbeg + kps);
+  const int kend = min(Kp, kbeg + kps);
   double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
 
-  uint4 ra[2][A_LD], rb[2][B_LD];
-  auto load16 = [&](const uint16_t* base, int64_t row, int64_t rows, int gk) -> uint4 {
-    if (row < rows && gk + 7 < kend) return *reinterpret_cast<const uint4*>(base + row * K + gk);
-    uint16_t t[8];
-    for (int e = 0; e < 8; ++e) t[e] = (row < rows && gk + e < kend) ? base[row * K + gk + e] : 0;
-    return make_uint4(t[0] | (uint32_t(t[1]) << 16), t[2] | (uint32_t(t[3]) << 16), t[4] | (uint32_t(t[5]) << 16),
-                      t[6] | (uint32_t(t[7]) << 16));
-  };
-  // stages that lie inside the matrices (every stage but ragged edges) load without
-  // per-chunk bounds checks; the test is uniform over the workgroup
-  const bool inside_mn = m0 + BM <= M && n0 + BN <= N;
+  // (native vectors: HIP's uint4 struct copies from global memory kept the staging in scratch)
+  u32x4 ra[2][A_LD], rb[2][B_LD];
+  // hi chunk of (row, k), k a multiple of 8 (its lo chunk sits 32 entries further);
+  // rows past M or N read the last row: their products land in outputs that are
+  // not stored
+  auto pair_off = [&](int64_t row, int k) -> int64_t { return row * 2 * Kp + (k >> 5) * 64 + (k & 31); };
   auto gload = [&](int k0) {
-    if (inside_mn && k0 + BK <= kend) {
-#pragma unroll
-      for (int i = 0; i < A_LD; ++i) {
-        const int q = tid + 256 * i;
-        if (q < BM * CH) {
-          const int64_t off = (m0 + q / CH) * K + k0 + (q % CH) * 8;
-          ra[0][i] = *reinterpret_cast<const uint4*>(Xh + off);
-          if constexpr (NPROD == 3) ra[1][i] = *reinterpret_cast<const uint4*>(Xl + off);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < B_LD; ++i) {
-        const int q = tid + 256 * i;
-        if (q < BN * CH) {
-          const int64_t off = static_cast<int64_t>(n0 + q / CH) * K + k0 + (q % CH) * 8;
-          rb[0][i] = *reinterpret_cast<const uint4*>(Oh + off);
-          if constexpr (NPROD == 3) rb[1][i] = *reinterpret_cast<const uint4*>(Ol + off);
-        }
-      }
-      return;
-    }
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = tid + 256 * i;
-      if (q < BM * CH) {
-        const int r = q / CH, kc = (q % CH) * 8;
-        ra[0][i] = load16(Xh, m0 + r, M, k0 + kc);
-        if constexpr (NPROD == 3) ra[1][i] = load16(Xl, m0 + r, M, k0 + kc);
-      }
+      const int64_t row = m0 + q / CH;
+      const int64_t off = pair_off(row < M ? row : M - 1, k0 + (q % CH) * 8);
+      ra[0][i] = *reinterpret_cast<const u32x4*>(Xp + off);
+      if constexpr (NPROD == 3) ra[1][i] = *reinterpret_cast<const u32x4*>(Xp + off + 32);
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
       const int q = tid + 256 * i;
-      if (q < BN * CH) {
-        const int r = q / CH, kc = (q % CH) * 8;
-        rb[0][i] = load16(Oh, n0 + r, N, k0 + kc);
-        if constexpr (NPROD == 3) rb[1][i] = load16(Ol, n0 + r, N, k0 + kc);
-      }
+      const int64_t row = n0 + q / CH;
+      const int64_t off = pair_off(row < N ? row : N - 1, k0 + (q % CH) * 8);
+      rb[0][i] = *reinterpret_cast<const u32x4*>(Op + off);
+      if constexpr (NPROD == 3) rb[1][i] = *reinterpret_cast<const u32x4*>(Op + off + 32);
     }
   };
   auto sstore = [&]() {
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
-      const int q = tid + 256 * i;
-      if (q < BM * CH) {
-        const int r = q / CH, kc = wslot;
-        *reinterpret_cast<uint4*>(&sA[0][r][kc]) = ra[0][i];
-        if constexpr (NPROD == 3) *reinterpret_cast<uint4*>(&sA[NPROD == 3 ? 1 : 0][r][kc]) = ra[1][i];
-      }
+      const int r = (tid + 256 * i) / CH, kc = wslot;
+      *reinterpret_cast<u32x4*>(&sA[0][r][kc]) = ra[0][i];
+      if constexpr (NPROD == 3) *reinterpret_cast<u32x4*>(&sA[NPROD == 3 ? 1 : 0][r][kc]) = ra[1][i];
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
-      const int q = tid + 256 * i;
-      if (q < BN * CH) {
-        const int r = q / CH, kc = wslot;
-        *reinterpret_cast<uint4*>(&sB[0][r][kc]) = rb[0][i];
-        if constexpr (NPROD == 3) *reinterpret_cast<uint4*>(&sB[NPROD == 3 ? 1 : 0][r][kc]) = rb[1][i];
-      }
+      const int r = (tid + 256 * i) / CH, kc = wslot;
+      *reinterpret_cast<u32x4*>(&sB[0][r][kc]) = rb[0][i];
+      if constexpr (NPROD == 3) *reinterpret_cast<u32x4*>(&sB[NPROD == 3 ? 1 : 0][r][kc]) = rb[1][i];
     }
   };
 
@@ -663,18 +638,151 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
       }
 }
 
-// Cell operand of the low-precision contractions, formed once per launch:
-// x = X - Xref (Xref null: X) split into bf16 hi + lo, or rounded to FP32.
-__global__ void split_x_kernel(const double* __restrict__ X, const double* __restrict__ Xref, int64_t count,
-                               uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const double x = Xref ? X[i] - Xref[i] : X[i];
-  const uint16_t h = bf16_rne(static_cast<float>(x));
-  hi[i] = h;
-  if (lo) lo[i] = bf16_rne(static_cast<float>(x - static_cast<double>(bf16_to_f32(h))));
+// 3xBF16 contraction on 256 x 256 output tiles, for large batches.  Eight waves
+// (4 along the cells x 2 along the operator rows), each owning 64 x 128 outputs
+// (128 FP32 accumulators per lane: two waves per SIMD fit the 256-register
+// budget without spills).  Stages are 32 deep: the 256 cell rows and 256
+// operator rows of a stage, hi and lo halves, are one 64 KB LDS buffer (rows of
+// 128 bytes, chunk c of row r at slot c ^ ((r / 2) % 8), as in the 128-row
+// kernel), and two buffers alternate.  The stages are written by LDS-DMA loads
+// (global_load_lds_dwordx4: each lane's 16 bytes land at its own slot of a
+// 1 KB run of eight rows; the swizzle is applied to the global address each
+// lane fetches), issued one stage ahead, so no registers carry the staging.
+// One barrier per stage: after it, the stage's data is visible to every wave and
+// the other buffer (the previous stage) is free for the next DMA.  The two
+// buffers are distinct LDS objects so that the compiler's LDS-DMA wait tracking
+// lets reads of one proceed while the other is being filled.  Per stage and
+// wave: the four A fragments (hi and lo), then the operator fragments in two
+// halves of four, each followed by its 48 MFMAs, product-major (lo*hi, hi*lo,
+// hi*hi) so consecutive MFMAs update different accumulators.  Per output element
+// the MFMA sequence is that of the 128-row kernel (same k blocks of 32, same
+// product order), so the two agree to the last bit at equal split-K.
+// Preconditions (checked by the launcher): rows * 4 Kp < 2^32 bytes for both
+// operands (32-bit DMA offsets).
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void gbl_void_t;
+
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_wide_kernel(
+    const uint16_t* __restrict__ Xp, const uint16_t* __restrict__ Op, double* __restrict__ C, int64_t M, int N, int Kp,
+    int kps) {
+  __shared__ uint4 buf0[512][8];
+  __shared__ uint4 buf1[512][8];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int2 tile = xcd_tile();
+  const int64_t m0 = static_cast<int64_t>(tile.y) * 256;
+  const int n0 = tile.x * 256;
+  const int kbeg = blockIdx.z * kps;
+  const int kend = min(Kp, kbeg + kps);
+  const int nk = kend > kbeg ? (kend - kbeg) / 32 : 0;
+  double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
+
+  // DMA sources: waves 0-3 fill buffer rows 0-255 (cells), waves 4-7 rows 256-511
+  // (operator rows), eight runs of eight rows each; rows past M or N read the last
+  // row (their products land in outputs that are not stored)
+  const bool isB = wave >= 4;
+  const char* gbase = reinterpret_cast<const char*>(isB ? Op : Xp);
+  const int64_t rows = isB ? N : M;
+  const int64_t row0 = isB ? n0 : m0;
+  uint32_t off[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int r = (wave & 3) * 64 + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((r >> 1) & 7);
+    const int64_t grow = min(row0 + r, rows - 1);
+    off[i] = static_cast<uint32_t>(grow * 4 * Kp + (c >> 2) * 64 + (c & 3) * 16);
+  }
+  auto issue = [&](uint4(*buf)[8], int k0) {
+    const uint32_t kb = static_cast<uint32_t>(k0) * 4u;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      __builtin_amdgcn_global_load_lds((gbl_void_t*)(gbase + static_cast<uint64_t>(off[i] + kb)),
+                                       (lds_void_t*)&buf[wave * 64 + i * 8][0], 16, 0, 0);
+    // keep the loads ahead of the reads and MFMAs that follow
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  const int rr = lane & 15, q = lane >> 4, rsw = rr >> 1;
+  const int s_hi = q ^ rsw, s_lo = (4 + q) ^ rsw;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 128;
+  v4f acc[4][8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  auto rd = [&](uint4(*buf)[8], int row, int slot) { return *reinterpret_cast<const v8bf*>(&buf[row][slot]); };
+  auto compute = [&](uint4(*buf)[8]) {
+    v8bf ah[4], al[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = rd(buf, wm + 16 * i + rr, s_hi);
+      al[i] = rd(buf, wm + 16 * i + rr, s_lo);
+    }
+#pragma unroll
+    for (int jh = 0; jh < 2; ++jh) {
+      v8bf bh[4], bl[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bh[j] = rd(buf, 256 + wn + 64 * jh + 16 * j + rr, s_hi);
+        bl[j] = rd(buf, 256 + wn + 64 * jh + 16 * j + rr, s_lo);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][jh * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][jh * 4 + j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][jh * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][jh * 4 + j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][jh * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][jh * 4 + j], 0, 0, 0);
+    }
+  };
+
+  // Stage s sits in buffer s % 2.  The loop handles stage pairs with the buffers
+  // named statically (no exit between the two halves: a mid-loop exit made the
+  // register allocator shuffle the accumulators); an odd last stage follows it.
+  // vmcnt(0) before each barrier: this wave's DMA of the stage has landed.  At the
+  // end the DMA target is clamped to a valid stage: the buffer is free after the
+  // barrier and nothing reads it again.
+  if (nk > 0) issue(buf0, kbeg);
+  int s = 0;
+  for (; s + 1 < nk; s += 2) {
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
+    issue(buf1, kbeg + (s + 1) * 32);
+    compute(buf0);
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
+    issue(buf0, kbeg + (s + 2 < nk ? s + 2 : 0) * 32);
+    compute(buf1);
+  }
+  if (s < nk) {
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
+    compute(buf0);
+  }
+  // drain the clamped DMA of the last loop pass before the workgroup can end
+  __builtin_amdgcn_s_waitcnt(0x0f70);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm + i * 16 + q * 4 + r;
+        const int gn = n0 + wn + j * 16 + rr;
+        if (gm < M && gn < N) Cz[gm * N + gn] = static_cast<double>(acc[i][j][r]);
+      }
 }
 
+// Cell operand of the FP32 contraction, formed once per launch: x = X - Xref
+// (Xref null: X) rounded to FP32.
 __global__ void convert_x_f32_kernel(const double* __restrict__ X, const double* __restrict__ Xref, int64_t count,
                                      float* __restrict__ out) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -2469,10 +2577,15 @@ hipError_t launch_reduce_operator(const double* op, int64_t ld, double* red, int
   return hipGetLastError();
 }
 
-hipError_t launch_split_x(const double* X, const double* Xref, int64_t count, uint16_t* hi, uint16_t* lo,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(split_x_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, X, Xref, count,
-                     hi, lo);
+int pair_stride(int K) { return (K + 63) / 64 * 64; }
+
+hipError_t launch_split_pairs(const double* X, const double* Xref, int64_t rows, int K, uint16_t* P, int with_lo,
+                              hipStream_t s) {
+  const int Kp = pair_stride(K);
+  const int64_t n = rows * Kp;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(split_pairs_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, X, Xref, rows,
+                     K, Kp, P, with_lo);
   return hipGetLastError();
 }
 
@@ -2487,11 +2600,6 @@ hipError_t launch_convert_f32(const double* op, float* out, int64_t count, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_split_bf16(const double* op, uint16_t* hi, uint16_t* lo, int64_t count, hipStream_t s) {
-  hipLaunchKernelGGL(split_bf16_kernel, dim3((count + 255) / 256), dim3(256), 0, s, op, hi, lo, count);
-  return hipGetLastError();
-}
-
 int gemm_k_per_split(int K, int splits) {
   const int unit = 64;  // multiple of every BK
   int kps = (K + splits - 1) / splits;
@@ -2499,20 +2607,30 @@ int gemm_k_per_split(int K, int splits) {
   return kps;
 }
 
-int gemm_tile_rows(int tile) { return (tile == 0 || tile == 3) ? 128 : (tile == 2 || tile == 4) ? 64 : 32; }
+int gemm_tile_rows(int tile) {
+  return tile == 5 ? 256 : (tile == 0 || tile == 3) ? 128 : (tile == 2 || tile == 4) ? 64 : 32;
+}
 
 int gemm_tile_depth(int tile, int precision) {
+  if (tile == 5) return 32;        // 3xBF16, 256 x 256: 32-deep stages in two LDS buffers
   if (precision >= 2) return 64;   // bf16 forms: both operands staged in 64-deep stages
   return tile >= 3 ? 32 : 16;
 }
 
+bool gemm_wide_fits(int64_t M, int N, int K) {
+  const int64_t row_bytes = 4 * static_cast<int64_t>(pair_stride(K));
+  return M * row_bytes < (int64_t(1) << 32) && N * row_bytes < (int64_t(1) << 32);
+}
+
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
-  const int kps = gemm_k_per_split(g.K, g.splits);
   const int BN = 128;
   const int BM = gemm_tile_rows(g.tile);
   dim3 grid((g.N + BN - 1) / BN, static_cast<unsigned>((g.M + BM - 1) / BM), g.splits);
-  if (g.tile >= 3 && g.precision != 0) return hipErrorInvalidValue;
+  if (g.tile >= 3 && g.precision == 1) return hipErrorInvalidValue;
+  if (g.tile == 5 && g.precision != 2) return hipErrorInvalidValue;
+  if ((g.tile == 3 || g.tile == 4) && g.precision != 0) return hipErrorInvalidValue;
   if (g.precision == 0) {
+    const int kps = gemm_k_per_split(g.K, g.splits);
     if (g.tile == 0)
       hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
     else if (g.tile == 2)
@@ -2524,6 +2642,7 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
     else
       hipLaunchKernelGGL((gemm_f64_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
   } else if (g.precision == 1) {
+    const int kps = gemm_k_per_split(g.K, g.splits);
     if (!g.X32) return hipErrorInvalidValue;
     if (g.tile == 0)
       hipLaunchKernelGGL((gemm_f32_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
@@ -2531,22 +2650,29 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
       hipLaunchKernelGGL((gemm_f32_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
     else
       hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
-  } else if (g.precision == 3) {
-    if (!g.Xh) return hipErrorInvalidValue;
-    if (g.tile == 0)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64, 1>), grid, dim3(256), 0, s, g.Xh, g.Xh, g.ophi, g.ophi, g.acc, g.M, g.N, g.K, kps);
-    else if (g.tile == 2)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64, 1>), grid, dim3(256), 0, s, g.Xh, g.Xh, g.ophi, g.ophi, g.acc, g.M, g.N, g.K, kps);
-    else
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32, 1>), grid, dim3(256), 0, s, g.Xh, g.Xh, g.ophi, g.ophi, g.acc, g.M, g.N, g.K, kps);
   } else {
-    if (!g.Xh || !g.Xl) return hipErrorInvalidValue;
-    if (g.tile == 0)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.Xh, g.Xl, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
-    else if (g.tile == 2)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.Xh, g.Xl, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
-    else
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.Xh, g.Xl, g.ophi, g.oplo, g.acc, g.M, g.N, g.K, kps);
+    // bf16 forms: operands in the pair layout, k running over the padded Kp (zeros past K)
+    if (!g.Xp || !g.opp) return hipErrorInvalidValue;
+    const int Kp = pair_stride(g.K);
+    const int kps = gemm_k_per_split(Kp, g.splits);
+    if (g.precision == 3) {
+      if (g.tile == 0)
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+      else if (g.tile == 2)
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+      else
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+    } else if (g.tile == 5) {
+      if (!gemm_wide_fits(g.M, g.N, g.K)) return hipErrorInvalidValue;
+      dim3 wgrid((g.N + 255) / 256, static_cast<unsigned>((g.M + 255) / 256), g.splits);
+      hipLaunchKernelGGL(gemm_bf16x3_wide_kernel, wgrid, dim3(512), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+    } else if (g.tile == 0) {
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+    } else if (g.tile == 2) {
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+    } else {
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+    }
   }
   return hipGetLastError();
 }

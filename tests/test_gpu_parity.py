@@ -395,14 +395,17 @@ def test_bf16_solve_with_fp64_anchors_matches_fp64():
 
 @pytest.mark.parametrize("nc", [300, 1000])
 def test_bf16_contraction_configurations_agree(nc):
-    """Every tile of the two bf16 contractions (k-stage 64), fixed through the ABI:
-    each output element runs the same MFMA sequence whatever the tile height and
-    the order in which tiles are assigned to XCDs, so at equal split-K the tiles
+    """Every tile of the two bf16 contractions (k-stage 64, and for 3xBF16 the
+    256 x 256 tile with 32-deep LDS-DMA stages), fixed through the ABI: each
+    output element runs the same MFMA sequence whatever the tile shape and the
+    order in which tiles are assigned to XCDs, so at equal split-K the tiles
     agree to the last bit, and all stay within the form's error of the FP64
-    contraction.  n3 = 864 leaves the last 64-deep stage half past the k range;
-    both cell counts leave a ragged last cell tile, and with 1000 cells every
-    tile height gives a tile count divisible by the 8 XCDs (the per-XCD runs of
-    the tile order) while 300 cells give counts that are not."""
+    contraction.  n3 = 864 is padded to 896 in the pair layout (the last 64-deep
+    stage half past the k range, zeros); both cell counts leave a ragged last
+    cell tile (and 864 operator rows a ragged last 256-row tile), and with 1000
+    cells every 128-wide tile height gives a tile count divisible by the 8 XCDs
+    (the per-XCD runs of the tile order) while 300 cells give counts that are
+    not.  Split-K 3 gives the 256 x 256 tile 10, 10 and 8 stages of 32."""
     p = sis.Plan(12, 4.0, m_angle=4, parity=1)
     h0 = inputs.rough_h(12, 4.0, nc)[..., 6:]
     h = dev(np.ascontiguousarray(h0).reshape(nc, -1))
@@ -416,7 +419,8 @@ def test_bf16_contraction_configurations_agree(nc):
         p.set_precision(prec)
         for splits in (1, 3):
             outs = {}
-            for rows, depth in ((128, 64), (64, 64), (32, 64)):
+            shapes = ((128, 64), (64, 64), (32, 64)) + (((256, 32),) if prec == "bf16x3" else ())
+            for rows, depth in shapes:
                 p.set_contraction_config(nc, rows, depth, splits, precision=prec)
                 out = torch.empty_like(h)
                 p.collide(h, delta, out)
@@ -430,6 +434,8 @@ def test_bf16_contraction_configurations_agree(nc):
                 assert np.array_equal(o, base), (prec, key, splits, rel(o, base))
     with pytest.raises(sis.SisError):
         p.set_contraction_config(nc, 128, 16, 1, precision="bf16x3")
+    with pytest.raises(sis.SisError):
+        p.set_contraction_config(nc, 256, 32, 1, precision="bf16")
     with pytest.raises(sis.SisError):
         p.set_contraction_config(nc, 128, 64, 1, precision="fp64")
 
