@@ -742,6 +742,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void g
         for (int j = 0; j < 4; ++j)
           acc[i][jh * 4 + j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][jh * 4 + j], 0, 0, 0);
     }
+    // issue order: the A and first-half reads, then the second half's eight reads
+    // one per six of the first half's MFMAs, then the second half's MFMAs
+    __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+    for (int g = 0; g < 8; ++g) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 48, 0);
   };
 
   // Stage s sits in buffer s % 2.  The loop handles stage pairs with the buffers
