@@ -420,6 +420,24 @@ def ttr_runs(W, runs, refresh_every):
     return ttr
 
 
+def ttr_persistent(W, launched):
+    """Time to residual 1e-8 of the FP64 solve run as persistent cooperative launches
+    (grid barriers between the steps of an iteration, 8 iterations per launch)."""
+    from paper_1612_04488_amd import sis
+    plan, geom = W["plan"], W["geom"]
+    plan.set_precision("fp64")
+    sis.solve(plan, geom, scheme="SIS", N=W["Npen"], eps=1e-8, max_it=400, persistent=1, check_every=8,
+              raise_not_converged=False)
+    r = sis.solve(plan, geom, scheme="SIS", N=W["Npen"], eps=1e-8, max_it=400, persistent=1, check_every=8,
+                  raise_not_converged=False)
+    import numpy as np
+    e = {"seconds": round(r["seconds"], 4), "iters": r["iters"].tolist(), "converged": bool(r["status"] == 0),
+         "max_rel_dev_M_vs_launched": float(np.max(np.abs(r["M"] - np.asarray(launched["M"])) / np.abs(launched["M"]))),
+         "speedup_vs_launched": round(launched["seconds"] / r["seconds"], 3)}
+    log(f"{W['w']['name']}: time-to-residual fp64 persistent: {r['seconds']:.4f} s, iters {r['iters'].tolist()}")
+    return e
+
+
 def config_of(W, precision):
     w, plan, geom, parity = W["w"], W["plan"], W["geom"], W["parity"]
     c = {"workload": w["name"], "kernel": w["kernel"], "n_v": w["n_v"], "l_v": w["l_v"], "n_pad": w["n_pad"],
@@ -579,6 +597,8 @@ def main():
             del eh, ed, erhs
             E["plan"].set_precision("fp64")
         et = ttr_runs(E, [("fp64", False), ("bf16x3", False)], args.refresh_every) if not args.no_ttr else {}
+        if et and E["planar"] and not E["mix"]:
+            et["fp64_persistent"] = ttr_persistent(E, et["fp64"])
         extras[E["w"]["name"]] = {
             "value": en * args.steps / ew, "unit": "cell-updates/s", "ms_per_step": ew * 1e3 / args.steps,
             "config": config_of(E, "fp64"), "roofline": er, "bf16x3_contraction": elp,

@@ -450,6 +450,22 @@ typedef struct {
                             iteration FP64; < 0 -> no anchors (plain
                             low-precision contraction every iteration).
                             Ignored in FP64.                                 */
+  int32_t persistent;    /* 0: each iteration as launched kernels (a graph
+                            with use_graph).  1: the check_every iterations
+                            between polls as ONE cooperative launch whose
+                            workgroups stay resident and separate the steps
+                            of the iteration (contraction, finish, sweep,
+                            moments, velocity equation and stop rule) by
+                            grid barriers -- for small batches, where each
+                            launched step is a few microseconds of work.
+                            > 1: the same with that many workgroups (capped
+                            at the co-resident limit).  Planar one-gas plans
+                            with the FP64 contraction only; any other
+                            solve returns SIS_E_UNSUPPORTED at creation.
+                            Results match the launched path to rounding
+                            (the contraction's split-K slicing differs).
+                            A barrier wait that runs out ends the launch
+                            early and the next poll returns SIS_E_DEVICE. */
 } sis_solve_opts;
 
 /* Mixtures: M, Q are [n_cases][2] (M_a = sqrt(m/m_A) 2 int U_a dx1, Q_a

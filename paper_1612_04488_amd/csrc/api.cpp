@@ -3046,6 +3046,11 @@ struct sis_state {
   hipGraph_t graph[2] = {nullptr, nullptr};    // [0] refresh / plain, [1] incremental
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   int total = 0;
+  // persistent launch (planar one-gas FP64 solves): workgroups, split-K slices of the
+  // contraction and their depth, the grid-barrier words
+  bool persistent = false;
+  int p_blocks = 0, p_splits = 1, p_kps = 0;
+  unsigned* bar = nullptr;
   ~sis_state() {
     for (int i = 0; i < 2; ++i) {
       if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
@@ -3053,7 +3058,7 @@ struct sis_state {
     }
     dfree(xref); dfree(accref);
     dfree(h); dfree(rhs); dfree(amom); dfree(mom); dfree(dU); dfree(U); dfree(q); dfree(state);
-    dfree(iters); dfree(cact); dfree(lact);
+    dfree(iters); dfree(cact); dfree(lact); dfree(bar);
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
@@ -3135,6 +3140,68 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind, bool h_is_zero
   return SIS_OK;
 }
 
+// n_iters iterations as one persistent cooperative launch (planar one-gas FP64 solves): the
+// arguments of the launched path's finish, sweep, moment and velocity-equation steps.
+sis_status persistent_iterations(sis_state* b, int n_iters, hipStream_t s) {
+  sis_plan* p = b->p;
+  sis_geom* g = b->g;
+  const bool sis = b->o.scheme == SIS_SCHEME_SIS;
+  sis::Persist1DArgs a{};
+  a.h = b->h;
+  a.op = p->op;
+  a.acc = static_cast<double*>(b->ws_acc.p);
+  a.n_cells = g->n_cells;
+  a.n3 = p->ndof;
+  a.kps = b->p_kps;
+  a.splits = b->p_splits;
+  a.fin = finish_args(p, g->n_cells, b->h, sis ? b->dU : nullptr, g->delta_cell, g->flow_cell, b->o.project, b->rhs,
+                      nullptr, b->amom, b->lact, 0, nullptr, nullptr);
+  a.sw.n = p->n;
+  a.sw.n3 = p->nv;
+  a.sw.d2 = p->d2;
+  a.sw.d3 = p->d3;
+  a.sw.nsp = p->nsp;
+  a.sw.n_cases = g->n_cases;
+  a.sw.node_off = g->off;
+  a.sw.coef = g->coef;
+  a.sw.delta_case = g->delta_case;
+  a.sw.v1d = p->v1d;
+  a.sw.nu = p->nu;
+  a.sw.rhs = b->rhs;
+  a.sw.h = b->h;
+  a.sw.case_active = b->cact;
+  a.vtab = p->vtab;
+  a.w = p->wr;
+  a.mom = b->mom;
+  a.dif.n_cases = g->n_cases;
+  a.dif.node_off = g->off;
+  a.dif.x = g->x;
+  a.dif.coef = g->coef;
+  a.dif.delta_case = g->delta_case;
+  a.dif.flow_case = g->flow_case;
+  a.dif.mom = b->mom;
+  a.dif.amom = b->amom;
+  a.dif.N = b->Npen;
+  a.dif.sis = sis ? 1 : 0;
+  a.dif.cU = p->cU;
+  a.dif.cq = p->cq;
+  a.dif.U = nullptr;
+  a.dif.ufield = b->U;
+  a.dif.dU = b->dU;
+  a.dif.state = b->state;
+  a.dif.iters = b->iters;
+  a.dif.case_active = b->cact;
+  a.dif.qfield = b->q;
+  a.dif.eps = b->o.eps;
+  set_species(a.dif, p, b->o.N);
+  a.cell_active = b->lact;
+  a.n_iters = n_iters;
+  a.first_from_zero = b->total == 0 ? 1 : 0;
+  a.bar = b->bar;
+  HIP_TRY(sis::launch_persist1d(a, b->p_blocks, s));
+  return SIS_OK;
+}
+
 sis_status state_init(sis_state* b, hipStream_t s) {
   const int64_t nc = b->g->n_cells;
   const int ncase = b->g->n_cases;
@@ -3208,7 +3275,32 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
     ST_TRY(dmalloc(&b->xref, static_cast<size_t>(nc) * n3));
     ST_TRY(dmalloc(&b->accref, static_cast<size_t>(nc) * n3));
   }
-  {
+  if (o->persistent) {
+    if (g->two_d || g->tube || p->polar || nsp != 1 || p->precision != SIS_PREC_FP64) {
+      delete b;
+      return fail(SIS_E_UNSUPPORTED, "the persistent launch runs planar one-gas solves with the FP64 contraction");
+    }
+    const int maxb = sis::persist1d_max_blocks();
+    if (maxb < 1) { delete b; return fail(SIS_E_DEVICE, "persistent launch: no co-resident workgroups"); }
+    // split-K slices (multiples of 16 deep, at least 32) so that the contraction has about
+    // 64 tiles; as many workgroups as the largest phase needs, at most 64 (each grid barrier
+    // costs more with more workgroups: 32-64 measured fastest on 2- and 17-cell batches)
+    // and within the co-resident limit, or the count the caller asked for
+    const int tiles = ((n3 + 127) / 128) * static_cast<int>((nc + 31) / 32);
+    int sp = std::max(1, std::min(64 / std::max(1, tiles), n3 / 32));
+    int kps = ((n3 + sp - 1) / sp + 15) / 16 * 16;
+    sp = (n3 + kps - 1) / kps;
+    int64_t want = std::min<int64_t>(64, std::max<int64_t>({static_cast<int64_t>(tiles) * sp, nc,
+                                                            static_cast<int64_t>(ncase)}));
+    if (o->persistent > 1) want = o->persistent;
+    b->persistent = true;
+    b->p_splits = sp;
+    b->p_kps = kps;
+    b->p_blocks = static_cast<int>(std::min<int64_t>(want, maxb));
+    ST_TRY(dmalloc(&b->bar, 4));
+    ST_TRY(b->ws_acc.ensure(static_cast<size_t>(sp) * nc * n3 * 8));
+  }
+  if (!b->persistent) {
     // contraction configurations of this shape (FP64 and the plan precision)
     if (sis_status st = tune_gemm(p, nc, SIS_PREC_FP64, b->h, &b->ws_acc, &b->ws_x, stream)) { delete b; return st; }
     if (p->precision != SIS_PREC_FP64)
@@ -3220,12 +3312,12 @@ sis_status sis_state_create(sis_plan_t p, sis_geom_t g, const sis_solve_opts* o,
       ST_TRY(b->ws_x.ensure(static_cast<size_t>(nc) * (p->precision == SIS_PREC_FP32 ? n3 : sis::pair_stride(n3)) * 4));
   }
   hipStream_t s = stream;
-  if (o->use_graph) {
+  if (o->use_graph && !b->persistent) {
     ST_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
     s = b->cap;
   }
   if (sis_status st = state_init(b, s)) { delete b; return st; }
-  if (o->use_graph) {
+  if (o->use_graph && !b->persistent) {
     const int kinds = b->refresh > 1 ? 2 : 1;
     for (int k = 0; k < kinds; ++k) {
       ST_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
@@ -3252,6 +3344,12 @@ sis_status sis_state_reset(sis_state_t b, hipStream_t stream) {
 sis_status sis_state_step(sis_state_t b, int32_t n_iters, hipStream_t stream) {
   if (!b) return fail(SIS_E_INVALID, "null state");
   if (n_iters < 0) return fail(SIS_E_INVALID, "n_iters must be >= 0");
+  if (b->persistent) {
+    if (n_iters == 0) return SIS_OK;
+    if (sis_status st = persistent_iterations(b, n_iters, stream)) return st;
+    b->total += n_iters;
+    return SIS_OK;
+  }
   for (int i = 0; i < n_iters; ++i) {
     // FP64 anchors at iteration 0 (h = 0, free) and at R/2, 3R/2, ...: a case that converges
     // within R iterations is still anchored once after the start
@@ -3274,7 +3372,10 @@ sis_status sis_state_poll(sis_state_t b, int32_t* n_active, hipStream_t stream) 
   if (!b || !n_active) return fail(SIS_E_INVALID, "null argument");
   std::vector<int32_t> act(b->g->n_cases);
   HIP_TRY(hipMemcpyAsync(act.data(), b->cact, act.size() * 4, hipMemcpyDeviceToHost, stream));
+  unsigned words[4] = {0, 0, 0, 0};
+  if (b->persistent) HIP_TRY(hipMemcpyAsync(words, b->bar, sizeof(words), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
+  if (words[2] != 0) return fail(SIS_E_DEVICE, "persistent launch: a grid-barrier wait ran out (results invalid)");
   int n = 0;
   for (int32_t a : act) n += a != 0;
   *n_active = n;

@@ -149,6 +149,34 @@ struct DiffusionArgs {
 };
 hipError_t launch_diffusion1d(const DiffusionArgs& a, hipStream_t s);
 
+// Persistent 1-D iteration (one gas, FP64 contraction): n_iters whole SIS/CIS iterations in
+// one cooperative launch of `blocks` workgroups (at most persist1d_max_blocks()), the phases
+// separated by grid barriers.  The contraction runs on 32 x 128 tiles with split-K slices of
+// kps (a multiple of 16) into acc [splits][n_cells][n3]; fin, sw, dif are the launched path's
+// arguments for the finish, sweep and velocity-equation steps (fin.acc and fin.splits are set
+// per iteration).  first_from_zero: the first iteration starts from h = 0 and skips the
+// contraction.  cell_active [n_cells] is rewritten from dif.case_active after each march.
+// bar: 4 device words, zeroed by the launcher; bar[2] != 0 after the launch means a barrier
+// wait ran out (the results are then invalid).
+struct Persist1DArgs {
+  const double* h;
+  const double* op;
+  double* acc;
+  int64_t n_cells;
+  int n3, kps, splits;
+  FinishArgs fin;
+  SweepArgs sw;
+  const double* vtab;
+  double w;
+  double* mom;
+  DiffusionArgs dif;
+  int32_t* cell_active;
+  int n_iters, first_from_zero;
+  unsigned* bar;
+};
+int persist1d_max_blocks();
+hipError_t launch_persist1d(const Persist1DArgs& a, int blocks, hipStream_t s);
+
 // ---------------------------------------------------------------- 2-D cross sections
 struct Sweep2DArgs {
   int n, n3, n_cases;

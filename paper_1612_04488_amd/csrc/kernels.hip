@@ -203,11 +203,12 @@ __device__ inline int2 xcd_tile() {
   return make_int2(in_group / rows_in_group, first_y + in_group % rows_in_group);
 }
 
+// One output tile (operator tile bx, cell tile by, split bz) of the FP64 contraction; called by
+// gemm_f64_kernel with the block indices and by the persistent 1-D iteration over virtual tiles.
 template <int BM, int BN, int WM, int WN, int BK = kBK, int NBUF = 2, int PAD = kPad>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict__ X,
-                                                       const double* __restrict__ Op,
-                                                       double* __restrict__ C, int64_t M, int N,
-                                                       int K, int kps) {
+__device__ __forceinline__ void gemm_f64_tile(const double* __restrict__ X, const double* __restrict__ Op,
+                                              double* __restrict__ C, int64_t M, int N, int K, int kps, int bx,
+                                              int by, int bz) {
   constexpr int WAVES_N = BN / WN;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int A_LD = BM * BK / 2 / 256;
@@ -220,11 +221,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WAVES_N) * WM, wn = (wave % WAVES_N) * WN;
   // plain grid order: the MFMA-bound FP64 tiles measured no faster (planar batch slower) with xcd_tile()
-  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * BM;
-  const int n0 = blockIdx.x * BN;
-  const int kbeg = blockIdx.z * kps;
+  const int64_t m0 = static_cast<int64_t>(by) * BM;
+  const int n0 = bx * BN;
+  const int kbeg = bz * kps;
   const int kend = min(K, kbeg + kps);
-  double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
+  double* Cz = C + static_cast<int64_t>(bz) * M * N;
 
   double2 ra[A_LD], rb[B_LD];
   auto gload = [&](int k0) {
@@ -364,6 +365,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
         const int gn = n0 + wn + j * 16 + cc;
         if (gm < M && gn < N) Cz[gm * N + gn] = acc[i][j][r];
       }
+}
+
+template <int BM, int BN, int WM, int WN, int BK = kBK, int NBUF = 2, int PAD = kPad>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict__ X, const double* __restrict__ Op,
+                                                       double* __restrict__ C, int64_t M, int N, int K, int kps) {
+  gemm_f64_tile<BM, BN, WM, WN, BK, NBUF, PAD>(X, Op, C, M, N, K, kps, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------------ FP32 MFMA GEMM
@@ -799,10 +806,12 @@ __global__ void convert_x_f32_kernel(const double* __restrict__ X, const double*
 }
 
 // ------------------------------------------------------------------ finish
-__global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
+// Row c = (cell, species) of the finish step; called by finish_kernel with the block index and by
+// the persistent 1-D iteration.
+__device__ __forceinline__ void finish_row(const FinishArgs& a, int64_t c_row, int nsplit, const double* acc_p) {
   __shared__ double sh[4 * 9];
   __shared__ double coef[5];
-  const int64_t c = blockIdx.x;  // (cell, species) row of n3 values
+  const int64_t c = c_row;  // (cell, species) row of n3 values
   const int nsp = a.nsp, sp = static_cast<int>(c % nsp);
   const int64_t cell = c / nsp;
   if (a.active && !a.active[cell]) return;
@@ -862,8 +871,8 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
   // pairs need 16-byte alignment of every row touched (caller arrays may be offset views)
   const uintptr_t align = reinterpret_cast<uintptr_t>(a.h + base) | reinterpret_cast<uintptr_t>(a.rhs + base) |
                           (a.lh ? reinterpret_cast<uintptr_t>(a.lh + base) : 0) |
-                          (a.splits > 0 ? reinterpret_cast<uintptr_t>(a.acc + base) |
-                                              reinterpret_cast<uintptr_t>(a.acc + sstride) : 0) |
+                          (nsplit > 0 ? reinterpret_cast<uintptr_t>(acc_p + base) |
+                                              reinterpret_cast<uintptr_t>(acc_p + sstride) : 0) |
                           (a.anchor_mode ? reinterpret_cast<uintptr_t>(a.accref + base) |
                                                reinterpret_cast<uintptr_t>(a.xref + base) : 0);
   if ((n3 & 1) == 0 && (align & 15) == 0) {
@@ -878,21 +887,21 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
         hv[u] = p0 + u * bs < np ? d2p(a.h + base)[p0 + u * bs] : make_double2(0.0, 0.0);
       }
       // split-K partials four at a time, summed in split order
-      for (int z0 = 0; z0 < a.splits; z0 += 4) {
+      for (int z0 = 0; z0 < nsplit; z0 += 4) {
         double2 t[4][UP];
 #pragma unroll
         for (int dz = 0; dz < 4; ++dz)
 #pragma unroll
           for (int u = 0; u < UP; ++u) {
             const int pp = p0 + u * bs;
-            t[dz][u] = (z0 + dz < a.splits && pp < np) ? d2p(a.acc + (z0 + dz) * sstride + base)[pp]
+            t[dz][u] = (z0 + dz < nsplit && pp < np) ? d2p(acc_p + (z0 + dz) * sstride + base)[pp]
                                                        : make_double2(0.0, 0.0);
           }
 #pragma unroll
         for (int dz = 0; dz < 4; ++dz)
 #pragma unroll
           for (int u = 0; u < UP; ++u)
-            if (z0 + dz < a.splits) {
+            if (z0 + dz < nsplit) {
               sv[u].x += t[dz][u].x;
               sv[u].y += t[dz][u].y;
             }
@@ -935,20 +944,20 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
         sv[u] = 0.0;
         hv[u] = v0 + u * bs < n3 ? a.h[base + v0 + u * bs] : 0.0;
       }
-      for (int z0 = 0; z0 < a.splits; z0 += 4) {
+      for (int z0 = 0; z0 < nsplit; z0 += 4) {
         double t[4][U];
 #pragma unroll
         for (int dz = 0; dz < 4; ++dz)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int v = v0 + u * bs;
-            t[dz][u] = (z0 + dz < a.splits && v < n3) ? a.acc[(z0 + dz) * sstride + base + v] : 0.0;
+            t[dz][u] = (z0 + dz < nsplit && v < n3) ? acc_p[(z0 + dz) * sstride + base + v] : 0.0;
           }
 #pragma unroll
         for (int dz = 0; dz < 4; ++dz)
 #pragma unroll
           for (int u = 0; u < U; ++u)
-            if (z0 + dz < a.splits) sv[u] += t[dz][u];
+            if (z0 + dz < nsplit) sv[u] += t[dz][u];
       }
       if (a.anchor_mode == 2)
 #pragma unroll
@@ -997,17 +1006,19 @@ __global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) {
 
 // ------------------------------------------------------------------ sweep
 // One thread per velocity pair (v1 > 0 index jp, mirror jm) of one case.
+__global__ __launch_bounds__(256) void finish_kernel(FinishArgs a) { finish_row(a, blockIdx.x, a.splits, a.acc); }
+
 // One thread per (case, species, |v1| > 0 velocity pair): the two marches of a velocity are
 // serial in x1, so the right sides and stencil coefficients of the next kSweepChunk nodes are
 // loaded while the current ones are processed (the dependency chain then holds arithmetic
 // only).  Moments are taken afterwards by moments_kernel.
 constexpr int kSweepChunk = 8;
 
-__global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
-  const int cs = blockIdx.y, sp = blockIdx.z, nsp = a.nsp;
+__device__ __forceinline__ void sweep1d_block(const SweepArgs& a, int bx, int cs, int sp) {
+  const int nsp = a.nsp;
   if (a.case_active && !a.case_active[cs]) return;
   const int half = a.n3 / 2, n3 = a.n3;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = bx * blockDim.x + threadIdx.x;
   if (t >= half) return;
   const int64_t c0 = a.node_off[cs];
   const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
@@ -1109,6 +1120,8 @@ __global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void sweep1d_kernel(SweepArgs a) { sweep1d_block(a, blockIdx.x, blockIdx.y, blockIdx.z); }
+
 // Calls f(v1, v2, v3, h) for every unknown of row `row` (n3 values): in 16-byte pairs for
 // rows of even length (the moment kernels are bound by their count of memory instructions).
 template <typename F>
@@ -1133,12 +1146,10 @@ __device__ inline void for_row(int n3, const double* __restrict__ vtab, const do
   }
 }
 
-__global__ __launch_bounds__(256) void moments_kernel(int n3, int nsp, double ms0, double ms1,
-                                                      const double* __restrict__ vtab,
-                                                      const double* __restrict__ h, double w,
-                                                      double* __restrict__ mom) {
+__device__ __forceinline__ void moments_row(int n3, int nsp, double ms0, double ms1, const double* __restrict__ vtab,
+                                            const double* __restrict__ h, double w, double* __restrict__ mom,
+                                            int64_t c) {   // c: (cell, species) row
   __shared__ double sh[4 * 4];
-  const int64_t c = blockIdx.x;  // (cell, species) row
   const double ms = (c % nsp) == 0 ? ms0 : ms1;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
   for_row(n3, vtab, h, c, [&](double v1, double v2, double v3, double hv) {
@@ -1154,6 +1165,13 @@ __global__ __launch_bounds__(256) void moments_kernel(int n3, int nsp, double ms
     for (int k = 0; k < 4; ++k) mom[c * 4 + k] = m[k];
 }
 
+__global__ __launch_bounds__(256) void moments_kernel(int n3, int nsp, double ms0, double ms1,
+                                                      const double* __restrict__ vtab,
+                                                      const double* __restrict__ h, double w,
+                                                      double* __restrict__ mom) {
+  moments_row(n3, nsp, ms0, ms1, vtab, h, w, mom, blockIdx.x);
+}
+
 // ------------------------------------------------------------------ diffusion (1-D)
 // One workgroup per case.  The march from the wall is a serial recurrence, so one
 // lane carries it; the per-node inputs (moments, source, stencil) are staged into LDS
@@ -1161,10 +1179,9 @@ __global__ __launch_bounds__(256) void moments_kernel(int n3, int nsp, double ms
 // way, so the march itself waits on LDS only.
 constexpr int kDiffChunk = 256;
 
-__global__ __launch_bounds__(kDiffChunk) void diffusion1d_kernel(DiffusionArgs a) {
+__device__ __forceinline__ void diffusion1d_case(const DiffusionArgs& a, int cs) {
   __shared__ double in[8][kDiffChunk];    // Uh, qh, G1, source, ca, cb, cc, x
   __shared__ double out[4][kDiffChunk];   // U, dU, q, U of the new iterate
-  const int cs = blockIdx.x;
   if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int64_t c0 = a.node_off[cs];
   const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
@@ -1246,6 +1263,8 @@ __global__ __launch_bounds__(kDiffChunk) void diffusion1d_kernel(DiffusionArgs a
   }
 }
 
+
+__global__ __launch_bounds__(kDiffChunk) void diffusion1d_kernel(DiffusionArgs a) { diffusion1d_case(a, blockIdx.x); }
 
 // Binary mixture (planar): the velocity equations of species B (own shear
 // stress) and A (total stress minus B's), integrated once from the symmetry
@@ -2554,6 +2573,100 @@ __global__ __launch_bounds__(kDiffChunk) void diffusion_tube_kernel(TubeDiffArgs
   }
 }
 
+// ------------------------------------------------------------------ persistent 1-D iteration
+// Small planar batches (a few dozen cells, the coarse-grid setting) are bound by launch
+// latency: one iteration is six dependent launches of a few microseconds of work each.
+// This kernel runs n_iters whole iterations in one cooperative launch: the same phases
+// as the launched path (contraction over virtual 32 x 128 tiles and split-K slices,
+// finish rows, sweep blocks, moment rows, one velocity-equation march per case, which
+// also writes its cells' active flags), each a grid-stride loop over the phase's units,
+// separated by grid barriers.  Results equal the launched path's to rounding (the
+// split-K slicing of the contraction differs).
+//
+// Grid barrier: one arrival counter that only grows within a launch (barrier number t
+// completes when it reaches t * gridDim.x) and a release word; agent-scope fences on
+// both sides make each phase's writes visible to every XCD's caches.  The wait is
+// bounded: a wait that runs out sets the abort word, every later barrier returns at
+// once, and the host reports the launch as failed (no hang).
+constexpr int kBarrierSpin = 1 << 22;
+
+__device__ inline void grid_barrier(unsigned* bar, unsigned& gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned target = ++gen;
+    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+      if (arrived == target * gridDim.x) {
+        __hip_atomic_store(&bar[1], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        int n = 0;
+        while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          if (++n > kBarrierSpin) {
+            __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    __threadfence();
+  } else {
+    ++gen;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void sis1d_persistent_kernel(Persist1DArgs a) {
+  __shared__ int32_t case_flag;
+  unsigned gen = 0;
+  const int G = gridDim.x;
+  const int n_n = (a.n3 + 127) / 128;
+  const int n_m = static_cast<int>((a.n_cells + 31) / 32);
+  const int n_tiles = n_n * n_m * a.splits;
+  const int nbx = (a.sw.n3 / 2 + 255) / 256;
+  const int n_sweep = nbx * a.sw.n_cases;
+  for (int it = 0; it < a.n_iters; ++it) {
+    const bool zero = a.first_from_zero && it == 0;   // h = 0: L+ h = 0, no contraction
+    if (!zero) {
+      for (int t = blockIdx.x; t < n_tiles; t += G) {
+        const int bz = t / (n_n * n_m), r = t - bz * (n_n * n_m);
+        gemm_f64_tile<32, 128, 32, 32>(a.h, a.op, a.acc, a.n_cells, a.n3, a.n3, a.kps, r % n_n, r / n_n, bz);
+        __syncthreads();
+      }
+      grid_barrier(a.bar, gen);
+    }
+    for (int64_t c = blockIdx.x; c < a.fin.n_cells; c += G) {
+      finish_row(a.fin, c, zero ? 0 : a.splits, zero ? nullptr : a.acc);
+      __syncthreads();
+    }
+    grid_barrier(a.bar, gen);
+    for (int t = blockIdx.x; t < n_sweep; t += G) sweep1d_block(a.sw, t % nbx, t / nbx, 0);
+    grid_barrier(a.bar, gen);
+    for (int64_t c = blockIdx.x; c < a.n_cells; c += G) {
+      moments_row(a.sw.n3, 1, 1.0, 1.0, a.vtab, a.sw.h, a.w, a.mom, c);
+      __syncthreads();
+    }
+    grid_barrier(a.bar, gen);
+    for (int cs = blockIdx.x; cs < a.dif.n_cases; cs += G) {
+      diffusion1d_case(a.dif, cs);
+      __syncthreads();
+      // the case's flag, as its march left it, for the cell-level flags of the next finish
+      if (threadIdx.x == 0) case_flag = __hip_atomic_load(&a.dif.case_active[cs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const int64_t c0 = a.dif.node_off[cs], c1 = a.dif.node_off[cs + 1];
+      for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) a.cell_active[c] = case_flag;
+      __syncthreads();
+    }
+    grid_barrier(a.bar, gen);
+  }
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  if (static_cast<int>(threadIdx.x) < n) p[threadIdx.x] = 0u;
+}
+
 __global__ void expand_active_kernel(const int32_t* __restrict__ case_active,
                                      const int32_t* __restrict__ case_of_cell, int64_t n_cells,
                                      int32_t* __restrict__ cell_active) {
@@ -2796,6 +2909,28 @@ hipError_t launch_ns_init(double* X, int n, double alpha, hipStream_t s) {
   const int64_t count = static_cast<int64_t>(n) * n;
   hipLaunchKernelGGL(ns_init_kernel, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, X, n, alpha);
   return hipGetLastError();
+}
+
+int persist1d_max_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, sis1d_persistent_kernel, 256, 0) != hipSuccess) return 0;
+  return cus * per;
+}
+
+hipError_t launch_persist1d(const Persist1DArgs& a, int blocks, hipStream_t s) {
+  if (blocks < 1 || blocks > persist1d_max_blocks()) return hipErrorInvalidConfiguration;
+  if (a.sw.nsp != 1 || a.fin.nsp != 1 || a.n3 != a.sw.n3) return hipErrorInvalidValue;
+  // the barrier words start at zero in every launch (a fill kernel, not a memset node, in
+  // case the caller captures the stream)
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, a.bar, 4);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  Persist1DArgs arg = a;
+  void* params[] = {&arg};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(sis1d_persistent_kernel), dim3(blocks), dim3(256),
+                                    params, 0, s);
 }
 
 hipError_t launch_expand_active(const int32_t* case_active, const int32_t* case_of_cell,

@@ -78,7 +78,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("N", ctypes.c_double), ("eps", ctypes.c_double),
                 ("max_it", ctypes.c_int32), ("project", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("refresh_every", ctypes.c_int32)]
+                ("refresh_every", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class SolveResult(ctypes.Structure):
@@ -465,8 +465,11 @@ def diffusion_correct(plan, geom, mom_half, amom, N, U_out=None, dU_out=None, st
 
 
 def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False,
-          check_every=4, use_graph=True, stream=None, raise_not_converged=True, refresh_every=0):
-    """Run sis_solve; returns a dict of numpy arrays (M, Q, iters, residual, U, q)."""
+          check_every=4, use_graph=True, stream=None, raise_not_converged=True, refresh_every=0,
+          persistent=0):
+    """Run sis_solve; returns a dict of numpy arrays (M, Q, iters, residual, U, q).
+    persistent: 1 (or a workgroup count) runs the iterations between polls as one
+    cooperative launch (planar one-gas FP64 solves)."""
     import numpy as np
     nc, ns, sp = geom.n_cells, geom.n_cases, plan.n_species
     M, Q, res = np.zeros((ns, sp)), np.zeros((ns, sp)), np.zeros(ns)
@@ -476,7 +479,8 @@ def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False
                     it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), res.ctypes.data_as(_D),
                     U.ctypes.data_as(_D), q.ctypes.data_as(_D), 0.0, 0)
     o = SolveOpts(SCHEME_SIS if scheme == "SIS" else SCHEME_CIS, float(N), float(eps), int(max_it),
-                  1 if project else 0, int(check_every), 1 if use_graph else 0, int(refresh_every))
+                  1 if project else 0, int(check_every), 1 if use_graph else 0, int(refresh_every),
+                  int(persistent))
     code = lib().sis_solve(plan.handle, geom.handle, ctypes.byref(o), ctypes.byref(r), _stream(stream))
     if code != SIS_OK and not (code == SIS_E_NOT_CONVERGED and not raise_not_converged):
         check(code)
@@ -486,19 +490,19 @@ def solve(plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False
                 total_iters=r.total_iters, status=code)
 
 
-def _opts(scheme, N, eps, max_it, project, check_every, use_graph, refresh_every=0):
+def _opts(scheme, N, eps, max_it, project, check_every, use_graph, refresh_every=0, persistent=0):
     return SolveOpts(SCHEME_SIS if scheme == "SIS" else SCHEME_CIS, float(N), float(eps),
                      int(max_it), 1 if project else 0, int(check_every), 1 if use_graph else 0,
-                     int(refresh_every))
+                     int(refresh_every), int(persistent))
 
 
 class State:
     """Persistent iteration state of sis_solve (sis_state_* entry points)."""
 
     def __init__(self, plan, geom, scheme="SIS", N=0.0, eps=1e-8, max_it=10000, project=False,
-                 use_graph=True, stream=None, refresh_every=0):
+                 use_graph=True, stream=None, refresh_every=0, persistent=0):
         self.plan, self.geom = plan, geom
-        o = _opts(scheme, N, eps, max_it, project, 4, use_graph, refresh_every)
+        o = _opts(scheme, N, eps, max_it, project, 4, use_graph, refresh_every, persistent)
         h = ctypes.c_void_p()
         check(lib().sis_state_create(plan.handle, geom.handle, ctypes.byref(o), _stream(stream),
                                      ctypes.byref(h)))
