@@ -597,7 +597,9 @@ def main():
             del eh, ed, erhs
             E["plan"].set_precision("fp64")
         et = ttr_runs(E, [("fp64", False), ("bf16x3", False)], args.refresh_every) if not args.no_ttr else {}
-        if et and E["planar"] and not E["mix"]:
+        if et and E["planar"] and not E["mix"] and en <= 64:
+            # the persistent launch is meant for small batches (its contraction runs on at most
+            # 64 workgroups with 32-row tiles)
             et["fp64_persistent"] = ttr_persistent(E, et["fp64"])
         extras[E["w"]["name"]] = {
             "value": en * args.steps / ew, "unit": "cell-updates/s", "ms_per_step": ew * 1e3 / args.steps,

@@ -459,9 +459,12 @@ typedef struct {
                             grid barriers -- for small batches, where each
                             launched step is a few microseconds of work.
                             > 1: the same with that many workgroups (capped
-                            at the co-resident limit).  Planar one-gas plans
-                            with the FP64 contraction only; any other
-                            solve returns SIS_E_UNSUPPORTED at creation.
+                            at the co-resident limit; default at most 64).
+                            Meant for small batches: its contraction runs
+                            on 32 x 128 tiles over those workgroups only.
+                            Planar one-gas plans with the FP64 contraction
+                            only; any other solve returns
+                            SIS_E_UNSUPPORTED at creation.
                             Results match the launched path to rounding
                             (the contraction's split-K slicing differs).
                             A barrier wait that runs out ends the launch

@@ -192,8 +192,8 @@ constexpr int kPad = 4;
 // tile fastest), so the workgroups resident on one XCD share a few cell and
 // operator tiles per k-stage.  A permutation of the (x, y) tiles: results are
 // unchanged.  Returns the cell tile in .y and the operator tile in .x.
+template <int kGroup = 8>
 __device__ inline int2 xcd_tile() {
-  constexpr int kGroup = 8;
   const int gx = gridDim.x, gy = gridDim.y, total = gx * gy;
   int b = blockIdx.y * gx + blockIdx.x;
   if (total % 8 == 0) b = (b % 8) * (total / 8) + b / 8;
@@ -676,7 +676,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void g
   __shared__ uint4 buf1[512][8];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int2 tile = xcd_tile();
+  // groups of 4 cell-tile rows: an XCD's 32 resident workgroups then share 4 cell tiles and
+  // 8 operator tiles per stage (2% faster on the duct than 8 x 4, which re-reads more of the
+  // cell operand, the array that does not stay in the last-level cache)
+  const int2 tile = xcd_tile<4>();
   const int64_t m0 = static_cast<int64_t>(tile.y) * 256;
   const int n0 = tile.x * 256;
   const int kbeg = blockIdx.z * kps;
