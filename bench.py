@@ -52,17 +52,17 @@ TRAFFIC_KIB = {
     ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16):
         (42415887.6 * 2.0, 1327104.0, "profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md"),
     ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32):
-        (3833658.0 * 2.0, 1327104.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md"),
+        (3694637.6 * 2.0, 1327104.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md"),
     ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32):
-        (240573.7 * 2.0, 103424.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md")}
+        (241401.5 * 2.0, 103424.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md")}
 # MFMA pipe utilisation of the same configuration from its counter pass:
 # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), and the shader clock
 # the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
 MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22),
              ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (0.788, 2.09),
              ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.801, 2.35),
-             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32): (0.635, 2.00),
-             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32): (0.668, 2.13)}
+             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32): (0.641, 2.00),
+             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32): (0.670, 2.11)}
 HBM_GBS = 8000.0
 # worker processes of the CPU baseline: the host's cores, at most the 16 that a
 # one-GPU share of the box holds
