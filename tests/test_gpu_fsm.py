@@ -167,7 +167,7 @@ def test_fsm_at_benchmark_size(workload):
     p.collide(hs, dev(delta), ref)
     torch.cuda.synchronize()
     say("fsm info", p.fsm_info())
-    assert rel(out.cpu().numpy(), ref.cpu().numpy()) < 1e-11
+    assert rel(out.cpu().numpy(), ref.cpu().numpy()) < 1e-12
     alpha = 2.0 * (1.0 - w.get("visc_index", 0.81)) if w["kernel"] == "ipl" else 1.0
     f = collision.FSM(VelocityGrid(w["n_v"], w["l_v"]), n_pad=w["n_pad"], m_angle=w["m_angle"], alpha=alpha)
     got = out.cpu().numpy()

@@ -142,7 +142,7 @@ def test_mix_sweep_moments_diffusion_parity(N):
             assert rel(mom2[a:b, :, k], m_o[:, :, k]) < 1e-12, (c, k)
         U_o = mixture.velocity_1d(o, x, m_o, amom[a:b, :, :2], d, Nn)
         assert rel(U[a:b], U_o) < 1e-12, c
-        assert rel(dU[a:b], U_o - m_o[:, :, 0] / o.chi) < 1e-11, c
+        assert rel(dU[a:b], U_o - m_o[:, :, 0] / o.chi) < 1e-12, c
 
 
 def test_mix_solve_matches_oracle():
@@ -248,4 +248,4 @@ def test_mix_collide_at_benchmark_size():
                            n_pad=w["n_pad"], m_angle=w["m_angle"], m_rho=mx["m_rho"])
     ref = delta[c] * o.lplus(h[c])
     say("mixture benchmark size: oracle done")
-    assert rel(got, np.ascontiguousarray(ref[..., half:, half:]).ravel()) < 1e-11, rel(got, ref[..., half:, half:].ravel())
+    assert rel(got, np.ascontiguousarray(ref[..., half:, half:]).ravel()) < 1e-12, rel(got, ref[..., half:, half:].ravel())
