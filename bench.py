@@ -49,8 +49,10 @@ TRAFFIC_KIB = {
         (1116445.9 * 2.0, 155136.0, "profiles/gemm_f64_planar-hs-32v-808cells-parity.md"),
     ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16):
         (1546552.0 * 2.0, 206848.0, "profiles/gemm_f64_planar-hs-32v-808cells-parity.md"),
+    ("planar-hs-32v-100cells-8cases", 2, "fp64", 128, 4, 16):
+        (1295020.7 * 2.0, 206848.0, "profiles/gemm_f64_planar-hs-32v-808cells-parity.md"),
     ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16):
-        (42415887.6 * 2.0, 1327104.0, "profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md"),
+        (46461496.4 * 2.0, 1327104.0, "profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md"),
     ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32):
         (3694637.6 * 2.0, 1327104.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md"),
     ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32):
@@ -60,7 +62,8 @@ TRAFFIC_KIB = {
 # the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
 MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22),
              ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (0.788, 2.09),
-             ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.801, 2.35),
+             ("planar-hs-32v-100cells-8cases", 2, "fp64", 128, 4, 16): (0.915, 2.06),
+             ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.932, 2.28),
              ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32): (0.641, 2.00),
              ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32): (0.670, 2.11)}
 HBM_GBS = 8000.0
@@ -438,6 +441,37 @@ def ttr_persistent(W, launched):
     return e
 
 
+def library_reference(n_cells, n3, reps):
+    """The vendor library's GEMM (torch.matmul: rocBLAS / hipBLASLt) on the contraction's own shape,
+    timed back to back with HIP events on random operands: FP64 X[n_cells, n3] @ Op[n3, n3]^T, and
+    the BF16 product with K = 3 n3 that the three products of the 3xBF16 contraction amount to
+    (FP32 accumulation, BF16 output).  A reference point for the hand-written kernels only: the
+    solver never calls it."""
+    import torch
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for name, dt, k, peak in (("fp64", torch.float64, n3, 78.6), ("bf16_k3n", torch.bfloat16, 3 * n3, 2500.0)):
+        x = torch.randn(n_cells, k, dtype=dt, device="cuda", generator=g)
+        op = torch.randn(n3, k, dtype=dt, device="cuda", generator=g)
+        c = torch.empty(n_cells, n3, dtype=dt, device="cuda")
+        torch.matmul(x, op.t(), out=c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch.matmul(x, op.t(), out=c)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * n_cells * n3 * k / (ms * 1e-3) / 1e12
+        out[name] = {"ms": round(ms, 4), "tflops": round(tf, 2), "frac": round(tf / peak, 4)}
+        del x, op, c
+    torch.cuda.empty_cache()
+    out["what"] = ("torch.matmul (rocBLAS/hipBLASLt) on the same shape, back-to-back launches; fp64: X @ Op^T; "
+                   "bf16_k3n: one BF16 GEMM with K = 3 n_dof, the work of the three BF16 products")
+    return out
+
+
 def config_of(W, precision):
     w, plan, geom, parity = W["w"], W["plan"], W["geom"], W["parity"]
     c = {"workload": w["name"], "kernel": w["kernel"], "n_v": w["n_v"], "l_v": w["l_v"], "n_pad": w["n_pad"],
@@ -481,6 +515,8 @@ def main():
                     help="only run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--no-ttr", action="store_true", help="skip time-to-residual runs")
     ap.add_argument("--no-fsm", action="store_true", help="skip the per-cell transform path")
+    ap.add_argument("--no-library", action="store_true",
+                    help="skip timing the vendor library's GEMM on the contraction's shape")
     ap.add_argument("--cis-max-it", type=int, default=0,
                     help="also run the conventional iteration (FP64) with this iteration cap")
     ap.add_argument("--refresh-every", type=int, default=16,
@@ -545,6 +581,8 @@ def main():
         W["plan"].set_precision(args.precision)
     sweep = sweep_rate(W, rhs, reps)
     del rhs
+    if not args.no_library and not W["mix"] and not W["tube"]:
+        roofline["library_reference"] = library_reference(nc, W["plan"].n_dof, min(reps, 10))
     fsm = None
     if not args.no_fsm and not W["mix"] and not W["tube"] and hasattr(W["plan"], "collide_fsm"):
         W["plan"].set_precision("fp64")

@@ -51,9 +51,11 @@ struct GemmArgs {
   int N, K;
   int splits;        // split-K factor (grid.z)
   int tile;          // tile configuration id: 0 (128 x 128), 2 (64 x 128), 1 (32 x 128) with 16-deep
-                     // double-buffered stages (64-deep single-buffered for the bf16 forms); FP64 only:
+                     // double-buffered stages (64-deep single-buffered for the bf16 forms; FP64 tile 0:
+                     // eight waves, LDS-DMA stages of k pairs, for K <= 2^20); FP64 only:
                      // 3 (128 x 128), 4 (64 x 128) with 32-deep single-buffered stages; BF16X3 only:
-                     // 5 (256 x 256, 32-deep LDS-DMA stages in two buffers; gemm_wide_fits)
+                     // 5 (256 x 256, 32-deep LDS-DMA stages in two buffers; gemm_wide_fits).
+                     // FP64 needs K even (hipErrorInvalidValue otherwise).
 };
 int gemm_tile_rows(int tile);
 int gemm_tile_depth(int tile, int precision);

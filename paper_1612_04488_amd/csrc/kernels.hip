@@ -21,6 +21,8 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void gbl_void_t;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -373,6 +375,153 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
   gemm_f64_tile<BM, BN, WM, WN, BK, NBUF, PAD>(X, Op, C, M, N, K, kps, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// FP64 contraction on 128 x 128 tiles with LDS-DMA staging: the 128-row tile of the
+// autotuner and the default heuristic.  Eight waves (4 along the cells x 2 along the
+// operator rows) of 32 x 64 outputs: 2 x 4 blocks of the 16x16x4 FP64 MFMA, 64
+// accumulator registers per lane, about 100 registers in all, so two workgroups per CU
+// give four waves per SIMD to cover each other's barrier and LDS waits.
+// A stage is 16 deep and holds k pairs: slot (p, r) of an operand is the 16 bytes
+// (k = 2p, 2p + 1) of its row r, 8 pairs x 128 rows per operand, 32 KB per stage with
+// both operands.  Lane (kq, c) of an MFMA block reads one pair, (kq + 4 h, c), and feeds
+// its first element to one MFMA and its second to the next, so a step of two MFMAs
+// covers k = 2 kq + 8 h + {0, 1} over the four lane groups kq and a stage is two such
+// ds_read_b128 steps (h = 0, 1) per block.  The stages are written by buffer-load LDS
+// DMA (each lane's 16 bytes land at slot (4 j + wave) * 64 + lane of the stage for its
+// instruction j, i.e. pair slot / 128, row slot % 128), so no registers or LDS stores
+// carry the staging and the rows are copied without the transposing stores of the
+// register-staged kernel.  The buffer descriptors start at the tile's first row and end
+// after its last valid row; a pair past the split's k range gets an offset beyond the
+// end: both read as zeros, which pads ragged cell, operator and k tails.
+// Two stage buffers (distinct LDS objects, so that the compiler's LDS-DMA wait tracking
+// lets reads of one proceed while the other is filled) and one barrier per stage: before
+// it this wave's DMA of the next stage has landed (vmcnt(0)) and its reads of the current
+// stage have completed; after it the next stage is visible to every wave and the current
+// buffer is free, so the next stage's first reads are issued, then the DMA of the stage
+// after it into the freed buffer, then the MFMAs of the current stage's second step.
+// Preconditions (checked by the launcher): K even, K <= 2^20 (32-bit offsets within a
+// tile's 128 rows).
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void gemm_f64_dma_kernel(
+    const double* __restrict__ X, const double* __restrict__ Op, double* __restrict__ C, int64_t M, int N, int K,
+    int kps) {
+  __shared__ double2 buf0[2048];   // [operand][pair 0..7][row 0..127]
+  __shared__ double2 buf1[2048];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // plain grid order: the XCD-grouped orders measured within 1% on the duct and mixture shapes
+  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * 128;
+  const int n0 = blockIdx.x * 128;
+  const int kbeg = blockIdx.z * kps;
+  const int kend = min(K, kbeg + kps);
+  const int nk = kend > kbeg ? (kend - kbeg + 15) / 16 : 0;
+  double* Cz = C + static_cast<int64_t>(blockIdx.z) * M * N;
+
+  const int rows_a = static_cast<int>(min<int64_t>(128, M - m0));
+  const int rows_b = min(128, N - n0);
+  const __amdgpu_buffer_rsrc_t rs_a =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X + m0 * K), 0, rows_a * K * 8, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_b = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(Op + static_cast<int64_t>(n0) * K), 0, rows_b * K * 8, 0x00020000);
+  // per DMA instruction j of this wave: the lane's pair and its byte offset within the tile
+  uint32_t roff[2];
+  int pj[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int slot = (8 * j + wave) * 64 + lane;
+    pj[j] = slot >> 7;
+    roff[j] = static_cast<uint32_t>(((slot & 127) * K + 2 * pj[j]) * 8);
+  }
+  auto issue = [&](double2* buf, int k0) {
+    const int krem = kend - k0;
+    const uint32_t kb = static_cast<uint32_t>(k0) * 8u;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t vo = 2 * pj[j] < krem ? roff[j] + kb : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_a, (lds_void_t*)&buf[(8 * j + wave) * 64], 16, vo, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t vo = 2 * pj[j] < krem ? roff[j] + kb : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_b, (lds_void_t*)&buf[1024 + (8 * j + wave) * 64], 16, vo, 0, 0,
+                                               0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  const int kq = lane >> 4, cc = lane & 15;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 64;
+  v4d acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+  double2 a0[2], b0[4], a1[2], b1[4];
+  auto lread = [&](const double2* buf, int h, double2* ar, double2* br) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) ar[i] = buf[(kq + 4 * h) * 128 + wm + 16 * i + cc];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) br[j] = buf[1024 + (kq + 4 * h) * 128 + wn + 16 * j + cc];
+  };
+  auto mfma = [&](const double2* ar, const double2* br) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i].x, br[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i].y, br[j].y, acc[i][j], 0, 0, 0);
+  };
+  // the stage in `cur` (its first step's operands already in a0, b0), the next one landing
+  // in `nxt`; the DMA of stage k_dma goes to `cur` once every wave is past the barrier.  The
+  // sched_barriers keep the MFMAs on their side of the barrier (they touch no memory, so the
+  // scheduler would otherwise move them across it).
+  auto stage = [&](double2* cur, double2* nxt, int k_dma) {
+    lread(cur, 1, a1, b1);
+    mfma(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
+    lread(nxt, 0, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    issue(cur, k_dma);
+    mfma(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  if (nk > 0) {
+    issue(buf0, kbeg);
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
+    issue(buf1, kbeg + (nk > 1 ? 16 : 0));
+    lread(buf0, 0, a0, b0);
+  }
+  // stage pairs with the buffers named statically, then an odd last stage; past the last
+  // stage the DMA target is clamped to the first stage (the freed buffer is not read again)
+  int s = 0;
+  for (; s + 1 < nk; s += 2) {
+    stage(buf0, buf1, kbeg + (s + 2 < nk ? s + 2 : 0) * 16);
+    stage(buf1, buf0, kbeg + (s + 3 < nk ? s + 3 : 0) * 16);
+  }
+  if (s < nk) {
+    lread(buf0, 1, a1, b1);
+    mfma(a0, b0);
+    mfma(a1, b1);
+  }
+  // drain the clamped DMA before the workgroup can end
+  __builtin_amdgcn_s_waitcnt(0x0f70);
+  // D layout of the 16x16x4 FP64 MFMA: lane l, element r -> row l/16 + 4 r, column l%16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm + i * 16 + kq + 4 * r;
+        const int gn = n0 + wn + j * 16 + cc;
+        if (gm < M && gn < N) Cz[gm * N + gn] = acc[i][j][r];
+      }
+}
+
 // ------------------------------------------------------------------ FP32 MFMA GEMM
 // X is converted from double to float when staged; op is stored as float.
 template <int BM, int BN, int WM, int WN>
@@ -666,8 +815,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 // product order), so the two agree to the last bit at equal split-K.
 // Preconditions (checked by the launcher): rows * 4 Kp < 2^32 bytes for both
 // operands (32-bit DMA offsets).
-typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) void gbl_void_t;
 
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_wide_kernel(
     const uint16_t* __restrict__ Xp, const uint16_t* __restrict__ Op, double* __restrict__ C, int64_t M, int N, int Kp,
@@ -2754,8 +2901,11 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.tile == 5 && g.precision != 2) return hipErrorInvalidValue;
   if ((g.tile == 3 || g.tile == 4) && g.precision != 0) return hipErrorInvalidValue;
   if (g.precision == 0) {
+    if (g.K % 2) return hipErrorInvalidValue;   // rows are loaded in 16-byte k pairs
     const int kps = gemm_k_per_split(g.K, g.splits);
-    if (g.tile == 0)
+    if (g.tile == 0 && g.K <= (1 << 20))
+      hipLaunchKernelGGL(gemm_f64_dma_kernel, grid, dim3(512), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
+    else if (g.tile == 0)
       hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
     else if (g.tile == 2)
       hipLaunchKernelGGL((gemm_f64_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.X, g.op64, g.acc, g.M, g.N, g.K, kps);
