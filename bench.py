@@ -54,9 +54,11 @@ TRAFFIC_KIB = {
     ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16):
         (46461496.4 * 2.0, 1327104.0, "profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md"),
     ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32):
-        (3694637.6 * 2.0, 1327104.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md"),
+        (3697812.8 * 2.0, 1327104.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md"),
+    ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 2, 32):
+        (3711624.7 * 2.0, 2654208.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md"),
     ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32):
-        (241401.5 * 2.0, 103424.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md")}
+        (239174.1 * 2.0, 103424.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md")}
 # MFMA pipe utilisation of the same configuration from its counter pass:
 # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCD x 1024 SIMDs), and the shader clock
 # the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
@@ -64,8 +66,9 @@ MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.
              ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (0.788, 2.09),
              ("planar-hs-32v-100cells-8cases", 2, "fp64", 128, 4, 16): (0.915, 2.06),
              ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.932, 2.28),
-             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32): (0.641, 2.00),
-             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32): (0.670, 2.11)}
+             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32): (0.678, 2.28),
+             ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 2, 32): (0.686, 1.87),
+             ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32): (0.689, 2.09)}
 HBM_GBS = 8000.0
 # worker processes of the CPU baseline: the host's cores, at most the 16 that a
 # one-GPU share of the box holds
