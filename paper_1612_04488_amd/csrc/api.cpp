@@ -440,13 +440,17 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   if (err != hipSuccess) return fail(SIS_E_DEVICE, "contraction tuning: %s", hipGetErrorString(err));
   std::pair<int, int> best(dt, ds);
   if (!timed.empty()) {
+    // each split-K partial beyond the first costs the finish step one more FP64 row read per
+    // cell (M x N x 8 bytes at the ~4 TB/s that finish_kernel streams): add it to the timing
+    for (auto& c : timed)
+      c.first += static_cast<float>((c.second.second - 1) * static_cast<double>(M) * p->ndof * 8.0 / 4.0e12 * 1e3);
     float fastest = timed[0].first;
     for (const auto& c : timed) fastest = std::min(fastest, c.first);
-    // within 3% of the fastest: fewest split-K partials, then the larger tile, then the faster
+    // within 1% of the fastest: fewest split-K partials, then the larger tile, then the faster
     int best_rows = -1, best_splits = 1 << 30;
     float best_ms = 0.f;
     for (const auto& c : timed) {
-      if (c.first > 1.03f * fastest) continue;
+      if (c.first > 1.01f * fastest) continue;
       const int rows = sis::gemm_tile_rows(c.second.first), sp = c.second.second;
       if (sp < best_splits || (sp == best_splits && rows > best_rows) ||
           (sp == best_splits && rows == best_rows && c.first < best_ms)) {
