@@ -50,9 +50,9 @@ TRAFFIC_KIB = {
     ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16):
         (1546552.0 * 2.0, 206848.0, "profiles/gemm_f64_planar-hs-32v-808cells-parity.md"),
     ("planar-hs-32v-100cells-8cases", 2, "fp64", 128, 4, 16):
-        (1242859.3 * 2.0, 206848.0, "profiles/gemm_f64_planar-hs-32v-808cells-parity.md"),
+        (1142963.6 * 2.0, 206848.0, "profiles/gemm_f64_planar-hs-32v-808cells-parity.md"),
     ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16):
-        (19625698.9 * 2.0, 1327104.0, "profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md"),
+        (19409697.6 * 2.0, 1327104.0, "profiles/gemm_f64_duct-ipl-24v-64x64-6cases.md"),
     ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32):
         (3697812.8 * 2.0, 1327104.0, "profiles/gemm_bf16x3_duct-ipl-24v-64x64-6cases_planar-hs-32v-808cells.md"),
     ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 2, 32):
@@ -64,8 +64,8 @@ TRAFFIC_KIB = {
 # the kernel ran at (GRBM_GUI_ACTIVE per XCD / kernel duration).
 MFMA_BUSY = {("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 3, 32): (0.779, 2.22),
              ("planar-hs-32v-100cells-8cases", 2, "fp64", 64, 4, 16): (0.788, 2.09),
-             ("planar-hs-32v-100cells-8cases", 2, "fp64", 128, 4, 16): (0.925, 2.04),
-             ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.933, 2.29),
+             ("planar-hs-32v-100cells-8cases", 2, "fp64", 128, 4, 16): (0.927, 2.08),
+             ("duct-ipl081-24v-64x64-6cases", 1, "fp64", 128, 1, 16): (0.932, 2.33),
              ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 1, 32): (0.678, 2.28),
              ("duct-ipl081-24v-64x64-6cases", 1, "bf16x3", 256, 2, 32): (0.686, 1.87),
              ("planar-hs-32v-100cells-8cases", 2, "bf16x3", 256, 2, 32): (0.689, 2.09)}

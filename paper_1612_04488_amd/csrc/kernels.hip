@@ -477,15 +477,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void g
   // in `nxt`; the DMA of stage k_dma goes to `cur` once every wave is past the barrier.  The
   // sched_barriers keep the MFMAs on their side of the barrier (they touch no memory, so the
   // scheduler would otherwise move them across it).
+  // The wave's priority is raised from the barrier until the DMA is issued, so that the memory
+  // instructions after the barrier are not held behind other waves' MFMAs (planar batch 1.74 ->
+  // 1.70 ms, other shapes unchanged).
   auto stage = [&](double2* cur, double2* nxt, int k_dma) {
     lread(cur, 1, a1, b1);
     mfma(a0, b0);
     __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(1);
     __builtin_amdgcn_s_waitcnt(0x0f70);
     __syncthreads();
     lread(nxt, 0, a0, b0);
     __builtin_amdgcn_sched_barrier(0);
     issue(cur, k_dma);
+    __builtin_amdgcn_s_setprio(0);
     mfma(a1, b1);
     __builtin_amdgcn_sched_barrier(0);
   };
