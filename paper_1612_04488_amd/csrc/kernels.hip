@@ -378,16 +378,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const double* __restrict_
 // FP64 contraction on 128 x 128 tiles with LDS-DMA staging: the 128-row tile of the
 // autotuner and the default heuristic.  Eight waves (4 along the cells x 2 along the
 // operator rows) of 32 x 64 outputs: 2 x 4 blocks of the 16x16x4 FP64 MFMA, 64
-// accumulator registers per lane, about 100 registers in all, so two workgroups per CU
-// give four waves per SIMD to cover each other's barrier and LDS waits.
+// accumulator registers per lane, 127 registers in all, so two workgroups per CU give
+// four waves per SIMD to cover each other's barrier and LDS waits.
 // A stage is 16 deep and holds k pairs: slot (p, r) of an operand is the 16 bytes
 // (k = 2p, 2p + 1) of its row r, 8 pairs x 128 rows per operand, 32 KB per stage with
 // both operands.  Lane (kq, c) of an MFMA block reads one pair, (kq + 4 h, c), and feeds
 // its first element to one MFMA and its second to the next, so a step of two MFMAs
 // covers k = 2 kq + 8 h + {0, 1} over the four lane groups kq and a stage is two such
 // ds_read_b128 steps (h = 0, 1) per block.  The stages are written by buffer-load LDS
-// DMA (each lane's 16 bytes land at slot (4 j + wave) * 64 + lane of the stage for its
-// instruction j, i.e. pair slot / 128, row slot % 128), so no registers or LDS stores
+// DMA (each lane's 16 bytes land at slot (8 j + wave) * 64 + lane of the operand's half
+// of the stage for its instruction j, i.e. pair slot / 128, row slot % 128), so no registers or LDS stores
 // carry the staging and the rows are copied without the transposing stores of the
 // register-staged kernel.  The buffer descriptors start at the tile's first row and end
 // after its last valid row; a pair past the split's k range gets an offset beyond the
