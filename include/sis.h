@@ -526,7 +526,7 @@ sis_status sis_plan_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t
  * (FP64, FP32) or 64 (BF16X3, BF16), or (FP64 only) 128 or 64 with k_stage
  * 32, or (BF16X3 only) 256 with k_stage 32 (256 cells x 256 operator rows
  * per tile; SIS_E_UNSUPPORTED when a bf16 pair array of the cells or of the
- * operator would reach 4 GiB); splits in 1..8.  Invalid combinations return
+ * operator would reach 4 GiB); splits in 1..32.  Invalid combinations return
  * SIS_E_INVALID.  At equal splits every BF16X3 tile gives bit-identical
  * results.                                                                  */
 sis_status sis_plan_set_contraction_config(sis_plan_t plan, int64_t n_cells, int32_t precision,

@@ -413,12 +413,14 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   std::vector<int> tiles = {0, 2, 1};
   if (precision == SIS_PREC_FP64) tiles.insert(tiles.end(), {3, 4});
   if (precision == SIS_PREC_BF16X3 && sis::gemm_wide_fits(M, p->ndof, p->ndof)) tiles.push_back(5);
-  const int splits[6] = {1, 2, 3, 4, 6, 8};
+  // split-K up to 32 (at least 64 k values per split): few cells leave most CUs idle otherwise
+  const int splits[10] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
   hipError_t err = hipSuccess;
   for (size_t ti = 0; ti < tiles.size() && err == hipSuccess; ++ti)
-    for (int si = 0; si < 6 && err == hipSuccess; ++si) {
+    for (int si = 0; si < 10 && err == hipSuccess; ++si) {
       const int sp = splits[si];
-      if (sp > 1 && sis::gemm_k_per_split(p->ndof, sp) < 256) continue;
+      if (sp > 1 && sis::gemm_k_per_split(p->ndof, sp) * (sp - 1) >= p->ndof) continue;   // an empty split
+      if (sp > 1 && sis::gemm_k_per_split(p->ndof, sp) < 64) continue;
       const double bytes = static_cast<double>(sp) * M * p->ndof * 8.0;
       if (bytes > 4.0 * (1 << 30)) continue;
       err = ws_acc->ensure(static_cast<size_t>(bytes));
@@ -3454,7 +3456,7 @@ sis_status sis_plan_set_contraction_config(sis_plan_t p, int64_t n_cells, int32_
                                            int32_t k_stage, int32_t splits) {
   if (sis_status st = check_plan(p)) return st;
   if (precision < SIS_PREC_FP64 || precision > SIS_PREC_BF16) return fail(SIS_E_INVALID, "unknown precision");
-  if (splits < 1 || splits > 8) return fail(SIS_E_INVALID, "splits must be in [1, 8]");
+  if (splits < 1 || splits > 32) return fail(SIS_E_INVALID, "splits must be in [1, 32]");
   int tile = -1;
   if (precision == SIS_PREC_BF16X3 && tile_rows == 256 && k_stage == 32) {
     tile = 5;
