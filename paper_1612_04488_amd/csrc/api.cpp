@@ -91,6 +91,14 @@ struct Scratch {
     if (e == hipSuccess) bytes = need;
     return e;
   }
+  // give back what the largest tuning candidate needed beyond `keep` bytes
+  hipError_t shrink(size_t keep) {
+    if (bytes <= keep) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    return keep ? ensure(keep) : hipSuccess;
+  }
   ~Scratch() { dfree(p); }
 };
 
@@ -464,6 +472,9 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
     }
   }
   p->gemm_choice[key] = best;
+  // the split-K partials of the kept configuration, not of the largest candidate
+  const size_t keep = best.second > 1 ? static_cast<size_t>(best.second) * M * p->ndof * sizeof(double) : 0;
+  if (ws_acc->shrink(keep) != hipSuccess) return fail(SIS_E_DEVICE, "contraction tuning: scratch reallocation failed");
   return SIS_OK;
 }
 
