@@ -442,7 +442,8 @@ def test_bf16_contraction_configurations_agree(nc):
 
 def test_fp64_tiles_with_ragged_k_stages_and_an_empty_split():
     """FP64 contraction on the full 6^3 grid (216 unknowns: the last 16-deep k-stage holds 8 of 16
-    values, and with split-K 3 the third k-range is empty), 300 cells (a ragged last cell tile) and
+    values; with split-K 3 the third k-range is empty, with split-K 32 (64-deep ranges) all but four
+    are), 300 cells (a ragged last cell tile) and
     216 operator rows (a ragged operator tile), every tile fixed through the ABI: rhs = delta L+ h + S
     against the oracle's FFT-form L+ (Eq. (2.3)-(2.6)) on sampled cells, to 1e-12."""
     n_v, l_v, m = 6, 4.0, 2
@@ -455,8 +456,8 @@ def test_fp64_tiles_with_ragged_k_stages_and_an_empty_split():
     hd, dd = dev(h.reshape(nc, -1)), dev(delta)
     sample = list(rng.choice(nc, 10, replace=False)) + [nc - 1]
     for k, (rows, depth) in enumerate([(128, 16), (64, 16), (32, 16), (128, 32), (64, 32)]):
-        for splits in (1, 3):
-            n = nc + 2 * k + (splits == 3)   # a fresh key per configuration (the extra cells repeat cell 0)
+        for si, splits in enumerate((1, 3, 32)):
+            n = nc + 3 * k + si   # a fresh key per configuration (the extra cells repeat cell 0)
             hh = torch.cat([hd, hd[:1].expand(n - nc, -1)]) if n > nc else hd
             dn = torch.cat([dd, dd[:1].expand(n - nc)]) if n > nc else dd
             p.set_contraction_config(n, rows, depth, splits)
@@ -467,6 +468,8 @@ def test_fp64_tiles_with_ragged_k_stages_and_an_empty_split():
             for c in sample:
                 ref = delta[c] * f.lplus(h[c])
                 assert rel(o[c], ref.ravel()) < 1e-12, (rows, depth, splits, c)
+    with pytest.raises(sis.SisError):
+        p.set_contraction_config(nc, 128, 16, 33)
 
 
 def test_every_contraction_configuration_gives_the_same_operator_action():
