@@ -389,11 +389,18 @@ sis_status prepare_lowp_operand(sis_plan* p, int precision, int64_t n_cells, con
   return SIS_OK;
 }
 
+// The 32-row BF16 tiles split the FP64 cell operand while staging it (no split_pairs launch):
+// the few-cell shapes that pick them are bound by launch latency.
+bool fused_split(int precision, int tile) {
+  return (precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16) && tile == 1;
+}
+
 // Autotuner of the contraction: times every (tile, split-K) candidate on the
 // actual shape (two launches each after a warm-up, HIP events on `s`) and
 // keeps, per (cells, precision), the candidate with the fewest split-K
-// partials, then the tallest tile, among those within 3% of the fastest (so
-// that timing noise does not flip between near-equal configurations).  Not
+// partials, then the tallest tile, among those within 1% of the fastest after
+// charging each extra partial its read by the finish step (so that timing noise
+// does not flip between near-equal configurations).  Not
 // callable while `s` is capturing.  Candidates whose split-K partials would
 // exceed 4 GiB are skipped.
 sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scratch* ws_acc, Scratch* ws_x,
@@ -410,6 +417,7 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   g.N = p->ndof;
   g.K = p->ndof;
   if (sis_status st = prepare_lowp_operand(p, precision, M, h, nullptr, ws_x, g, s)) return st;
+  const uint16_t* xp_split = g.Xp;
   int dt, ds;
   choose_gemm(M, p->ndof, &dt, &ds);
   std::vector<std::pair<float, std::pair<int, int>>> timed;
@@ -436,6 +444,7 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
       g.acc = static_cast<double*>(ws_acc->p);
       g.tile = tiles[ti];
       g.splits = sp;
+      g.Xp = fused_split(precision, g.tile) ? nullptr : xp_split;
       err = sis::launch_gemm(g, s);
       if (err == hipSuccess) err = hipEventRecord(e0, s);
       for (int r = 0; r < 2 && err == hipSuccess; ++r) err = sis::launch_gemm(g, s);
@@ -547,7 +556,10 @@ sis_status run_collide(sis_plan* p, int64_t n_cells, const double* h, const doub
   g.precision = precision;
   g.X = h;
   g.Xref = anchor_mode == 2 ? xref : nullptr;
-  if (sis_status st = prepare_lowp_operand(p, precision, n_cells, h, g.Xref, ws_x, g, s)) return st;
+  if (fused_split(precision, tile))
+    g.Xp = nullptr;   // the contraction splits h (minus the anchor) itself
+  else if (sis_status st = prepare_lowp_operand(p, precision, n_cells, h, g.Xref, ws_x, g, s))
+    return st;
   g.op64 = p->op;
   g.op32 = p->op32;
   g.opp = p->opp;

@@ -663,10 +663,13 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // NPROD = 1: the hi*hi product alone (lo halves neither loaded nor staged).
-template <int BM, int BN, int WM, int WN, int NPROD = 3>
+// FUSED (32-row tile only): the cell operand is read in FP64 (X, minus Xref when given; K values
+// per row) and split into its hi and lo parts while it is staged, exactly as split_pairs_kernel
+// does, so that a launch on few cells needs no separate split kernel; results are bit-identical.
+template <int BM, int BN, int WM, int WN, int NPROD = 3, bool FUSED = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gemm_bf16x3_kernel(
     const uint16_t* __restrict__ Xp, const uint16_t* __restrict__ Op, double* __restrict__ C, int64_t M, int N, int Kp,
-    int kps) {
+    int kps, const double* __restrict__ X, const double* __restrict__ Xref, int K) {
   constexpr int BK = 64;                      // two MFMA k-steps per stage
   constexpr int WAVES_N = BN / WN;
   constexpr int TM = WM / 16, TN = WN / 16;
@@ -703,18 +706,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
 
   // (native vectors: HIP's uint4 struct copies from global memory kept the staging in scratch)
   u32x4 ra[2][A_LD], rb[2][B_LD];
+  static_assert(!FUSED || A_LD == 1, "the fused split stages one chunk of eight values per thread");
+  double2 xa[4], xr[4];   // FUSED: the eight FP64 values of the thread's chunk (and of the anchor)
   // hi chunk of (row, k), k a multiple of 8 (its lo chunk sits 32 entries further);
   // rows past M or N read the last row: their products land in outputs that are
   // not stored
   auto pair_off = [&](int64_t row, int k) -> int64_t { return row * 2 * Kp + (k >> 5) * 64 + (k & 31); };
   auto gload = [&](int k0) {
+    if constexpr (FUSED) {
+      const int64_t row = m0 + tid / CH;
+      const int k = k0 + (tid % CH) * 8;
+      const double2* x2 = reinterpret_cast<const double2*>(X + (row < M ? row : M - 1) * K);
+      const double2* r2 = Xref ? reinterpret_cast<const double2*>(Xref + (row < M ? row : M - 1) * K) : nullptr;
 #pragma unroll
-    for (int i = 0; i < A_LD; ++i) {
-      const int q = tid + 256 * i;
-      const int64_t row = m0 + q / CH;
-      const int64_t off = pair_off(row < M ? row : M - 1, k0 + (q % CH) * 8);
-      ra[0][i] = *reinterpret_cast<const u32x4*>(Xp + off);
-      if constexpr (NPROD == 3) ra[1][i] = *reinterpret_cast<const u32x4*>(Xp + off + 32);
+      for (int j = 0; j < 4; ++j) {
+        const bool in = k + 2 * j < K;   // K even: a pair is wholly inside or outside
+        xa[j] = in ? x2[(k >> 1) + j] : make_double2(0.0, 0.0);
+        xr[j] = in && r2 ? r2[(k >> 1) + j] : make_double2(0.0, 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) {
+        const int q = tid + 256 * i;
+        const int64_t row = m0 + q / CH;
+        const int64_t off = pair_off(row < M ? row : M - 1, k0 + (q % CH) * 8);
+        ra[0][i] = *reinterpret_cast<const u32x4*>(Xp + off);
+        if constexpr (NPROD == 3) ra[1][i] = *reinterpret_cast<const u32x4*>(Xp + off + 32);
+      }
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
@@ -726,6 +744,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void g
     }
   };
   auto sstore = [&]() {
+    if constexpr (FUSED) {
+      // x - xref rounded to bf16 (hi), the remainder rounded again (lo), as in split_pairs_kernel
+      uint32_t hw[4], lw[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double x0 = xa[j].x - xr[j].x, x1 = xa[j].y - xr[j].y;
+        const uint16_t h0 = bf16_rne(static_cast<float>(x0)), h1 = bf16_rne(static_cast<float>(x1));
+        hw[j] = static_cast<uint32_t>(h0) | (static_cast<uint32_t>(h1) << 16);
+        if constexpr (NPROD == 3) {
+          const uint16_t l0 = bf16_rne(static_cast<float>(x0 - static_cast<double>(bf16_to_f32(h0))));
+          const uint16_t l1 = bf16_rne(static_cast<float>(x1 - static_cast<double>(bf16_to_f32(h1))));
+          lw[j] = static_cast<uint32_t>(l0) | (static_cast<uint32_t>(l1) << 16);
+        }
+      }
+      ra[0][0] = u32x4{hw[0], hw[1], hw[2], hw[3]};
+      if constexpr (NPROD == 3) ra[1][0] = u32x4{lw[0], lw[1], lw[2], lw[3]};
+    }
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int r = (tid + 256 * i) / CH, kc = wslot;
@@ -2955,27 +2990,34 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
     else
       hipLaunchKernelGGL((gemm_f32_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.X32, g.op32, g.acc, g.M, g.N, g.K, kps);
   } else {
-    // bf16 forms: operands in the pair layout, k running over the padded Kp (zeros past K)
-    if (!g.Xp || !g.opp) return hipErrorInvalidValue;
+    // bf16 forms: operands in the pair layout, k running over the padded Kp (zeros past K); with
+    // no cell operand in that layout (Xp null) the 32-row tile splits X (minus Xref) itself
+    if (!g.opp) return hipErrorInvalidValue;
+    const bool fused = !g.Xp;
+    if (fused && (g.tile != 1 || !g.X || g.K % 2)) return hipErrorInvalidValue;
     const int Kp = pair_stride(g.K);
     const int kps = gemm_k_per_split(Kp, g.splits);
     if (g.precision == 3) {
-      if (g.tile == 0)
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+      if (fused)
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32, 1, true>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps, g.X, g.Xref, g.K);
+      else if (g.tile == 0)
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps, nullptr, nullptr, 0);
       else if (g.tile == 2)
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps, nullptr, nullptr, 0);
       else
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32, 1>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps, nullptr, nullptr, 0);
     } else if (g.tile == 5) {
       if (!gemm_wide_fits(g.M, g.N, g.K)) return hipErrorInvalidValue;
       dim3 wgrid((g.N + 255) / 256, static_cast<unsigned>((g.M + 255) / 256), g.splits);
       hipLaunchKernelGGL(gemm_bf16x3_wide_kernel, wgrid, dim3(512), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+    } else if (fused) {
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32, 3, true>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps, g.X, g.Xref, g.K);
     } else if (g.tile == 0) {
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128, 64, 64>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps, nullptr, nullptr, 0);
     } else if (g.tile == 2) {
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 128, 32, 64>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps, nullptr, nullptr, 0);
     } else {
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps);
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<32, 128, 32, 32>), grid, dim3(256), 0, s, g.Xp, g.opp, g.acc, g.M, g.N, Kp, kps, nullptr, nullptr, 0);
     }
   }
   return hipGetLastError();
