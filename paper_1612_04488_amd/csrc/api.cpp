@@ -3163,9 +3163,9 @@ sis_status state_iteration(sis_state* b, hipStream_t s, int kind, bool h_is_zero
   a.case_active = b->cact;
   a.qfield = b->q;
   a.eps = b->o.eps;
+  a.cell_active = b->lact;   // the march writes its cells' flags (no expansion launch)
   set_species(a, p, b->o.N);
   HIP_TRY(sis::launch_diffusion1d(a, s));
-  HIP_TRY(sis::launch_expand_active(b->cact, g->case_of_cell, g->n_cells, b->lact, s));
   return SIS_OK;
 }
 

@@ -142,6 +142,7 @@ struct DiffusionArgs {
   int32_t* case_active;      // [n_cases]
   double* qfield;            // [cells] q3 of the new iterate or null
   double* ufield;            // [cells] U3 of the new iterate or null
+  int32_t* cell_active;      // [cells] or null: set to the case's flag after its march (1-D cases)
   double eps;
   // binary mixture (nsp == 2): arrays above are per (cell, species) row,
   // state is [n_cases][6] = {M_A, M_B, Q_A, Q_B, residual, iterations}

@@ -1479,7 +1479,22 @@ __device__ __forceinline__ void diffusion1d_case(const DiffusionArgs& a, int cs)
 }
 
 
-__global__ __launch_bounds__(kDiffChunk) void diffusion1d_kernel(DiffusionArgs a) { diffusion1d_case(a, blockIdx.x); }
+// The case's flag, as its march left it, copied to the flags of its cells (what the next
+// iteration's finish and sweep read), so that no separate expansion launch is needed.
+__device__ __forceinline__ void case_flag_to_cells(const DiffusionArgs& a, int cs) {
+  __shared__ int32_t flag;
+  if (!a.cell_active || !a.case_active) return;
+  __syncthreads();
+  if (threadIdx.x == 0) flag = __hip_atomic_load(&a.case_active[cs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int64_t c0 = a.node_off[cs], c1 = a.node_off[cs + 1];
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) a.cell_active[c] = flag;
+}
+
+__global__ __launch_bounds__(kDiffChunk) void diffusion1d_kernel(DiffusionArgs a) {
+  diffusion1d_case(a, blockIdx.x);
+  case_flag_to_cells(a, blockIdx.x);
+}
 
 // Binary mixture (planar): the velocity equations of species B (own shear
 // stress) and A (total stress minus B's), integrated once from the symmetry
@@ -1487,12 +1502,11 @@ __global__ __launch_bounds__(kDiffChunk) void diffusion1d_kernel(DiffusionArgs a
 // first.  mom[row][4] = {int v3 h, q, G1, P13}; U is per unit molar fraction.
 // The two species march independently (lane s carries species s); inputs and outputs
 // are staged through LDS as in diffusion1d_kernel.
-__global__ __launch_bounds__(kDiffChunk) void diffusion1d_mix_kernel(DiffusionArgs a) {
+__device__ __forceinline__ void diffusion1d_mix_case(const DiffusionArgs& a, int cs) {
   __shared__ double in_s[2][4][kDiffChunk];   // per species: Uh, qh, G, source
   __shared__ double in_c[4][kDiffChunk];      // per node: ca, cb, cc, x
   __shared__ double out[2][4][kDiffChunk];    // per species: U, dU, q, U of the new iterate
   __shared__ double red[2][2];                // per species: M, Q integrals
-  const int cs = blockIdx.x;
   if (a.case_active && !a.case_active[cs]) return;   // uniform over the workgroup
   const int64_t c0 = a.node_off[cs];
   const int nodes = static_cast<int>(a.node_off[cs + 1] - c0);
@@ -1588,6 +1602,11 @@ __global__ __launch_bounds__(kDiffChunk) void diffusion1d_mix_kernel(DiffusionAr
     if (!(res >= a.eps) || bad) a.case_active[cs] = 0;
     st[5] = static_cast<double>(it);
   }
+}
+
+__global__ __launch_bounds__(kDiffChunk) void diffusion1d_mix_kernel(DiffusionArgs a) {
+  diffusion1d_mix_case(a, blockIdx.x);
+  case_flag_to_cells(a, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ 2-D sweep
