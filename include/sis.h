@@ -509,8 +509,10 @@ sis_status sis_state_destroy(sis_state_t state);
 /* Contraction configuration used for n_cells cells in `precision`: the
  * autotuner (run on the first eager sis_collide of a shape and at
  * sis_state_create, outside stream capture) times every (tile, split-K)
- * candidate on the device, adds the finish step's cost of reading each
- * split-K partial beyond the first (M x N x 8 bytes at 4 TB/s), and keeps,
+ * candidate on the device (per launch), adds the finish step's cost of
+ * reading each split-K partial beyond the first (M x N x 8 bytes at 4 TB/s)
+ * and, for the bf16 tiles that read the pair layout, the measured split of
+ * the cell operand into it, and keeps,
  * among those within 1% of the fastest, the fewest split-K partials, then
  * the taller tile; tile_rows is the
  * cell-tile height (128, 64 or 32, the operator tile 128; or 256 for the

@@ -424,6 +424,24 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
+  // the split of the cell operand into the bf16 pair layout, per launch (two timed launches)
+  const bool bf16 = precision == SIS_PREC_BF16X3 || precision == SIS_PREC_BF16;
+  float split_ms = 0.f;
+  if (bf16) {
+    uint16_t* xp = const_cast<uint16_t*>(xp_split);
+    hipError_t e = hipEventRecord(e0, s);
+    for (int r = 0; r < 2 && e == hipSuccess; ++r)
+      e = sis::launch_split_pairs(h, nullptr, M, p->ndof, xp, precision == SIS_PREC_BF16X3, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&split_ms, e0, e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(SIS_E_DEVICE, "contraction tuning: %s", hipGetErrorString(e));
+    }
+    split_ms *= 0.5f;
+  }
   // candidates: FP64 tiles 0, 2, 1, 3, 4; FP32 and BF16 tiles 0, 2, 1; BF16X3 tiles 0, 2, 1 and the
   // 256 x 256 tile 5 where its pair arrays take 32-bit offsets
   std::vector<int> tiles = {0, 2, 1};
@@ -452,6 +470,9 @@ sis_status tune_gemm(sis_plan* p, int64_t M, int precision, const double* h, Scr
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       float ms = 0.f;
       if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      // per launch; the bf16 tiles that read the pair layout also pay its split launch
+      ms *= 0.5f;
+      if (bf16 && !fused_split(precision, g.tile)) ms += split_ms;
       if (err == hipSuccess) timed.emplace_back(ms, std::make_pair(g.tile, sp));
     }
   (void)hipEventDestroy(e0);
