@@ -236,14 +236,18 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
   double* Si = Sr + Q * NB;
   double* Y1r = Si + Q * NB;       // [n3][B1][L]
   double* Y1i = Y1r + n3 * NB;
-  double* Y2r = Y1i + n3 * NB;     // [B1][n2][n3]
-  double* Y2i = Y2r + B1 * N3c;
-  double* E3r = Y2i + B1 * N3c;    // [n3][Q]
-  double* E3i = E3r + n3 * Q;
-  double* E2r = E3i + n3 * Q;      // [n2][L]
+  // Rows padded by one double where 16 lanes read (or write) down a column: E3 (stride Q, 32 at
+  // n_pad 64), Y2 (stride n3) and E1 (stride B1) would otherwise put those lanes on a few banks.
+  const int Qp = Q + 1, n3p = n3 + 1, B1p = B1 + 1;
+  const int N3p = n2 * n3p;
+  double* Y2r = Y1i + n3 * NB;     // [B1][n2][n3 + 1]
+  double* Y2i = Y2r + B1 * N3p;
+  double* E3r = Y2i + B1 * N3p;    // [n3][Q + 1]
+  double* E3i = E3r + n3 * Qp;
+  double* E2r = E3i + n3 * Qp;     // [n2][L]
   double* E2i = E2r + n2 * L;
-  double* E1r = E2i + n2 * L;      // [n][B1] (the slab's columns)
-  double* E1i = E1r + n * B1;
+  double* E1r = E2i + n2 * L;      // [n][B1 + 1] (the slab's columns)
+  double* E1i = E1r + n * B1p;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
 
   const double* Sc = S + (cell * L + l10) * 2 * static_cast<int64_t>(Q) * L;
@@ -256,8 +260,9 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
     (ri ? Si : Sr)[l3 * NB + b * L + l2] = Sc[i];
   }
   for (int i = threadIdx.x; i < n3 * Q; i += kInvThreads) {
-    E3r[i] = f.e3r[i];
-    E3i[i] = f.e3i[i];
+    const int o = (i / Q) * Qp + i % Q;
+    E3r[o] = f.e3r[i];
+    E3i[o] = f.e3i[i];
   }
   for (int i = threadIdx.x; i < n2 * L; i += kInvThreads) {
     E2r[i] = f.e2r[i];
@@ -265,8 +270,8 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
   }
   for (int i = threadIdx.x; i < n * B1; i += kInvThreads) {
     const int j1 = i / B1, b = i - j1 * B1;
-    E1r[i] = b < nb ? f.e1r[j1 * L + l10 + b] : 0.0;
-    E1i[i] = b < nb ? f.e1i[j1 * L + l10 + b] : 0.0;
+    E1r[j1 * B1p + b] = b < nb ? f.e1r[j1 * L + l10 + b] : 0.0;
+    E1i[j1 * B1p + b] = b < nb ? f.e1i[j1 * L + l10 + b] : 0.0;
   }
   __syncthreads();
 
@@ -294,8 +299,8 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
           const int k = ks * 4 + kr;
           const bool oka = ks < nks1 && k < Q && m < M;
           const bool okb = ks < nks1 && k < Q && c < N;
-          ar[ks] = oka ? E3r[m * Q + k] : 0.0;
-          ai[ks] = oka ? -E3i[m * Q + k] : 0.0;   // negated: the imaginary product enters cr with a minus
+          ar[ks] = oka ? E3r[m * Qp + k] : 0.0;
+          ai[ks] = oka ? -E3i[m * Qp + k] : 0.0;   // negated: the imaginary product enters cr with a minus
           const double mv = okb ? mt[k * LL + c] : 0.0;
           br[ks] = okb ? mv * Sr[k * NB + c] : 0.0;
           bi[ks] = okb ? mv * Si[k * NB + c] : 0.0;
@@ -354,8 +359,8 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
           const int row = m0 + kr + 4 * q, col = n0 + cc;
           const int s3 = row / B1, b = row - s3 * B1;
           if (row < M && b < nb && col < N) {
-            Y2r[(b * n2 + col) * n3 + s3] = cr[q];
-            Y2i[(b * n2 + col) * n3 + s3] = ci[q];
+            Y2r[(b * n2 + col) * n3p + s3] = cr[q];
+            Y2i[(b * n2 + col) * n3p + s3] = ci[q];
           }
         }
       }
@@ -375,13 +380,15 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
             fv[r] = (j1 < n && c < N3c) ? ft[j1 * N3c + c] : 0.0;
           }
           v4d o = v4d{0.0, 0.0, 0.0, 0.0};
+          // the lane's column s2 n3 + s3 of the tile in the padded Y2 rows
+          const int col = n0 + cc, s2c = col / n3, colp = s2c * n3p + (col - s2c * n3);
           for (int k0 = 0; k0 < 2 * B1; k0 += 4) {
             const int kk = k0 + kr;
             const int ri = kk / B1, b = kk - ri * B1;
             const bool okk = kk < 2 * B1 && b < nb;
             double av = 0.0, bv = 0.0;
-            if (okk && m0 + cc < n) av = ri ? -E1i[(m0 + cc) * B1 + b] : E1r[(m0 + cc) * B1 + b];
-            if (okk && n0 + cc < N3c) bv = (ri ? Y2i : Y2r)[b * N3c + n0 + cc];
+            if (okk && m0 + cc < n) av = ri ? -E1i[(m0 + cc) * B1p + b] : E1r[(m0 + cc) * B1p + b];
+            if (okk && col < N3c) bv = (ri ? Y2i : Y2r)[b * N3p + colp];
             o = mfma(av, bv, o);
           }
 #pragma unroll
@@ -592,8 +599,10 @@ int forward_chunk(const FsmDims& d) {
 
 size_t inverse_lds_bytes(const FsmDims& d, int B1) {
   const size_t NB = static_cast<size_t>(B1) * d.L;
-  return (2 * d.Q * NB + 2 * d.n3 * NB + 2 * static_cast<size_t>(B1) * d.n2 * d.n3 +
-          2 * static_cast<size_t>(d.n3) * d.Q + 2 * static_cast<size_t>(d.n2) * d.L + 2 * static_cast<size_t>(d.n) * B1) *
+  // Y2, E3 and E1 rows padded by one double (bank spread of the column-wise lane accesses)
+  return (2 * d.Q * NB + 2 * d.n3 * NB + 2 * static_cast<size_t>(B1) * d.n2 * (d.n3 + 1) +
+          2 * static_cast<size_t>(d.n3) * (d.Q + 1) + 2 * static_cast<size_t>(d.n2) * d.L +
+          2 * static_cast<size_t>(d.n) * (B1 + 1)) *
          sizeof(double);
 }
 
