@@ -293,26 +293,37 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
       for (int blk = wave; blk < mb * nbk; blk += kInvWaves) {
         const int m0 = (blk / nbk) * 16, n0 = (blk % nbk) * 16;
         const int m = m0 + cc, c = n0 + cc;
-        double ar[kKs1], ai[kKs1], br[kKs1], bi[kKs1];
+        // Loads from clamped (in-bounds) addresses, masked after the load: no lane-divergent
+        // branch between them, so all of a block's loads are in flight together.
+        const int mcl = min(m, M - 1), ccl = min(c, N - 1);
+        // All loads first, nothing computed from them until every one is issued (one latency per block).
+        double ar[kKs1], ai[kKs1], mv[kKs1], br[kKs1], bi[kKs1];
 #pragma unroll
         for (int ks = 0; ks < kKs1; ++ks) {
-          const int k = ks * 4 + kr;
-          const bool oka = ks < nks1 && k < Q && m < M;
-          const bool okb = ks < nks1 && k < Q && c < N;
-          ar[ks] = oka ? E3r[m * Qp + k] : 0.0;
-          ai[ks] = oka ? -E3i[m * Qp + k] : 0.0;   // negated: the imaginary product enters cr with a minus
-          const double mv = okb ? mt[k * LL + c] : 0.0;
-          br[ks] = okb ? mv * Sr[k * NB + c] : 0.0;
-          bi[ks] = okb ? mv * Si[k * NB + c] : 0.0;
+          ar[ks] = ai[ks] = mv[ks] = br[ks] = bi[ks] = 0.0;
+          if (ks < nks1) {
+            const int kcl = min(ks * 4 + kr, Q - 1);
+            ar[ks] = E3r[mcl * Qp + kcl];
+            ai[ks] = E3i[mcl * Qp + kcl];
+            mv[ks] = mt[kcl * LL + ccl];
+            br[ks] = Sr[kcl * NB + ccl];
+            bi[ks] = Si[kcl * NB + ccl];
+          }
         }
         v4d cr = v4d{0.0, 0.0, 0.0, 0.0}, ci = cr;
 #pragma unroll
         for (int ks = 0; ks < kKs1; ++ks)
           if (ks < nks1) {
-            cr = mfma(ar[ks], br[ks], cr);
-            ci = mfma(ar[ks], bi[ks], ci);
-            cr = mfma(ai[ks], bi[ks], cr);
-            ci = mfma(-ai[ks], br[ks], ci);
+            const int k = ks * 4 + kr;
+            const bool oka = k < Q && m < M, okb = k < Q && c < N;
+            const double xr = oka ? ar[ks] : 0.0;
+            const double xi = oka ? -ai[ks] : 0.0;   // negated: the imaginary product enters cr with a minus
+            const double yr = okb ? mv[ks] * br[ks] : 0.0;
+            const double yi = okb ? mv[ks] * bi[ks] : 0.0;
+            cr = mfma(xr, yr, cr);
+            ci = mfma(xr, yi, ci);
+            cr = mfma(xi, yi, cr);
+            ci = mfma(-xi, yr, ci);
           }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -333,17 +344,20 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
         const int m0 = (blk / nbk) * 16, n0 = (blk % nbk) * 16;
         const int r = m0 + cc, s2 = n0 + cc;
         const bool rowok = r < M && (r % B1) < nb, colok = s2 < N;
+        const int rcl = min(r, M - 1), s2cl = min(s2, N - 1);
         v4d cr = v4d{0.0, 0.0, 0.0, 0.0}, ci = cr;
         for (int kc = 0; kc < nks2; kc += 4) {
           double ar[4], ai[4], br[4], bi[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int k = (kc + u) * 4 + kr;
-            const bool ok = kc + u < nks2 && k < L;
-            ar[u] = ok && rowok ? Y1r[r * L + k] : 0.0;
-            ai[u] = ok && rowok ? Y1i[r * L + k] : 0.0;
-            br[u] = ok && colok ? E2r[s2 * L + k] : 0.0;
-            bi[u] = ok && colok ? E2i[s2 * L + k] : 0.0;
+            const int k = (kc + u) * 4 + kr, kcl = min(k, L - 1);
+            const bool ok = k < L;
+            const double yr = Y1r[rcl * L + kcl], yi = Y1i[rcl * L + kcl];
+            const double er = E2r[s2cl * L + kcl], ei = E2i[s2cl * L + kcl];
+            ar[u] = ok && rowok ? yr : 0.0;
+            ai[u] = ok && rowok ? yi : 0.0;
+            br[u] = ok && colok ? er : 0.0;
+            bi[u] = ok && colok ? ei : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
@@ -373,22 +387,25 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
         const int tile = wave + kInvWaves * q;
         if (tile < tiles3) {
           const int m0 = (tile / nb3) * 16, n0 = (tile % nb3) * 16;
+          const int col = n0 + cc, ccl = min(col, N3c - 1);
+          // Unmasked loads from clamped addresses (finite values): rows or columns outside the grid
+          // accumulate into entries of G that are never stored, and a masked load would be turned
+          // into a branch with its own wait.
           double fv[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int j1 = m0 + kr + 4 * r, c = n0 + cc;
-            fv[r] = (j1 < n && c < N3c) ? ft[j1 * N3c + c] : 0.0;
-          }
+          for (int r = 0; r < 4; ++r) fv[r] = ft[min(m0 + kr + 4 * r, n - 1) * N3c + ccl];
           v4d o = v4d{0.0, 0.0, 0.0, 0.0};
           // the lane's column s2 n3 + s3 of the tile in the padded Y2 rows
-          const int col = n0 + cc, s2c = col / n3, colp = s2c * n3p + (col - s2c * n3);
+          const int s2c = ccl / n3, colp = s2c * n3p + (ccl - s2c * n3);
+          const int mcl = min(m0 + cc, n - 1);
           for (int k0 = 0; k0 < 2 * B1; k0 += 4) {
-            const int kk = k0 + kr;
+            const int kk = min(k0 + kr, 2 * B1 - 1);
             const int ri = kk / B1, b = kk - ri * B1;
-            const bool okk = kk < 2 * B1 && b < nb;
-            double av = 0.0, bv = 0.0;
-            if (okk && m0 + cc < n) av = ri ? -E1i[(m0 + cc) * B1p + b] : E1r[(m0 + cc) * B1p + b];
-            if (okk && col < N3c) bv = (ri ? Y2i : Y2r)[b * N3p + colp];
+            const bool okk = k0 + kr < 2 * B1 && b < nb;
+            const double e = (ri ? E1i : E1r)[mcl * B1p + b];
+            const double y = (ri ? Y2i : Y2r)[b * N3p + colp];
+            const double av = okk && m0 + cc < n ? (ri ? -e : e) : 0.0;
+            const double bv = okk && col < N3c ? y : 0.0;
             o = mfma(av, bv, o);
           }
 #pragma unroll
