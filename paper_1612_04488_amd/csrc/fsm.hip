@@ -248,7 +248,9 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
   double* E2i = E2r + n2 * L;
   double* E1r = E2i + n2 * L;      // [n][B1 + 1] (the slab's columns)
   double* E1i = E1r + n * B1p;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
+  // wave index as a scalar: the per-wave block and tile loops below branch uniformly
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
 
   const double* Sc = S + (cell * L + l10) * 2 * static_cast<int64_t>(Q) * L;
   for (int i = threadIdx.x; i < nb * 2 * Q * L; i += kInvThreads) {
@@ -283,9 +285,19 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
   const int64_t LL = static_cast<int64_t>(L) * L;
   const int64_t qll = static_cast<int64_t>(Q) * LL;
   const int nks1 = (Q + 3) / 4, nks2 = (L + 3) / 4;
+  // Stage 2 has few 16 x 16 tiles (2 for 32^3 velocities on the v2, v3 > 0 quarter).  When two
+  // per tile fit in the waves, each tile's k-steps are split in two halves taken by different
+  // waves, which evens out the four SIMDs' work: both halves add into the zeroed Y2, and
+  // 0 + x + y rounds the same in either order, so the result does not depend on which wave adds
+  // first.  The split costs a zeroing pass and a barrier per term, so it is used only then.
+  const int mb2 = (n3 * B1 + 15) / 16, nbk2 = (n2 + 15) / 16;
+  const bool ksplit = 2 * mb2 * nbk2 <= kInvWaves;
 
   for (int t = 0; t < d.T; ++t) {
     const double* mt = mult + t * qll + static_cast<int64_t>(l10) * L;
+    // with the split, Y2 is accumulated by stage 2; nothing reads or writes it during stage 1
+    if (ksplit)
+      for (int i = threadIdx.x; i < 2 * B1 * N3p; i += kInvThreads) Y2r[i] = 0.0;
     {
       // stage 1: M = n3, N = nb L, K = Q
       const int M = n3, N = nb * L;
@@ -338,20 +350,22 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
     __syncthreads();
     {
       // stage 2: rows r = (s3, b) (M = n3 B1), columns s2 (N = n2), K = L
-      const int M = n3 * B1, N = n2;
-      const int mb = (M + 15) / 16, nbk = (N + 15) / 16;
-      for (int blk = wave; blk < mb * nbk; blk += kInvWaves) {
+      const int M = n3 * B1, N = n2, nbk = nbk2;
+      const int kh = ksplit ? (nks2 + 1) / 2 : nks2;
+      for (int it = wave; it < (ksplit ? 2 : 1) * mb2 * nbk2; it += kInvWaves) {
+        const int blk = ksplit ? it >> 1 : it;
+        const int kb = ksplit && (it & 1) ? kh : 0, ke = ksplit && !(it & 1) ? kh : nks2;
         const int m0 = (blk / nbk) * 16, n0 = (blk % nbk) * 16;
         const int r = m0 + cc, s2 = n0 + cc;
         const bool rowok = r < M && (r % B1) < nb, colok = s2 < N;
         const int rcl = min(r, M - 1), s2cl = min(s2, N - 1);
         v4d cr = v4d{0.0, 0.0, 0.0, 0.0}, ci = cr;
-        for (int kc = 0; kc < nks2; kc += 4) {
+        for (int kc = kb; kc < ke; kc += 4) {
           double ar[4], ai[4], br[4], bi[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int k = (kc + u) * 4 + kr, kcl = min(k, L - 1);
-            const bool ok = k < L;
+            const bool ok = kc + u < ke && k < L;
             const double yr = Y1r[rcl * L + kcl], yi = Y1i[rcl * L + kcl];
             const double er = E2r[s2cl * L + kcl], ei = E2i[s2cl * L + kcl];
             ar[u] = ok && rowok ? yr : 0.0;
@@ -361,7 +375,7 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (kc + u < nks2) {
+            if (kc + u < ke) {
               cr = mfma(ar[u], br[u], cr);
               ci = mfma(ar[u], bi[u], ci);
               cr = mfma(-ai[u], bi[u], cr);
@@ -373,8 +387,14 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
           const int row = m0 + kr + 4 * q, col = n0 + cc;
           const int s3 = row / B1, b = row - s3 * B1;
           if (row < M && b < nb && col < N) {
-            Y2r[(b * n2 + col) * n3p + s3] = cr[q];
-            Y2i[(b * n2 + col) * n3p + s3] = ci[q];
+            const int o = (b * n2 + col) * n3p + s3;
+            if (ksplit) {
+              __hip_atomic_fetch_add(&Y2r[o], cr[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              __hip_atomic_fetch_add(&Y2i[o], ci[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+              Y2r[o] = cr[q];
+              Y2i[o] = ci[q];
+            }
           }
         }
       }
@@ -413,6 +433,7 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
         }
       }
     }
+    if (ksplit) __syncthreads();   // every read of Y2 done before the next term zeroes it
   }
   double* out = accp + (static_cast<int64_t>(slab) * n_cells + cell) * d.nv;
 #pragma unroll
