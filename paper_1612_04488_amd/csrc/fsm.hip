@@ -14,6 +14,8 @@ namespace sis {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void gbl_void_t;
 constexpr int kThreads = 256;   // four wave64s
 
 __device__ inline v4d mfma(double a, double b, v4d c) {
@@ -248,6 +250,7 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
   double* E2i = E2r + n2 * L;
   double* E1r = E2i + n2 * L;      // [n][B1 + 1] (the slab's columns)
   double* E1i = E1r + n * B1p;
+  double* pf = E1i + n * B1p;      // 256 B that the multiplier prefetch writes and nothing reads
   // wave index as a scalar: the per-wave block and tile loops below branch uniformly
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, kr = lane >> 4, cc = lane & 15;
@@ -348,6 +351,23 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
       }
     }
     __syncthreads();
+    if (t + 1 < d.T) {
+      // Prefetch into L2 the multiplier lines that the stage-1 blocks read in the next term
+      // (otherwise each block's first loads wait on a table of 55 MB to 0.3 GB in MALL or HBM):
+      // one dword per line, lanes 0..31 the first and lanes 32..63 the last line of each row's
+      // 16 columns.  The dwords land in pf through the LDS DMA path, so no register holds them.
+      // The waves that stage 2 leaves idle issue it, so it does not delay stage 2.
+      const double* mn = mult + (t + 1) * qll + static_cast<int64_t>(l10) * L;
+      const int N1 = nb * L, nbk1 = (N1 + 15) / 16;
+      const int kp = min(lane & 31, Q - 1);
+      const int items2 = (ksplit ? 2 : 1) * mb2 * nbk2, nidle = kInvWaves - items2;
+      const int first = nidle > 0 ? wave - items2 : wave, step = nidle > 0 ? nidle : kInvWaves;
+      for (int blk = first; blk >= 0 && blk < ((n3 + 15) / 16) * nbk1; blk += step) {
+        const int n0 = (blk % nbk1) * 16;
+        const int c = lane < 32 ? n0 : min(n0 + 15, N1 - 1);
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(mn + kp * LL + c), (lds_void_t*)pf, 4, 0, 0);
+      }
+    }
     {
       // stage 2: rows r = (s3, b) (M = n3 B1), columns s2 (N = n2), K = L
       const int M = n3 * B1, N = n2, nbk = nbk2;
@@ -638,9 +658,10 @@ int forward_chunk(const FsmDims& d) {
 size_t inverse_lds_bytes(const FsmDims& d, int B1) {
   const size_t NB = static_cast<size_t>(B1) * d.L;
   // Y2, E3 and E1 rows padded by one double (bank spread of the column-wise lane accesses)
+  // (+ 32 doubles written by the multiplier prefetch)
   return (2 * d.Q * NB + 2 * d.n3 * NB + 2 * static_cast<size_t>(B1) * d.n2 * (d.n3 + 1) +
           2 * static_cast<size_t>(d.n3) * (d.Q + 1) + 2 * static_cast<size_t>(d.n2) * d.L +
-          2 * static_cast<size_t>(d.n) * (B1 + 1)) *
+          2 * static_cast<size_t>(d.n) * (B1 + 1) + 32) *
          sizeof(double);
 }
 
