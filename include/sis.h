@@ -348,9 +348,9 @@ sis_status sis_collide_fsm(sis_plan_t plan, int64_t n_cells, const double* h, co
  * padding included), its l1-slab width (modes per workgroup of the inverse
  * transforms) and the device bytes of its tables; all nullable.             */
 sis_status sis_plan_fsm_info(sis_plan_t plan, double* flops_per_cell, int32_t* slab_l1, int64_t* table_bytes);
-/* l1 modes per inverse-transform workgroup (1..8; default: the widest whose LDS
- * lets two workgroups share a CU).  Results do not depend on it beyond rounding
- * order.                                                                     */
+/* l1 modes per inverse-transform workgroup (1..8, with the workgroup's LDS
+ * within 160 KiB; default: the widest up to 4 that fits).  Results do not
+ * depend on it beyond rounding order.                                        */
 sis_status sis_plan_set_fsm_slab(sis_plan_t plan, int32_t slab_l1);
 /* Summed milliseconds and number of sis_collide_fsm calls timed since
  * sis_plan_timing enabled timing (synchronises).                              */

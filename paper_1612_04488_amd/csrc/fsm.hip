@@ -455,6 +455,8 @@ __global__ __launch_bounds__(kInvThreads) void fsm_inverse_kernel(FsmDims d, Fsm
     }
     if (ksplit) __syncthreads();   // every read of Y2 done before the next term zeroes it
   }
+  // no prefetch into pf may still be in flight when the workgroup's LDS is released
+  __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
   double* out = accp + (static_cast<int64_t>(slab) * n_cells + cell) * d.nv;
 #pragma unroll
   for (int q = 0; q < MAXG; ++q) {
