@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void fsm_forward_kernel(FsmDims d, FsmFac
 // (l1 = l10 + b).  Each block's operands for all its k-steps (stage 1) or four
 // k-steps at a time (stage 2) are loaded before its MFMAs, so one load latency is
 // paid per block or chunk, not per k-step.  G stays in registers: stage-3 tile q
-// of wave w is tile w + 4q.
+// of wave w is tile w + 8q.
 constexpr int kKs1 = 8;   // stage-1 k-steps held in registers: Q <= 32 (n_pad <= 64)
 
 constexpr int kInvWaves = 8;
